@@ -1,0 +1,206 @@
+/*
+ * eahp.h -- C ABI of the energy-adaptive Riemannian CG (EARCG) hot path for
+ * plane-wave Kohn-Sham energy minimisation on the Stiefel manifold, on one
+ * AMD MI355X (gfx950) GPU.
+ *
+ * The problem (Sec. 2.1, eq. (2.2), and its discrete product form, Sec. 5.1,
+ * eq. (5.1)): minimise E(Psi) over Psi in St(p, n_1) x ... x St(p, n_K),
+ * Psi_k^* Psi_k = I, with E the Kohn-Sham energy of eq. (1.1) in the Hartree
+ * scaling of the experiments (H = -1/2 Laplacian + V_eff, doubly occupied
+ * orbitals), a Gaussian local ionic potential, Hartree, Slater exchange and
+ * one Gaussian s-projector per atom.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Orbital blocks ("frames"): device memory, complex values with interleaved
+ *   real/imaginary parts (complex128 = 2 x double).  For k-point b the block
+ *   is column-major n_b x p (orbital j contiguous, rows in the canonical
+ *   plane-wave order: ascending linear FFT-box index (i1*n2 + i2)*n3 + i3 with
+ *   i_d = m_d mod n_d); the blocks of successive k-points are concatenated, so
+ *   block b starts at element p * offsets[b] (eahp_problem_layout).
+ * p x p matrices (Lambda): device memory, nk consecutive column-major p x p
+ *   complex128 matrices.
+ * Ownership: the caller owns every buffer passed in; the library never frees
+ *   caller memory.  Handles are library-owned and released by *_destroy.
+ * Ordering: all device work is ordered on the context's HIP stream; every
+ *   entry point that returns host scalars synchronises that stream before it
+ *   returns.  Calls on one problem must not overlap (they share workspaces).
+ * Errors: every int-returning function returns EAHP_OK (0) or a negative
+ *   status; no exception crosses the ABI.  After an error the output buffers
+ *   are unspecified and the handles stay valid.  eahp_strerror names a status;
+ *   eahp_last_error returns a message for the calling thread's last error.
+ */
+#ifndef EAHP_H
+#define EAHP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  EAHP_OK = 0,
+  EAHP_EINVAL = -1,      /* bad argument (null pointer, size, layout)        */
+  EAHP_ENOMEM = -2,      /* device or host allocation failed                 */
+  EAHP_EDEVICE = -3,     /* HIP runtime error                                */
+  EAHP_ENOTPD = -4,      /* Gram matrix of a retraction not positive definite*/
+  EAHP_EFOM = -5,        /* metric solve broke down                          */
+  EAHP_ELINESEARCH = -6, /* line search found no acceptable step             */
+  EAHP_ENODESCENT = -7,  /* no descent direction after the reset rules       */
+  EAHP_ENOCONV = -8,     /* solve reached maxit above tolerance              */
+  EAHP_ENONFINITE = -9   /* NaN or Inf encountered                           */
+};
+
+enum { EAHP_FP64 = 0, EAHP_MIXED = 1 };
+
+/* term switches of the Hamiltonian (all set = the full model) */
+enum { EAHP_TERM_ION = 1, EAHP_TERM_HARTREE = 2, EAHP_TERM_XC = 4, EAHP_TERM_NONLOCAL = 8 };
+
+typedef struct eahp_ctx eahp_ctx;
+typedef struct eahp_problem eahp_problem;
+typedef struct eahp_solver eahp_solver;
+
+/* A crystal and its discretisation (Sec. 5.1).  All arrays are host memory
+ * and are copied during eahp_problem_create. */
+typedef struct {
+  double lattice[9];     /* lattice vectors as columns: lattice[3*j+i] = (a_j)_i, bohr */
+  int natoms;
+  const double* frac;    /* natoms x 3 fractional positions (row-major)                */
+  const double* Z;       /* natoms valence charges                                      */
+  double r_loc;          /* Gaussian width of the local ionic potential (bohr)          */
+  double r_proj;         /* width of the Gaussian s-projector (bohr)                    */
+  double D_proj;         /* projector coupling D_I (Ha)                                 */
+  double ecut;           /* kinetic cutoff |k+G|^2/2 <= ecut (Ha)                       */
+  int fft[3];            /* FFT box; 0 = smallest 2/3/5-smooth n >= 4 max|m| + 1        */
+  int nk;
+  const double* kfrac;   /* nk x 3 fractional k-points (row-major)                      */
+  const double* kweight; /* nk weights (sum 1)                                          */
+  int p;                 /* orbitals per k-point                                        */
+  double occ;            /* occupation per orbital (2 = doubly occupied)                */
+  int precision;         /* EAHP_FP64 or EAHP_MIXED                                     */
+  int terms;             /* bitwise or of EAHP_TERM_*                                   */
+} eahp_system_desc;
+
+/* Method constants (Sec. 5.2: delta, sigma, gamma, eps, mu, FOM tolerance). */
+typedef struct {
+  double mu;         /* shift correction mu > 0 of Sigma = Lambda - mu I (Prop. 4.4)      */
+  double fom_rtol;   /* relative residual at which the block FOM stops (2.5e-2)           */
+  int fom_maxit;     /* block FOM iteration cap (per k-point)                             */
+  double delta, sigma, gamma, eps; /* step-size parameters of Algorithm 2                 */
+  int ls_maxit;      /* maximum energy evaluations per line search                        */
+  double tol;        /* stop when ||R||_F <= tol                                          */
+  int maxit;         /* outer iteration cap                                               */
+  double mu_warm;    /* shift correction used while ||R||_F > warm_rtol (random starts)   */
+  double warm_rtol;
+  double rank_tol;   /* deflation threshold of the rank-revealing orthonormalisation      */
+} eahp_solve_params;
+
+/* Statistics of eahp_solve (host memory, filled on return). */
+typedef struct {
+  int iters;            /* outer iterations done                         */
+  int64_t napply;       /* orbital H-applies (one column at one k)       */
+  int64_t napply_fp32;  /* of which in single precision                  */
+  int ls_trials;        /* energy evaluations in all line searches       */
+  int fom_iters;        /* block FOM iterations, summed over k and calls */
+  double energy;        /* final energy                                  */
+  double rnorm;         /* final ||R||_F                                 */
+  double seconds;       /* wall time inside eahp_solve                   */
+} eahp_stats;
+
+/* Context: binds a device and a HIP stream (hipStream_t, may be NULL for the
+ * null stream).  The stream is not owned. */
+int eahp_ctx_create(int device, void* hip_stream, eahp_ctx** out);
+void eahp_ctx_destroy(eahp_ctx* ctx);
+int eahp_ctx_set_stream(eahp_ctx* ctx, void* hip_stream);
+
+/* Builds the plane-wave bases (Sec. 5.1), the ionic potential on the FFT grid,
+ * the projectors and all device workspaces. */
+int eahp_problem_create(eahp_ctx* ctx, const eahp_system_desc* desc, eahp_problem** out);
+void eahp_problem_destroy(eahp_problem* pb);
+
+/* npw_per_k[nk], offsets[nk+1] (row offsets of the k-blocks), fft[3], p.
+ * Any output pointer may be NULL. */
+int eahp_problem_layout(const eahp_problem* pb, int64_t* npw_per_k, int64_t* offsets, int* fft, int* p);
+int eahp_problem_nk(const eahp_problem* pb);
+/* Device bytes held by the problem's workspaces. */
+size_t eahp_problem_footprint(const eahp_problem* pb);
+
+/* E(Psi) of eq. (1.1) (discrete form); terms (may be NULL) receives
+ * [kinetic, nonlocal, ionic, Hartree, exchange].  Psi: frame, orthonormal. */
+int eahp_energy(eahp_problem* pb, const void* Psi, double* E, double* terms);
+
+/* Density rho(r) = sum_k w_k f sum_i |psi_ik(r)|^2 on the FFT grid (N_g reals,
+ * layout (i1*n2+i2)*n3+i3), written to device buffer rho (may be NULL), and
+ * V_eff = V_ion + V_H + V_x of that density, which becomes the problem's
+ * current potential for eahp_apply_H. */
+int eahp_density(eahp_problem* pb, const void* Psi, void* rho, void* Veff);
+
+/* H_Psi X for a frame X (same layout as Psi): builds V_eff from the density of
+ * Psi (Sec. 5.1), then applies kinetic + local (batched 3D FFTs) + nonlocal. */
+int eahp_apply_H(eahp_problem* pb, const void* Psi, const void* X, void* HX);
+
+/* Residual of the NLEVP (Sec. 2.2): Lambda_k = Hermitian part of
+ * Psi_k^* (H Psi)_k (eq. (2.6)), R = H Psi - Psi Lambda; rnorm = ||R||_F,
+ * E = energy.  R, Lambda, rnorm, E may each be NULL. */
+int eahp_residual(eahp_problem* pb, const void* Psi, void* R, void* Lambda, double* rnorm, double* E);
+
+/* Metric solve (Appendix A, Algorithm 4) per k-point: X solves
+ * H_Psi X - X Sigma = Psi (eq. (5.2)) with Sigma = Lambda - mu I, X0 = Psi/mu,
+ * TPA preconditioner, stopped at ||E_j||_F/||C||_F <= rtol or maxit.
+ * iters_per_k, relres_per_k: host arrays of nk (may be NULL). */
+int eahp_metric_solve(eahp_problem* pb, const void* Psi, double mu, double rtol, int maxit,
+                      void* X, int* iters_per_k, double* relres_per_k);
+
+/* Energy-adaptive gradient G = Psi - X (Psi^* X)^-1 per k (Sec. 5.2). */
+int eahp_ea_gradient(eahp_problem* pb, const void* Psi, const void* X, void* G);
+
+/* Polar retraction Psi_out = pf(Psi + tau eta) (eqs. (3.1)-(3.2)), per k.
+ * Returns EAHP_ENOTPD when (Psi + tau eta)^*(Psi + tau eta) is not positive
+ * definite. */
+int eahp_retract(eahp_problem* pb, const void* Psi, const void* eta, double tau, void* Psi_out);
+
+/* Differentiated polar-retraction transport (Prop. 3.1, eqs. (3.3)-(3.4)):
+ * Tv = T_xi(v) = (v - R(xi) X) S^-1 with S = sf(Psi + xi),
+ * S X + X S = xi^* v + v^* xi. */
+int eahp_transport(eahp_problem* pb, const void* Psi, const void* xi, const void* v, void* Tv);
+
+/* One line search (Algorithm 2) on f(t) = E(R_Psi(t eta)) from tau0;
+ * on success tau, Psi_out = R_Psi(tau eta), trials (energy evaluations). */
+int eahp_linesearch(eahp_problem* pb, const void* Psi, const void* eta, double tau0,
+                    const eahp_solve_params* prm, double* tau, void* Psi_out, int* trials);
+
+/* Full EARCG solve (Algorithm 3) from Psi_inout (any full-rank frame: it is
+ * orthonormalised by pf first); the minimiser is written back.  Returns
+ * EAHP_ENOCONV (with Psi_inout holding the last iterate) at maxit. */
+int eahp_solve(eahp_problem* pb, void* Psi_inout, const eahp_solve_params* prm, eahp_stats* stats);
+
+/* Steppable form of eahp_solve (Algorithm 3): create evaluates the start
+ * point pf(Psi0), its residual and its first energy-adaptive gradient; step
+ * runs up to nsteps outer iterations (fewer when ||R||_F <= tol is reached)
+ * and fills cumulative stats; it returns EAHP_ENOCONV while not converged.
+ * The solver owns its frames (about 12 frames of device memory); Psi0 is not
+ * retained.  get copies the current iterate (may be NULL) and its scalars. */
+int eahp_solver_create(eahp_problem* pb, const void* Psi0, const eahp_solve_params* prm, eahp_solver** out);
+int eahp_solver_step(eahp_solver* sv, int nsteps, eahp_stats* stats);
+int eahp_solver_get(eahp_solver* sv, void* Psi_out, double* E, double* rnorm);
+void eahp_solver_destroy(eahp_solver* sv);
+
+/* Per-kernel timing with HIP events recorded on the context stream around
+ * every launch of the H-apply kernels: 0 = inverse y/z plane transforms,
+ * 1 = x-line transforms with the V_eff product, 2 = forward y/z transforms
+ * with the gather and kinetic term, 3 = density x-line transforms.
+ * enable(1) starts recording (and resets), read returns and resets the
+ * summed duration, the launch count and the algorithmic bytes (compulsory
+ * loads and stores of each launch) since the last read. */
+int eahp_prof_enable(eahp_ctx* ctx, int on);
+int eahp_prof_read(eahp_ctx* ctx, int kernel, double* total_ms, int64_t* launches, double* bytes);
+
+const char* eahp_strerror(int status);
+const char* eahp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EAHP_H */

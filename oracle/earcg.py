@@ -12,7 +12,13 @@ eta+ = -G+ + beta T(eta).
 
 Readings for a seeded random start (the paper starts from a partially
 converged SCF state, Sec. 5.2, where Prop. 4.4's coercivity holds):
-* mu = mu_warm while ||R||_F > warm_rtol, then the paper's mu;
+* while ||R||_F > warm_rtol the shift correction is
+  max(mu_warm, lambda_max(Lambda) - min_r V_eff(r) + 1): since
+  H >= min V_eff (kinetic and projector terms are non-negative), every
+  H - s_l, s_l an eigenvalue of Sigma = Lambda - mu I, is then positive
+  definite, the metric is coercive (Remark 4.1 with a uniform bound) and the
+  FOM is a Galerkin solve of definite systems; once ||R||_F <= warm_rtol
+  the paper's mu is used;
 * if f'(0) = <R, eta> >= 0 the direction is reset to -G; if -G is not a
   descent direction either, mu is doubled and G recomputed.
 Convergence is measured by ||R||_F (the quantity the paper plots).
@@ -69,8 +75,11 @@ def earcg(model, Phi0, prm, log=None, maxit=None, callback=None):
     st = mf.state(model, Phi)
     stats["napply"] += p_tot
 
-    def mu_for(rn):
-        return prm["mu_warm"] if rn > prm["warm_rtol"] else prm["mu"]
+    def mu_for(rn, st):
+        if rn <= prm["warm_rtol"]:
+            return prm["mu"]
+        lam_max = max(float(np.linalg.eigvalsh(L)[-1]) for L in st["lams"])
+        return max(prm["mu_warm"], lam_max - float(st["Veff"].min()) + 1.0)
 
     def gradient(st, mu):
         X, _ = metric_solve(model, st["Phi"], st["HPhi"], st["lams"], st["Veff"], mu, prm, stats)
@@ -78,7 +87,7 @@ def earcg(model, Phi0, prm, log=None, maxit=None, callback=None):
 
     st["Phi"] = Phi
     rn = float(np.linalg.norm(st["R"]))
-    mu = mu_for(rn)
+    mu = mu_for(rn, st)
     G = gradient(st, mu)
     eta = -G
     tau_prev = 1.0
@@ -102,7 +111,7 @@ def earcg(model, Phi0, prm, log=None, maxit=None, callback=None):
         stats["trials"].append(trials)
         stats["taus"].append(tau)
         rn = float(np.linalg.norm(new["R"]))
-        mu = mu_for(rn)
+        mu = mu_for(rn, new)
         stats["mus"].append(mu)
         Gn = gradient(new, mu)
         TG = mf.transport_general(model, new["Phi"], tau * eta, G, new["facs"])

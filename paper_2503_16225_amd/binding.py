@@ -1,0 +1,274 @@
+"""ctypes binding of libeahp.so (argument marshalling only).
+
+Device buffers are torch tensors on the current HIP device; host scalars and
+descriptions go through ctypes.  Frames are 1-D complex tensors holding, for
+every k-point b, the column-major n_b x p block (orbital j contiguous),
+blocks concatenated in k order (the layout of include/eahp.h).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EAHP_FP64, EAHP_MIXED = 0, 1
+_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTPD", -5: "EFOM", -6: "ELINESEARCH",
+           -7: "ENODESCENT", -8: "ENOCONV", -9: "ENONFINITE"}
+
+
+class EahpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SystemDesc(C.Structure):
+    _fields_ = [("lattice", C.c_double * 9), ("natoms", C.c_int), ("frac", C.POINTER(C.c_double)),
+                ("Z", C.POINTER(C.c_double)), ("r_loc", C.c_double), ("r_proj", C.c_double),
+                ("D_proj", C.c_double), ("ecut", C.c_double), ("fft", C.c_int * 3), ("nk", C.c_int),
+                ("kfrac", C.POINTER(C.c_double)), ("kweight", C.POINTER(C.c_double)), ("p", C.c_int),
+                ("occ", C.c_double), ("precision", C.c_int), ("terms", C.c_int)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("mu", C.c_double), ("fom_rtol", C.c_double), ("fom_maxit", C.c_int), ("delta", C.c_double),
+                ("sigma", C.c_double), ("gamma", C.c_double), ("eps", C.c_double), ("ls_maxit", C.c_int),
+                ("tol", C.c_double), ("maxit", C.c_int), ("mu_warm", C.c_double), ("warm_rtol", C.c_double),
+                ("rank_tol", C.c_double)]
+
+    @classmethod
+    def from_dict(cls, d):
+        s = cls()
+        for name, _ in cls._fields_:
+            setattr(s, name, d[name])
+        return s
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("napply", C.c_int64), ("napply_fp32", C.c_int64), ("ls_trials", C.c_int),
+                ("fom_iters", C.c_int), ("energy", C.c_double), ("rnorm", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def library_path():
+    return os.path.join(HERE, "libeahp.so")
+
+
+def load_library():
+    """Loads the in-tree libeahp.so; fails loudly when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2503_16225_amd.build`")
+    lib = C.CDLL(path)
+    vp, dp, ip, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int64)
+    sig = {
+        "eahp_ctx_create": ([C.c_int, vp, C.POINTER(vp)], C.c_int),
+        "eahp_ctx_destroy": ([vp], None),
+        "eahp_ctx_set_stream": ([vp, vp], C.c_int),
+        "eahp_problem_create": ([vp, C.POINTER(SystemDesc), C.POINTER(vp)], C.c_int),
+        "eahp_problem_destroy": ([vp], None),
+        "eahp_problem_layout": ([vp, i64p, i64p, ip, ip], C.c_int),
+        "eahp_problem_nk": ([vp], C.c_int),
+        "eahp_problem_footprint": ([vp], C.c_size_t),
+        "eahp_energy": ([vp, vp, dp, dp], C.c_int),
+        "eahp_density": ([vp, vp, vp, vp], C.c_int),
+        "eahp_apply_H": ([vp, vp, vp, vp], C.c_int),
+        "eahp_residual": ([vp, vp, vp, vp, dp, dp], C.c_int),
+        "eahp_metric_solve": ([vp, vp, C.c_double, C.c_double, C.c_int, vp, ip, dp], C.c_int),
+        "eahp_ea_gradient": ([vp, vp, vp, vp], C.c_int),
+        "eahp_retract": ([vp, vp, vp, C.c_double, vp], C.c_int),
+        "eahp_transport": ([vp, vp, vp, vp, vp], C.c_int),
+        "eahp_linesearch": ([vp, vp, vp, C.c_double, C.POINTER(SolveParams), dp, vp, ip], C.c_int),
+        "eahp_solve": ([vp, vp, C.POINTER(SolveParams), C.POINTER(Stats)], C.c_int),
+        "eahp_strerror": ([C.c_int], C.c_char_p),
+        "eahp_last_error": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc, allow=()):
+    if rc != 0 and rc not in allow:
+        lib = load_library()
+        raise EahpError(rc, lib.eahp_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def frame_to_blocks(npw, p, frame):
+    """Device-layout 1-D frame (numpy or torch) -> stacked (sum n_k) x p numpy array."""
+    f = frame.detach().cpu().numpy() if hasattr(frame, "detach") else np.asarray(frame)
+    out, o = [], 0
+    for n in npw:
+        out.append(f[o:o + n * p].reshape(p, n).T)
+        o += n * p
+    return np.concatenate(out, axis=0)
+
+
+def frame_from_blocks(npw, p, blocks):
+    """Stacked (sum n_k) x p array -> device-layout 1-D numpy array."""
+    out, o = [], 0
+    for n in npw:
+        out.append(np.ascontiguousarray(blocks[o:o + n].T).ravel())
+        o += n
+    return np.concatenate(out)
+
+
+class Problem:
+    """One crystal on one GPU (owns a context bound to torch's current stream)."""
+
+    def __init__(self, sysd, precision=EAHP_FP64, device=0):
+        import torch
+        self.torch = torch
+        lib = load_library()
+        self.lib = lib
+        self.device = torch.device("cuda", device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        ctx = C.c_void_p()
+        _check(lib.eahp_ctx_create(device, C.c_void_p(stream), C.byref(ctx)))
+        self.ctx = ctx
+        lat = np.asarray(sysd["lattice"], float)
+        self._keep = [np.ascontiguousarray(np.asarray(sysd["frac"], float).reshape(-1)),
+                      np.ascontiguousarray(np.asarray(sysd["Z"], float)),
+                      np.ascontiguousarray(np.asarray(sysd["kfrac"], float).reshape(-1)),
+                      np.ascontiguousarray(np.asarray(sysd["kweight"], float))]
+        d = SystemDesc()
+        d.lattice[:] = list(lat.flatten(order="F"))
+        d.natoms = len(self._keep[1])
+        d.frac = self._keep[0].ctypes.data_as(C.POINTER(C.c_double))
+        d.Z = self._keep[1].ctypes.data_as(C.POINTER(C.c_double))
+        d.r_loc, d.r_proj, d.D_proj = sysd["r_loc"], sysd["r_proj"], sysd["D_proj"]
+        d.ecut = sysd["ecut"]
+        d.fft[:] = [int(x) for x in sysd.get("fft", (0, 0, 0))]
+        d.nk = len(self._keep[3])
+        d.kfrac = self._keep[2].ctypes.data_as(C.POINTER(C.c_double))
+        d.kweight = self._keep[3].ctypes.data_as(C.POINTER(C.c_double))
+        d.p = sysd["p"]
+        d.occ = sysd["occ"]
+        d.precision = precision
+        d.terms = sysd.get("terms", 15)
+        pb = C.c_void_p()
+        _check(lib.eahp_problem_create(ctx, C.byref(d), C.byref(pb)))
+        self.pb = pb
+        nk = lib.eahp_problem_nk(pb)
+        npw = (C.c_int64 * nk)()
+        off = (C.c_int64 * (nk + 1))()
+        fft = (C.c_int * 3)()
+        p = C.c_int()
+        _check(lib.eahp_problem_layout(pb, npw, off, fft, C.byref(p)))
+        self.nk, self.npw, self.offsets = nk, list(npw), list(off)
+        self.fft, self.p = tuple(fft), p.value
+        self.ntot = self.offsets[-1]
+        self.size = self.ntot * self.p
+
+    # ---- buffers --------------------------------------------------------
+    def empty_frame(self):
+        return self.torch.empty(self.size, dtype=self.torch.complex128, device=self.device)
+
+    def to_device(self, blocks):
+        return self.torch.from_numpy(frame_from_blocks(self.npw, self.p, blocks)).to(self.device)
+
+    def to_blocks(self, frame):
+        return frame_to_blocks(self.npw, self.p, frame)
+
+    def lambdas(self, L):
+        a = L.detach().cpu().numpy().reshape(self.nk, self.p, self.p)
+        return [m.T for m in a]
+
+    # ---- entry points ------------------------------------------------------
+    def energy(self, Psi):
+        E = C.c_double()
+        terms = (C.c_double * 5)()
+        _check(self.lib.eahp_energy(self.pb, _ptr(Psi), C.byref(E), terms))
+        return E.value, list(terms)
+
+    def density(self, Psi):
+        n = int(np.prod(self.fft))
+        rho = self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+        veff = self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+        _check(self.lib.eahp_density(self.pb, _ptr(Psi), _ptr(rho), _ptr(veff)))
+        return rho, veff
+
+    def apply_H(self, Psi, X):
+        HX = self.empty_frame()
+        _check(self.lib.eahp_apply_H(self.pb, _ptr(Psi), _ptr(X), _ptr(HX)))
+        return HX
+
+    def residual(self, Psi):
+        R = self.empty_frame()
+        L = self.torch.empty(self.nk * self.p * self.p, dtype=self.torch.complex128, device=self.device)
+        rn, E = C.c_double(), C.c_double()
+        _check(self.lib.eahp_residual(self.pb, _ptr(Psi), _ptr(R), _ptr(L), C.byref(rn), C.byref(E)))
+        return R, L, rn.value, E.value
+
+    def metric_solve(self, Psi, mu, rtol, maxit=50):
+        X = self.empty_frame()
+        it = (C.c_int * self.nk)()
+        rr = (C.c_double * self.nk)()
+        _check(self.lib.eahp_metric_solve(self.pb, _ptr(Psi), mu, rtol, maxit, _ptr(X), it, rr))
+        return X, list(it), list(rr)
+
+    def ea_gradient(self, Psi, X):
+        G = self.empty_frame()
+        _check(self.lib.eahp_ea_gradient(self.pb, _ptr(Psi), _ptr(X), _ptr(G)))
+        return G
+
+    def retract(self, Psi, eta, tau):
+        out = self.empty_frame()
+        _check(self.lib.eahp_retract(self.pb, _ptr(Psi), _ptr(eta), tau, _ptr(out)))
+        return out
+
+    def transport(self, Psi, xi, v):
+        out = self.empty_frame()
+        _check(self.lib.eahp_transport(self.pb, _ptr(Psi), _ptr(xi), _ptr(v), _ptr(out)))
+        return out
+
+    def linesearch(self, Psi, eta, tau0, params):
+        prm = SolveParams.from_dict(params)
+        tau = C.c_double()
+        trials = C.c_int()
+        out = self.empty_frame()
+        _check(self.lib.eahp_linesearch(self.pb, _ptr(Psi), _ptr(eta), tau0, C.byref(prm), C.byref(tau), _ptr(out),
+                                        C.byref(trials)))
+        return tau.value, out, trials.value
+
+    def solve(self, Psi, params, allow_noconv=False):
+        prm = SolveParams.from_dict(params)
+        st = Stats()
+        rc = self.lib.eahp_solve(self.pb, _ptr(Psi), C.byref(prm), C.byref(st))
+        _check(rc, allow=(-8,) if allow_noconv else ())
+        return st.as_dict(), rc
+
+    def footprint(self):
+        return int(self.lib.eahp_problem_footprint(self.pb))
+
+    def close(self):
+        if getattr(self, "pb", None):
+            self.lib.eahp_problem_destroy(self.pb)
+            self.pb = None
+        if getattr(self, "ctx", None):
+            self.lib.eahp_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

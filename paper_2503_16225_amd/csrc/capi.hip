@@ -1,0 +1,613 @@
+// C entry points, the line search (Algorithm 2) and the EARCG driver
+// (Algorithm 3).  Control flow runs on the host; every vector, matrix and
+// reduction operation is a device kernel; only scalars (energies, pairings,
+// norms, ranks) cross to the host.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "ops.h"
+#include "setup.h"
+
+using namespace eahp;
+
+namespace {
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    f();
+    return EAHP_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return EAHP_ENOMEM;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return EAHP_EDEVICE;
+  }
+}
+
+z64* frame(eahp_problem* pb, int i) {
+  pb->ws.f[i].ensure(sizeof(z64) * pb->ntot * pb->p);
+  return pb->ws.f[i].as<z64>();
+}
+
+void check_problem(eahp_problem* pb) {
+  if (!pb) fail(EAHP_EINVAL, "null problem");
+  HIPCK(hipSetDevice(pb->ctx->device));
+}
+
+// ------------------------------------------------------------------ line search
+struct Trial {
+  z64 *Phi, *HPhi, *R, *Lam, *Teta;
+  RetractFactors* F;
+  PointScalars sc;
+  double df;
+};
+
+// f(t), f'(t) at R_Phi(t eta) into the trial buffers
+void eval_trial(eahp_problem* pb, const z64* Phi, const z64* eta, double t, Trial& tr) {
+  retract(pb, Phi, eta, t, tr.Phi, *tr.F);
+  evaluate_point(pb, tr.Phi, tr.HPhi, tr.R, tr.Lam, &tr.sc);
+  transport_self(pb, tr.Phi, eta, t, *tr.F, tr.Teta);
+  tr.df = frame_dot(pb, tr.R, tr.Teta);
+  if (!std::isfinite(tr.df)) fail(EAHP_ENONFINITE, "non-finite slope in the line search");
+}
+
+// Modified secant step (Algorithm 2) with the readings documented with the
+// oracle's line search: approximate Wolfe test f <= f0 + eps|f0| and
+// |f'| <= min(sigma, 1 - 2 delta)|f'(0)|; bisection on equal slopes; a secant
+// point left of a enlarges the bracket without an evaluation; a kept bracket
+// whose right end has energy above f0 is bisected next.  The accepted point is
+// always the last evaluated one, left in tr.
+double secant_step(eahp_problem* pb, const z64* Phi, const z64* eta, double f0, double df0, double tau0,
+                   const eahp_solve_params& prm, Trial& tr, int* trials_out) {
+  const double c = std::min(prm.sigma, 1.0 - 2.0 * prm.delta);
+  const double fbound = f0 + prm.eps * std::fabs(f0);
+  int trials = 0;
+  auto ev = [&](double t) {
+    if (trials >= prm.ls_maxit) fail(EAHP_ELINESEARCH, "line search: no acceptable step");
+    ++trials;
+    eval_trial(pb, Phi, eta, t, tr);
+  };
+  auto ok = [&](double f, double df) { return f <= fbound && std::fabs(df) <= c * std::fabs(df0); };
+  double a = 0.0, dfa = df0;
+  double b = tau0;
+  ev(b);
+  double dfb = tr.df;
+  double tau = b, ft = tr.sc.E, dft = tr.df;
+  bool bisect = false;
+  while (!ok(ft, dft)) {
+    const double den = dfb - dfa;
+    double tn;
+    if (bisect) {
+      tn = 0.5 * (a + b);
+      bisect = false;
+    } else if (den != 0.0 && std::isfinite(den)) {
+      tn = (a * dfb - b * dfa) / den;
+    } else {
+      tn = 0.5 * (a + b);
+    }
+    if (tn < a) {
+      tau = b / prm.gamma;
+      a = 0.0;
+      dfa = df0;
+      b = tau;
+      ev(b);
+      dfb = tr.df;
+      ft = tr.sc.E;
+      dft = tr.df;
+      continue;
+    }
+    ev(tn);
+    const double fn = tr.sc.E, dfn = tr.df;
+    if (fn > fbound && dfn < 0.0) {
+      tau = prm.gamma * b;
+      a = 0.0;
+      dfa = df0;
+      b = tau;
+      ev(b);
+      dfb = tr.df;
+      ft = tr.sc.E;
+      dft = tr.df;
+    } else if (tn > b) {
+      a = b;
+      dfa = dfb;
+      b = tn;
+      dfb = dfn;
+      tau = tn;
+      ft = fn;
+      dft = dfn;
+    } else {
+      tau = tn;
+      ft = fn;
+      dft = dfn;
+      if (dfn >= 0.0) {
+        b = tn;
+        dfb = dfn;
+        bisect = fn > fbound;
+      } else {
+        a = tn;
+        dfa = dfn;
+      }
+    }
+  }
+  if (trials_out) *trials_out = trials;
+  return tau;
+}
+
+}  // namespace
+
+struct eahp_solver {
+  eahp_problem* pb = nullptr;
+  eahp_solve_params prm{};
+  DevMem fr[12], lamA, lamB, lamw;
+  RetractFactors Fa, Fb;
+  RetractFactors* Ft = nullptr;
+  z64 *Phi = nullptr, *HPhi = nullptr, *R = nullptr, *Phit = nullptr, *HPhit = nullptr, *Rt = nullptr;
+  z64 *eta = nullptr, *G = nullptr, *X = nullptr, *Tetat = nullptr, *TG = nullptr, *xi = nullptr;
+  z64 *Lam = nullptr, *Lamt = nullptr;
+  PointScalars sc;
+  double rn = 0, mu = 0, tau_prev = 1.0;
+  int it = 0, ls_trials = 0, fom_iters = 0;
+  int64_t napply = 0, napply32 = 0;
+  double seconds = 0;
+};
+
+namespace {
+
+bool solver_converged(const eahp_solver* sv) { return sv->rn <= sv->prm.tol; }
+
+// Shift correction: the paper's mu once ||R||_F <= warm_rtol; before that
+// max(mu_warm, lambda_max(Lambda) - min V_eff + 1), which makes every
+// H - s_l (s_l eigenvalues of Sigma) positive definite because H >= min V_eff.
+double mu_for(eahp_solver* sv, double r, const z64* Lam) {
+  if (r <= sv->prm.warm_rtol) return sv->prm.mu;
+  eahp_problem* pb = sv->pb;
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p, nk = pb->nk;
+  const int64_t pp = (int64_t)p * p;
+  sv->lamw.ensure(sizeof(z64) * nk * pp * 2 + sizeof(double) * nk * p);
+  z64* A = sv->lamw.as<z64>();
+  z64* V = A + nk * pp;
+  double* w = reinterpret_cast<double*>(V + nk * pp);
+  copy2d(st, p, p * nk, Lam, p, A, p);
+  heev(st, p, A, p, pp, w, p, V, p, pp, nk, pb->d_info.as<int>());
+  maxval(st, nk * p, w, scal(pb, S_DOT2));
+  minval_big(st, pb->Ng, pb->d_veff.as<double>(), scal(pb, S_DOT3), pb->ws.partial);
+  fetch_scalars(pb, S_DOT3 + 1);
+  return std::max(sv->prm.mu_warm, pb->h_scal[S_DOT2] - pb->h_scal[S_DOT3] + 1.0);
+}
+
+void solver_gradient(eahp_solver* sv, const z64* P, const z64* Rr, const z64* L, double m, z64* Gout) {
+  eahp_problem* pb = sv->pb;
+  metric_solve(pb, P, Rr, L, m, sv->prm.fom_rtol, sv->prm.fom_maxit, sv->prm.rank_tol, sv->X, nullptr);
+  ea_gradient(pb, P, sv->X, Gout);
+}
+
+struct Counters {
+  eahp_solver* sv;
+  std::chrono::steady_clock::time_point t0;
+  int64_t a0, a32;
+  int f0;
+  explicit Counters(eahp_solver* s)
+      : sv(s), t0(std::chrono::steady_clock::now()), a0(s->pb->napply), a32(s->pb->napply32), f0(s->pb->fom_iters) {}
+  ~Counters() {
+    sv->napply += sv->pb->napply - a0;
+    sv->napply32 += sv->pb->napply32 - a32;
+    sv->fom_iters += sv->pb->fom_iters - f0;
+    sv->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+void solver_init(eahp_solver* sv, const z64* Psi0) {
+  eahp_problem* pb = sv->pb;
+  Counters cnt(sv);
+  const size_t fb = sizeof(z64) * pb->ntot * pb->p;
+  for (auto& f : sv->fr) f.alloc(fb);
+  const size_t lamb = sizeof(z64) * pb->nk * pb->p * pb->p;
+  sv->lamA.alloc(lamb);
+  sv->lamB.alloc(lamb);
+  sv->Phi = sv->fr[0].as<z64>();
+  sv->HPhi = sv->fr[1].as<z64>();
+  sv->R = sv->fr[2].as<z64>();
+  sv->Phit = sv->fr[3].as<z64>();
+  sv->HPhit = sv->fr[4].as<z64>();
+  sv->Rt = sv->fr[5].as<z64>();
+  sv->eta = sv->fr[6].as<z64>();
+  sv->G = sv->fr[7].as<z64>();
+  sv->X = sv->fr[8].as<z64>();
+  sv->Tetat = sv->fr[9].as<z64>();
+  sv->TG = sv->fr[10].as<z64>();
+  sv->xi = sv->fr[11].as<z64>();
+  sv->Lam = sv->lamA.as<z64>();
+  sv->Lamt = sv->lamB.as<z64>();
+  sv->Ft = &sv->Fb;
+  // Phi^(0) = pf(Psi0)
+  retract(pb, Psi0, Psi0, 0.0, sv->Phi, sv->Fa);
+  evaluate_point(pb, sv->Phi, sv->HPhi, sv->R, sv->Lam, &sv->sc);
+  sv->rn = sv->sc.rnorm;
+  sv->mu = mu_for(sv, sv->rn, sv->Lam);
+  solver_gradient(sv, sv->Phi, sv->R, sv->Lam, sv->mu, sv->G);
+  axpby<double>(pb->ctx->stream, pb->ntot * pb->p, -1.0, sv->G, 0.0, sv->eta);
+  sv->tau_prev = 1.0;
+}
+
+// One outer iteration of Algorithm 3.
+void solver_iterate(eahp_solver* sv) {
+  eahp_problem* pb = sv->pb;
+  Counters cnt(sv);
+  hipStream_t st = pb->ctx->stream;
+  const int64_t N = pb->ntot * pb->p;
+  const eahp_solve_params& prm = sv->prm;
+  double df0 = frame_dot(pb, sv->R, sv->eta);
+  if (!(df0 < 0.0)) {
+    // reset to the gradient direction; if that fails too, enlarge mu
+    axpby<double>(st, N, -1.0, sv->G, 0.0, sv->eta);
+    df0 = frame_dot(pb, sv->R, sv->eta);
+    int doublings = 0;
+    while (!(df0 < 0.0)) {
+      if (++doublings > 30) fail(EAHP_ENODESCENT, "no descent direction");
+      sv->mu *= 2.0;
+      evaluate_point(pb, sv->Phi, sv->HPhi, sv->R, sv->Lam, &sv->sc);  // makes V_eff current
+      solver_gradient(sv, sv->Phi, sv->R, sv->Lam, sv->mu, sv->G);
+      axpby<double>(st, N, -1.0, sv->G, 0.0, sv->eta);
+      df0 = frame_dot(pb, sv->R, sv->eta);
+    }
+  }
+  Trial tr{sv->Phit, sv->HPhit, sv->Rt, sv->Lamt, sv->Tetat, sv->Ft, {}, 0};
+  int trials = 0;
+  const double tau = secant_step(pb, sv->Phi, sv->eta, sv->sc.E, df0, sv->tau_prev, prm, tr, &trials);
+  sv->ls_trials += trials;
+  const double rg = frame_dot(pb, sv->R, sv->G);
+  // the accepted point is in the trial buffers (it was evaluated last)
+  std::swap(sv->Phi, sv->Phit);
+  std::swap(sv->HPhi, sv->HPhit);
+  std::swap(sv->R, sv->Rt);
+  std::swap(sv->Lam, sv->Lamt);
+  RetractFactors* Facc = sv->Ft;
+  sv->Ft = (sv->Ft == &sv->Fb) ? &sv->Fa : &sv->Fb;
+  sv->sc = tr.sc;
+  sv->rn = sv->sc.rnorm;
+  sv->mu = mu_for(sv, sv->rn, sv->Lam);
+  // T_{tau eta}(G_old), before eta and G change
+  axpby<double>(st, N, tau, sv->eta, 0.0, sv->xi);
+  transport_general(pb, sv->Phi, sv->xi, sv->G, *Facc, sv->TG);
+  z64* Gn = sv->Phit;  // the previous point's buffer is free
+  solver_gradient(sv, sv->Phi, sv->R, sv->Lam, sv->mu, Gn);
+  const double rgn = frame_dot(pb, sv->R, Gn);
+  const double rtg = frame_dot(pb, sv->R, sv->TG);
+  const double fr = rgn / rg;
+  const double prp = (rgn - rtg) / rg;
+  const double beta = std::max(0.0, std::min(fr, prp));
+  // eta = -G_new + beta T(eta)
+  axpby<double>(st, N, -1.0, Gn, 0.0, sv->eta);
+  axpby<double>(st, N, beta, sv->Tetat, 1.0, sv->eta);
+  std::swap(sv->G, sv->Phit);
+  sv->tau_prev = tau;
+  ++sv->it;
+}
+
+void solver_stats(const eahp_solver* sv, eahp_stats* s) {
+  s->iters = sv->it;
+  s->napply = sv->napply;
+  s->napply_fp32 = sv->napply32;
+  s->ls_trials = sv->ls_trials;
+  s->fom_iters = sv->fom_iters;
+  s->energy = sv->sc.E;
+  s->rnorm = sv->rn;
+  s->seconds = sv->seconds;
+}
+
+}  // namespace
+
+// ====================================================================== C API
+extern "C" {
+
+const char* eahp_strerror(int s) {
+  switch (s) {
+    case EAHP_OK: return "ok";
+    case EAHP_EINVAL: return "invalid argument";
+    case EAHP_ENOMEM: return "out of memory";
+    case EAHP_EDEVICE: return "HIP runtime error";
+    case EAHP_ENOTPD: return "retraction Gram matrix not positive definite";
+    case EAHP_EFOM: return "metric solve breakdown";
+    case EAHP_ELINESEARCH: return "line search failed";
+    case EAHP_ENODESCENT: return "no descent direction";
+    case EAHP_ENOCONV: return "not converged";
+    case EAHP_ENONFINITE: return "non-finite value";
+    default: return "unknown status";
+  }
+}
+
+const char* eahp_last_error(void) { return g_last_error.c_str(); }
+
+int eahp_ctx_create(int device, void* hip_stream, eahp_ctx** out) {
+  return guarded([&] {
+    if (!out) fail(EAHP_EINVAL, "null output");
+    int n = 0;
+    HIPCK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) fail(EAHP_EINVAL, "no such device");
+    HIPCK(hipSetDevice(device));
+    auto* c = new eahp_ctx;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+  });
+}
+
+void eahp_ctx_destroy(eahp_ctx* ctx) { delete ctx; }
+
+int eahp_ctx_set_stream(eahp_ctx* ctx, void* hip_stream) {
+  return guarded([&] {
+    if (!ctx) fail(EAHP_EINVAL, "null context");
+    ctx->stream = (hipStream_t)hip_stream;
+  });
+}
+
+int eahp_problem_create(eahp_ctx* ctx, const eahp_system_desc* desc, eahp_problem** out) {
+  eahp_problem* pb = nullptr;
+  const int rc = guarded([&] {
+    if (!ctx || !desc || !out) fail(EAHP_EINVAL, "null argument");
+    HIPCK(hipSetDevice(ctx->device));
+    pb = new eahp_problem;
+    pb->ctx = ctx;
+    build_problem(pb, desc);
+    *out = pb;
+  });
+  if (rc != EAHP_OK) delete pb;
+  return rc;
+}
+
+void eahp_problem_destroy(eahp_problem* pb) {
+  if (pb) {
+    (void)hipSetDevice(pb->ctx->device);
+    (void)hipDeviceSynchronize();
+  }
+  delete pb;
+}
+
+int eahp_problem_nk(const eahp_problem* pb) { return pb ? pb->nk : 0; }
+
+int eahp_problem_layout(const eahp_problem* pb, int64_t* npw, int64_t* offsets, int* fft, int* p) {
+  return guarded([&] {
+    if (!pb) fail(EAHP_EINVAL, "null problem");
+    for (int k = 0; k < pb->nk; ++k) {
+      if (npw) npw[k] = pb->kp[k].npw;
+      if (offsets) offsets[k] = pb->kp[k].off;
+    }
+    if (offsets) offsets[pb->nk] = pb->ntot;
+    if (fft)
+      for (int d = 0; d < 3; ++d) fft[d] = pb->n[d];
+    if (p) *p = pb->p;
+  });
+}
+
+size_t eahp_problem_footprint(const eahp_problem* pb) {
+  if (!pb) return 0;
+  size_t b = pb->d_vion.bytes + pb->d_veff.bytes + pb->d_veff32.bytes + pb->d_rho.bytes + pb->d_box.bytes +
+             pb->ws.planes.bytes + pb->ws.gemm_part.bytes + pb->ws.small.bytes + pb->ws.partial.bytes;
+  for (auto& K : pb->kp) b += K.d_kin.bytes + K.d_kin32.bytes + K.d_box.bytes + K.d_proj.bytes + K.d_proj32.bytes;
+  for (auto& f : pb->ws.f) b += f.bytes;
+  return b;
+}
+
+int eahp_density(eahp_problem* pb, const void* Psi, void* rho, void* Veff) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!Psi) fail(EAHP_EINVAL, "null frame");
+    hipStream_t st = pb->ctx->stream;
+    density_potentials(pb, (const z64*)Psi);
+    if (rho) HIPCK(hipMemcpyAsync(rho, pb->d_rho.p, sizeof(double) * pb->Ng, hipMemcpyDeviceToDevice, st));
+    if (Veff) HIPCK(hipMemcpyAsync(Veff, pb->d_veff.p, sizeof(double) * pb->Ng, hipMemcpyDeviceToDevice, st));
+    HIPCK(hipStreamSynchronize(st));
+  });
+}
+
+int eahp_energy(eahp_problem* pb, const void* Psi, double* E, double* terms) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!Psi || !E) fail(EAHP_EINVAL, "null argument");
+    PointScalars sc;
+    DevMem lam;
+    lam.alloc(sizeof(z64) * pb->nk * pb->p * pb->p);
+    evaluate_point(pb, (const z64*)Psi, frame(pb, 0), frame(pb, 1), lam.as<z64>(), &sc);
+    *E = sc.E;
+    if (terms)
+      for (int i = 0; i < 5; ++i) terms[i] = sc.terms[i];
+  });
+}
+
+int eahp_apply_H(eahp_problem* pb, const void* Psi, const void* X, void* HX) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!Psi || !X || !HX) fail(EAHP_EINVAL, "null argument");
+    density_potentials(pb, (const z64*)Psi);
+    apply_H_frame(pb, (const z64*)X, (z64*)HX, X == Psi, nullptr);
+    HIPCK(hipStreamSynchronize(pb->ctx->stream));
+  });
+}
+
+int eahp_residual(eahp_problem* pb, const void* Psi, void* R, void* Lambda, double* rnorm, double* E) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!Psi) fail(EAHP_EINVAL, "null frame");
+    PointScalars sc;
+    DevMem lam;
+    z64* L = (z64*)Lambda;
+    if (!L) {
+      lam.alloc(sizeof(z64) * pb->nk * pb->p * pb->p);
+      L = lam.as<z64>();
+    }
+    z64* Rb = R ? (z64*)R : frame(pb, 1);
+    evaluate_point(pb, (const z64*)Psi, frame(pb, 0), Rb, L, &sc);
+    if (rnorm) *rnorm = sc.rnorm;
+    if (E) *E = sc.E;
+  });
+}
+
+int eahp_metric_solve(eahp_problem* pb, const void* Psi, double mu, double rtol, int maxit, void* X, int* iters,
+                      double* relres) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!Psi || !X) fail(EAHP_EINVAL, "null argument");
+    if (maxit <= 0 || !(rtol >= 0)) fail(EAHP_EINVAL, "bad FOM limits");
+    DevMem lam;
+    lam.alloc(sizeof(z64) * pb->nk * pb->p * pb->p);
+    evaluate_point(pb, (const z64*)Psi, frame(pb, 0), frame(pb, 1), lam.as<z64>(), nullptr);
+    std::vector<FomInfo> info;
+    metric_solve(pb, (const z64*)Psi, frame(pb, 1), lam.as<z64>(), mu, rtol, maxit, 1e-7, (z64*)X, &info);
+    for (int k = 0; k < pb->nk; ++k) {
+      if (iters) iters[k] = info[k].iters;
+      if (relres) relres[k] = info[k].relres;
+    }
+    HIPCK(hipStreamSynchronize(pb->ctx->stream));
+  });
+}
+
+int eahp_ea_gradient(eahp_problem* pb, const void* Psi, const void* X, void* G) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!Psi || !X || !G) fail(EAHP_EINVAL, "null argument");
+    ea_gradient(pb, (const z64*)Psi, (const z64*)X, (z64*)G);
+  });
+}
+
+int eahp_retract(eahp_problem* pb, const void* Psi, const void* eta, double tau, void* Psi_out) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!Psi || !eta || !Psi_out) fail(EAHP_EINVAL, "null argument");
+    RetractFactors F;
+    retract(pb, (const z64*)Psi, (const z64*)eta, tau, (z64*)Psi_out, F);
+    HIPCK(hipStreamSynchronize(pb->ctx->stream));
+  });
+}
+
+int eahp_transport(eahp_problem* pb, const void* Psi, const void* xi, const void* v, void* Tv) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!Psi || !xi || !v || !Tv) fail(EAHP_EINVAL, "null argument");
+    RetractFactors F;
+    z64* Pn = frame(pb, 2);
+    retract(pb, (const z64*)Psi, (const z64*)xi, 1.0, Pn, F);
+    transport_general(pb, Pn, (const z64*)xi, (const z64*)v, F, (z64*)Tv);
+    HIPCK(hipStreamSynchronize(pb->ctx->stream));
+  });
+}
+
+int eahp_linesearch(eahp_problem* pb, const void* Psi, const void* eta, double tau0, const eahp_solve_params* prm,
+                    double* tau, void* Psi_out, int* trials) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!Psi || !eta || !prm || !tau) fail(EAHP_EINVAL, "null argument");
+    DevMem lam0, lam1;
+    lam0.alloc(sizeof(z64) * pb->nk * pb->p * pb->p);
+    lam1.alloc(sizeof(z64) * pb->nk * pb->p * pb->p);
+    PointScalars s0;
+    evaluate_point(pb, (const z64*)Psi, frame(pb, 0), frame(pb, 1), lam0.as<z64>(), &s0);
+    const double df0 = frame_dot(pb, frame(pb, 1), (const z64*)eta);
+    if (!(df0 < 0)) fail(EAHP_ENODESCENT, "eta is not a descent direction");
+    RetractFactors F;
+    Trial tr{frame(pb, 2), frame(pb, 3), frame(pb, 4), lam1.as<z64>(), frame(pb, 5), &F, {}, 0};
+    *tau = secant_step(pb, (const z64*)Psi, (const z64*)eta, s0.E, df0, tau0, *prm, tr, trials);
+    if (Psi_out)
+      HIPCK(hipMemcpyAsync(Psi_out, tr.Phi, sizeof(z64) * pb->ntot * pb->p, hipMemcpyDeviceToDevice, pb->ctx->stream));
+    HIPCK(hipStreamSynchronize(pb->ctx->stream));
+  });
+}
+
+int eahp_solver_create(eahp_problem* pb, const void* Psi0, const eahp_solve_params* prmp, eahp_solver** out) {
+  eahp_solver* sv = nullptr;
+  const int rc = guarded([&] {
+    check_problem(pb);
+    if (!Psi0 || !prmp || !out) fail(EAHP_EINVAL, "null argument");
+    const eahp_solve_params& prm = *prmp;
+    if (!(prm.mu > 0) || !(prm.mu_warm > 0) || prm.fom_maxit <= 0 || prm.ls_maxit <= 0 ||
+        !(prm.gamma > 0 && prm.gamma < 1))
+      fail(EAHP_EINVAL, "bad solve parameters");
+    sv = new eahp_solver;
+    sv->pb = pb;
+    sv->prm = prm;
+    solver_init(sv, (const z64*)Psi0);
+    *out = sv;
+  });
+  if (rc != EAHP_OK) delete sv;
+  return rc;
+}
+
+int eahp_solver_step(eahp_solver* sv, int nsteps, eahp_stats* stats) {
+  int rc = guarded([&] {
+    if (!sv) fail(EAHP_EINVAL, "null solver");
+    check_problem(sv->pb);
+    for (int i = 0; i < nsteps && !solver_converged(sv); ++i) solver_iterate(sv);
+  });
+  if (sv && stats) solver_stats(sv, stats);
+  if (rc == EAHP_OK && sv && !solver_converged(sv)) rc = EAHP_ENOCONV;
+  return rc;
+}
+
+int eahp_solver_get(eahp_solver* sv, void* Psi_out, double* E, double* rnorm) {
+  return guarded([&] {
+    if (!sv) fail(EAHP_EINVAL, "null solver");
+    if (Psi_out)
+      HIPCK(hipMemcpyAsync(Psi_out, sv->Phi, sizeof(z64) * sv->pb->ntot * sv->pb->p, hipMemcpyDeviceToDevice,
+                           sv->pb->ctx->stream));
+    HIPCK(hipStreamSynchronize(sv->pb->ctx->stream));
+    if (E) *E = sv->sc.E;
+    if (rnorm) *rnorm = sv->rn;
+  });
+}
+
+void eahp_solver_destroy(eahp_solver* sv) {
+  if (sv) (void)hipStreamSynchronize(sv->pb->ctx->stream);
+  delete sv;
+}
+
+int eahp_solve(eahp_problem* pb, void* Psi_inout, const eahp_solve_params* prmp, eahp_stats* stats) {
+  eahp_solver* sv = nullptr;
+  int rc = eahp_solver_create(pb, Psi_inout, prmp, &sv);
+  if (rc != EAHP_OK) {
+    if (stats) *stats = eahp_stats{};
+    return rc;
+  }
+  rc = eahp_solver_step(sv, prmp->maxit, stats);
+  const int rc2 = eahp_solver_get(sv, Psi_inout, nullptr, nullptr);
+  eahp_solver_destroy(sv);
+  return rc != EAHP_OK ? rc : rc2;
+}
+
+int eahp_prof_enable(eahp_ctx* ctx, int on) {
+  return guarded([&] {
+    if (!ctx) fail(EAHP_EINVAL, "null context");
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    ctx->prof = on != 0;
+    for (auto& s : ctx->slot) {
+      s.used = 0;
+      s.bytes = 0;
+    }
+  });
+}
+
+int eahp_prof_read(eahp_ctx* ctx, int kernel, double* total_ms, int64_t* launches, double* bytes) {
+  return guarded([&] {
+    if (!ctx || kernel < 0 || kernel >= kProfKernels) fail(EAHP_EINVAL, "bad kernel id");
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    ProfSlot& s = ctx->slot[kernel];
+    double tot = 0;
+    for (int i = 0; i < s.used; ++i) {
+      float ms = 0;
+      HIPCK(hipEventElapsedTime(&ms, s.start[i], s.stop[i]));
+      tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = s.used;
+    if (bytes) *bytes = s.bytes;
+    s.used = 0;
+    s.bytes = 0;
+  });
+}
+
+}  // extern "C"

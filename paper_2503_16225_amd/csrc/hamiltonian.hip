@@ -1,0 +1,485 @@
+// Kohn-Sham H-apply, density and potentials on gfx950.
+//
+// Local potential (Sec. 5.1; plane-wave discretisation): for each orbital the
+// sphere coefficients are scattered into a pruned FFT box, transformed to the
+// grid, multiplied by V_eff and transformed back.  The box is never
+// materialised: only the x-planes that hold plane waves ("active planes") are
+// kept, in an intermediate buffer T laid out [column][plane s][i2][i3].
+//
+//   inv_yz  : one work-group per (plane, column); scatter the plane's sphere
+//             coefficients into a whole i2 x i3 plane in LDS, inverse z- and
+//             y-transforms in LDS, one coalesced store of the plane.
+//   x_local : one work-group per tile of (i2, i3) positions and a chunk of
+//             columns; loads the active-plane values of the tile, inverse
+//             x-transform, multiply by V_eff (tile kept in LDS and reused by
+//             the chunk's columns), forward x-transform, stores the active
+//             planes back.
+//   fwd_yz  : forward y- and z-transforms of a plane in LDS, gather of the
+//             sphere coefficients, scaled by 1/N_g, plus the kinetic term.
+//   x_density: inverse x-transform of every column of a tile and accumulation
+//             of w_k f |psi|^2 / Omega in registers (fixed order, no atomics).
+#include <cmath>
+
+#include "devcommon.h"
+#include "kernels.h"
+
+namespace eahp {
+
+template <typename T> __device__ __forceinline__ const T* kin_of(const KDesc& k);
+template <> __device__ __forceinline__ const double* kin_of<double>(const KDesc& k) { return k.kin; }
+template <> __device__ __forceinline__ const float* kin_of<float>(const KDesc& k) { return k.kin32; }
+
+__device__ __forceinline__ const KDesc& col_kd(const ColMap& cm, int c, int64_t& base) {
+  const int kk = cm.k0 + c / cm.cpk;
+  const int j = c - (c / cm.cpk) * cm.cpk;
+  const KDesc& k = cm.kd[kk];
+  base = (cm.frame ? (int64_t)cm.cpk * k.off : 0) + (int64_t)j * k.npw;
+  return k;
+}
+
+static int pick_maxpts(int64_t pts, int nt) {
+  const int64_t per = (pts + nt - 1) / nt;
+  if (per <= 4) return 4;
+  if (per <= 8) return 8;
+  if (per <= 16) return 16;
+  if (per <= 32) return 32;
+  fail(EAHP_EINVAL, "FFT work per thread too large");
+}
+
+// ------------------------------------------------------------------ inv_yz
+template <typename T, int MAXPTS>
+__global__ void __launch_bounds__(1024) k_inv_yz(ColMap cm, GridGeom g, FftPlan pz, FftPlan py,
+                                                 const cplx<T>* __restrict__ twz, const cplx<T>* __restrict__ twy,
+                                                 const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Tb) {
+  extern __shared__ unsigned char smem_raw[];
+  const int np = g.n2 * g.n3;
+  cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* tz = pl + np;
+  cplx<T>* ty = tz + g.n3;
+  const int s = blockIdx.x, c = blockIdx.y;
+  int64_t base;
+  const KDesc& k = col_kd(cm, c, base);
+  for (int i = threadIdx.x; i < np; i += blockDim.x) pl[i] = mk<T>(0, 0);
+  for (int i = threadIdx.x; i < g.n3; i += blockDim.x) tz[i] = twz[i];
+  for (int i = threadIdx.x; i < g.n2; i += blockDim.x) ty[i] = twy[i];
+  __syncthreads();
+  const int g0 = k.plane_start[s], g1 = k.plane_start[s + 1];
+  const cplx<T>* x = X + base;
+  for (int r = g0 + threadIdx.x; r < g1; r += blockDim.x) pl[k.box[r] % np] = x[r];
+  __syncthreads();
+  lds_fft<T, MAXPTS>(pl, Lines{g.n3, 1, g.n2, g.n3, 0}, pz, tz, (T)1);
+  lds_fft<T, MAXPTS>(pl, Lines{g.n2, g.n3, g.n3, 1, 1}, py, ty, (T)1);
+  cplx<T>* out = Tb + ((int64_t)c * g.ns + s) * np;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) out[i] = pl[i];
+}
+
+// ------------------------------------------------------------------ fwd_yz
+template <typename T, int MAXPTS>
+__global__ void __launch_bounds__(1024) k_fwd_yz(ColMap cm, GridGeom g, FftPlan pz, FftPlan py,
+                                                 const cplx<T>* __restrict__ twz, const cplx<T>* __restrict__ twy,
+                                                 const cplx<T>* __restrict__ Tb, const cplx<T>* __restrict__ X,
+                                                 cplx<T>* __restrict__ HX, T scale) {
+  extern __shared__ unsigned char smem_raw[];
+  const int np = g.n2 * g.n3;
+  cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* tz = pl + np;
+  cplx<T>* ty = tz + g.n3;
+  const int s = blockIdx.x, c = blockIdx.y;
+  int64_t base;
+  const KDesc& k = col_kd(cm, c, base);
+  const int g0 = k.plane_start[s], g1 = k.plane_start[s + 1];
+  if (g1 == g0) return;  // block-uniform: this k-point has no plane waves here
+  const cplx<T>* in = Tb + ((int64_t)c * g.ns + s) * np;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) pl[i] = in[i];
+  for (int i = threadIdx.x; i < g.n3; i += blockDim.x) tz[i] = twz[i];
+  for (int i = threadIdx.x; i < g.n2; i += blockDim.x) ty[i] = twy[i];
+  __syncthreads();
+  lds_fft<T, MAXPTS>(pl, Lines{g.n2, g.n3, g.n3, 1, 1}, py, ty, (T)-1);
+  lds_fft<T, MAXPTS>(pl, Lines{g.n3, 1, g.n2, g.n3, 0}, pz, tz, (T)-1);
+  const T* kin = kin_of<T>(k);
+  const cplx<T>* x = X + base;
+  cplx<T>* y = HX + base;
+  for (int r = g0 + threadIdx.x; r < g1; r += blockDim.x) {
+    const cplx<T> v = pl[k.box[r] % np];
+    const cplx<T> xv = x[r];
+    const T kr = kin[r];
+    y[r] = mk<T>(v.x * scale + kr * xv.x, v.y * scale + kr * xv.y);
+  }
+}
+
+// ------------------------------------------------------------------ x_local
+template <typename T, int MAXPTS>
+__global__ void __launch_bounds__(512) k_x_local(int ncols, int cb, GridGeom g, int tile, FftPlan px,
+                                                 const cplx<T>* __restrict__ twx, const T* __restrict__ V,
+                                                 cplx<T>* __restrict__ Tb) {
+  extern __shared__ unsigned char smem_raw[];
+  const int n1 = g.n1, np = g.n2 * g.n3;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);      // n1 x tile, element (i1, t) at i1 * tile + t
+  T* vt = reinterpret_cast<T*>(buf + n1 * tile);             // n1 x tile
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(vt + n1 * tile);  // n1
+  const int t0 = blockIdx.x * tile;
+  const int cnt = min(tile, np - t0);
+  for (int i = threadIdx.x; i < n1; i += blockDim.x) tw[i] = twx[i];
+  for (int e = threadIdx.x; e < n1 * tile; e += blockDim.x) {
+    const int i1 = e / tile, t = e - i1 * tile;
+    vt[e] = t < cnt ? V[(int64_t)i1 * np + t0 + t] : (T)0;
+  }
+  const int c0 = blockIdx.y * cb;
+  const int c1 = min(ncols, c0 + cb);
+  const Lines L{n1, tile, tile, 1, 1};
+  for (int c = c0; c < c1; ++c) {
+    for (int e = threadIdx.x; e < n1 * tile; e += blockDim.x) buf[e] = mk<T>(0, 0);
+    __syncthreads();
+    const cplx<T>* in = Tb + (int64_t)c * g.ns * np + t0;
+    for (int e = threadIdx.x; e < g.ns * cnt; e += blockDim.x) {
+      const int s = e / cnt, t = e - s * cnt;
+      buf[g.plane_i1[s] * tile + t] = in[(int64_t)s * np + t];
+    }
+    __syncthreads();
+    lds_fft<T, MAXPTS>(buf, L, px, tw, (T)1);
+    for (int e = threadIdx.x; e < n1 * tile; e += blockDim.x) buf[e] = cscale<T>(buf[e], vt[e]);
+    __syncthreads();
+    lds_fft<T, MAXPTS>(buf, L, px, tw, (T)-1);
+    cplx<T>* out = Tb + (int64_t)c * g.ns * np + t0;
+    for (int e = threadIdx.x; e < g.ns * cnt; e += blockDim.x) {
+      const int s = e / cnt, t = e - s * cnt;
+      out[(int64_t)s * np + t] = buf[g.plane_i1[s] * tile + t];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ x_density
+template <int MAXPTS>
+__global__ void __launch_bounds__(512) k_x_density(ColMap cm, int ncols, GridGeom g, int tile, FftPlan px,
+                                                   const z64* __restrict__ twx, const z64* __restrict__ Tb,
+                                                   double occ_over_omega, double* __restrict__ rho, int accumulate) {
+  extern __shared__ unsigned char smem_raw[];
+  const int n1 = g.n1, np = g.n2 * g.n3;
+  z64* buf = reinterpret_cast<z64*>(smem_raw);
+  z64* tw = buf + n1 * tile;
+  const int t0 = blockIdx.x * tile;
+  const int cnt = min(tile, np - t0);
+  for (int i = threadIdx.x; i < n1; i += blockDim.x) tw[i] = twx[i];
+  double acc[MAXPTS];
+#pragma unroll
+  for (int r = 0; r < MAXPTS; ++r) acc[r] = 0.0;
+  const Lines L{n1, tile, tile, 1, 1};
+  for (int c = 0; c < ncols; ++c) {
+    int64_t base;
+    const KDesc& k = col_kd(cm, c, base);
+    const double wgt = k.w * occ_over_omega;
+    for (int e = threadIdx.x; e < n1 * tile; e += blockDim.x) buf[e] = mk<double>(0, 0);
+    __syncthreads();
+    const z64* in = Tb + (int64_t)c * g.ns * np + t0;
+    for (int e = threadIdx.x; e < g.ns * cnt; e += blockDim.x) {
+      const int s = e / cnt, t = e - s * cnt;
+      buf[g.plane_i1[s] * tile + t] = in[(int64_t)s * np + t];
+    }
+    __syncthreads();
+    lds_fft<double, MAXPTS>(buf, L, px, tw, 1.0);
+#pragma unroll
+    for (int r = 0; r < MAXPTS; ++r) {
+      const int e = threadIdx.x + r * blockDim.x;
+      if (e < n1 * tile) {
+        const z64 v = buf[e];
+        acc[r] += wgt * (v.x * v.x + v.y * v.y);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < MAXPTS; ++r) {
+    const int e = threadIdx.x + r * blockDim.x;
+    if (e < n1 * tile) {
+      const int i1 = e / tile, t = e - i1 * tile;
+      if (t < cnt) {
+        double* d = rho + (int64_t)i1 * np + t0 + t;
+        *d = accumulate ? *d + acc[r] : acc[r];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T> static size_t plane_lds(const GridGeom& g) {
+  return sizeof(cplx<T>) * ((size_t)g.n2 * g.n3 + g.n2 + g.n3);
+}
+
+template <typename T, int M>
+static void set_lds(const void* f, size_t bytes) {
+  HIPCK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+static constexpr size_t kLdsMax = 160 * 1024;
+
+template <typename T>
+void launch_inv_yz(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const FftPlan& pz,
+                   const FftPlan& py, const cplx<T>* twz, const cplx<T>* twy, const cplx<T>* X, cplx<T>* Tb) {
+  if (ncols <= 0) return;
+  const size_t lds = plane_lds<T>(g);
+  if (lds > kLdsMax) fail(EAHP_EINVAL, "FFT plane does not fit in LDS");
+  const int np = g.n2 * g.n3;
+  const int nt = np >= 2048 ? 1024 : (np >= 512 ? 256 : 64);
+  dim3 grid(g.ns, ncols);
+  switch (pick_maxpts(np, nt)) {
+#define CASE(M)                                                                                   \
+  case M:                                                                                         \
+    set_lds<T, M>((const void*)k_inv_yz<T, M>, lds);                                              \
+    hipLaunchKernelGGL((k_inv_yz<T, M>), grid, dim3(nt), lds, st, cm, g, pz, py, twz, twy, X, Tb); \
+    break;
+    CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+  }
+  HIPCK(hipGetLastError());
+}
+
+template <typename T>
+void launch_fwd_yz(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const FftPlan& pz,
+                   const FftPlan& py, const cplx<T>* twz, const cplx<T>* twy, const cplx<T>* Tb, const cplx<T>* X,
+                   cplx<T>* HX) {
+  if (ncols <= 0) return;
+  const size_t lds = plane_lds<T>(g);
+  if (lds > kLdsMax) fail(EAHP_EINVAL, "FFT plane does not fit in LDS");
+  const int np = g.n2 * g.n3;
+  const int nt = np >= 2048 ? 1024 : (np >= 512 ? 256 : 64);
+  const T scale = (T)(1.0 / ((double)g.n1 * g.n2 * g.n3));
+  dim3 grid(g.ns, ncols);
+  switch (pick_maxpts(np, nt)) {
+#define CASE(M)                                                                                             \
+  case M:                                                                                                   \
+    set_lds<T, M>((const void*)k_fwd_yz<T, M>, lds);                                                        \
+    hipLaunchKernelGGL((k_fwd_yz<T, M>), grid, dim3(nt), lds, st, cm, g, pz, py, twz, twy, Tb, X, HX, scale); \
+    break;
+    CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+  }
+  HIPCK(hipGetLastError());
+}
+
+static int x_tile(int n1, int np, size_t per_elem, size_t budget) {
+  int tile = 64;
+  while (tile > 8 && (size_t)n1 * tile * per_elem > budget) tile /= 2;
+  if (tile > np) tile = np;
+  return tile;
+}
+
+template <typename T>
+void launch_x_local(hipStream_t st, int ncols, const GridGeom& g, const FftPlan& px, const cplx<T>* twx,
+                    const T* V, cplx<T>* Tb) {
+  if (ncols <= 0) return;
+  const int np = g.n2 * g.n3;
+  const int tile = x_tile(g.n1, np, sizeof(cplx<T>) + sizeof(T), 72 * 1024);
+  const size_t lds = (size_t)g.n1 * tile * (sizeof(cplx<T>) + sizeof(T)) + g.n1 * sizeof(cplx<T>);
+  const int nt = g.n1 * tile >= 2048 ? 512 : 256;
+  const int ntiles = (np + tile - 1) / tile;
+  // columns per work-group: enough work-groups to fill the chip, V reused by the chunk
+  int cb = 8;
+  while (cb > 1 && (int64_t)ntiles * ((ncols + cb - 1) / cb) < 2048) cb /= 2;
+  dim3 grid(ntiles, (ncols + cb - 1) / cb);
+  switch (pick_maxpts((int64_t)g.n1 * tile, nt)) {
+#define CASE(M)                                                                                       \
+  case M:                                                                                             \
+    set_lds<T, M>((const void*)k_x_local<T, M>, lds);                                                 \
+    hipLaunchKernelGGL((k_x_local<T, M>), grid, dim3(nt), lds, st, ncols, cb, g, tile, px, twx, V, Tb); \
+    break;
+    CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+  }
+  HIPCK(hipGetLastError());
+}
+
+void launch_x_density(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const FftPlan& px,
+                      const z64* twx, const z64* Tb, double occ_over_omega, double* rho, int accumulate) {
+  const int np = g.n2 * g.n3;
+  const int tile = std::min(32, x_tile(g.n1, np, sizeof(z64), 48 * 1024));
+  const size_t lds = (size_t)g.n1 * tile * sizeof(z64) + g.n1 * sizeof(z64);
+  const int nt = 256;
+  const int ntiles = (np + tile - 1) / tile;
+  switch (pick_maxpts((int64_t)g.n1 * tile, nt)) {
+#define CASE(M)                                                                                              \
+  case M:                                                                                                    \
+    set_lds<double, M>((const void*)k_x_density<M>, lds);                                                   \
+    hipLaunchKernelGGL((k_x_density<M>), dim3(ntiles), dim3(nt), lds, st, cm, ncols, g, tile, px, twx, Tb,   \
+                       occ_over_omega, rho, accumulate);                                                     \
+    break;
+    CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+  }
+  HIPCK(hipGetLastError());
+}
+
+template void launch_inv_yz<double>(hipStream_t, const ColMap&, int, const GridGeom&, const FftPlan&, const FftPlan&,
+                                    const z64*, const z64*, const z64*, z64*);
+template void launch_inv_yz<float>(hipStream_t, const ColMap&, int, const GridGeom&, const FftPlan&, const FftPlan&,
+                                   const c32*, const c32*, const c32*, c32*);
+template void launch_fwd_yz<double>(hipStream_t, const ColMap&, int, const GridGeom&, const FftPlan&, const FftPlan&,
+                                    const z64*, const z64*, const z64*, const z64*, z64*);
+template void launch_fwd_yz<float>(hipStream_t, const ColMap&, int, const GridGeom&, const FftPlan&, const FftPlan&,
+                                   const c32*, const c32*, const c32*, const c32*, c32*);
+template void launch_x_local<double>(hipStream_t, int, const GridGeom&, const FftPlan&, const z64*, const double*,
+                                     z64*);
+template void launch_x_local<float>(hipStream_t, int, const GridGeom&, const FftPlan&, const c32*, const float*,
+                                    c32*);
+
+// ------------------------------------------------------------------ full-box FFT (potentials)
+template <int MAXPTS>
+__global__ void __launch_bounds__(1024) k_box_yz(int n2, int n3, FftPlan pz, FftPlan py, const z64* twz,
+                                                 const z64* twy, z64* box, double sg) {
+  extern __shared__ unsigned char smem_raw[];
+  const int np = n2 * n3;
+  z64* pl = reinterpret_cast<z64*>(smem_raw);
+  z64* tz = pl + np;
+  z64* ty = tz + n3;
+  z64* p0 = box + (int64_t)blockIdx.x * np;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) pl[i] = p0[i];
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) tz[i] = twz[i];
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) ty[i] = twy[i];
+  __syncthreads();
+  lds_fft<double, MAXPTS>(pl, Lines{n3, 1, n2, n3, 0}, pz, tz, sg);
+  lds_fft<double, MAXPTS>(pl, Lines{n2, n3, n3, 1, 1}, py, ty, sg);
+  for (int i = threadIdx.x; i < np; i += blockDim.x) p0[i] = pl[i];
+}
+
+template <int MAXPTS>
+__global__ void __launch_bounds__(512) k_box_x(int n1, int np, int tile, FftPlan px, const z64* twx, z64* box,
+                                               double sg) {
+  extern __shared__ unsigned char smem_raw[];
+  z64* buf = reinterpret_cast<z64*>(smem_raw);
+  z64* tw = buf + n1 * tile;
+  const int t0 = blockIdx.x * tile;
+  const int cnt = min(tile, np - t0);
+  for (int i = threadIdx.x; i < n1; i += blockDim.x) tw[i] = twx[i];
+  for (int e = threadIdx.x; e < n1 * tile; e += blockDim.x) {
+    const int i1 = e / tile, t = e - i1 * tile;
+    buf[e] = t < cnt ? box[(int64_t)i1 * np + t0 + t] : mk<double>(0, 0);
+  }
+  __syncthreads();
+  lds_fft<double, MAXPTS>(buf, Lines{n1, tile, tile, 1, 1}, px, tw, sg);
+  for (int e = threadIdx.x; e < n1 * tile; e += blockDim.x) {
+    const int i1 = e / tile, t = e - i1 * tile;
+    if (t < cnt) box[(int64_t)i1 * np + t0 + t] = buf[e];
+  }
+}
+
+void launch_box_fft(hipStream_t st, int n1, int n2, int n3, const FftPlan p[3], const z64* const tw[3], z64* box,
+                    double sign) {
+  const int np = n2 * n3;
+  const size_t lds = sizeof(z64) * ((size_t)np + n2 + n3);
+  if (lds > kLdsMax) fail(EAHP_EINVAL, "FFT plane does not fit in LDS");
+  const int nt = np >= 2048 ? 1024 : (np >= 512 ? 256 : 64);
+  switch (pick_maxpts(np, nt)) {
+#define CASE(M)                                                                                                  \
+  case M:                                                                                                        \
+    set_lds<double, M>((const void*)k_box_yz<M>, lds);                                                           \
+    hipLaunchKernelGGL((k_box_yz<M>), dim3(n1), dim3(nt), lds, st, n2, n3, p[2], p[1], tw[2], tw[1], box, sign); \
+    break;
+    CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+  }
+  HIPCK(hipGetLastError());
+  const int tile = x_tile(n1, np, sizeof(z64), 64 * 1024);
+  const size_t lds2 = (size_t)n1 * tile * sizeof(z64) + n1 * sizeof(z64);
+  const int nt2 = 256;
+  switch (pick_maxpts((int64_t)n1 * tile, nt2)) {
+#define CASE(M)                                                                                                   \
+  case M:                                                                                                         \
+    set_lds<double, M>((const void*)k_box_x<M>, lds2);                                                            \
+    hipLaunchKernelGGL((k_box_x<M>), dim3((np + tile - 1) / tile), dim3(nt2), lds2, st, n1, np, tile, p[0], tw[0], \
+                       box, sign);                                                                                \
+    break;
+    CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+  }
+  HIPCK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ potentials
+__global__ void k_rho_to_box(int64_t Ng, const double* rho, z64* box) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Ng; i += (int64_t)gridDim.x * blockDim.x)
+    box[i] = mk<double>(rho[i], 0.0);
+}
+void launch_rho_to_box(hipStream_t st, int64_t Ng, const double* rho, z64* box) {
+  hipLaunchKernelGGL(k_rho_to_box, dim3(2048), dim3(256), 0, st, Ng, rho, box);
+  HIPCK(hipGetLastError());
+}
+
+struct Mat3 {
+  double b[9];
+};
+
+__device__ __forceinline__ int freq_of(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+
+// box holds the forward DFT of rho (no 1/N_g); becomes V_H(G) = 4 pi rho^(G)/|G|^2
+__global__ void k_hartree_g(int n1, int n2, int n3, Mat3 B, z64* box) {
+  const int64_t Ng = (int64_t)n1 * n2 * n3;
+  const double sc = 4.0 * M_PI / (double)Ng;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Ng; i += (int64_t)gridDim.x * blockDim.x) {
+    const int i3 = (int)(i % n3);
+    const int i2 = (int)((i / n3) % n2);
+    const int i1 = (int)(i / ((int64_t)n2 * n3));
+    const double m1 = freq_of(i1, n1), m2 = freq_of(i2, n2), m3 = freq_of(i3, n3);
+    const double gx = B.b[0] * m1 + B.b[3] * m2 + B.b[6] * m3;
+    const double gy = B.b[1] * m1 + B.b[4] * m2 + B.b[7] * m3;
+    const double gz = B.b[2] * m1 + B.b[5] * m2 + B.b[8] * m3;
+    const double g2 = gx * gx + gy * gy + gz * gz;
+    const z64 v = box[i];
+    const double f = (i == 0) ? 0.0 : sc / g2;
+    box[i] = mk<double>(v.x * f, v.y * f);
+  }
+}
+void launch_hartree_g(hipStream_t st, int n1, int n2, int n3, const double* B, z64* box) {
+  Mat3 m;
+  for (int i = 0; i < 9; ++i) m.b[i] = B[i];
+  hipLaunchKernelGGL(k_hartree_g, dim3(2048), dim3(256), 0, st, n1, n2, n3, m, box);
+  HIPCK(hipGetLastError());
+}
+
+// Veff = Vion + VH + Vx;  partial[b*3 + {0,1,2}] = block sums of Vion rho, VH rho / 2, e_x
+__global__ void __launch_bounds__(256) k_veff(int64_t Ng, const double* rho, const double* vion, const z64* vh,
+                                              int terms, double cx, double* veff, float* veff32, double* partial) {
+  __shared__ double sh[16];
+  double s0 = 0, s1 = 0, s2 = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Ng; i += (int64_t)gridDim.x * blockDim.x) {
+    const double r = fmax(rho[i], 0.0);
+    const double vi = (terms & EAHP_TERM_ION) ? vion[i] : 0.0;
+    const double h = (terms & EAHP_TERM_HARTREE) ? vh[i].x : 0.0;
+    double vx = 0.0, ex = 0.0;
+    if (terms & EAHP_TERM_XC) {
+      vx = -cx * cbrt(r);
+      ex = 0.75 * r * vx;
+    }
+    const double v = vi + h + vx;
+    veff[i] = v;
+    if (veff32) veff32[i] = (float)v;
+    s0 += vi * rho[i];
+    s1 += 0.5 * h * rho[i];
+    s2 += ex;
+  }
+  s0 = block_sum(s0, sh);
+  s1 = block_sum(s1, sh);
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x * 3 + 0] = s0;
+    partial[blockIdx.x * 3 + 1] = s1;
+    partial[blockIdx.x * 3 + 2] = s2;
+  }
+}
+void launch_veff(hipStream_t st, int64_t Ng, const double* rho, const double* vion, const z64* vh_box, int terms,
+                 double* veff, float* veff32, double* partial3, int nblocks) {
+  const double cx = std::cbrt(3.0 / M_PI);  // Slater: V_x = -(3 rho / pi)^(1/3)
+  hipLaunchKernelGGL(k_veff, dim3(nblocks), dim3(256), 0, st, Ng, rho, vion, vh_box, terms, cx, veff, veff32,
+                     partial3);
+  HIPCK(hipGetLastError());
+}
+
+__global__ void k_real_part(int64_t Ng, const z64* box, double scale, double* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Ng; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = box[i].x * scale;
+}
+void launch_real_part(hipStream_t st, int64_t Ng, const z64* box, double scale, double* out) {
+  hipLaunchKernelGGL(k_real_part, dim3(2048), dim3(256), 0, st, Ng, box, scale, out);
+  HIPCK(hipGetLastError());
+}
+
+}  // namespace eahp

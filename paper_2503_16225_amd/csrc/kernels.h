@@ -1,0 +1,115 @@
+// Launchers of the device kernels (host side).  All launches are asynchronous
+// on the given stream; sizes are validated by the callers.
+#pragma once
+
+#include "internal.h"
+
+namespace eahp {
+
+// Per-k-point descriptor kept in device memory.
+struct KDesc {
+  int64_t npw;
+  int64_t off;              // row offset of the k-block in a stacked frame
+  const int* box;           // linear box index per plane wave
+  const int* plane_start;   // ns + 1 row starts of the active planes
+  const double* kin;        // |k+G|^2 / 2
+  const float* kin32;
+  const z64* proj;          // npw x natoms projectors (column-major)
+  const c32* proj32;
+  double w;                 // k-point weight
+};
+
+// Columns of an H-apply: column c belongs to k-point k0 + c / cpk and is
+// column j = c % cpk of that k-point's block; in frame mode the block of k
+// starts at cpk * off_k, otherwise at 0 (single k-point blocks).
+struct ColMap {
+  const KDesc* kd;
+  int k0;
+  int cpk;
+  int frame;
+};
+
+struct GridGeom {
+  int n1, n2, n3;
+  int ns;              // active x-planes
+  const int* plane_i1; // device: i1 of each active plane
+};
+
+// ---- local-potential apply and density (hamiltonian.hip) -----------------
+template <typename T>
+void launch_inv_yz(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const FftPlan& pz,
+                   const FftPlan& py, const cplx<T>* twz, const cplx<T>* twy, const cplx<T>* X, cplx<T>* Tb);
+template <typename T>
+void launch_x_local(hipStream_t st, int ncols, const GridGeom& g, const FftPlan& px, const cplx<T>* twx,
+                    const T* V, cplx<T>* Tb);
+template <typename T>
+void launch_fwd_yz(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const FftPlan& pz,
+                   const FftPlan& py, const cplx<T>* twz, const cplx<T>* twy, const cplx<T>* Tb, const cplx<T>* X,
+                   cplx<T>* HX);
+// rho(r) (+)= sum_c wgt(c) |psi_c(r)|^2, wgt(c) = w_k occ / Omega (FP64 only)
+void launch_x_density(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const FftPlan& px,
+                      const z64* twx, const z64* Tb, double occ_over_omega, double* rho, int accumulate);
+
+// ---- potentials on the full box (hamiltonian.hip) ---------------------------
+void launch_box_fft(hipStream_t st, int n1, int n2, int n3, const FftPlan p[3], const z64* const tw[3],
+                    z64* box, double sign);
+void launch_rho_to_box(hipStream_t st, int64_t Ng, const double* rho, z64* box);
+void launch_hartree_g(hipStream_t st, int n1, int n2, int n3, const double* B, z64* box);
+// Veff = Vion + VH + Vx(rho); partial sums of Vion*rho, VH*rho/2, e_x(rho)
+void launch_veff(hipStream_t st, int64_t Ng, const double* rho, const double* vion, const z64* vh_box,
+                 int terms, double* veff, float* veff32, double* partial3, int nblocks);
+void launch_real_part(hipStream_t st, int64_t Ng, const z64* box, double scale, double* out);
+
+// ---- BLAS-like (blas.hip) ------------------------------------------------------
+// C[a x b] = alpha * A^H B + beta * C over n rows; A lda, B ldb, C ldc (column-major).
+template <typename T>
+void gemm_hn(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* B,
+             int64_t ldb, cplx<T>* C, int64_t ldc, double alpha, double beta, DevMem& part, int batch = 1,
+             int64_t sA = 0, int64_t sB = 0, int64_t sC = 0);
+// C[n x b] = alpha * A[n x a] M[a x b] + beta * C ; opM: 0 = M, 1 = M^H
+template <typename T>
+void gemm_nn(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* M, int64_t ldm,
+             int opM, cplx<T>* C, int64_t ldc, double alpha_re, double alpha_im, double beta, int batch = 1,
+             int64_t sA = 0, int64_t sM = 0, int64_t sC = 0);
+// y = a x + b y (complex, length n, real coefficients)
+template <typename T>
+void axpby(hipStream_t st, int64_t n, double a, const cplx<T>* x, double b, cplx<T>* y);
+// out = Re sum conj(x) y over n, deterministic (partials in part)
+void dot_re(hipStream_t st, int64_t n, const z64* x, const z64* y, double* out_dev, DevMem& part);
+// out[j] = sum_g w[g] |x[g, j]|^2 (column reductions), or with w == null plain norms
+void col_weighted_norm2(hipStream_t st, int64_t n, int ncols, const z64* X, int64_t ldx, const double* w,
+                        double* out);
+template <typename T>
+void convert(hipStream_t st, int64_t n, const void* src, int src_fp64, void* dst, int dst_fp64);
+// TPA preconditioner: Y[:, j] = X[:, j] / (kin + alpha_j)
+template <typename T>
+void tpa_apply(hipStream_t st, int64_t n, int ncols, const double* kin, const double* alpha, const cplx<T>* X,
+               int64_t ldx, cplx<T>* Y, int64_t ldy);
+// D-scaling of projector coefficients: B[I, j] *= D[I]
+template <typename T>
+void scale_rows(hipStream_t st, int m, int ncols, const double* D, cplx<T>* B, int64_t ldb);
+
+// ---- small dense (dense.hip) ---------------------------------------------------
+// Hermitian eigendecomposition A = V diag(w) V^H by parallel cyclic Jacobi, one
+// work-group per matrix (batch over blockIdx.x).  A is overwritten.
+void heev(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
+          int64_t sV, int batch, int* info);
+// In-place inverse of a general n x n matrix (Gauss-Jordan, partial pivoting).
+void inverse(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, z64* work, int batch, int* info);
+// Pivoted Cholesky of a Hermitian PSD G (n x n): G[piv, piv] = L L^H with rank r
+// (diagonal pivots below tol * first pivot are dropped); outputs the upper
+// triangular inverse factor U = L^-H padded (n x r), piv and r.
+void pchol_inv(hipStream_t st, int n, z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* Uinv,
+               int64_t ldu, int* info);
+// Elementwise helpers on small matrices (n x m, column-major).
+// Y = Q^H C U-ish products use gemm; these handle the spectral divisions.
+void sylv_divide(hipStream_t st, int q, int p, const double* w, const double* s, z64* Y, int64_t ldy);
+void lyap_divide(hipStream_t st, int p, const double* d, z64* X, int64_t ldx, int batch, int64_t sd, int64_t sX);
+// M = V f(d) V^H with f(d) = d^e (e in {0.5, -0.5, -1}); batch over k
+void spectral_fn(hipStream_t st, int p, const z64* V, int64_t ldv, int64_t sV, const double* d, int64_t sd,
+                 double e, z64* M, int64_t ldm, int64_t sM, int batch);
+void hermitize(hipStream_t st, int p, z64* M, int64_t ldm, int64_t sM, int batch);
+void add_diag(hipStream_t st, int p, z64* M, int64_t ldm, int64_t sM, double v, int batch);
+void set_identity(hipStream_t st, int p, z64* M, int64_t ldm);
+
+}  // namespace eahp

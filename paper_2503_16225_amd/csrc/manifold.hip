@@ -1,0 +1,339 @@
+// Manifold operations on frames, per k-point: polar retraction (eqs. (3.1)-(3.2)),
+// differentiated-retraction transports (Prop. 3.1 and its closed form for
+// xi = tau eta, Sec. 3.2), the energy-adaptive gradient (Sec. 5.2) and the
+// preconditioned block FOM for the Sylvester equation (Appendix A, Algorithm 4).
+#include <algorithm>
+#include <cmath>
+
+#include "ops.h"
+#include "setup.h"
+
+namespace eahp {
+
+namespace {
+struct Scratch {
+  DevMem a, b, c, d, e, f, g;
+};
+Scratch& scratch() {
+  static Scratch s;
+  return s;
+}
+}  // namespace
+
+// ---------------------------------------------------------------- retraction
+void retract(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* out, RetractFactors& F) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p, nk = pb->nk;
+  const int64_t pp = (int64_t)p * p;
+  const int64_t N = pb->ntot * p;
+  F.d.ensure(sizeof(double) * nk * p);
+  F.V.ensure(sizeof(z64) * nk * pp);
+  F.Sinv.ensure(sizeof(z64) * nk * pp);
+  Scratch& s = scratch();
+  s.a.ensure(sizeof(z64) * N);
+  s.b.ensure(sizeof(z64) * nk * pp);
+  z64* Psi = s.a.as<z64>();
+  z64* Gm = s.b.as<z64>();
+  axpby<double>(st, N, 1.0, Phi, 0.0, Psi);
+  axpby<double>(st, N, tau, eta, 1.0, Psi);
+  for (int ik = 0; ik < nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    gemm_hn<double>(st, K.npw, p, p, Psi + o, K.npw, Psi + o, K.npw, Gm + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
+  }
+  heev(st, p, Gm, p, pp, F.d.as<double>(), p, F.V.as<z64>(), p, pp, nk, pb->d_info.as<int>());
+  minval(st, nk * p, F.d.as<double>(), scal(pb, S_MIN));
+  spectral_fn(st, p, F.V.as<z64>(), p, pp, F.d.as<double>(), p, -0.5, F.Sinv.as<z64>(), p, pp, nk);
+  for (int ik = 0; ik < nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    gemm_nn<double>(st, K.npw, p, p, Psi + o, K.npw, F.Sinv.as<z64>() + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0, 0.0);
+  }
+  fetch_scalars(pb, S_MIN + 1);
+  const double dmin = pb->h_scal[S_MIN];
+  if (!std::isfinite(dmin)) fail(EAHP_ENONFINITE, "non-finite Gram matrix in the retraction");
+  if (!(dmin > 0.0)) fail(EAHP_ENOTPD, "retraction Gram matrix not positive definite");
+}
+
+// ---------------------------------------------------------------- transports
+// T(eta) = eta S^-1 - tau R(tau eta) (eta S^-1)^H (eta S^-1)
+void transport_self(eahp_problem* pb, const z64* Phi_new, const z64* eta, double tau, const RetractFactors& F,
+                    z64* out) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p;
+  const int64_t pp = (int64_t)p * p;
+  Scratch& s = scratch();
+  s.c.ensure(sizeof(z64) * pb->ntot * p);
+  s.d.ensure(sizeof(z64) * pb->nk * pp);
+  z64* ES = s.c.as<z64>();
+  z64* M = s.d.as<z64>();
+  for (int ik = 0; ik < pb->nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    gemm_nn<double>(st, K.npw, p, p, eta + o, K.npw, F.Sinv.as<z64>() + ik * pp, p, 0, ES + o, K.npw, 1.0, 0.0, 0.0);
+    gemm_hn<double>(st, K.npw, p, p, ES + o, K.npw, ES + o, K.npw, M + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
+    axpby<double>(st, K.npw * p, 1.0, ES + o, 0.0, out + o);
+    gemm_nn<double>(st, K.npw, p, p, Phi_new + o, K.npw, M + ik * pp, p, 0, out + o, K.npw, -tau, 0.0, 1.0);
+  }
+}
+
+// T_xi(v) = (v - R(xi) X) S^-1 with S X + X S = xi^H v + v^H xi, in the eigenbasis of S
+void transport_general(eahp_problem* pb, const z64* Phi_new, const z64* xi, const z64* v, const RetractFactors& F,
+                       z64* out) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p, nk = pb->nk;
+  const int64_t pp = (int64_t)p * p;
+  Scratch& s = scratch();
+  s.c.ensure(sizeof(z64) * pb->ntot * p);
+  s.d.ensure(sizeof(z64) * nk * pp);
+  s.e.ensure(sizeof(z64) * nk * pp);
+  z64* Wf = s.c.as<z64>();
+  z64* Bm = s.d.as<z64>();
+  z64* Tm = s.e.as<z64>();
+  const z64* V = F.V.as<z64>();
+  for (int ik = 0; ik < nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    gemm_hn<double>(st, K.npw, p, p, xi + o, K.npw, v + o, K.npw, Bm + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
+  }
+  hermitize(st, p, Bm, p, pp, nk);  // (B + B^H) / 2
+  for (int ik = 0; ik < nk; ++ik) {
+    // Tm = V^H Bh ; Bm = Tm V  (= V^H Bh V)
+    gemm_hn<double>(st, p, p, p, V + ik * pp, p, Bm + ik * pp, p, Tm + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
+    gemm_nn<double>(st, p, p, p, Tm + ik * pp, p, V + ik * pp, p, 0, Bm + ik * pp, p, 2.0, 0.0, 0.0);
+  }
+  lyap_divide(st, p, F.d.as<double>(), Bm, p, nk, p, pp);
+  for (int ik = 0; ik < nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    // X = V Xt V^H
+    gemm_nn<double>(st, p, p, p, V + ik * pp, p, Bm + ik * pp, p, 0, Tm + ik * pp, p, 1.0, 0.0, 0.0);
+    gemm_nn<double>(st, p, p, p, Tm + ik * pp, p, V + ik * pp, p, 1, Bm + ik * pp, p, 1.0, 0.0, 0.0);
+    // W = v - Phi_new X ; out = W S^-1
+    axpby<double>(st, K.npw * p, 1.0, v + o, 0.0, Wf + o);
+    gemm_nn<double>(st, K.npw, p, p, Phi_new + o, K.npw, Bm + ik * pp, p, 0, Wf + o, K.npw, -1.0, 0.0, 1.0);
+    gemm_nn<double>(st, K.npw, p, p, Wf + o, K.npw, F.Sinv.as<z64>() + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0, 0.0);
+  }
+}
+
+// ---------------------------------------------------------------- EA gradient
+void ea_gradient(eahp_problem* pb, const z64* Phi, const z64* X, z64* G) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p, nk = pb->nk;
+  const int64_t pp = (int64_t)p * p;
+  Scratch& s = scratch();
+  s.d.ensure(sizeof(z64) * nk * pp);
+  s.f.ensure(sizeof(z64) * nk * pp * 2);
+  z64* M = s.d.as<z64>();
+  for (int ik = 0; ik < nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    gemm_hn<double>(st, K.npw, p, p, Phi + o, K.npw, X + o, K.npw, M + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
+  }
+  inverse(st, p, M, p, pp, s.f.as<z64>(), nk, pb->d_info.as<int>());
+  for (int ik = 0; ik < nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    axpby<double>(st, K.npw * p, 1.0, Phi + o, 0.0, G + o);
+    gemm_nn<double>(st, K.npw, p, p, X + o, K.npw, M + ik * pp, p, 0, G + o, K.npw, -1.0, 0.0, 1.0);
+  }
+  HIPCK(hipMemcpyAsync(pb->h_info, pb->d_info.p, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  for (int ik = 0; ik < nk; ++ik)
+    if (pb->h_info[ik]) fail(EAHP_EFOM, "Phi^H X is singular in the energy-adaptive gradient");
+}
+
+// ---------------------------------------------------------------- block FOM
+namespace {
+
+struct FomWork {
+  DevMem V, W, A, Cj, C, E, Rj, Ah, QA, wA, T1, T2, Y, YS, Sig, U, s, alpha, Gm, PU, tmp, piv;
+  int64_t n = 0;
+  int qcap = 0;
+};
+FomWork& fomwork() {
+  static FomWork w;
+  return w;
+}
+
+// Orthonormal basis of span(R) (n x c, ld n) by pivoted CholQR twice; written to
+// dest (ld n).  Returns the rank.
+int rrqr(eahp_problem* pb, int64_t n, int c, const z64* R, z64* dest, double tol, FomWork& w) {
+  hipStream_t st = pb->ctx->stream;
+  if (c <= 0) return 0;
+  w.Gm.ensure(sizeof(z64) * c * c);
+  w.PU.ensure(sizeof(z64) * c * c);
+  w.tmp.ensure(sizeof(z64) * n * c);
+  w.piv.ensure(sizeof(int) * c);
+  int* piv = w.piv.as<int>();
+  int* rank = pb->d_info.as<int>();
+  gemm_hn<double>(st, n, c, c, R, n, R, n, w.Gm.as<z64>(), c, 1.0, 0.0, pb->ws.gemm_part);
+  pchol_inv(st, c, w.Gm.as<z64>(), c, tol, piv, rank, w.PU.as<z64>(), c, nullptr);
+  HIPCK(hipMemcpyAsync(pb->h_info, pb->d_info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  const int r = pb->h_info[0];
+  if (r <= 0) return 0;
+  gemm_nn<double>(st, n, c, r, R, n, w.PU.as<z64>(), c, 0, w.tmp.as<z64>(), n, 1.0, 0.0, 0.0);
+  // second pass
+  gemm_hn<double>(st, n, r, r, w.tmp.as<z64>(), n, w.tmp.as<z64>(), n, w.Gm.as<z64>(), r, 1.0, 0.0,
+                  pb->ws.gemm_part);
+  pchol_inv(st, r, w.Gm.as<z64>(), r, 0.0, piv, rank, w.PU.as<z64>(), r, nullptr);
+  HIPCK(hipMemcpyAsync(pb->h_info, pb->d_info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  const int r2 = pb->h_info[0];
+  gemm_nn<double>(st, n, r, r2, w.tmp.as<z64>(), n, w.PU.as<z64>(), r, 0, dest, n, 1.0, 0.0, 0.0);
+  return r2;
+}
+
+void grow(FomWork& w, int64_t n, int need, int p) {
+  if (need <= w.qcap && n == w.n) return;
+  const int old = (n == w.n) ? w.qcap : 0;
+  const int cap = std::max(need, old + 4 * p);
+  DevMem V2, W2, A2, C2;
+  V2.alloc(sizeof(z64) * n * cap);
+  W2.alloc(sizeof(z64) * n * cap);
+  A2.alloc(sizeof(z64) * (size_t)cap * cap);
+  C2.alloc(sizeof(z64) * (size_t)cap * p);
+  if (old > 0) {
+    HIPCK(hipDeviceSynchronize());
+    HIPCK(hipMemcpy(V2.p, w.V.p, sizeof(z64) * n * old, hipMemcpyDeviceToDevice));
+    HIPCK(hipMemcpy(W2.p, w.W.p, sizeof(z64) * n * old, hipMemcpyDeviceToDevice));
+    HIPCK(hipMemcpy2D(A2.p, sizeof(z64) * cap, w.A.p, sizeof(z64) * old, sizeof(z64) * old, old, hipMemcpyDeviceToDevice));
+    HIPCK(hipMemcpy2D(C2.p, sizeof(z64) * cap, w.Cj.p, sizeof(z64) * old, sizeof(z64) * old, p, hipMemcpyDeviceToDevice));
+  }
+  std::swap(w.V.p, V2.p);
+  std::swap(w.V.bytes, V2.bytes);
+  std::swap(w.W.p, W2.p);
+  std::swap(w.W.bytes, W2.bytes);
+  std::swap(w.A.p, A2.p);
+  std::swap(w.A.bytes, A2.bytes);
+  std::swap(w.Cj.p, C2.p);
+  std::swap(w.Cj.bytes, C2.bytes);
+  w.qcap = cap;
+  w.n = n;
+}
+
+double norm2(eahp_problem* pb, int64_t len, const z64* x) {
+  dot_re(pb->ctx->stream, len, x, x, scal(pb, S_NRM), pb->ws.partial);
+  fetch_scalars(pb, S_NRM + 1);
+  return pb->h_scal[S_NRM];
+}
+
+FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64* Lam, double mu, double rtol,
+              int maxit, double rank_tol, z64* X) {
+  hipStream_t st = pb->ctx->stream;
+  FomWork& w = fomwork();
+  const int p = pb->p;
+  auto& K = pb->kp[ik];
+  const int64_t n = K.npw;
+  const int64_t np_ = n * p;
+  grow(w, n, 2 * p, p);
+  w.C.ensure(sizeof(z64) * np_);
+  w.E.ensure(sizeof(z64) * np_);
+  w.Rj.ensure(sizeof(z64) * np_);
+  w.Sig.ensure(sizeof(z64) * p * p);
+  w.U.ensure(sizeof(z64) * p * p);
+  w.s.ensure(sizeof(double) * p);
+  w.alpha.ensure(sizeof(double) * p);
+  z64* C = w.C.as<z64>();
+  z64* E = w.E.as<z64>();
+  z64* Rj = w.Rj.as<z64>();
+  // C = Phi - (H X0 - X0 Sigma) with X0 = Phi / mu equals -R / mu
+  axpby<double>(st, np_, -1.0 / mu, R, 0.0, C);
+  const double nC2 = norm2(pb, np_, C);
+  // Sigma = Lambda - mu I and its eigendecomposition
+  copy2d(st, p, p, Lam, p, w.Sig.as<z64>(), p);
+  add_diag(st, p, w.Sig.as<z64>(), p, 0, -mu, 1);
+  w.T1.ensure(sizeof(z64) * p * p);
+  copy2d(st, p, p, w.Sig.as<z64>(), p, w.T1.as<z64>(), p);
+  heev(st, p, w.T1.as<z64>(), p, 0, w.s.as<double>(), 0, w.U.as<z64>(), p, 0, 1, pb->d_info.as<int>());
+  // TPA: alpha_j = sum_G |k+G|^2/2 |phi_jG|^2
+  col_weighted_norm2(st, n, p, Phi, n, K.d_kin.as<double>(), w.alpha.as<double>());
+  // V_1 = rrqr(P^-1 C), W_1 = H V_1
+  tpa_apply<double>(st, n, p, K.d_kin.as<double>(), w.alpha.as<double>(), C, n, Rj, n);
+  int q = rrqr(pb, n, p, Rj, w.V.as<z64>(), rank_tol, w);
+  FomInfo info;
+  if (q == 0) {
+    axpby<double>(st, np_, 1.0 / mu, Phi, 0.0, X);
+    info.relres = nC2 > 0 ? 1.0 : 0.0;
+    return info;
+  }
+  apply_H_block<double>(pb, ik, q, w.V.as<z64>(), w.W.as<z64>());
+  int ldA = w.qcap;
+  gemm_hn<double>(st, n, q, q, w.V.as<z64>(), n, w.W.as<z64>(), n, w.A.as<z64>(), ldA, 1.0, 0.0, pb->ws.gemm_part);
+  gemm_hn<double>(st, n, q, p, w.V.as<z64>(), n, C, n, w.Cj.as<z64>(), ldA, 1.0, 0.0, pb->ws.gemm_part);
+  int it = 0;
+  double relres = 1.0;
+  for (;;) {
+    ++it;
+    ldA = w.qcap;
+    // ---- projected Sylvester A_q Y - Y Sigma = C_q
+    w.Ah.ensure(sizeof(z64) * q * q);
+    w.QA.ensure(sizeof(z64) * q * q);
+    w.wA.ensure(sizeof(double) * q);
+    w.T1.ensure(sizeof(z64) * q * p);
+    w.T2.ensure(sizeof(z64) * q * p);
+    w.Y.ensure(sizeof(z64) * q * p);
+    w.YS.ensure(sizeof(z64) * q * p);
+    copy2d(st, q, q, w.A.as<z64>(), ldA, w.Ah.as<z64>(), q);
+    heev(st, q, w.Ah.as<z64>(), q, 0, w.wA.as<double>(), 0, w.QA.as<z64>(), q, 0, 1, pb->d_info.as<int>());
+    gemm_hn<double>(st, q, q, p, w.QA.as<z64>(), q, w.Cj.as<z64>(), ldA, w.T1.as<z64>(), q, 1.0, 0.0,
+                    pb->ws.gemm_part);
+    gemm_nn<double>(st, q, p, p, w.T1.as<z64>(), q, w.U.as<z64>(), p, 0, w.T2.as<z64>(), q, 1.0, 0.0, 0.0);
+    sylv_divide(st, q, p, w.wA.as<double>(), w.s.as<double>(), w.T2.as<z64>(), q);
+    gemm_nn<double>(st, q, q, p, w.QA.as<z64>(), q, w.T2.as<z64>(), q, 0, w.T1.as<z64>(), q, 1.0, 0.0, 0.0);
+    gemm_nn<double>(st, q, p, p, w.T1.as<z64>(), q, w.U.as<z64>(), p, 1, w.Y.as<z64>(), q, 1.0, 0.0, 0.0);
+    // ---- E = C - (W Y - V Y Sigma)
+    axpby<double>(st, np_, 1.0, C, 0.0, E);
+    gemm_nn<double>(st, n, q, p, w.W.as<z64>(), n, w.Y.as<z64>(), q, 0, E, n, -1.0, 0.0, 1.0);
+    gemm_nn<double>(st, q, p, p, w.Y.as<z64>(), q, w.Sig.as<z64>(), p, 0, w.YS.as<z64>(), q, 1.0, 0.0, 0.0);
+    gemm_nn<double>(st, n, q, p, w.V.as<z64>(), n, w.YS.as<z64>(), q, 0, E, n, 1.0, 0.0, 1.0);
+    const double nE2 = norm2(pb, np_, E);
+    relres = nC2 > 0 ? std::sqrt(nE2 / nC2) : 0.0;
+    if (!std::isfinite(relres)) fail(EAHP_ENONFINITE, "non-finite residual in the metric solve");
+    if (relres <= rtol || it >= maxit) break;
+    // ---- R_j = (I - V V^H) P^-1 E_j, projected twice
+    tpa_apply<double>(st, n, p, K.d_kin.as<double>(), w.alpha.as<double>(), E, n, Rj, n);
+    for (int pass = 0; pass < 2; ++pass) {
+      gemm_hn<double>(st, n, q, p, w.V.as<z64>(), n, Rj, n, w.T1.as<z64>(), q, 1.0, 0.0, pb->ws.gemm_part);
+      gemm_nn<double>(st, n, q, p, w.V.as<z64>(), n, w.T1.as<z64>(), q, 0, Rj, n, -1.0, 0.0, 1.0);
+    }
+    grow(w, n, q + p, p);
+    ldA = w.qcap;
+    z64* Vn = w.V.as<z64>() + (int64_t)q * n;
+    const int r = rrqr(pb, n, p, Rj, Vn, rank_tol, w);
+    if (r == 0) break;
+    z64* Wn = w.W.as<z64>() + (int64_t)q * n;
+    apply_H_block<double>(pb, ik, r, Vn, Wn);
+    // border A with V^H W_new (rows 0..q+r) and mirror; C_{j+1} = [C_j ; V_new^H C]
+    gemm_hn<double>(st, n, q + r, r, w.V.as<z64>(), n, Wn, n, w.A.as<z64>() + (int64_t)q * ldA, ldA, 1.0, 0.0,
+                    pb->ws.gemm_part);
+    border_mirror(st, q, r, w.A.as<z64>(), ldA);
+    gemm_hn<double>(st, n, r, p, Vn, n, C, n, w.Cj.as<z64>() + q, ldA, 1.0, 0.0, pb->ws.gemm_part);
+    q += r;
+  }
+  // X = X0 + V Y
+  axpby<double>(st, np_, 1.0 / mu, Phi, 0.0, X);
+  gemm_nn<double>(st, n, q, p, w.V.as<z64>(), n, w.Y.as<z64>(), q, 0, X, n, 1.0, 0.0, 1.0);
+  info.iters = it;
+  info.relres = relres;
+  info.q = q;
+  pb->fom_iters += it;
+  return info;
+}
+
+}  // namespace
+
+void metric_solve(eahp_problem* pb, const z64* Phi, const z64* R, const z64* Lam, double mu, double rtol, int maxit,
+                  double rank_tol, z64* X, std::vector<FomInfo>* info) {
+  if (!(mu > 0)) fail(EAHP_EINVAL, "mu must be positive");
+  if (info) info->clear();
+  const int p = pb->p;
+  for (int ik = 0; ik < pb->nk; ++ik) {
+    const int64_t o = (int64_t)p * pb->kp[ik].off;
+    FomInfo fi = fom_k(pb, ik, Phi + o, R + o, Lam + (int64_t)ik * p * p, mu, rtol, maxit, rank_tol, X + o);
+    if (info) info->push_back(fi);
+  }
+}
+
+}  // namespace eahp

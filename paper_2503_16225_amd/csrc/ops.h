@@ -1,0 +1,56 @@
+// Host-side operators of the method (declarations shared by the .hip files).
+#pragma once
+
+#include <array>
+
+#include "kernels.h"
+
+namespace eahp {
+
+enum ScalarSlot {
+  S_ION = 0, S_HART = 1, S_XC = 2, S_KIN = 3, S_NL = 4, S_RR = 5, S_DOT = 6, S_DOT2 = 7, S_DOT3 = 8,
+  S_MIN = 9, S_NRM = 10, S_NRM2 = 11, kNumScal = 64
+};
+
+struct PointScalars {
+  double E = 0, rnorm = 0;
+  double terms[5] = {0, 0, 0, 0, 0};
+};
+
+extern thread_local std::string g_last_error;
+
+void build_problem(eahp_problem* pb, const eahp_system_desc* d);
+GridGeom geom(const eahp_problem* pb);
+ColMap frame_map(const eahp_problem* pb);
+ColMap block_map(const eahp_problem* pb, int k, int ncols);
+void fetch_scalars(eahp_problem* pb, int n);
+double* scal(eahp_problem* pb, int i);
+
+void potentials(eahp_problem* pb);
+void density_potentials(eahp_problem* pb, const z64* Psi);
+void apply_H_frame(eahp_problem* pb, const z64* X, z64* HX, bool tb_ready, double* nlvals);
+template <typename T> void apply_H_block(eahp_problem* pb, int ik, int ncols, const cplx<T>* X, cplx<T>* HX);
+void evaluate_point(eahp_problem* pb, const z64* Psi, z64* HPsi, z64* R, z64* Lam, PointScalars* out);
+void lambda_residual(eahp_problem* pb, const z64* Psi, const z64* HPsi, z64* R, z64* Lam);
+double frame_dot(eahp_problem* pb, const z64* A, const z64* B);
+
+// Retraction factors per k: eigenvalues d of (Psi+xi)^H(Psi+xi), eigenvectors V, S^-1.
+struct RetractFactors {
+  DevMem d, V, Sinv;
+};
+void retract(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* out, RetractFactors& F);
+void transport_self(eahp_problem* pb, const z64* Phi_new, const z64* eta, double tau, const RetractFactors& F,
+                    z64* out);
+void transport_general(eahp_problem* pb, const z64* Phi_new, const z64* xi, const z64* v, const RetractFactors& F,
+                       z64* out);
+void ea_gradient(eahp_problem* pb, const z64* Phi, const z64* X, z64* G);
+struct FomInfo {
+  int iters = 0;
+  double relres = 0;
+  int q = 0;
+};
+// Algorithm 4 on every k-point; X out (frame); the potential must be that of Phi.
+void metric_solve(eahp_problem* pb, const z64* Phi, const z64* R, const z64* Lam, double mu, double rtol, int maxit,
+                  double rank_tol, z64* X, std::vector<FomInfo>* info);
+
+}  // namespace eahp

@@ -1,0 +1,213 @@
+"""GPU parity: every entry point of libeahp against the FP64 oracle.
+
+Inputs are seeded (workloads); the oracle computes the expected values on the
+CPU from the same inputs.  FP64 tolerances follow from the arithmetic: the
+FFT apply and the density carry ~1e-15 relative rounding per transform, so
+1e-12 relative bounds the FFT-based quantities, and quantities that pass
+through a Jacobi eigensolver or a Krylov solve are compared at 1e-10.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_16225_amd import Problem, load_library
+    load_library()
+    return Problem
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    "tiny_gamma": lambda: W.system(*W.diamond_cell(), 3.0, (0, 0, 0)),
+    "tiny_k2": lambda: W.system(*W.diamond_cell(), 3.0, (0, 0, 0), np.array([[0.25, -0.125, 0.375], [-0.25, 0.25, 0.25]]),
+                                np.array([0.5, 0.5])),
+    "si8_gamma_e10": lambda: W.config("si8_gamma_e10"),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def pair(request):
+    from oracle import hamiltonian as ham, manifold as mf
+    Problem = _gpu()
+    sysd = CASES[request.param]()
+    log("case", request.param)
+    om = ham.Model(sysd)
+    gp = Problem(sysd)
+    assert gp.npw == om.npw and gp.fft == om.fft
+    Z = W.gaussian_block(1, om.npw, om.p)
+    Phi = np.concatenate([mf.polar(b)[0] for b in om.blocks(Z)], axis=0)
+    yield request.param, om, gp, Phi
+    gp.close()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_kinetic_only_layout():
+    """terms = 0: H X = |k+G|^2/2 X elementwise, pins the basis order."""
+    Problem = _gpu()
+    from oracle import hamiltonian as ham
+    sysd = W.system(*W.diamond_cell(), 3.0, (0, 0, 0), np.array([[0.1, 0.2, -0.3]]), np.ones(1), terms=0)
+    om = ham.Model(sysd)
+    gp = Problem(sysd)
+    X = W.gaussian_block(4, om.npw, om.p)
+    HX = gp.to_blocks(gp.apply_H(gp.to_device(np.linalg.qr(X)[0]), gp.to_device(X)))
+    assert rel(HX, om.bases[0]["kin"][:, None] * X) < 1e-14
+    gp.close()
+
+
+def test_density_and_potential(pair):
+    name, om, gp, Phi = pair
+    from oracle import hamiltonian as ham
+    rho_o = ham.density(om, Phi)
+    Veff_o, _ = ham.potentials(om, rho_o)
+    rho, veff = gp.density(gp.to_device(Phi))
+    rho = rho.cpu().numpy().reshape(om.fft)
+    veff = veff.cpu().numpy().reshape(om.fft)
+    log(name, "rho", rel(rho, rho_o), "veff", rel(veff, Veff_o))
+    assert rel(rho, rho_o) < 1e-12
+    assert rel(veff, Veff_o) < 1e-12
+
+
+def test_apply_H(pair):
+    name, om, gp, Phi = pair
+    from oracle import hamiltonian as ham
+    rho_o = ham.density(om, Phi)
+    Veff_o, _ = ham.potentials(om, rho_o)
+    X = W.gaussian_block(3, om.npw, om.p)
+    HX_o = ham.apply_H(om, Veff_o, X)
+    HX = gp.to_blocks(gp.apply_H(gp.to_device(Phi), gp.to_device(X)))
+    log(name, "apply_H", rel(HX, HX_o))
+    assert rel(HX, HX_o) < 1e-12
+
+
+def test_energy_residual_lambda(pair):
+    name, om, gp, Phi = pair
+    from oracle import manifold as mf
+    st = mf.state(om, Phi)
+    E, terms = gp.energy(gp.to_device(Phi))
+    R, L, rn, E2 = gp.residual(gp.to_device(Phi))
+    log(name, "E", E, st["E"], abs(E - st["E"]) / abs(st["E"]))
+    assert abs(E - st["E"]) <= 1e-12 * abs(st["E"])
+    assert abs(E2 - st["E"]) <= 1e-12 * abs(st["E"])
+    for k, key in enumerate(["kin", "nl", "ion", "hartree", "xc"]):
+        assert abs(terms[k] - st["terms"][key]) <= 1e-11 * max(1.0, abs(st["terms"][key]))
+    assert rel(gp.to_blocks(R), st["R"]) < 1e-11
+    for Lg, Lo in zip(gp.lambdas(L), st["lams"]):
+        assert rel(Lg, Lo) < 1e-12
+    assert abs(rn - np.linalg.norm(st["R"])) <= 1e-11 * np.linalg.norm(st["R"])
+
+
+def test_retract_and_transport(pair):
+    name, om, gp, Phi = pair
+    from oracle import manifold as mf
+    Z1 = W.gaussian_block(8, om.npw, om.p)
+    Z2 = W.gaussian_block(9, om.npw, om.p)
+
+    def tangent(Zb):
+        out = []
+        for Pk, Zk in zip(om.blocks(Phi), om.blocks(Zb)):
+            M = Pk.conj().T @ Zk
+            out.append(Zk - Pk @ (0.5 * (M + M.conj().T)))
+        return np.concatenate(out, 0)
+
+    eta, v = 0.3 * tangent(Z1), tangent(Z2)
+    tau = 0.7
+    Pn_o, facs = mf.retract(om, Phi, eta, tau)
+    Pn = gp.to_blocks(gp.retract(gp.to_device(Phi), gp.to_device(eta), tau))
+    log(name, "retract", rel(Pn, Pn_o))
+    assert rel(Pn, Pn_o) < 1e-12
+    T_o = mf.transport_general(om, Pn_o, tau * eta, v, facs)
+    T = gp.to_blocks(gp.transport(gp.to_device(Phi), gp.to_device(tau * eta), gp.to_device(v)))
+    log(name, "transport", rel(T, T_o))
+    assert rel(T, T_o) < 1e-11
+    # Psi^H Psi = I after the retraction, per k
+    for Pk in om.blocks(Pn):
+        assert np.abs(Pk.conj().T @ Pk - np.eye(om.p)).max() < 1e-13
+
+
+def test_metric_solve_and_gradient(pair):
+    """Algorithm 4 with a shift for which every H - s_l is positive definite
+    (the FOM iterate is then a well-conditioned Galerkin solution), at the
+    paper's tolerance and near convergence; and the EA gradient of the result."""
+    name, om, gp, Phi = pair
+    from oracle import earcg, manifold as mf
+    st = mf.state(om, Phi)
+    prm = dict(W.DEFAULT_PARAMS)
+    lam_max = max(np.linalg.eigvalsh(L)[-1] for L in st["lams"])
+    mu = lam_max - float(st["Veff"].min()) + 1.0  # H >= min V_eff, so H - (lambda_l - mu) >= 1
+    for rtol in (2.5e-2, 1e-9):
+        X_o, info_o = earcg.metric_solve(om, Phi, st["HPhi"], st["lams"], st["Veff"], mu, dict(prm, fom_rtol=rtol))
+        X, its, rr = gp.metric_solve(gp.to_device(Phi), mu, rtol, prm["fom_maxit"])
+        X = gp.to_blocks(X)
+        log(name, "fom", mu, rtol, its, [i["iters"] for i in info_o], rel(X, X_o))
+        assert its == [i["iters"] for i in info_o]
+        for a, i in zip(rr, info_o):
+            assert abs(a - i["relres"]) <= 1e-7 * i["relres"] + 1e-13
+        assert rel(X, X_o) < 1e-9
+        G_o = mf.ea_gradient(om, Phi, X_o)
+        G = gp.to_blocks(gp.ea_gradient(gp.to_device(Phi), gp.to_device(X_o)))
+        assert rel(G, G_o) < 1e-10
+
+
+def test_linesearch_step(pair):
+    name, om, gp, Phi = pair
+    from oracle import earcg, linesearch, manifold as mf
+    st = mf.state(om, Phi)
+    prm = dict(W.DEFAULT_PARAMS)
+    X, _ = earcg.metric_solve(om, Phi, st["HPhi"], st["lams"], st["Veff"], prm["mu_warm"], prm)
+    eta = -mf.ea_gradient(om, Phi, X)
+    df0 = mf.pair(om, st["R"], eta)
+    tau_o, f, df, pl, trials_o = linesearch.secant_step(lambda t: earcg.evaluate_point(om, Phi, eta, t), st["E"], df0,
+                                                        1.0, prm["delta"], prm["sigma"], prm["gamma"], prm["eps"])
+    tau, out, trials = gp.linesearch(gp.to_device(Phi), gp.to_device(eta), 1.0, prm)
+    log(name, "linesearch", tau, tau_o, trials, trials_o)
+    assert trials == trials_o
+    assert abs(tau - tau_o) <= 1e-9 * abs(tau_o)
+    assert rel(gp.to_blocks(out), pl["Phi"]) < 1e-9
+
+
+def test_full_size_apply_sampled_columns():
+    """64-atom supercell at full size (90^3 box, p = 128): density, V_eff and
+    the energy everywhere, H X on sampled columns (the oracle computes them one
+    by one)."""
+    Problem = _gpu()
+    from oracle import hamiltonian as ham, manifold as mf
+    sysd = W.config("si64_gamma_e20")
+    om = ham.Model(sysd, workers=8)
+    gp = Problem(sysd)
+    assert gp.npw == om.npw and gp.fft == om.fft
+    Z = W.gaussian_block(1, om.npw, om.p)
+    Phi = np.concatenate([mf.polar(b)[0] for b in om.blocks(Z)], axis=0)
+    Phid = gp.to_device(Phi)
+    rho_o = ham.density(om, Phi)
+    Veff_o, _ = ham.potentials(om, rho_o)
+    rho, veff = gp.density(Phid)
+    assert rel(rho.cpu().numpy().reshape(om.fft), rho_o) < 1e-12
+    assert rel(veff.cpu().numpy().reshape(om.fft), Veff_o) < 1e-12
+    X = W.gaussian_block(3, om.npw, om.p)
+    HX = gp.to_blocks(gp.apply_H(Phid, gp.to_device(X)))
+    cols = [0, 1, 63, 127]
+    HX_o = ham.apply_H_k(om, 0, Veff_o, X[:, cols])
+    log("si64 apply_H sampled", rel(HX[:, cols], HX_o))
+    assert rel(HX[:, cols], HX_o) < 1e-12
+    E, terms = gp.energy(Phid)
+    E_o = ham.energy_terms(om, Phi, rho_o)[0]["total"]
+    log("si64 E", E, E_o)
+    assert abs(E - E_o) <= 1e-11 * abs(E_o)
+    gp.close()
