@@ -149,9 +149,15 @@ __global__ void __launch_bounds__(1024) k_heev(int n, z64* Ab, int64_t lda, int6
   if (tid == 0 && info) info[blockIdx.x] = sweeps >= 40 ? 1 : 0;
 }
 
+bool heev_lds(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V,
+              int64_t ldv, int64_t sV, int batch, DevMem& logbuf);
+bool pchol_inv_lds(hipStream_t st, int n, const z64* G, int64_t ldg, double tol, int* rank, z64* Uinv, int64_t ldu);
+
 void heev(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
           int64_t sV, int batch, int* info) {
   if (n <= 0 || batch <= 0) return;
+  static DevMem logbuf;
+  if (heev_lds(st, n, A, lda, sA, w, sw, V, ldv, sV, batch, logbuf)) return;
   const int np = n + (n & 1), half = np / 2;
   const size_t lds = (size_t)half * (2 * sizeof(int) + 2 * sizeof(double) + sizeof(z64)) + 32 * sizeof(double) + 64;
   const int nt = n <= 32 ? 256 : 1024;
@@ -167,6 +173,7 @@ __global__ void __launch_bounds__(1024) k_inverse(int n, z64* Ab, int64_t lda, i
   __shared__ int imax[1024];
   __shared__ int piv;
   __shared__ z64 pinv;
+  __shared__ z64 fcol[1024];
   z64* A = Ab + blockIdx.x * sA;
   z64* W = Wb + (int64_t)blockIdx.x * n * 2 * n;  // W[i + j n], j < 2n
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -179,7 +186,7 @@ __global__ void __launch_bounds__(1024) k_inverse(int n, z64* Ab, int64_t lda, i
   int bad = 0;
   for (int k = 0; k < n; ++k) {
     double best = -1.0;
-    int bi = k;
+    int bi = n;
     for (int i = k + tid; i < n; i += nt) {
       const z64 v = W[i + (int64_t)k * n];
       const double a = v.x * v.x + v.y * v.y;
@@ -188,11 +195,16 @@ __global__ void __launch_bounds__(1024) k_inverse(int n, z64* Ab, int64_t lda, i
     vmax[tid] = best;
     imax[tid] = bi;
     __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double o = vmax[tid + s];
+        const int oi = imax[tid + s];
+        if (o > vmax[tid] || (o == vmax[tid] && oi < imax[tid])) { vmax[tid] = o; imax[tid] = oi; }
+      }
+      __syncthreads();
+    }
     if (tid == 0) {
-      double b = -1.0;
-      int ib = k;
-      for (int t = 0; t < nt; ++t)
-        if (vmax[t] > b || (vmax[t] == b && imax[t] < ib)) { b = vmax[t]; ib = imax[t]; }
+      const int ib = imax[0] < n ? imax[0] : k;
       piv = ib;
       const z64 d = W[ib + (int64_t)k * n];
       const double den = d.x * d.x + d.y * d.y;
@@ -201,26 +213,29 @@ __global__ void __launch_bounds__(1024) k_inverse(int n, z64* Ab, int64_t lda, i
     __syncthreads();
     if (pinv.x == 0.0 && pinv.y == 0.0) bad = 1;
     const int pr = piv;
+    // columns 0..k-1 of the A part are already unit vectors; all others take part
+    const int width = m - k;
     if (pr != k)
-      for (int j = tid; j < m; j += nt) {
-        const z64 t = W[k + (int64_t)j * n];
+      for (int t = tid; t < width; t += nt) {
+        const int j = k + t;
+        const z64 tv = W[k + (int64_t)j * n];
         W[k + (int64_t)j * n] = W[pr + (int64_t)j * n];
-        W[pr + (int64_t)j * n] = t;
+        W[pr + (int64_t)j * n] = tv;
       }
     __syncthreads();
-    for (int j = tid; j < m; j += nt) W[k + (int64_t)j * n] = cmul<double>(W[k + (int64_t)j * n], pinv);
-    __syncthreads();
-    // eliminate column k from the other rows; the multipliers are read before
-    // any row is updated (column k itself is updated last)
-    for (int e = tid; e < n * m; e += nt) {
-      const int i = e % n, j = e / n;
-      if (i == k || j == k) continue;
-      const z64 f = W[i + (int64_t)k * n];
-      W[e] = csub<double>(W[e], cmul<double>(f, W[k + (int64_t)j * n]));
+    for (int t = tid; t < width; t += nt) {
+      const int j = k + t;
+      W[k + (int64_t)j * n] = cmul<double>(W[k + (int64_t)j * n], pinv);
     }
+    for (int i = tid; i < n; i += nt) fcol[i] = W[i + (int64_t)k * n];
     __syncthreads();
-    for (int i = tid; i < n; i += nt)
-      if (i != k) W[i + (int64_t)k * n] = mk<double>(0, 0);
+    for (int e = tid; e < n * width; e += nt) {
+      const int i = e % n, t = e / n;
+      if (i == k) continue;
+      const int j = k + t;
+      const z64 f = fcol[i];
+      W[i + (int64_t)j * n] = csub<double>(W[i + (int64_t)j * n], cmul<double>(f, W[k + (int64_t)j * n]));
+    }
     __syncthreads();
   }
   for (int e = tid; e < n * n; e += nt) {
@@ -232,7 +247,8 @@ __global__ void __launch_bounds__(1024) k_inverse(int n, z64* Ab, int64_t lda, i
 
 void inverse(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, z64* work, int batch, int* info) {
   if (n <= 0 || batch <= 0) return;
-  hipLaunchKernelGGL(k_inverse, dim3(batch), dim3(n <= 64 ? 256 : 1024), 0, st, n, A, lda, sA, work, info);
+  if (n > 1024) fail(EAHP_EINVAL, "inverse: n > 1024");
+  hipLaunchKernelGGL(k_inverse, dim3(batch), dim3(1024), 0, st, n, A, lda, sA, work, info);
   HIPCK(hipGetLastError());
 }
 
@@ -352,6 +368,7 @@ __global__ void __launch_bounds__(1024) k_pchol(int n, z64* G, int64_t ldg, doub
 void pchol_inv(hipStream_t st, int n, z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* Uinv, int64_t ldu,
                int* info) {
   if (n <= 0) return;
+  if (pchol_inv_lds(st, n, G, ldg, tol, rank, Uinv, ldu)) return;
   const size_t lds = (size_t)n * sizeof(int) + 64;
   HIPCK(hipFuncSetAttribute((const void*)k_pchol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_pchol, dim3(1), dim3(n <= 64 ? 256 : 1024), lds, st, n, G, ldg, tol, piv, rank, Uinv, ldu,

@@ -111,5 +111,8 @@ void spectral_fn(hipStream_t st, int p, const z64* V, int64_t ldv, int64_t sV, c
 void hermitize(hipStream_t st, int p, z64* M, int64_t ldm, int64_t sM, int batch);
 void add_diag(hipStream_t st, int p, z64* M, int64_t ldm, int64_t sM, double v, int batch);
 void set_identity(hipStream_t st, int p, z64* M, int64_t ldm);
+// (A - s_l I) y_l = c_l for all columns of Yt (q x p, ld q; overwritten by the
+// solutions) through one Householder tridiagonalisation of A (destroyed).
+void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws);
 
 }  // namespace eahp

@@ -147,7 +147,7 @@ void ea_gradient(eahp_problem* pb, const z64* Phi, const z64* X, z64* G) {
 namespace {
 
 struct FomWork {
-  DevMem V, W, A, Cj, C, E, Rj, Ah, QA, wA, T1, T2, Y, YS, Sig, U, s, alpha, Gm, PU, tmp, piv;
+  DevMem V, W, A, Cj, C, E, Rj, Ah, QA, wA, T1, T2, Y, YS, Sig, U, s, alpha, Gm, PU, tmp, piv, tri;
   int64_t n = 0;
   int qcap = 0;
 };
@@ -275,14 +275,11 @@ FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64*
     w.T2.ensure(sizeof(z64) * q * p);
     w.Y.ensure(sizeof(z64) * q * p);
     w.YS.ensure(sizeof(z64) * q * p);
+    // in the eigenbasis of Sigma: (A_q - s_l) y~_l = (C_q U)[:, l], then Y = Y~ U^H
     copy2d(st, q, q, w.A.as<z64>(), ldA, w.Ah.as<z64>(), q);
-    heev(st, q, w.Ah.as<z64>(), q, 0, w.wA.as<double>(), 0, w.QA.as<z64>(), q, 0, 1, pb->d_info.as<int>());
-    gemm_hn<double>(st, q, q, p, w.QA.as<z64>(), q, w.Cj.as<z64>(), ldA, w.T1.as<z64>(), q, 1.0, 0.0,
-                    pb->ws.gemm_part);
-    gemm_nn<double>(st, q, p, p, w.T1.as<z64>(), q, w.U.as<z64>(), p, 0, w.T2.as<z64>(), q, 1.0, 0.0, 0.0);
-    sylv_divide(st, q, p, w.wA.as<double>(), w.s.as<double>(), w.T2.as<z64>(), q);
-    gemm_nn<double>(st, q, q, p, w.QA.as<z64>(), q, w.T2.as<z64>(), q, 0, w.T1.as<z64>(), q, 1.0, 0.0, 0.0);
-    gemm_nn<double>(st, q, p, p, w.T1.as<z64>(), q, w.U.as<z64>(), p, 1, w.Y.as<z64>(), q, 1.0, 0.0, 0.0);
+    gemm_nn<double>(st, q, p, p, w.Cj.as<z64>(), ldA, w.U.as<z64>(), p, 0, w.T2.as<z64>(), q, 1.0, 0.0, 0.0);
+    sylvester_tridiag(st, q, p, w.Ah.as<z64>(), q, w.s.as<double>(), w.T2.as<z64>(), w.tri);
+    gemm_nn<double>(st, q, p, p, w.T2.as<z64>(), q, w.U.as<z64>(), p, 1, w.Y.as<z64>(), q, 1.0, 0.0, 0.0);
     // ---- E = C - (W Y - V Y Sigma)
     axpby<double>(st, np_, 1.0, C, 0.0, E);
     gemm_nn<double>(st, n, q, p, w.W.as<z64>(), n, w.Y.as<z64>(), q, 0, E, n, -1.0, 0.0, 1.0);

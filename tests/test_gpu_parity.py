@@ -211,3 +211,44 @@ def test_full_size_apply_sampled_columns():
     log("si64 E", E, E_o)
     assert abs(E - E_o) <= 1e-11 * abs(E_o)
     gp.close()
+
+
+def test_full_size_manifold_ops():
+    """p = 128 (the LDS Jacobi, pivoted Cholesky and Gauss-Jordan paths):
+    retraction, transport, EA gradient and a 3-iteration FOM on the 64-atom
+    supercell against the oracle."""
+    Problem = _gpu()
+    from oracle import earcg, hamiltonian as ham, manifold as mf
+    sysd = W.config("si64_gamma_e20")
+    om = ham.Model(sysd, workers=8)
+    gp = Problem(sysd)
+    Z = W.gaussian_block(1, om.npw, om.p)
+    Phi = np.concatenate([mf.polar(b)[0] for b in om.blocks(Z)], axis=0)
+    M = Phi.conj().T @ W.gaussian_block(8, om.npw, om.p)
+    eta = 0.05 * (W.gaussian_block(8, om.npw, om.p) - Phi @ (0.5 * (M + M.conj().T)))
+    v = W.gaussian_block(9, om.npw, om.p)
+    tau = 0.8
+    Pn_o, facs = mf.retract(om, Phi, eta, tau)
+    Pn = gp.to_blocks(gp.retract(gp.to_device(Phi), gp.to_device(eta), tau))
+    log("si64 retract", rel(Pn, Pn_o))
+    assert rel(Pn, Pn_o) < 1e-11
+    T_o = mf.transport_general(om, Pn_o, tau * eta, v, facs)
+    T = gp.to_blocks(gp.transport(gp.to_device(Phi), gp.to_device(tau * eta), gp.to_device(v)))
+    log("si64 transport", rel(T, T_o))
+    assert rel(T, T_o) < 1e-10
+    st = mf.state(om, Phi)
+    lam_max = float(np.linalg.eigvalsh(st["lams"][0])[-1])
+    mu = lam_max - float(st["Veff"].min()) + 1.0
+    prm = dict(W.DEFAULT_PARAMS, fom_rtol=1e-12, fom_maxit=3)
+    X_o, info_o = earcg.metric_solve(om, Phi, st["HPhi"], st["lams"], st["Veff"], mu, prm)
+    X, its, rr = gp.metric_solve(gp.to_device(Phi), mu, 1e-12, 3)
+    X = gp.to_blocks(X)
+    log("si64 fom", its, info_o[0]["iters"], rr, info_o[0]["relres"], rel(X, X_o))
+    assert its[0] == info_o[0]["iters"]
+    assert abs(rr[0] - info_o[0]["relres"]) <= 1e-8 * info_o[0]["relres"]
+    assert rel(X, X_o) < 1e-9
+    G_o = mf.ea_gradient(om, Phi, X_o)
+    G = gp.to_blocks(gp.ea_gradient(gp.to_device(Phi), gp.to_device(X_o)))
+    log("si64 gradient", rel(G, G_o))
+    assert rel(G, G_o) < 1e-10
+    gp.close()
