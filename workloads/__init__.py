@@ -49,7 +49,7 @@ DEFAULT_PARAMS = dict(
     tol=1e-8,
     maxit=200,
     mu_warm=1.0,
-    warm_rtol=0.1,
+    warm_rtol=1e-2,
     rank_tol=1e-7,
 )
 
