@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--config", default="si64_gamma_e20")
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 512 MiB device copy (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not part of this build",
@@ -115,6 +117,12 @@ def main():
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     lib.eahp_solver_destroy(sv)
     pb.close()
+    if args.copy_probe:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] copy probe: 536870912 bytes read, 536870912 bytes written", file=sys.stderr, flush=True)
     elapsed = t1 - t0
     value = napply / elapsed
     out = {

@@ -145,6 +145,7 @@ struct eahp_solver {
   eahp_problem* pb = nullptr;
   eahp_solve_params prm{};
   DevMem fr[12], lamA, lamB, lamw;
+  LamEig le;
   RetractFactors Fa, Fb;
   RetractFactors* Ft = nullptr;
   z64 *Phi = nullptr, *HPhi = nullptr, *R = nullptr, *Phit = nullptr, *HPhit = nullptr, *Rt = nullptr;
@@ -165,18 +166,11 @@ bool solver_converged(const eahp_solver* sv) { return sv->rn <= sv->prm.tol; }
 // max(mu_warm, lambda_max(Lambda) - min V_eff + 1), which makes every
 // H - s_l (s_l eigenvalues of Sigma) positive definite because H >= min V_eff.
 double mu_for(eahp_solver* sv, double r, const z64* Lam) {
-  if (r <= sv->prm.warm_rtol) return sv->prm.mu;
   eahp_problem* pb = sv->pb;
+  lambda_eig(pb, Lam, sv->le);  // also the eigenbasis of Sigma = Lambda - mu I for the FOM
+  if (r <= sv->prm.warm_rtol) return sv->prm.mu;
   hipStream_t st = pb->ctx->stream;
-  const int p = pb->p, nk = pb->nk;
-  const int64_t pp = (int64_t)p * p;
-  sv->lamw.ensure(sizeof(z64) * nk * pp * 2 + sizeof(double) * nk * p);
-  z64* A = sv->lamw.as<z64>();
-  z64* V = A + nk * pp;
-  double* w = reinterpret_cast<double*>(V + nk * pp);
-  copy2d(st, p, p * nk, Lam, p, A, p);
-  heev(st, p, A, p, pp, w, p, V, p, pp, nk, pb->d_info.as<int>());
-  maxval(st, nk * p, w, scal(pb, S_DOT2));
+  maxval(st, pb->nk * pb->p, sv->le.w.as<double>(), scal(pb, S_DOT2));
   minval_big(st, pb->Ng, pb->d_veff.as<double>(), scal(pb, S_DOT3), pb->ws.partial);
   fetch_scalars(pb, S_DOT3 + 1);
   return std::max(sv->prm.mu_warm, pb->h_scal[S_DOT2] - pb->h_scal[S_DOT3] + 1.0);
@@ -184,7 +178,7 @@ double mu_for(eahp_solver* sv, double r, const z64* Lam) {
 
 void solver_gradient(eahp_solver* sv, const z64* P, const z64* Rr, const z64* L, double m, z64* Gout) {
   eahp_problem* pb = sv->pb;
-  metric_solve(pb, P, Rr, L, m, sv->prm.fom_rtol, sv->prm.fom_maxit, sv->prm.rank_tol, sv->X, nullptr);
+  metric_solve(pb, P, Rr, L, m, sv->prm.fom_rtol, sv->prm.fom_maxit, sv->prm.rank_tol, sv->X, nullptr, &sv->le);
   ea_gradient(pb, P, sv->X, Gout);
 }
 

@@ -55,6 +55,8 @@ __global__ void __launch_bounds__(1024) k_heev(int n, z64* Ab, int64_t lda, int6
   }
   __syncthreads();
   int sweeps = 0;
+  const double tol2 = (4.0 * n * 2.220446049250313e-16) * (4.0 * n * 2.220446049250313e-16);
+  double prev_off = -1.0;
   for (; sweeps < 40; ++sweeps) {
     // convergence test: off-diagonal mass against the whole matrix
     double off = 0, tot = 0;
@@ -67,7 +69,9 @@ __global__ void __launch_bounds__(1024) k_heev(int n, z64* Ab, int64_t lda, int6
     }
     off = block_sum(off, red);
     tot = block_sum(tot, red + 16);
-    if (tid == 0) done = (off <= 1e-30 * tot) || (tot == 0.0);
+    if (tid == 0)
+      done = (off <= tol2 * tot) || (tot == 0.0) || (prev_off >= 0.0 && off < 1e-20 * tot && off > 0.25 * prev_off);
+    prev_off = off;
     __syncthreads();
     if (done) break;
     for (int r = 0; r < np - 1; ++r) {
@@ -423,6 +427,14 @@ __global__ void k_spectral(int p, const z64* Vb, int64_t ldv, int64_t sV, const 
     M[i + (int64_t)j * ldm] = mk<double>(sx, sy);
   }
 }
+__global__ void k_affine(int n, const double* x, double a, double b, double* y) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) y[i] = a + b * x[i];
+}
+void affine(hipStream_t st, int n, const double* x, double a, double b, double* y) {
+  hipLaunchKernelGGL(k_affine, dim3(std::max(1, std::min(1024, (n + 255) / 256))), dim3(256), 0, st, n, x, a, b, y);
+  HIPCK(hipGetLastError());
+}
+
 void spectral_fn(hipStream_t st, int p, const z64* V, int64_t ldv, int64_t sV, const double* d, int64_t sd, double e,
                  z64* M, int64_t ldm, int64_t sM, int batch) {
   hipLaunchKernelGGL(k_spectral, dim3(std::min(1024, (p * p + 255) / 256), batch), dim3(256), 0, st, p, V, ldv, sV, d,

@@ -31,6 +31,8 @@ struct Rot {
   z64 e;  // e^{-i phi}
 };
 
+constexpr int kRing = 8;  // rounds of rotations buffered in LDS before a flush to global memory
+
 // One matrix per work-group.  A (n x n, lda) is read (Hermitian part) and its
 // eigenvalues written to w; rotations to log[batch][round][pair]; the number of
 // rounds performed to nrounds[batch].
@@ -39,10 +41,12 @@ __global__ void __launch_bounds__(1024) k_jacobi_lds(int n, const z64* Ab, int64
                                                      int* nrounds) {
   extern __shared__ unsigned char smem_raw[];
   const int np = n + (n & 1), half = np / 2;
-  z64* P = reinterpret_cast<z64*>(smem_raw);            // n(n+1)/2
-  Rot* rot = reinterpret_cast<Rot*>(P + n * (n + 1) / 2);  // half
-  int* pa = reinterpret_cast<int*>(rot + half);         // half
-  int* pb = pa + half;                                  // half
+  const int nblk = half * (half + 1) / 2;
+  z64* P = reinterpret_cast<z64*>(smem_raw);                   // n(n+1)/2
+  Rot* ring = reinterpret_cast<Rot*>(P + n * (n + 1) / 2);     // kRing x half
+  int* pa = reinterpret_cast<int*>(ring + kRing * half);       // half
+  int* pb = pa + half;                                         // half
+  unsigned short* bq = reinterpret_cast<unsigned short*>(pb + half);  // nblk: (Pp, Q) pairs with Pp <= Q
   __shared__ double red[32];
   __shared__ int done;
   const z64* A = Ab + blockIdx.x * sA;
@@ -59,30 +63,43 @@ __global__ void __launch_bounds__(1024) k_jacobi_lds(int n, const z64* Ab, int64
       P[pk(i, i)] = mk<double>(A[i + (int64_t)i * lda].x, 0.0);
     }
   }
+  // block table: entry Q (Q + 1) / 2 + Pp holds (Pp, Q)
+  for (int Q = tid; Q < half; Q += nt)
+    for (int Pp = 0; Pp <= Q; ++Pp) {
+      bq[2 * (Q * (Q + 1) / 2 + Pp)] = (unsigned short)Pp;
+      bq[2 * (Q * (Q + 1) / 2 + Pp) + 1] = (unsigned short)Q;
+    }
   __syncthreads();
   int rounds = 0;
+  // stop at the rounding floor: off-diagonal mass below (4 n eps)^2 of the
+  // total, or no longer shrinking once below 1e-20 of it
+  const double tol2 = (4.0 * n * 2.220446049250313e-16) * (4.0 * n * 2.220446049250313e-16);
+  double prev_off = -1.0;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0, tot = 0;
-    for (int e = tid; e < ntri; e += nt) {
-      const z64 a = P[e];
-      const double m2 = a.x * a.x + a.y * a.y;
-      // decode: diagonal entries have e = i(i+1)/2 + i
-      int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-      while (i * (i + 1) / 2 > e) --i;
-      while ((i + 1) * (i + 2) / 2 <= e) ++i;
-      const int j = e - i * (i + 1) / 2;
-      if (i == j) tot += m2;
-      else {
-        off += 2.0 * m2;
-        tot += 2.0 * m2;
+    for (int i = 0; i < n; ++i) {
+      // row i of the packed triangle: entries pk(i, 0..i)
+      const int base = i * (i + 1) / 2;
+      for (int j = tid; j <= i; j += nt) {
+        const z64 a = P[base + j];
+        const double m2 = a.x * a.x + a.y * a.y;
+        if (i == j) tot += m2;
+        else {
+          off += 2.0 * m2;
+          tot += 2.0 * m2;
+        }
       }
     }
     off = block_sum(off, red);
     tot = block_sum(tot, red + 16);
-    if (tid == 0) done = (off <= 1e-30 * tot) || (tot == 0.0) || (rounds + np - 1 > max_rounds);
+    if (tid == 0)
+      done = (off <= tol2 * tot) || (tot == 0.0) || (rounds + np - 1 > max_rounds) ||
+             (prev_off >= 0.0 && off < 1e-20 * tot && off > 0.25 * prev_off);
+    prev_off = off;
     __syncthreads();
     if (done) break;
     for (int r = 0; r < np - 1; ++r) {
+      Rot* rot = ring + (rounds % kRing) * half;
       for (int k = tid; k < half; k += nt) {
         int a = rr_slot(k, r, np), b = rr_slot(np - 1 - k, r, np);
         if (a > b) { const int t = a; a = b; b = t; }
@@ -102,16 +119,11 @@ __global__ void __launch_bounds__(1024) k_jacobi_lds(int n, const z64* Ab, int64
           }
         }
         rot[k] = R;
-        log[(int64_t)rounds * half + k] = R;
       }
       __syncthreads();
       // A <- U^H A U on the 2x2 blocks (P <= Q), U_k = [[c, s], [-s e, c e]]
-      const int nblk = half * (half + 1) / 2;
       for (int e2 = tid; e2 < nblk; e2 += nt) {
-        int Q = (int)((sqrt(8.0 * e2 + 1.0) - 1.0) * 0.5);
-        while (Q * (Q + 1) / 2 > e2) --Q;
-        while ((Q + 1) * (Q + 2) / 2 <= e2) ++Q;
-        const int Pp = e2 - Q * (Q + 1) / 2;  // Pp <= Q
+        const int Pp = bq[2 * e2], Q = bq[2 * e2 + 1];
         const int p0 = pa[Pp], p1 = pb[Pp], q0 = pa[Q], q1 = pb[Q];
         const bool vp1 = p1 < n, vq1 = q1 < n;
         const z64 a00 = pget(P, p0, q0);
@@ -129,7 +141,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_lds(int n, const z64* Ab, int64
         z64 c10 = cadd<double>(cscale<double>(b00, RP.s), cscale<double>(cmul<double>(b10, epc), RP.c));
         z64 c11 = cadd<double>(cscale<double>(b01, RP.s), cscale<double>(cmul<double>(b11, epc), RP.c));
         if (Pp == Q) {
-          // diagonal block: (p0,p0), (p1,p1) real; (p1,p0) annihilated when the pair is real
+          // diagonal block: (p0,p0), (p1,p1) real; (p1,p0) annihilated by the rotation
           c00.y = 0.0;
           P[pk(p0, p0)] = c00;
           if (vp1) {
@@ -144,20 +156,32 @@ __global__ void __launch_bounds__(1024) k_jacobi_lds(int n, const z64* Ab, int64
           if (vp1 && vq1) pset(P, p1, q1, c11);
         }
       }
-      __syncthreads();
       ++rounds;
+      if (rounds % kRing == 0) {
+        // flush the ring (its stores are waited on only at the next barrier)
+        Rot* dst = log + (int64_t)(rounds - kRing) * half;
+        for (int e = tid; e < kRing * half; e += nt) dst[e] = ring[e];
+      }
+      __syncthreads();
     }
+  }
+  if (rounds % kRing) {
+    const int first = rounds - rounds % kRing;
+    Rot* dst = log + (int64_t)first * half;
+    for (int e = tid; e < (rounds % kRing) * half; e += nt) dst[e] = ring[e];
   }
   for (int i = tid; i < n; i += nt) w[i] = P[pk(i, i)].x;
   if (tid == 0) nrounds[blockIdx.x] = rounds;
 }
 
-// V (n x n, ldv) = I * U_round0 * U_round1 * ...; grid (row blocks, batch)
+// V (n x n, ldv) = I * U_round0 * U_round1 * ...; grid (row blocks, batch).
+// Rotations are staged kRing rounds at a time in LDS.
 __global__ void __launch_bounds__(256) k_rot_apply(int n, int rows_per_wg, const Rot* logb, int64_t slog,
                                                    const int* nrounds, z64* Vb, int64_t ldv, int64_t sV) {
   extern __shared__ unsigned char smem_raw[];
   const int np = n + (n & 1), half = np / 2;
-  z64* Vs = reinterpret_cast<z64*>(smem_raw);  // rows_per_wg x n, element (r, c) at c * rows + r
+  z64* Vs = reinterpret_cast<z64*>(smem_raw);          // rows_per_wg x n, element (r, c) at c * rows + r
+  Rot* rs = reinterpret_cast<Rot*>(Vs + rows_per_wg * n);  // kRing x half
   const int bt = blockIdx.y;
   const Rot* log = logb + bt * slog;
   z64* V = Vb + bt * sV;
@@ -168,23 +192,29 @@ __global__ void __launch_bounds__(256) k_rot_apply(int n, int rows_per_wg, const
     const int r = e % rows, c = e / rows;
     Vs[c * rows + r] = mk<double>((r0 + r) == c ? 1.0 : 0.0, 0.0);
   }
-  __syncthreads();
   const int nr = nrounds[bt];
-  for (int t = 0; t < nr; ++t) {
-    const int rr = t % (np - 1);
-    for (int e = tid; e < rows * half; e += nt) {
-      const int r = e % rows, k = e / rows;
-      int a = rr_slot(k, rr, np), b = rr_slot(np - 1 - k, rr, np);
-      if (a > b) { const int tmp = a; a = b; b = tmp; }
-      if (b >= n) continue;
-      const Rot R = log[(int64_t)t * half + k];
-      const z64 v0 = Vs[a * rows + r], v1 = Vs[b * rows + r];
-      const z64 v1e = cmul<double>(v1, R.e);
-      Vs[a * rows + r] = cadd<double>(cscale<double>(v0, R.c), cscale<double>(v1e, -R.s));
-      Vs[b * rows + r] = cadd<double>(cscale<double>(v0, R.s), cscale<double>(v1e, R.c));
-    }
+  for (int t0 = 0; t0 < nr; t0 += kRing) {
+    const int cnt = min(kRing, nr - t0);
     __syncthreads();
+    for (int e = tid; e < cnt * half; e += nt) rs[e] = log[(int64_t)t0 * half + e];
+    __syncthreads();
+    for (int u = 0; u < cnt; ++u) {
+      const int rr = (t0 + u) % (np - 1);
+      for (int e = tid; e < rows * half; e += nt) {
+        const int r = e % rows, k = e / rows;
+        int a = rr_slot(k, rr, np), b = rr_slot(np - 1 - k, rr, np);
+        if (a > b) { const int tmp = a; a = b; b = tmp; }
+        if (b >= n) continue;
+        const Rot R = rs[u * half + k];
+        const z64 v0 = Vs[a * rows + r], v1 = Vs[b * rows + r];
+        const z64 v1e = cmul<double>(v1, R.e);
+        Vs[a * rows + r] = cadd<double>(cscale<double>(v0, R.c), cscale<double>(v1e, -R.s));
+        Vs[b * rows + r] = cadd<double>(cscale<double>(v0, R.s), cscale<double>(v1e, R.c));
+      }
+      __syncthreads();
+    }
   }
+  __syncthreads();
   for (int e = tid; e < rows * n; e += nt) {
     const int r = e % rows, c = e / rows;
     V[(r0 + r) + (int64_t)c * ldv] = Vs[c * rows + r];
@@ -202,13 +232,15 @@ bool heev_lds(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, doub
   logbuf.ensure(sizeof(Rot) * slog * batch + sizeof(int) * (batch + 4) + 64);
   Rot* log = logbuf.as<Rot>();
   int* nr = reinterpret_cast<int*>(log + slog * batch);
-  const size_t lds = sizeof(z64) * (size_t)n * (n + 1) / 2 + sizeof(Rot) * half + 2 * sizeof(int) * half + 64;
+  const int nblk = half * (half + 1) / 2;
+  const size_t lds = sizeof(z64) * (size_t)n * (n + 1) / 2 + sizeof(Rot) * kRing * half + 2 * sizeof(int) * half +
+                     2 * sizeof(unsigned short) * nblk + 64;
   HIPCK(hipFuncSetAttribute((const void*)k_jacobi_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_jacobi_lds, dim3(batch), dim3(n <= 32 ? 256 : 1024), lds, st, n, A, lda, sA, w, sw, log, slog,
                      max_rounds, nr);
   HIPCK(hipGetLastError());
   const int rows = n <= 32 ? n : 32;
-  const size_t lds2 = sizeof(z64) * (size_t)rows * n;
+  const size_t lds2 = sizeof(z64) * (size_t)rows * n + sizeof(Rot) * kRing * half;
   HIPCK(hipFuncSetAttribute((const void*)k_rot_apply, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
   hipLaunchKernelGGL(k_rot_apply, dim3((n + rows - 1) / rows, batch), dim3(256), lds2, st, n, rows, log, slog, nr, V,
                      ldv, sV);
@@ -225,8 +257,8 @@ __global__ void __launch_bounds__(1024) k_pchol_lds(int n, const z64* G, int64_t
   z64* P = reinterpret_cast<z64*>(smem_raw);        // packed lower n(n+1)/2
   z64* tmp = P + n * (n + 1) / 2;                   // n
   int* perm = reinterpret_cast<int*>(tmp + n);      // n
-  __shared__ double bv[1024];
-  __shared__ int bi[1024];
+  __shared__ double bv[16];
+  __shared__ int bi[16];
   __shared__ int rk, piv;
   __shared__ double d0;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -243,28 +275,32 @@ __global__ void __launch_bounds__(1024) k_pchol_lds(int n, const z64* G, int64_t
   if (tid == 0) rk = n;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    // parallel argmax of the trailing diagonal (ties -> smallest index)
+    // parallel argmax of the trailing diagonal (ties -> smallest index): waves then block
     double best = -1.0;
     int bidx = n;
     for (int i = k + tid; i < n; i += nt) {
       const double v = P[pk(i, i)].x;
       if (v > best) { best = v; bidx = i; }
     }
-    bv[tid] = best;
-    bi[tid] = bidx;
-    __syncthreads();
-    for (int s = nt / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double o = bv[tid + s];
-        const int oi = bi[tid + s];
-        if (o > bv[tid] || (o == bv[tid] && oi < bi[tid])) { bv[tid] = o; bi[tid] = oi; }
-      }
-      __syncthreads();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bidx, o, 64);
+      if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
     }
+    if ((tid & 63) == 0) {
+      bv[tid >> 6] = best;
+      bi[tid >> 6] = bidx;
+    }
+    __syncthreads();
     if (tid == 0) {
-      if (k == 0) d0 = bv[0];
-      piv = bi[0];
-      if (!(bv[0] > tol * d0) || !(bv[0] > 0.0)) rk = k;
+      double b0 = bv[0];
+      int i0 = bi[0];
+      for (int wv = 1; wv < (nt >> 6); ++wv)
+        if (bv[wv] > b0 || (bv[wv] == b0 && bi[wv] < i0)) { b0 = bv[wv]; i0 = bi[wv]; }
+      if (k == 0) d0 = b0;
+      piv = i0;
+      if (!(b0 > tol * d0) || !(b0 > 0.0)) rk = k;
     }
     __syncthreads();
     if (rk == k) break;

@@ -109,6 +109,8 @@ void lyap_divide(hipStream_t st, int p, const double* d, z64* X, int64_t ldx, in
 void spectral_fn(hipStream_t st, int p, const z64* V, int64_t ldv, int64_t sV, const double* d, int64_t sd,
                  double e, z64* M, int64_t ldm, int64_t sM, int batch);
 void hermitize(hipStream_t st, int p, z64* M, int64_t ldm, int64_t sM, int batch);
+// y = a + b x elementwise (n doubles)
+void affine(hipStream_t st, int n, const double* x, double a, double b, double* y);
 void add_diag(hipStream_t st, int p, z64* M, int64_t ldm, int64_t sM, double v, int batch);
 void set_identity(hipStream_t st, int p, z64* M, int64_t ldm);
 // (A - s_l I) y_l = c_l for all columns of Yt (q x p, ld q; overwritten by the

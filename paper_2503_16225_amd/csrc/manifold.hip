@@ -55,6 +55,18 @@ void retract(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* 
   if (!(dmin > 0.0)) fail(EAHP_ENOTPD, "retraction Gram matrix not positive definite");
 }
 
+void lambda_eig(eahp_problem* pb, const z64* Lam, LamEig& E) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p, nk = pb->nk;
+  const int64_t pp = (int64_t)p * p;
+  E.w.ensure(sizeof(double) * nk * p);
+  E.U.ensure(sizeof(z64) * nk * pp);
+  Scratch& s = scratch();
+  s.b.ensure(sizeof(z64) * nk * pp);
+  copy2d(st, p, p * nk, Lam, p, s.b.as<z64>(), p);
+  heev(st, p, s.b.as<z64>(), p, pp, E.w.as<double>(), p, E.U.as<z64>(), p, pp, nk, pb->d_info.as<int>());
+}
+
 // ---------------------------------------------------------------- transports
 // T(eta) = eta S^-1 - tau R(tau eta) (eta S^-1)^H (eta S^-1)
 void transport_self(eahp_problem* pb, const z64* Phi_new, const z64* eta, double tau, const RetractFactors& F,
@@ -220,7 +232,7 @@ double norm2(eahp_problem* pb, int64_t len, const z64* x) {
 }
 
 FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64* Lam, double mu, double rtol,
-              int maxit, double rank_tol, z64* X) {
+              int maxit, double rank_tol, z64* X, const double* lw, const z64* lU) {
   hipStream_t st = pb->ctx->stream;
   FomWork& w = fomwork();
   const int p = pb->p;
@@ -245,8 +257,14 @@ FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64*
   copy2d(st, p, p, Lam, p, w.Sig.as<z64>(), p);
   add_diag(st, p, w.Sig.as<z64>(), p, 0, -mu, 1);
   w.T1.ensure(sizeof(z64) * p * p);
-  copy2d(st, p, p, w.Sig.as<z64>(), p, w.T1.as<z64>(), p);
-  heev(st, p, w.T1.as<z64>(), p, 0, w.s.as<double>(), 0, w.U.as<z64>(), p, 0, 1, pb->d_info.as<int>());
+  if (lw) {
+    // Sigma = Lambda - mu I shares the eigenvectors of Lambda: s = w - mu
+    affine(st, p, lw, -mu, 1.0, w.s.as<double>());
+    copy2d(st, p, p, lU, p, w.U.as<z64>(), p);
+  } else {
+    copy2d(st, p, p, w.Sig.as<z64>(), p, w.T1.as<z64>(), p);
+    heev(st, p, w.T1.as<z64>(), p, 0, w.s.as<double>(), 0, w.U.as<z64>(), p, 0, 1, pb->d_info.as<int>());
+  }
   // TPA: alpha_j = sum_G |k+G|^2/2 |phi_jG|^2
   col_weighted_norm2(st, n, p, Phi, n, K.d_kin.as<double>(), w.alpha.as<double>());
   // V_1 = rrqr(P^-1 C), W_1 = H V_1
@@ -322,13 +340,15 @@ FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64*
 }  // namespace
 
 void metric_solve(eahp_problem* pb, const z64* Phi, const z64* R, const z64* Lam, double mu, double rtol, int maxit,
-                  double rank_tol, z64* X, std::vector<FomInfo>* info) {
+                  double rank_tol, z64* X, std::vector<FomInfo>* info, const LamEig* leig) {
   if (!(mu > 0)) fail(EAHP_EINVAL, "mu must be positive");
   if (info) info->clear();
   const int p = pb->p;
   for (int ik = 0; ik < pb->nk; ++ik) {
     const int64_t o = (int64_t)p * pb->kp[ik].off;
-    FomInfo fi = fom_k(pb, ik, Phi + o, R + o, Lam + (int64_t)ik * p * p, mu, rtol, maxit, rank_tol, X + o);
+    const double* lw = leig ? leig->w.as<double>() + (int64_t)ik * p : nullptr;
+    const z64* lU = leig ? leig->U.as<z64>() + (int64_t)ik * p * p : nullptr;
+    FomInfo fi = fom_k(pb, ik, Phi + o, R + o, Lam + (int64_t)ik * p * p, mu, rtol, maxit, rank_tol, X + o, lw, lU);
     if (info) info->push_back(fi);
   }
 }

@@ -39,6 +39,11 @@ struct RetractFactors {
   DevMem d, V, Sinv;
 };
 void retract(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* out, RetractFactors& F);
+// Eigendecomposition of Lambda per k (w ascending order not guaranteed).
+struct LamEig {
+  DevMem w, U;
+};
+void lambda_eig(eahp_problem* pb, const z64* Lam, LamEig& E);
 void transport_self(eahp_problem* pb, const z64* Phi_new, const z64* eta, double tau, const RetractFactors& F,
                     z64* out);
 void transport_general(eahp_problem* pb, const z64* Phi_new, const z64* xi, const z64* v, const RetractFactors& F,
@@ -51,6 +56,6 @@ struct FomInfo {
 };
 // Algorithm 4 on every k-point; X out (frame); the potential must be that of Phi.
 void metric_solve(eahp_problem* pb, const z64* Phi, const z64* R, const z64* Lam, double mu, double rtol, int maxit,
-                  double rank_tol, z64* X, std::vector<FomInfo>* info);
+                  double rank_tol, z64* X, std::vector<FomInfo>* info, const LamEig* leig = nullptr);
 
 }  // namespace eahp

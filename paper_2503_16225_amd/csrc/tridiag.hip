@@ -25,70 +25,94 @@ namespace eahp {
 // beta = 2 / v^H v (Hermitian, H x = alpha e1); trailing block
 // A' = H A H via p = beta A v, w = p - (beta/2)(v^H p) v, A' = A - v w^H - w v^H.
 // Outputs: d (diagonal), e (sub-diagonal T[k+1][k]), the reflectors
-// Vh[k+1:, k] and beta[k].  A is destroyed.  Column c of A is owned by
-// work-group c mod G in every step.
-__global__ void __launch_bounds__(256) k_tridiag(int q, z64* A, int64_t lda, double* d, z64* e, z64* Vh,
-                                                 int64_t ldv, double* beta, z64* P) {
+// Vh[k+1:, k] and beta[k].  A is destroyed.
+//
+// Column c of A is owned by work-group c mod G.  One grid barrier per column:
+// after it every work-group holds p (global), forms w, updates its own
+// columns c >= k+2, and recomputes the updated column k+1 itself (nobody
+// writes column k+1 in step k), from which it forms the next reflector and
+// the next p entries of its own columns (double-buffered p).
+__device__ void tri_reflector(int m, const z64* x_in, z64* v, double* red, double* sc, z64& alpha, double& b) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double s2 = 0;
+  for (int i = tid; i < m; i += nt) {
+    const z64 t = x_in ? x_in[i] : v[i];
+    v[i] = t;
+    s2 += t.x * t.x + t.y * t.y;
+  }
+  s2 = block_sum(s2, red);
+  if (tid == 0) sc[0] = s2;
+  __syncthreads();
+  const double xn = sqrt(sc[0]);
+  const z64 x0 = v[0];
+  const double a0 = sqrt(x0.x * x0.x + x0.y * x0.y);
+  if (a0 > 0) alpha = mk<double>(-x0.x / a0 * xn, -x0.y / a0 * xn);
+  else alpha = mk<double>(-xn, 0.0);
+  const z64 v0 = csub<double>(x0, alpha);
+  const double vv = (sc[0] - a0 * a0) + (v0.x * v0.x + v0.y * v0.y);
+  b = vv > 0 ? 2.0 / vv : 0.0;
+  __syncthreads();
+  if (tid == 0) v[0] = v0;
+  __syncthreads();
+}
+
+// p entries of the owned columns c >= c_first: P[c - (k+1)] = b * conj(A[k+1:, c]) . v
+// one wave per column, wave-level reduction
+__device__ void tri_matvec(int q, int k, int c_first, int G, const z64* A, int64_t lda, const z64* v, double b,
+                           z64* P) {
+  const int m = q - k - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int g = blockIdx.x;
+  const int c0 = c_first + ((g - c_first) % G + G) % G;
+  for (int c = c0 + wave * G; c < q; c += nw * G) {
+    const z64* col = A + (k + 1) + (int64_t)c * lda;
+    double sx = 0, sy = 0;
+    for (int r = lane; r < m; r += 64) {
+      const z64 a = col[r], vr = v[r];
+      sx += a.x * vr.x + a.y * vr.y;
+      sy += a.x * vr.y - a.y * vr.x;
+    }
+    sx = warp_sum(sx);
+    sy = warp_sum(sy);
+    if (lane == 0) P[c - (k + 1)] = mk<double>(b * sx, b * sy);
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, double* d, z64* e, z64* Vh,
+                                                  int64_t ldv, double* beta, z64* Pbuf) {
   extern __shared__ unsigned char smem_raw[];
   z64* v = reinterpret_cast<z64*>(smem_raw);  // q
   z64* w = v + q;                             // q
+  z64* vn = w + q;                            // q: next reflector
   __shared__ double red[32];
   __shared__ double sc[4];
   cg::grid_group grid = cg::this_grid();
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  // step 0 reflector and p
+  z64 alpha;
+  double b;
+  tri_reflector(q - 1, A + 1, v, red, sc, alpha, b);
+  if (g == 0) {
+    for (int i = tid; i < q - 1; i += nt) Vh[1 + i] = v[i];
+    if (tid == 0) {
+      d[0] = A[0].x;
+      e[0] = alpha;
+      beta[0] = b;
+    }
+  }
+  tri_matvec(q, 0, 1, G, A, lda, v, b, Pbuf);
+  grid.sync();
   for (int k = 0; k + 1 < q; ++k) {
     const int m = q - k - 1;
-    const z64* x = A + (k + 1) + (int64_t)k * lda;
-    // (a) reflector, computed redundantly by every work-group
-    double s2 = 0;
-    for (int i = tid; i < m; i += nt) {
-      const z64 t = x[i];
-      v[i] = t;
-      s2 += t.x * t.x + t.y * t.y;
-    }
-    s2 = block_sum(s2, red);
-    if (tid == 0) sc[0] = s2;
-    __syncthreads();
-    const double xn = sqrt(sc[0]);
-    const z64 x0 = v[0];
-    const double a0 = sqrt(x0.x * x0.x + x0.y * x0.y);
-    z64 alpha;
-    if (a0 > 0) alpha = mk<double>(-x0.x / a0 * xn, -x0.y / a0 * xn);
-    else alpha = mk<double>(-xn, 0.0);
-    const z64 v0 = csub<double>(x0, alpha);
-    const double vv = (sc[0] - a0 * a0) + (v0.x * v0.x + v0.y * v0.y);
-    const double b = vv > 0 ? 2.0 / vv : 0.0;
-    __syncthreads();
-    if (tid == 0) v[0] = v0;
-    __syncthreads();
-    if (g == 0) {
-      for (int i = tid; i < m; i += nt) Vh[(k + 1 + i) + (int64_t)k * ldv] = v[i];
-      if (tid == 0) {
-        d[k] = A[k + (int64_t)k * lda].x;
-        e[k] = alpha;
-        beta[k] = b;
-      }
-    }
-    // (b) p = beta A_tr v, one owned column at a time (A Hermitian: p_i = beta col_i^H v)
-    for (int c = k + 1 + ((g - (k + 1)) % G + G) % G; c < q; c += G) {
-      const z64* col = A + (k + 1) + (int64_t)c * lda;
-      double sx = 0, sy = 0;
-      for (int r = tid; r < m; r += nt) {
-        const z64 a = col[r], vr = v[r];
-        sx += a.x * vr.x + a.y * vr.y;  // conj(a) v
-        sy += a.x * vr.y - a.y * vr.x;
-      }
-      sx = block_sum(sx, red);
-      sy = block_sum(sy, red + 16);
-      if (tid == 0) P[c - (k + 1)] = mk<double>(b * sx, b * sy);
-    }
-    grid.sync();
-    // (c) w = p - (beta/2)(v^H p) v
+    const z64* P = Pbuf + (int64_t)(k & 1) * q;
+    z64* Pn = Pbuf + (int64_t)((k + 1) & 1) * q;
+    // w = p - (beta/2)(v^H p) v
     double kx = 0;
     for (int i = tid; i < m; i += nt) {
       const z64 pi = P[i];
       w[i] = pi;
-      kx += v[i].x * pi.x + v[i].y * pi.y;  // Re(conj(v) p); v^H p is real for Hermitian A
+      kx += v[i].x * pi.x + v[i].y * pi.y;
     }
     kx = block_sum(kx, red);
     if (tid == 0) sc[1] = 0.5 * b * kx;
@@ -96,23 +120,67 @@ __global__ void __launch_bounds__(256) k_tridiag(int q, z64* A, int64_t lda, dou
     const double K = sc[1];
     for (int i = tid; i < m; i += nt) w[i] = mk<double>(w[i].x - K * v[i].x, w[i].y - K * v[i].y);
     __syncthreads();
-    // (d) A_tr -= v w^H + w v^H on owned columns
-    for (int c = k + 1 + ((g - (k + 1)) % G + G) % G; c < q; c += G) {
-      const int j = c - (k + 1);
-      const z64 wj = w[j], vj = v[j];
-      z64* col = A + (k + 1) + (int64_t)c * lda;
-      for (int r = tid; r < m; r += nt) {
-        const z64 vr = v[r], wr = w[r];
-        // v_r conj(w_j) + w_r conj(v_j)
-        const double ux = vr.x * wj.x + vr.y * wj.y + wr.x * vj.x + wr.y * vj.y;
-        const double uy = vr.y * wj.x - vr.x * wj.y + wr.y * vj.x - wr.x * vj.y;
-        const z64 a = col[r];
-        col[r] = mk<double>(a.x - ux, a.y - uy);
+    if (m == 1) {
+      // last step: only the 1 x 1 trailing block remains
+      if (g == 0 && tid == 0) {
+        const z64 a = A[(k + 1) + (int64_t)(k + 1) * lda];
+        const double u = 2.0 * (v[0].x * w[0].x + v[0].y * w[0].y);
+        d[k + 1] = a.x - u;
+      }
+      break;
+    }
+    // update owned columns c >= k + 2, one wave per column
+    {
+      const int cf = k + 2;
+      const int c0 = cf + ((g - cf) % G + G) % G;
+      for (int c = c0 + wave * G; c < q; c += nw * G) {
+        const int j = c - (k + 1);
+        const z64 wj = w[j], vj = v[j];
+        z64* col = A + (k + 1) + (int64_t)c * lda;
+        for (int r = lane; r < m; r += 64) {
+          const z64 vr = v[r], wr = w[r];
+          const double ux = vr.x * wj.x + vr.y * wj.y + wr.x * vj.x + wr.y * vj.y;
+          const double uy = vr.y * wj.x - vr.x * wj.y + wr.y * vj.x - wr.x * vj.y;
+          const z64 a = col[r];
+          col[r] = mk<double>(a.x - ux, a.y - uy);
+        }
       }
     }
+    // updated column k+1 (rows k+2..), recomputed redundantly: x = A[k+2:, k+1] - v w_0^* - w v_0^*
+    const int m2 = m - 1;
+    {
+      const z64* colk1 = A + (k + 2) + (int64_t)(k + 1) * lda;
+      const z64 w0 = w[0], v0 = v[0];
+      for (int r = tid; r < m2; r += nt) {
+        const z64 vr = v[r + 1], wr = w[r + 1];
+        const double ux = vr.x * w0.x + vr.y * w0.y + wr.x * v0.x + wr.y * v0.y;
+        const double uy = vr.y * w0.x - vr.x * w0.y + wr.y * v0.x - wr.x * v0.y;
+        const z64 a = colk1[r];
+        vn[r] = mk<double>(a.x - ux, a.y - uy);
+      }
+    }
+    double dk1 = 0;
+    if (tid == 0) {
+      const z64 a = A[(k + 1) + (int64_t)(k + 1) * lda];
+      dk1 = a.x - 2.0 * (v[0].x * w[0].x + v[0].y * w[0].y);
+    }
+    __syncthreads();
+    // next reflector from vn (in place), then it becomes v
+    tri_reflector(m2, nullptr, vn, red, sc, alpha, b);
+    for (int i = tid; i < m2; i += nt) v[i] = vn[i];
+    __syncthreads();
+    if (g == 0) {
+      for (int i = tid; i < m2; i += nt) Vh[(k + 2 + i) + (int64_t)(k + 1) * ldv] = v[i];
+      if (tid == 0) {
+        d[k + 1] = dk1;
+        e[k + 1] = alpha;
+        beta[k + 1] = b;
+      }
+    }
+    // p of step k+1 on owned columns c >= k + 2 (already updated by this work-group)
+    tri_matvec(q, k + 1, k + 2, G, A, lda, v, b, Pn);
     grid.sync();
   }
-  if (g == 0 && tid == 0) d[q - 1] = A[(q - 1) + (int64_t)(q - 1) * lda].x;
 }
 
 // Apply the reflectors to the columns of B (q x ncols, ld ldb), one work-group
@@ -207,8 +275,9 @@ __global__ void k_set_d0(const z64* A, double* d) { d[0] = A[0].x; }
 // destroyed.  ws must hold q*q + q*3*p + 4*q complex values.
 void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws) {
   if (q <= 0 || p <= 0) return;
-  if (q > 4096) fail(EAHP_EINVAL, "projected FOM system larger than 4096");
+  if (q > 3200) fail(EAHP_EINVAL, "projected FOM system larger than 3200");
   const size_t need = sizeof(z64) * ((size_t)q * q + (size_t)3 * q * p + 4 * (size_t)q) + sizeof(double) * 2 * q + 256;
+  // P is double-buffered: 2 q entries after e (q) fit in the 4 q tail
   ws.ensure(need);
   z64* Vh = ws.as<z64>();
   z64* W = Vh + (size_t)q * q;
@@ -217,18 +286,19 @@ void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const 
   double* dd = reinterpret_cast<double*>(P + 2 * q);
   double* bt = dd + q;
   if (q >= 2) {
-    const size_t lds = sizeof(z64) * 2 * (size_t)q;
+    const size_t lds = sizeof(z64) * 3 * (size_t)q;
     HIPCK(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
-    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tridiag, 256, lds));
+    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tridiag, 1024, lds));
     int dev = 0, ncu = 0;
     HIPCK(hipGetDevice(&dev));
     HIPCK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    int G = std::min({std::max(1, per_cu) * ncu, ncu, std::max(1, (q + 3) / 4)});
+    // one work-group per 16 columns: enough waves for the column loops, few work-groups per barrier
+    const int G = std::min({std::max(1, per_cu) * ncu, ncu, std::max(1, (q + 15) / 16)});
     int qq = q;
     int64_t la = lda, lv = q;
     void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P};
-    HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(G), dim3(256), args, lds, st));
+    HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(G), dim3(1024), args, lds, st));
     hipLaunchKernelGGL(k_apply_refl, dim3(p), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, 1);
   } else {
     hipLaunchKernelGGL(k_set_d0, dim3(1), dim3(1), 0, st, A, dd);

@@ -1,0 +1,79 @@
+"""Summaries of rocprofv3 results databases (kernel durations, PMC counters).
+
+    python -m paper_2503_16225_amd.profile_summary trace DB
+    python -m paper_2503_16225_amd.profile_summary pmc FETCH_DB WRITE_DB --kernel NAME [--copy-bytes B]
+
+The pmc mode reports FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the named
+kernel, scaled by the ratio of the known byte count of a plain device copy
+to what the same counters read for that copy kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import sqlite3
+import statistics
+
+
+def trace(db, top=20):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, duration from kernels").fetchall()
+    agg = {}
+    for name, dur in rows:
+        agg.setdefault(name.split("(")[0], []).append(dur)
+    tot = sum(sum(v) for v in agg.values())
+    out = []
+    for name, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        out.append((name, len(v), sum(v) / 1e6, statistics.mean(v) / 1e6, 100.0 * sum(v) / tot))
+    return out, tot / 1e6
+
+
+def pmc(db, counter):
+    """{kernel: [counter value per dispatch]} (summed over counter instances)."""
+    con = sqlite3.connect(db)
+    rows = con.execute(
+        "select k.name, p.dispatch_id, p.counter_value from pmc_events p join kernels k on p.dispatch_id = k.dispatch_id "
+        "where p.counter_name = ?", (counter,)).fetchall()
+    agg = {}
+    for name, did, val in rows:
+        agg.setdefault(name.split("(")[0], {}).setdefault(did, 0.0)
+        agg[name.split("(")[0]][did] += float(val)
+    return {k: list(v.values()) for k, v in agg.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["trace", "pmc"])
+    ap.add_argument("dbs", nargs="+")
+    ap.add_argument("--kernel", default=None)
+    ap.add_argument("--copy-bytes", type=float, default=536870912.0)
+    ap.add_argument("--copy-kernel", default="copy")
+    a = ap.parse_args()
+    if a.mode == "trace":
+        rows, tot = trace(a.dbs[0])
+        print(f"total kernel time {tot:.3f} ms")
+        print("| kernel | calls | total ms | avg ms | % |")
+        print("|---|---|---|---|---|")
+        for name, n, t, avg, pct in rows:
+            print(f"| {name} | {n} | {t:.3f} | {avg:.4f} | {pct:.1f} |")
+        return
+    fetch = pmc(a.dbs[0], "FETCH_SIZE")
+    write = pmc(a.dbs[1], "WRITE_SIZE")
+    # the copy probe is the largest single dispatch of the copy kernel
+    ck = [k for k in fetch if a.copy_kernel.lower() in k.lower() and "eahp" not in k]
+    cf = max(max(fetch[k]) for k in ck) * 1024.0 if ck else float("nan")
+    cw = max(max(write[k]) for k in ck if k in write) * 1024.0 if ck else float("nan")
+    sf, sw = a.copy_bytes / cf, a.copy_bytes / cw
+    print(f"copy probe ({ck}): FETCH {cf:.6g} B, WRITE {cw:.6g} B for a {a.copy_bytes:.6g} B copy "
+          f"-> scale FETCH x{sf:.4f}, WRITE x{sw:.4f}")
+    print("| kernel | dispatches | FETCH MB/dispatch (scaled) | WRITE MB/dispatch (scaled) | total MB |")
+    print("|---|---|---|---|---|")
+    for k in sorted(fetch, key=lambda x: -statistics.mean(fetch[x])):
+        if a.kernel and a.kernel not in k:
+            continue
+        f = statistics.mean(fetch[k]) * 1024.0 * sf
+        w = statistics.mean(write.get(k, [0.0])) * 1024.0 * sw
+        print(f"| {k} | {len(fetch[k])} | {f / 1e6:.3f} | {w / 1e6:.3f} | {(f + w) / 1e6:.3f} |")
+
+
+if __name__ == "__main__":
+    main()
