@@ -48,9 +48,14 @@ struct Trial {
   double df;
 };
 
+LineFactors& line_factors() {
+  static LineFactors L;
+  return L;
+}
+
 // f(t), f'(t) at R_Phi(t eta) into the trial buffers
 void eval_trial(eahp_problem* pb, const z64* Phi, const z64* eta, double t, Trial& tr) {
-  retract(pb, Phi, eta, t, tr.Phi, *tr.F);
+  if (!retract_line(pb, Phi, eta, t, line_factors(), tr.Phi, *tr.F)) retract(pb, Phi, eta, t, tr.Phi, *tr.F);
   evaluate_point(pb, tr.Phi, tr.HPhi, tr.R, tr.Lam, &tr.sc);
   transport_self(pb, tr.Phi, eta, t, *tr.F, tr.Teta);
   tr.df = frame_dot(pb, tr.R, tr.Teta);
@@ -74,6 +79,7 @@ double secant_step(eahp_problem* pb, const z64* Phi, const z64* eta, double f0, 
     eval_trial(pb, Phi, eta, t, tr);
   };
   auto ok = [&](double f, double df) { return f <= fbound && std::fabs(df) <= c * std::fabs(df0); };
+  line_prepare(pb, Phi, eta, line_factors());
   double a = 0.0, dfa = df0;
   double b = tau0;
   ev(b);

@@ -427,6 +427,38 @@ __global__ void k_spectral(int p, const z64* Vb, int64_t ldv, int64_t sV, const 
     M[i + (int64_t)j * ldm] = mk<double>(sx, sy);
   }
 }
+// Inverse square root of S = V (diag(d) + Dt) V^H to first order in the
+// Hermitian perturbation Dt (given in the eigenbasis V of the unperturbed
+// part, d = 1 + tau^2 w): Mt = diag(d^-1/2) - Dt o K with
+// K_ij = 1 / (s_i s_j (s_i + s_j)), s = d^1/2 (the divided difference of
+// x^-1/2 at d_i, d_j).  Writes d and Mt; the caller forms V Mt V^H.
+__global__ void k_polar_fo(int p, const double* wb, int64_t sw, double tau, const z64* Dtb, int64_t sD, double* db,
+                           z64* Mtb, int64_t sM) {
+  const double* w = wb + blockIdx.y * sw;
+  const z64* Dt = Dtb + blockIdx.y * sD;
+  double* d = db + blockIdx.y * sw;
+  z64* Mt = Mtb + blockIdx.y * sM;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < p * p; e += gridDim.x * blockDim.x) {
+    const int i = e % p, j = e / p;
+    const double di = 1.0 + tau * tau * w[i], dj = 1.0 + tau * tau * w[j];
+    const double si = sqrt(di), sj = sqrt(dj);
+    const double k = 1.0 / (si * sj * (si + sj));
+    z64 m = cscale<double>(Dt[i + (int64_t)j * p], -k);
+    if (i == j) {
+      m.x += 1.0 / si;
+      m.y = 0.0;
+      d[i] = di;
+    }
+    Mt[i + (int64_t)j * p] = m;
+  }
+}
+void polar_first_order(hipStream_t st, int p, const double* w, double tau, const z64* Dt, double* d, z64* Mt,
+                       int batch) {
+  hipLaunchKernelGGL(k_polar_fo, dim3(std::min(1024, (p * p + 255) / 256), batch), dim3(256), 0, st, p, w,
+                     (int64_t)p, tau, Dt, (int64_t)p * p, d, Mt, (int64_t)p * p);
+  HIPCK(hipGetLastError());
+}
+
 __global__ void k_affine(int n, const double* x, double a, double b, double* y) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) y[i] = a + b * x[i];
 }

@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(1024) k_inv_yz(ColMap cm, GridGeom g, FftPlan 
   __syncthreads();
   lds_fft<T, MAXPTS>(pl, Lines{g.n3, 1, g.n2, g.n3, 0}, pz, tz, (T)1);
   lds_fft<T, MAXPTS>(pl, Lines{g.n2, g.n3, g.n3, 1, 1}, py, ty, (T)1);
-  cplx<T>* out = Tb + ((int64_t)c * g.ns + s) * np;
+  cplx<T>* out = Tb + ((int64_t)c * g.ns + s) * g.ps;
   for (int i = threadIdx.x; i < np; i += blockDim.x) out[i] = pl[i];
 }
 
@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(1024) k_fwd_yz(ColMap cm, GridGeom g, FftPlan 
   const KDesc& k = col_kd(cm, c, base);
   const int g0 = k.plane_start[s], g1 = k.plane_start[s + 1];
   if (g1 == g0) return;  // block-uniform: this k-point has no plane waves here
-  const cplx<T>* in = Tb + ((int64_t)c * g.ns + s) * np;
+  const cplx<T>* in = Tb + ((int64_t)c * g.ns + s) * g.ps;
   for (int i = threadIdx.x; i < np; i += blockDim.x) pl[i] = in[i];
   for (int i = threadIdx.x; i < g.n3; i += blockDim.x) tz[i] = twz[i];
   for (int i = threadIdx.x; i < g.n2; i += blockDim.x) ty[i] = twy[i];
@@ -130,20 +130,20 @@ __global__ void __launch_bounds__(512) k_x_local(int ncols, int cb, GridGeom g, 
   for (int c = c0; c < c1; ++c) {
     for (int e = threadIdx.x; e < n1 * tile; e += blockDim.x) buf[e] = mk<T>(0, 0);
     __syncthreads();
-    const cplx<T>* in = Tb + (int64_t)c * g.ns * np + t0;
+    const cplx<T>* in = Tb + (int64_t)c * g.ns * g.ps + t0;
     for (int e = threadIdx.x; e < g.ns * cnt; e += blockDim.x) {
       const int s = e / cnt, t = e - s * cnt;
-      buf[g.plane_i1[s] * tile + t] = in[(int64_t)s * np + t];
+      buf[g.plane_i1[s] * tile + t] = in[(int64_t)s * g.ps + t];
     }
     __syncthreads();
     lds_fft<T, MAXPTS>(buf, L, px, tw, (T)1);
     for (int e = threadIdx.x; e < n1 * tile; e += blockDim.x) buf[e] = cscale<T>(buf[e], vt[e]);
     __syncthreads();
     lds_fft<T, MAXPTS>(buf, L, px, tw, (T)-1);
-    cplx<T>* out = Tb + (int64_t)c * g.ns * np + t0;
+    cplx<T>* out = Tb + (int64_t)c * g.ns * g.ps + t0;
     for (int e = threadIdx.x; e < g.ns * cnt; e += blockDim.x) {
       const int s = e / cnt, t = e - s * cnt;
-      out[(int64_t)s * np + t] = buf[g.plane_i1[s] * tile + t];
+      out[(int64_t)s * g.ps + t] = buf[g.plane_i1[s] * tile + t];
     }
     __syncthreads();
   }
@@ -151,9 +151,10 @@ __global__ void __launch_bounds__(512) k_x_local(int ncols, int cb, GridGeom g, 
 
 // ------------------------------------------------------------------ x_density
 template <int MAXPTS>
-__global__ void __launch_bounds__(512) k_x_density(ColMap cm, int ncols, GridGeom g, int tile, FftPlan px,
+__global__ void __launch_bounds__(512) k_x_density(ColMap cm, int ncols, int cpg, GridGeom g, int tile, FftPlan px,
                                                    const z64* __restrict__ twx, const z64* __restrict__ Tb,
-                                                   double occ_over_omega, double* __restrict__ rho, int accumulate) {
+                                                   double occ_over_omega, double* __restrict__ rho, int accumulate,
+                                                   int64_t sgrp) {
   extern __shared__ unsigned char smem_raw[];
   const int n1 = g.n1, np = g.n2 * g.n3;
   z64* buf = reinterpret_cast<z64*>(smem_raw);
@@ -165,16 +166,19 @@ __global__ void __launch_bounds__(512) k_x_density(ColMap cm, int ncols, GridGeo
 #pragma unroll
   for (int r = 0; r < MAXPTS; ++r) acc[r] = 0.0;
   const Lines L{n1, tile, tile, 1, 1};
-  for (int c = 0; c < ncols; ++c) {
+  // column group blockIdx.y writes its own partial density (rho + blockIdx.y * sgrp)
+  const int cbeg = blockIdx.y * cpg, cend = min(ncols, cbeg + cpg);
+  rho += blockIdx.y * sgrp;
+  for (int c = cbeg; c < cend; ++c) {
     int64_t base;
     const KDesc& k = col_kd(cm, c, base);
     const double wgt = k.w * occ_over_omega;
     for (int e = threadIdx.x; e < n1 * tile; e += blockDim.x) buf[e] = mk<double>(0, 0);
     __syncthreads();
-    const z64* in = Tb + (int64_t)c * g.ns * np + t0;
+    const z64* in = Tb + (int64_t)c * g.ns * g.ps + t0;
     for (int e = threadIdx.x; e < g.ns * cnt; e += blockDim.x) {
       const int s = e / cnt, t = e - s * cnt;
-      buf[g.plane_i1[s] * tile + t] = in[(int64_t)s * np + t];
+      buf[g.plane_i1[s] * tile + t] = in[(int64_t)s * g.ps + t];
     }
     __syncthreads();
     lds_fft<double, MAXPTS>(buf, L, px, tw, 1.0);
@@ -274,8 +278,8 @@ void launch_x_local(hipStream_t st, int ncols, const GridGeom& g, const FftPlan&
   const int nt = g.n1 * tile >= 2048 ? 512 : 256;
   const int ntiles = (np + tile - 1) / tile;
   // columns per work-group: enough work-groups to fill the chip, V reused by the chunk
-  int cb = 8;
-  while (cb > 1 && (int64_t)ntiles * ((ncols + cb - 1) / cb) < 2048) cb /= 2;
+  int cb = 16;
+  while (cb > 1 && (int64_t)ntiles * ((ncols + cb - 1) / cb) < 1024) cb /= 2;
   dim3 grid(ntiles, (ncols + cb - 1) / cb);
   switch (pick_maxpts((int64_t)g.n1 * tile, nt)) {
 #define CASE(M)                                                                                       \
@@ -289,24 +293,56 @@ void launch_x_local(hipStream_t st, int ncols, const GridGeom& g, const FftPlan&
   HIPCK(hipGetLastError());
 }
 
+// rho[i] (+)= sum over the column groups of part[grp][i], groups in order
+__global__ void __launch_bounds__(256) k_sum_groups(int64_t n, int ngrp, const double* __restrict__ part,
+                                                    int64_t sgrp, double* __restrict__ rho, int accumulate) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int gi = 0; gi < ngrp; ++gi) acc += part[gi * sgrp + i];
+    rho[i] = accumulate ? rho[i] + acc : acc;
+  }
+}
+
 void launch_x_density(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const FftPlan& px,
-                      const z64* twx, const z64* Tb, double occ_over_omega, double* rho, int accumulate) {
+                      const z64* twx, const z64* Tb, double occ_over_omega, double* rho, int accumulate,
+                      DevMem& part) {
   const int np = g.n2 * g.n3;
   const int tile = std::min(32, x_tile(g.n1, np, sizeof(z64), 48 * 1024));
   const size_t lds = (size_t)g.n1 * tile * sizeof(z64) + g.n1 * sizeof(z64);
   const int nt = 256;
   const int ntiles = (np + tile - 1) / tile;
+  // column groups until the grid fills the chip, while the partial densities
+  // (written and read once more) stay under a tenth of the slab bytes; each
+  // group sums into its own partial, reduced afterwards in a fixed order
+  int ngrp = 1;
+  while (ngrp < 16 && (int64_t)ntiles * ngrp < 1024 && (int64_t)(2 * ngrp) * g.n1 * 10 <= (int64_t)ncols * g.ns)
+    ngrp *= 2;
+  const int cpg = (ncols + ngrp - 1) / ngrp;
+  ngrp = (ncols + cpg - 1) / cpg;
+  const int64_t Ng = (int64_t)g.n1 * np;
+  double* dst = rho;
+  int acc_k = accumulate;
+  if (ngrp > 1) {
+    part.ensure(sizeof(double) * Ng * ngrp);
+    dst = part.as<double>();
+    acc_k = 0;
+  }
   switch (pick_maxpts((int64_t)g.n1 * tile, nt)) {
-#define CASE(M)                                                                                              \
-  case M:                                                                                                    \
-    set_lds<double, M>((const void*)k_x_density<M>, lds);                                                   \
-    hipLaunchKernelGGL((k_x_density<M>), dim3(ntiles), dim3(nt), lds, st, cm, ncols, g, tile, px, twx, Tb,   \
-                       occ_over_omega, rho, accumulate);                                                     \
+#define CASE(M)                                                                                                 \
+  case M:                                                                                                       \
+    set_lds<double, M>((const void*)k_x_density<M>, lds);                                                      \
+    hipLaunchKernelGGL((k_x_density<M>), dim3(ntiles, ngrp), dim3(nt), lds, st, cm, ncols, cpg, g, tile, px, twx, \
+                       Tb, occ_over_omega, dst, acc_k, Ng);                                                     \
     break;
     CASE(4) CASE(8) CASE(16) CASE(32)
 #undef CASE
   }
   HIPCK(hipGetLastError());
+  if (ngrp > 1) {
+    hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)std::min<int64_t>(2048, (Ng + 255) / 256)), dim3(256), 0, st, Ng,
+                       ngrp, part.as<double>(), Ng, rho, accumulate);
+    HIPCK(hipGetLastError());
+  }
 }
 
 template void launch_inv_yz<double>(hipStream_t, const ColMap&, int, const GridGeom&, const FftPlan&, const FftPlan&,

@@ -86,6 +86,7 @@ struct Workspace {
   DevMem partial;      // reduction partials
   DevMem small;        // small dense scratch
   DevMem gemm_part;    // split-K partials of the Gram kernels
+  DevMem rho_part;     // per-column-group partial densities
   DevMem f[10];        // frame-sized scratch used by the entry points and the solver
 };
 

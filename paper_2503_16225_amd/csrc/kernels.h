@@ -33,6 +33,7 @@ struct GridGeom {
   int n1, n2, n3;
   int ns;              // active x-planes
   const int* plane_i1; // device: i1 of each active plane
+  int ps;              // element stride between (y, z) planes of the slab buffer: n2 n3 rounded up to 16
 };
 
 // ---- local-potential apply and density (hamiltonian.hip) -----------------
@@ -47,8 +48,10 @@ void launch_fwd_yz(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& 
                    const FftPlan& py, const cplx<T>* twz, const cplx<T>* twy, const cplx<T>* Tb, const cplx<T>* X,
                    cplx<T>* HX);
 // rho(r) (+)= sum_c wgt(c) |psi_c(r)|^2, wgt(c) = w_k occ / Omega (FP64 only)
+// (columns are split into groups that write partial densities to part, then summed in order)
 void launch_x_density(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const FftPlan& px,
-                      const z64* twx, const z64* Tb, double occ_over_omega, double* rho, int accumulate);
+                      const z64* twx, const z64* Tb, double occ_over_omega, double* rho, int accumulate,
+                      DevMem& part);
 
 // ---- potentials on the full box (hamiltonian.hip) ---------------------------
 void launch_box_fft(hipStream_t st, int n1, int n2, int n3, const FftPlan p[3], const z64* const tw[3],
@@ -108,6 +111,10 @@ void lyap_divide(hipStream_t st, int p, const double* d, z64* X, int64_t ldx, in
 // M = V f(d) V^H with f(d) = d^e (e in {0.5, -0.5, -1}); batch over k
 void spectral_fn(hipStream_t st, int p, const z64* V, int64_t ldv, int64_t sV, const double* d, int64_t sd,
                  double e, z64* M, int64_t ldm, int64_t sM, int batch);
+// First-order inverse square root in a fixed eigenbasis (p x p blocks, ld p,
+// batch over k): d = 1 + tau^2 w, Mt = diag(d^-1/2) - Dt o K (see dense.hip).
+void polar_first_order(hipStream_t st, int p, const double* w, double tau, const z64* Dt, double* d, z64* Mt,
+                       int batch);
 void hermitize(hipStream_t st, int p, z64* M, int64_t ldm, int64_t sM, int batch);
 // y = a + b x elementwise (n doubles)
 void affine(hipStream_t st, int n, const double* x, double a, double b, double* y);

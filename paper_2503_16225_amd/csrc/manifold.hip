@@ -55,6 +55,73 @@ void retract(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* 
   if (!(dmin > 0.0)) fail(EAHP_ENOTPD, "retraction Gram matrix not positive definite");
 }
 
+void line_prepare(eahp_problem* pb, const z64* Phi, const z64* eta, LineFactors& L) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p, nk = pb->nk;
+  const int64_t pp = (int64_t)p * p;
+  for (DevMem* m : {&L.E0, &L.A1, &L.V, &L.Dt, &L.T}) m->ensure(sizeof(z64) * nk * pp);
+  L.w.ensure(sizeof(double) * nk * p);
+  Scratch& s = scratch();
+  s.b.ensure(sizeof(z64) * nk * pp);
+  for (int ik = 0; ik < nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    gemm_hn<double>(st, K.npw, p, p, Phi + o, K.npw, Phi + o, K.npw, L.E0.as<z64>() + ik * pp, p, 1.0, 0.0,
+                    pb->ws.gemm_part);
+    gemm_hn<double>(st, K.npw, p, p, Phi + o, K.npw, eta + o, K.npw, L.A1.as<z64>() + ik * pp, p, 1.0, 0.0,
+                    pb->ws.gemm_part);
+    gemm_hn<double>(st, K.npw, p, p, eta + o, K.npw, eta + o, K.npw, s.b.as<z64>() + ik * pp, p, 1.0, 0.0,
+                    pb->ws.gemm_part);
+  }
+  hermitize(st, p, L.E0.as<z64>(), p, pp, nk);
+  add_diag(st, p, L.E0.as<z64>(), p, pp, -1.0, nk);
+  hermitize(st, p, L.A1.as<z64>(), p, pp, nk);  // (X + X^H) / 2 with X = Phi^H eta
+  heev(st, p, s.b.as<z64>(), p, pp, L.w.as<double>(), p, L.V.as<z64>(), p, pp, nk, pb->d_info.as<int>());
+}
+
+bool retract_line(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, LineFactors& L, z64* out,
+                  RetractFactors& F) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p, nk = pb->nk;
+  const int64_t pp = (int64_t)p * p;
+  const int64_t N = pb->ntot * p;
+  z64* Dt = L.Dt.as<z64>();
+  z64* T = L.T.as<z64>();
+  const z64* V = L.V.as<z64>();
+  // Delta = E0 + 2 tau A1h
+  axpby<double>(st, nk * pp, 2.0 * tau, L.A1.as<z64>(), 0.0, Dt);
+  axpby<double>(st, nk * pp, 1.0, L.E0.as<z64>(), 1.0, Dt);
+  dot_re(st, nk * pp, Dt, Dt, scal(pb, S_NRM2), pb->ws.partial);
+  fetch_scalars(pb, S_NRM2 + 1);
+  const double nd2 = pb->h_scal[S_NRM2];
+  if (!std::isfinite(nd2)) fail(EAHP_ENONFINITE, "non-finite Gram matrix in the retraction");
+  // second-order remainder below 1e-16 (d >= 1 bounds every divided difference)
+  if (nd2 > 1e-16) return false;
+  F.d.ensure(sizeof(double) * nk * p);
+  F.V.ensure(sizeof(z64) * nk * pp);
+  F.Sinv.ensure(sizeof(z64) * nk * pp);
+  // Dt <- V^H Delta V
+  gemm_hn<double>(st, p, p, p, V, p, Dt, p, T, p, 1.0, 0.0, pb->ws.gemm_part, nk, pp, pp, pp);
+  gemm_nn<double>(st, p, p, p, T, p, V, p, 0, Dt, p, 1.0, 0.0, 0.0, nk, pp, pp, pp);
+  polar_first_order(st, p, L.w.as<double>(), tau, Dt, F.d.as<double>(), T, nk);
+  // Sinv = V Mt V^H
+  gemm_nn<double>(st, p, p, p, V, p, T, p, 0, Dt, p, 1.0, 0.0, 0.0, nk, pp, pp, pp);
+  gemm_nn<double>(st, p, p, p, Dt, p, V, p, 1, F.Sinv.as<z64>(), p, 1.0, 0.0, 0.0, nk, pp, pp, pp);
+  hermitize(st, p, F.Sinv.as<z64>(), p, pp, nk);
+  HIPCK(hipMemcpyAsync(F.V.p, V, sizeof(z64) * nk * pp, hipMemcpyDeviceToDevice, st));
+  Scratch& s = scratch();
+  s.a.ensure(sizeof(z64) * N);
+  z64* Psi = s.a.as<z64>();
+  axpby<double>(st, N, 1.0, Phi, 0.0, Psi);
+  axpby<double>(st, N, tau, eta, 1.0, Psi);
+  for (int ik = 0; ik < nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    gemm_nn<double>(st, K.npw, p, p, Psi + o, K.npw, F.Sinv.as<z64>() + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0, 0.0);
+  }
+  return true;
+}
+
 void lambda_eig(eahp_problem* pb, const z64* Lam, LamEig& E) {
   hipStream_t st = pb->ctx->stream;
   const int p = pb->p, nk = pb->nk;

@@ -39,6 +39,19 @@ struct RetractFactors {
   DevMem d, V, Sinv;
 };
 void retract(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* out, RetractFactors& F);
+// Retraction along a fixed direction eta at Phi: the Gram matrix of Phi + tau eta
+// is S(tau) = (I + tau^2 eta^H eta) + Delta(tau) with the rounding-level
+// Delta = (Phi^H Phi - I) + tau (Phi^H eta + eta^H Phi).  One eigendecomposition
+// of eta^H eta = V diag(w) V^H serves every tau; S^-1/2 is taken to first
+// order in Delta, which is exact to rounding while ||Delta|| stays tiny.
+struct LineFactors {
+  DevMem E0, A1, w, V, Dt, T;
+};
+void line_prepare(eahp_problem* pb, const z64* Phi, const z64* eta, LineFactors& L);
+// pf(Phi + tau eta) from the line factors; false (nothing written) when Delta
+// is too large for the first-order form, in which case retract() applies.
+bool retract_line(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, LineFactors& L, z64* out,
+                  RetractFactors& F);
 // Eigendecomposition of Lambda per k (w ascending order not guaranteed).
 struct LamEig {
   DevMem w, U;

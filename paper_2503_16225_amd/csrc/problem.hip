@@ -289,13 +289,17 @@ void build_problem(eahp_problem* pb, const eahp_system_desc* d) {
 }
 
 // -------------------------------------------------------------------- helpers
-GridGeom geom(const eahp_problem* pb) { return GridGeom{pb->n[0], pb->n[1], pb->n[2], pb->ns, pb->d_plane_i1.as<int>()}; }
+// slab planes start on 256-byte boundaries (FP64) so every x-line tile is whole cache lines
+int plane_stride(const eahp_problem* pb) { return ((pb->n[1] * pb->n[2] + 15) / 16) * 16; }
+GridGeom geom(const eahp_problem* pb) {
+  return GridGeom{pb->n[0], pb->n[1], pb->n[2], pb->ns, pb->d_plane_i1.as<int>(), plane_stride(pb)};
+}
 
 ColMap frame_map(const eahp_problem* pb) { return ColMap{pb->d_kdesc.as<KDesc>(), 0, pb->p, 1}; }
 ColMap block_map(const eahp_problem* pb, int k, int ncols) { return ColMap{pb->d_kdesc.as<KDesc>(), k, ncols, 0}; }
 
 template <typename T> void* planes_for(eahp_problem* pb, int ncols) {
-  const size_t b = sizeof(cplx<T>) * (size_t)ncols * pb->ns * pb->n[1] * pb->n[2];
+  const size_t b = sizeof(cplx<T>) * (size_t)ncols * pb->ns * plane_stride(pb);
   pb->ws.planes.ensure(b);
   return pb->ws.planes.p;
 }
@@ -379,7 +383,7 @@ void density_potentials(eahp_problem* pb, const z64* Psi) {
   prof_end(pb, 0, bytes_inv(pb, ncols, nsum, 16));
   prof_begin(pb, 3);
   launch_x_density(st, frame_map(pb), ncols, g, pb->plan[0], pb->d_tw[0].as<z64>(), Tb, pb->occ / pb->Omega,
-                   pb->d_rho.as<double>(), 0);
+                   pb->d_rho.as<double>(), 0, pb->ws.rho_part);
   prof_end(pb, 3, bytes_dens(pb, ncols));
   potentials(pb);
 }
