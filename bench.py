@@ -8,7 +8,12 @@ p = 128, Gamma), starting from a seeded random frame.  The metric is the
 throughput of orbital H-applies (one orbital at one k-point) inside the
 solve.  Everything is resident in HBM before timing starts.
 
+The headline runs the mixed-precision path (the metric solve in single
+precision, everything else in FP64); the FP64 path is measured beside it
+from the same start ("compare").
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
+                       [--precision mixed|fp64] [--no-compare]
 """
 from __future__ import annotations
 
@@ -23,7 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_NAMES = ["inv_yz", "x_local", "fwd_yz", "x_density"]
+KERNEL_NAMES = ["inv_yz", "x_local", "fwd_yz", "x_density", "inv_yz_f32", "x_local_f32", "fwd_yz_f32"]
 
 
 def cpu_baseline(config, seconds=15.0):
@@ -54,13 +59,68 @@ def cpu_baseline(config, seconds=15.0):
                       f"{reps} repetitions, scipy.fft workers={cores}"}
 
 
+def measure(args, precision):
+    """Warmup + timed outer iterations of one solver at one precision."""
+    import ctypes as C
+
+    import torch
+
+    import workloads as W
+    from paper_2503_16225_amd import binding as B
+    from paper_2503_16225_amd.binding import SolveParams, Stats, _check
+
+    sysd = W.config(args.config)
+    prm = dict(W.DEFAULT_PARAMS, tol=0.0, maxit=10 ** 6)
+    pb = B.Problem(sysd, precision=B.EAHP_MIXED if precision == "mixed" else B.EAHP_FP64)
+    lib = pb.lib
+    Z = W.gaussian_block(1, pb.npw, pb.p)
+    Psi0 = pb.to_device(Z)
+    sp = SolveParams.from_dict(prm)
+    sv = C.c_void_p()
+    print(f"[bench] {args.config} {precision}: npw={pb.npw} fft={pb.fft} p={pb.p}; init", file=sys.stderr, flush=True)
+    _check(lib.eahp_solver_create(pb.pb, C.c_void_p(Psi0.data_ptr()), C.byref(sp), C.byref(sv)))
+    st = Stats()
+    for i in range(args.warmup):
+        lib.eahp_solver_step(sv, 1, C.byref(st))
+        print(f"[bench] {precision} warmup {i + 1}/{args.warmup}: E={st.energy:.10f} |R|={st.rnorm:.3e} "
+              f"napply={st.napply}", file=sys.stderr, flush=True)
+    n0, n32 = st.napply, st.napply_fp32
+    _check(lib.eahp_prof_enable(pb.ctx, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        rc = lib.eahp_solver_step(sv, 1, C.byref(st))
+        if rc not in (0, -8):
+            _check(rc)
+        print(f"[bench] {precision} step {i + 1}/{args.steps}: E={st.energy:.10f} |R|={st.rnorm:.3e} "
+              f"napply={st.napply} (fp32 {st.napply_fp32}) fom_iters={st.fom_iters} trials={st.ls_trials}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {}
+    for kid, name in enumerate(KERNEL_NAMES):
+        ms, nl, by = C.c_double(), C.c_int64(), C.c_double()
+        _check(lib.eahp_prof_read(pb.ctx, kid, C.byref(ms), C.byref(nl), C.byref(by)))
+        if nl.value:
+            kern[name] = (ms.value, nl.value, by.value)
+    _check(lib.eahp_prof_enable(pb.ctx, 0))
+    lib.eahp_solver_destroy(sv)
+    pb.close()
+    elapsed = t1 - t0
+    return {"napply": st.napply - n0, "napply_fp32": st.napply_fp32 - n32, "elapsed": elapsed,
+            "value": (st.napply - n0) / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+            "energy": st.energy, "rnorm": st.rnorm, "kernels": kern}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="si64_gamma_e20")
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"],
+                    help="precision of the headline figure; the other one is measured beside it")
+    ap.add_argument("--no-compare", action="store_true", help="skip the run at the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates FETCH_SIZE / WRITE_SIZE counters)")
@@ -69,84 +129,51 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not part of this build",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
-    import workloads as W
-    from paper_2503_16225_amd import Problem
-    from paper_2503_16225_amd.binding import SolveParams, Stats, _check
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    sysd = W.config(args.config)
-    prm = dict(W.DEFAULT_PARAMS, tol=0.0, maxit=10 ** 6)
-    pb = Problem(sysd)
-    lib = pb.lib
-    Z = W.gaussian_block(1, pb.npw, pb.p)
-    Psi0 = pb.to_device(Z)
-    import ctypes as C
-    sp = SolveParams.from_dict(prm)
-    sv = C.c_void_p()
-    print(f"[bench] {args.config}: npw={pb.npw} fft={pb.fft} p={pb.p}; init", file=sys.stderr, flush=True)
-    _check(lib.eahp_solver_create(pb.pb, C.c_void_p(Psi0.data_ptr()), C.byref(sp), C.byref(sv)))
-    st = Stats()
-    for i in range(args.warmup):
-        lib.eahp_solver_step(sv, 1, C.byref(st))
-        print(f"[bench] warmup {i + 1}/{args.warmup}: E={st.energy:.10f} |R|={st.rnorm:.3e} "
-              f"napply={st.napply}", file=sys.stderr, flush=True)
-    n0 = st.napply
-    _check(lib.eahp_prof_enable(pb.ctx, 1))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        rc = lib.eahp_solver_step(sv, 1, C.byref(st))
-        if rc not in (0, -8):
-            _check(rc)
-        print(f"[bench] step {i + 1}/{args.steps}: E={st.energy:.10f} |R|={st.rnorm:.3e} napply={st.napply} "
-              f"fom_iters={st.fom_iters} trials={st.ls_trials}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    napply = st.napply - n0
-    kern = {}
-    for kid, name in enumerate(KERNEL_NAMES):
-        ms, nl, by = C.c_double(), C.c_int64(), C.c_double()
-        _check(lib.eahp_prof_read(pb.ctx, kid, C.byref(ms), C.byref(nl), C.byref(by)))
-        kern[name] = (ms.value, nl.value, by.value)
-    _check(lib.eahp_prof_enable(pb.ctx, 0))
-    dom = max(kern, key=lambda k: kern[k][0])
-    ms, nl, by = kern[dom]
-    achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    lib.eahp_solver_destroy(sv)
-    pb.close()
+    head = measure(args, args.precision)
+    other = None
+    if not args.no_compare:
+        other = measure(args, "fp64" if args.precision == "mixed" else "mixed")
     if args.copy_probe:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         print("[bench] copy probe: 536870912 bytes read, 536870912 bytes written", file=sys.stderr, flush=True)
-    elapsed = t1 - t0
-    value = napply / elapsed
+    kern = head["kernels"]
+    dom = max(kern, key=lambda k: kern[k][0])
+    ms, nl, by = kern[dom]
+    achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     out = {
         "metric": "orbital H-applies/s",
-        "value": value,
+        "value": head["value"],
         "unit": "orbital H-applies/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32 metric solve, f64 outer iteration",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: 2x2x2 diamond supercell, 64 atoms, p=128, Ecut 20 Ha, 90^3 box, "
-                               f"Gamma, seeded random start, FP64 EARCG outer iterations",
-                   "precision": args.precision},
+                               f"Gamma, seeded random start, EARCG outer iterations",
+                   "precision": args.precision,
+                   "napply": head["napply"], "napply_fp32": head["napply_fp32"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": dom,
                      "avg_launch_ms": ms / max(nl, 1), "launches": nl},
         "kernels": {k: {"total_ms": v[0], "launches": v[1], "GB/s": (v[2] / (v[0] * 1e-3) / 1e9) if v[0] else 0.0}
                     for k, v in kern.items()},
     }
+    if other is not None:
+        out["compare"] = {"precision": "fp64" if args.precision == "mixed" else "mixed", "value": other["value"],
+                          "ms_per_step": other["ms_per_step"], "napply": other["napply"],
+                          "napply_fp32": other["napply_fp32"], "energy_after": other["energy"],
+                          "energy_after_headline": head["energy"]}
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(args.config)

@@ -190,7 +190,8 @@ void eahp_solver_destroy(eahp_solver* sv);
 /* Per-kernel timing with HIP events recorded on the context stream around
  * every launch of the H-apply kernels: 0 = inverse y/z plane transforms,
  * 1 = x-line transforms with the V_eff product, 2 = forward y/z transforms
- * with the gather and kinetic term, 3 = density x-line transforms.
+ * with the gather and kinetic term, 3 = density x-line transforms; 4, 5, 6 =
+ * the single-precision launches of 0, 1, 2 (metric solve of EAHP_MIXED).
  * enable(1) starts recording (and resets), read returns and resets the
  * summed duration, the launch count and the algorithmic bytes (compulsory
  * loads and stores of each launch) since the last read. */

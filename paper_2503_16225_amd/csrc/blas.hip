@@ -244,12 +244,13 @@ template void axpby<float>(hipStream_t, int64_t, double, const c32*, double, c32
 
 constexpr int kRedBlocks = 1024;
 
-__global__ void __launch_bounds__(256) k_dot_re(int64_t n, const z64* x, const z64* y, double* part) {
+template <typename C>
+__global__ void __launch_bounds__(256) k_dot_re(int64_t n, const C* x, const C* y, double* part) {
   __shared__ double sh[16];
   double s = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const z64 a = x[i], b = y[i];
-    s += a.x * b.x + a.y * b.y;
+    const C a = x[i], b = y[i];
+    s += (double)a.x * (double)b.x + (double)a.y * (double)b.y;
   }
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -261,12 +262,19 @@ __global__ void __launch_bounds__(256) k_sum_partials(int m, const double* part,
   s = block_sum(s, sh);
   if (threadIdx.x == 0) *out = s;
 }
-void dot_re(hipStream_t st, int64_t n, const z64* x, const z64* y, double* out_dev, DevMem& part) {
+template <typename C>
+static void dot_re_impl(hipStream_t st, int64_t n, const C* x, const C* y, double* out_dev, DevMem& part) {
   part.ensure(sizeof(double) * kRedBlocks);
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (n + 255) / 256));
-  hipLaunchKernelGGL(k_dot_re, dim3(nb), dim3(256), 0, st, n, x, y, part.as<double>());
+  hipLaunchKernelGGL((k_dot_re<C>), dim3(nb), dim3(256), 0, st, n, x, y, part.as<double>());
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, nb, part.as<double>(), out_dev);
   HIPCK(hipGetLastError());
+}
+void dot_re(hipStream_t st, int64_t n, const z64* x, const z64* y, double* out_dev, DevMem& part) {
+  dot_re_impl(st, n, x, y, out_dev, part);
+}
+void dot_re(hipStream_t st, int64_t n, const c32* x, const c32* y, double* out_dev, DevMem& part) {
+  dot_re_impl(st, n, x, y, out_dev, part);
 }
 
 // out[j] = sum_i w_i |X_ij|^2 (w == nullptr: w_i = 1); one work-group per column
@@ -309,6 +317,45 @@ void convert(hipStream_t st, int64_t n, const void* src, int src_fp64, void* dst
   HIPCK(hipGetLastError());
 }
 template void convert<double>(hipStream_t, int64_t, const void*, int, void*, int);
+
+// D[rows x cols, ldd] = S[rows x cols, lds] with a change of precision
+template <typename S, typename D>
+__global__ void k_convert2d(int rows, int cols, const S* src, int64_t lds, D* dst, int64_t ldd) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)rows * cols;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % rows), j = (int)(e / rows);
+    const S v = src[i + j * lds];
+    dst[i + j * ldd].x = v.x;
+    dst[i + j * ldd].y = v.y;
+  }
+}
+void convert2d(hipStream_t st, int rows, int cols, const c32* src, int64_t lds, z64* dst, int64_t ldd) {
+  if ((int64_t)rows * cols <= 0) return;
+  const int nb = (int)std::min<int64_t>(4096, ((int64_t)rows * cols + 255) / 256);
+  hipLaunchKernelGGL((k_convert2d<c32, z64>), dim3(nb), dim3(256), 0, st, rows, cols, src, lds, dst, ldd);
+  HIPCK(hipGetLastError());
+}
+void convert2d(hipStream_t st, int rows, int cols, const z64* src, int64_t lds, c32* dst, int64_t ldd) {
+  if ((int64_t)rows * cols <= 0) return;
+  const int nb = (int)std::min<int64_t>(4096, ((int64_t)rows * cols + 255) / 256);
+  hipLaunchKernelGGL((k_convert2d<z64, c32>), dim3(nb), dim3(256), 0, st, rows, cols, src, lds, dst, ldd);
+  HIPCK(hipGetLastError());
+}
+
+// y += a x with x single precision and y double (n complex values)
+__global__ void k_axpy_mixed(int64_t n, double a, const c32* x, z64* y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const c32 v = x[i];
+    y[i].x += a * (double)v.x;
+    y[i].y += a * (double)v.y;
+  }
+}
+void axpy_mixed(hipStream_t st, int64_t n, double a, const c32* x, z64* y) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  hipLaunchKernelGGL(k_axpy_mixed, dim3(nb), dim3(256), 0, st, n, a, x, y);
+  HIPCK(hipGetLastError());
+}
 
 template <typename T>
 __global__ void k_tpa(int64_t n, int ncols, const double* kin, const double* alpha, const cplx<T>* X, int64_t ldx,

@@ -93,7 +93,7 @@ struct Workspace {
 }  // namespace eahp
 
 // Optional per-kernel timing with HIP events on the context stream.
-constexpr int kProfKernels = 4;  // 0 inv_yz, 1 x_local, 2 fwd_yz, 3 x_density
+constexpr int kProfKernels = 8;  // 0 inv_yz, 1 x_local, 2 fwd_yz, 3 x_density; 4..6 the same in FP32
 struct ProfSlot {
   std::vector<hipEvent_t> start, stop;
   int used = 0;

@@ -79,6 +79,12 @@ template <typename T>
 void axpby(hipStream_t st, int64_t n, double a, const cplx<T>* x, double b, cplx<T>* y);
 // out = Re sum conj(x) y over n, deterministic (partials in part)
 void dot_re(hipStream_t st, int64_t n, const z64* x, const z64* y, double* out_dev, DevMem& part);
+void dot_re(hipStream_t st, int64_t n, const c32* x, const c32* y, double* out_dev, DevMem& part);  // FP64 sums
+// 2-D copies between precisions (column-major, leading dimensions lds / ldd)
+void convert2d(hipStream_t st, int rows, int cols, const c32* src, int64_t lds, z64* dst, int64_t ldd);
+void convert2d(hipStream_t st, int rows, int cols, const z64* src, int64_t lds, c32* dst, int64_t ldd);
+// y += a x, x single and y double precision
+void axpy_mixed(hipStream_t st, int64_t n, double a, const c32* x, z64* y);
 // out[j] = sum_g w[g] |x[g, j]|^2 (column reductions), or with w == null plain norms
 void col_weighted_norm2(hipStream_t st, int64_t n, int ncols, const z64* X, int64_t ldx, const double* w,
                         double* out);

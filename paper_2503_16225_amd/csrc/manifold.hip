@@ -223,60 +223,92 @@ void ea_gradient(eahp_problem* pb, const z64* Phi, const z64* X, z64* G) {
 }
 
 // ---------------------------------------------------------------- block FOM
+// Templated on the precision T of everything of length n (Krylov basis V,
+// W = H V, residual blocks, the H-applies, TPA and the Gram products); the
+// q x q projected problem and its solution Y are kept in FP64 (A, Cj, Y).
 namespace {
 
+template <typename T>
 struct FomWork {
-  DevMem V, W, A, Cj, C, E, Rj, Ah, QA, wA, T1, T2, Y, YS, Sig, U, s, alpha, Gm, PU, tmp, piv, tri;
+  DevMem V, W, A, Cj, C, E, Rj, Ah, T1, T2, Y, YS, YT, YST, Sig, U, s, alpha, Gm, Gm64, PU, PU64, tmp, piv, tri, stage,
+      Xt;
   int64_t n = 0;
   int qcap = 0;
 };
-FomWork& fomwork() {
-  static FomWork w;
+template <typename T>
+FomWork<T>& fomwork() {
+  static FomWork<T> w;
   return w;
 }
 
+constexpr bool is_fp64(double) { return true; }
+constexpr bool is_fp64(float) { return false; }
+
+// C (a x b, ldc, FP64) = alpha A^H B over n rows of precision T
+template <typename T>
+void gram_into64(eahp_problem* pb, FomWork<T>& w, int64_t n, int a, int b, const cplx<T>* A, const cplx<T>* B, z64* C,
+                 int64_t ldc) {
+  hipStream_t st = pb->ctx->stream;
+  if constexpr (sizeof(T) == 8) {
+    gemm_hn<double>(st, n, a, b, A, n, B, n, C, ldc, 1.0, 0.0, pb->ws.gemm_part);
+  } else {
+    w.stage.ensure(sizeof(cplx<T>) * (size_t)a * b);
+    gemm_hn<T>(st, n, a, b, A, n, B, n, w.stage.template as<cplx<T>>(), a, 1.0, 0.0, pb->ws.gemm_part);
+    convert2d(st, a, b, w.stage.template as<cplx<T>>(), a, C, ldc);
+  }
+}
+
 // Orthonormal basis of span(R) (n x c, ld n) by pivoted CholQR twice; written to
-// dest (ld n).  Returns the rank.
-int rrqr(eahp_problem* pb, int64_t n, int c, const z64* R, z64* dest, double tol, FomWork& w) {
+// dest (ld n).  Returns the rank.  The pivoted Cholesky runs in FP64 on the
+// Gram matrix of precision T.
+template <typename T>
+int rrqr(eahp_problem* pb, int64_t n, int c, const cplx<T>* R, cplx<T>* dest, double tol, FomWork<T>& w) {
   hipStream_t st = pb->ctx->stream;
   if (c <= 0) return 0;
-  w.Gm.ensure(sizeof(z64) * c * c);
-  w.PU.ensure(sizeof(z64) * c * c);
-  w.tmp.ensure(sizeof(z64) * n * c);
+  w.Gm64.ensure(sizeof(z64) * c * c);
+  w.PU64.ensure(sizeof(z64) * c * c);
+  w.PU.ensure(sizeof(cplx<T>) * c * c);
+  w.tmp.ensure(sizeof(cplx<T>) * n * c);
   w.piv.ensure(sizeof(int) * c);
-  int* piv = w.piv.as<int>();
+  int* piv = w.piv.template as<int>();
   int* rank = pb->d_info.as<int>();
-  gemm_hn<double>(st, n, c, c, R, n, R, n, w.Gm.as<z64>(), c, 1.0, 0.0, pb->ws.gemm_part);
-  pchol_inv(st, c, w.Gm.as<z64>(), c, tol, piv, rank, w.PU.as<z64>(), c, nullptr);
-  HIPCK(hipMemcpyAsync(pb->h_info, pb->d_info.p, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
-  const int r = pb->h_info[0];
+  cplx<T>* tmp = w.tmp.template as<cplx<T>>();
+  auto factor = [&](const cplx<T>* X, int cols, double tl) {
+    gram_into64<T>(pb, w, n, cols, cols, X, X, w.Gm64.template as<z64>(), cols);
+    pchol_inv(st, cols, w.Gm64.template as<z64>(), cols, tl, piv, rank, w.PU64.template as<z64>(), cols, nullptr);
+    HIPCK(hipMemcpyAsync(pb->h_info, pb->d_info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    const int r = pb->h_info[0];
+    if constexpr (sizeof(T) == 4) convert2d(st, cols, std::max(r, 0), w.PU64.template as<z64>(), cols, w.PU.template as<c32>(), cols);
+    return r;
+  };
+  auto pu = [&]() -> const cplx<T>* {
+    if constexpr (sizeof(T) == 8) return w.PU64.template as<z64>();
+    else return w.PU.template as<c32>();
+  };
+  const int r = factor(R, c, tol);
   if (r <= 0) return 0;
-  gemm_nn<double>(st, n, c, r, R, n, w.PU.as<z64>(), c, 0, w.tmp.as<z64>(), n, 1.0, 0.0, 0.0);
+  gemm_nn<T>(st, n, c, r, R, n, pu(), c, 0, tmp, n, 1.0, 0.0, 0.0);
   // second pass
-  gemm_hn<double>(st, n, r, r, w.tmp.as<z64>(), n, w.tmp.as<z64>(), n, w.Gm.as<z64>(), r, 1.0, 0.0,
-                  pb->ws.gemm_part);
-  pchol_inv(st, r, w.Gm.as<z64>(), r, 0.0, piv, rank, w.PU.as<z64>(), r, nullptr);
-  HIPCK(hipMemcpyAsync(pb->h_info, pb->d_info.p, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
-  const int r2 = pb->h_info[0];
-  gemm_nn<double>(st, n, r, r2, w.tmp.as<z64>(), n, w.PU.as<z64>(), r, 0, dest, n, 1.0, 0.0, 0.0);
+  const int r2 = factor(tmp, r, 0.0);
+  gemm_nn<T>(st, n, r, r2, tmp, n, pu(), r, 0, dest, n, 1.0, 0.0, 0.0);
   return r2;
 }
 
-void grow(FomWork& w, int64_t n, int need, int p) {
+template <typename T>
+void grow(FomWork<T>& w, int64_t n, int need, int p) {
   if (need <= w.qcap && n == w.n) return;
   const int old = (n == w.n) ? w.qcap : 0;
   const int cap = std::max(need, old + 4 * p);
   DevMem V2, W2, A2, C2;
-  V2.alloc(sizeof(z64) * n * cap);
-  W2.alloc(sizeof(z64) * n * cap);
+  V2.alloc(sizeof(cplx<T>) * n * cap);
+  W2.alloc(sizeof(cplx<T>) * n * cap);
   A2.alloc(sizeof(z64) * (size_t)cap * cap);
   C2.alloc(sizeof(z64) * (size_t)cap * p);
   if (old > 0) {
     HIPCK(hipDeviceSynchronize());
-    HIPCK(hipMemcpy(V2.p, w.V.p, sizeof(z64) * n * old, hipMemcpyDeviceToDevice));
-    HIPCK(hipMemcpy(W2.p, w.W.p, sizeof(z64) * n * old, hipMemcpyDeviceToDevice));
+    HIPCK(hipMemcpy(V2.p, w.V.p, sizeof(cplx<T>) * n * old, hipMemcpyDeviceToDevice));
+    HIPCK(hipMemcpy(W2.p, w.W.p, sizeof(cplx<T>) * n * old, hipMemcpyDeviceToDevice));
     HIPCK(hipMemcpy2D(A2.p, sizeof(z64) * cap, w.A.p, sizeof(z64) * old, sizeof(z64) * old, old, hipMemcpyDeviceToDevice));
     HIPCK(hipMemcpy2D(C2.p, sizeof(z64) * cap, w.Cj.p, sizeof(z64) * old, sizeof(z64) * old, p, hipMemcpyDeviceToDevice));
   }
@@ -292,111 +324,137 @@ void grow(FomWork& w, int64_t n, int need, int p) {
   w.n = n;
 }
 
-double norm2(eahp_problem* pb, int64_t len, const z64* x) {
+template <typename T>
+double norm2(eahp_problem* pb, int64_t len, const cplx<T>* x) {
   dot_re(pb->ctx->stream, len, x, x, scal(pb, S_NRM), pb->ws.partial);
   fetch_scalars(pb, S_NRM + 1);
   return pb->h_scal[S_NRM];
 }
 
+template <typename T>
 FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64* Lam, double mu, double rtol,
               int maxit, double rank_tol, z64* X, const double* lw, const z64* lU) {
   hipStream_t st = pb->ctx->stream;
-  FomWork& w = fomwork();
+  FomWork<T>& w = fomwork<T>();
   const int p = pb->p;
   auto& K = pb->kp[ik];
   const int64_t n = K.npw;
   const int64_t np_ = n * p;
   grow(w, n, 2 * p, p);
-  w.C.ensure(sizeof(z64) * np_);
-  w.E.ensure(sizeof(z64) * np_);
-  w.Rj.ensure(sizeof(z64) * np_);
+  w.C.ensure(sizeof(cplx<T>) * np_);
+  w.E.ensure(sizeof(cplx<T>) * np_);
+  w.Rj.ensure(sizeof(cplx<T>) * np_);
   w.Sig.ensure(sizeof(z64) * p * p);
   w.U.ensure(sizeof(z64) * p * p);
   w.s.ensure(sizeof(double) * p);
   w.alpha.ensure(sizeof(double) * p);
-  z64* C = w.C.as<z64>();
-  z64* E = w.E.as<z64>();
-  z64* Rj = w.Rj.as<z64>();
+  cplx<T>* C = w.C.template as<cplx<T>>();
+  cplx<T>* E = w.E.template as<cplx<T>>();
+  cplx<T>* Rj = w.Rj.template as<cplx<T>>();
+  auto Vp = [&]() { return w.V.template as<cplx<T>>(); };
+  auto Wp = [&]() { return w.W.template as<cplx<T>>(); };
   // C = Phi - (H X0 - X0 Sigma) with X0 = Phi / mu equals -R / mu
-  axpby<double>(st, np_, -1.0 / mu, R, 0.0, C);
-  const double nC2 = norm2(pb, np_, C);
+  if constexpr (sizeof(T) == 8) {
+    axpby<double>(st, np_, -1.0 / mu, R, 0.0, C);
+  } else {
+    convert<double>(st, np_, R, 1, C, 0);
+    axpby<float>(st, np_, -1.0 / mu, C, 0.0, C);
+  }
+  const double nC2 = norm2<T>(pb, np_, C);
   // Sigma = Lambda - mu I and its eigendecomposition
-  copy2d(st, p, p, Lam, p, w.Sig.as<z64>(), p);
-  add_diag(st, p, w.Sig.as<z64>(), p, 0, -mu, 1);
+  copy2d(st, p, p, Lam, p, w.Sig.template as<z64>(), p);
+  add_diag(st, p, w.Sig.template as<z64>(), p, 0, -mu, 1);
   w.T1.ensure(sizeof(z64) * p * p);
   if (lw) {
     // Sigma = Lambda - mu I shares the eigenvectors of Lambda: s = w - mu
-    affine(st, p, lw, -mu, 1.0, w.s.as<double>());
-    copy2d(st, p, p, lU, p, w.U.as<z64>(), p);
+    affine(st, p, lw, -mu, 1.0, w.s.template as<double>());
+    copy2d(st, p, p, lU, p, w.U.template as<z64>(), p);
   } else {
-    copy2d(st, p, p, w.Sig.as<z64>(), p, w.T1.as<z64>(), p);
-    heev(st, p, w.T1.as<z64>(), p, 0, w.s.as<double>(), 0, w.U.as<z64>(), p, 0, 1, pb->d_info.as<int>());
+    copy2d(st, p, p, w.Sig.template as<z64>(), p, w.T1.template as<z64>(), p);
+    heev(st, p, w.T1.template as<z64>(), p, 0, w.s.template as<double>(), 0, w.U.template as<z64>(), p, 0, 1, pb->d_info.as<int>());
   }
   // TPA: alpha_j = sum_G |k+G|^2/2 |phi_jG|^2
-  col_weighted_norm2(st, n, p, Phi, n, K.d_kin.as<double>(), w.alpha.as<double>());
+  col_weighted_norm2(st, n, p, Phi, n, K.d_kin.as<double>(), w.alpha.template as<double>());
   // V_1 = rrqr(P^-1 C), W_1 = H V_1
-  tpa_apply<double>(st, n, p, K.d_kin.as<double>(), w.alpha.as<double>(), C, n, Rj, n);
-  int q = rrqr(pb, n, p, Rj, w.V.as<z64>(), rank_tol, w);
+  tpa_apply<T>(st, n, p, K.d_kin.as<double>(), w.alpha.template as<double>(), C, n, Rj, n);
+  int q = rrqr<T>(pb, n, p, Rj, Vp(), rank_tol, w);
   FomInfo info;
   if (q == 0) {
     axpby<double>(st, np_, 1.0 / mu, Phi, 0.0, X);
     info.relres = nC2 > 0 ? 1.0 : 0.0;
     return info;
   }
-  apply_H_block<double>(pb, ik, q, w.V.as<z64>(), w.W.as<z64>());
+  apply_H_block<T>(pb, ik, q, Vp(), Wp());
   int ldA = w.qcap;
-  gemm_hn<double>(st, n, q, q, w.V.as<z64>(), n, w.W.as<z64>(), n, w.A.as<z64>(), ldA, 1.0, 0.0, pb->ws.gemm_part);
-  gemm_hn<double>(st, n, q, p, w.V.as<z64>(), n, C, n, w.Cj.as<z64>(), ldA, 1.0, 0.0, pb->ws.gemm_part);
+  gram_into64<T>(pb, w, n, q, q, Vp(), Wp(), w.A.template as<z64>(), ldA);
+  gram_into64<T>(pb, w, n, q, p, Vp(), C, w.Cj.template as<z64>(), ldA);
   int it = 0;
   double relres = 1.0;
+  const cplx<T>* Yt = nullptr;  // Y in precision T (q x p, ld q)
   for (;;) {
     ++it;
     ldA = w.qcap;
-    // ---- projected Sylvester A_q Y - Y Sigma = C_q
+    // ---- projected Sylvester A_q Y - Y Sigma = C_q (FP64)
     w.Ah.ensure(sizeof(z64) * q * q);
-    w.QA.ensure(sizeof(z64) * q * q);
-    w.wA.ensure(sizeof(double) * q);
-    w.T1.ensure(sizeof(z64) * q * p);
+    w.T1.ensure(sizeof(cplx<T>) * q * p);
     w.T2.ensure(sizeof(z64) * q * p);
     w.Y.ensure(sizeof(z64) * q * p);
     w.YS.ensure(sizeof(z64) * q * p);
     // in the eigenbasis of Sigma: (A_q - s_l) y~_l = (C_q U)[:, l], then Y = Y~ U^H
-    copy2d(st, q, q, w.A.as<z64>(), ldA, w.Ah.as<z64>(), q);
-    gemm_nn<double>(st, q, p, p, w.Cj.as<z64>(), ldA, w.U.as<z64>(), p, 0, w.T2.as<z64>(), q, 1.0, 0.0, 0.0);
-    sylvester_tridiag(st, q, p, w.Ah.as<z64>(), q, w.s.as<double>(), w.T2.as<z64>(), w.tri);
-    gemm_nn<double>(st, q, p, p, w.T2.as<z64>(), q, w.U.as<z64>(), p, 1, w.Y.as<z64>(), q, 1.0, 0.0, 0.0);
+    copy2d(st, q, q, w.A.template as<z64>(), ldA, w.Ah.template as<z64>(), q);
+    gemm_nn<double>(st, q, p, p, w.Cj.template as<z64>(), ldA, w.U.template as<z64>(), p, 0, w.T2.template as<z64>(), q, 1.0, 0.0, 0.0);
+    sylvester_tridiag(st, q, p, w.Ah.template as<z64>(), q, w.s.template as<double>(), w.T2.template as<z64>(), w.tri);
+    gemm_nn<double>(st, q, p, p, w.T2.template as<z64>(), q, w.U.template as<z64>(), p, 1, w.Y.template as<z64>(), q, 1.0, 0.0, 0.0);
+    gemm_nn<double>(st, q, p, p, w.Y.template as<z64>(), q, w.Sig.template as<z64>(), p, 0, w.YS.template as<z64>(), q, 1.0, 0.0, 0.0);
+    const cplx<T>* Ys;
+    if constexpr (sizeof(T) == 8) {
+      Yt = w.Y.template as<z64>();
+      Ys = w.YS.template as<z64>();
+    } else {
+      w.YT.ensure(sizeof(c32) * q * p);
+      w.YST.ensure(sizeof(c32) * q * p);
+      convert<double>(st, (int64_t)q * p, w.Y.template as<z64>(), 1, w.YT.p, 0);
+      convert<double>(st, (int64_t)q * p, w.YS.template as<z64>(), 1, w.YST.p, 0);
+      Yt = w.YT.template as<c32>();
+      Ys = w.YST.template as<c32>();
+    }
     // ---- E = C - (W Y - V Y Sigma)
-    axpby<double>(st, np_, 1.0, C, 0.0, E);
-    gemm_nn<double>(st, n, q, p, w.W.as<z64>(), n, w.Y.as<z64>(), q, 0, E, n, -1.0, 0.0, 1.0);
-    gemm_nn<double>(st, q, p, p, w.Y.as<z64>(), q, w.Sig.as<z64>(), p, 0, w.YS.as<z64>(), q, 1.0, 0.0, 0.0);
-    gemm_nn<double>(st, n, q, p, w.V.as<z64>(), n, w.YS.as<z64>(), q, 0, E, n, 1.0, 0.0, 1.0);
-    const double nE2 = norm2(pb, np_, E);
+    axpby<T>(st, np_, 1.0, C, 0.0, E);
+    gemm_nn<T>(st, n, q, p, Wp(), n, Yt, q, 0, E, n, -1.0, 0.0, 1.0);
+    gemm_nn<T>(st, n, q, p, Vp(), n, Ys, q, 0, E, n, 1.0, 0.0, 1.0);
+    const double nE2 = norm2<T>(pb, np_, E);
     relres = nC2 > 0 ? std::sqrt(nE2 / nC2) : 0.0;
     if (!std::isfinite(relres)) fail(EAHP_ENONFINITE, "non-finite residual in the metric solve");
     if (relres <= rtol || it >= maxit) break;
     // ---- R_j = (I - V V^H) P^-1 E_j, projected twice
-    tpa_apply<double>(st, n, p, K.d_kin.as<double>(), w.alpha.as<double>(), E, n, Rj, n);
+    tpa_apply<T>(st, n, p, K.d_kin.as<double>(), w.alpha.template as<double>(), E, n, Rj, n);
     for (int pass = 0; pass < 2; ++pass) {
-      gemm_hn<double>(st, n, q, p, w.V.as<z64>(), n, Rj, n, w.T1.as<z64>(), q, 1.0, 0.0, pb->ws.gemm_part);
-      gemm_nn<double>(st, n, q, p, w.V.as<z64>(), n, w.T1.as<z64>(), q, 0, Rj, n, -1.0, 0.0, 1.0);
+      gemm_hn<T>(st, n, q, p, Vp(), n, Rj, n, w.T1.template as<cplx<T>>(), q, 1.0, 0.0, pb->ws.gemm_part);
+      gemm_nn<T>(st, n, q, p, Vp(), n, w.T1.template as<cplx<T>>(), q, 0, Rj, n, -1.0, 0.0, 1.0);
     }
     grow(w, n, q + p, p);
     ldA = w.qcap;
-    z64* Vn = w.V.as<z64>() + (int64_t)q * n;
-    const int r = rrqr(pb, n, p, Rj, Vn, rank_tol, w);
+    cplx<T>* Vn = Vp() + (int64_t)q * n;
+    const int r = rrqr<T>(pb, n, p, Rj, Vn, rank_tol, w);
     if (r == 0) break;
-    z64* Wn = w.W.as<z64>() + (int64_t)q * n;
-    apply_H_block<double>(pb, ik, r, Vn, Wn);
+    cplx<T>* Wn = Wp() + (int64_t)q * n;
+    apply_H_block<T>(pb, ik, r, Vn, Wn);
     // border A with V^H W_new (rows 0..q+r) and mirror; C_{j+1} = [C_j ; V_new^H C]
-    gemm_hn<double>(st, n, q + r, r, w.V.as<z64>(), n, Wn, n, w.A.as<z64>() + (int64_t)q * ldA, ldA, 1.0, 0.0,
-                    pb->ws.gemm_part);
-    border_mirror(st, q, r, w.A.as<z64>(), ldA);
-    gemm_hn<double>(st, n, r, p, Vn, n, C, n, w.Cj.as<z64>() + q, ldA, 1.0, 0.0, pb->ws.gemm_part);
+    gram_into64<T>(pb, w, n, q + r, r, Vp(), Wn, w.A.template as<z64>() + (int64_t)q * ldA, ldA);
+    border_mirror(st, q, r, w.A.template as<z64>(), ldA);
+    gram_into64<T>(pb, w, n, r, p, Vn, C, w.Cj.template as<z64>() + q, ldA);
     q += r;
+    Yt = nullptr;
   }
-  // X = X0 + V Y
+  // X = X0 + V Y (Y is that of the last projected solve, of size q x p)
   axpby<double>(st, np_, 1.0 / mu, Phi, 0.0, X);
-  gemm_nn<double>(st, n, q, p, w.V.as<z64>(), n, w.Y.as<z64>(), q, 0, X, n, 1.0, 0.0, 1.0);
+  if constexpr (sizeof(T) == 8) {
+    gemm_nn<double>(st, n, q, p, Vp(), n, w.Y.template as<z64>(), q, 0, X, n, 1.0, 0.0, 1.0);
+  } else {
+    w.Xt.ensure(sizeof(c32) * np_);
+    gemm_nn<float>(st, n, q, p, Vp(), n, w.YT.template as<c32>(), q, 0, w.Xt.template as<c32>(), n, 1.0, 0.0, 0.0);
+    axpy_mixed(st, np_, 1.0, w.Xt.template as<c32>(), X);
+  }
   info.iters = it;
   info.relres = relres;
   info.q = q;
@@ -411,11 +469,16 @@ void metric_solve(eahp_problem* pb, const z64* Phi, const z64* R, const z64* Lam
   if (!(mu > 0)) fail(EAHP_EINVAL, "mu must be positive");
   if (info) info->clear();
   const int p = pb->p;
+  const bool mixed = pb->precision == EAHP_MIXED;
+  // single-precision Gram matrices cannot resolve pivots much below 1e-5 of the largest
+  const double tol = mixed ? std::max(rank_tol, 1e-5) : rank_tol;
   for (int ik = 0; ik < pb->nk; ++ik) {
     const int64_t o = (int64_t)p * pb->kp[ik].off;
     const double* lw = leig ? leig->w.as<double>() + (int64_t)ik * p : nullptr;
     const z64* lU = leig ? leig->U.as<z64>() + (int64_t)ik * p * p : nullptr;
-    FomInfo fi = fom_k(pb, ik, Phi + o, R + o, Lam + (int64_t)ik * p * p, mu, rtol, maxit, rank_tol, X + o, lw, lU);
+    const z64* L = Lam + (int64_t)ik * p * p;
+    FomInfo fi = mixed ? fom_k<float>(pb, ik, Phi + o, R + o, L, mu, rtol, maxit, tol, X + o, lw, lU)
+                       : fom_k<double>(pb, ik, Phi + o, R + o, L, mu, rtol, maxit, tol, X + o, lw, lU);
     if (info) info->push_back(fi);
   }
 }

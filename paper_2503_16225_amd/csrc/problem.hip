@@ -468,15 +468,16 @@ void apply_H_block(eahp_problem* pb, int ik, int ncols, const cplx<T>* X, cplx<T
   const T* V = sizeof(T) == 8 ? (const T*)pb->d_veff.p : (const T*)pb->d_veff32.p;
   const double nsum = (double)pb->kp[ik].npw * ncols;
   const int b = 2 * (int)sizeof(T);
-  prof_begin(pb, 0);
+  const int slot0 = sizeof(T) == 8 ? 0 : 4;  // timing slots 4..7 hold the single-precision launches
+  prof_begin(pb, slot0 + 0);
   launch_inv_yz<T>(st, cm, ncols, g, pb->plan[2], pb->plan[1], twz, twy, X, Tb);
-  prof_end(pb, 0, bytes_inv(pb, ncols, nsum, b));
-  prof_begin(pb, 1);
+  prof_end(pb, slot0 + 0, bytes_inv(pb, ncols, nsum, b));
+  prof_begin(pb, slot0 + 1);
   launch_x_local<T>(st, ncols, g, pb->plan[0], twx, V, Tb);
-  prof_end(pb, 1, bytes_xloc(pb, ncols, b));
-  prof_begin(pb, 2);
+  prof_end(pb, slot0 + 1, bytes_xloc(pb, ncols, b));
+  prof_begin(pb, slot0 + 2);
   launch_fwd_yz<T>(st, cm, ncols, g, pb->plan[2], pb->plan[1], twz, twy, Tb, X, HX);
-  prof_end(pb, 2, bytes_fwd(pb, ncols, nsum, b));
+  prof_end(pb, slot0 + 2, bytes_fwd(pb, ncols, nsum, b));
   const int64_t n = pb->kp[ik].npw;
   nonlocal_block<T>(pb, ik, ncols, X, n, HX, n, nullptr);
   pb->napply += ncols;
