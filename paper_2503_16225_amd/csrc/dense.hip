@@ -155,13 +155,15 @@ __global__ void __launch_bounds__(1024) k_heev(int n, z64* Ab, int64_t lda, int6
 
 bool heev_lds(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V,
               int64_t ldv, int64_t sV, int batch, DevMem& logbuf);
+bool heev_dc(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
+             int64_t sV, int batch, DevMem& scr);
 bool pchol_inv_lds(hipStream_t st, int n, const z64* G, int64_t ldg, double tol, int* rank, z64* Uinv, int64_t ldu);
 
 void heev(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
           int64_t sV, int batch, int* info) {
   if (n <= 0 || batch <= 0) return;
-  static DevMem logbuf;
-  if (heev_lds(st, n, A, lda, sA, w, sw, V, ldv, sV, batch, logbuf)) return;
+  static DevMem dcbuf;
+  if (heev_dc(st, n, A, lda, sA, w, sw, V, ldv, sV, batch, dcbuf)) return;
   const int np = n + (n & 1), half = np / 2;
   const size_t lds = (size_t)half * (2 * sizeof(int) + 2 * sizeof(double) + sizeof(z64)) + 32 * sizeof(double) + 64;
   const int nt = n <= 32 ? 256 : 1024;

@@ -1,0 +1,654 @@
+// Hermitian eigendecomposition A = V diag(w) V^H for n <= 128, one work-group
+// of 1024 threads per matrix (batch over blockIdx.x):
+//
+//  1. Householder reduction to real symmetric tridiagonal form, Q^H A Q = T,
+//     with the matrix held in registers (thread t owns row t/8 and the 16
+//     columns congruent to t mod 8); reflectors H_k = I - tau_k v_k v_k^H are
+//     chosen so that every subdiagonal entry comes out real.
+//  2. Cuppen's divide and conquer on T, bottom up from 1 x 1 blocks: each
+//     merge solves the secular equation of a rank-one update of a diagonal
+//     matrix (Gu and Eisenstat's eigenvectors from the Loewner formula, so
+//     they are orthogonal to working precision), with deflation of tiny
+//     components and of close pole pairs by Givens rotations.  Q of the
+//     current blocks lives in LDS.
+//  3. V = Q Z, applying the reflectors to the real eigenvector matrix Z of T.
+//
+// Eigenvalues ascending.  Global scratch per matrix: the reflectors (n x n
+// complex + n), the secular differences (n x n) and a staging copy of the
+// merged eigenvector blocks (n x n).
+#include "devcommon.h"
+#include "kernels.h"
+
+namespace eahp {
+
+namespace {
+
+constexpr int kDcMax = 128;
+constexpr double kEps = 2.220446049250313e-16;
+
+__device__ __forceinline__ z64 cmulz(z64 a, z64 b) { return mk<double>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ z64 conjz(z64 a) { return mk<double>(a.x, -a.y); }
+
+struct DcShared {
+  double* Qs;   // n x n, column-major (aliased by the tridiagonalisation and back-transform buffers)
+  double *D, *dl, *zz, *rc, *rs, *tv, *zh, *nrm, *dd, *ee, *Uc;
+  int *srt, *nd, *dfl, *ra, *rb, *org, *outk, *Km, *nrot, *ndf;
+};
+
+// One secular root of 1 + rho sum_j z_j^2 / (dK_j - lam) = 0 for the i-th
+// interval, by the fixed-weight rational iteration of the two nearest poles,
+// safeguarded by the bracket; the sums over j are split over the 8 lanes of
+// the calling group.  Returns tau with lam = dK[org] + tau.
+__device__ double secular_root(const double* dK, const double* zK, int K, double rho, int i, int lane8, int& org) {
+  const bool last = i == K - 1;
+  auto sum8 = [&](double v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    return v;
+  };
+  double lo, hi;
+  int o;
+  if (!last) {
+    const double mid = 0.5 * (dK[i + 1] - dK[i]);
+    double s = 0.0;
+    for (int j = lane8; j < K; j += 8) s += zK[j] * zK[j] / ((dK[j] - dK[i]) - mid);
+    const double fm = 1.0 + rho * sum8(s);
+    if (fm >= 0.0) {
+      o = i;
+      lo = 0.0;
+      hi = mid;
+    } else {
+      o = i + 1;
+      lo = -mid;
+      hi = 0.0;
+    }
+  } else {
+    double s = 0.0;
+    for (int j = lane8; j < K; j += 8) s += zK[j] * zK[j];
+    o = K - 1;
+    lo = 0.0;
+    hi = rho * sum8(s);
+  }
+  const double dO = dK[o];
+  double t = 0.5 * (lo + hi);
+  for (int it = 0; it < 60; ++it) {
+    double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
+    for (int j = lane8; j < K; j += 8) {
+      const double r = 1.0 / ((dK[j] - dO) - t);
+      const double w = zK[j] * zK[j] * r;
+      if (j <= i) {
+        ps += w;
+        dps += w * r;
+      } else {
+        ph += w;
+        dph += w * r;
+      }
+    }
+    ps = rho * sum8(ps);
+    dps = rho * sum8(dps);
+    ph = rho * sum8(ph);
+    dph = rho * sum8(dph);
+    const double f = 1.0 + ps + ph;
+    if (f < 0.0) lo = t;
+    else hi = t;
+    // stop once f is within its own rounding error (the bound used by LAPACK's
+    // secular solvers) or the bracket has collapsed
+    const double erretm = 8.0 * (ph - ps) + 2.0 + 3.0 * fabs(t) * (dps + dph);
+    if (fabs(f) <= kEps * erretm || hi - lo <= 2.0 * kEps * fmax(fabs(lo), fabs(hi))) break;
+    const double DL = (dK[i] - dO) - t;
+    double eta;
+    bool have = false;
+    if (!last) {
+      const double DR = (dK[i + 1] - dO) - t;
+      const double a = dps * DL * DL, b = dph * DR * DR;
+      const double c = f - dps * DL - dph * DR;
+      const double A = c, B = c * (DL + DR) + a + b, C = c * DL * DR + a * DR + b * DL;
+      const double sq = sqrt(fmax(B * B - 4.0 * A * C, 0.0));
+      // the root of the two-pole model inside (DL, DR), from the stable forms first
+      auto consider = [&](double v) {
+        if (!have && v > DL && v < DR) {
+          eta = v;
+          have = true;
+        }
+      };
+      if (B + sq != 0.0) consider(2.0 * C / (B + sq));
+      if (B - sq != 0.0) consider(2.0 * C / (B - sq));
+      if (A != 0.0) {
+        consider((B + sq) / (2.0 * A));
+        consider((B - sq) / (2.0 * A));
+      }
+      if (!have) eta = -f / (dps + dph);
+    } else {
+      const double a = dps * DL * DL, c = f - dps * DL;
+      eta = (c != 0.0) ? DL + a / c : -f / dps;
+    }
+    double tn = t + eta;
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    if (tn == t || fabs(tn - t) <= kEps * fabs(t)) {
+      t = tn;
+      break;
+    }
+    t = tn;
+  }
+  org = o;
+  return t;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__ Ab, int64_t lda, int64_t sA,
+                                                  double* __restrict__ wb, int64_t sw, z64* __restrict__ Vb,
+                                                  int64_t ldv, int64_t sV, double* __restrict__ scrb, int64_t sscr) {
+  extern __shared__ unsigned char smem_raw[];
+  DcShared S;
+  S.Qs = reinterpret_cast<double*>(smem_raw);
+  double* p = S.Qs + kDcMax * kDcMax;
+  S.D = p; p += kDcMax;
+  S.dl = p; p += kDcMax;
+  S.zz = p; p += kDcMax;
+  S.rc = p; p += kDcMax;
+  S.rs = p; p += kDcMax;
+  S.tv = p; p += kDcMax;
+  S.zh = p; p += kDcMax;
+  S.nrm = p; p += kDcMax;
+  S.dd = p; p += kDcMax;
+  S.ee = p; p += kDcMax;
+  S.Uc = p; p += 8 * kDcMax;
+  int* ip = reinterpret_cast<int*>(p);
+  S.srt = ip; ip += kDcMax;
+  S.nd = ip; ip += kDcMax;
+  S.dfl = ip; ip += kDcMax;
+  S.ra = ip; ip += kDcMax;
+  S.rb = ip; ip += kDcMax;
+  S.org = ip; ip += kDcMax;
+  S.outk = ip; ip += kDcMax;
+  S.Km = ip; ip += kDcMax;
+  S.nrot = ip; ip += kDcMax;
+  S.ndf = ip; ip += kDcMax;
+
+  const z64* A = Ab + blockIdx.x * sA;
+  double* w = wb + blockIdx.x * sw;
+  z64* V = Vb + blockIdx.x * sV;
+  double* scr = scrb + blockIdx.x * sscr;
+  z64* refl = reinterpret_cast<z64*>(scr);            // n x n: column k holds v_k (rows k+1..n-1)
+  z64* rtau = refl + (int64_t)n * n;                   // n
+  double* delta = reinterpret_cast<double*>(rtau + n);  // n x n
+  double* Qt = delta + (int64_t)n * n;                 // n x n
+  double* Ub = Qt + (int64_t)n * n;                    // n x n
+
+  const int t = threadIdx.x;
+  const int r = t >> 3, cg = t & 7;
+
+  // ------------------------------------------------------------ 1. tridiagonal form
+  {
+    // per column k: xs = column k, vs = reflector vector, ps = tau A v; each
+    // double-buffered by the parity of k so that one barrier per phase suffices
+    z64* xsb = reinterpret_cast<z64*>(S.Qs);
+    z64* vsb = xsb + 2 * kDcMax;
+    z64* psb = vsb + 2 * kDcMax;
+    z64* wsb = psb + 2 * kDcMax;
+    z64* taus = wsb + 2 * kDcMax;  // 2
+    const int lane = t & 63;
+    const int nw64 = 64 * ((n + 63) >> 6);  // whole waves covering the rows (shuffles need every lane)
+    z64 a[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int c = cg + 8 * m;
+      z64 v = mk<double>(0.0, 0.0);
+      if (r < n && c < n) {
+        const z64 x = A[r + (int64_t)c * lda], y = A[c + (int64_t)r * lda];
+        v = mk<double>(0.5 * (x.x + y.x), r == c ? 0.0 : 0.5 * (x.y - y.y));
+      }
+      a[m] = v;
+    }
+    for (int k = 0; k < n - 1; ++k) {
+      z64* xs = xsb + (k & 1) * kDcMax;
+      z64* vs = vsb + (k & 1) * kDcMax;
+      z64* ps = psb + (k & 1) * kDcMax;
+      z64* ws = wsb + (k & 1) * kDcMax;
+      if (r < n) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+          if (cg + 8 * m == k) xs[r] = a[m];
+      }
+      __syncthreads();
+      // the reflector: waves 0 and 1 (threads t < n) each compute the scalars
+      if (t < nw64) {
+        double sg = 0.0;
+        for (int i = k + 2 + lane; i < n; i += 64) sg += xs[i].x * xs[i].x + xs[i].y * xs[i].y;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sg += __shfl_xor(sg, o, 64);
+        const z64 al = xs[k + 1];
+        double beta;
+        z64 tau, inv;
+        if (sg == 0.0 && al.y == 0.0) {
+          tau = mk<double>(0.0, 0.0);
+          beta = al.x;
+          inv = mk<double>(0.0, 0.0);
+        } else {
+          const double nrm = sqrt(al.x * al.x + al.y * al.y + sg);
+          beta = al.x >= 0.0 ? -nrm : nrm;
+          tau = mk<double>((beta - al.x) / beta, -al.y / beta);
+          const double dx = al.x - beta, dy = al.y;
+          const double m2 = dx * dx + dy * dy;
+          inv = mk<double>(dx / m2, -dy / m2);
+        }
+        if (t < n) {
+          z64 v;
+          if (t <= k) v = mk<double>(0.0, 0.0);
+          else if (t == k + 1) v = mk<double>(1.0, 0.0);
+          else v = cmulz(xs[t], inv);
+          vs[t] = v;
+          if (t > k) refl[t + (int64_t)k * n] = v;
+        }
+        if (t == 0) {
+          rtau[k] = tau;
+          taus[k & 1] = tau;
+          S.ee[k] = beta;
+          S.dd[k] = xs[k].x;
+        }
+      }
+      __syncthreads();
+      {
+        const z64 tau = taus[k & 1];
+        z64 sv = mk<double>(0.0, 0.0);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const int c = cg + 8 * m;
+          if (c > k && c < n) sv = cadd<double>(sv, cmulz(a[m], vs[c]));
+        }
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+          sv.x += __shfl_xor(sv.x, o, 64);
+          sv.y += __shfl_xor(sv.y, o, 64);
+        }
+        if (cg == 0 && r < n) ps[r] = r > k ? cmulz(tau, sv) : mk<double>(0.0, 0.0);
+      }
+      __syncthreads();
+      // w = p + alpha v with alpha = -tau (p^H v) / 2 (waves 0 and 1)
+      if (t < nw64) {
+        double dx = 0.0, dy = 0.0;
+        for (int i = k + 1 + lane; i < n; i += 64) {
+          dx += ps[i].x * vs[i].x + ps[i].y * vs[i].y;
+          dy += ps[i].x * vs[i].y - ps[i].y * vs[i].x;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          dx += __shfl_xor(dx, o, 64);
+          dy += __shfl_xor(dy, o, 64);
+        }
+        const z64 al2 = cscale<double>(cmulz(taus[k & 1], mk<double>(dx, dy)), -0.5);
+        if (t < n) ws[t] = cadd<double>(ps[t], cmulz(al2, vs[t]));
+      }
+      __syncthreads();
+      // A -= v w^H + w v^H on the trailing block
+      if (r > k && r < n) {
+        const z64 vr = vs[r], wr = ws[r];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const int c = cg + 8 * m;
+          if (c > k && c < n) {
+            const z64 vc = vs[c], wc = ws[c];
+            a[m] = csub<double>(a[m], cadd<double>(cmulz(vr, conjz(wc)), cmulz(wr, conjz(vc))));
+          }
+        }
+      }
+    }
+    if (r == n - 1) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m)
+        if (cg + 8 * m == n - 1) S.dd[n - 1] = a[m].x;
+    }
+    __syncthreads();
+  }
+
+  // ------------------------------------------------------------ 2. divide and conquer on (dd, ee)
+  double* Q = S.Qs;
+  for (int e = t; e < n * n; e += blockDim.x) Q[e] = (e % n == e / n) ? 1.0 : 0.0;
+  for (int i = t; i < n; i += blockDim.x) {
+    double v = S.dd[i];
+    if (i > 0) v -= fabs(S.ee[i - 1]);
+    if (i < n - 1) v -= fabs(S.ee[i]);
+    S.D[i] = v;
+  }
+  __syncthreads();
+  for (int size = 1; size < n; size *= 2) {
+    const int nmerge = (n + 2 * size - 1) / (2 * size);
+    // A: gather z, sort the poles, deflate (one thread per merge)
+    if (t < nmerge) {
+      const int s = t * 2 * size;
+      const int n1 = min(size, n - s), n2 = min(size, n - s - n1);
+      S.Km[t] = 0;
+      S.nrot[t] = 0;
+      S.ndf[t] = 0;
+      if (n2 > 0) {
+        const int m = n1 + n2;
+        const double ev = S.ee[s + n1 - 1];
+        const double sg = ev >= 0.0 ? 1.0 : -1.0;
+        const double rho = 2.0 * fabs(ev);
+        const double isq2 = 0.7071067811865476;
+        // merge the two ascending halves
+        int i1 = 0, i2 = n1;
+        for (int q = 0; q < m; ++q) {
+          int j;
+          if (i2 >= m || (i1 < n1 && S.D[s + i1] <= S.D[s + i2])) j = i1++;
+          else j = i2++;
+          S.srt[s + q] = j;
+          S.dl[s + q] = S.D[s + j];
+          S.zz[s + q] = (j < n1 ? Q[(s + n1 - 1) + (s + j) * n] : sg * Q[(s + n1) + (s + j) * n]) * isq2;
+        }
+        double dmax = 0.0, zmax = 0.0;
+        for (int q = 0; q < m; ++q) {
+          dmax = fmax(dmax, fabs(S.dl[s + q]));
+          zmax = fmax(zmax, fabs(S.zz[s + q]));
+        }
+        const double tol = 8.0 * kEps * fmax(dmax, rho * zmax);
+        int K = 0, nd = 0, nr = 0, pj = -1;
+        for (int j = 0; j < m; ++j) {
+          if (rho * fabs(S.zz[s + j]) <= tol) {
+            S.dfl[s + nd++] = j;
+            continue;
+          }
+          if (pj < 0) {
+            pj = j;
+            continue;
+          }
+          const double zs = S.zz[s + pj], zc = S.zz[s + j];
+          const double tau = hypot(zc, zs);
+          const double c = zc / tau, sn = -zs / tau;
+          const double tt = S.dl[s + j] - S.dl[s + pj];
+          if (fabs(tt * c * sn) <= tol) {
+            S.zz[s + j] = tau;
+            S.zz[s + pj] = 0.0;
+            S.ra[s + nr] = S.srt[s + pj];
+            S.rb[s + nr] = S.srt[s + j];
+            S.rc[s + nr] = c;
+            S.rs[s + nr] = sn;
+            ++nr;
+            const double dp = S.dl[s + pj], dj = S.dl[s + j];
+            S.dl[s + pj] = c * c * dp + sn * sn * dj;
+            S.dl[s + j] = sn * sn * dp + c * c * dj;
+            S.dfl[s + nd++] = pj;
+            pj = j;
+          } else {
+            S.nd[s + K++] = pj;
+            pj = j;
+          }
+        }
+        if (pj >= 0) S.nd[s + K++] = pj;
+        S.Km[t] = K;
+        S.nrot[t] = nr;
+        S.ndf[t] = nd;
+      }
+    }
+    __syncthreads();
+    // B: the deflation rotations act on columns of the block's eigenvector matrix
+    for (int R = t; R < n; R += blockDim.x) {
+      const int mi = R / (2 * size), s = mi * 2 * size;
+      const int nr = S.nrot[mi];
+      for (int q = 0; q < nr; ++q) {
+        const int ca = s + S.ra[s + q], cb = s + S.rb[s + q];
+        const double c = S.rc[s + q], sn = S.rs[s + q];
+        const double qa = Q[R + ca * n], qb = Q[R + cb * n];
+        Q[R + ca * n] = c * qa + sn * qb;
+        Q[R + cb * n] = -sn * qa + c * qb;
+      }
+    }
+    // C: secular roots, 8 lanes per root (slot g = s + i);
+    // gather the non-deflated poles/weights contiguously (dK into tv, zK into nrm)
+    for (int g = t; g < n; g += blockDim.x) {
+      const int mi = g / (2 * size), s = mi * 2 * size, i = g - s;
+      if (i < S.Km[mi]) {
+        S.tv[g] = S.dl[s + S.nd[s + i]];
+        S.nrm[g] = S.zz[s + S.nd[s + i]];
+      }
+    }
+    __syncthreads();
+    // roots: lam_i = dK[org_i] + tau_i; origin index into org, tau into rc (rotations are done)
+    {
+      const int g = t >> 3, lane8 = t & 7;
+      if (g < n) {
+        const int mi = g / (2 * size), s = mi * 2 * size, i = g - s;
+        const int K = S.Km[mi];
+        if (i < K) {
+          const double rho = 2.0 * fabs(S.ee[s + min(size, n - s) - 1]);
+          int o;
+          const double tau = secular_root(S.tv + s, S.nrm + s, K, rho, i, lane8, o);
+          if (lane8 == 0) {
+            S.org[g] = o;
+            S.rc[g] = tau;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // D: delta[i][j] = dK_j - lam_i (rows i, columns j of the block), global scratch
+    for (int e = t; e < n * n; e += blockDim.x) {
+      const int R = e % n, C = e / n;
+      const int mi = R / (2 * size), s = mi * 2 * size;
+      if (C / (2 * size) != mi) continue;
+      const int K = S.Km[mi], i = R - s, j = C - s;
+      if (i < K && j < K) delta[R + (int64_t)C * n] = (S.tv[s + j] - S.tv[s + S.org[R]]) - S.rc[R];
+    }
+    __syncthreads();
+    // E: Loewner weights z^_i (sign of z_i)
+    for (int g = t; g < n; g += blockDim.x) {
+      const int mi = g / (2 * size), s = mi * 2 * size, i = g - s;
+      const int K = S.Km[mi];
+      if (i < K) {
+        const double* dK = S.tv + s;
+        // delta[i][j] at delta[(s+i) + (s+j) n]; dK_i - lam_j = delta[j][i]
+        double wv = delta[g + (int64_t)g * n];
+        for (int j = 0; j < K; ++j)
+          if (j != i) wv *= delta[(s + j) + (int64_t)g * n] / (dK[i] - dK[j]);
+        S.zh[g] = copysign(sqrt(fmax(-wv, 0.0)), S.nrm[g]);
+      }
+    }
+    __syncthreads();
+    // U[i][k] = z^_i / (dK_i - lam_k) (unnormalised eigenvector k of the rank-one update)
+    for (int e = t; e < n * n; e += blockDim.x) {
+      const int R = e % n, C = e / n;
+      const int mi = R / (2 * size), s = mi * 2 * size;
+      if (C / (2 * size) != mi) continue;
+      const int K = S.Km[mi], i = R - s, k = C - s;
+      if (i < K && k < K) Ub[R + (int64_t)C * n] = S.zh[R] / delta[C + (int64_t)R * n];
+    }
+    __syncthreads();
+    // F: column norms of U (8 lanes per column), the final order of each merged
+    // block (one thread per merge) and the source columns of the product
+    {
+      const int g = t >> 3, lane8 = t & 7;
+      double acc = 0.0;
+      int K = 0, s = 0;
+      if (g < n) {
+        const int mi = g / (2 * size);
+        s = mi * 2 * size;
+        K = S.Km[mi];
+        if (g - s < K)
+          for (int i = lane8; i < K; i += 8) {
+            const double u = Ub[(s + i) + (int64_t)g * n];
+            acc += u * u;
+          }
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      acc += __shfl_xor(acc, 4, 64);
+      if (g < n && g - s < K && lane8 == 0) S.dd[g] = 1.0 / sqrt(acc);  // the diagonal of T is no longer needed
+    }
+    for (int g = t; g < n; g += blockDim.x) {
+      const int mi = g / (2 * size), s = mi * 2 * size, i = g - s;
+      if (i < S.Km[mi]) S.ra[g] = s + S.srt[s + S.nd[s + i]];  // Q column of non-deflated pole i
+    }
+    if (t < nmerge) {
+      const int s = t * 2 * size;
+      const int n1 = min(size, n - s), n2 = min(size, n - s - n1);
+      if (n2 > 0) {
+        const int m = n1 + n2, K = S.Km[t], nd = S.ndf[t];
+        // insertion sort of the deflated values (ascending), stable
+        for (int a2 = 1; a2 < nd; ++a2) {
+          const int v = S.dfl[s + a2];
+          const double key = S.dl[s + v];
+          int b2 = a2 - 1;
+          while (b2 >= 0 && S.dl[s + S.dfl[s + b2]] > key) {
+            S.dfl[s + b2 + 1] = S.dfl[s + b2];
+            --b2;
+          }
+          S.dfl[s + b2 + 1] = v;
+        }
+        // outk[q] >= 0: root outk[q]; otherwise the Q column -outk[q] - 1 (deflated);
+        // rb[k] = output position of root k
+        int ia = 0, ib = 0;
+        for (int q = 0; q < m; ++q) {
+          const double lr = ia < K ? S.tv[s + S.org[s + ia]] + S.rc[s + ia] : 0.0;
+          const double ld = ib < nd ? S.dl[s + S.dfl[s + ib]] : 0.0;
+          if (ib >= nd || (ia < K && lr <= ld)) {
+            S.outk[s + q] = ia;
+            S.rb[s + ia] = q;
+            S.D[s + q] = lr;
+            ++ia;
+          } else {
+            S.outk[s + q] = -(s + S.srt[s + S.dfl[s + ib]] + 1);
+            S.D[s + q] = ld;
+            ++ib;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // G: merged eigenvectors into the staging copy; thread (row R, column
+    // group cgp) forms the roots k = cgp + 8 j of its block, two passes of 8
+    // accumulators, with rows of U staged in LDS 8 at a time
+    {
+      const int R = t & (kDcMax - 1), cgp = t >> 7;
+      int kmax = 0;
+      for (int q = 0; q < nmerge; ++q) kmax = max(kmax, S.Km[q]);
+      const int mi = R / (2 * size), s = mi * 2 * size;
+      const int n1 = min(size, n - s), n2 = min(size, n - s - n1);
+      const bool valid = R < n && n2 > 0;
+      const int K = valid ? S.Km[mi] : 0;
+      for (int j0 = 0; j0 < 16; j0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+        for (int i0 = 0; i0 < kmax; i0 += 8) {
+          __syncthreads();
+          {
+            const int ii = t >> 7, C = t & (kDcMax - 1);
+            double u = 0.0;
+            if (C < n) {
+              const int mc = C / (2 * size), sc = mc * 2 * size, Kc = S.Km[mc];
+              if (i0 + ii < Kc && C - sc < Kc) u = Ub[(sc + i0 + ii) + (int64_t)C * n];
+            }
+            S.Uc[ii * kDcMax + C] = u;
+          }
+          __syncthreads();
+          if (valid) {
+            for (int ii = 0; ii < 8 && i0 + ii < K; ++ii) {
+              const double qv = Q[R + S.ra[s + i0 + ii] * n];
+              const double* urow = S.Uc + ii * kDcMax + s;
+#pragma unroll
+              for (int j = 0; j < 8; ++j) acc[j] += qv * urow[min(cgp + 8 * (j0 + j), kDcMax - 1 - s)];
+            }
+          }
+        }
+        if (valid) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int k = cgp + 8 * (j0 + j);
+            if (k < K) Qt[R + (int64_t)(s + S.rb[s + k]) * n] = acc[j] * S.dd[s + k];
+          }
+        }
+      }
+      if (valid) {
+        const int m = n1 + n2;
+        for (int q = cgp; q < m; q += 8) {
+          const int o = S.outk[s + q];
+          if (o < 0) Qt[R + (int64_t)(s + q) * n] = Q[R + (-o - 1) * n];
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < n * n; e += blockDim.x) {
+      const int R = e % n, C = e / n;
+      const int mi = C / (2 * size), s = mi * 2 * size;
+      const int n1 = min(size, n - s), n2 = min(size, n - s - n1);
+      if (n2 <= 0 || R / (2 * size) != mi) continue;
+      Q[R + C * n] = Qt[R + (int64_t)C * n];
+    }
+    __syncthreads();
+  }
+
+  // ------------------------------------------------------------ 3. V = Q_householder Z
+  {
+    const int c = t >> 3, rg = t & 7;  // column c, rows rg + 8 m
+    z64 zv[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int rr = rg + 8 * m;
+      zv[m] = mk<double>((c < n && rr < n) ? Q[rr + c * n] : 0.0, 0.0);
+    }
+    for (int i = t; i < n; i += blockDim.x) w[i] = S.D[i];
+    __syncthreads();
+    constexpr int CH = 32;
+    z64* vst = reinterpret_cast<z64*>(S.Qs);  // CH x n reflectors
+    z64* tst = vst + CH * kDcMax;              // CH taus
+    for (int k1 = n - 2; k1 >= 0; k1 -= CH) {
+      const int k0 = max(0, k1 - CH + 1);
+      const int cnt = k1 - k0 + 1;
+      for (int e = t; e < cnt * n; e += blockDim.x) {
+        const int kk = e / n, i = e % n;
+        const int k = k0 + kk;
+        vst[kk * kDcMax + i] = i > k ? refl[i + (int64_t)k * n] : mk<double>(0.0, 0.0);
+      }
+      for (int kk = t; kk < cnt; kk += blockDim.x) tst[kk] = rtau[k0 + kk];
+      __syncthreads();
+      for (int k = k1; k >= k0; --k) {
+        const z64* vk = vst + (k - k0) * kDcMax;
+        const z64 tk = tst[k - k0];
+        z64 s = mk<double>(0.0, 0.0);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const int rr = rg + 8 * m;
+          if (rr > k && rr < n) s = cadd<double>(s, cmulz(conjz(vk[rr]), zv[m]));
+        }
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+          s.x += __shfl_xor(s.x, o, 64);
+          s.y += __shfl_xor(s.y, o, 64);
+        }
+        const z64 f = cmulz(tk, s);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const int rr = rg + 8 * m;
+          if (rr > k && rr < n) zv[m] = csub<double>(zv[m], cmulz(f, vk[rr]));
+        }
+      }
+      __syncthreads();
+    }
+    if (c < n) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int rr = rg + 8 * m;
+        if (rr < n) V[rr + (int64_t)c * ldv] = zv[m];
+      }
+    }
+  }
+}
+
+size_t heev_dc_scratch(int n) { return sizeof(double) * ((size_t)5 * n * n + 2 * n) + 256; }
+
+bool heev_dc(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
+             int64_t sV, int batch, DevMem& scr) {
+  if (n < 1 || n > kDcMax) return false;
+  const int64_t per = (int64_t)((heev_dc_scratch(n) + 255) / 256 * 256 / sizeof(double));
+  scr.ensure(sizeof(double) * per * batch);
+  const size_t lds = sizeof(double) * ((size_t)kDcMax * kDcMax + 18 * kDcMax) + sizeof(int) * 10 * kDcMax;
+  HIPCK(hipFuncSetAttribute((const void*)k_heev_dc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_heev_dc, dim3(batch), dim3(1024), lds, st, n, A, lda, sA, w, sw, V, ldv, sV,
+                     scr.as<double>(), per);
+  HIPCK(hipGetLastError());
+  return true;
+}
+
+}  // namespace eahp

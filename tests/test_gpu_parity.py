@@ -36,6 +36,7 @@ CASES = {
     "tiny_k2": lambda: W.system(*W.diamond_cell(), 3.0, (0, 0, 0), np.array([[0.25, -0.125, 0.375], [-0.25, 0.25, 0.25]]),
                                 np.array([0.5, 0.5])),
     "si8_gamma_e10": lambda: W.config("si8_gamma_e10"),
+    "tiny_p13": lambda: W.system(*W.diamond_cell(), 3.0, (0, 0, 0), p=13),
 }
 
 
@@ -252,3 +253,33 @@ def test_full_size_manifold_ops():
     log("si64 gradient", rel(G, G_o))
     assert rel(G, G_o) < 1e-10
     gp.close()
+
+
+def test_retract_degenerate_and_odd_sizes():
+    """The p x p eigensolver behind the retraction on sizes that are not powers
+    of two and on Gram matrices with exactly degenerate eigenvalues:
+    pf(Phi (I + tau M)) = Phi for Hermitian M with I + tau M positive
+    definite (the polar factor of a positive definite matrix is I), and
+    random directions against the oracle."""
+    Problem = _gpu()
+    from oracle import hamiltonian as ham, manifold as mf
+    rng = np.random.default_rng(11)
+    for p in (100, 37, 128):
+        sysd = W.system(*W.diamond_cell(), 10.0, (32, 32, 32), p=p)
+        om = ham.Model(sysd)
+        gp = Problem(sysd)
+        Z = W.gaussian_block(1, om.npw, p)
+        Phi = np.concatenate([mf.polar(b)[0] for b in om.blocks(Z)], axis=0)
+        U, _ = np.linalg.qr(rng.standard_normal((p, p)) + 1j * rng.standard_normal((p, p)))
+        m = np.repeat(np.linspace(0.0, 2.0, 5), (p + 4) // 5)[:p]
+        M = (U * m) @ U.conj().T
+        out = gp.to_blocks(gp.retract(gp.to_device(Phi), gp.to_device(Phi @ M), 0.7))
+        log("degenerate retract p", p, rel(out, Phi))
+        assert rel(out, Phi) < 1e-13
+        eta = W.gaussian_block(5, om.npw, p)
+        Pn_o, _ = mf.retract(om, Phi, eta, 0.3)
+        Pn = gp.to_blocks(gp.retract(gp.to_device(Phi), gp.to_device(eta), 0.3))
+        log("random retract p", p, rel(Pn, Pn_o))
+        assert rel(Pn, Pn_o) < 1e-12
+        assert np.abs(Pn.conj().T @ Pn - np.eye(p)).max() < 1e-13
+        gp.close()
