@@ -157,7 +157,8 @@ bool heev_lds(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, doub
               int64_t ldv, int64_t sV, int batch, DevMem& logbuf);
 bool heev_dc(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
              int64_t sV, int batch, DevMem& scr);
-bool pchol_inv_lds(hipStream_t st, int n, const z64* G, int64_t ldg, double tol, int* rank, z64* Uinv, int64_t ldu);
+bool pchol_inv_reg(hipStream_t st, int n, const z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* U,
+                   int64_t ldu, DevMem& scr);
 
 void heev(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
           int64_t sV, int batch, int* info) {
@@ -374,7 +375,8 @@ __global__ void __launch_bounds__(1024) k_pchol(int n, z64* G, int64_t ldg, doub
 void pchol_inv(hipStream_t st, int n, z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* Uinv, int64_t ldu,
                int* info) {
   if (n <= 0) return;
-  if (pchol_inv_lds(st, n, G, ldg, tol, rank, Uinv, ldu)) return;
+  static DevMem lbuf;
+  if (pchol_inv_reg(st, n, G, ldg, tol, piv, rank, Uinv, ldu, lbuf)) return;
   const size_t lds = (size_t)n * sizeof(int) + 64;
   HIPCK(hipFuncSetAttribute((const void*)k_pchol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_pchol, dim3(1), dim3(n <= 64 ? 256 : 1024), lds, st, n, G, ldg, tol, piv, rank, Uinv, ldu,
