@@ -198,6 +198,43 @@ void eahp_solver_destroy(eahp_solver* sv);
 int eahp_prof_enable(eahp_ctx* ctx, int on);
 int eahp_prof_read(eahp_ctx* ctx, int kernel, double* total_ms, int64_t* launches, double* bytes);
 
+/* Layout of a system without touching the device: plane waves per k-point
+ * (npw_per_k[nk], the row counts of the k-blocks of a frame), the FFT box and
+ * an estimate of the device bytes one EARCG solve of it needs (frames, the
+ * slab of a frame-wide H-apply, the block FOM, grids).  Any output may be
+ * NULL.  Host-only; EAHP_EINVAL for an invalid description. */
+int eahp_layout_estimate(const eahp_system_desc* desc, int64_t* npw_per_k, int fft[3], int64_t* bytes);
+
+/* Serving loop over independent ground-state requests (Sec. 5 systems solved
+ * to ||R||_F <= tol by Algorithm 3, each with its own system and frame).
+ *
+ * create: a scheduler for `device` that admits queued requests while their
+ *   summed estimated footprints stay within hbm_budget bytes and fewer than
+ *   max_slots run (a request larger than the budget runs alone).  Admitted
+ *   requests run concurrently, each on its own stream from its own host
+ *   thread, and keep all their state on the device until they finish.
+ * submit: copies the description, the parameters and the initial frame
+ *   (host memory, complex128, the layout of eahp_layout_estimate) and queues
+ *   the request; *ticket identifies it.  Returns immediately.
+ * poll: *state = 0 queued, 1 running, 2 done, 3 failed; once finished, the
+ *   statistics, the latency from submission to completion and the time spent
+ *   queued; returns the request's own status (EAHP_ENOCONV when maxit was
+ *   reached) once finished, EAHP_OK before.
+ * result: copies the final frame to host memory (same layout) and releases
+ *   the ticket.  wait_all blocks until nothing is queued or running.
+ * destroy waits for running requests, then frees everything.
+ * A request's result is independent of the others in the mix: no reduction
+ * crosses requests. */
+typedef struct eahp_server eahp_server;
+int eahp_server_create(int device, size_t hbm_budget, int max_slots, eahp_server** out);
+int eahp_server_submit(eahp_server* srv, const eahp_system_desc* desc, const eahp_solve_params* prm,
+                       const void* Psi0_host, uint64_t* ticket);
+int eahp_server_poll(eahp_server* srv, uint64_t ticket, int* state, eahp_stats* stats, double* latency_s,
+                     double* queued_s);
+int eahp_server_result(eahp_server* srv, uint64_t ticket, void* Psi_host);
+int eahp_server_wait_all(eahp_server* srv);
+void eahp_server_destroy(eahp_server* srv);
+
 const char* eahp_strerror(int status);
 const char* eahp_last_error(void);
 

@@ -90,6 +90,14 @@ def load_library():
         "eahp_transport": ([vp, vp, vp, vp, vp], C.c_int),
         "eahp_linesearch": ([vp, vp, vp, C.c_double, C.POINTER(SolveParams), dp, vp, ip], C.c_int),
         "eahp_solve": ([vp, vp, C.POINTER(SolveParams), C.POINTER(Stats)], C.c_int),
+        "eahp_layout_estimate": ([C.POINTER(SystemDesc), i64p, ip, i64p], C.c_int),
+        "eahp_server_create": ([C.c_int, C.c_size_t, C.c_int, C.POINTER(vp)], C.c_int),
+        "eahp_server_submit": ([vp, C.POINTER(SystemDesc), C.POINTER(SolveParams), vp, C.POINTER(C.c_uint64)],
+                               C.c_int),
+        "eahp_server_poll": ([vp, C.c_uint64, ip, C.POINTER(Stats), dp, dp], C.c_int),
+        "eahp_server_result": ([vp, C.c_uint64, vp], C.c_int),
+        "eahp_server_wait_all": ([vp], C.c_int),
+        "eahp_server_destroy": ([vp], None),
         "eahp_strerror": ([C.c_int], C.c_char_p),
         "eahp_last_error": ([], C.c_char_p),
     }
@@ -131,6 +139,96 @@ def frame_from_blocks(npw, p, blocks):
     return np.concatenate(out)
 
 
+def make_desc(sysd, precision=EAHP_FP64):
+    """SystemDesc of a system dict; returns (desc, arrays that must outlive it)."""
+    lat = np.asarray(sysd["lattice"], float)
+    keep = [np.ascontiguousarray(np.asarray(sysd["frac"], float).reshape(-1)),
+            np.ascontiguousarray(np.asarray(sysd["Z"], float)),
+            np.ascontiguousarray(np.asarray(sysd["kfrac"], float).reshape(-1)),
+            np.ascontiguousarray(np.asarray(sysd["kweight"], float))]
+    d = SystemDesc()
+    d.lattice[:] = list(lat.flatten(order="F"))
+    d.natoms = len(keep[1])
+    d.frac = keep[0].ctypes.data_as(C.POINTER(C.c_double))
+    d.Z = keep[1].ctypes.data_as(C.POINTER(C.c_double))
+    d.r_loc, d.r_proj, d.D_proj = sysd["r_loc"], sysd["r_proj"], sysd["D_proj"]
+    d.ecut = sysd["ecut"]
+    d.fft[:] = [int(x) for x in sysd.get("fft", (0, 0, 0))]
+    d.nk = len(keep[3])
+    d.kfrac = keep[2].ctypes.data_as(C.POINTER(C.c_double))
+    d.kweight = keep[3].ctypes.data_as(C.POINTER(C.c_double))
+    d.p = sysd["p"]
+    d.occ = sysd["occ"]
+    d.precision = precision
+    d.terms = sysd.get("terms", 15)
+    return d, keep
+
+
+def layout_estimate(sysd):
+    """(plane waves per k, FFT box, estimated device bytes of a solve), host only."""
+    lib = load_library()
+    d, keep = make_desc(sysd)
+    npw = (C.c_int64 * d.nk)()
+    fft = (C.c_int * 3)()
+    b = C.c_int64()
+    _check(lib.eahp_layout_estimate(C.byref(d), npw, fft, C.byref(b)))
+    return list(npw), tuple(fft), b.value
+
+
+class Server:
+    """Serving loop of libeahp (eahp_server_*): submit returns a ticket at once;
+    poll / result / wait_all as in the C API."""
+
+    def __init__(self, budget_bytes, max_slots, device=0):
+        self.lib = load_library()
+        h = C.c_void_p()
+        _check(self.lib.eahp_server_create(device, C.c_size_t(int(budget_bytes)), int(max_slots), C.byref(h)))
+        self.h = h
+        self._meta = {}
+
+    def submit(self, sysd, params, psi0_blocks, precision=EAHP_FP64):
+        d, keep = make_desc(sysd, precision)
+        npw, _, _ = layout_estimate(sysd)
+        frame = np.ascontiguousarray(frame_from_blocks(npw, sysd["p"], psi0_blocks).astype(np.complex128))
+        prm = SolveParams.from_dict(params)
+        t = C.c_uint64()
+        _check(self.lib.eahp_server_submit(self.h, C.byref(d), C.byref(prm), frame.ctypes.data_as(C.c_void_p),
+                                           C.byref(t)))
+        self._meta[t.value] = (npw, sysd["p"], frame.size)
+        return t.value
+
+    def poll(self, ticket):
+        """(state, stats dict or None, latency s, queued s, status)."""
+        state = C.c_int()
+        st = Stats()
+        lat, qd = C.c_double(), C.c_double()
+        rc = self.lib.eahp_server_poll(self.h, C.c_uint64(ticket), C.byref(state), C.byref(st), C.byref(lat),
+                                       C.byref(qd))
+        if state.value < 2:
+            return state.value, None, None, None, rc
+        return state.value, st.as_dict(), lat.value, qd.value, rc
+
+    def result(self, ticket):
+        npw, p, size = self._meta.pop(ticket)
+        out = np.empty(size, np.complex128)
+        _check(self.lib.eahp_server_result(self.h, C.c_uint64(ticket), out.ctypes.data_as(C.c_void_p)))
+        return frame_to_blocks(npw, p, out)
+
+    def wait_all(self):
+        _check(self.lib.eahp_server_wait_all(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.eahp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Problem:
     """One crystal on one GPU (owns a context bound to torch's current stream)."""
 
@@ -144,26 +242,7 @@ class Problem:
         ctx = C.c_void_p()
         _check(lib.eahp_ctx_create(device, C.c_void_p(stream), C.byref(ctx)))
         self.ctx = ctx
-        lat = np.asarray(sysd["lattice"], float)
-        self._keep = [np.ascontiguousarray(np.asarray(sysd["frac"], float).reshape(-1)),
-                      np.ascontiguousarray(np.asarray(sysd["Z"], float)),
-                      np.ascontiguousarray(np.asarray(sysd["kfrac"], float).reshape(-1)),
-                      np.ascontiguousarray(np.asarray(sysd["kweight"], float))]
-        d = SystemDesc()
-        d.lattice[:] = list(lat.flatten(order="F"))
-        d.natoms = len(self._keep[1])
-        d.frac = self._keep[0].ctypes.data_as(C.POINTER(C.c_double))
-        d.Z = self._keep[1].ctypes.data_as(C.POINTER(C.c_double))
-        d.r_loc, d.r_proj, d.D_proj = sysd["r_loc"], sysd["r_proj"], sysd["D_proj"]
-        d.ecut = sysd["ecut"]
-        d.fft[:] = [int(x) for x in sysd.get("fft", (0, 0, 0))]
-        d.nk = len(self._keep[3])
-        d.kfrac = self._keep[2].ctypes.data_as(C.POINTER(C.c_double))
-        d.kweight = self._keep[3].ctypes.data_as(C.POINTER(C.c_double))
-        d.p = sysd["p"]
-        d.occ = sysd["occ"]
-        d.precision = precision
-        d.terms = sysd.get("terms", 15)
+        d, self._keep = make_desc(sysd, precision)
         pb = C.c_void_p()
         _check(lib.eahp_problem_create(ctx, C.byref(d), C.byref(pb)))
         self.pb = pb

@@ -48,14 +48,10 @@ struct Trial {
   double df;
 };
 
-LineFactors& line_factors() {
-  static LineFactors L;
-  return L;
-}
 
 // f(t), f'(t) at R_Phi(t eta) into the trial buffers
 void eval_trial(eahp_problem* pb, const z64* Phi, const z64* eta, double t, Trial& tr) {
-  if (!retract_line(pb, Phi, eta, t, line_factors(), tr.Phi, *tr.F)) retract(pb, Phi, eta, t, tr.Phi, *tr.F);
+  if (!retract_line(pb, Phi, eta, t, pb->arena->line, tr.Phi, *tr.F)) retract(pb, Phi, eta, t, tr.Phi, *tr.F);
   evaluate_point(pb, tr.Phi, tr.HPhi, tr.R, tr.Lam, &tr.sc);
   transport_self(pb, tr.Phi, eta, t, *tr.F, tr.Teta);
   tr.df = frame_dot(pb, tr.R, tr.Teta);
@@ -79,7 +75,7 @@ double secant_step(eahp_problem* pb, const z64* Phi, const z64* eta, double f0, 
     eval_trial(pb, Phi, eta, t, tr);
   };
   auto ok = [&](double f, double df) { return f <= fbound && std::fabs(df) <= c * std::fabs(df0); };
-  line_prepare(pb, Phi, eta, line_factors());
+  line_prepare(pb, Phi, eta, pb->arena->line);
   double a = 0.0, dfa = df0;
   double b = tau0;
   ev(b);
@@ -355,6 +351,7 @@ int eahp_problem_create(eahp_ctx* ctx, const eahp_system_desc* desc, eahp_proble
     HIPCK(hipSetDevice(ctx->device));
     pb = new eahp_problem;
     pb->ctx = ctx;
+    pb->arena = new Arena;
     build_problem(pb, desc);
     *out = pb;
   });
@@ -365,7 +362,7 @@ int eahp_problem_create(eahp_ctx* ctx, const eahp_system_desc* desc, eahp_proble
 void eahp_problem_destroy(eahp_problem* pb) {
   if (pb) {
     (void)hipSetDevice(pb->ctx->device);
-    (void)hipDeviceSynchronize();
+    (void)hipStreamSynchronize(pb->ctx->stream);
   }
   delete pb;
 }

@@ -161,10 +161,9 @@ bool pchol_inv_reg(hipStream_t st, int n, const z64* G, int64_t ldg, double tol,
                    int64_t ldu, DevMem& scr);
 
 void heev(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
-          int64_t sV, int batch, int* info) {
+          int64_t sV, int batch, int* info, DevMem& scr) {
   if (n <= 0 || batch <= 0) return;
-  static DevMem dcbuf;
-  if (heev_dc(st, n, A, lda, sA, w, sw, V, ldv, sV, batch, dcbuf)) return;
+  if (heev_dc(st, n, A, lda, sA, w, sw, V, ldv, sV, batch, scr)) return;
   const int np = n + (n & 1), half = np / 2;
   const size_t lds = (size_t)half * (2 * sizeof(int) + 2 * sizeof(double) + sizeof(z64)) + 32 * sizeof(double) + 64;
   const int nt = n <= 32 ? 256 : 1024;
@@ -373,10 +372,9 @@ __global__ void __launch_bounds__(1024) k_pchol(int n, z64* G, int64_t ldg, doub
 }
 
 void pchol_inv(hipStream_t st, int n, z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* Uinv, int64_t ldu,
-               int* info) {
+               int* info, DevMem& scr) {
   if (n <= 0) return;
-  static DevMem lbuf;
-  if (pchol_inv_reg(st, n, G, ldg, tol, piv, rank, Uinv, ldu, lbuf)) return;
+  if (pchol_inv_reg(st, n, G, ldg, tol, piv, rank, Uinv, ldu, scr)) return;
   const size_t lds = (size_t)n * sizeof(int) + 64;
   HIPCK(hipFuncSetAttribute((const void*)k_pchol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_pchol, dim3(1), dim3(n <= 64 ? 256 : 1024), lds, st, n, G, ldg, tol, piv, rank, Uinv, ldu,

@@ -80,6 +80,8 @@ struct KPoint {
 
 struct Scalars;        // device scalar workspace (reductions)
 
+struct Arena;  // defined in ops.h
+
 struct Workspace {
   DevMem planes;       // T buffer: cols x ns x n2 x n3 complex (FP64 or FP32)
   DevMem grid_c;       // complex N_g scratch (potentials)
@@ -87,6 +89,8 @@ struct Workspace {
   DevMem small;        // small dense scratch
   DevMem gemm_part;    // split-K partials of the Gram kernels
   DevMem rho_part;     // per-column-group partial densities
+  DevMem eig;          // scratch of the p x p eigensolver
+  DevMem chol;         // scratch of the pivoted Cholesky
   DevMem f[10];        // frame-sized scratch used by the entry points and the solver
 };
 
@@ -137,6 +141,7 @@ struct eahp_problem {
   eahp::DevMem d_D;        // double[natoms] projector couplings
   // workspaces
   eahp::Workspace ws;
+  eahp::Arena* arena = nullptr;  // solver-side buffers (retraction, transports, FOM), owned
   eahp::DevMem d_kdesc;     // KDesc[nk]
   eahp::DevMem d_kw;        // double[nk]
   eahp::DevMem d_R;         // natoms x 3 positions (device)

@@ -102,14 +102,14 @@ void scale_rows(hipStream_t st, int m, int ncols, const double* D, cplx<T>* B, i
 // Hermitian eigendecomposition A = V diag(w) V^H by parallel cyclic Jacobi, one
 // work-group per matrix (batch over blockIdx.x).  A is overwritten.
 void heev(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
-          int64_t sV, int batch, int* info);
+          int64_t sV, int batch, int* info, DevMem& scr);
 // In-place inverse of a general n x n matrix (Gauss-Jordan, partial pivoting).
 void inverse(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, z64* work, int batch, int* info);
 // Pivoted Cholesky of a Hermitian PSD G (n x n): G[piv, piv] = L L^H with rank r
 // (diagonal pivots below tol * first pivot are dropped); outputs the upper
 // triangular inverse factor U = L^-H padded (n x r), piv and r.
 void pchol_inv(hipStream_t st, int n, z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* Uinv,
-               int64_t ldu, int* info);
+               int64_t ldu, int* info, DevMem& scr);
 // Elementwise helpers on small matrices (n x m, column-major).
 // Y = Q^H C U-ish products use gemm; these handle the spectral divisions.
 void sylv_divide(hipStream_t st, int q, int p, const double* w, const double* s, z64* Y, int64_t ldy);

@@ -10,15 +10,7 @@
 
 namespace eahp {
 
-namespace {
-struct Scratch {
-  DevMem a, b, c, d, e, f, g;
-};
-Scratch& scratch() {
-  static Scratch s;
-  return s;
-}
-}  // namespace
+
 
 // ---------------------------------------------------------------- retraction
 void retract(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* out, RetractFactors& F) {
@@ -29,7 +21,7 @@ void retract(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* 
   F.d.ensure(sizeof(double) * nk * p);
   F.V.ensure(sizeof(z64) * nk * pp);
   F.Sinv.ensure(sizeof(z64) * nk * pp);
-  Scratch& s = scratch();
+  Scratch& s = pb->arena->s;
   s.a.ensure(sizeof(z64) * N);
   s.b.ensure(sizeof(z64) * nk * pp);
   z64* Psi = s.a.as<z64>();
@@ -41,7 +33,7 @@ void retract(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* 
     const int64_t o = (int64_t)p * K.off;
     gemm_hn<double>(st, K.npw, p, p, Psi + o, K.npw, Psi + o, K.npw, Gm + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
   }
-  heev(st, p, Gm, p, pp, F.d.as<double>(), p, F.V.as<z64>(), p, pp, nk, pb->d_info.as<int>());
+  heev(st, p, Gm, p, pp, F.d.as<double>(), p, F.V.as<z64>(), p, pp, nk, pb->d_info.as<int>(), pb->ws.eig);
   minval(st, nk * p, F.d.as<double>(), scal(pb, S_MIN));
   spectral_fn(st, p, F.V.as<z64>(), p, pp, F.d.as<double>(), p, -0.5, F.Sinv.as<z64>(), p, pp, nk);
   for (int ik = 0; ik < nk; ++ik) {
@@ -61,7 +53,7 @@ void line_prepare(eahp_problem* pb, const z64* Phi, const z64* eta, LineFactors&
   const int64_t pp = (int64_t)p * p;
   for (DevMem* m : {&L.E0, &L.A1, &L.V, &L.Dt, &L.T}) m->ensure(sizeof(z64) * nk * pp);
   L.w.ensure(sizeof(double) * nk * p);
-  Scratch& s = scratch();
+  Scratch& s = pb->arena->s;
   s.b.ensure(sizeof(z64) * nk * pp);
   for (int ik = 0; ik < nk; ++ik) {
     auto& K = pb->kp[ik];
@@ -76,7 +68,7 @@ void line_prepare(eahp_problem* pb, const z64* Phi, const z64* eta, LineFactors&
   hermitize(st, p, L.E0.as<z64>(), p, pp, nk);
   add_diag(st, p, L.E0.as<z64>(), p, pp, -1.0, nk);
   hermitize(st, p, L.A1.as<z64>(), p, pp, nk);  // (X + X^H) / 2 with X = Phi^H eta
-  heev(st, p, s.b.as<z64>(), p, pp, L.w.as<double>(), p, L.V.as<z64>(), p, pp, nk, pb->d_info.as<int>());
+  heev(st, p, s.b.as<z64>(), p, pp, L.w.as<double>(), p, L.V.as<z64>(), p, pp, nk, pb->d_info.as<int>(), pb->ws.eig);
 }
 
 bool retract_line(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, LineFactors& L, z64* out,
@@ -109,7 +101,7 @@ bool retract_line(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, 
   gemm_nn<double>(st, p, p, p, Dt, p, V, p, 1, F.Sinv.as<z64>(), p, 1.0, 0.0, 0.0, nk, pp, pp, pp);
   hermitize(st, p, F.Sinv.as<z64>(), p, pp, nk);
   HIPCK(hipMemcpyAsync(F.V.p, V, sizeof(z64) * nk * pp, hipMemcpyDeviceToDevice, st));
-  Scratch& s = scratch();
+  Scratch& s = pb->arena->s;
   s.a.ensure(sizeof(z64) * N);
   z64* Psi = s.a.as<z64>();
   axpby<double>(st, N, 1.0, Phi, 0.0, Psi);
@@ -128,10 +120,10 @@ void lambda_eig(eahp_problem* pb, const z64* Lam, LamEig& E) {
   const int64_t pp = (int64_t)p * p;
   E.w.ensure(sizeof(double) * nk * p);
   E.U.ensure(sizeof(z64) * nk * pp);
-  Scratch& s = scratch();
+  Scratch& s = pb->arena->s;
   s.b.ensure(sizeof(z64) * nk * pp);
   copy2d(st, p, p * nk, Lam, p, s.b.as<z64>(), p);
-  heev(st, p, s.b.as<z64>(), p, pp, E.w.as<double>(), p, E.U.as<z64>(), p, pp, nk, pb->d_info.as<int>());
+  heev(st, p, s.b.as<z64>(), p, pp, E.w.as<double>(), p, E.U.as<z64>(), p, pp, nk, pb->d_info.as<int>(), pb->ws.eig);
 }
 
 // ---------------------------------------------------------------- transports
@@ -141,7 +133,7 @@ void transport_self(eahp_problem* pb, const z64* Phi_new, const z64* eta, double
   hipStream_t st = pb->ctx->stream;
   const int p = pb->p;
   const int64_t pp = (int64_t)p * p;
-  Scratch& s = scratch();
+  Scratch& s = pb->arena->s;
   s.c.ensure(sizeof(z64) * pb->ntot * p);
   s.d.ensure(sizeof(z64) * pb->nk * pp);
   z64* ES = s.c.as<z64>();
@@ -162,7 +154,7 @@ void transport_general(eahp_problem* pb, const z64* Phi_new, const z64* xi, cons
   hipStream_t st = pb->ctx->stream;
   const int p = pb->p, nk = pb->nk;
   const int64_t pp = (int64_t)p * p;
-  Scratch& s = scratch();
+  Scratch& s = pb->arena->s;
   s.c.ensure(sizeof(z64) * pb->ntot * p);
   s.d.ensure(sizeof(z64) * nk * pp);
   s.e.ensure(sizeof(z64) * nk * pp);
@@ -200,7 +192,7 @@ void ea_gradient(eahp_problem* pb, const z64* Phi, const z64* X, z64* G) {
   hipStream_t st = pb->ctx->stream;
   const int p = pb->p, nk = pb->nk;
   const int64_t pp = (int64_t)p * p;
-  Scratch& s = scratch();
+  Scratch& s = pb->arena->s;
   s.d.ensure(sizeof(z64) * nk * pp);
   s.f.ensure(sizeof(z64) * nk * pp * 2);
   z64* M = s.d.as<z64>();
@@ -229,16 +221,9 @@ void ea_gradient(eahp_problem* pb, const z64* Phi, const z64* X, z64* G) {
 namespace {
 
 template <typename T>
-struct FomWork {
-  DevMem V, W, A, Cj, C, E, Rj, Ah, T1, T2, Y, YS, YT, YST, Sig, U, s, alpha, Gm, Gm64, PU, PU64, tmp, piv, tri, stage,
-      Xt;
-  int64_t n = 0;
-  int qcap = 0;
-};
-template <typename T>
-FomWork<T>& fomwork() {
-  static FomWork<T> w;
-  return w;
+FomWork<T>& fomwork(eahp_problem* pb) {
+  if constexpr (sizeof(T) == 8) return pb->arena->fw64;
+  else return pb->arena->fw32;
 }
 
 constexpr bool is_fp64(double) { return true; }
@@ -275,7 +260,7 @@ int rrqr(eahp_problem* pb, int64_t n, int c, const cplx<T>* R, cplx<T>* dest, do
   cplx<T>* tmp = w.tmp.template as<cplx<T>>();
   auto factor = [&](const cplx<T>* X, int cols, double tl) {
     gram_into64<T>(pb, w, n, cols, cols, X, X, w.Gm64.template as<z64>(), cols);
-    pchol_inv(st, cols, w.Gm64.template as<z64>(), cols, tl, piv, rank, w.PU64.template as<z64>(), cols, nullptr);
+    pchol_inv(st, cols, w.Gm64.template as<z64>(), cols, tl, piv, rank, w.PU64.template as<z64>(), cols, nullptr, pb->ws.chol);
     HIPCK(hipMemcpyAsync(pb->h_info, pb->d_info.p, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     const int r = pb->h_info[0];
@@ -296,7 +281,7 @@ int rrqr(eahp_problem* pb, int64_t n, int c, const cplx<T>* R, cplx<T>* dest, do
 }
 
 template <typename T>
-void grow(FomWork<T>& w, int64_t n, int need, int p) {
+void grow(hipStream_t st, FomWork<T>& w, int64_t n, int need, int p) {
   if (need <= w.qcap && n == w.n) return;
   const int old = (n == w.n) ? w.qcap : 0;
   const int cap = std::max(need, old + 4 * p);
@@ -306,11 +291,13 @@ void grow(FomWork<T>& w, int64_t n, int need, int p) {
   A2.alloc(sizeof(z64) * (size_t)cap * cap);
   C2.alloc(sizeof(z64) * (size_t)cap * p);
   if (old > 0) {
-    HIPCK(hipDeviceSynchronize());
-    HIPCK(hipMemcpy(V2.p, w.V.p, sizeof(cplx<T>) * n * old, hipMemcpyDeviceToDevice));
-    HIPCK(hipMemcpy(W2.p, w.W.p, sizeof(cplx<T>) * n * old, hipMemcpyDeviceToDevice));
-    HIPCK(hipMemcpy2D(A2.p, sizeof(z64) * cap, w.A.p, sizeof(z64) * old, sizeof(z64) * old, old, hipMemcpyDeviceToDevice));
-    HIPCK(hipMemcpy2D(C2.p, sizeof(z64) * cap, w.Cj.p, sizeof(z64) * old, sizeof(z64) * old, p, hipMemcpyDeviceToDevice));
+    HIPCK(hipMemcpyAsync(V2.p, w.V.p, sizeof(cplx<T>) * n * old, hipMemcpyDeviceToDevice, st));
+    HIPCK(hipMemcpyAsync(W2.p, w.W.p, sizeof(cplx<T>) * n * old, hipMemcpyDeviceToDevice, st));
+    HIPCK(hipMemcpy2DAsync(A2.p, sizeof(z64) * cap, w.A.p, sizeof(z64) * old, sizeof(z64) * old, old,
+                           hipMemcpyDeviceToDevice, st));
+    HIPCK(hipMemcpy2DAsync(C2.p, sizeof(z64) * cap, w.Cj.p, sizeof(z64) * old, sizeof(z64) * old, p,
+                           hipMemcpyDeviceToDevice, st));
+    HIPCK(hipStreamSynchronize(st));  // the old buffers are freed below
   }
   std::swap(w.V.p, V2.p);
   std::swap(w.V.bytes, V2.bytes);
@@ -335,12 +322,12 @@ template <typename T>
 FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64* Lam, double mu, double rtol,
               int maxit, double rank_tol, z64* X, const double* lw, const z64* lU) {
   hipStream_t st = pb->ctx->stream;
-  FomWork<T>& w = fomwork<T>();
+  FomWork<T>& w = fomwork<T>(pb);
   const int p = pb->p;
   auto& K = pb->kp[ik];
   const int64_t n = K.npw;
   const int64_t np_ = n * p;
-  grow(w, n, 2 * p, p);
+  grow(st, w, n, 2 * p, p);
   w.C.ensure(sizeof(cplx<T>) * np_);
   w.E.ensure(sizeof(cplx<T>) * np_);
   w.Rj.ensure(sizeof(cplx<T>) * np_);
@@ -371,7 +358,7 @@ FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64*
     copy2d(st, p, p, lU, p, w.U.template as<z64>(), p);
   } else {
     copy2d(st, p, p, w.Sig.template as<z64>(), p, w.T1.template as<z64>(), p);
-    heev(st, p, w.T1.template as<z64>(), p, 0, w.s.template as<double>(), 0, w.U.template as<z64>(), p, 0, 1, pb->d_info.as<int>());
+    heev(st, p, w.T1.template as<z64>(), p, 0, w.s.template as<double>(), 0, w.U.template as<z64>(), p, 0, 1, pb->d_info.as<int>(), pb->ws.eig);
   }
   // TPA: alpha_j = sum_G |k+G|^2/2 |phi_jG|^2
   col_weighted_norm2(st, n, p, Phi, n, K.d_kin.as<double>(), w.alpha.template as<double>());
@@ -432,7 +419,7 @@ FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64*
       gemm_hn<T>(st, n, q, p, Vp(), n, Rj, n, w.T1.template as<cplx<T>>(), q, 1.0, 0.0, pb->ws.gemm_part);
       gemm_nn<T>(st, n, q, p, Vp(), n, w.T1.template as<cplx<T>>(), q, 0, Rj, n, -1.0, 0.0, 1.0);
     }
-    grow(w, n, q + p, p);
+    grow(st, w, n, q + p, p);
     ldA = w.qcap;
     cplx<T>* Vn = Vp() + (int64_t)q * n;
     const int r = rrqr<T>(pb, n, p, Rj, Vn, rank_tol, w);

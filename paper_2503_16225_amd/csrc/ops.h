@@ -20,6 +20,7 @@ struct PointScalars {
 extern thread_local std::string g_last_error;
 
 void build_problem(eahp_problem* pb, const eahp_system_desc* d);
+void layout_estimate(const eahp_system_desc* d, std::vector<int64_t>& npw, int n[3], int& ns, size_t& bytes);
 GridGeom geom(const eahp_problem* pb);
 ColMap frame_map(const eahp_problem* pb);
 ColMap block_map(const eahp_problem* pb, int k, int ncols);
@@ -52,6 +53,26 @@ void line_prepare(eahp_problem* pb, const z64* Phi, const z64* eta, LineFactors&
 // is too large for the first-order form, in which case retract() applies.
 bool retract_line(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, LineFactors& L, z64* out,
                   RetractFactors& F);
+// Frame- and block-sized buffers of the manifold operations (per problem).
+struct Scratch {
+  DevMem a, b, c, d, e, f, g;
+};
+// Buffers of the block FOM at precision T (Krylov basis V, W = H V, the
+// projected matrices, the rank-revealing step); they grow on demand.
+template <typename T>
+struct FomWork {
+  DevMem V, W, A, Cj, C, E, Rj, Ah, T1, T2, Y, YS, YT, YST, Sig, U, s, alpha, Gm, Gm64, PU, PU64, tmp, piv, tri, stage,
+      Xt;
+  int64_t n = 0;
+  int qcap = 0;
+};
+struct Arena {
+  Scratch s;
+  LineFactors line;
+  FomWork<double> fw64;
+  FomWork<float> fw32;
+};
+
 // Eigendecomposition of Lambda per k (w ascending order not guaranteed).
 struct LamEig {
   DevMem w, U;

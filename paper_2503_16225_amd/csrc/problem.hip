@@ -85,6 +85,91 @@ static void inv3(const double* A, double* Ai) {  // column-major 3x3 inverse
 
 static int freq_of(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
 
+// Plane waves of every k-point: G = B m with |k+G|^2/2 <= ecut, k = B kfrac.
+// Also the largest |m_d| per direction (it fixes the smallest alias-free box).
+void enumerate_bases(const eahp_system_desc* d, const double L[9], const double B[9],
+                     std::vector<std::vector<std::array<int, 3>>>& ms, std::vector<std::vector<double>>& kins,
+                     std::vector<std::array<double, 3>>& kvec, int mmax[3]) {
+  const double gmax = std::sqrt(2.0 * d->ecut);
+  ms.assign(d->nk, {});
+  kins.assign(d->nk, {});
+  kvec.assign(d->nk, {0.0, 0.0, 0.0});
+  for (int ik = 0; ik < d->nk; ++ik) {
+    double k[3];
+    for (int i = 0; i < 3; ++i) {
+      double s = 0;
+      for (int j = 0; j < 3; ++j) s += B[i + 3 * j] * d->kfrac[3 * ik + j];
+      k[i] = s;
+      kvec[ik][i] = s;
+    }
+    const double kn = std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    int lim[3];
+    for (int dd = 0; dd < 3; ++dd) {
+      // |m_d| <= |row d of B^-1| (gmax + |k|), B^-1 = L^T / (2 pi)
+      const double rn = std::sqrt(L[0 + 3 * dd] * L[0 + 3 * dd] + L[1 + 3 * dd] * L[1 + 3 * dd] +
+                                  L[2 + 3 * dd] * L[2 + 3 * dd]) / (2.0 * M_PI);
+      lim[dd] = (int)std::ceil((gmax + kn) * rn) + 1;
+    }
+    for (int a = -lim[0]; a <= lim[0]; ++a)
+      for (int b = -lim[1]; b <= lim[1]; ++b)
+        for (int c = -lim[2]; c <= lim[2]; ++c) {
+          double q[3];
+          for (int i = 0; i < 3; ++i) q[i] = k[i] + B[i] * a + B[i + 3] * b + B[i + 6] * c;
+          const double kin = 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+          if (kin <= d->ecut) {
+            ms[ik].push_back({a, b, c});
+            kins[ik].push_back(kin);
+            mmax[0] = std::max(mmax[0], std::abs(a));
+            mmax[1] = std::max(mmax[1], std::abs(b));
+            mmax[2] = std::max(mmax[2], std::abs(c));
+          }
+        }
+  }
+}
+
+void reciprocal(const double L[9], double B[9]) {
+  double Li[9];
+  inv3(L, Li);
+  // B = 2 pi L^-T: column j of B is row j of L^-1 times 2 pi
+  for (int j = 0; j < 3; ++j)
+    for (int i = 0; i < 3; ++i) B[i + 3 * j] = 2.0 * M_PI * Li[j + 3 * i];
+}
+
+// Sizes of a system without touching the device: plane waves per k, the box,
+// the number of active x-planes and an estimate of the device bytes a solve
+// needs (frames of the solver and the entry points, the slab of a frame-wide
+// H-apply, the block FOM with a Krylov basis of 8 p columns, grids).
+void layout_estimate(const eahp_system_desc* d, std::vector<int64_t>& npw, int n[3], int& ns, size_t& bytes) {
+  if (!d || d->nk <= 0 || d->p <= 0 || !(d->ecut > 0) || !d->kfrac || !d->kweight)
+    fail(EAHP_EINVAL, "invalid system description");
+  double B[9];
+  reciprocal(d->lattice, B);
+  std::vector<std::vector<std::array<int, 3>>> ms;
+  std::vector<std::vector<double>> kins;
+  std::vector<std::array<double, 3>> kvec;
+  int mmax[3] = {0, 0, 0};
+  enumerate_bases(d, d->lattice, B, ms, kins, kvec, mmax);
+  for (int dd = 0; dd < 3; ++dd) n[dd] = d->fft[dd] > 0 ? d->fft[dd] : smooth_at_least(4 * mmax[dd] + 1);
+  std::vector<char> used(n[0], 0);
+  npw.assign(d->nk, 0);
+  int64_t ntot = 0, nmax = 0;
+  for (int ik = 0; ik < d->nk; ++ik) {
+    npw[ik] = (int64_t)ms[ik].size();
+    ntot += npw[ik];
+    nmax = std::max(nmax, npw[ik]);
+    for (const auto& m : ms[ik]) used[((m[0] % n[0]) + n[0]) % n[0]] = 1;
+  }
+  ns = 0;
+  for (char u : used) ns += u;
+  const double p = d->p, Ng = (double)n[0] * n[1] * n[2];
+  const double ps = ((n[1] * n[2] + 15) / 16) * 16;
+  const double frame = 16.0 * ntot * p;
+  const double fom = 16.0 * nmax * (2.0 * 8 * p + 5 * p);
+  const double slab = 16.0 * d->nk * p * ns * ps;
+  const double grids = 16.0 * 12 * Ng + 24.0 * ntot * std::max(d->natoms, 1);
+  bytes = (size_t)(30 * frame + fom + slab + grids + 64.0 * 1024 * 1024);
+}
+
 // -------------------------------------------------------------------- build
 void build_problem(eahp_problem* pb, const eahp_system_desc* d) {
   if (!d || d->natoms < 0 || d->nk <= 0 || d->p <= 0 || !(d->ecut > 0) || !d->kfrac || !d->kweight)
@@ -93,11 +178,7 @@ void build_problem(eahp_problem* pb, const eahp_system_desc* d) {
   if (d->precision != EAHP_FP64 && d->precision != EAHP_MIXED) fail(EAHP_EINVAL, "unknown precision");
   hipStream_t st = pb->ctx->stream;
   std::memcpy(pb->lat, d->lattice, sizeof(pb->lat));
-  double Li[9];
-  inv3(pb->lat, Li);
-  // B = 2 pi L^-T: column j of B is row j of L^-1 times 2 pi
-  for (int j = 0; j < 3; ++j)
-    for (int i = 0; i < 3; ++i) pb->B[i + 3 * j] = 2.0 * M_PI * Li[j + 3 * i];
+  reciprocal(pb->lat, pb->B);
   const double* L = pb->lat;
   pb->Omega = std::fabs(L[0] * (L[4] * L[8] - L[7] * L[5]) - L[3] * (L[1] * L[8] - L[7] * L[2]) +
                         L[6] * (L[1] * L[5] - L[4] * L[2]));
@@ -121,41 +202,16 @@ void build_problem(eahp_problem* pb, const eahp_system_desc* d) {
   pb->terms = d->terms;
 
   // ---- bases: |k+G|^2/2 <= ecut, G = B m
-  const double gmax = std::sqrt(2.0 * d->ecut);
   std::vector<std::vector<std::array<int, 3>>> ms(d->nk);
   std::vector<std::vector<double>> kins(d->nk);
   int mmax[3] = {0, 0, 0};
+  std::vector<std::array<double, 3>> kvec;
+  enumerate_bases(d, pb->lat, pb->B, ms, kins, kvec, mmax);
   pb->kp.resize(d->nk);
   for (int ik = 0; ik < d->nk; ++ik) {
     auto& K = pb->kp[ik];
-    for (int i = 0; i < 3; ++i) {
-      double s = 0;
-      for (int j = 0; j < 3; ++j) s += pb->B[i + 3 * j] * d->kfrac[3 * ik + j];
-      K.k[i] = s;
-    }
+    for (int i = 0; i < 3; ++i) K.k[i] = kvec[ik][i];
     K.w = d->kweight[ik];
-    const double kn = std::sqrt(K.k[0] * K.k[0] + K.k[1] * K.k[1] + K.k[2] * K.k[2]);
-    int lim[3];
-    for (int dd = 0; dd < 3; ++dd) {
-      // |m_d| <= |row d of B^-1| (gmax + |k|), B^-1 = L^T / (2 pi)
-      const double rn = std::sqrt(L[0 + 3 * dd] * L[0 + 3 * dd] + L[1 + 3 * dd] * L[1 + 3 * dd] +
-                                  L[2 + 3 * dd] * L[2 + 3 * dd]) / (2.0 * M_PI);
-      lim[dd] = (int)std::ceil((gmax + kn) * rn) + 1;
-    }
-    for (int a = -lim[0]; a <= lim[0]; ++a)
-      for (int b = -lim[1]; b <= lim[1]; ++b)
-        for (int c = -lim[2]; c <= lim[2]; ++c) {
-          double q[3];
-          for (int i = 0; i < 3; ++i) q[i] = K.k[i] + pb->B[i] * a + pb->B[i + 3] * b + pb->B[i + 6] * c;
-          const double kin = 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
-          if (kin <= d->ecut) {
-            ms[ik].push_back({a, b, c});
-            kins[ik].push_back(kin);
-            mmax[0] = std::max(mmax[0], std::abs(a));
-            mmax[1] = std::max(mmax[1], std::abs(b));
-            mmax[2] = std::max(mmax[2], std::abs(c));
-          }
-        }
   }
   for (int dd = 0; dd < 3; ++dd) {
     pb->n[dd] = d->fft[dd] > 0 ? d->fft[dd] : smooth_at_least(4 * mmax[dd] + 1);
@@ -556,6 +612,7 @@ eahp_ctx::~eahp_ctx() {
 }
 
 eahp_problem::~eahp_problem() {
+  delete arena;
   if (h_scal) (void)hipHostFree(h_scal);
   if (h_info) (void)hipHostFree(h_info);
 }

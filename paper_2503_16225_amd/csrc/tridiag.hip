@@ -12,6 +12,7 @@
 #include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "devcommon.h"
 #include "kernels.h"
@@ -298,7 +299,15 @@ void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const 
     int qq = q;
     int64_t la = lda, lv = q;
     void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P};
-    HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(G), dim3(1024), args, lds, st));
+    {
+      // grid-synchronising kernels of concurrent streams (the serving loop)
+      // could each hold part of the CUs while waiting for the rest of their
+      // grid: one at a time per process, waited for before the next
+      static std::mutex coop;
+      std::lock_guard<std::mutex> lk(coop);
+      HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(G), dim3(1024), args, lds, st));
+      HIPCK(hipStreamSynchronize(st));
+    }
     hipLaunchKernelGGL(k_apply_refl, dim3(p), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, 1);
   } else {
     hipLaunchKernelGGL(k_set_d0, dim3(1), dim3(1), 0, st, A, dd);

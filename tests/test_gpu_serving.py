@@ -1,0 +1,94 @@
+"""Serving loop (eahp_server_*): independent requests of the serving stream
+(strained supercells of the 8-atom cell, Ecut 10-20 Ha, Gamma or 2x2x2 k)
+admitted by estimated device footprint and run concurrently on their own
+streams.  Each request's result must be the same alone and in the mix: the
+kernels are deterministic and nothing is reduced across requests, so the
+final frames and energies are compared to 1e-12 (they come out identical).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+RIDS = [22, 6, 15, 14]
+
+
+def sysd_of(rid):
+    r = W.serving_request(rid)
+    return W.system(r["lattice"], r["frac"], r["Z"], r["ecut"], (0, 0, 0), r["kfrac"], r["kweight"])
+
+
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_16225_amd import binding as B
+    return B
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def alone():
+    B = _lib()
+    prm = dict(W.DEFAULT_PARAMS, tol=1e-6, maxit=40)
+    out = {}
+    for i, rid in enumerate(RIDS):
+        sysd = sysd_of(rid)
+        prec = B.EAHP_MIXED if i == len(RIDS) - 1 else B.EAHP_FP64
+        gp = B.Problem(sysd, precision=prec)
+        Z = W.gaussian_block(100 + rid, gp.npw, gp.p)
+        Psi = gp.to_device(Z)
+        st, rc = gp.solve(Psi, prm, allow_noconv=True)
+        out[rid] = (Z, prec, st, gp.to_blocks(Psi))
+        print("alone", rid, gp.npw, gp.fft, gp.p, st["iters"], st["energy"], st["rnorm"], flush=True)
+        gp.close()
+    return prm, out
+
+
+def _run_mix(B, prm, alone_res, budget, slots):
+    srv = B.Server(budget, slots)
+    tickets = {}
+    for rid in RIDS:
+        Z, prec, _, _ = alone_res[rid]
+        tickets[rid] = srv.submit(sysd_of(rid), prm, Z, precision=prec)
+    srv.wait_all()
+    res = {}
+    for rid, t in tickets.items():
+        state, st, lat, queued, rc = srv.poll(t)
+        assert state == 2, (rid, state, rc)
+        res[rid] = (st, lat, queued, srv.result(t))
+    srv.close()
+    return res
+
+
+def test_mix_equals_alone(alone):
+    B = _lib()
+    prm, ref = alone
+    res = _run_mix(B, prm, ref, 64 << 30, 4)
+    for rid in RIDS:
+        st, lat, queued, frame = res[rid]
+        _, _, st0, frame0 = ref[rid]
+        print("mix", rid, "latency %.3f s queued %.3f s" % (lat, queued), st["iters"], st["energy"], flush=True)
+        assert st["iters"] == st0["iters"]
+        assert abs(st["energy"] - st0["energy"]) <= 1e-12 * abs(st0["energy"])
+        assert rel(frame, frame0) <= 1e-12
+
+
+def test_admission_by_footprint(alone):
+    """A budget that holds one request at a time: the requests run one after
+    the other (later ones wait in the queue) and still give the same results."""
+    B = _lib()
+    from paper_2503_16225_amd import layout_estimate
+    prm, ref = alone
+    est = max(layout_estimate(sysd_of(r))[2] for r in RIDS)
+    res = _run_mix(B, prm, ref, est + 1, 4)
+    queued = sorted(res[r][2] for r in RIDS)
+    print("queued times", queued, flush=True)
+    assert queued[-1] > 0.0 and queued[-1] >= queued[0]
+    for rid in RIDS:
+        assert rel(res[rid][3], ref[rid][3]) <= 1e-12
