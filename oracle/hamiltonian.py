@@ -110,12 +110,15 @@ class Model:
 
 
 # -- density and potentials ----------------------------------------------------
-def density(model, Phi):
-    """rho(r_j) = sum_k w_k f sum_i |psi_ik(r_j)|^2."""
+def density(model, Phi, chunk=None):
+    """rho(r_j) = sum_k w_k f sum_i |psi_ik(r_j)|^2 (columns taken `chunk` at a
+    time when given, which bounds the memory of the grid values)."""
     rho = np.zeros(model.fft)
     for ik, c in enumerate(model.blocks(Phi)):
-        psi = model.to_grid(ik, c)
-        rho += model.kw[ik] * model.occ * np.sum(np.abs(psi) ** 2, axis=0) / model.Omega
+        step = c.shape[1] if chunk is None else chunk
+        for j0 in range(0, c.shape[1], step):
+            psi = model.to_grid(ik, c[:, j0:j0 + step])
+            rho += model.kw[ik] * model.occ * np.sum(np.abs(psi) ** 2, axis=0) / model.Omega
     return rho
 
 

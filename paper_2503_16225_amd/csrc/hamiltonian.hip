@@ -205,6 +205,119 @@ __global__ void __launch_bounds__(512) k_x_density(ColMap cm, int ncols, int cpg
   }
 }
 
+// ------------------------------------------------------------------ split planes
+// Boxes whose (y, z) plane does not fit in LDS run the plane transforms as
+// blocks of lines: the z-lines of a block of i2 values (with the sphere
+// scatter / gather) and the y-lines of a block of i3 values, each block in
+// LDS, with the slab in global memory in between.
+
+// Blocks of lines of a strided array: plane p at base + p * pstride; line l of
+// the plane at l * ls, element j at j * es; block b holds lines
+// [b * BL, min(nlines, (b + 1) * BL)).  Grid (blocks, planes).
+template <typename T, int MAXPTS>
+__global__ void __launch_bounds__(512) k_lines_fft(cplx<T>* __restrict__ base, int64_t pstride, int N, int64_t es,
+                                                   int64_t ls, int nlines, int BL, FftPlan P,
+                                                   const cplx<T>* __restrict__ tw, T sg) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);  // BL x N, line-major
+  cplx<T>* tws = buf + (size_t)BL * N;
+  const int l0 = blockIdx.x * BL, nl = min(BL, nlines - l0);
+  cplx<T>* pl = base + (int64_t)blockIdx.y * pstride + (int64_t)l0 * ls;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) tws[i] = tw[i];
+  // consecutive threads along the unit-stride direction of global memory
+  if (es == 1) {
+    for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
+      const int l = e / N, j = e - l * N;
+      buf[l * N + j] = pl[l * ls + j];
+    }
+  } else {
+    for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
+      const int j = e / nl, l = e - j * nl;
+      buf[l * N + j] = pl[l * ls + j * es];
+    }
+  }
+  __syncthreads();
+  lds_fft<T, MAXPTS>(buf, Lines{N, 1, nl, N, 0}, P, tws, sg);
+  if (es == 1) {
+    for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
+      const int l = e / N, j = e - l * N;
+      pl[l * ls + j] = buf[l * N + j];
+    }
+  } else {
+    for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
+      const int j = e / nl, l = e - j * nl;
+      pl[l * ls + j * es] = buf[l * N + j];
+    }
+  }
+}
+
+// Inverse z-transform of a block of z-lines (i2 in [b*BZ, ...)) of plane s of
+// column c after scattering the sphere coefficients; grid (blocks, ns, ncols).
+template <typename T, int MAXPTS>
+__global__ void __launch_bounds__(512) k_inv_z_sphere(ColMap cm, GridGeom g, int BZ, FftPlan pz,
+                                                      const cplx<T>* __restrict__ twz, const cplx<T>* __restrict__ X,
+                                                      cplx<T>* __restrict__ Tb) {
+  extern __shared__ unsigned char smem_raw[];
+  const int n3 = g.n3, np = g.n2 * g.n3;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);  // BZ x n3
+  cplx<T>* tz = buf + (size_t)BZ * n3;
+  const int s = blockIdx.y, c = blockIdx.z;
+  const int i2a = blockIdx.x * BZ, nl = min(BZ, g.n2 - i2a);
+  int64_t base;
+  const KDesc& k = col_kd(cm, c, base);
+  for (int e = threadIdx.x; e < nl * n3; e += blockDim.x) buf[e] = mk<T>(0, 0);
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) tz[i] = twz[i];
+  __syncthreads();
+  const int g0 = k.plane_start[s], g1 = k.plane_start[s + 1];
+  const cplx<T>* x = X + base;
+  for (int r = g0 + threadIdx.x; r < g1; r += blockDim.x) {
+    const int q = k.box[r] % np;
+    const int i2 = q / n3 - i2a;
+    if (i2 >= 0 && i2 < nl) buf[i2 * n3 + (q - (q / n3) * n3)] = x[r];
+  }
+  __syncthreads();
+  lds_fft<T, MAXPTS>(buf, Lines{n3, 1, nl, n3, 0}, pz, tz, (T)1);
+  cplx<T>* out = Tb + ((int64_t)c * g.ns + s) * g.ps + (int64_t)i2a * n3;
+  for (int e = threadIdx.x; e < nl * n3; e += blockDim.x) out[e] = buf[e];
+}
+
+// Forward z-transform of a block of z-lines, gather of the sphere
+// coefficients of the block, times 1/N_g, plus the kinetic term.
+template <typename T, int MAXPTS>
+__global__ void __launch_bounds__(512) k_fwd_z_sphere(ColMap cm, GridGeom g, int BZ, FftPlan pz,
+                                                      const cplx<T>* __restrict__ twz, const cplx<T>* __restrict__ Tb,
+                                                      const cplx<T>* __restrict__ X, cplx<T>* __restrict__ HX,
+                                                      T scale) {
+  extern __shared__ unsigned char smem_raw[];
+  const int n3 = g.n3, np = g.n2 * g.n3;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* tz = buf + (size_t)BZ * n3;
+  const int s = blockIdx.y, c = blockIdx.z;
+  const int i2a = blockIdx.x * BZ, nl = min(BZ, g.n2 - i2a);
+  int64_t base;
+  const KDesc& k = col_kd(cm, c, base);
+  const int g0 = k.plane_start[s], g1 = k.plane_start[s + 1];
+  if (g1 == g0) return;  // block-uniform
+  const cplx<T>* in = Tb + ((int64_t)c * g.ns + s) * g.ps + (int64_t)i2a * n3;
+  for (int e = threadIdx.x; e < nl * n3; e += blockDim.x) buf[e] = in[e];
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) tz[i] = twz[i];
+  __syncthreads();
+  lds_fft<T, MAXPTS>(buf, Lines{n3, 1, nl, n3, 0}, pz, tz, (T)-1);
+  const T* kin = kin_of<T>(k);
+  const cplx<T>* x = X + base;
+  cplx<T>* y = HX + base;
+  for (int r = g0 + threadIdx.x; r < g1; r += blockDim.x) {
+    const int q = k.box[r] % np;
+    const int i2 = q / n3 - i2a;
+    if (i2 >= 0 && i2 < nl) {
+      const cplx<T> v = buf[i2 * n3 + (q - (q / n3) * n3)];
+      const cplx<T> xv = x[r];
+      const T kr = kin[r];
+      y[r] = mk<T>(v.x * scale + kr * xv.x, v.y * scale + kr * xv.y);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 template <typename T> static size_t plane_lds(const GridGeom& g) {
   return sizeof(cplx<T>) * ((size_t)g.n2 * g.n3 + g.n2 + g.n3);
@@ -217,12 +330,57 @@ static void set_lds(const void* f, size_t bytes) {
 
 static constexpr size_t kLdsMax = 160 * 1024;
 
+// line block size for lines of length N within an LDS budget
+static int line_block(int N, size_t elem, size_t budget) {
+  int bl = 64;
+  while (bl > 1 && (size_t)bl * N * elem + N * elem > budget) bl /= 2;
+  return bl;
+}
+
+template <typename T>
+static void launch_lines(hipStream_t st, cplx<T>* base, int64_t pstride, int nplanes, int N, int64_t es, int64_t ls,
+                         int nlines, const FftPlan& P, const cplx<T>* tw, T sg) {
+  const int BL = line_block(N, sizeof(cplx<T>), 64 * 1024);
+  const size_t lds = sizeof(cplx<T>) * ((size_t)BL * N + N);
+  const int nt = 256;
+  dim3 grid((nlines + BL - 1) / BL, nplanes);
+  switch (pick_maxpts((int64_t)BL * N, nt)) {
+#define CASE(M)                                                                                                 \
+  case M:                                                                                                       \
+    set_lds<T, M>((const void*)k_lines_fft<T, M>, lds);                                                        \
+    hipLaunchKernelGGL((k_lines_fft<T, M>), grid, dim3(nt), lds, st, base, pstride, N, es, ls, nlines, BL, P, tw, \
+                       sg);                                                                                     \
+    break;
+    CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+  }
+  HIPCK(hipGetLastError());
+}
+
+
 template <typename T>
 void launch_inv_yz(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const FftPlan& pz,
                    const FftPlan& py, const cplx<T>* twz, const cplx<T>* twy, const cplx<T>* X, cplx<T>* Tb) {
   if (ncols <= 0) return;
   const size_t lds = plane_lds<T>(g);
-  if (lds > kLdsMax) fail(EAHP_EINVAL, "FFT plane does not fit in LDS");
+  if (lds > kLdsMax) {
+    // split plane: scatter + z-transform per block of z-lines, then the y-lines
+    const int BZ = line_block(g.n3, sizeof(cplx<T>), 64 * 1024);
+    const size_t lz = sizeof(cplx<T>) * ((size_t)BZ * g.n3 + g.n3);
+    dim3 gz((g.n2 + BZ - 1) / BZ, g.ns, ncols);
+    switch (pick_maxpts((int64_t)BZ * g.n3, 256)) {
+#define CASE(M)                                                                                   \
+  case M:                                                                                         \
+    set_lds<T, M>((const void*)k_inv_z_sphere<T, M>, lz);                                        \
+    hipLaunchKernelGGL((k_inv_z_sphere<T, M>), gz, dim3(256), lz, st, cm, g, BZ, pz, twz, X, Tb); \
+    break;
+      CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+    }
+    HIPCK(hipGetLastError());
+    launch_lines<T>(st, Tb, g.ps, ncols * g.ns, g.n2, g.n3, 1, g.n3, py, twy, (T)1);
+    return;
+  }
   const int np = g.n2 * g.n3;
   const int nt = np >= 2048 ? 1024 : (np >= 512 ? 256 : 64);
   dim3 grid(g.ns, ncols);
@@ -244,10 +402,27 @@ void launch_fwd_yz(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& 
                    cplx<T>* HX) {
   if (ncols <= 0) return;
   const size_t lds = plane_lds<T>(g);
-  if (lds > kLdsMax) fail(EAHP_EINVAL, "FFT plane does not fit in LDS");
+  const T scale = (T)(1.0 / ((double)g.n1 * g.n2 * g.n3));
+  if (lds > kLdsMax) {
+    // split plane: the y-lines in place on the slab, then z-transform + gather per block of z-lines
+    launch_lines<T>(st, const_cast<cplx<T>*>(Tb), g.ps, ncols * g.ns, g.n2, g.n3, 1, g.n3, py, twy, (T)-1);
+    const int BZ = line_block(g.n3, sizeof(cplx<T>), 64 * 1024);
+    const size_t lz = sizeof(cplx<T>) * ((size_t)BZ * g.n3 + g.n3);
+    dim3 gz((g.n2 + BZ - 1) / BZ, g.ns, ncols);
+    switch (pick_maxpts((int64_t)BZ * g.n3, 256)) {
+#define CASE(M)                                                                                                \
+  case M:                                                                                                      \
+    set_lds<T, M>((const void*)k_fwd_z_sphere<T, M>, lz);                                                     \
+    hipLaunchKernelGGL((k_fwd_z_sphere<T, M>), gz, dim3(256), lz, st, cm, g, BZ, pz, twz, Tb, X, HX, scale); \
+    break;
+      CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+    }
+    HIPCK(hipGetLastError());
+    return;
+  }
   const int np = g.n2 * g.n3;
   const int nt = np >= 2048 ? 1024 : (np >= 512 ? 256 : 64);
-  const T scale = (T)(1.0 / ((double)g.n1 * g.n2 * g.n3));
   dim3 grid(g.ns, ncols);
   switch (pick_maxpts(np, nt)) {
 #define CASE(M)                                                                                             \
@@ -402,8 +577,12 @@ void launch_box_fft(hipStream_t st, int n1, int n2, int n3, const FftPlan p[3], 
                     double sign) {
   const int np = n2 * n3;
   const size_t lds = sizeof(z64) * ((size_t)np + n2 + n3);
-  if (lds > kLdsMax) fail(EAHP_EINVAL, "FFT plane does not fit in LDS");
   const int nt = np >= 2048 ? 1024 : (np >= 512 ? 256 : 64);
+  if (lds > kLdsMax) {
+    // split plane: z-lines, then y-lines, of every x-plane
+    launch_lines<double>(st, box, np, n1, n3, 1, n3, n2, p[2], tw[2], sign);
+    launch_lines<double>(st, box, np, n1, n2, n3, 1, n3, p[1], tw[1], sign);
+  } else
   switch (pick_maxpts(np, nt)) {
 #define CASE(M)                                                                                                  \
   case M:                                                                                                        \
