@@ -84,6 +84,22 @@ struct Lines {
   int N, es, nlines, ls, lfast;
 };
 
+// Quotient by a runtime divisor without an integer division: a float
+// reciprocal gives the quotient to within one for n < 2^22, then one
+// correction step (all butterfly indices here are far below that).
+struct FDiv {
+  int d;
+  float r;
+};
+__device__ __forceinline__ FDiv fdiv_make(int d) { return FDiv{d, 1.0f / (float)d}; }
+__device__ __forceinline__ int fdiv_q(int n, FDiv f) {
+  int q = (int)((float)n * f.r);
+  const int rem = n - q * f.d;
+  if (rem < 0) --q;
+  else if (rem >= f.d) ++q;
+  return q;
+}
+
 // One self-sorting (Stockham) radix-R stage, in place: every thread loads its
 // butterflies into registers, the block synchronises, then writes them back.
 // Requires nlines * N / R <= MAXBF * blockDim.x (checked by the host).
@@ -93,15 +109,16 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, const Lines L, int span,
   const int total = L.nlines * nb;
   const int step = L.N / (span * R);
   const int nt = blockDim.x;
+  const FDiv fl = fdiv_make(L.lfast ? L.nlines : nb), fs = fdiv_make(span);
   cplx<T> u[MAXBF][R];
 #pragma unroll
   for (int b = 0; b < MAXBF; ++b) {
     const int idx = threadIdx.x + b * nt;
     if (idx < total) {
       int l, i;
-      if (L.lfast) { l = idx % L.nlines; i = idx / L.nlines; }
-      else { l = idx / nb; i = idx - l * nb; }
-      const int k = i % span;
+      if (L.lfast) { i = fdiv_q(idx, fl); l = idx - i * L.nlines; }
+      else { l = fdiv_q(idx, fl); i = idx - l * nb; }
+      const int k = i - fdiv_q(i, fs) * span;
       const cplx<T>* line = buf + l * L.ls;
 #pragma unroll
       for (int j = 0; j < R; ++j) u[b][j] = line[(i + j * nb) * L.es];
@@ -120,10 +137,11 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, const Lines L, int span,
     const int idx = threadIdx.x + b * nt;
     if (idx < total) {
       int l, i;
-      if (L.lfast) { l = idx % L.nlines; i = idx / L.nlines; }
-      else { l = idx / nb; i = idx - l * nb; }
-      const int k = i % span;
-      const int base = (i / span) * span * R + k;
+      if (L.lfast) { i = fdiv_q(idx, fl); l = idx - i * L.nlines; }
+      else { l = fdiv_q(idx, fl); i = idx - l * nb; }
+      const int is = fdiv_q(i, fs);
+      const int k = i - is * span;
+      const int base = is * span * R + k;
       cplx<T>* line = buf + l * L.ls;
 #pragma unroll
       for (int j = 0; j < R; ++j) line[(base + j * span) * L.es] = u[b][j];

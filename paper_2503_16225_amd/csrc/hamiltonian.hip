@@ -65,7 +65,8 @@ __global__ void __launch_bounds__(1024) k_inv_yz(ColMap cm, GridGeom g, FftPlan 
   __syncthreads();
   const int g0 = k.plane_start[s], g1 = k.plane_start[s + 1];
   const cplx<T>* x = X + base;
-  for (int r = g0 + threadIdx.x; r < g1; r += blockDim.x) pl[k.box[r] % np] = x[r];
+  const int pbase = g.plane_i1[s] * np;  // box index of the plane start
+  for (int r = g0 + threadIdx.x; r < g1; r += blockDim.x) pl[k.box[r] - pbase] = x[r];
   __syncthreads();
   lds_fft<T, MAXPTS>(pl, Lines{g.n3, 1, g.n2, g.n3, 0}, pz, tz, (T)1);
   lds_fft<T, MAXPTS>(pl, Lines{g.n2, g.n3, g.n3, 1, 1}, py, ty, (T)1);
@@ -89,6 +90,7 @@ __global__ void __launch_bounds__(1024) k_fwd_yz(ColMap cm, GridGeom g, FftPlan 
   const KDesc& k = col_kd(cm, c, base);
   const int g0 = k.plane_start[s], g1 = k.plane_start[s + 1];
   if (g1 == g0) return;  // block-uniform: this k-point has no plane waves here
+  const int pbase = g.plane_i1[s] * np;
   const cplx<T>* in = Tb + ((int64_t)c * g.ns + s) * g.ps;
   for (int i = threadIdx.x; i < np; i += blockDim.x) pl[i] = in[i];
   for (int i = threadIdx.x; i < g.n3; i += blockDim.x) tz[i] = twz[i];
@@ -100,7 +102,7 @@ __global__ void __launch_bounds__(1024) k_fwd_yz(ColMap cm, GridGeom g, FftPlan 
   const cplx<T>* x = X + base;
   cplx<T>* y = HX + base;
   for (int r = g0 + threadIdx.x; r < g1; r += blockDim.x) {
-    const cplx<T> v = pl[k.box[r] % np];
+    const cplx<T> v = pl[k.box[r] - pbase];
     const cplx<T> xv = x[r];
     const T kr = kin[r];
     y[r] = mk<T>(v.x * scale + kr * xv.x, v.y * scale + kr * xv.y);
@@ -119,9 +121,10 @@ __global__ void __launch_bounds__(512) k_x_local(int ncols, int cb, GridGeom g, 
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(vt + n1 * tile);  // n1
   const int t0 = blockIdx.x * tile;
   const int cnt = min(tile, np - t0);
+  const FDiv fc = fdiv_make(cnt), ft = fdiv_make(tile);
   for (int i = threadIdx.x; i < n1; i += blockDim.x) tw[i] = twx[i];
   for (int e = threadIdx.x; e < n1 * tile; e += blockDim.x) {
-    const int i1 = e / tile, t = e - i1 * tile;
+    const int i1 = fdiv_q(e, ft), t = e - i1 * tile;
     vt[e] = t < cnt ? V[(int64_t)i1 * np + t0 + t] : (T)0;
   }
   const int c0 = blockIdx.y * cb;
@@ -132,7 +135,7 @@ __global__ void __launch_bounds__(512) k_x_local(int ncols, int cb, GridGeom g, 
     __syncthreads();
     const cplx<T>* in = Tb + (int64_t)c * g.ns * g.ps + t0;
     for (int e = threadIdx.x; e < g.ns * cnt; e += blockDim.x) {
-      const int s = e / cnt, t = e - s * cnt;
+      const int s = fdiv_q(e, fc), t = e - s * cnt;
       buf[g.plane_i1[s] * tile + t] = in[(int64_t)s * g.ps + t];
     }
     __syncthreads();
@@ -142,7 +145,7 @@ __global__ void __launch_bounds__(512) k_x_local(int ncols, int cb, GridGeom g, 
     lds_fft<T, MAXPTS>(buf, L, px, tw, (T)-1);
     cplx<T>* out = Tb + (int64_t)c * g.ns * g.ps + t0;
     for (int e = threadIdx.x; e < g.ns * cnt; e += blockDim.x) {
-      const int s = e / cnt, t = e - s * cnt;
+      const int s = fdiv_q(e, fc), t = e - s * cnt;
       out[(int64_t)s * g.ps + t] = buf[g.plane_i1[s] * tile + t];
     }
     __syncthreads();
@@ -161,6 +164,7 @@ __global__ void __launch_bounds__(512) k_x_density(ColMap cm, int ncols, int cpg
   z64* tw = buf + n1 * tile;
   const int t0 = blockIdx.x * tile;
   const int cnt = min(tile, np - t0);
+  const FDiv fc = fdiv_make(cnt), ft = fdiv_make(tile);
   for (int i = threadIdx.x; i < n1; i += blockDim.x) tw[i] = twx[i];
   double acc[MAXPTS];
 #pragma unroll
@@ -177,7 +181,7 @@ __global__ void __launch_bounds__(512) k_x_density(ColMap cm, int ncols, int cpg
     __syncthreads();
     const z64* in = Tb + (int64_t)c * g.ns * g.ps + t0;
     for (int e = threadIdx.x; e < g.ns * cnt; e += blockDim.x) {
-      const int s = e / cnt, t = e - s * cnt;
+      const int s = fdiv_q(e, fc), t = e - s * cnt;
       buf[g.plane_i1[s] * tile + t] = in[(int64_t)s * g.ps + t];
     }
     __syncthreads();
@@ -196,7 +200,7 @@ __global__ void __launch_bounds__(512) k_x_density(ColMap cm, int ncols, int cpg
   for (int r = 0; r < MAXPTS; ++r) {
     const int e = threadIdx.x + r * blockDim.x;
     if (e < n1 * tile) {
-      const int i1 = e / tile, t = e - i1 * tile;
+      const int i1 = fdiv_q(e, ft), t = e - i1 * tile;
       if (t < cnt) {
         double* d = rho + (int64_t)i1 * np + t0 + t;
         *d = accumulate ? *d + acc[r] : acc[r];
@@ -269,11 +273,14 @@ __global__ void __launch_bounds__(512) k_inv_z_sphere(ColMap cm, GridGeom g, int
   for (int i = threadIdx.x; i < n3; i += blockDim.x) tz[i] = twz[i];
   __syncthreads();
   const int g0 = k.plane_start[s], g1 = k.plane_start[s + 1];
+  const int pbase = g.plane_i1[s] * np;
+  const FDiv f3 = fdiv_make(n3);
   const cplx<T>* x = X + base;
   for (int r = g0 + threadIdx.x; r < g1; r += blockDim.x) {
-    const int q = k.box[r] % np;
-    const int i2 = q / n3 - i2a;
-    if (i2 >= 0 && i2 < nl) buf[i2 * n3 + (q - (q / n3) * n3)] = x[r];
+    const int q = k.box[r] - pbase;
+    const int qi = fdiv_q(q, f3);
+    const int i2 = qi - i2a;
+    if (i2 >= 0 && i2 < nl) buf[i2 * n3 + (q - qi * n3)] = x[r];
   }
   __syncthreads();
   lds_fft<T, MAXPTS>(buf, Lines{n3, 1, nl, n3, 0}, pz, tz, (T)1);
@@ -298,6 +305,8 @@ __global__ void __launch_bounds__(512) k_fwd_z_sphere(ColMap cm, GridGeom g, int
   const KDesc& k = col_kd(cm, c, base);
   const int g0 = k.plane_start[s], g1 = k.plane_start[s + 1];
   if (g1 == g0) return;  // block-uniform
+  const int pbase = g.plane_i1[s] * np;
+  const FDiv f3 = fdiv_make(n3);
   const cplx<T>* in = Tb + ((int64_t)c * g.ns + s) * g.ps + (int64_t)i2a * n3;
   for (int e = threadIdx.x; e < nl * n3; e += blockDim.x) buf[e] = in[e];
   for (int i = threadIdx.x; i < n3; i += blockDim.x) tz[i] = twz[i];
@@ -307,10 +316,11 @@ __global__ void __launch_bounds__(512) k_fwd_z_sphere(ColMap cm, GridGeom g, int
   const cplx<T>* x = X + base;
   cplx<T>* y = HX + base;
   for (int r = g0 + threadIdx.x; r < g1; r += blockDim.x) {
-    const int q = k.box[r] % np;
-    const int i2 = q / n3 - i2a;
+    const int q = k.box[r] - pbase;
+    const int qi = fdiv_q(q, f3);
+    const int i2 = qi - i2a;
     if (i2 >= 0 && i2 < nl) {
-      const cplx<T> v = buf[i2 * n3 + (q - (q / n3) * n3)];
+      const cplx<T> v = buf[i2 * n3 + (q - qi * n3)];
       const cplx<T> xv = x[r];
       const T kr = kin[r];
       y[r] = mk<T>(v.x * scale + kr * xv.x, v.y * scale + kr * xv.y);
@@ -448,7 +458,9 @@ void launch_x_local(hipStream_t st, int ncols, const GridGeom& g, const FftPlan&
                     const T* V, cplx<T>* Tb) {
   if (ncols <= 0) return;
   const int np = g.n2 * g.n3;
-  const int tile = x_tile(g.n1, np, sizeof(cplx<T>) + sizeof(T), 72 * 1024);
+  // LDS per work-group bounds how many work-groups share a CU, and with them
+  // how much of the slab traffic is in flight: about 36 KB gives four
+  const int tile = x_tile(g.n1, np, sizeof(cplx<T>) + sizeof(T), 36 * 1024);
   const size_t lds = (size_t)g.n1 * tile * (sizeof(cplx<T>) + sizeof(T)) + g.n1 * sizeof(cplx<T>);
   const int nt = g.n1 * tile >= 2048 ? 512 : 256;
   const int ntiles = (np + tile - 1) / tile;

@@ -97,23 +97,22 @@ __global__ void __launch_bounds__(1024) k_pchol_reg(int n, const z64* __restrict
           else v = cscale<double>(a[m], 1.0 / lbb);
           lcol[k & 1][rr] = v;
           Lg[rr + (int64_t)k * n] = v;
+          if (rr == b) done[b] = 1;  // read only after the barrier below
         }
     }
     __syncthreads();
-    if (rr < n && !done[rr] && rr != b) {
+    if (rr < n && !done[rr]) {
       const z64 li = lcol[k & 1][rr];
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
         const int c = cg + 8 * m;
-        if (c < n && c != b && !done[c]) {
+        if (c < n && !done[c]) {
           const z64 lc = lcol[k & 1][c];
           a[m] = csub<double>(a[m], cmulz(li, mk<double>(lc.x, -lc.y)));
         }
       }
       if (cg == 0) diag[rr] -= li.x * li.x + li.y * li.y;
     }
-    __syncthreads();
-    if (t == 0) done[b] = 1;
     __syncthreads();
   }
   // remaining indices after the pivots, in increasing order
@@ -132,10 +131,14 @@ __global__ void __launch_bounds__(1024) k_pchol_reg(int n, const z64* __restrict
 #pragma unroll
   for (int m = 0; m < 16; ++m) acc[m] = mk<double>(0.0, 0.0);
   z64* xrow = &lcol[0][0];  // reused: 2 x kPcMax
+  // Lt[rr][arow] is loaded one row ahead so that its latency overlaps the barrier
+  z64 lnext = (rr < r) ? Lg[pv[rr]] : mk<double>(0.0, 0.0);
   for (int arow = 0; arow < r; ++arow) {
     z64* xr = xrow + (arow & 1) * kPcMax;
+    const z64 l = lnext;
+    if (rr < r && arow + 1 < r) lnext = Lg[pv[rr] + (int64_t)(arow + 1) * n];
     if (rr == arow) {
-      const double inv = 1.0 / Lg[pv[arow] + (int64_t)arow * n].x;
+      const double inv = 1.0 / l.x;
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
         const int j = cg + 8 * m;
@@ -148,7 +151,6 @@ __global__ void __launch_bounds__(1024) k_pchol_reg(int n, const z64* __restrict
     }
     __syncthreads();
     if (rr > arow && rr < r) {
-      const z64 l = Lg[pv[rr] + (int64_t)arow * n];
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
         const int j = cg + 8 * m;
