@@ -171,6 +171,31 @@ template <typename T> __device__ __forceinline__ T warp_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+// Cross-lane moves of a double by DPP (both 32-bit halves with the same control).
+template <int kCtrl> __device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Value of lane l (wave-uniform l) in every lane.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Sum over the 64 lanes of a full wave, the same value in every lane: quad
+// swaps and row rotations leave each 16-lane row's sum in all its lanes, the
+// four row sums are then read out and added in a fixed order.
+__device__ __forceinline__ double wave_allsum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x124>(v);  // row_ror:4
+  v += dpp_f64<0x128>(v);  // row_ror:8
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 // Block-wide sum (blockDim.x multiple of 64, <= 1024); result valid in thread 0.
 template <typename T> __device__ __forceinline__ T block_sum(T v, T* sh /* >= 16 */) {
   v = warp_sum(v);

@@ -2,13 +2,16 @@
 // with A (q x q) and Sigma (p x p) Hermitian.  In the eigenbasis of
 // Sigma = U diag(s) U^H the columns decouple into (A - s_l I) y~_l = c~_l.
 // A is reduced once to Hermitian tridiagonal form A = Q T Q^H with Householder
-// reflectors (a cooperative kernel over many work-groups, one grid barrier
-// pair per column), after which every shifted system is a tridiagonal solve:
+// reflectors (a cooperative kernel over several work-groups, one grid barrier
+// per column), after which every shifted system is a tridiagonal solve:
 //
 //   y~_l = Q (T - s_l I)^-1 Q^H c~_l.
 //
 // The result is the same Galerkin solution as with a full eigendecomposition
 // of A (it is unique), at the cost of one reduction of A per FOM iteration.
+// Up to q = 512 the reduction keeps A in registers and synchronises through a
+// counter barrier; larger q use an L2-resident variant with the cooperative
+// groups barrier.
 #include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
@@ -184,6 +187,328 @@ __global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, do
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident reduction for q <= 64 NS.  Every wave holds two whole
+// columns of A (row i in lane i % 64, slot i / 64) and its own copy of the
+// reflector v, of w and of the next column, so every inner product is a
+// wave reduction and the only exchange between waves is the vector p of each
+// step: its entries (one per owned column) and the next column to be reduced
+// go to global memory, followed by one grid barrier (a counter in global
+// memory; the waits are bounded and a timeout is reported through *err).
+namespace {
+constexpr int kTrWaves = 8;  // waves per work-group
+constexpr int kTrCols = 2;   // columns per wave
+constexpr int kTrSpin = 1 << 20;
+
+// Row r (wave-uniform) of a register-distributed vector, in every lane.  The
+// lane read happens inside the branch of the matching slot, so that no slot
+// is selected by a computed index (which would move the array to scratch).
+template <int NS> __device__ __forceinline__ z64 pick_row(const z64 (&x)[NS], int r) {
+  z64 t = mk<double>(0.0, 0.0);
+  const int sl = r >> 6, l = r & 63;
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+    if (sl == s) t = mk<double>(readlane_f64(x[s].x, l), readlane_f64(x[s].y, l));
+  return t;
+}
+
+// Householder vector from x (rows >= r0, zero elsewhere): x[r0] -= alpha.
+template <int NS> __device__ __forceinline__ void reflector_reg(z64 (&x)[NS], int r0, z64& alpha, double& b) {
+  double s2 = 0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) s2 += x[s].x * x[s].x + x[s].y * x[s].y;
+  s2 = wave_allsum(s2);
+  const z64 x0 = pick_row<NS>(x, r0);
+  const double xn = sqrt(s2);
+  const double a0 = sqrt(x0.x * x0.x + x0.y * x0.y);
+  if (a0 > 0) alpha = mk<double>(-x0.x / a0 * xn, -x0.y / a0 * xn);
+  else alpha = mk<double>(-xn, 0.0);
+  const z64 v0 = csub<double>(x0, alpha);
+  const double vv = (s2 - a0 * a0) + (v0.x * v0.x + v0.y * v0.y);
+  b = vv > 0 ? 2.0 / vv : 0.0;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+    if (lane + 64 * s == r0) x[s] = v0;
+}
+
+// Barrier over the grid; false when the wait timed out (then every later
+// barrier of the launch times out as well and the kernel ends).
+__device__ __forceinline__ bool grid_barrier(unsigned* ctr, unsigned target, int* err, int* sbad) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins > kTrSpin) {
+        *sbad = 1;
+        *reinterpret_cast<volatile int*>(err) = 1;
+        break;
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+  return *sbad == 0;
+}
+}  // namespace
+
+template <int NS>
+__global__ void __launch_bounds__(64 * kTrWaves) k_tridiag_reg(int q, const z64* __restrict__ A, int64_t lda,
+                                                               double* d, z64* e, z64* Vh, int64_t ldv, double* beta,
+                                                               z64* Pb, z64* Cb, unsigned* ctr, int* err) {
+  __shared__ int sbad;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int G = gridDim.x;
+  const int nwt = G * kTrWaves;
+  const int gw = blockIdx.x * kTrWaves + wv;
+  if (threadIdx.x == 0) sbad = 0;
+  int col[kTrCols];
+  z64 a[kTrCols][NS];
+#pragma unroll
+  for (int j = 0; j < kTrCols; ++j) {
+    col[j] = gw + j * nwt;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int i = lane + 64 * s;
+      a[j][s] = (col[j] < q && i < q) ? A[i + (int64_t)col[j] * lda] : mk<double>(0.0, 0.0);
+    }
+  }
+  // reflector 0 from column 0 (rows 1..q-1)
+  z64 v[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = lane + 64 * s;
+    v[s] = (i >= 1 && i < q) ? A[i] : mk<double>(0.0, 0.0);
+  }
+  z64 alpha;
+  double b;
+  reflector_reg<NS>(v, 1, alpha, b);
+  if (gw == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (lane + 64 * s < q) Vh[lane + 64 * s] = v[s];
+    if (lane == 0) {
+      d[0] = A[0].x;
+      e[0] = alpha;
+      beta[0] = b;
+    }
+  }
+  // p_0 entries of the owned columns c >= 1
+#pragma unroll
+  for (int j = 0; j < kTrCols; ++j) {
+    if (col[j] >= 1 && col[j] < q) {
+      double sx = 0, sy = 0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        sx += a[j][s].x * v[s].x + a[j][s].y * v[s].y;
+        sy += a[j][s].x * v[s].y - a[j][s].y * v[s].x;
+      }
+      sx = wave_allsum(sx);
+      sy = wave_allsum(sy);
+      if (lane == 0) Pb[col[j]] = mk<double>(b * sx, b * sy);
+    }
+  }
+  if (!grid_barrier(ctr, (unsigned)G, err, &sbad)) return;
+  for (int k = 0; k + 1 < q; ++k) {
+    const z64* P = Pb + (int64_t)(k & 1) * q;
+    // w = p - (beta/2)(v^H p) v and the column k+1 as updated through step k-1
+    z64 w[NS], cc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int i = lane + 64 * s;
+      const bool in = i >= k + 1 && i < q;
+      w[s] = in ? P[i] : mk<double>(0.0, 0.0);
+      cc[s] = in ? (k == 0 ? A[i + lda] : Cb[(int64_t)(k & 1) * q + i]) : mk<double>(0.0, 0.0);
+    }
+    double kx = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) kx += v[s].x * w[s].x + v[s].y * w[s].y;
+    const double K = 0.5 * b * wave_allsum(kx);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) w[s] = mk<double>(w[s].x - K * v[s].x, w[s].y - K * v[s].y);
+    const z64 v1 = pick_row<NS>(v, k + 1), w1 = pick_row<NS>(w, k + 1), c1 = pick_row<NS>(cc, k + 1);
+    const double dk1 = c1.x - 2.0 * (v1.x * w1.x + v1.y * w1.y);
+    if (k + 2 == q) {
+      if (gw == 0 && lane == 0) d[k + 1] = dk1;
+      break;
+    }
+    // next reflector from x = A'[k+2:, k+1] = c - v conj(w1) - w conj(v1)
+    z64 x[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int i = lane + 64 * s;
+      if (i >= k + 2) {
+        const double ux = v[s].x * w1.x + v[s].y * w1.y + w[s].x * v1.x + w[s].y * v1.y;
+        const double uy = v[s].y * w1.x - v[s].x * w1.y + w[s].y * v1.x - w[s].x * v1.y;
+        x[s] = mk<double>(cc[s].x - ux, cc[s].y - uy);
+      } else {
+        x[s] = mk<double>(0.0, 0.0);
+      }
+    }
+    z64 an;
+    double bn;
+    reflector_reg<NS>(x, k + 2, an, bn);
+    // rank-2 update of the owned columns c >= k+2 and their entries of p_{k+1}
+    z64* Pn = Pb + (int64_t)((k + 1) & 1) * q;
+#pragma unroll
+    for (int j = 0; j < kTrCols; ++j) {
+      const int c = col[j];
+      if (c >= k + 2 && c < q) {
+        const z64 vc = pick_row<NS>(v, c), wc = pick_row<NS>(w, c);
+        double sx = 0, sy = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const double ux = v[s].x * wc.x + v[s].y * wc.y + w[s].x * vc.x + w[s].y * vc.y;
+          const double uy = v[s].y * wc.x - v[s].x * wc.y + w[s].y * vc.x - w[s].x * vc.y;
+          a[j][s] = mk<double>(a[j][s].x - ux, a[j][s].y - uy);
+          sx += a[j][s].x * x[s].x + a[j][s].y * x[s].y;
+          sy += a[j][s].x * x[s].y - a[j][s].y * x[s].x;
+        }
+        sx = wave_allsum(sx);
+        sy = wave_allsum(sy);
+        if (lane == 0) Pn[c] = mk<double>(bn * sx, bn * sy);
+        if (c == k + 2) {
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const int i = lane + 64 * s;
+            if (i >= k + 2 && i < q) Cb[(int64_t)((k + 1) & 1) * q + i] = a[j][s];
+          }
+        }
+      }
+    }
+    if (gw == 0) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (lane + 64 * s < q) Vh[lane + 64 * s + (int64_t)(k + 1) * ldv] = x[s];
+      if (lane == 0) {
+        d[k + 1] = dk1;
+        e[k + 1] = an;
+        beta[k + 1] = bn;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) v[s] = x[s];
+    b = bn;
+    if (!grid_barrier(ctr, (unsigned)(k + 2) * (unsigned)G, err, &sbad)) return;
+  }
+}
+
+// H_k b = b - beta_k v_k (v_k^H b) for k = 0..q-2 (forward: Q^H B) or
+// k = q-2..0 (backward: Q B), one wave per column of B held in registers;
+// the reflector of the next step is loaded while the current one is applied.
+template <int NS>
+__global__ void __launch_bounds__(256) k_apply_refl_reg(int q, const z64* __restrict__ Vh, int64_t ldv,
+                                                        const double* __restrict__ beta, z64* B, int64_t ldb,
+                                                        int ncols, int forward) {
+  const int lane = threadIdx.x & 63;
+  const int l = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (l >= ncols || q < 2) return;
+  z64* bc = B + (int64_t)l * ldb;
+  z64 x[NS], vn[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = lane + 64 * s;
+    x[s] = i < q ? bc[i] : mk<double>(0.0, 0.0);
+  }
+  const int nr = q - 1;
+  auto load = [&](int k) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int i = lane + 64 * s;
+      vn[s] = (i > k && i < q) ? Vh[i + (int64_t)k * ldv] : mk<double>(0.0, 0.0);
+    }
+  };
+  load(forward ? 0 : nr - 1);
+  for (int t = 0; t < nr; ++t) {
+    const int k = forward ? t : nr - 1 - t;
+    z64 v[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) v[s] = vn[s];
+    if (t + 1 < nr) load(forward ? k + 1 : k - 1);
+    double sx = 0, sy = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      sx += v[s].x * x[s].x + v[s].y * x[s].y;
+      sy += v[s].x * x[s].y - v[s].y * x[s].x;
+    }
+    const double bk = beta[k];
+    const z64 f = mk<double>(bk * wave_allsum(sx), bk * wave_allsum(sy));
+#pragma unroll
+    for (int s = 0; s < NS; ++s) x[s] = csub<double>(x[s], cmul<double>(v[s], f));
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = lane + 64 * s;
+    if (i < q) bc[i] = x[s];
+  }
+}
+
+// (T - s_l I) y = b for every column l, Gaussian elimination with partial
+// pivoting between adjacent rows, one thread per column.  The running row and
+// right-hand side stay in registers; the finished rows (diagonal, first and
+// second super-diagonal) go to W with the columns interleaved (coalesced).
+__global__ void __launch_bounds__(64) k_trisolve_reg(int q, int ncols, const double* __restrict__ d,
+                                                     const z64* __restrict__ e, const double* __restrict__ sh,
+                                                     z64* B, int64_t ldb, z64* W) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= ncols) return;
+  z64* b = B + (int64_t)l * ldb;
+  auto row = [&](int i, int c) -> z64& { return W[((int64_t)3 * i + c) * ncols + l]; };
+  auto rdiv = [](z64 a, z64 c) {
+    const double r = 1.0 / (c.x * c.x + c.y * c.y);
+    return mk<double>((a.x * c.x + a.y * c.y) * r, (a.y * c.x - a.x * c.y) * r);
+  };
+  const double s = sh[l];
+  z64 Dc = mk<double>(d[0] - s, 0.0);
+  z64 Uc = q > 1 ? mk<double>(e[0].x, -e[0].y) : mk<double>(0.0, 0.0);
+  z64 bc = b[0];
+  for (int i = 0; i + 1 < q; ++i) {
+    const z64 L = e[i];
+    const z64 Dn = mk<double>(d[i + 1] - s, 0.0);
+    const z64 Un = i + 2 < q ? mk<double>(e[i + 1].x, -e[i + 1].y) : mk<double>(0.0, 0.0);
+    const z64 bn = b[i + 1];
+    if (sqrt(Dc.x * Dc.x + Dc.y * Dc.y) >= sqrt(L.x * L.x + L.y * L.y)) {
+      const z64 f = rdiv(L, Dc);
+      row(i, 0) = Dc;
+      row(i, 1) = Uc;
+      row(i, 2) = mk<double>(0.0, 0.0);
+      b[i] = bc;
+      Dc = csub<double>(Dn, cmul<double>(f, Uc));
+      Uc = Un;
+      bc = csub<double>(bn, cmul<double>(f, bc));
+    } else {
+      const z64 f = rdiv(Dc, L);
+      row(i, 0) = L;
+      row(i, 1) = Dn;
+      row(i, 2) = Un;
+      b[i] = bn;
+      const z64 Dnew = csub<double>(Uc, cmul<double>(f, Dn));
+      Uc = mk<double>(-(f.x * Un.x - f.y * Un.y), -(f.x * Un.y + f.y * Un.x));
+      bc = csub<double>(bc, cmul<double>(f, bn));
+      Dc = Dnew;
+    }
+  }
+  // back substitution, x_{i+1} and x_{i+2} carried in registers
+  z64 x1 = rdiv(bc, Dc), x2 = mk<double>(0.0, 0.0);
+  b[q - 1] = x1;
+  for (int i = q - 2; i >= 0; --i) {
+    z64 r = csub<double>(b[i], cmul<double>(row(i, 1), x1));
+    r = csub<double>(r, cmul<double>(row(i, 2), x2));
+    const z64 xi = rdiv(r, row(i, 0));
+    b[i] = xi;
+    x2 = x1;
+    x1 = xi;
+  }
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 // Apply the reflectors to the columns of B (q x ncols, ld ldb), one work-group
 // per column: forward (Q^H B = H_{q-2} ... H_0 B) or backward (Q B).
 __global__ void __launch_bounds__(256) k_apply_refl(int q, const z64* Vh, int64_t ldv, const double* beta, z64* B,
@@ -219,101 +544,85 @@ __device__ __forceinline__ z64 cdiv_(z64 a, z64 b) {
   return mk<double>((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
 }
 
-// (T - s_l I) z = b for every column l (in place in B), Gaussian elimination
-// with partial pivoting between adjacent rows (one fill-in super-diagonal).
-// T[k][k] = d_k, T[k+1][k] = e_k, T[k][k+1] = conj(e_k).  W: 3 q scratch per column.
-__global__ void k_trisolve(int q, int ncols, const double* d, const z64* e, const double* s, z64* B, int64_t ldb,
-                           z64* W) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= ncols) return;
-  z64* b = B + (int64_t)l * ldb;
-  z64* D = W + (int64_t)l * 3 * q;
-  z64* U = D + q;
-  z64* L = U + q;  // sub-diagonal, later the fill-in second super-diagonal
-  const double sl = s[l];
-  for (int i = 0; i < q; ++i) {
-    D[i] = mk<double>(d[i] - sl, 0.0);
-    if (i + 1 < q) {
-      L[i] = e[i];
-      U[i] = mk<double>(e[i].x, -e[i].y);
-    }
-  }
-  for (int i = 0; i + 1 < q; ++i) {
-    if (cabs_(D[i]) >= cabs_(L[i])) {
-      const z64 f = cdiv_(L[i], D[i]);
-      D[i + 1] = csub<double>(D[i + 1], cmul<double>(f, U[i]));
-      b[i + 1] = csub<double>(b[i + 1], cmul<double>(f, b[i]));
-      L[i] = mk<double>(0, 0);
-    } else {
-      const z64 f = cdiv_(D[i], L[i]);
-      D[i] = L[i];
-      const z64 t = D[i + 1];
-      D[i + 1] = csub<double>(U[i], cmul<double>(f, t));
-      if (i + 2 < q) {
-        L[i] = U[i + 1];
-        U[i + 1] = mk<double>(-(f.x * L[i].x - f.y * L[i].y), -(f.x * L[i].y + f.y * L[i].x));
-      } else {
-        L[i] = mk<double>(0, 0);
-      }
-      U[i] = t;
-      const z64 bi = b[i];
-      b[i] = b[i + 1];
-      b[i + 1] = csub<double>(bi, cmul<double>(f, b[i]));
-    }
-  }
-  b[q - 1] = cdiv_(b[q - 1], D[q - 1]);
-  if (q >= 2) b[q - 2] = cdiv_(csub<double>(b[q - 2], cmul<double>(U[q - 2], b[q - 1])), D[q - 2]);
-  for (int i = q - 3; i >= 0; --i) {
-    z64 r = csub<double>(b[i], cmul<double>(U[i], b[i + 1]));
-    r = csub<double>(r, cmul<double>(L[i], b[i + 2]));
-    b[i] = cdiv_(r, D[i]);
-  }
-}
-
 __global__ void k_set_d0(const z64* A, double* d) { d[0] = A[0].x; }
 
-// Y~ (q x p, ld q) := solution of (A - s_l) y~_l = C~[:, l]; A (q x q, ld lda) is
-// destroyed.  ws must hold q*q + q*3*p + 4*q complex values.
+// Y~ (q x p, ld q) := solution of (A - s_l) y~_l = C~[:, l]; A (q x q, ld lda)
+// may be destroyed.  ws grows to what the chosen kernels need.
+namespace {
+template <int NS>
+void tridiag_reg_launch(hipStream_t st, int q, int p, z64* A, int64_t lda, double* dd, z64* e, z64* Vh, double* bt,
+                        z64* P, z64* Cb, unsigned* ctr, z64* Yt, int* herr) {
+  const int G = (q + kTrWaves * kTrCols - 1) / (kTrWaves * kTrCols);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ctr, 1);
+  int qq = q;
+  int64_t la = lda, lv = q;
+  void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P, &Cb, &ctr, &herr};
+  *reinterpret_cast<volatile int*>(herr) = 0;
+  HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag_reg<NS>, dim3(G), dim3(64 * kTrWaves), args, 0, st));
+  HIPCK(hipStreamSynchronize(st));
+  if (*reinterpret_cast<volatile int*>(herr) != 0) fail(EAHP_EDEVICE, "grid barrier of the tridiagonal reduction timed out");
+  hipLaunchKernelGGL(k_apply_refl_reg<NS>, dim3((p + 3) / 4), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q,
+                     p, 1);
+}
+}  // namespace
+
 void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws) {
   if (q <= 0 || p <= 0) return;
   if (q > 3200) fail(EAHP_EINVAL, "projected FOM system larger than 3200");
-  const size_t need = sizeof(z64) * ((size_t)q * q + (size_t)3 * q * p + 4 * (size_t)q) + sizeof(double) * 2 * q + 256;
-  // P is double-buffered: 2 q entries after e (q) fit in the 4 q tail
+  // Vh (q x q), W (3 q p), e (q), P (2 q), Cb (2 q), d (q), beta (q), counter
+  const size_t need =
+      sizeof(z64) * ((size_t)q * q + (size_t)3 * q * p + 5 * (size_t)q) + sizeof(double) * 2 * q + 512;
   ws.ensure(need);
   z64* Vh = ws.as<z64>();
   z64* W = Vh + (size_t)q * q;
   z64* e = W + (size_t)3 * q * p;
   z64* P = e + q;
-  double* dd = reinterpret_cast<double*>(P + 2 * q);
+  z64* Cb = P + 2 * q;
+  double* dd = reinterpret_cast<double*>(Cb + 2 * q);
   double* bt = dd + q;
+  unsigned* ctr = reinterpret_cast<unsigned*>(bt + q + 8);
+  const bool reg = q >= 2 && q <= 512;
   if (q >= 2) {
-    const size_t lds = sizeof(z64) * 3 * (size_t)q;
-    HIPCK(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    int per_cu = 0;
-    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tridiag, 1024, lds));
-    int dev = 0, ncu = 0;
-    HIPCK(hipGetDevice(&dev));
-    HIPCK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    // one work-group per 16 columns: enough waves for the column loops, few work-groups per barrier
-    const int G = std::min({std::max(1, per_cu) * ncu, ncu, std::max(1, (q + 15) / 16)});
-    int qq = q;
-    int64_t la = lda, lv = q;
-    void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P};
-    {
-      // grid-synchronising kernels of concurrent streams (the serving loop)
-      // could each hold part of the CUs while waiting for the rest of their
-      // grid: one at a time per process, waited for before the next
-      static std::mutex coop;
-      std::lock_guard<std::mutex> lk(coop);
+    // grid-synchronising kernels of concurrent streams (the serving loop)
+    // could each hold part of the CUs while waiting for the rest of their
+    // grid: one at a time per process, waited for before the next
+    static std::mutex coop;
+    static int* herr = nullptr;
+    std::lock_guard<std::mutex> lk(coop);
+    if (reg) {
+      if (!herr) HIPCK(hipHostMalloc((void**)&herr, 64, hipHostMallocDefault));
+      if (q <= 128) tridiag_reg_launch<2>(st, q, p, A, lda, dd, e, Vh, bt, P, Cb, ctr, Yt, herr);
+      else if (q <= 256) tridiag_reg_launch<4>(st, q, p, A, lda, dd, e, Vh, bt, P, Cb, ctr, Yt, herr);
+      else tridiag_reg_launch<8>(st, q, p, A, lda, dd, e, Vh, bt, P, Cb, ctr, Yt, herr);
+    } else {
+      const size_t lds = sizeof(z64) * 3 * (size_t)q;
+      HIPCK(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      int per_cu = 0;
+      HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tridiag, 1024, lds));
+      int dev = 0, ncu = 0;
+      HIPCK(hipGetDevice(&dev));
+      HIPCK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      // one work-group per 16 columns: enough waves for the column loops, few work-groups per barrier
+      const int G = std::min({std::max(1, per_cu) * ncu, ncu, std::max(1, (q + 15) / 16)});
+      int qq = q;
+      int64_t la = lda, lv = q;
+      void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P};
       HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(G), dim3(1024), args, lds, st));
       HIPCK(hipStreamSynchronize(st));
+      hipLaunchKernelGGL(k_apply_refl, dim3(p), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, 1);
     }
-    hipLaunchKernelGGL(k_apply_refl, dim3(p), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, 1);
   } else {
     hipLaunchKernelGGL(k_set_d0, dim3(1), dim3(1), 0, st, A, dd);
   }
-  hipLaunchKernelGGL(k_trisolve, dim3((p + 63) / 64), dim3(64), 0, st, q, p, dd, e, s, Yt, (int64_t)q, W);
-  if (q >= 2) hipLaunchKernelGGL(k_apply_refl, dim3(p), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, 0);
+  hipLaunchKernelGGL(k_trisolve_reg, dim3((p + 63) / 64), dim3(64), 0, st, q, p, dd, e, s, Yt, (int64_t)q, W);
+  if (reg) {
+    const dim3 g((p + 3) / 4), b(256);
+    if (q <= 128) hipLaunchKernelGGL(k_apply_refl_reg<2>, g, b, 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, p, 0);
+    else if (q <= 256) hipLaunchKernelGGL(k_apply_refl_reg<4>, g, b, 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, p, 0);
+    else hipLaunchKernelGGL(k_apply_refl_reg<8>, g, b, 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, p, 0);
+  } else if (q >= 2) {
+    hipLaunchKernelGGL(k_apply_refl, dim3(p), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, 0);
+  }
   HIPCK(hipGetLastError());
 }
 
