@@ -251,10 +251,112 @@ __global__ void __launch_bounds__(1024) k_inverse(int n, z64* Ab, int64_t lda, i
   if (tid == 0 && info) info[blockIdx.x] = bad;
 }
 
+// In-place Gauss-Jordan (the sweep at each pivot) for n <= 128 with the matrix
+// in registers: thread t owns row t/8 and the 16 columns congruent to t mod 8.
+// Column k is eliminated at step k with the unused row of largest modulus in
+// it (ties: the smaller row index); rows are exchanged only logically, so the
+// swept matrix B holds the inverse as inv(A)[pos(r)][piv(j)] = B[r][j], with
+// piv(k) the pivot row of step k and pos its inverse.  Per step: the pivot
+// candidates of each wave (a shuffle reduction over its 8 rows) meet in LDS,
+// every thread picks the winner itself, the pivot row is scaled into LDS and
+// every other row takes its rank-1 update.
+__global__ void __launch_bounds__(1024) k_inverse_reg(int n, z64* Ab, int64_t lda, int64_t sA, int* info) {
+  __shared__ double cv[16];
+  __shared__ int ci[16];
+  __shared__ z64 cz[16];
+  __shared__ z64 prow[128];
+  __shared__ int prk[128], pos[128];
+  z64* A = Ab + blockIdx.x * sA;
+  const int t = threadIdx.x, rr = t >> 3, cg = t & 7, lane = t & 63, wv = t >> 6;
+  const int ncg = n - cg;  // column cg + 8 m exists while 8 m < ncg
+  d16 ar, ai;              // row rr, columns cg + 8 m (real and imaginary parts)
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const z64 v = (rr < n && 8 * m < ncg) ? A[rr + (int64_t)(cg + 8 * m) * lda] : mk<double>(0.0, 0.0);
+    ar[m] = v.x;
+    ai[m] = v.y;
+  }
+  bool used = rr >= n;
+  int bad = 0;
+  for (int k = 0; k < n; ++k) {
+    const int km = __builtin_amdgcn_readfirstlane(k >> 3);
+    const bool mine = cg == (k & 7);  // this lane holds column k (in slot km)
+    const z64 ak = mk<double>(ar[km], ai[km]);
+    // candidate of this wave: the largest |a_rk| over its unused rows
+    double val = (mine && !used) ? ak.x * ak.x + ak.y * ak.y : -1.0;
+    int row = (mine && !used) ? rr : 1 << 20;
+    wave_argmax(val, row);
+    if (lane == 0) {
+      cv[wv] = val;
+      ci[wv] = row;
+    }
+    if (mine && rr == row) cz[wv] = ak;
+    // entry of column k in this thread's row, from the lane of the row that holds it
+    const int src = (lane & ~7) | (k & 7);
+    const z64 f = mk<double>(__shfl(ak.x, src, 64), __shfl(ak.y, src, 64));
+    __syncthreads();
+    double best = lane < 16 ? cv[lane] : -2.0;
+    int pr = lane < 16 ? ci[lane] : 1 << 20;
+    row16_argmax(best, pr);
+    pr = __builtin_amdgcn_readlane(pr, 0);
+    const z64 pz = cz[pr >> 3];
+    const double den = pz.x * pz.x + pz.y * pz.y;
+    if (!(den > 0)) bad = 1;
+    const z64 pinv = den > 0 ? mk<double>(pz.x / den, -pz.y / den) : mk<double>(0.0, 0.0);
+    const bool piv = rr == pr;
+    if (piv) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        prow[cg + 8 * m] = mk<double>(ar[m] * pinv.x - ai[m] * pinv.y, ar[m] * pinv.y + ai[m] * pinv.x);
+        ar[m] = 0.0;
+        ai[m] = 0.0;
+      }
+      if (mine) prow[k] = pinv;
+      used = true;
+      if (cg == 0) {
+        prk[k] = pr;
+        pos[pr] = k;
+      }
+    }
+    __syncthreads();
+    // every row: a_rj + g prow_j with g = -a_rk (1 on the pivot row, whose a is
+    // zeroed above); then column k of the other rows becomes -a_rk pinv
+    const z64 g = piv ? mk<double>(1.0, 0.0) : mk<double>(-f.x, -f.y);
+#pragma unroll
+    for (int mb = 0; mb < 16; mb += 4) {
+      z64 pw[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pw[u] = prow[cg + 8 * (mb + u)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int m = mb + u;
+        ar[m] = fma(g.x, pw[u].x, fma(-g.y, pw[u].y, ar[m]));
+        ai[m] = fma(g.x, pw[u].y, fma(g.y, pw[u].x, ai[m]));
+      }
+    }
+    {
+      const bool fix = mine && !piv;
+      const double nr = fix ? -(f.x * pinv.x - f.y * pinv.y) : ar[km];
+      const double ni = fix ? -(f.x * pinv.y + f.y * pinv.x) : ai[km];
+      ar[km] = nr;
+      ai[km] = ni;
+    }
+  }
+  __syncthreads();
+  if (rr < n) {
+    const int r = pos[rr];
+#pragma unroll
+    for (int m = 0; m < 16; ++m)
+      if (8 * m < ncg) A[r + (int64_t)prk[cg + 8 * m] * lda] = mk<double>(ar[m], ai[m]);
+  }
+  if (t == 0 && info) info[blockIdx.x] = bad;
+}
+
 void inverse(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, z64* work, int batch, int* info) {
   if (n <= 0 || batch <= 0) return;
   if (n > 1024) fail(EAHP_EINVAL, "inverse: n > 1024");
-  hipLaunchKernelGGL(k_inverse, dim3(batch), dim3(1024), 0, st, n, A, lda, sA, work, info);
+  if (n <= 128) hipLaunchKernelGGL(k_inverse_reg, dim3(batch), dim3(1024), 0, st, n, A, lda, sA, info);
+  else hipLaunchKernelGGL(k_inverse, dim3(batch), dim3(1024), 0, st, n, A, lda, sA, work, info);
   HIPCK(hipGetLastError());
 }
 

@@ -196,6 +196,38 @@ __device__ __forceinline__ double wave_allsum(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// Sixteen doubles held in registers; an element picked by a wave-uniform index
+// compiles to indexed register moves (no scratch, no select chains).
+typedef double d16 __attribute__((ext_vector_type(16)));
+
+template <int kCtrl> __device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xF, 0xF, true);
+}
+// (v, i) pairs: the larger v wins, ties go to the smaller i.
+__device__ __forceinline__ void argmax_merge(double& v, int& i, double ov, int oi) {
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+// Arg-max over each 16-lane row of a full wave, left in every lane of the row.
+__device__ __forceinline__ void row16_argmax(double& v, int& i) {
+  argmax_merge(v, i, dpp_f64<0xB1>(v), dpp_i32<0xB1>(i));
+  argmax_merge(v, i, dpp_f64<0x4E>(v), dpp_i32<0x4E>(i));
+  argmax_merge(v, i, dpp_f64<0x124>(v), dpp_i32<0x124>(i));
+  argmax_merge(v, i, dpp_f64<0x128>(v), dpp_i32<0x128>(i));
+}
+// Arg-max over a full wave, the same (v, i) in every lane.
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  row16_argmax(v, i);
+  double bv = readlane_f64(v, 0);
+  int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+  for (int r = 16; r < 64; r += 16) argmax_merge(bv, bi, readlane_f64(v, r), __builtin_amdgcn_readlane(i, r));
+  v = bv;
+  i = bi;
+}
+
 // Block-wide sum (blockDim.x multiple of 64, <= 1024); result valid in thread 0.
 template <typename T> __device__ __forceinline__ T block_sum(T v, T* sh /* >= 16 */) {
   v = warp_sum(v);

@@ -7,7 +7,9 @@
 //
 // One work-group of 1024 threads, n <= 128, the matrix in registers (thread t
 // owns row t/8 and the 16 columns congruent to t mod 8).  Pivoting is logical
-// (rows and columns are marked done instead of being exchanged).  The
+// (rows and columns are marked done instead of being exchanged); the pivot
+// search is a shuffle reduction in every wave followed by a scan of the 16
+// wave candidates in every thread, so a step takes two barriers.  The
 // triangular inverse runs row by row in pivot order with the 16 columns of
 // each row accumulated in the same registers.
 #include "devcommon.h"
@@ -23,16 +25,15 @@ __device__ __forceinline__ z64 cmulz(z64 a, z64 b) { return mk<double>(a.x * b.x
 __global__ void __launch_bounds__(1024) k_pchol_reg(int n, const z64* __restrict__ G, int64_t ldg, double tol,
                                                     int* __restrict__ piv, int* __restrict__ rank_out,
                                                     z64* __restrict__ U, int64_t ldu, z64* __restrict__ Lg) {
-  __shared__ double diag[kPcMax];
+  __shared__ double cv[16];
+  __shared__ int ci[16];
   __shared__ int done[kPcMax];
   __shared__ int pv[kPcMax];
   __shared__ z64 lcol[2][kPcMax];
-  __shared__ int sb[2];
-  __shared__ int srank;
-  __shared__ double sd0;
   const int t = threadIdx.x;
-  const int rr = t >> 3, cg = t & 7;
-  z64 a[16];
+  if (t < 2 * kPcMax) lcol[t >> 7][t & (kPcMax - 1)] = mk<double>(0.0, 0.0);
+  const int rr = t >> 3, cg = t & 7, lane = t & 63, wv = t >> 6;
+  d16 ar, ai;  // row rr, columns cg + 8 m (real and imaginary parts)
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
     const int c = cg + 8 * m;
@@ -41,80 +42,73 @@ __global__ void __launch_bounds__(1024) k_pchol_reg(int n, const z64* __restrict
       const z64 x = G[rr + (int64_t)c * ldg], y = G[c + (int64_t)rr * ldg];
       v = mk<double>(0.5 * (x.x + y.x), rr == c ? 0.0 : 0.5 * (x.y - y.y));
     }
-    a[m] = v;
+    ar[m] = v.x;
+    ai[m] = v.y;
   }
-  if (t < n) {
-    diag[t] = G[t + (int64_t)t * ldg].x;
-    done[t] = 0;
-  }
-  if (t == 0) srank = n;
-  __syncthreads();
+  // the remaining diagonal of this thread's row (the same in the 8 lanes of the
+  // row) and whether the row has been a pivot.  Rows and columns that are done
+  // keep being updated: their entries are never read again.
+  double dg = rr < n ? G[rr + (int64_t)rr * ldg].x : 0.0;
+  bool isp = false;
   int r = n;
+  double d0 = 0;
   for (int k = 0; k < n; ++k) {
-    // pivot: largest remaining diagonal (ties: smallest index), wave 0
-    if (t < 64) {
-      double best = -1.0;
-      int bi = n;
-      for (int i = t; i < n; i += 64)
-        if (!done[i] && diag[i] > best) {
-          best = diag[i];
-          bi = i;
-        }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (t == 0) {
-        if (k == 0) sd0 = best;
-        const double d0 = k == 0 ? best : sd0;
-        if (!(best > tol * d0) || !(best > 0.0)) srank = k;
-        else {
-          sb[k & 1] = bi;
-          pv[k] = bi;
-        }
+    // pivot: largest remaining diagonal (ties: smallest index); arg-max in
+    // every wave, then over the 16 wave candidates in every wave
+    {
+      const bool live = rr < n && !isp;
+      double val = live ? dg : -1.0;
+      int row = live ? rr : 1 << 20;
+      wave_argmax(val, row);
+      if (lane == 0) {
+        cv[wv] = val;
+        ci[wv] = row;
       }
     }
     __syncthreads();
-    if (srank == k) {
+    double best = lane < 16 ? cv[lane] : -2.0;
+    int b = lane < 16 ? ci[lane] : 1 << 20;
+    row16_argmax(best, b);
+    best = readlane_f64(best, 0);
+    b = __builtin_amdgcn_readlane(b, 0);
+    if (k == 0) d0 = best;
+    if (!(best > tol * d0) || !(best > 0.0)) {
       r = k;
       break;
     }
-    const int b = sb[k & 1];
-    const double lbb = sqrt(diag[b]);
+    if (t == 0) pv[k] = b;
+    const double lbb = sqrt(best);
+    const double ilbb = 1.0 / lbb;
     // column b of the factor: l_i = a_ib / l_bb for the remaining rows, l_b = l_bb
-    if (rr < n) {
-#pragma unroll
-      for (int m = 0; m < 16; ++m)
-        if (cg + 8 * m == b) {
-          z64 v;
-          if (rr == b) v = mk<double>(lbb, 0.0);
-          else if (done[rr]) v = mk<double>(0.0, 0.0);
-          else v = cscale<double>(a[m], 1.0 / lbb);
-          lcol[k & 1][rr] = v;
-          Lg[rr + (int64_t)k * n] = v;
-          if (rr == b) done[b] = 1;  // read only after the barrier below
-        }
+    const int bm = __builtin_amdgcn_readfirstlane(b >> 3);
+    const z64 ab = mk<double>(ar[bm], ai[bm]);
+    z64 lv = rr == b ? mk<double>(lbb, 0.0) : (isp || rr >= n) ? mk<double>(0.0, 0.0) : cscale<double>(ab, ilbb);
+    if (cg == (b & 7) && rr < n) {
+      lcol[k & 1][rr] = lv;
+      Lg[rr + (int64_t)k * n] = lv;
     }
+    // this row's l, from the lane of the row that holds column b
+    const int src = (lane & ~7) | (b & 7);
+    lv = mk<double>(__shfl(lv.x, src, 64), __shfl(lv.y, src, 64));
+    if (rr == b) isp = true;
     __syncthreads();
-    if (rr < n && !done[rr]) {
-      const z64 li = lcol[k & 1][rr];
+    // a_rc -= l_r conj(l_c), reads of l in groups of four
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int c = cg + 8 * m;
-        if (c < n && !done[c]) {
-          const z64 lc = lcol[k & 1][c];
-          a[m] = csub<double>(a[m], cmulz(li, mk<double>(lc.x, -lc.y)));
-        }
+    for (int mb = 0; mb < 16; mb += 4) {
+      z64 lc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) lc[u] = lcol[k & 1][cg + 8 * (mb + u)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int m = mb + u;
+        ar[m] = fma(-lv.x, lc[u].x, fma(-lv.y, lc[u].y, ar[m]));
+        ai[m] = fma(-lv.y, lc[u].x, fma(lv.x, lc[u].y, ai[m]));
       }
-      if (cg == 0) diag[rr] -= li.x * li.x + li.y * li.y;
     }
-    __syncthreads();
+    dg -= lv.x * lv.x + lv.y * lv.y;
   }
+  if (cg == 0 && rr < n) done[rr] = isp ? 1 : 0;
+  __syncthreads();
   // remaining indices after the pivots, in increasing order
   if (t == 0) {
     // the pivots 0..r-1 are exactly the indices marked done
@@ -131,30 +125,37 @@ __global__ void __launch_bounds__(1024) k_pchol_reg(int n, const z64* __restrict
 #pragma unroll
   for (int m = 0; m < 16; ++m) acc[m] = mk<double>(0.0, 0.0);
   z64* xrow = &lcol[0][0];  // reused: 2 x kPcMax
-  // Lt[rr][arow] is loaded one row ahead so that its latency overlaps the barrier
+  // Lt[rr][arow] is loaded one row ahead so that its latency overlaps the barrier;
+  // it is zero for rr < arow (rows that were pivots before step arow)
   z64 lnext = (rr < r) ? Lg[pv[rr]] : mk<double>(0.0, 0.0);
   for (int arow = 0; arow < r; ++arow) {
     z64* xr = xrow + (arow & 1) * kPcMax;
     const z64 l = lnext;
     if (rr < r && arow + 1 < r) lnext = Lg[pv[rr] + (int64_t)(arow + 1) * n];
     if (rr == arow) {
+      // row arow of X is final: (e_arow - acc) / Lt[arow][arow]; zero beyond column arow
       const double inv = 1.0 / l.x;
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
         const int j = cg + 8 * m;
-        if (j <= arow) {
-          const z64 rhs = csub<double>(mk<double>(j == arow ? 1.0 : 0.0, 0.0), acc[m]);
-          acc[m] = cscale<double>(rhs, inv);
-          xr[j] = acc[m];
-        }
+        const z64 rhs = csub<double>(mk<double>(j == arow ? 1.0 : 0.0, 0.0), acc[m]);
+        acc[m] = j <= arow ? cscale<double>(rhs, inv) : mk<double>(0.0, 0.0);
+        xr[j] = acc[m];
       }
     }
     __syncthreads();
-    if (rr > arow && rr < r) {
+    // later rows: acc += Lt[rr][arow] X[arow][:] (rows before arow have l = 0)
+    const z64 lu = rr == arow ? mk<double>(0.0, 0.0) : l;
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int j = cg + 8 * m;
-        if (j <= arow) acc[m] = cadd<double>(acc[m], cmulz(l, xr[j]));
+    for (int mb = 0; mb < 16; mb += 4) {
+      z64 xw[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xw[u] = xr[cg + 8 * (mb + u)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        z64& x = acc[mb + u];
+        x.x = fma(lu.x, xw[u].x, fma(-lu.y, xw[u].y, x.x));
+        x.y = fma(lu.x, xw[u].y, fma(lu.y, xw[u].x, x.y));
       }
     }
   }

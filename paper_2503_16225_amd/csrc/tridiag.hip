@@ -9,9 +9,9 @@
 //
 // The result is the same Galerkin solution as with a full eigendecomposition
 // of A (it is unique), at the cost of one reduction of A per FOM iteration.
-// Up to q = 512 the reduction keeps A in registers and synchronises through a
-// counter barrier; larger q use an L2-resident variant with the cooperative
-// groups barrier.
+// Up to q = 512 the reduction keeps A in registers and its work-groups hand
+// each other the data of every step through polled exchange slots; larger q
+// use an L2-resident variant with the cooperative groups barrier.
 #include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
@@ -232,32 +232,45 @@ template <int NS> __device__ __forceinline__ void reflector_reg(z64 (&x)[NS], in
     if (lane + 64 * s == r0) x[s] = v0;
 }
 
-// Barrier over the grid; false when the wait timed out (then every later
-// barrier of the launch times out as well and the kernel ends).
-__device__ __forceinline__ bool grid_barrier(unsigned* ctr, unsigned target, int* err, int* sbad) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int spins = 0;
-    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (++spins > kTrSpin) {
-        *sbad = 1;
-        *reinterpret_cast<volatile int*>(err) = 1;
-        break;
-      }
+// Exchange slots: every value that one wave hands to others has a slot of
+// its own (per step), filled beforehand with a signalling-NaN pattern that no
+// arithmetic produces.  Producers store with device-scope atomic stores, and
+// consumers poll the slot with device-scope atomic loads until the pattern is
+// gone, so no barrier is needed.  Waits are bounded; a timeout is reported.
+constexpr unsigned long long kEmpty = 0x7FF4A5A5A5A5A5A5ull;
+
+__device__ __forceinline__ void put_z(z64* p, z64 v) {
+  unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
+  unsigned long long x = (unsigned long long)__double_as_longlong(v.x);
+  unsigned long long y = (unsigned long long)__double_as_longlong(v.y);
+  if (x == kEmpty) x = 0x7FF8000000000000ull;
+  if (y == kEmpty) y = 0x7FF8000000000000ull;
+  __hip_atomic_store(u, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(u + 1, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ z64 poll_z(const z64* p, bool& ok) {
+  const unsigned long long* u = reinterpret_cast<const unsigned long long*>(p);
+  unsigned long long x = kEmpty, y = kEmpty;
+  for (int spins = 0;; ++spins) {
+    x = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    y = __hip_atomic_load(u + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (x != kEmpty && y != kEmpty) break;
+    if (spins > kTrSpin) {
+      ok = false;
+      break;
     }
-    __threadfence();
   }
-  __syncthreads();
-  return *sbad == 0;
+  return mk<double>(__longlong_as_double((long long)x), __longlong_as_double((long long)y));
 }
 }  // namespace
 
 template <int NS>
 __global__ void __launch_bounds__(64 * kTrWaves) k_tridiag_reg(int q, const z64* __restrict__ A, int64_t lda,
                                                                double* d, z64* e, z64* Vh, int64_t ldv, double* beta,
-                                                               z64* Pb, z64* Cb, unsigned* ctr, int* err) {
+                                                               z64* Pb, z64* Cb, int* err) {
+  // Pb, Cb: q x q exchange slots (row k = step k) holding the kEmpty pattern
+  __shared__ z64 sP[2][64 * NS], sC[2][64 * NS];
   __shared__ int sbad;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -265,6 +278,7 @@ __global__ void __launch_bounds__(64 * kTrWaves) k_tridiag_reg(int q, const z64*
   const int nwt = G * kTrWaves;
   const int gw = blockIdx.x * kTrWaves + wv;
   if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
   int col[kTrCols];
   z64 a[kTrCols][NS];
 #pragma unroll
@@ -308,20 +322,34 @@ __global__ void __launch_bounds__(64 * kTrWaves) k_tridiag_reg(int q, const z64*
       }
       sx = wave_allsum(sx);
       sy = wave_allsum(sy);
-      if (lane == 0) Pb[col[j]] = mk<double>(b * sx, b * sy);
+      if (lane == 0) put_z(Pb + col[j], mk<double>(b * sx, b * sy));
     }
   }
-  if (!grid_barrier(ctr, (unsigned)G, err, &sbad)) return;
   for (int k = 0; k + 1 < q; ++k) {
-    const z64* P = Pb + (int64_t)(k & 1) * q;
-    // w = p - (beta/2)(v^H p) v and the column k+1 as updated through step k-1
+    // p_k and the column k+1 as updated through step k-1 (rows k+1..), polled
+    // by the threads of the work-group into LDS (double-buffered by step)
+    {
+      const int t = threadIdx.x;
+      if (t >= k + 1 && t < q) {
+        bool ok = true;
+        sP[k & 1][t] = poll_z(Pb + (int64_t)k * q + t, ok);
+        sC[k & 1][t] = k == 0 ? A[t + lda] : poll_z(Cb + (int64_t)k * q + t, ok);
+        if (!ok) sbad = 1;
+      }
+      __syncthreads();
+      if (sbad) {
+        if (threadIdx.x == 0) *reinterpret_cast<volatile int*>(err) = 1;
+        return;
+      }
+    }
+    // w = p - (beta/2)(v^H p) v
     z64 w[NS], cc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int i = lane + 64 * s;
       const bool in = i >= k + 1 && i < q;
-      w[s] = in ? P[i] : mk<double>(0.0, 0.0);
-      cc[s] = in ? (k == 0 ? A[i + lda] : Cb[(int64_t)(k & 1) * q + i]) : mk<double>(0.0, 0.0);
+      w[s] = in ? sP[k & 1][i] : mk<double>(0.0, 0.0);
+      cc[s] = in ? sC[k & 1][i] : mk<double>(0.0, 0.0);
     }
     double kx = 0;
 #pragma unroll
@@ -352,7 +380,7 @@ __global__ void __launch_bounds__(64 * kTrWaves) k_tridiag_reg(int q, const z64*
     double bn;
     reflector_reg<NS>(x, k + 2, an, bn);
     // rank-2 update of the owned columns c >= k+2 and their entries of p_{k+1}
-    z64* Pn = Pb + (int64_t)((k + 1) & 1) * q;
+    z64* Pn = Pb + (int64_t)(k + 1) * q;
 #pragma unroll
     for (int j = 0; j < kTrCols; ++j) {
       const int c = col[j];
@@ -369,12 +397,12 @@ __global__ void __launch_bounds__(64 * kTrWaves) k_tridiag_reg(int q, const z64*
         }
         sx = wave_allsum(sx);
         sy = wave_allsum(sy);
-        if (lane == 0) Pn[c] = mk<double>(bn * sx, bn * sy);
+        if (lane == 0) put_z(Pn + c, mk<double>(bn * sx, bn * sy));
         if (c == k + 2) {
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
             const int i = lane + 64 * s;
-            if (i >= k + 2 && i < q) Cb[(int64_t)((k + 1) & 1) * q + i] = a[j][s];
+            if (i >= k + 2 && i < q) put_z(Cb + (int64_t)(k + 1) * q + i, a[j][s]);
           }
         }
       }
@@ -392,7 +420,6 @@ __global__ void __launch_bounds__(64 * kTrWaves) k_tridiag_reg(int q, const z64*
 #pragma unroll
     for (int s = 0; s < NS; ++s) v[s] = x[s];
     b = bn;
-    if (!grid_barrier(ctr, (unsigned)(k + 2) * (unsigned)G, err, &sbad)) return;
   }
 }
 
@@ -504,9 +531,8 @@ __global__ void __launch_bounds__(64) k_trisolve_reg(int q, int ncols, const dou
   }
 }
 
-__global__ void k_zero_u32(unsigned* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
 // Apply the reflectors to the columns of B (q x ncols, ld ldb), one work-group
@@ -551,16 +577,19 @@ __global__ void k_set_d0(const z64* A, double* d) { d[0] = A[0].x; }
 namespace {
 template <int NS>
 void tridiag_reg_launch(hipStream_t st, int q, int p, z64* A, int64_t lda, double* dd, z64* e, z64* Vh, double* bt,
-                        z64* P, z64* Cb, unsigned* ctr, z64* Yt, int* herr) {
+                        z64* Pb, z64* Cb, z64* Yt, int* herr) {
   const int G = (q + kTrWaves * kTrCols - 1) / (kTrWaves * kTrCols);
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ctr, 1);
+  // Pb and Cb are contiguous: 2 q^2 complex slots, 4 q^2 words
+  const int64_t nw = (int64_t)4 * q * q;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>(1024, (nw + 255) / 256)), dim3(256), 0, st,
+                     reinterpret_cast<unsigned long long*>(Pb), nw, kEmpty);
   int qq = q;
   int64_t la = lda, lv = q;
-  void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P, &Cb, &ctr, &herr};
+  void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &Pb, &Cb, &herr};
   *reinterpret_cast<volatile int*>(herr) = 0;
   HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag_reg<NS>, dim3(G), dim3(64 * kTrWaves), args, 0, st));
   HIPCK(hipStreamSynchronize(st));
-  if (*reinterpret_cast<volatile int*>(herr) != 0) fail(EAHP_EDEVICE, "grid barrier of the tridiagonal reduction timed out");
+  if (*reinterpret_cast<volatile int*>(herr) != 0) fail(EAHP_EDEVICE, "exchange wait of the tridiagonal reduction timed out");
   hipLaunchKernelGGL(k_apply_refl_reg<NS>, dim3((p + 3) / 4), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q,
                      p, 1);
 }
@@ -569,31 +598,32 @@ void tridiag_reg_launch(hipStream_t st, int q, int p, z64* A, int64_t lda, doubl
 void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws) {
   if (q <= 0 || p <= 0) return;
   if (q > 3200) fail(EAHP_EINVAL, "projected FOM system larger than 3200");
-  // Vh (q x q), W (3 q p), e (q), P (2 q), Cb (2 q), d (q), beta (q), counter
-  const size_t need =
-      sizeof(z64) * ((size_t)q * q + (size_t)3 * q * p + 5 * (size_t)q) + sizeof(double) * 2 * q + 512;
+  const bool reg = q >= 2 && q <= 512;
+  // Vh (q x q), W (3 q p), e (q), P (2 q), then d, beta (q each), then for the
+  // register-resident reduction the exchange slots Pb, Cb (q x q each)
+  const size_t base = sizeof(z64) * ((size_t)q * q + (size_t)3 * q * p + 3 * (size_t)q) + sizeof(double) * 2 * q;
+  const size_t need = base + (reg ? sizeof(z64) * 2 * (size_t)q * q : 0) + 512;
   ws.ensure(need);
   z64* Vh = ws.as<z64>();
   z64* W = Vh + (size_t)q * q;
   z64* e = W + (size_t)3 * q * p;
   z64* P = e + q;
-  z64* Cb = P + 2 * q;
-  double* dd = reinterpret_cast<double*>(Cb + 2 * q);
+  double* dd = reinterpret_cast<double*>(P + 2 * q);
   double* bt = dd + q;
-  unsigned* ctr = reinterpret_cast<unsigned*>(bt + q + 8);
-  const bool reg = q >= 2 && q <= 512;
+  z64* Pb = reinterpret_cast<z64*>(bt + q + 8);
+  z64* Cb = Pb + (size_t)q * q;
   if (q >= 2) {
-    // grid-synchronising kernels of concurrent streams (the serving loop)
-    // could each hold part of the CUs while waiting for the rest of their
-    // grid: one at a time per process, waited for before the next
+    // kernels that wait on each other's work-groups must not share the CUs
+    // with another such launch from a concurrent stream (the serving loop):
+    // one at a time per process, waited for before the next
     static std::mutex coop;
     static int* herr = nullptr;
     std::lock_guard<std::mutex> lk(coop);
     if (reg) {
       if (!herr) HIPCK(hipHostMalloc((void**)&herr, 64, hipHostMallocDefault));
-      if (q <= 128) tridiag_reg_launch<2>(st, q, p, A, lda, dd, e, Vh, bt, P, Cb, ctr, Yt, herr);
-      else if (q <= 256) tridiag_reg_launch<4>(st, q, p, A, lda, dd, e, Vh, bt, P, Cb, ctr, Yt, herr);
-      else tridiag_reg_launch<8>(st, q, p, A, lda, dd, e, Vh, bt, P, Cb, ctr, Yt, herr);
+      if (q <= 128) tridiag_reg_launch<2>(st, q, p, A, lda, dd, e, Vh, bt, Pb, Cb, Yt, herr);
+      else if (q <= 256) tridiag_reg_launch<4>(st, q, p, A, lda, dd, e, Vh, bt, Pb, Cb, Yt, herr);
+      else tridiag_reg_launch<8>(st, q, p, A, lda, dd, e, Vh, bt, Pb, Cb, Yt, herr);
     } else {
       const size_t lds = sizeof(z64) * 3 * (size_t)q;
       HIPCK(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
