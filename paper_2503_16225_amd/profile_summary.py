@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 results databases (kernel durations, PMC counters).
 
-    python -m paper_2503_16225_amd.profile_summary trace DB
+    python -m paper_2503_16225_amd.profile_summary trace DB [--split-gap-ms G]
     python -m paper_2503_16225_amd.profile_summary pmc FETCH_DB WRITE_DB --kernel NAME [--copy-bytes B]
 
 The pmc mode reports FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the named
@@ -14,9 +14,27 @@ import sqlite3
 import statistics
 
 
-def trace(db, top=20):
+def segments(db, gap_ms):
+    """Dispatches (name, duration) split where the device sat idle for more
+    than gap_ms between two kernels (e.g. between two runs of one program)."""
     con = sqlite3.connect(db)
-    rows = con.execute("select name, duration from kernels").fetchall()
+    rows = con.execute("select name, start, end, duration from kernels order by start").fetchall()
+    segs, cur, last = [], [], None
+    for name, start, end, dur in rows:
+        if last is not None and (start - last) / 1e6 > gap_ms and cur:
+            segs.append(cur)
+            cur = []
+        cur.append((name, dur))
+        last = end if last is None else max(last, end)
+    if cur:
+        segs.append(cur)
+    return segs
+
+
+def trace(db, top=20, rows=None):
+    if rows is None:
+        con = sqlite3.connect(db)
+        rows = con.execute("select name, duration from kernels").fetchall()
     agg = {}
     for name, dur in rows:
         agg.setdefault(name.split("(")[0], []).append(dur)
@@ -47,14 +65,23 @@ def main():
     ap.add_argument("--kernel", default=None)
     ap.add_argument("--copy-bytes", type=float, default=536870912.0)
     ap.add_argument("--copy-kernel", default="copy")
+    ap.add_argument("--split-gap-ms", type=float, default=0.0,
+                    help="report separately the stretches of dispatches separated by idle gaps above this")
+    ap.add_argument("--min-dispatches", type=int, default=100)
     a = ap.parse_args()
     if a.mode == "trace":
-        rows, tot = trace(a.dbs[0])
-        print(f"total kernel time {tot:.3f} ms")
-        print("| kernel | calls | total ms | avg ms | % |")
-        print("|---|---|---|---|---|")
-        for name, n, t, avg, pct in rows:
-            print(f"| {name} | {n} | {t:.3f} | {avg:.4f} | {pct:.1f} |")
+        segs = segments(a.dbs[0], a.split_gap_ms) if a.split_gap_ms > 0 else [None]
+        if a.split_gap_ms > 0:
+            segs = [sg for sg in segs if len(sg) >= a.min_dispatches]
+        for i, sg in enumerate(segs):
+            rows, tot = trace(a.dbs[0], rows=sg)
+            if sg is not None:
+                print(f"\nsegment {i + 1} of {len(segs)}: {len(sg)} dispatches")
+            print(f"total kernel time {tot:.3f} ms")
+            print("| kernel | calls | total ms | avg ms | % |")
+            print("|---|---|---|---|---|")
+            for name, n, t, avg, pct in rows:
+                print(f"| {name} | {n} | {t:.3f} | {avg:.4f} | {pct:.1f} |")
         return
     fetch = pmc(a.dbs[0], "FETCH_SIZE")
     write = pmc(a.dbs[1], "WRITE_SIZE")
