@@ -54,6 +54,9 @@ enum {
 };
 
 enum { EAHP_FP64 = 0, EAHP_MIXED = 1 };
+/* Outer iteration (eahp_solve_params.method) and retraction (.retraction). */
+enum { EAHP_EARCG = 0, EAHP_EARGD = 1 };
+enum { EAHP_POLAR = 0 };
 
 /* term switches of the Hamiltonian (all set = the full model) */
 enum { EAHP_TERM_ION = 1, EAHP_TERM_HARTREE = 2, EAHP_TERM_XC = 4, EAHP_TERM_NONLOCAL = 8 };
@@ -95,6 +98,14 @@ typedef struct {
   double mu_warm;    /* shift correction used while ||R||_F > warm_rtol (random starts)   */
   double warm_rtol;
   double rank_tol;   /* deflation threshold of the rank-revealing orthonormalisation      */
+  int method;        /* EAHP_EARCG (Algorithm 3) or EAHP_EARGD: the energy-adaptive        */
+                     /* gradient -G as direction, an alternating Barzilai-Borwein step and */
+                     /* non-monotone (Zhang-Hager) backtracking, the gradient-descent      */
+                     /* method the paper compares against (Sec. 5.2)                       */
+  int retraction;    /* EAHP_POLAR (eq. (3.1))                                             */
+  double nm_rho;     /* EARGD: accept tau when E(tau) <= C + nm_rho tau dE/dtau(0)         */
+  double nm_backtrack; /* EARGD: tau <- nm_backtrack tau on rejection (0 < . < 1)          */
+  double nm_theta;   /* EARGD: C_{k+1} = (theta Q_k C_k + E_{k+1}) / (theta Q_k + 1)       */
 } eahp_solve_params;
 
 /* Statistics of eahp_solve (host memory, filled on return). */

@@ -14,6 +14,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 EAHP_FP64, EAHP_MIXED = 0, 1
+EAHP_EARCG, EAHP_EARGD = 0, 1
+EAHP_POLAR = 0
 _STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTPD", -5: "EFOM", -6: "ELINESEARCH",
            -7: "ENODESCENT", -8: "ENOCONV", -9: "ENONFINITE"}
 
@@ -36,7 +38,8 @@ class SolveParams(C.Structure):
     _fields_ = [("mu", C.c_double), ("fom_rtol", C.c_double), ("fom_maxit", C.c_int), ("delta", C.c_double),
                 ("sigma", C.c_double), ("gamma", C.c_double), ("eps", C.c_double), ("ls_maxit", C.c_int),
                 ("tol", C.c_double), ("maxit", C.c_int), ("mu_warm", C.c_double), ("warm_rtol", C.c_double),
-                ("rank_tol", C.c_double)]
+                ("rank_tol", C.c_double), ("method", C.c_int), ("retraction", C.c_int), ("nm_rho", C.c_double),
+                ("nm_backtrack", C.c_double), ("nm_theta", C.c_double)]
 
     @classmethod
     def from_dict(cls, d):

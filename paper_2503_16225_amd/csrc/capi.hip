@@ -155,6 +155,7 @@ struct eahp_solver {
   z64 *Lam = nullptr, *Lamt = nullptr;
   PointScalars sc;
   double rn = 0, mu = 0, tau_prev = 1.0;
+  double nmC = 0, nmQ = 1;  // EARGD: Zhang-Hager reference energy and its weight
   int it = 0, ls_trials = 0, fom_iters = 0;
   int64_t napply = 0, napply32 = 0;
   double seconds = 0;
@@ -230,6 +231,75 @@ void solver_init(eahp_solver* sv, const z64* Psi0) {
   solver_gradient(sv, sv->Phi, sv->R, sv->Lam, sv->mu, sv->G);
   axpby<double>(pb->ctx->stream, pb->ntot * pb->p, -1.0, sv->G, 0.0, sv->eta);
   sv->tau_prev = 1.0;
+  sv->nmC = sv->sc.E;
+  sv->nmQ = 1.0;
+}
+
+// One iteration of EARGD: d = -G, an alternating Barzilai-Borwein trial step
+// from S = Phi_k - Phi_{k-1}, Y = G_k - G_{k-1} (the first iteration tries 1),
+// clamped to [1e-10, 1e10], and backtracking until the energy passes the
+// non-monotone test E <= C + rho tau dE/dtau(0) against the Zhang-Hager
+// reference C.  Trials evaluate the energy only; the accepted point then gets
+// H Phi and its residual.  Phit holds the previous iterate between iterations.
+void solver_iterate_gd(eahp_solver* sv) {
+  eahp_problem* pb = sv->pb;
+  Counters cnt(sv);
+  hipStream_t st = pb->ctx->stream;
+  const int64_t N = pb->ntot * pb->p;
+  const eahp_solve_params& prm = sv->prm;
+  const double slope_scale = 2.0 * pb->occ;
+  axpby<double>(st, N, -1.0, sv->G, 0.0, sv->eta);
+  double dE = slope_scale * frame_dot_weighted(pb, sv->R, sv->eta);
+  int doublings = 0;
+  while (!(dE < 0.0)) {
+    if (++doublings > 30) fail(EAHP_ENODESCENT, "no descent direction");
+    sv->mu *= 2.0;
+    evaluate_point(pb, sv->Phi, sv->HPhi, sv->R, sv->Lam, &sv->sc);  // makes V_eff current
+    solver_gradient(sv, sv->Phi, sv->R, sv->Lam, sv->mu, sv->G);
+    axpby<double>(st, N, -1.0, sv->G, 0.0, sv->eta);
+    dE = slope_scale * frame_dot_weighted(pb, sv->R, sv->eta);
+  }
+  double tau = 1.0;
+  if (sv->it > 0) {
+    // S into xi, Y into Rt (both free here); TG holds G_{k-1}
+    axpby<double>(st, N, 1.0, sv->Phi, 0.0, sv->xi);
+    axpby<double>(st, N, -1.0, sv->Phit, 1.0, sv->xi);
+    axpby<double>(st, N, 1.0, sv->G, 0.0, sv->Rt);
+    axpby<double>(st, N, -1.0, sv->TG, 1.0, sv->Rt);
+    const double sy = std::fabs(frame_dot(pb, sv->xi, sv->Rt));
+    if (sy == 0.0) {
+      tau = sv->tau_prev;
+    } else {
+      tau = (sv->it % 2 == 1) ? frame_dot(pb, sv->xi, sv->xi) / sy : sy / frame_dot(pb, sv->Rt, sv->Rt);
+      tau = std::min(std::max(tau, 1e-10), 1e10);
+    }
+  }
+  int trials = 0;
+  PointScalars sct;
+  for (;;) {
+    if (trials >= prm.ls_maxit) fail(EAHP_ELINESEARCH, "backtracking: no acceptable step");
+    ++trials;
+    retract(pb, sv->Phi, sv->eta, tau, sv->Phit, *sv->Ft);
+    evaluate_energy(pb, sv->Phit, &sct);
+    if (sct.E <= sv->nmC + prm.nm_rho * tau * dE) break;
+    tau *= prm.nm_backtrack;
+  }
+  sv->ls_trials += trials;
+  complete_point(pb, sv->Phit, sv->HPhit, sv->Rt, sv->Lamt, &sct);
+  std::swap(sv->Phi, sv->Phit);  // Phit keeps the previous iterate for the next step
+  std::swap(sv->HPhi, sv->HPhit);
+  std::swap(sv->R, sv->Rt);
+  std::swap(sv->Lam, sv->Lamt);
+  sv->sc = sct;
+  sv->rn = sv->sc.rnorm;
+  const double Qn = prm.nm_theta * sv->nmQ + 1.0;
+  sv->nmC = (prm.nm_theta * sv->nmQ * sv->nmC + sv->sc.E) / Qn;
+  sv->nmQ = Qn;
+  sv->mu = mu_for(sv, sv->rn, sv->Lam);
+  solver_gradient(sv, sv->Phi, sv->R, sv->Lam, sv->mu, sv->TG);
+  std::swap(sv->G, sv->TG);  // TG keeps G_{k-1}
+  sv->tau_prev = tau;
+  ++sv->it;
 }
 
 // One outer iteration of Algorithm 3.
@@ -525,6 +595,12 @@ int eahp_solver_create(eahp_problem* pb, const void* Psi0, const eahp_solve_para
     if (!(prm.mu > 0) || !(prm.mu_warm > 0) || prm.fom_maxit <= 0 || prm.ls_maxit <= 0 ||
         !(prm.gamma > 0 && prm.gamma < 1))
       fail(EAHP_EINVAL, "bad solve parameters");
+    if (prm.method != EAHP_EARCG && prm.method != EAHP_EARGD) fail(EAHP_EINVAL, "unknown method");
+    if (prm.retraction != EAHP_POLAR) fail(EAHP_EINVAL, "unknown retraction");
+    if (prm.method == EAHP_EARGD &&
+        !(prm.nm_rho > 0 && prm.nm_rho < 1 && prm.nm_backtrack > 0 && prm.nm_backtrack < 1 && prm.nm_theta >= 0 &&
+          prm.nm_theta <= 1))
+      fail(EAHP_EINVAL, "bad EARGD parameters");
     sv = new eahp_solver;
     sv->pb = pb;
     sv->prm = prm;
@@ -539,7 +615,10 @@ int eahp_solver_step(eahp_solver* sv, int nsteps, eahp_stats* stats) {
   int rc = guarded([&] {
     if (!sv) fail(EAHP_EINVAL, "null solver");
     check_problem(sv->pb);
-    for (int i = 0; i < nsteps && !solver_converged(sv); ++i) solver_iterate(sv);
+    for (int i = 0; i < nsteps && !solver_converged(sv); ++i) {
+      if (sv->prm.method == EAHP_EARGD) solver_iterate_gd(sv);
+      else solver_iterate(sv);
+    }
   });
   if (sv && stats) solver_stats(sv, stats);
   if (rc == EAHP_OK && sv && !solver_converged(sv)) rc = EAHP_ENOCONV;

@@ -34,6 +34,10 @@ template <typename T> void apply_H_block(eahp_problem* pb, int ik, int ncols, co
 void evaluate_point(eahp_problem* pb, const z64* Psi, z64* HPsi, z64* R, z64* Lam, PointScalars* out);
 void lambda_residual(eahp_problem* pb, const z64* Psi, const z64* HPsi, z64* R, z64* Lam);
 double frame_dot(eahp_problem* pb, const z64* A, const z64* B);
+double frame_dot_weighted(eahp_problem* pb, const z64* A, const z64* B);  // sum_k w_k Re tr(A_k^H B_k)
+// Energy only (no H-apply); complete_point then adds H Psi, Lambda, R, ||R||_F.
+void evaluate_energy(eahp_problem* pb, const z64* Psi, PointScalars* out);
+void complete_point(eahp_problem* pb, const z64* Psi, z64* HPsi, z64* R, z64* Lam, PointScalars* out);
 
 // Retraction factors per k: eigenvalues d of (Psi+xi)^H(Psi+xi), eigenvectors V, S^-1.
 struct RetractFactors {

@@ -579,6 +579,72 @@ void evaluate_point(eahp_problem* pb, const z64* Psi, z64* HPsi, z64* R, z64* La
   }
 }
 
+// Energy at Psi without an H-apply: density, V_eff and the local terms, the
+// kinetic term from the coefficients and the nonlocal term from the projector
+// products.  Leaves the inverse y/z transforms of Psi in the plane buffer, so
+// that complete_point can follow without repeating them.
+void evaluate_energy(eahp_problem* pb, const z64* Psi, PointScalars* out) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p, nk = pb->nk;
+  density_potentials(pb, Psi);
+  double* vals = pb->d_vals.as<double>();
+  double* kinv = vals;
+  double* nlv = vals + (size_t)nk * p;
+  const bool nl = (pb->terms & EAHP_TERM_NONLOCAL) && pb->natoms > 0;
+  for (int ik = 0; ik < nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    col_weighted_norm2(st, K.npw, p, Psi + o, K.npw, K.d_kin.as<double>(), kinv + ik * p);
+    if (nl) {
+      const int na = pb->natoms;
+      pb->ws.small.ensure(sizeof(z64) * (size_t)na * p);
+      z64* Bm = pb->ws.small.as<z64>();
+      gemm_hn<double>(st, K.npw, na, p, K.d_proj.as<z64>(), K.npw, Psi + o, K.npw, Bm, na, 1.0, 0.0,
+                      pb->ws.gemm_part);
+      col_weighted_norm2(st, na, p, Bm, na, pb->d_D.as<double>(), nlv + ik * p);
+    }
+  }
+  weighted_sum(st, nk, p, kinv, pb->d_kw.as<double>(), pb->occ, scal(pb, S_KIN));
+  if (nl) weighted_sum(st, nk, p, nlv, pb->d_kw.as<double>(), pb->occ, scal(pb, S_NL));
+  else weighted_sum(st, 0, p, nlv, pb->d_kw.as<double>(), 0.0, scal(pb, S_NL));  // writes 0
+  fetch_scalars(pb, S_NL + 1);
+  const double* h = pb->h_scal;
+  out->terms[0] = h[S_KIN];
+  out->terms[1] = h[S_NL];
+  out->terms[2] = h[S_ION];
+  out->terms[3] = h[S_HART];
+  out->terms[4] = h[S_XC];
+  out->E = h[S_KIN] + h[S_NL] + h[S_ION] + h[S_HART] + h[S_XC];
+  out->rnorm = 0;
+  if (!std::isfinite(out->E)) fail(EAHP_ENONFINITE, "non-finite energy");
+}
+
+// H Psi, Lambda, R and ||R||_F at the point whose energy evaluate_energy just
+// computed (V_eff and the plane buffer are still those of Psi).
+void complete_point(eahp_problem* pb, const z64* Psi, z64* HPsi, z64* R, z64* Lam, PointScalars* out) {
+  hipStream_t st = pb->ctx->stream;
+  apply_H_frame(pb, Psi, HPsi, true, nullptr);
+  lambda_residual(pb, Psi, HPsi, R, Lam);
+  dot_re(st, pb->ntot * pb->p, R, R, scal(pb, S_RR), pb->ws.partial);
+  fetch_scalars(pb, S_RR + 1);
+  out->rnorm = std::sqrt(std::max(0.0, pb->h_scal[S_RR]));
+  if (!std::isfinite(out->rnorm)) fail(EAHP_ENONFINITE, "non-finite residual");
+}
+
+// sum_k w_k Re tr(A_k^H B_k)
+double frame_dot_weighted(eahp_problem* pb, const z64* A, const z64* B) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p, nk = pb->nk;
+  double* vals = pb->d_vals.as<double>();
+  for (int ik = 0; ik < nk; ++ik) {
+    const int64_t o = (int64_t)p * pb->kp[ik].off;
+    dot_re(st, pb->kp[ik].npw * p, A + o, B + o, vals + ik, pb->ws.partial);
+  }
+  weighted_sum(st, nk, 1, vals, pb->d_kw.as<double>(), 1.0, scal(pb, S_DOT));
+  fetch_scalars(pb, S_DOT + 1);
+  return pb->h_scal[S_DOT];
+}
+
 // Lambda_k = herm(Psi_k^H (H Psi)_k), R_k = (H Psi)_k - Psi_k Lambda_k
 void lambda_residual(eahp_problem* pb, const z64* Psi, const z64* HPsi, z64* R, z64* Lam) {
   hipStream_t st = pb->ctx->stream;
