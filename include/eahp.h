@@ -55,8 +55,8 @@ enum {
 
 enum { EAHP_FP64 = 0, EAHP_MIXED = 1 };
 /* Outer iteration (eahp_solve_params.method) and retraction (.retraction). */
-enum { EAHP_EARCG = 0, EAHP_EARGD = 1 };
-enum { EAHP_POLAR = 0 };
+enum { EAHP_EARCG = 0, EAHP_EARGD = 1, EAHP_L2RCG = 2 };
+enum { EAHP_POLAR = 0, EAHP_QR = 1 };
 
 /* term switches of the Hamiltonian (all set = the full model) */
 enum { EAHP_TERM_ION = 1, EAHP_TERM_HARTREE = 2, EAHP_TERM_XC = 4, EAHP_TERM_NONLOCAL = 8 };
@@ -98,14 +98,17 @@ typedef struct {
   double mu_warm;    /* shift correction used while ||R||_F > warm_rtol (random starts)   */
   double warm_rtol;
   double rank_tol;   /* deflation threshold of the rank-revealing orthonormalisation      */
-  int method;        /* EAHP_EARCG (Algorithm 3) or EAHP_EARGD: the energy-adaptive        */
+  int method;        /* EAHP_EARCG (Algorithm 3); EAHP_EARGD: the energy-adaptive          */
                      /* gradient -G as direction, an alternating Barzilai-Borwein step and */
                      /* non-monotone (Zhang-Hager) backtracking, the gradient-descent      */
-                     /* method the paper compares against (Sec. 5.2)                       */
-  int retraction;    /* EAHP_POLAR (eq. (3.1))                                             */
-  double nm_rho;     /* EARGD: accept tau when E(tau) <= C + nm_rho tau dE/dtau(0)         */
-  double nm_backtrack; /* EARGD: tau <- nm_backtrack tau on rejection (0 < . < 1)          */
-  double nm_theta;   /* EARGD: C_{k+1} = (theta Q_k C_k + E_{k+1}) / (theta Q_k + 1)       */
+                     /* method the paper compares against (Sec. 5.2); EAHP_L2RCG: CG on   */
+                     /* the unpreconditioned L2 gradient R with the frozen-potential       */
+                     /* Hessian step and the same backtracking (Sec. 5.2)                  */
+  int retraction;    /* EAHP_POLAR (eq. (3.1)) or EAHP_QR (Gram-Schmidt, Sec. 3.1), with    */
+                     /* the differentiated transport of the chosen retraction              */
+  double nm_rho;     /* EARGD, L2RCG: accept tau when E(tau) <= C + nm_rho tau dE/dtau(0)  */
+  double nm_backtrack; /* EARGD, L2RCG: tau <- nm_backtrack tau on rejection (0 < . < 1)   */
+  double nm_theta;   /* EARGD, L2RCG: C_{k+1} = (theta Q_k C_k + E_{k+1}) / (theta Q_k + 1) */
 } eahp_solve_params;
 
 /* Statistics of eahp_solve (host memory, filled on return). */
@@ -176,6 +179,16 @@ int eahp_retract(eahp_problem* pb, const void* Psi, const void* eta, double tau,
  * Tv = T_xi(v) = (v - R(xi) X) S^-1 with S = sf(Psi + xi),
  * S X + X S = xi^* v + v^* xi. */
 int eahp_transport(eahp_problem* pb, const void* Psi, const void* xi, const void* v, void* Tv);
+
+/* qR retraction, the alternative the paper names in Sec. 3.1: Psi_out =
+ * qf(Psi + tau eta), the Q factor of (Psi + tau eta) = Q R with R upper
+ * triangular and positive on the diagonal, from the Cholesky factor of the
+ * Gram matrix; EAHP_ENOTPD when a Gram matrix is not positive definite.
+ * transport_qr: the differentiated qR retraction D qf(Psi + xi)[v]
+ * (Tv tangent at qf(Psi + xi)).  Layouts and ownership as eahp_retract /
+ * eahp_transport. */
+int eahp_retract_qr(eahp_problem* pb, const void* Psi, const void* eta, double tau, void* Psi_out);
+int eahp_transport_qr(eahp_problem* pb, const void* Psi, const void* xi, const void* v, void* Tv);
 
 /* One line search (Algorithm 2) on f(t) = E(R_Psi(t eta)) from tau0;
  * on success tau, Psi_out = R_Psi(tau eta), trials (energy evaluations). */

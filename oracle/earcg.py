@@ -56,11 +56,12 @@ def metric_solve(model, Phi, HPhi, lams, Veff, mu, prm, stats=None):
     return np.concatenate(Xs, axis=0), info_all
 
 
-def evaluate_point(model, Phi, eta, tau):
+def evaluate_point(model, Phi, eta, tau, retraction=0):
     """f(tau), f'(tau) and everything the accepted step reuses."""
-    Phin, facs = mf.retract(model, Phi, eta, tau)
+    retract, transport_self, _ = mf.retraction_ops(retraction)
+    Phin, facs = retract(model, Phi, eta, tau)
     st = mf.state(model, Phin)
-    Teta = mf.transport_self(model, Phin, eta, tau, facs)
+    Teta = transport_self(model, Phin, eta, tau, facs)
     df = mf.pair(model, st["R"], Teta)
     st.update(Phi=Phin, facs=facs, Teta=Teta)
     return st["E"], df, st
@@ -105,7 +106,7 @@ def earcg(model, Phi0, prm, log=None, maxit=None, callback=None):
                 eta = -G
                 df0 = mf.pair(model, st["R"], eta)
         tau, f, df, new, trials = _ls.secant_step(
-            lambda t: evaluate_point(model, st["Phi"], eta, t), st["E"], df0, tau_prev,
+            lambda t: evaluate_point(model, st["Phi"], eta, t, prm.get("retraction", 0)), st["E"], df0, tau_prev,
             prm["delta"], prm["sigma"], prm["gamma"], prm["eps"], prm["ls_maxit"])
         stats["napply"] += trials * p_tot
         stats["trials"].append(trials)
@@ -114,7 +115,7 @@ def earcg(model, Phi0, prm, log=None, maxit=None, callback=None):
         mu = mu_for(rn, new)
         stats["mus"].append(mu)
         Gn = gradient(new, mu)
-        TG = mf.transport_general(model, new["Phi"], tau * eta, G, new["facs"])
+        TG = mf.retraction_ops(prm.get("retraction", 0))[2](model, new["Phi"], tau * eta, G, new["facs"])
         rg = mf.pair(model, st["R"], G)
         fr = mf.pair(model, new["R"], Gn) / rg
         prp = mf.pair(model, new["R"], Gn - TG) / rg

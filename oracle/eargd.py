@@ -21,7 +21,8 @@ notes, A28-A31):
   an energy-adaptive metric, whose gradient is Newton-like); <S,Y> = 0 keeps
   the previous accepted step;
 * A30 non-monotone backtracking in the Zhang-Hager form: a trial tau is
-  accepted when E(pf(Phi + tau d)) <= C_k + rho tau dE_k, with dE_k the
+  accepted when E(R_Phi(tau d)) <= C_k + rho tau dE_k (R the polar
+  retraction, or the qR one when selected), with dE_k the
   derivative of the energy along d (C11: 2 f sum_k w_k Re tr(R_k^* d_k)),
   otherwise tau <- delta tau; C_0 = E_0, Q_0 = 1, Q_{k+1} = theta Q_k + 1,
   C_{k+1} = (theta Q_k C_k + E_{k+1}) / Q_{k+1};
@@ -115,7 +116,7 @@ def eargd(model, Phi0, prm, log=None, maxit=None, callback=None):
             if trials >= prm["ls_maxit"]:
                 raise BacktrackError("no acceptable step")
             trials += 1
-            Phin, _ = mf.retract(model, st["Phi"], d, tau)
+            Phin, _ = mf.retraction_ops(prm.get("retraction", 0))[0](model, st["Phi"], d, tau)
             En = ham.energy_terms(model, Phin)[0]["total"]
             if En <= C + rho * tau * dE:
                 break

@@ -88,6 +88,53 @@ def transport_general(model, Phi_new, xi, v, facs):
     return np.concatenate(out, axis=0)
 
 
+# -- qR retraction (Sec. 3.1 names it as the alternative to the polar one) -----
+def qf(Psi):
+    """Q factor of Psi = qf(Psi) R with R upper triangular and positive on
+    the diagonal (Gram-Schmidt orthonormalisation), from the Cholesky factor
+    of Psi^* Psi = R^* R.  Returns (Q, R, R^-1)."""
+    p = Psi.shape[1]
+    R = np.linalg.cholesky(Psi.conj().T @ Psi).conj().T
+    Rinv = sla.solve_triangular(R, np.eye(p), lower=False)
+    return Psi @ Rinv, R, Rinv
+
+
+def retract_qr(model, Phi, eta, tau):
+    """R^qr_Phi(tau eta) = qf(Phi + tau eta) per k; factors (R, R^-1) per k."""
+    outs, facs = [], []
+    for Pk, Ek in zip(model.blocks(Phi), model.blocks(eta)):
+        Q, R, Rinv = qf(Pk + tau * Ek)
+        outs.append(Q)
+        facs.append((R, Rinv))
+    return np.concatenate(outs, axis=0), facs
+
+
+def transport_qr(model, Phi_new, v, facs):
+    """Differentiated qR retraction: with psi = Q R and M = Q^* v R^-1,
+    D qf(psi)[v] = Q Omega + (I - Q Q^*) v R^-1, where Omega is the
+    skew-Hermitian matrix with the strictly lower triangle of M, the negated
+    conjugate transpose of it above the diagonal and i Im(M_jj) on the
+    diagonal (differentiating psi = Q R with Q^* Q = I and R upper triangular
+    with a real diagonal).  Depends only on the new point and its factors."""
+    out = []
+    for Qk, Vk, (R, Rinv) in zip(model.blocks(Phi_new), model.blocks(v), facs):
+        M = Qk.conj().T @ Vk @ Rinv
+        L = np.tril(M, -1)
+        Om = L - L.conj().T + 1j * np.diag(np.imag(np.diag(M)))
+        out.append(Qk @ Om + (Vk - Qk @ (Qk.conj().T @ Vk)) @ Rinv)
+    return np.concatenate(out, axis=0)
+
+
+def retraction_ops(kind):
+    """(retract, transport_self, transport_general) of the polar (0) or qR (1)
+    retraction, with the signatures of the polar functions."""
+    if kind == 1:
+        return (retract_qr,
+                lambda model, Phi_new, eta, tau, facs: transport_qr(model, Phi_new, eta, facs),
+                lambda model, Phi_new, xi, v, facs: transport_qr(model, Phi_new, v, facs))
+    return retract, transport_self, transport_general
+
+
 def tpa_alpha(model, Phi):
     """alpha_jk = sum_G |k+G|^2/2 |phi_jk(G)|^2 (orbital-wise mean kinetic energy)."""
     return [np.sum(b["kin"][:, None] * np.abs(Pk) ** 2, axis=0)

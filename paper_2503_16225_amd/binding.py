@@ -14,8 +14,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 EAHP_FP64, EAHP_MIXED = 0, 1
-EAHP_EARCG, EAHP_EARGD = 0, 1
-EAHP_POLAR = 0
+EAHP_EARCG, EAHP_EARGD, EAHP_L2RCG = 0, 1, 2
+EAHP_POLAR, EAHP_QR = 0, 1
 _STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTPD", -5: "EFOM", -6: "ELINESEARCH",
            -7: "ENODESCENT", -8: "ENOCONV", -9: "ENONFINITE"}
 
@@ -91,6 +91,8 @@ def load_library():
         "eahp_ea_gradient": ([vp, vp, vp, vp], C.c_int),
         "eahp_retract": ([vp, vp, vp, C.c_double, vp], C.c_int),
         "eahp_transport": ([vp, vp, vp, vp, vp], C.c_int),
+        "eahp_retract_qr": ([vp, vp, vp, C.c_double, vp], C.c_int),
+        "eahp_transport_qr": ([vp, vp, vp, vp, vp], C.c_int),
         "eahp_linesearch": ([vp, vp, vp, C.c_double, C.POINTER(SolveParams), dp, vp, ip], C.c_int),
         "eahp_solve": ([vp, vp, C.POINTER(SolveParams), C.POINTER(Stats)], C.c_int),
         "eahp_layout_estimate": ([C.POINTER(SystemDesc), i64p, ip, i64p], C.c_int),
@@ -312,14 +314,16 @@ class Problem:
         _check(self.lib.eahp_ea_gradient(self.pb, _ptr(Psi), _ptr(X), _ptr(G)))
         return G
 
-    def retract(self, Psi, eta, tau):
+    def retract(self, Psi, eta, tau, qr=False):
         out = self.empty_frame()
-        _check(self.lib.eahp_retract(self.pb, _ptr(Psi), _ptr(eta), tau, _ptr(out)))
+        fn = self.lib.eahp_retract_qr if qr else self.lib.eahp_retract
+        _check(fn(self.pb, _ptr(Psi), _ptr(eta), tau, _ptr(out)))
         return out
 
-    def transport(self, Psi, xi, v):
+    def transport(self, Psi, xi, v, qr=False):
         out = self.empty_frame()
-        _check(self.lib.eahp_transport(self.pb, _ptr(Psi), _ptr(xi), _ptr(v), _ptr(out)))
+        fn = self.lib.eahp_transport_qr if qr else self.lib.eahp_transport
+        _check(fn(self.pb, _ptr(Psi), _ptr(xi), _ptr(v), _ptr(out)))
         return out
 
     def linesearch(self, Psi, eta, tau0, params):

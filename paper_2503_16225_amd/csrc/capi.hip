@@ -49,11 +49,16 @@ struct Trial {
 };
 
 
-// f(t), f'(t) at R_Phi(t eta) into the trial buffers
-void eval_trial(eahp_problem* pb, const z64* Phi, const z64* eta, double t, Trial& tr) {
-  if (!retract_line(pb, Phi, eta, t, pb->arena->line, tr.Phi, *tr.F)) retract(pb, Phi, eta, t, tr.Phi, *tr.F);
+// f(t), f'(t) at R_Phi(t eta) into the trial buffers (polar or qR retraction)
+void eval_trial(eahp_problem* pb, const z64* Phi, const z64* eta, double t, Trial& tr, int retraction) {
+  if (retraction == EAHP_QR) {
+    retract_qr(pb, Phi, eta, t, tr.Phi, *tr.F);
+  } else if (!retract_line(pb, Phi, eta, t, pb->arena->line, tr.Phi, *tr.F)) {
+    retract(pb, Phi, eta, t, tr.Phi, *tr.F);
+  }
   evaluate_point(pb, tr.Phi, tr.HPhi, tr.R, tr.Lam, &tr.sc);
-  transport_self(pb, tr.Phi, eta, t, *tr.F, tr.Teta);
+  if (retraction == EAHP_QR) transport_qr(pb, tr.Phi, eta, *tr.F, tr.Teta);
+  else transport_self(pb, tr.Phi, eta, t, *tr.F, tr.Teta);
   tr.df = frame_dot(pb, tr.R, tr.Teta);
   if (!std::isfinite(tr.df)) fail(EAHP_ENONFINITE, "non-finite slope in the line search");
 }
@@ -72,10 +77,10 @@ double secant_step(eahp_problem* pb, const z64* Phi, const z64* eta, double f0, 
   auto ev = [&](double t) {
     if (trials >= prm.ls_maxit) fail(EAHP_ELINESEARCH, "line search: no acceptable step");
     ++trials;
-    eval_trial(pb, Phi, eta, t, tr);
+    eval_trial(pb, Phi, eta, t, tr, prm.retraction);
   };
   auto ok = [&](double f, double df) { return f <= fbound && std::fabs(df) <= c * std::fabs(df0); };
-  line_prepare(pb, Phi, eta, pb->arena->line);
+  if (prm.retraction != EAHP_QR) line_prepare(pb, Phi, eta, pb->arena->line);
   double a = 0.0, dfa = df0;
   double b = tau0;
   ev(b);
@@ -155,7 +160,8 @@ struct eahp_solver {
   z64 *Lam = nullptr, *Lamt = nullptr;
   PointScalars sc;
   double rn = 0, mu = 0, tau_prev = 1.0;
-  double nmC = 0, nmQ = 1;  // EARGD: Zhang-Hager reference energy and its weight
+  double nmC = 0, nmQ = 1;  // EARGD, L2RCG: Zhang-Hager reference energy and its weight
+  PointScalars sct;         // scalars of the last accepted trial
   int it = 0, ls_trials = 0, fom_iters = 0;
   int64_t napply = 0, napply32 = 0;
   double seconds = 0;
@@ -227,13 +233,19 @@ void solver_init(eahp_solver* sv, const z64* Psi0) {
   retract(pb, Psi0, Psi0, 0.0, sv->Phi, sv->Fa);
   evaluate_point(pb, sv->Phi, sv->HPhi, sv->R, sv->Lam, &sv->sc);
   sv->rn = sv->sc.rnorm;
-  sv->mu = mu_for(sv, sv->rn, sv->Lam);
-  solver_gradient(sv, sv->Phi, sv->R, sv->Lam, sv->mu, sv->G);
-  axpby<double>(pb->ctx->stream, pb->ntot * pb->p, -1.0, sv->G, 0.0, sv->eta);
+  if (sv->prm.method == EAHP_L2RCG) {
+    axpby<double>(pb->ctx->stream, pb->ntot * pb->p, -1.0, sv->R, 0.0, sv->eta);
+  } else {
+    sv->mu = mu_for(sv, sv->rn, sv->Lam);
+    solver_gradient(sv, sv->Phi, sv->R, sv->Lam, sv->mu, sv->G);
+    axpby<double>(pb->ctx->stream, pb->ntot * pb->p, -1.0, sv->G, 0.0, sv->eta);
+  }
   sv->tau_prev = 1.0;
   sv->nmC = sv->sc.E;
   sv->nmQ = 1.0;
 }
+
+double nonmonotone_step(eahp_solver* sv, double tau, double dE);
 
 // One iteration of EARGD: d = -G, an alternating Barzilai-Borwein trial step
 // from S = Phi_k - Phi_{k-1}, Y = G_k - G_{k-1} (the first iteration tries 1),
@@ -274,27 +286,13 @@ void solver_iterate_gd(eahp_solver* sv) {
       tau = std::min(std::max(tau, 1e-10), 1e10);
     }
   }
-  int trials = 0;
-  PointScalars sct;
-  for (;;) {
-    if (trials >= prm.ls_maxit) fail(EAHP_ELINESEARCH, "backtracking: no acceptable step");
-    ++trials;
-    retract(pb, sv->Phi, sv->eta, tau, sv->Phit, *sv->Ft);
-    evaluate_energy(pb, sv->Phit, &sct);
-    if (sct.E <= sv->nmC + prm.nm_rho * tau * dE) break;
-    tau *= prm.nm_backtrack;
-  }
-  sv->ls_trials += trials;
-  complete_point(pb, sv->Phit, sv->HPhit, sv->Rt, sv->Lamt, &sct);
+  tau = nonmonotone_step(sv, tau, dE);
   std::swap(sv->Phi, sv->Phit);  // Phit keeps the previous iterate for the next step
   std::swap(sv->HPhi, sv->HPhit);
   std::swap(sv->R, sv->Rt);
   std::swap(sv->Lam, sv->Lamt);
-  sv->sc = sct;
+  sv->sc = sv->sct;
   sv->rn = sv->sc.rnorm;
-  const double Qn = prm.nm_theta * sv->nmQ + 1.0;
-  sv->nmC = (prm.nm_theta * sv->nmQ * sv->nmC + sv->sc.E) / Qn;
-  sv->nmQ = Qn;
   sv->mu = mu_for(sv, sv->rn, sv->Lam);
   solver_gradient(sv, sv->Phi, sv->R, sv->Lam, sv->mu, sv->TG);
   std::swap(sv->G, sv->TG);  // TG keeps G_{k-1}
@@ -341,7 +339,8 @@ void solver_iterate(eahp_solver* sv) {
   sv->mu = mu_for(sv, sv->rn, sv->Lam);
   // T_{tau eta}(G_old), before eta and G change
   axpby<double>(st, N, tau, sv->eta, 0.0, sv->xi);
-  transport_general(pb, sv->Phi, sv->xi, sv->G, *Facc, sv->TG);
+  if (prm.retraction == EAHP_QR) transport_qr(pb, sv->Phi, sv->G, *Facc, sv->TG);
+  else transport_general(pb, sv->Phi, sv->xi, sv->G, *Facc, sv->TG);
   z64* Gn = sv->Phit;  // the previous point's buffer is free
   solver_gradient(sv, sv->Phi, sv->R, sv->Lam, sv->mu, Gn);
   const double rgn = frame_dot(pb, sv->R, Gn);
@@ -353,6 +352,85 @@ void solver_iterate(eahp_solver* sv) {
   axpby<double>(st, N, -1.0, Gn, 0.0, sv->eta);
   axpby<double>(st, N, beta, sv->Tetat, 1.0, sv->eta);
   std::swap(sv->G, sv->Phit);
+  sv->tau_prev = tau;
+  ++sv->it;
+}
+
+// Energy-only trials of R_Phi(tau eta) with backtracking until the
+// non-monotone test E <= C + rho tau dE passes; the accepted point is left
+// in the trial buffers with H Phi, R, Lambda, and C, Q are updated.
+double nonmonotone_step(eahp_solver* sv, double tau, double dE) {
+  eahp_problem* pb = sv->pb;
+  const eahp_solve_params& prm = sv->prm;
+  int trials = 0;
+  PointScalars sct;
+  for (;;) {
+    if (trials >= prm.ls_maxit) fail(EAHP_ELINESEARCH, "backtracking: no acceptable step");
+    ++trials;
+    if (prm.retraction == EAHP_QR) retract_qr(pb, sv->Phi, sv->eta, tau, sv->Phit, *sv->Ft);
+    else retract(pb, sv->Phi, sv->eta, tau, sv->Phit, *sv->Ft);
+    evaluate_energy(pb, sv->Phit, &sct);
+    if (sct.E <= sv->nmC + prm.nm_rho * tau * dE) break;
+    tau *= prm.nm_backtrack;
+  }
+  sv->ls_trials += trials;
+  complete_point(pb, sv->Phit, sv->HPhit, sv->Rt, sv->Lamt, &sct);
+  sv->sct = sct;
+  const double Qn = prm.nm_theta * sv->nmQ + 1.0;
+  sv->nmC = (prm.nm_theta * sv->nmQ * sv->nmC + sct.E) / Qn;
+  sv->nmQ = Qn;
+  return tau;
+}
+
+// One iteration of L2RCG: the L2 gradient R as the gradient (no metric solve,
+// no preconditioner), the step from the quadratic model with the frozen-
+// potential Hessian, tau = -dE / h with h = 2 f sum_k w_k Re tr(eta^H (H eta -
+// eta Lambda)) (the previous step when h <= 0), safeguarded by non-monotone
+// backtracking; eta+ = -R+ + beta T(eta) with the hybrid FR-PRP beta on R.
+void solver_iterate_l2(eahp_solver* sv) {
+  eahp_problem* pb = sv->pb;
+  Counters cnt(sv);
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p;
+  const int64_t pp = (int64_t)p * p;
+  const int64_t N = pb->ntot * p;
+  const eahp_solve_params& prm = sv->prm;
+  if (!(frame_dot(pb, sv->R, sv->eta) < 0.0)) axpby<double>(st, N, -1.0, sv->R, 0.0, sv->eta);
+  const double dE = 2.0 * pb->occ * frame_dot_weighted(pb, sv->R, sv->eta);
+  // H eta - eta Lambda into G (unused by this method); V_eff is that of Phi
+  z64* He = sv->G;
+  apply_H_frame(pb, sv->eta, He, false, nullptr);
+  for (int ik = 0; ik < pb->nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    gemm_nn<double>(st, K.npw, p, p, sv->eta + o, K.npw, sv->Lam + ik * pp, p, 0, He + o, K.npw, -1.0, 0.0, 1.0);
+  }
+  const double h = 2.0 * pb->occ * frame_dot_weighted(pb, sv->eta, He);
+  double tau = h > 0.0 ? -dE / h : sv->tau_prev;
+  tau = std::min(std::max(tau, 1e-10), 1e10);
+  const double rr = frame_dot(pb, sv->R, sv->R);
+  tau = nonmonotone_step(sv, tau, dE);
+  // transports to the accepted point (trial buffers): T(eta) into Tetat, T(R) into TG
+  RetractFactors* Facc = sv->Ft;
+  axpby<double>(st, N, tau, sv->eta, 0.0, sv->xi);
+  if (prm.retraction == EAHP_QR) {
+    transport_qr(pb, sv->Phit, sv->eta, *Facc, sv->Tetat);
+    transport_qr(pb, sv->Phit, sv->R, *Facc, sv->TG);
+  } else {
+    transport_self(pb, sv->Phit, sv->eta, tau, *Facc, sv->Tetat);
+    transport_general(pb, sv->Phit, sv->xi, sv->R, *Facc, sv->TG);
+  }
+  std::swap(sv->Phi, sv->Phit);
+  std::swap(sv->HPhi, sv->HPhit);
+  std::swap(sv->R, sv->Rt);
+  std::swap(sv->Lam, sv->Lamt);
+  sv->sc = sv->sct;
+  sv->rn = sv->sc.rnorm;
+  const double rn2 = frame_dot(pb, sv->R, sv->R);
+  const double rtr = frame_dot(pb, sv->R, sv->TG);
+  const double beta = std::max(0.0, std::min(rn2 / rr, (rn2 - rtr) / rr));
+  axpby<double>(st, N, -1.0, sv->R, 0.0, sv->eta);
+  axpby<double>(st, N, beta, sv->Tetat, 1.0, sv->eta);
   sv->tau_prev = tau;
   ++sv->it;
 }
@@ -565,6 +643,28 @@ int eahp_transport(eahp_problem* pb, const void* Psi, const void* xi, const void
   });
 }
 
+int eahp_retract_qr(eahp_problem* pb, const void* Psi, const void* eta, double tau, void* Psi_out) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!Psi || !eta || !Psi_out) fail(EAHP_EINVAL, "null argument");
+    RetractFactors F;
+    retract_qr(pb, (const z64*)Psi, (const z64*)eta, tau, (z64*)Psi_out, F);
+    HIPCK(hipStreamSynchronize(pb->ctx->stream));
+  });
+}
+
+int eahp_transport_qr(eahp_problem* pb, const void* Psi, const void* xi, const void* v, void* Tv) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!Psi || !xi || !v || !Tv) fail(EAHP_EINVAL, "null argument");
+    RetractFactors F;
+    z64* Pn = frame(pb, 2);
+    retract_qr(pb, (const z64*)Psi, (const z64*)xi, 1.0, Pn, F);
+    transport_qr(pb, Pn, (const z64*)v, F, (z64*)Tv);
+    HIPCK(hipStreamSynchronize(pb->ctx->stream));
+  });
+}
+
 int eahp_linesearch(eahp_problem* pb, const void* Psi, const void* eta, double tau0, const eahp_solve_params* prm,
                     double* tau, void* Psi_out, int* trials) {
   return guarded([&] {
@@ -595,12 +695,13 @@ int eahp_solver_create(eahp_problem* pb, const void* Psi0, const eahp_solve_para
     if (!(prm.mu > 0) || !(prm.mu_warm > 0) || prm.fom_maxit <= 0 || prm.ls_maxit <= 0 ||
         !(prm.gamma > 0 && prm.gamma < 1))
       fail(EAHP_EINVAL, "bad solve parameters");
-    if (prm.method != EAHP_EARCG && prm.method != EAHP_EARGD) fail(EAHP_EINVAL, "unknown method");
-    if (prm.retraction != EAHP_POLAR) fail(EAHP_EINVAL, "unknown retraction");
-    if (prm.method == EAHP_EARGD &&
+    if (prm.method != EAHP_EARCG && prm.method != EAHP_EARGD && prm.method != EAHP_L2RCG)
+      fail(EAHP_EINVAL, "unknown method");
+    if (prm.retraction != EAHP_POLAR && prm.retraction != EAHP_QR) fail(EAHP_EINVAL, "unknown retraction");
+    if (prm.method != EAHP_EARCG &&
         !(prm.nm_rho > 0 && prm.nm_rho < 1 && prm.nm_backtrack > 0 && prm.nm_backtrack < 1 && prm.nm_theta >= 0 &&
           prm.nm_theta <= 1))
-      fail(EAHP_EINVAL, "bad EARGD parameters");
+      fail(EAHP_EINVAL, "bad backtracking parameters");
     sv = new eahp_solver;
     sv->pb = pb;
     sv->prm = prm;
@@ -617,6 +718,7 @@ int eahp_solver_step(eahp_solver* sv, int nsteps, eahp_stats* stats) {
     check_problem(sv->pb);
     for (int i = 0; i < nsteps && !solver_converged(sv); ++i) {
       if (sv->prm.method == EAHP_EARGD) solver_iterate_gd(sv);
+      else if (sv->prm.method == EAHP_L2RCG) solver_iterate_l2(sv);
       else solver_iterate(sv);
     }
   });

@@ -153,12 +153,10 @@ __global__ void __launch_bounds__(1024) k_heev(int n, z64* Ab, int64_t lda, int6
   if (tid == 0 && info) info[blockIdx.x] = sweeps >= 40 ? 1 : 0;
 }
 
-bool heev_lds(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V,
-              int64_t ldv, int64_t sV, int batch, DevMem& logbuf);
 bool heev_dc(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
              int64_t sV, int batch, DevMem& scr);
 bool pchol_inv_reg(hipStream_t st, int n, const z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* U,
-                   int64_t ldu, DevMem& scr);
+                   int64_t ldu, DevMem& scr, bool pivot);
 
 void heev(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
           int64_t sV, int batch, int* info, DevMem& scr) {
@@ -364,7 +362,7 @@ void inverse(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, z64* work, 
 // G (n x n Hermitian PSD) is overwritten by the pivoted factor.  Outputs
 // Uinv (n x r, ld ldu): row piv[k] holds row k of L^-H, other rows zero.
 __global__ void __launch_bounds__(1024) k_pchol(int n, z64* G, int64_t ldg, double tol, int* pivout, int* rank,
-                                                z64* Uinv, int64_t ldu, int* info) {
+                                                z64* Uinv, int64_t ldu, int* info, int pivot) {
   extern __shared__ unsigned char smem_raw[];
   int* perm = reinterpret_cast<int*>(smem_raw);  // n
   __shared__ int rk, pk;
@@ -387,9 +385,13 @@ __global__ void __launch_bounds__(1024) k_pchol(int n, z64* G, int64_t ldg, doub
     if (tid == 0) {
       double best = -1.0;
       int b = k;
-      for (int i = k; i < n; ++i) {
-        const double v = G[i + (int64_t)i * ldg].x;
-        if (v > best) { best = v; b = i; }
+      if (pivot) {
+        for (int i = k; i < n; ++i) {
+          const double v = G[i + (int64_t)i * ldg].x;
+          if (v > best) { best = v; b = i; }
+        }
+      } else {
+        best = G[k + (int64_t)k * ldg].x;
       }
       if (k == 0) d0 = best;
       pk = b;
@@ -474,13 +476,13 @@ __global__ void __launch_bounds__(1024) k_pchol(int n, z64* G, int64_t ldg, doub
 }
 
 void pchol_inv(hipStream_t st, int n, z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* Uinv, int64_t ldu,
-               int* info, DevMem& scr) {
+               int* info, DevMem& scr, bool pivot) {
   if (n <= 0) return;
-  if (pchol_inv_reg(st, n, G, ldg, tol, piv, rank, Uinv, ldu, scr)) return;
+  if (pchol_inv_reg(st, n, G, ldg, tol, piv, rank, Uinv, ldu, scr, pivot)) return;
   const size_t lds = (size_t)n * sizeof(int) + 64;
   HIPCK(hipFuncSetAttribute((const void*)k_pchol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_pchol, dim3(1), dim3(n <= 64 ? 256 : 1024), lds, st, n, G, ldg, tol, piv, rank, Uinv, ldu,
-                     info);
+                     info, pivot ? 1 : 0);
   HIPCK(hipGetLastError());
 }
 
@@ -495,6 +497,32 @@ __global__ void k_sylv_divide(int q, int p, const double* w, const double* s, z6
 void sylv_divide(hipStream_t st, int q, int p, const double* w, const double* s, z64* Y, int64_t ldy) {
   if (q * p <= 0) return;
   hipLaunchKernelGGL(k_sylv_divide, dim3(std::min(1024, (q * p + 255) / 256)), dim3(256), 0, st, q, p, w, s, Y, ldy);
+  HIPCK(hipGetLastError());
+}
+
+// D = Omega(M) - M: zero below the diagonal, -conj(M_ji) - M_ij above, -Re M_jj on it
+__global__ void k_qr_omega_minus(int p, const z64* Mb, int64_t ldm, int64_t sM, z64* Db, int64_t ldd, int64_t sD) {
+  const z64* M = Mb + blockIdx.y * sM;
+  z64* D = Db + blockIdx.y * sD;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < p * p; e += gridDim.x * blockDim.x) {
+    const int i = e % p, j = e / p;
+    const z64 m = M[i + (int64_t)j * ldm];
+    z64 d;
+    if (i > j) {
+      d = mk<double>(0.0, 0.0);
+    } else if (i == j) {
+      d = mk<double>(-m.x, 0.0);
+    } else {
+      const z64 t = M[j + (int64_t)i * ldm];
+      d = mk<double>(-t.x - m.x, t.y - m.y);
+    }
+    D[i + (int64_t)j * ldd] = d;
+  }
+}
+void qr_omega_minus(hipStream_t st, int p, const z64* M, int64_t ldm, int64_t sM, z64* D, int64_t ldd, int64_t sD,
+                    int batch) {
+  hipLaunchKernelGGL(k_qr_omega_minus, dim3(std::min(1024, (p * p + 255) / 256), batch), dim3(256), 0, st, p, M, ldm,
+                     sM, D, ldd, sD);
   HIPCK(hipGetLastError());
 }
 

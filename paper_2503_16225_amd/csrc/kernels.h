@@ -107,9 +107,17 @@ void heev(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, double* w, int
 void inverse(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, z64* work, int batch, int* info);
 // Pivoted Cholesky of a Hermitian PSD G (n x n): G[piv, piv] = L L^H with rank r
 // (diagonal pivots below tol * first pivot are dropped); outputs the upper
-// triangular inverse factor U = L^-H padded (n x r), piv and r.
+// triangular inverse factor U = L^-H padded (n x r), piv and r.  With pivot =
+// false the pivots are taken in order (piv = identity, G = L L^H, U = R^-1 for
+// the Cholesky factor R = L^H) and r is the number of positive pivots before
+// the first non-positive one.
 void pchol_inv(hipStream_t st, int n, z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* Uinv,
-               int64_t ldu, int* info, DevMem& scr);
+               int64_t ldu, int* info, DevMem& scr, bool pivot = true);
+// qR retraction support: D = Omega(M) - M for a p x p M (batch), where Omega is the
+// skew-Hermitian matrix with the strictly lower triangle of M, minus its
+// conjugate transpose above, and i Im(M_jj) on the diagonal.
+void qr_omega_minus(hipStream_t st, int p, const z64* M, int64_t ldm, int64_t sM, z64* D, int64_t ldd, int64_t sD,
+                    int batch);
 // Elementwise helpers on small matrices (n x m, column-major).
 // Y = Q^H C U-ish products use gemm; these handle the spectral divisions.
 void sylv_divide(hipStream_t st, int q, int p, const double* w, const double* s, z64* Y, int64_t ldy);

@@ -1,6 +1,6 @@
 // Manifold operations on frames, per k-point: polar retraction (eqs. (3.1)-(3.2)),
 // differentiated-retraction transports (Prop. 3.1 and its closed form for
-// xi = tau eta, Sec. 3.2), the energy-adaptive gradient (Sec. 5.2) and the
+// xi = tau eta, Sec. 3.2), the qR retraction and its differentiated transport, the energy-adaptive gradient (Sec. 5.2) and the
 // preconditioned block FOM for the Sylvester equation (Appendix A, Algorithm 4).
 #include <algorithm>
 #include <cmath>
@@ -112,6 +112,71 @@ bool retract_line(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, 
     gemm_nn<double>(st, K.npw, p, p, Psi + o, K.npw, F.Sinv.as<z64>() + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0, 0.0);
   }
   return true;
+}
+
+// ---------------------------------------------------------------- qR retraction
+// qf(Phi + tau eta) = Psi R^-1 with Psi^H Psi = R^H R (R upper triangular with a
+// positive diagonal), the Gram-Schmidt retraction the paper names as the
+// alternative to the polar one (Sec. 3.1).  R^-1 per k goes to F.Sinv.
+void retract_qr(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* out, RetractFactors& F) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p, nk = pb->nk;
+  const int64_t pp = (int64_t)p * p;
+  const int64_t N = pb->ntot * p;
+  F.Sinv.ensure(sizeof(z64) * nk * pp);
+  Scratch& s = pb->arena->s;
+  s.a.ensure(sizeof(z64) * N);
+  s.b.ensure(sizeof(z64) * nk * pp);
+  s.g.ensure(sizeof(int) * (size_t)nk * (p + 1));
+  z64* Psi = s.a.as<z64>();
+  z64* Gm = s.b.as<z64>();
+  int* piv = s.g.as<int>();
+  int* rank = pb->d_info.as<int>();
+  if (nk > 1024) fail(EAHP_EINVAL, "too many k-points for the qR retraction");
+  axpby<double>(st, N, 1.0, Phi, 0.0, Psi);
+  axpby<double>(st, N, tau, eta, 1.0, Psi);
+  for (int ik = 0; ik < nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    gemm_hn<double>(st, K.npw, p, p, Psi + o, K.npw, Psi + o, K.npw, Gm + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
+    pchol_inv(st, p, Gm + ik * pp, p, 0.0, piv + (size_t)ik * p, rank + ik, F.Sinv.as<z64>() + ik * pp, p, nullptr,
+              pb->ws.chol, false);
+    gemm_nn<double>(st, K.npw, p, p, Psi + o, K.npw, F.Sinv.as<z64>() + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0,
+                    0.0);
+  }
+  HIPCK(hipMemcpyAsync(pb->h_info, rank, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  for (int ik = 0; ik < nk; ++ik)
+    if (pb->h_info[ik] != p) fail(EAHP_ENOTPD, "retraction Gram matrix not positive definite");
+}
+
+// Differentiated qR retraction at the new point Q = qf(psi) with psi = Q R:
+// with M = Q^H v R^-1, D qf(psi)[v] = v R^-1 + Q (Omega(M) - M), Omega(M) the
+// skew-Hermitian part fixed by M's strictly lower triangle and the imaginary
+// part of its diagonal.  Needs only F.Sinv = R^-1 of the retraction.
+void transport_qr(eahp_problem* pb, const z64* Q, const z64* v, const RetractFactors& F, z64* out) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p, nk = pb->nk;
+  const int64_t pp = (int64_t)p * p;
+  Scratch& s = pb->arena->s;
+  s.d.ensure(sizeof(z64) * nk * pp);
+  s.e.ensure(sizeof(z64) * nk * pp);
+  z64* W = s.d.as<z64>();
+  z64* M = s.e.as<z64>();
+  const z64* Rinv = F.Sinv.as<z64>();
+  for (int ik = 0; ik < nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    gemm_hn<double>(st, K.npw, p, p, Q + o, K.npw, v + o, K.npw, W + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
+  }
+  gemm_nn<double>(st, p, p, p, W, p, Rinv, p, 0, M, p, 1.0, 0.0, 0.0, nk, pp, pp, pp);
+  qr_omega_minus(st, p, M, p, pp, W, p, pp, nk);  // W <- Omega(M) - M
+  for (int ik = 0; ik < nk; ++ik) {
+    auto& K = pb->kp[ik];
+    const int64_t o = (int64_t)p * K.off;
+    gemm_nn<double>(st, K.npw, p, p, v + o, K.npw, Rinv + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0, 0.0);
+    gemm_nn<double>(st, K.npw, p, p, Q + o, K.npw, W + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0, 1.0);
+  }
 }
 
 void lambda_eig(eahp_problem* pb, const z64* Lam, LamEig& E) {

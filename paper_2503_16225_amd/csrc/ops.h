@@ -44,6 +44,10 @@ struct RetractFactors {
   DevMem d, V, Sinv;
 };
 void retract(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* out, RetractFactors& F);
+// qR retraction qf(Phi + tau eta) (R^-1 per k in F.Sinv) and its differentiated
+// transport of v at the new point Q (uses F.Sinv of the same retraction).
+void retract_qr(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* out, RetractFactors& F);
+void transport_qr(eahp_problem* pb, const z64* Q, const z64* v, const RetractFactors& F, z64* out);
 // Retraction along a fixed direction eta at Phi: the Gram matrix of Phi + tau eta
 // is S(tau) = (I + tau^2 eta^H eta) + Delta(tau) with the rounding-level
 // Delta = (Phi^H Phi - I) + tau (Phi^H eta + eta^H Phi).  One eigendecomposition

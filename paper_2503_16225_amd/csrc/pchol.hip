@@ -1,6 +1,7 @@
 // Diagonally pivoted Cholesky factorisation with rank cut-off and the inverse
 // of the factor, for the rank-revealing orthonormalisation of the block FOM
-// (CholQR on the Gram matrix of a block): G[piv, piv] = L L^H, pivots below
+// (CholQR on the Gram matrix of a block) and, unpivoted, for the qR
+// retraction: G[piv, piv] = L L^H, pivots below
 // tol times the first one end the factorisation (rank r), and the output is
 // U = P L^-H (n x r; row piv[k] of U holds row k of L^-H), so that R U has
 // orthonormal columns spanning the retained directions of R.
@@ -24,7 +25,8 @@ __device__ __forceinline__ z64 cmulz(z64 a, z64 b) { return mk<double>(a.x * b.x
 
 __global__ void __launch_bounds__(1024) k_pchol_reg(int n, const z64* __restrict__ G, int64_t ldg, double tol,
                                                     int* __restrict__ piv, int* __restrict__ rank_out,
-                                                    z64* __restrict__ U, int64_t ldu, z64* __restrict__ Lg) {
+                                                    z64* __restrict__ U, int64_t ldu, z64* __restrict__ Lg,
+                                                    int pivot) {
   __shared__ double cv[16];
   __shared__ int ci[16];
   __shared__ int done[kPcMax];
@@ -55,7 +57,7 @@ __global__ void __launch_bounds__(1024) k_pchol_reg(int n, const z64* __restrict
   for (int k = 0; k < n; ++k) {
     // pivot: largest remaining diagonal (ties: smallest index); arg-max in
     // every wave, then over the 16 wave candidates in every wave
-    {
+    if (pivot) {
       const bool live = rr < n && !isp;
       double val = live ? dg : -1.0;
       int row = live ? rr : 1 << 20;
@@ -64,13 +66,22 @@ __global__ void __launch_bounds__(1024) k_pchol_reg(int n, const z64* __restrict
         cv[wv] = val;
         ci[wv] = row;
       }
+    } else if (rr == k && cg == 0) {
+      cv[0] = dg;  // pivots in order: row k
     }
     __syncthreads();
-    double best = lane < 16 ? cv[lane] : -2.0;
-    int b = lane < 16 ? ci[lane] : 1 << 20;
-    row16_argmax(best, b);
-    best = readlane_f64(best, 0);
-    b = __builtin_amdgcn_readlane(b, 0);
+    double best;
+    int b;
+    if (pivot) {
+      best = lane < 16 ? cv[lane] : -2.0;
+      b = lane < 16 ? ci[lane] : 1 << 20;
+      row16_argmax(best, b);
+      best = readlane_f64(best, 0);
+      b = __builtin_amdgcn_readlane(b, 0);
+    } else {
+      best = cv[0];
+      b = k;
+    }
     if (k == 0) d0 = best;
     if (!(best > tol * d0) || !(best > 0.0)) {
       r = k;
@@ -170,10 +181,11 @@ __global__ void __launch_bounds__(1024) k_pchol_reg(int n, const z64* __restrict
 }
 
 bool pchol_inv_reg(hipStream_t st, int n, const z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* U,
-                   int64_t ldu, DevMem& scr) {
+                   int64_t ldu, DevMem& scr, bool pivot) {
   if (n < 1 || n > kPcMax) return false;
   scr.ensure(sizeof(z64) * (size_t)n * n);
-  hipLaunchKernelGGL(k_pchol_reg, dim3(1), dim3(1024), 0, st, n, G, ldg, tol, piv, rank, U, ldu, scr.as<z64>());
+  hipLaunchKernelGGL(k_pchol_reg, dim3(1), dim3(1024), 0, st, n, G, ldg, tol, piv, rank, U, ldu, scr.as<z64>(),
+                     pivot ? 1 : 0);
   HIPCK(hipGetLastError());
   return true;
 }

@@ -51,11 +51,11 @@ DEFAULT_PARAMS = dict(
     mu_warm=1.0,
     warm_rtol=1e-2,
     rank_tol=1e-7,
-    method=0,          # 0 EARCG (Algorithm 3), 1 EARGD
-    retraction=0,      # 0 polar (eq. (3.1))
-    nm_rho=1e-4,       # EARGD: Armijo constant of the non-monotone test
-    nm_backtrack=0.5,  # EARGD: backtracking factor
-    nm_theta=0.85,     # EARGD: weight of the Zhang-Hager reference energy
+    method=0,          # 0 EARCG (Algorithm 3), 1 EARGD, 2 L2RCG
+    retraction=0,      # 0 polar (eq. (3.1)), 1 qR
+    nm_rho=1e-4,       # EARGD, L2RCG: Armijo constant of the non-monotone test
+    nm_backtrack=0.5,  # EARGD, L2RCG: backtracking factor
+    nm_theta=0.85,     # EARGD, L2RCG: weight of the Zhang-Hager reference energy
 )
 
 # term switches (used by closed-form special cases)
