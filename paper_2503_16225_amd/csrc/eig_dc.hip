@@ -41,10 +41,12 @@ struct DcShared {
 // the calling group.  Returns tau with lam = dK[org] + tau.
 __device__ double secular_root(const double* dK, const double* zK, int K, double rho, int i, int lane8, int& org) {
   const bool last = i == K - 1;
+  // sum over the 8 lanes of the group (DPP within quads, then across the two
+  // quads of the 8 lanes; the 8 lanes of a group are active together)
   auto sum8 = [&](double v) {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
     return v;
   };
   double lo, hi;
@@ -182,16 +184,18 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
 
   // ------------------------------------------------------------ 1. tridiagonal form
   {
-    // per column k: xs = column k, vs = reflector vector, ps = tau A v; each
-    // double-buffered by the parity of k so that one barrier per phase suffices
+    // per column k: xs = column k, vs = the reflector, ps = tau A v, ws =
+    // p + alpha v (each double-buffered by the parity of k).  Waves 0 and 1
+    // (the rows) form the reflector and alpha with DPP wave sums; a wave whose
+    // eight rows all lie above the trailing block skips the products.
     z64* xsb = reinterpret_cast<z64*>(S.Qs);
     z64* vsb = xsb + 2 * kDcMax;
     z64* psb = vsb + 2 * kDcMax;
     z64* wsb = psb + 2 * kDcMax;
     z64* taus = wsb + 2 * kDcMax;  // 2
     const int lane = t & 63;
-    const int nw64 = 64 * ((n + 63) >> 6);  // whole waves covering the rows (shuffles need every lane)
-    z64 a[16];
+    const int wv = t >> 6;
+    d16 ar, ai;  // row r, columns cg + 8 m
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const int c = cg + 8 * m;
@@ -200,25 +204,27 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
         const z64 x = A[r + (int64_t)c * lda], y = A[c + (int64_t)r * lda];
         v = mk<double>(0.5 * (x.x + y.x), r == c ? 0.0 : 0.5 * (x.y - y.y));
       }
-      a[m] = v;
+      ar[m] = v.x;
+      ai[m] = v.y;
     }
     for (int k = 0; k < n - 1; ++k) {
       z64* xs = xsb + (k & 1) * kDcMax;
       z64* vs = vsb + (k & 1) * kDcMax;
       z64* ps = psb + (k & 1) * kDcMax;
       z64* ws = wsb + (k & 1) * kDcMax;
-      if (r < n) {
-#pragma unroll
-        for (int m = 0; m < 16; ++m)
-          if (cg + 8 * m == k) xs[r] = a[m];
-      }
+      const int km = __builtin_amdgcn_readfirstlane(k >> 3);
+      if (r < n && cg == (k & 7)) xs[r] = mk<double>(ar[km], ai[km]);
       __syncthreads();
-      // the reflector: waves 0 and 1 (threads t < n) each compute the scalars
-      if (t < nw64) {
+      // reflector H = I - tau v v^H with v_{k+1} = 1 that maps x[k+1:] to beta e_1
+      // (beta real), in waves 0 and 1 (vs[t] for t < 128)
+      if (t < kDcMax) {
         double sg = 0.0;
-        for (int i = k + 2 + lane; i < n; i += 64) sg += xs[i].x * xs[i].x + xs[i].y * xs[i].y;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) sg += __shfl_xor(sg, o, 64);
+        for (int h = 0; h < 2; ++h) {
+          const int i = lane + 64 * h;
+          if (i >= k + 2 && i < n) sg += xs[i].x * xs[i].x + xs[i].y * xs[i].y;
+        }
+        sg = wave_allsum(sg);
         const z64 al = xs[k + 1];
         double beta;
         z64 tau, inv;
@@ -234,72 +240,85 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
           const double m2 = dx * dx + dy * dy;
           inv = mk<double>(dx / m2, -dy / m2);
         }
-        if (t < n) {
-          z64 v;
-          if (t <= k) v = mk<double>(0.0, 0.0);
-          else if (t == k + 1) v = mk<double>(1.0, 0.0);
-          else v = cmulz(xs[t], inv);
-          vs[t] = v;
-          if (t > k) refl[t + (int64_t)k * n] = v;
-        }
+        const z64 v = (t <= k || t >= n) ? mk<double>(0.0, 0.0) : t == k + 1 ? mk<double>(1.0, 0.0) : cmulz(xs[t], inv);
+        vs[t] = v;
+        if (t > k && t < n) refl[t + (int64_t)k * n] = v;
         if (t == 0) {
-          rtau[k] = tau;
           taus[k & 1] = tau;
+          rtau[k] = tau;
           S.ee[k] = beta;
           S.dd[k] = xs[k].x;
         }
       }
       __syncthreads();
-      {
-        const z64 tau = taus[k & 1];
+      // rows of this wave in the trailing block at all (wave-uniform)
+      const bool active = __builtin_amdgcn_readfirstlane((8 * wv + 7 > k) ? 1 : 0) != 0;
+      // p_r = tau (A v)_r (8 lanes per row, DPP sums); v is zero at rows <= k
+      if (active) {
         z64 sv = mk<double>(0.0, 0.0);
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
-          const int c = cg + 8 * m;
-          if (c > k && c < n) sv = cadd<double>(sv, cmulz(a[m], vs[c]));
-        }
+        for (int mb = 0; mb < 16; mb += 4) {
+          z64 vw[4];
 #pragma unroll
-        for (int o = 1; o < 8; o <<= 1) {
-          sv.x += __shfl_xor(sv.x, o, 64);
-          sv.y += __shfl_xor(sv.y, o, 64);
+          for (int u = 0; u < 4; ++u) vw[u] = vs[cg + 8 * (mb + u)];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int m = mb + u;
+            sv.x += ar[m] * vw[u].x - ai[m] * vw[u].y;
+            sv.y += ar[m] * vw[u].y + ai[m] * vw[u].x;
+          }
         }
-        if (cg == 0 && r < n) ps[r] = r > k ? cmulz(tau, sv) : mk<double>(0.0, 0.0);
+        sv.x += dpp_f64<0xB1>(sv.x);
+        sv.y += dpp_f64<0xB1>(sv.y);
+        sv.x += dpp_f64<0x4E>(sv.x);
+        sv.y += dpp_f64<0x4E>(sv.y);
+        sv.x += dpp_f64<0x141>(sv.x);  // row_half_mirror: the other quad of the 8 lanes
+        sv.y += dpp_f64<0x141>(sv.y);
+        if (cg == 0) ps[r] = (r > k && r < n) ? cmulz(taus[k & 1], sv) : mk<double>(0.0, 0.0);
+      } else if (cg == 0) {
+        ps[r] = mk<double>(0.0, 0.0);
       }
       __syncthreads();
-      // w = p + alpha v with alpha = -tau (p^H v) / 2 (waves 0 and 1)
-      if (t < nw64) {
+      // w = p + alpha v with alpha = -tau (p^H v) / 2, in waves 0 and 1
+      if (t < kDcMax) {
         double dx = 0.0, dy = 0.0;
-        for (int i = k + 1 + lane; i < n; i += 64) {
-          dx += ps[i].x * vs[i].x + ps[i].y * vs[i].y;
-          dy += ps[i].x * vs[i].y - ps[i].y * vs[i].x;
-        }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          dx += __shfl_xor(dx, o, 64);
-          dy += __shfl_xor(dy, o, 64);
+        for (int h = 0; h < 2; ++h) {
+          const int i = lane + 64 * h;
+          const z64 pi = ps[i], vi = vs[i];
+          dx += pi.x * vi.x + pi.y * vi.y;
+          dy += pi.x * vi.y - pi.y * vi.x;
         }
+        dx = wave_allsum(dx);
+        dy = wave_allsum(dy);
         const z64 al2 = cscale<double>(cmulz(taus[k & 1], mk<double>(dx, dy)), -0.5);
-        if (t < n) ws[t] = cadd<double>(ps[t], cmulz(al2, vs[t]));
+        ws[t] = cadd<double>(ps[t], cmulz(al2, vs[t]));
       }
       __syncthreads();
-      // A -= v w^H + w v^H on the trailing block
-      if (r > k && r < n) {
+      // A -= v w^H + w v^H on the trailing block (v, w vanish outside rows and
+      // columns > k, so the rows of an active wave need no branch)
+      if (active) {
         const z64 vr = vs[r], wr = ws[r];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
-          const int c = cg + 8 * m;
-          if (c > k && c < n) {
-            const z64 vc = vs[c], wc = ws[c];
-            a[m] = csub<double>(a[m], cadd<double>(cmulz(vr, conjz(wc)), cmulz(wr, conjz(vc))));
+        for (int mb = 0; mb < 16; mb += 4) {
+          z64 vw[4], ww[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            vw[u] = vs[cg + 8 * (mb + u)];
+            ww[u] = ws[cg + 8 * (mb + u)];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int m = mb + u;
+            const z64 vc = vw[u], wc = ww[u];
+            // v_r conj(w_c) + w_r conj(v_c)
+            ar[m] -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
+            ai[m] -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
           }
         }
       }
     }
-    if (r == n - 1) {
-#pragma unroll
-      for (int m = 0; m < 16; ++m)
-        if (cg + 8 * m == n - 1) S.dd[n - 1] = a[m].x;
-    }
+    if (r == n - 1 && cg == ((n - 1) & 7)) S.dd[n - 1] = ar[__builtin_amdgcn_readfirstlane((n - 1) >> 3)];
     __syncthreads();
   }
 
@@ -471,9 +490,9 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
             acc += u * u;
           }
       }
-      acc += __shfl_xor(acc, 1, 64);
-      acc += __shfl_xor(acc, 2, 64);
-      acc += __shfl_xor(acc, 4, 64);
+      acc += dpp_f64<0xB1>(acc);
+      acc += dpp_f64<0x4E>(acc);
+      acc += dpp_f64<0x141>(acc);
       if (g < n && g - s < K && lane8 == 0) S.dd[g] = 1.0 / sqrt(acc);  // the diagonal of T is no longer needed
     }
     for (int g = t; g < n; g += blockDim.x) {
@@ -612,11 +631,12 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
           const int rr = rg + 8 * m;
           if (rr > k && rr < n) s = cadd<double>(s, cmulz(conjz(vk[rr]), zv[m]));
         }
-#pragma unroll
-        for (int o = 1; o < 8; o <<= 1) {
-          s.x += __shfl_xor(s.x, o, 64);
-          s.y += __shfl_xor(s.y, o, 64);
-        }
+        s.x += dpp_f64<0xB1>(s.x);  // sum over the 8 lanes of the column
+        s.y += dpp_f64<0xB1>(s.y);
+        s.x += dpp_f64<0x4E>(s.x);
+        s.y += dpp_f64<0x4E>(s.y);
+        s.x += dpp_f64<0x141>(s.x);
+        s.y += dpp_f64<0x141>(s.y);
         const z64 f = cmulz(tk, s);
 #pragma unroll
         for (int m = 0; m < 16; ++m) {

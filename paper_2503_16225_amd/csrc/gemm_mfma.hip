@@ -122,36 +122,57 @@ __global__ void __launch_bounds__(256) k_gemm_hn_mfma(int64_t n, int a, int b, c
       for (int s = 0; s < 4; ++s) P[(u * 2 + v) * 256 + lane * 4 + s] = mk<T>(cre[u][v][s], cim[u][v][s]);
 }
 
-// C = alpha sum_splits(partials) + beta C; one thread per fragment position
+// C = alpha sum_splits(partials) + beta C.  A work-group takes 16 consecutive
+// fragment positions; its 16 groups of 16 threads sum every 16th split each
+// (independent loads in flight), and the 16 group sums are added in a fixed
+// order, so the result does not depend on timing.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gemm_hn_mfma_reduce(int a, int b, int nsplit, const cplx<T>* __restrict__ part,
                                                              cplx<T>* C, int64_t ldc, double alpha, double beta,
                                                              int64_t sC) {
   using M = Mfma<T>;
+  __shared__ double sx[16][17], sy[16][17];
   const int tiles_a = (a + MT - 1) / MT;
   const int tiles = tiles_a * ((b + MT - 1) / MT);
   const int64_t per_split = (int64_t)tiles * 4 * 4 * 256;
   const int batch = blockIdx.y;
   C += batch * sC;
   const cplx<T>* P = part + (int64_t)batch * nsplit * per_split;
-  for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < per_split; f += (int64_t)gridDim.x * blockDim.x) {
-    const int s = (int)(f & 3), lane = (int)((f >> 2) & 63), uv = (int)((f >> 8) & 3), w = (int)((f >> 10) & 3);
-    const int tile = (int)(f >> 12);
-    const int ta = tile % tiles_a, tb = tile / tiles_a;
-    const int i = ta * MT + (w & 1) * 32 + (uv >> 1) * 16 + M::row(lane, s);
-    const int j = tb * MT + (w >> 1) * 32 + (uv & 1) * 16 + (lane & 15);
-    if (i >= a || j >= b) continue;
-    double sx = 0, sy = 0;
-    for (int sp = 0; sp < nsplit; ++sp) {
-      const cplx<T> v = P[sp * per_split + f];
-      sx += (double)v.x;
-      sy += (double)v.y;
+  const int j = threadIdx.x & 15, g = threadIdx.x >> 4;
+  for (int64_t f0 = (int64_t)blockIdx.x * 16; f0 < per_split; f0 += (int64_t)gridDim.x * 16) {
+    const int64_t f = f0 + j;
+    double ax = 0, ay = 0;
+    if (f < per_split) {
+      for (int sp = g; sp < nsplit; sp += 16) {
+        const cplx<T> v = P[sp * per_split + f];
+        ax += (double)v.x;
+        ay += (double)v.y;
+      }
     }
-    cplx<T>* c = C + i + (int64_t)j * ldc;
-    cplx<T> o;
-    if (beta == 0.0) o = mk<T>((T)(alpha * sx), (T)(alpha * sy));
-    else o = mk<T>((T)(alpha * sx + beta * (double)c->x), (T)(alpha * sy + beta * (double)c->y));
-    *c = o;
+    sx[g][j] = ax;
+    sy[g][j] = ay;
+    __syncthreads();
+    if (g == 0 && f < per_split) {
+      double tx = 0, ty = 0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        tx += sx[q][j];
+        ty += sy[q][j];
+      }
+      const int s = (int)(f & 3), lane = (int)((f >> 2) & 63), uv = (int)((f >> 8) & 3), w = (int)((f >> 10) & 3);
+      const int tile = (int)(f >> 12);
+      const int ta = tile % tiles_a, tb = tile / tiles_a;
+      const int i = ta * MT + (w & 1) * 32 + (uv >> 1) * 16 + M::row(lane, s);
+      const int jj = tb * MT + (w >> 1) * 32 + (uv & 1) * 16 + (lane & 15);
+      if (i < a && jj < b) {
+        cplx<T>* c = C + i + (int64_t)jj * ldc;
+        cplx<T> o;
+        if (beta == 0.0) o = mk<T>((T)(alpha * tx), (T)(alpha * ty));
+        else o = mk<T>((T)(alpha * tx + beta * (double)c->x), (T)(alpha * ty + beta * (double)c->y));
+        *c = o;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -303,7 +324,7 @@ void gemm_hn_mfma(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int
   hipLaunchKernelGGL((k_gemm_hn_mfma<T>), dim3(tiles, (unsigned)nsplit, batch), dim3(256), 0, st, n, a, b, A, lda, B,
                      ldb, rps, part.as<cplx<T>>(), sA, sB);
   HIPCK(hipGetLastError());
-  const int nb = (int)std::min<int64_t>(1024, (per_split + 255) / 256);
+  const int nb = (int)std::min<int64_t>(4096, (per_split + 15) / 16);
   hipLaunchKernelGGL((k_gemm_hn_mfma_reduce<T>), dim3(nb, batch), dim3(256), 0, st, a, b, (int)nsplit,
                      part.as<cplx<T>>(), C, ldc, alpha, beta, sC);
   HIPCK(hipGetLastError());
