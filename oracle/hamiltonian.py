@@ -27,6 +27,7 @@ import numpy as np
 import scipy.fft as sfft
 
 from . import basis as _basis
+from . import symmetry as _sym
 
 TERM_ION, TERM_HARTREE, TERM_XC, TERM_NONLOCAL = 1, 2, 4, 8
 
@@ -57,6 +58,9 @@ class Model:
         self.R = np.asarray(sysd["frac"], float) @ np.asarray(lat, float).T
         self.Vion_r = self._vion() if self.terms & TERM_ION else np.zeros(self.fft)
         self.proj = [self._projectors(b) for b in self.bases]
+        rot = sysd.get("sym_rot")
+        self.sym = [] if rot is None else [(np.asarray(W, dtype=np.int64).reshape(3, 3), np.asarray(t, float))
+                                           for W, t in zip(rot, sysd["sym_trans"])]
 
     # -- static potentials -------------------------------------------------
     def _vion(self):
@@ -112,13 +116,16 @@ class Model:
 # -- density and potentials ----------------------------------------------------
 def density(model, Phi, chunk=None):
     """rho(r_j) = sum_k w_k f sum_i |psi_ik(r_j)|^2 (columns taken `chunk` at a
-    time when given, which bounds the memory of the grid values)."""
+    time when given, which bounds the memory of the grid values); averaged over
+    the symmetry operations when the k-point set is a reduced one (A38)."""
     rho = np.zeros(model.fft)
     for ik, c in enumerate(model.blocks(Phi)):
         step = c.shape[1] if chunk is None else chunk
         for j0 in range(0, c.shape[1], step):
             psi = model.to_grid(ik, c[:, j0:j0 + step])
             rho += model.kw[ik] * model.occ * np.sum(np.abs(psi) ** 2, axis=0) / model.Omega
+    if len(model.sym) > 1:
+        rho = _sym.symmetrize(rho, model.sym)
     return rho
 
 
