@@ -14,8 +14,7 @@
 //  3. V = Q Z, applying the reflectors to the real eigenvector matrix Z of T.
 //
 // Eigenvalues ascending.  Global scratch per matrix: the reflectors (n x n
-// complex + n), the secular differences (n x n) and a staging copy of the
-// merged eigenvector blocks (n x n).
+// complex + n).
 #include "devcommon.h"
 #include "kernels.h"
 
@@ -175,9 +174,6 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
   double* scr = scrb + blockIdx.x * sscr;
   z64* refl = reinterpret_cast<z64*>(scr);            // n x n: column k holds v_k (rows k+1..n-1)
   z64* rtau = refl + (int64_t)n * n;                   // n
-  double* delta = reinterpret_cast<double*>(rtau + n);  // n x n
-  double* Qt = delta + (int64_t)n * n;                 // n x n
-  double* Ub = Qt + (int64_t)n * n;                    // n x n
 
   const int t = threadIdx.x;
   const int r = t >> 3, cg = t & 7;
@@ -334,7 +330,48 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
   __syncthreads();
   for (int size = 1; size < n; size *= 2) {
     const int nmerge = (n + 2 * size - 1) / (2 * size);
-    // A: gather z, sort the poles, deflate (one thread per merge)
+    // A1: merge the two ascending halves of every block and gather z, one
+    // thread per element: its output position is its index in its own half
+    // plus the count of smaller entries of the other half (ties: left half first)
+    for (int g = t; g < n; g += blockDim.x) {
+      const int mi = g / (2 * size), s = mi * 2 * size;
+      const int n1 = min(size, n - s), n2 = min(size, n - s - n1);
+      if (n2 <= 0) continue;
+      const int j = g - s;
+      const double x = S.D[g];
+      int lo, cnt;
+      if (j < n1) {  // entries of the right half strictly below x
+        lo = 0, cnt = n2;
+        while (cnt > 0) {
+          const int h = cnt >> 1;
+          if (S.D[s + n1 + lo + h] < x) {
+            lo += h + 1;
+            cnt -= h + 1;
+          } else {
+            cnt = h;
+          }
+        }
+      } else {  // entries of the left half at or below x
+        lo = 0, cnt = n1;
+        while (cnt > 0) {
+          const int h = cnt >> 1;
+          if (S.D[s + lo + h] <= x) {
+            lo += h + 1;
+            cnt -= h + 1;
+          } else {
+            cnt = h;
+          }
+        }
+      }
+      const int q = (j < n1 ? j : j - n1) + lo;
+      const double ev = S.ee[s + n1 - 1];
+      const double sg = ev >= 0.0 ? 1.0 : -1.0;
+      S.srt[s + q] = j;
+      S.dl[s + q] = x;
+      S.zz[s + q] = (j < n1 ? Q[(s + n1 - 1) + (s + j) * n] : sg * Q[(s + n1) + (s + j) * n]) * 0.7071067811865476;
+    }
+    __syncthreads();
+    // A2: deflate (one thread per merge)
     if (t < nmerge) {
       const int s = t * 2 * size;
       const int n1 = min(size, n - s), n2 = min(size, n - s - n1);
@@ -344,19 +381,7 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
       if (n2 > 0) {
         const int m = n1 + n2;
         const double ev = S.ee[s + n1 - 1];
-        const double sg = ev >= 0.0 ? 1.0 : -1.0;
         const double rho = 2.0 * fabs(ev);
-        const double isq2 = 0.7071067811865476;
-        // merge the two ascending halves
-        int i1 = 0, i2 = n1;
-        for (int q = 0; q < m; ++q) {
-          int j;
-          if (i2 >= m || (i1 < n1 && S.D[s + i1] <= S.D[s + i2])) j = i1++;
-          else j = i2++;
-          S.srt[s + q] = j;
-          S.dl[s + q] = S.D[s + j];
-          S.zz[s + q] = (j < n1 ? Q[(s + n1 - 1) + (s + j) * n] : sg * Q[(s + n1) + (s + j) * n]) * isq2;
-        }
         double dmax = 0.0, zmax = 0.0;
         for (int q = 0; q < m; ++q) {
           dmax = fmax(dmax, fabs(S.dl[s + q]));
@@ -442,36 +467,21 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
       }
     }
     __syncthreads();
-    // D: delta[i][j] = dK_j - lam_i (rows i, columns j of the block), global scratch
-    for (int e = t; e < n * n; e += blockDim.x) {
-      const int R = e % n, C = e / n;
-      const int mi = R / (2 * size), s = mi * 2 * size;
-      if (C / (2 * size) != mi) continue;
-      const int K = S.Km[mi], i = R - s, j = C - s;
-      if (i < K && j < K) delta[R + (int64_t)C * n] = (S.tv[s + j] - S.tv[s + S.org[R]]) - S.rc[R];
-    }
-    __syncthreads();
+    // The secular differences delta(root k, pole i) = dK_i - lambda_k are
+    // formed where needed as (dK_i - dK_org(k)) - tau_k (the root relative to
+    // its nearest pole, which keeps them accurate); U[i][k] = z^_i / delta(k, i).
     // E: Loewner weights z^_i (sign of z_i)
     for (int g = t; g < n; g += blockDim.x) {
       const int mi = g / (2 * size), s = mi * 2 * size, i = g - s;
       const int K = S.Km[mi];
       if (i < K) {
         const double* dK = S.tv + s;
-        // delta[i][j] at delta[(s+i) + (s+j) n]; dK_i - lam_j = delta[j][i]
-        double wv = delta[g + (int64_t)g * n];
+        const double di = dK[i];
+        double wv = (di - dK[S.org[g]]) - S.rc[g];
         for (int j = 0; j < K; ++j)
-          if (j != i) wv *= delta[(s + j) + (int64_t)g * n] / (dK[i] - dK[j]);
+          if (j != i) wv *= ((di - dK[S.org[s + j]]) - S.rc[s + j]) / (di - dK[j]);
         S.zh[g] = copysign(sqrt(fmax(-wv, 0.0)), S.nrm[g]);
       }
-    }
-    __syncthreads();
-    // U[i][k] = z^_i / (dK_i - lam_k) (unnormalised eigenvector k of the rank-one update)
-    for (int e = t; e < n * n; e += blockDim.x) {
-      const int R = e % n, C = e / n;
-      const int mi = R / (2 * size), s = mi * 2 * size;
-      if (C / (2 * size) != mi) continue;
-      const int K = S.Km[mi], i = R - s, k = C - s;
-      if (i < K && k < K) Ub[R + (int64_t)C * n] = S.zh[R] / delta[C + (int64_t)R * n];
     }
     __syncthreads();
     // F: column norms of U (8 lanes per column), the final order of each merged
@@ -484,11 +494,13 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
         const int mi = g / (2 * size);
         s = mi * 2 * size;
         K = S.Km[mi];
-        if (g - s < K)
+        if (g - s < K) {
+          const double lo = S.tv[s + S.org[g]], tk = S.rc[g];
           for (int i = lane8; i < K; i += 8) {
-            const double u = Ub[(s + i) + (int64_t)g * n];
+            const double u = S.zh[s + i] / ((S.tv[s + i] - lo) - tk);
             acc += u * u;
           }
+        }
       }
       acc += dpp_f64<0xB1>(acc);
       acc += dpp_f64<0x4E>(acc);
@@ -535,9 +547,11 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
       }
     }
     __syncthreads();
-    // G: merged eigenvectors into the staging copy; thread (row R, column
-    // group cgp) forms the roots k = cgp + 8 j of its block, two passes of 8
-    // accumulators, with rows of U staged in LDS 8 at a time
+    // G: merged eigenvectors, Q[:, block] <- Q[:, ra] U diag(dd) with the roots
+    // in output order and the deflated columns moved to theirs.  Thread (row R,
+    // column group cgp) forms the roots k = cgp + 8 j of its block; rows of U
+    // are computed into LDS 8 at a time.  Every thread reads only its own row
+    // of Q, so after a barrier the results go straight back into Q.
     {
       const int R = t & (kDcMax - 1), cgp = t >> 7;
       int kmax = 0;
@@ -546,54 +560,48 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
       const int n1 = min(size, n - s), n2 = min(size, n - s - n1);
       const bool valid = R < n && n2 > 0;
       const int K = valid ? S.Km[mi] : 0;
-      for (int j0 = 0; j0 < 16; j0 += 8) {
-        double acc[8];
+      const int m = n1 + n2;
+      double acc[16];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[j] = 0.0;
-        for (int i0 = 0; i0 < kmax; i0 += 8) {
-          __syncthreads();
-          {
-            const int ii = t >> 7, C = t & (kDcMax - 1);
-            double u = 0.0;
-            if (C < n) {
-              const int mc = C / (2 * size), sc = mc * 2 * size, Kc = S.Km[mc];
-              if (i0 + ii < Kc && C - sc < Kc) u = Ub[(sc + i0 + ii) + (int64_t)C * n];
-            }
-            S.Uc[ii * kDcMax + C] = u;
+      for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+      for (int i0 = 0; i0 < kmax; i0 += 8) {
+        __syncthreads();
+        {
+          const int ii = t >> 7, C = t & (kDcMax - 1);
+          double u = 0.0;
+          if (C < n) {
+            const int mc = C / (2 * size), sc = mc * 2 * size, Kc = S.Km[mc];
+            const int i = i0 + ii;
+            if (i < Kc && C - sc < Kc) u = S.zh[sc + i] / ((S.tv[sc + i] - S.tv[sc + S.org[C]]) - S.rc[C]);
           }
-          __syncthreads();
-          if (valid) {
-            for (int ii = 0; ii < 8 && i0 + ii < K; ++ii) {
-              const double qv = Q[R + S.ra[s + i0 + ii] * n];
-              const double* urow = S.Uc + ii * kDcMax + s;
-#pragma unroll
-              for (int j = 0; j < 8; ++j) acc[j] += qv * urow[min(cgp + 8 * (j0 + j), kDcMax - 1 - s)];
-            }
-          }
+          S.Uc[ii * kDcMax + C] = u;
         }
+        __syncthreads();
         if (valid) {
+          for (int ii = 0; ii < 8 && i0 + ii < K; ++ii) {
+            const double qv = Q[R + S.ra[s + i0 + ii] * n];
+            const double* urow = S.Uc + ii * kDcMax + s;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int k = cgp + 8 * (j0 + j);
-            if (k < K) Qt[R + (int64_t)(s + S.rb[s + k]) * n] = acc[j] * S.dd[s + k];
+            for (int j = 0; j < 16; ++j) acc[j] += qv * urow[min(cgp + 8 * j, kDcMax - 1 - s)];
           }
         }
       }
+      double dfv[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int q = cgp + 8 * j;
+        const int o = (valid && q < m) ? S.outk[s + q] : 0;
+        dfv[j] = o < 0 ? Q[R + (-o - 1) * n] : 0.0;
+      }
+      __syncthreads();  // every row of Q has been read
       if (valid) {
-        const int m = n1 + n2;
-        for (int q = cgp; q < m; q += 8) {
-          const int o = S.outk[s + q];
-          if (o < 0) Qt[R + (int64_t)(s + q) * n] = Q[R + (-o - 1) * n];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int k = cgp + 8 * j;
+          if (k < K) Q[R + (s + S.rb[s + k]) * n] = acc[j] * S.dd[s + k];
+          if (k < m && S.outk[s + k] < 0) Q[R + (s + k) * n] = dfv[j];
         }
       }
-    }
-    __syncthreads();
-    for (int e = t; e < n * n; e += blockDim.x) {
-      const int R = e % n, C = e / n;
-      const int mi = C / (2 * size), s = mi * 2 * size;
-      const int n1 = min(size, n - s), n2 = min(size, n - s - n1);
-      if (n2 <= 0 || R / (2 * size) != mi) continue;
-      Q[R + C * n] = Qt[R + (int64_t)C * n];
     }
     __syncthreads();
   }
@@ -656,7 +664,7 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
   }
 }
 
-size_t heev_dc_scratch(int n) { return sizeof(double) * ((size_t)5 * n * n + 2 * n) + 256; }
+size_t heev_dc_scratch(int n) { return sizeof(z64) * ((size_t)n * n + n) + 256; }
 
 bool heev_dc(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
              int64_t sV, int batch, DevMem& scr) {
