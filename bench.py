@@ -31,8 +31,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_NAMES = ["inv_yz", "x_local", "fwd_yz", "x_density", "inv_yz_f32", "x_local_f32", "fwd_yz_f32"]
 # HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain
 # device copy) measured at si64_gamma_e20 for the kernels built from sources
-# with this SHA-1 (hamiltonian.hip + devcommon.h); reported as null once the
-# sources differ.
+# with this SHA-1 (hamiltonian.hip + devcommon.h + regfft.h); reported as null
+# once the sources differ.
 MEASURED_TRAFFIC = {
     "sources_sha1": "b74bac1b2587f214eb65077f1ed1408f57763948",
     "config": "si64_gamma_e20",
@@ -44,7 +44,7 @@ def measured_traffic(kernel, config):
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha1()
-    for f in ("hamiltonian.hip", "devcommon.h"):
+    for f in ("hamiltonian.hip", "devcommon.h", "regfft.h"):
         with open(os.path.join(here, "paper_2503_16225_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if h.hexdigest() != MEASURED_TRAFFIC["sources_sha1"] or config != MEASURED_TRAFFIC["config"]:

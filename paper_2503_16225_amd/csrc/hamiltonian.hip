@@ -22,6 +22,7 @@
 
 #include "devcommon.h"
 #include "kernels.h"
+#include "regfft.h"
 
 namespace eahp {
 
@@ -446,6 +447,138 @@ void launch_fwd_yz(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& 
   HIPCK(hipGetLastError());
 }
 
+// ------------------------------------------------------------------ x_local, register x-transform
+// The same operation as k_x_local for n1 = N1 N2 (both products of at most two
+// of 2, 3, 4, 5), with the x-transform as a four-step DFT in registers:
+// j = N2 j1 + j2, k = k1 + N1 k2,
+//   z(k1; j2) = w_n^{j2 k1} sum_j1 w_N1^{j1 k1} x(N2 j1 + j2),
+//   y(k1 + N1 k2) = sum_j2 w_N2^{j2 k2} z(k1; j2).
+// One wave per work-group, 16 (i2, i3) lines per wave, lane = line + 16 grp.
+// Step A (the lane's j2 = grp + 4a): loads of the active planes straight from
+// the slab (16 consecutive positions per plane), size-N1 DFTs, twiddles, to
+// LDS.  Step B (k1 = grp + 4b): size-N2 DFTs, times V_eff (held in registers
+// for the work-group's columns), inverse size-N2 DFTs, twiddles, to LDS.
+// Step A': inverse size-N1 DFTs, stores of the active planes.  An LDS location
+// (k1, j2, line) is touched by one lane in steps A and A' and by one lane in
+// step B, so the two barriers between the steps are the only ones.
+template <typename T, int N1, int N2>
+__global__ void __launch_bounds__(64) k_x_local_reg(int ncols, int cb, GridGeom g, const cplx<T>* __restrict__ twx,
+                                                    const T* __restrict__ V, cplx<T>* __restrict__ Tb) {
+  constexpr int n1 = N1 * N2, L = 16, G = 4;
+  constexpr int JA = (N2 + G - 1) / G, KB = (N1 + G - 1) / G;
+  __shared__ cplx<T> buf[n1 * L];
+  __shared__ cplx<T> tw[n1];
+  __shared__ int sidx[n1];
+  const int lane = threadIdx.x, t = lane & (L - 1), grp = lane >> 4;
+  const int np = g.n2 * g.n3;
+  const int pos = blockIdx.x * L + t;
+  const bool valid = pos < np;
+  for (int i = lane; i < n1; i += 64) {
+    tw[i] = twx[i];
+    sidx[i] = -1;
+  }
+  __syncthreads();
+  for (int s = lane; s < g.ns; s += 64) sidx[g.plane_i1[s]] = s;
+  __syncthreads();
+  T vr[KB][N2];
+#pragma unroll
+  for (int b = 0; b < KB; ++b) {
+    const int k1 = grp + G * b;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2)
+      vr[b][k2] = (k1 < N1 && valid) ? V[(int64_t)(k1 + N1 * k2) * np + pos] : (T)0;
+  }
+  const int c0 = blockIdx.y * cb, c1 = min(ncols, c0 + cb);
+  for (int c = c0; c < c1; ++c) {
+    cplx<T>* col = Tb + (int64_t)c * g.ns * g.ps + pos;
+    cplx<T> u[JA][N1];
+#pragma unroll
+    for (int a = 0; a < JA; ++a) {
+      const int j2 = grp + G * a;
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) {
+        const int s = j2 < N2 ? sidx[N2 * j1 + j2] : -1;
+        u[a][j1] = (s >= 0 && valid) ? col[(int64_t)s * g.ps] : mk<T>(0, 0);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < JA; ++a) {
+      const int j2 = grp + G * a;
+      if (j2 < N2) {
+        RegFft<T, N1>::run(u[a], (T)1);
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) {
+          cplx<T> w = tw[j2 * k1];
+          w.y = -w.y;  // exp(+2 pi i j2 k1 / n1)
+          buf[(k1 * N2 + j2) * L + t] = cmul<T>(u[a][k1], w);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      const int k1 = grp + G * b;
+      if (k1 < N1) {
+        cplx<T> y[N2];
+#pragma unroll
+        for (int j2 = 0; j2 < N2; ++j2) y[j2] = buf[(k1 * N2 + j2) * L + t];
+        RegFft<T, N2>::run(y, (T)1);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) y[k2] = cscale<T>(y[k2], vr[b][k2]);
+        RegFft<T, N2>::run(y, (T)-1);
+#pragma unroll
+        for (int j2 = 0; j2 < N2; ++j2) buf[(k1 * N2 + j2) * L + t] = cmul<T>(y[j2], tw[j2 * k1]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < JA; ++a) {
+      const int j2 = grp + G * a;
+      if (j2 < N2) {
+        cplx<T> x[N1];
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) x[k1] = buf[(k1 * N2 + j2) * L + t];
+        RegFft<T, N1>::run(x, (T)-1);
+        if (valid) {
+#pragma unroll
+          for (int j1 = 0; j1 < N1; ++j1) {
+            const int s = sidx[N2 * j1 + j2];
+            if (s >= 0) col[(int64_t)s * g.ps] = x[j1];
+          }
+        }
+      }
+    }
+  }
+}
+
+// x-lengths with a register x-transform, as (n1, N1, N2)
+#define EAHP_XREG_SIZES(X)                                                                                     \
+  X(18, 3, 6) X(20, 4, 5) X(24, 4, 6) X(27, 3, 9) X(30, 5, 6) X(32, 4, 8) X(36, 6, 6) X(40, 5, 8) X(45, 5, 9)   \
+  X(48, 6, 8) X(50, 5, 10) X(54, 6, 9) X(60, 6, 10) X(64, 8, 8) X(72, 8, 9) X(75, 5, 15) X(80, 8, 10)          \
+  X(81, 9, 9) X(90, 9, 10) X(96, 8, 12) X(100, 10, 10) X(108, 9, 12) X(120, 10, 12) X(128, 8, 16) X(144, 12, 12)
+
+template <typename T>
+static bool launch_x_local_reg(hipStream_t st, int ncols, const GridGeom& g, const cplx<T>* twx, const T* V,
+                               cplx<T>* Tb) {
+  const int np = g.n2 * g.n3;
+  const int ntiles = (np + 15) / 16;
+  // columns per work-group: V is loaded once per work-group; keep >= 2048 work-groups
+  int cb = 8;
+  while (cb > 1 && (int64_t)ntiles * ((ncols + cb - 1) / cb) < 2048) cb /= 2;
+  dim3 grid(ntiles, (ncols + cb - 1) / cb);
+  switch (g.n1) {
+#define X(n, a, b)                                                                                           \
+  case n:                                                                                                    \
+    hipLaunchKernelGGL((k_x_local_reg<T, a, b>), grid, dim3(64), 0, st, ncols, cb, g, twx, V, Tb);             \
+    HIPCK(hipGetLastError());                                                                                \
+    return true;
+    EAHP_XREG_SIZES(X)
+#undef X
+    default:
+      return false;
+  }
+}
+
 static int x_tile(int n1, int np, size_t per_elem, size_t budget) {
   int tile = 64;
   while (tile > 8 && (size_t)n1 * tile * per_elem > budget) tile /= 2;
@@ -457,6 +590,7 @@ template <typename T>
 void launch_x_local(hipStream_t st, int ncols, const GridGeom& g, const FftPlan& px, const cplx<T>* twx,
                     const T* V, cplx<T>* Tb) {
   if (ncols <= 0) return;
+  if (launch_x_local_reg<T>(st, ncols, g, twx, V, Tb)) return;
   const int np = g.n2 * g.n3;
   // LDS per work-group bounds how many work-groups share a CU, and with them
   // how much of the slab traffic is in flight: about 36 KB gives four
@@ -490,9 +624,148 @@ __global__ void __launch_bounds__(256) k_sum_groups(int64_t n, int ngrp, const d
   }
 }
 
+// x_density with the register x-transform of k_x_local_reg (steps A and B of
+// the inverse transform), w_k f |psi|^2 / Omega accumulated in registers over
+// the work-group's columns, in column order.
+template <int N1, int N2>
+__global__ void __launch_bounds__(64) k_x_density_reg(ColMap cm, int ncols, int cpg, GridGeom g,
+                                                      const z64* __restrict__ twx, const z64* __restrict__ Tb,
+                                                      double occ_over_omega, double* __restrict__ rho, int accumulate,
+                                                      int64_t sgrp) {
+  constexpr int n1 = N1 * N2, L = 16, G = 4;
+  constexpr int JA = (N2 + G - 1) / G, KB = (N1 + G - 1) / G;
+  __shared__ z64 buf[n1 * L];
+  __shared__ z64 tw[n1];
+  __shared__ int sidx[n1];
+  const int lane = threadIdx.x, t = lane & (L - 1), grp = lane >> 4;
+  const int np = g.n2 * g.n3;
+  const int pos = blockIdx.x * L + t;
+  const bool valid = pos < np;
+  for (int i = lane; i < n1; i += 64) {
+    tw[i] = twx[i];
+    sidx[i] = -1;
+  }
+  __syncthreads();
+  for (int s = lane; s < g.ns; s += 64) sidx[g.plane_i1[s]] = s;
+  __syncthreads();
+  double acc[KB][N2];
+#pragma unroll
+  for (int b = 0; b < KB; ++b)
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) acc[b][k2] = 0.0;
+  const int cbeg = blockIdx.y * cpg, cend = min(ncols, cbeg + cpg);
+  rho += blockIdx.y * sgrp;
+  for (int c = cbeg; c < cend; ++c) {
+    int64_t base;
+    const KDesc& k = col_kd(cm, c, base);
+    const double wgt = k.w * occ_over_omega;
+    const z64* col = Tb + (int64_t)c * g.ns * g.ps + pos;
+    z64 u[JA][N1];
+#pragma unroll
+    for (int a = 0; a < JA; ++a) {
+      const int j2 = grp + G * a;
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) {
+        const int s = j2 < N2 ? sidx[N2 * j1 + j2] : -1;
+        u[a][j1] = (s >= 0 && valid) ? col[(int64_t)s * g.ps] : mk<double>(0, 0);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < JA; ++a) {
+      const int j2 = grp + G * a;
+      if (j2 < N2) {
+        RegFft<double, N1>::run(u[a], 1.0);
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) {
+          z64 w = tw[j2 * k1];
+          w.y = -w.y;
+          buf[(k1 * N2 + j2) * L + t] = cmul<double>(u[a][k1], w);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      const int k1 = grp + G * b;
+      if (k1 < N1) {
+        z64 y[N2];
+#pragma unroll
+        for (int j2 = 0; j2 < N2; ++j2) y[j2] = buf[(k1 * N2 + j2) * L + t];
+        RegFft<double, N2>::run(y, 1.0);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) acc[b][k2] += wgt * (y[k2].x * y[k2].x + y[k2].y * y[k2].y);
+      }
+    }
+    __syncthreads();  // the next column's step A writes locations read here by other lanes
+  }
+  if (valid) {
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      const int k1 = grp + G * b;
+      if (k1 < N1) {
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+          double* d = rho + (int64_t)(k1 + N1 * k2) * np + pos;
+          *d = accumulate ? *d + acc[b][k2] : acc[b][k2];
+        }
+      }
+    }
+  }
+}
+
+static bool launch_x_density_reg(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const z64* twx,
+                                 const z64* Tb, double occ_over_omega, double* rho, int accumulate, DevMem& part) {
+  switch (g.n1) {
+#define X(n, a, b) case n:
+    EAHP_XREG_SIZES(X)
+#undef X
+    break;
+    default:
+      return false;
+  }
+  const int np = g.n2 * g.n3;
+  const int ntiles = (np + 15) / 16;
+  // column groups until there are >= 2048 single-wave work-groups, while the
+  // partial densities (written and read once more) stay under a fifth of the
+  // slab bytes; each group sums into its own partial, reduced in a fixed order
+  int ngrp = 1;
+  while (ngrp < 16 && (int64_t)ntiles * ngrp < 2048 && (int64_t)(2 * ngrp) * g.n1 * 5 <= (int64_t)ncols * g.ns)
+    ngrp *= 2;
+  const int cpg = (ncols + ngrp - 1) / ngrp;
+  ngrp = (ncols + cpg - 1) / cpg;
+  const int64_t Ng = (int64_t)g.n1 * np;
+  double* dst = rho;
+  int acc_k = accumulate;
+  if (ngrp > 1) {
+    part.ensure(sizeof(double) * Ng * ngrp);
+    dst = part.as<double>();
+    acc_k = 0;
+  }
+  dim3 grid(ntiles, ngrp);
+  switch (g.n1) {
+#define X(n, a, b)                                                                                                 \
+  case n:                                                                                                          \
+    hipLaunchKernelGGL((k_x_density_reg<a, b>), grid, dim3(64), 0, st, cm, ncols, cpg, g, twx, Tb, occ_over_omega, \
+                       dst, acc_k, Ng);                                                                            \
+    break;
+    EAHP_XREG_SIZES(X)
+#undef X
+    default:
+      break;
+  }
+  HIPCK(hipGetLastError());
+  if (ngrp > 1) {
+    hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)std::min<int64_t>(2048, (Ng + 255) / 256)), dim3(256), 0, st, Ng,
+                       ngrp, part.as<double>(), Ng, rho, accumulate);
+    HIPCK(hipGetLastError());
+  }
+  return true;
+}
+
 void launch_x_density(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const FftPlan& px,
                       const z64* twx, const z64* Tb, double occ_over_omega, double* rho, int accumulate,
                       DevMem& part) {
+  if (launch_x_density_reg(st, cm, ncols, g, twx, Tb, occ_over_omega, rho, accumulate, part)) return;
   const int np = g.n2 * g.n3;
   const int tile = std::min(32, x_tile(g.n1, np, sizeof(z64), 48 * 1024));
   const size_t lds = (size_t)g.n1 * tile * sizeof(z64) + g.n1 * sizeof(z64);
