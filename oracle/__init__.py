@@ -18,7 +18,12 @@ Modules, in the order the method uses them:
                   (Appendix A, Algorithm 4)
 * ``linesearch``  modified secant step size strategy (Algorithm 2)
 * ``earcg``       energy-adaptive RCG (Algorithm 3)
-* ``scf``         dense SCF ground state used only as a pin
+* ``eargd``       energy-adaptive gradient descent (Sec. 5.2 comparison)
+* ``l2rcg``       L2-gradient RCG (Sec. 5.2 comparison)
+* ``symmetry``    crystal symmetry, symmetry-reduced k-sets and density
+                  symmetrisation (Sec. 5.1, periodic structures)
+* ``scf``         dense SCF ground state: a pin of the minimisers and the
+                  oracle of the SCF comparator (Sec. 5.2)
 
 Every function is pinned by the ``-m "not gpu"`` tests against closed forms,
 brute force or invariants; none is marked "parity unpinned".

@@ -66,7 +66,10 @@ def space_group(sysd, fft, symprec=1e-5):
     for W in lattice_rotations(lat):
         if any(W[a, b] != 0 and n[a] != n[b] for a in range(3) for b in range(3)):
             continue
-        cands = [frac[b] - W @ frac[0] for b in range(len(Z)) if Z[b] == Z[0]]
+        if len(Z) == 0:
+            cands = [np.zeros(3)]
+        else:
+            cands = [frac[b] - W @ frac[0] for b in range(len(Z)) if Z[b] == Z[0]]
         found = []
         for t in cands:
             t = t - np.floor(t)
