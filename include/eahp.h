@@ -84,6 +84,17 @@ typedef struct {
   double occ;            /* occupation per orbital (2 = doubly occupied)                */
   int precision;         /* EAHP_FP64 or EAHP_MIXED                                     */
   int terms;             /* bitwise or of EAHP_TERM_*                                   */
+  /* Symmetry of a reduced k-point set (Sec. 5.1: the k-grid divided by the
+   * symmetries of the crystal).  nsym <= 1: the k-set is used as given and the
+   * density is not symmetrised.  nsym > 1: operations x -> W x + t on
+   * fractional positions, as returned by eahp_symmetry_find; they must form a
+   * group, map every atom onto an atom of the same charge (within 1e-4 bohr)
+   * and map the FFT box onto itself (W_ab != 0 only where fft[a] = fft[b],
+   * fft[a] t_a an integer), else EAHP_EINVAL.  The density of the k-set is
+   * then averaged over the operations before the potentials are formed.    */
+  int nsym;              /* number of operations, at most 4096                          */
+  const int* sym_rot;    /* nsym x 9 integer rotations W, row-major (entries -1, 0, 1)  */
+  const double* sym_trans; /* nsym x 3 fractional translations t                        */
 } eahp_system_desc;
 
 /* Method constants (Sec. 5.2: delta, sigma, gamma, eps, mu, FOM tolerance). */
@@ -258,6 +269,73 @@ int eahp_server_poll(eahp_server* srv, uint64_t ticket, int* state, eahp_stats* 
 int eahp_server_result(eahp_server* srv, uint64_t ticket, void* Psi_host);
 int eahp_server_wait_all(eahp_server* srv);
 void eahp_server_destroy(eahp_server* srv);
+
+/* ---------------------------------------------------------------- SCF comparator
+ * Self-consistent field iteration, the method the paper compares EARCG with
+ * and runs to make the experiments' initial guesses (Sec. 5.2): the p lowest
+ * eigenpairs of every H_k at the potential of the current density (LOBPCG
+ * with the TPA preconditioner), the output density, Anderson mixing of the
+ * density (the nonlinear eigenvector problem of eq. (1.3) with the Aufbau
+ * principle, Sec. 2.1).
+ *
+ * eahp_scf: Psi_inout (frame, device) is the start block on entry (any full-
+ *   rank block per k) and the orthonormal eigenvector block of the last
+ *   potential on return.  Returns EAHP_ENOCONV when maxit is reached above
+ *   tol (Psi and stats are filled then too), EAHP_EINVAL for bad parameters
+ *   or fewer than 3 p plane waves at a k-point.
+ * eahp_eigensolve: the eigensolver alone: the potential is that of the
+ *   density of Psi_pot (frame, device; NULL keeps the current potential of
+ *   the problem); X_inout (frame) is the start block and receives the Ritz
+ *   vectors; eigvals (host, nk x p, ascending per k), iters (host, summed
+ *   over k) and rnorm (host, the largest ||H x - theta x||) may be NULL.    */
+typedef struct {
+  double tol;      /* stop when ||rho_out - rho_in||_2 over the cell <= tol               */
+  int maxit;       /* SCF iterations                                                    */
+  double beta;     /* damping of the mixed update, > 0                                   */
+  int depth;       /* Anderson history length 1..16 (1: damped simple mixing)            */
+  double eig_tol;  /* eigensolver stop: every ||H x - theta x|| <= eig_tol at every k;   */
+                   /* 0: adaptive, 0.1 x the last density residual within [1e-12, 1e-2] */
+  int eig_maxit;   /* eigensolver iterations per k-point and SCF step                   */
+} eahp_scf_params;
+typedef struct {
+  int iters;       /* SCF iterations done                                   */
+  int64_t napply;  /* orbital H-applies (one column at one k)               */
+  int eig_iters;   /* eigensolver iterations, summed over k and SCF steps   */
+  double energy;   /* energy of the returned block                          */
+  double res;      /* last ||rho_out - rho_in||_2                           */
+  double seconds;  /* wall time inside eahp_scf                             */
+} eahp_scf_stats;
+int eahp_scf(eahp_problem* pb, void* Psi_inout, const eahp_scf_params* prm, eahp_scf_stats* stats);
+int eahp_eigensolve(eahp_problem* pb, const void* Psi_pot, void* X_inout, double tol, int maxit, double* eigvals,
+                    int* iters, double* rnorm);
+
+/* ---------------------------------------------------------------- symmetry
+ * Host-only helpers for symmetry-reduced k-point sets (Sec. 5.1: K is the
+ * k1 k2 k3 points of the grid divided by the symmetries of the crystal).
+ *
+ * eahp_symmetry_find: the operations (W, t), x -> W x + t on fractional
+ *   positions, that map the crystal of desc onto itself: W integer with
+ *   entries in {-1, 0, 1} preserving the metric A^T A to 1e-8 relative, every
+ *   atom mapped onto an atom of the same charge within symprec (bohr, modulo
+ *   the lattice), and the FFT box of desc (fft[] = 0: the size eahp_problem_create
+ *   would choose) mapped onto itself.  Pure translations of a non-primitive
+ *   cell are operations too.  Order: W read row-major, lexicographic with
+ *   -1 < 0 < 1, then t ascending; t in [0, 1) is a multiple of 1/fft[a].
+ *   rot (max_ops x 9 ints) and trans (max_ops x 3 doubles) are host buffers
+ *   of the caller; *nsym receives the count, and EAHP_EINVAL is returned when
+ *   it exceeds max_ops (nothing is written to rot or trans then).
+ * eahp_kpoints_reduce: the orbits of the nk fractional k-points under
+ *   u -> W^T u for the distinct rotations of the nsym operations, and u -> -u
+ *   when time_reversal != 0, points equal modulo integers (1e-8).  Keeps, in
+ *   input order, the first point of every orbit with the summed weight of the
+ *   orbit: kfrac_out (nk x 3) and kweight_out (nk) receive *nk_out points,
+ *   kmap (nk) the kept index of every input point.  A set that is not closed
+ *   under the operations is EAHP_EINVAL.  All buffers are host memory of the
+ *   caller, sized for nk points.                                            */
+int eahp_symmetry_find(const eahp_system_desc* desc, double symprec, int max_ops, int* rot, double* trans,
+                       int* nsym);
+int eahp_kpoints_reduce(int nsym, const int* rot, int time_reversal, int nk, const double* kfrac,
+                        const double* kweight, double* kfrac_out, double* kweight_out, int* kmap, int* nk_out);
 
 const char* eahp_strerror(int status);
 const char* eahp_last_error(void);

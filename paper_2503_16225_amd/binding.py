@@ -31,7 +31,8 @@ class SystemDesc(C.Structure):
                 ("Z", C.POINTER(C.c_double)), ("r_loc", C.c_double), ("r_proj", C.c_double),
                 ("D_proj", C.c_double), ("ecut", C.c_double), ("fft", C.c_int * 3), ("nk", C.c_int),
                 ("kfrac", C.POINTER(C.c_double)), ("kweight", C.POINTER(C.c_double)), ("p", C.c_int),
-                ("occ", C.c_double), ("precision", C.c_int), ("terms", C.c_int)]
+                ("occ", C.c_double), ("precision", C.c_int), ("terms", C.c_int), ("nsym", C.c_int),
+                ("sym_rot", C.POINTER(C.c_int)), ("sym_trans", C.POINTER(C.c_double))]
 
 
 class SolveParams(C.Structure):
@@ -47,6 +48,26 @@ class SolveParams(C.Structure):
         for name, _ in cls._fields_:
             setattr(s, name, d[name])
         return s
+
+
+class ScfParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("beta", C.c_double), ("depth", C.c_int),
+                ("eig_tol", C.c_double), ("eig_maxit", C.c_int)]
+
+    @classmethod
+    def from_dict(cls, d):
+        s = cls()
+        for name, _ in cls._fields_:
+            setattr(s, name, d[name])
+        return s
+
+
+class ScfStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("napply", C.c_int64), ("eig_iters", C.c_int), ("energy", C.c_double),
+                ("res", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Stats(C.Structure):
@@ -103,6 +124,10 @@ def load_library():
         "eahp_server_result": ([vp, C.c_uint64, vp], C.c_int),
         "eahp_server_wait_all": ([vp], C.c_int),
         "eahp_server_destroy": ([vp], None),
+        "eahp_scf": ([vp, vp, C.POINTER(ScfParams), C.POINTER(ScfStats)], C.c_int),
+        "eahp_eigensolve": ([vp, vp, vp, C.c_double, C.c_int, dp, ip, dp], C.c_int),
+        "eahp_symmetry_find": ([C.POINTER(SystemDesc), C.c_double, C.c_int, ip, dp, ip], C.c_int),
+        "eahp_kpoints_reduce": ([C.c_int, ip, C.c_int, C.c_int, dp, dp, dp, dp, ip, ip], C.c_int),
         "eahp_strerror": ([C.c_int], C.c_char_p),
         "eahp_last_error": ([], C.c_char_p),
     }
@@ -166,7 +191,47 @@ def make_desc(sysd, precision=EAHP_FP64):
     d.occ = sysd["occ"]
     d.precision = precision
     d.terms = sysd.get("terms", 15)
+    rot = sysd.get("sym_rot")
+    if rot is not None and len(rot) > 1:
+        keep.append(np.ascontiguousarray(np.asarray(rot, dtype=np.int32).reshape(-1)))
+        keep.append(np.ascontiguousarray(np.asarray(sysd["sym_trans"], float).reshape(-1)))
+        d.nsym = len(rot)
+        d.sym_rot = keep[4].ctypes.data_as(C.POINTER(C.c_int))
+        d.sym_trans = keep[5].ctypes.data_as(C.POINTER(C.c_double))
     return d, keep
+
+
+def symmetry_find(sysd, symprec=1e-5):
+    """Symmetry operations of the crystal and FFT box of sysd (host only):
+    (rotations nsym x 3 x 3 int32, translations nsym x 3)."""
+    lib = load_library()
+    d, keep = make_desc(dict(sysd, sym_rot=None))
+    n = C.c_int()
+    rc = lib.eahp_symmetry_find(C.byref(d), symprec, 0, None, None, C.byref(n))
+    if rc != 0 and n.value == 0:
+        _check(rc)
+    rot = np.zeros((max(n.value, 1), 9), dtype=np.int32)
+    tr = np.zeros((max(n.value, 1), 3))
+    _check(lib.eahp_symmetry_find(C.byref(d), symprec, n.value, rot.ctypes.data_as(C.POINTER(C.c_int)),
+                                  tr.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)))
+    return rot[:n.value].reshape(-1, 3, 3), tr[:n.value]
+
+
+def kpoints_reduce(rot, kfrac, kweight, time_reversal=True):
+    """Symmetry-reduced k-set (host only): (kept points, weights, map input -> kept index)."""
+    lib = load_library()
+    r = np.ascontiguousarray(np.asarray(rot, dtype=np.int32).reshape(-1))
+    k = np.ascontiguousarray(np.asarray(kfrac, float).reshape(-1))
+    w = np.ascontiguousarray(np.asarray(kweight, float))
+    nk = len(w)
+    ko, wo = np.zeros(3 * nk), np.zeros(nk)
+    km = np.zeros(nk, dtype=np.int32)
+    n = C.c_int()
+    _check(lib.eahp_kpoints_reduce(len(r) // 9, r.ctypes.data_as(C.POINTER(C.c_int)), int(bool(time_reversal)), nk,
+                                   k.ctypes.data_as(C.POINTER(C.c_double)), w.ctypes.data_as(C.POINTER(C.c_double)),
+                                   ko.ctypes.data_as(C.POINTER(C.c_double)), wo.ctypes.data_as(C.POINTER(C.c_double)),
+                                   km.ctypes.data_as(C.POINTER(C.c_int)), C.byref(n)))
+    return ko.reshape(-1, 3)[:n.value].copy(), wo[:n.value].copy(), km
 
 
 def layout_estimate(sysd):
@@ -341,6 +406,24 @@ class Problem:
         rc = self.lib.eahp_solve(self.pb, _ptr(Psi), C.byref(prm), C.byref(st))
         _check(rc, allow=(-8,) if allow_noconv else ())
         return st.as_dict(), rc
+
+    def scf(self, Psi, params, allow_noconv=False):
+        """SCF iteration on the frame Psi (in place); returns (stats dict, status)."""
+        prm = ScfParams.from_dict(params)
+        st = ScfStats()
+        rc = self.lib.eahp_scf(self.pb, _ptr(Psi), C.byref(prm), C.byref(st))
+        _check(rc, allow=(-8,) if allow_noconv else ())
+        return st.as_dict(), rc
+
+    def eigensolve(self, Psi_pot, X, tol, maxit):
+        """Lowest p eigenpairs per k at the potential of Psi_pot's density (X in place):
+        (eigenvalues nk x p, iterations, largest residual norm)."""
+        ev = np.zeros(self.nk * self.p)
+        it = C.c_int()
+        rn = C.c_double()
+        _check(self.lib.eahp_eigensolve(self.pb, _ptr(Psi_pot), _ptr(X), tol, maxit,
+                                        ev.ctypes.data_as(C.POINTER(C.c_double)), C.byref(it), C.byref(rn)))
+        return ev.reshape(self.nk, self.p), it.value, rn.value
 
     def footprint(self):
         return int(self.lib.eahp_problem_footprint(self.pb))

@@ -451,6 +451,74 @@ void solver_stats(const eahp_solver* sv, eahp_stats* s) {
 // ====================================================================== C API
 extern "C" {
 
+int eahp_scf(eahp_problem* pb, void* Psi_inout, const eahp_scf_params* prm, eahp_scf_stats* stats) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!Psi_inout || !prm) fail(EAHP_EINVAL, "null argument");
+    scf_run(pb, static_cast<z64*>(Psi_inout), *prm, stats);
+  });
+}
+
+int eahp_eigensolve(eahp_problem* pb, const void* Psi_pot, void* X_inout, double tol, int maxit, double* eigvals,
+                    int* iters, double* rnorm) {
+  return guarded([&] {
+    check_problem(pb);
+    if (!X_inout || !(tol > 0) || maxit < 0) fail(EAHP_EINVAL, "bad argument");
+    if (Psi_pot) density_potentials(pb, static_cast<const z64*>(Psi_pot));
+    std::vector<double> th(pb->p);
+    int64_t napply = 0;
+    int its = 0;
+    double rmax = 0;
+    for (int ik = 0; ik < pb->nk; ++ik) {
+      double r = 0;
+      its += lobpcg_k(pb, ik, static_cast<z64*>(X_inout) + (int64_t)pb->p * pb->kp[ik].off, tol, maxit, th.data(),
+                      &r, &napply);
+      rmax = std::max(rmax, r);
+      if (eigvals) std::memcpy(eigvals + (size_t)ik * pb->p, th.data(), sizeof(double) * pb->p);
+    }
+    HIPCK(hipStreamSynchronize(pb->ctx->stream));
+    if (iters) *iters = its;
+    if (rnorm) *rnorm = rmax;
+  });
+}
+
+int eahp_symmetry_find(const eahp_system_desc* desc, double symprec, int max_ops, int* rot, double* trans,
+                       int* nsym) {
+  return guarded([&] {
+    if (!desc || !nsym || max_ops < 0 || (max_ops > 0 && (!rot || !trans))) fail(EAHP_EINVAL, "null argument");
+    std::vector<int64_t> npw;
+    int n[3], ns;
+    size_t bytes;
+    layout_estimate(desc, npw, n, ns, bytes);
+    std::vector<SymOp> ops;
+    find_symmetry(desc, n, symprec, ops);
+    *nsym = (int)ops.size();
+    if ((int)ops.size() > max_ops) fail(EAHP_EINVAL, "more operations than max_ops");
+    for (size_t g = 0; g < ops.size(); ++g) {
+      std::memcpy(rot + 9 * g, ops[g].W, sizeof(int) * 9);
+      std::memcpy(trans + 3 * g, ops[g].t, sizeof(double) * 3);
+    }
+  });
+}
+
+int eahp_kpoints_reduce(int nsym, const int* rot, int time_reversal, int nk, const double* kfrac,
+                        const double* kweight, double* kfrac_out, double* kweight_out, int* kmap, int* nk_out) {
+  return guarded([&] {
+    if (nsym < 0 || nk <= 0 || (nsym > 0 && !rot) || !kfrac || !kweight || !kfrac_out || !kweight_out || !kmap ||
+        !nk_out)
+      fail(EAHP_EINVAL, "null argument or empty set");
+    const int ident[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    std::vector<double> kout, wout;
+    std::vector<int> owner;
+    reduce_kpoints(nsym > 0 ? nsym : 1, nsym > 0 ? rot : ident, time_reversal != 0, nk, kfrac, kweight, kout, wout,
+                   owner);
+    std::memcpy(kfrac_out, kout.data(), sizeof(double) * kout.size());
+    std::memcpy(kweight_out, wout.data(), sizeof(double) * wout.size());
+    std::memcpy(kmap, owner.data(), sizeof(int) * nk);
+    *nk_out = (int)wout.size();
+  });
+}
+
 const char* eahp_strerror(int s) {
   switch (s) {
     case EAHP_OK: return "ok";

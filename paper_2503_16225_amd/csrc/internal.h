@@ -139,6 +139,10 @@ struct eahp_problem {
   // fields on the grid (double unless noted)
   eahp::DevMem d_vion, d_veff, d_veff32, d_rho, d_energy_dens;
   eahp::DevMem d_D;        // double[natoms] projector couplings
+  // symmetry of a reduced k-set: the box partitioned into orbits of the operations
+  int nsym = 0, norb = 0;
+  eahp::DevMem d_orb_start;  // int[norb + 1]
+  eahp::DevMem d_orb_idx;    // int[N_g] box indices, orbit by orbit
   // workspaces
   eahp::Workspace ws;
   eahp::Arena* arena = nullptr;  // solver-side buffers (retraction, transports, FOM), owned

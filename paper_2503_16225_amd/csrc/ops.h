@@ -27,6 +27,18 @@ ColMap block_map(const eahp_problem* pb, int k, int ncols);
 void fetch_scalars(eahp_problem* pb, int n);
 double* scal(eahp_problem* pb, int i);
 
+// Crystal symmetry (symmetry.hip)
+constexpr int kMaxSymOps = 4096;
+struct SymOp {
+  int W[9];     // row-major, fractional coordinates
+  double t[3];  // fractional translation in [0, 1)
+};
+void find_symmetry(const eahp_system_desc* d, const int n[3], double symprec, std::vector<SymOp>& ops);
+void reduce_kpoints(int nrot, const int* rot, bool time_reversal, int nk, const double* kfrac, const double* kw,
+                    std::vector<double>& kout, std::vector<double>& wout, std::vector<int>& owner);
+void setup_symmetry(eahp_problem* pb, const eahp_system_desc* d);  // validates, builds the box orbits
+void symmetrize_density(eahp_problem* pb);                         // d_rho <- its orbit means
+
 void potentials(eahp_problem* pb);
 void density_potentials(eahp_problem* pb, const z64* Psi);
 void apply_H_frame(eahp_problem* pb, const z64* X, z64* HX, bool tb_ready, double* nlvals);
@@ -74,7 +86,13 @@ struct FomWork {
   int64_t n = 0;
   int qcap = 0;
 };
+// Buffers of the block eigensolver of the SCF iteration (per problem).
+struct LobWork {
+  DevMem S, HS, T1, T2, T3, T4, R, A, V, w, C, Y, G, PU, piv, th, rn, alpha, idx;
+  void ensure(int64_t n, int p);
+};
 struct Arena {
+  LobWork lob;
   Scratch s;
   LineFactors line;
   FomWork<double> fw64;
@@ -97,6 +115,12 @@ struct FomInfo {
   int q = 0;
 };
 // Algorithm 4 on every k-point; X out (frame); the potential must be that of Phi.
+// SCF comparator (scf.hip): LOBPCG for the p lowest eigenpairs of H_k at the
+// current potential (X: n_k x p block at k-point ik, in and out; theta: host,
+// p Ritz values), and the SCF iteration with Anderson mixing on the frame Psi.
+int lobpcg_k(eahp_problem* pb, int ik, z64* X, double tol, int maxit, double* theta, double* rnorm_max,
+             int64_t* napply);
+void scf_run(eahp_problem* pb, z64* Psi, const eahp_scf_params& prm, eahp_scf_stats* out);
 void metric_solve(eahp_problem* pb, const z64* Phi, const z64* R, const z64* Lam, double mu, double rtol, int maxit,
                   double rank_tol, z64* X, std::vector<FomInfo>* info, const LamEig* leig = nullptr);
 

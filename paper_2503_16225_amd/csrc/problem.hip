@@ -218,6 +218,8 @@ void build_problem(eahp_problem* pb, const eahp_system_desc* d) {
     if (2 * mmax[dd] >= pb->n[dd]) fail(EAHP_EINVAL, "FFT box too small for the basis");
   }
   pb->Ng = (int64_t)pb->n[0] * pb->n[1] * pb->n[2];
+  if (pb->Ng > INT32_MAX) fail(EAHP_EINVAL, "FFT box too large");
+  setup_symmetry(pb, d);
   const int n1 = pb->n[0], n2 = pb->n[1], n3 = pb->n[2];
   std::vector<char> plane_used(n1, 0);
   pb->ntot = 0;
@@ -441,6 +443,7 @@ void density_potentials(eahp_problem* pb, const z64* Psi) {
   launch_x_density(st, frame_map(pb), ncols, g, pb->plan[0], pb->d_tw[0].as<z64>(), Tb, pb->occ / pb->Omega,
                    pb->d_rho.as<double>(), 0, pb->ws.rho_part);
   prof_end(pb, 3, bytes_dens(pb, ncols));
+  symmetrize_density(pb);
   potentials(pb);
 }
 

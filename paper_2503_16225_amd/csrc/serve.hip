@@ -30,7 +30,8 @@ double now_s() {
 struct Request {
   uint64_t ticket = 0;
   eahp_system_desc desc{};
-  std::vector<double> frac, Z, kfrac, kweight;
+  std::vector<double> frac, Z, kfrac, kweight, sym_trans;
+  std::vector<int> sym_rot;
   eahp_solve_params prm{};
   std::vector<z64> psi;  // initial frame, then the result
   size_t est = 0;
@@ -191,6 +192,12 @@ int eahp_server_submit(eahp_server* sv, const eahp_system_desc* desc, const eahp
     rq->desc.Z = rq->Z.data();
     rq->desc.kfrac = rq->kfrac.data();
     rq->desc.kweight = rq->kweight.data();
+    if (desc->nsym > 1 && desc->sym_rot && desc->sym_trans) {
+      rq->sym_rot.assign(desc->sym_rot, desc->sym_rot + 9 * (size_t)desc->nsym);
+      rq->sym_trans.assign(desc->sym_trans, desc->sym_trans + 3 * (size_t)desc->nsym);
+      rq->desc.sym_rot = rq->sym_rot.data();
+      rq->desc.sym_trans = rq->sym_trans.data();
+    }
     rq->prm = *prm;
     std::vector<int64_t> npw;
     int n[3], ns;

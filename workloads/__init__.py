@@ -58,6 +58,10 @@ DEFAULT_PARAMS = dict(
     nm_theta=0.85,     # EARGD, L2RCG: weight of the Zhang-Hager reference energy
 )
 
+# SCF comparator: Anderson mixing of the density (damping, history) as in the
+# dense SCF of the tests; eig_tol 0 selects the adaptive eigensolver tolerance
+DEFAULT_SCF_PARAMS = dict(tol=1e-10, maxit=100, beta=0.5, depth=6, eig_tol=0.0, eig_maxit=100)
+
 # term switches (used by closed-form special cases)
 TERM_ION = 1
 TERM_HARTREE = 2
