@@ -80,8 +80,11 @@ template <typename T> struct Dft<T, 5> {
 // ------------------------------------------------------------------ LDS FFT
 // A set of lines stored in LDS: element (line l, position j) at l * ls + j * es.
 // lfast: consecutive threads take consecutive lines (use when ls == 1).
+// Line l sits at row (l0 + l) mod lwrap, which lets a transform cover a
+// cyclic range of rows (l0 = 0 and lwrap beyond nlines: rows 0..nlines-1).
 struct Lines {
   int N, es, nlines, ls, lfast;
+  int l0 = 0, lwrap = 1 << 30;
 };
 
 // Quotient by a runtime divisor without an integer division: a float
@@ -119,7 +122,9 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, const Lines L, int span,
       if (L.lfast) { i = fdiv_q(idx, fl); l = idx - i * L.nlines; }
       else { l = fdiv_q(idx, fl); i = idx - l * nb; }
       const int k = i - fdiv_q(i, fs) * span;
-      const cplx<T>* line = buf + l * L.ls;
+      int lr = l + L.l0;
+      lr -= lr >= L.lwrap ? L.lwrap : 0;
+      const cplx<T>* line = buf + lr * L.ls;
 #pragma unroll
       for (int j = 0; j < R; ++j) u[b][j] = line[(i + j * nb) * L.es];
 #pragma unroll
@@ -142,7 +147,9 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, const Lines L, int span,
       const int is = fdiv_q(i, fs);
       const int k = i - is * span;
       const int base = is * span * R + k;
-      cplx<T>* line = buf + l * L.ls;
+      int lr = l + L.l0;
+      lr -= lr >= L.lwrap ? L.lwrap : 0;
+      cplx<T>* line = buf + lr * L.ls;
 #pragma unroll
       for (int j = 0; j < R; ++j) line[(base + j * span) * L.es] = u[b][j];
     }

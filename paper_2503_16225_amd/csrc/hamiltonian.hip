@@ -69,7 +69,8 @@ __global__ void __launch_bounds__(1024) k_inv_yz(ColMap cm, GridGeom g, FftPlan 
   const int pbase = g.plane_i1[s] * np;  // box index of the plane start
   for (int r = g0 + threadIdx.x; r < g1; r += blockDim.x) pl[k.box[r] - pbase] = x[r];
   __syncthreads();
-  lds_fft<T, MAXPTS>(pl, Lines{g.n3, 1, g.n2, g.n3, 0}, pz, tz, (T)1);
+  // z-lines only on the rows i2 = m2 mod n2 with |m2| <= m2max (the others are zero)
+  lds_fft<T, MAXPTS>(pl, Lines{g.n3, 1, 2 * g.m2max + 1, g.n3, 0, g.n2 - g.m2max, g.n2}, pz, tz, (T)1);
   lds_fft<T, MAXPTS>(pl, Lines{g.n2, g.n3, g.n3, 1, 1}, py, ty, (T)1);
   cplx<T>* out = Tb + ((int64_t)c * g.ns + s) * g.ps;
   for (int i = threadIdx.x; i < np; i += blockDim.x) out[i] = pl[i];
@@ -98,7 +99,8 @@ __global__ void __launch_bounds__(1024) k_fwd_yz(ColMap cm, GridGeom g, FftPlan 
   for (int i = threadIdx.x; i < g.n2; i += blockDim.x) ty[i] = twy[i];
   __syncthreads();
   lds_fft<T, MAXPTS>(pl, Lines{g.n2, g.n3, g.n3, 1, 1}, py, ty, (T)-1);
-  lds_fft<T, MAXPTS>(pl, Lines{g.n3, 1, g.n2, g.n3, 0}, pz, tz, (T)-1);
+  // z-lines only where the sphere is gathered: rows with |m2| <= m2max
+  lds_fft<T, MAXPTS>(pl, Lines{g.n3, 1, 2 * g.m2max + 1, g.n3, 0, g.n2 - g.m2max, g.n2}, pz, tz, (T)-1);
   const T* kin = kin_of<T>(k);
   const cplx<T>* x = X + base;
   cplx<T>* y = HX + base;

@@ -123,6 +123,7 @@ struct eahp_problem {
   std::vector<double> Z;
   double r_loc = 0.8, r_proj = 0.8, D_proj = 1.0, ecut = 0;
   int n[3] = {0, 0, 0};
+  int m2max = 0;      // largest |m2| over the bases
   int64_t Ng = 0;
   int p = 0, nk = 0, precision = 0, terms = 15;
   double occ = 2.0;

@@ -34,6 +34,7 @@ struct GridGeom {
   int ns;              // active x-planes
   const int* plane_i1; // device: i1 of each active plane
   int ps;              // element stride between (y, z) planes of the slab buffer: n2 n3 rounded up to 16
+  int m2max;           // largest |m2| of any plane wave: rows i2 = m2 mod n2 with |m2| > m2max stay zero
 };
 
 // ---- local-potential apply and density (hamiltonian.hip) -----------------

@@ -217,6 +217,7 @@ void build_problem(eahp_problem* pb, const eahp_system_desc* d) {
     pb->n[dd] = d->fft[dd] > 0 ? d->fft[dd] : smooth_at_least(4 * mmax[dd] + 1);
     if (2 * mmax[dd] >= pb->n[dd]) fail(EAHP_EINVAL, "FFT box too small for the basis");
   }
+  pb->m2max = mmax[1];
   pb->Ng = (int64_t)pb->n[0] * pb->n[1] * pb->n[2];
   if (pb->Ng > INT32_MAX) fail(EAHP_EINVAL, "FFT box too large");
   setup_symmetry(pb, d);
@@ -350,7 +351,7 @@ void build_problem(eahp_problem* pb, const eahp_system_desc* d) {
 // slab planes start on 256-byte boundaries (FP64) so every x-line tile is whole cache lines
 int plane_stride(const eahp_problem* pb) { return ((pb->n[1] * pb->n[2] + 15) / 16) * 16; }
 GridGeom geom(const eahp_problem* pb) {
-  return GridGeom{pb->n[0], pb->n[1], pb->n[2], pb->ns, pb->d_plane_i1.as<int>(), plane_stride(pb)};
+  return GridGeom{pb->n[0], pb->n[1], pb->n[2], pb->ns, pb->d_plane_i1.as<int>(), plane_stride(pb), pb->m2max};
 }
 
 ColMap frame_map(const eahp_problem* pb) { return ColMap{pb->d_kdesc.as<KDesc>(), 0, pb->p, 1}; }
