@@ -24,6 +24,18 @@
 #include "kernels.h"
 #include "regfft.h"
 
+// line lengths with register transforms (x lines, square yz planes), as (n1, N1, N2)
+#define EAHP_XREG_SIZES(X)                                                                                     \
+  X(18, 3, 6) X(20, 4, 5) X(24, 4, 6) X(27, 3, 9) X(30, 5, 6) X(32, 4, 8) X(36, 6, 6) X(40, 5, 8) X(45, 5, 9)   \
+  X(48, 6, 8) X(50, 5, 10) X(54, 6, 9) X(60, 6, 10) X(64, 8, 8) X(72, 8, 9) X(75, 5, 15) X(80, 8, 10)          \
+  X(81, 9, 9) X(90, 9, 10) X(96, 8, 12) X(100, 10, 10) X(108, 9, 12) X(120, 10, 12) X(128, 8, 16) X(144, 12, 12)
+// square yz planes whose padded plane fits LDS in single precision (double: up to 100)
+#define EAHP_YZREG_SIZES(X)                                                                                    \
+  X(18, 3, 6) X(20, 4, 5) X(24, 4, 6) X(27, 3, 9) X(30, 5, 6) X(32, 4, 8) X(36, 6, 6) X(40, 5, 8) X(45, 5, 9)   \
+  X(48, 6, 8) X(50, 5, 10) X(54, 6, 9) X(60, 6, 10) X(64, 8, 8) X(72, 8, 9) X(75, 5, 15) X(80, 8, 10)          \
+  X(81, 9, 9) X(90, 9, 10) X(96, 8, 12) X(100, 10, 10) X(108, 9, 12) X(120, 10, 12) X(128, 8, 16)
+
+
 namespace eahp {
 
 template <typename T> __device__ __forceinline__ const T* kin_of(const KDesc& k);
@@ -371,10 +383,282 @@ static void launch_lines(hipStream_t st, cplx<T>* base, int64_t pstride, int npl
 }
 
 
+// ------------------------------------------------------------------ yz planes, register transforms
+// The plane transforms of k_inv_yz / k_fwd_yz for square planes n2 = n3 =
+// n = N1 N2 (the register four-step of k_x_local_reg), one work-group of
+// 8 waves per (plane, column), the plane in LDS with row stride n + 1.
+// z-lines (rows, only |m2| <= m2max) and y-lines (columns) each take 16
+// lines per wave and 4 lane groups; every step works in place on its
+// line's LDS positions, so each transform needs only the barriers between
+// its two steps (plus one where the natural-order results are written back).
+// The y-transform reads (forward) or writes (inverse) the slab directly:
+// 16 consecutive i3 of one row per lane group.
+constexpr int kYzThreads = 512;
+
+__device__ __forceinline__ bool row_active(int r, int n, int m2max) { return r <= m2max || r >= n - m2max; }
+
+// one line of the four-step in LDS: element j of the line at base + j * es.
+// Step A for the lane's j2 = grp + 4a: x(N2 j1 + j2) -> z(k1; j2) at k1 N2 + j2.
+template <typename T, int N1, int N2, bool kSkipInactive>
+__device__ __forceinline__ void yz_step_a(cplx<T>* base, int es, int grp, const cplx<T>* tw, T sg, int n, int m2max) {
+  constexpr int JA = (N2 + 3) / 4;
+#pragma unroll
+  for (int a = 0; a < JA; ++a) {
+    const int j2 = grp + 4 * a;
+    if (j2 < N2) {
+      cplx<T> u[N1];
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) {
+        const int r = N2 * j1 + j2;
+        u[j1] = (!kSkipInactive || row_active(r, n, m2max)) ? base[r * es] : mk<T>(0, 0);
+      }
+      RegFft<T, N1>::run(u, sg);
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) {
+        cplx<T> w = tw[j2 * k1];
+        w.y *= -sg;  // the table holds exp(-2 pi i m / n)
+        base[(k1 * N2 + j2) * es] = cmul<T>(u[k1], w);
+      }
+    }
+  }
+}
+
+// Step B, first half: z(k1; j2) for the lane's k1 = grp + 4b into registers
+// and the size-N2 DFTs; y[b][k2] is element k1 + N1 k2 of the line.
+template <typename T, int N1, int N2>
+__device__ __forceinline__ void yz_step_b(const cplx<T>* base, int es, int grp, T sg, cplx<T> (&y)[(N1 + 3) / 4][N2]) {
+  constexpr int KB = (N1 + 3) / 4;
+#pragma unroll
+  for (int b = 0; b < KB; ++b) {
+    const int k1 = grp + 4 * b;
+    if (k1 < N1) {
+#pragma unroll
+      for (int j2 = 0; j2 < N2; ++j2) y[b][j2] = base[(k1 * N2 + j2) * es];
+      RegFft<T, N2>::run(y[b], sg);
+    }
+  }
+}
+
+template <typename T, int N1, int N2>
+__global__ void __launch_bounds__(kYzThreads) k_inv_yz_reg(ColMap cm, GridGeom g, const cplx<T>* __restrict__ tws,
+                                                           const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Tb) {
+  constexpr int n = N1 * N2, LS = n + 1, KB = (N1 + 3) / 4;
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* P = reinterpret_cast<cplx<T>*>(smem_raw);  // n rows of LS
+  cplx<T>* tw = P + n * LS;
+  const int s = blockIdx.x, c = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = lane & 15, grp = lane >> 4;
+  const int m2 = g.m2max, nrow = 2 * m2 + 1;
+  int64_t xb;
+  const KDesc& k = col_kd(cm, c, xb);
+  for (int i = threadIdx.x; i < n; i += kYzThreads) tw[i] = tws[i];
+  for (int e = threadIdx.x; e < nrow * n; e += kYzThreads) {
+    const int l = e / n, i3 = e - l * n;
+    int r = n - m2 + l;
+    r -= r >= n ? n : 0;
+    P[r * LS + i3] = mk<T>(0, 0);
+  }
+  __syncthreads();
+  const int g0 = k.plane_start[s], g1 = k.plane_start[s + 1];
+  const int pbase = g.plane_i1[s] * n * n;
+  const cplx<T>* x = X + xb;
+  for (int q = g0 + threadIdx.x; q < g1; q += kYzThreads) {
+    const int e = k.box[q] - pbase;
+    const int i2 = e / n;
+    P[i2 * LS + (e - i2 * n)] = x[q];
+  }
+  __syncthreads();
+  // z-lines: rows with |m2| <= m2max
+  const int zpasses = (nrow + 16 * (kYzThreads / 64) - 1) / (16 * (kYzThreads / 64));
+  for (int ps = 0; ps < zpasses; ++ps) {
+    const int l = (ps * (kYzThreads / 64) + wave) * 16 + t;
+    int r = n - m2 + l;
+    r -= r >= n ? n : 0;
+    cplx<T>* row = P + r * LS;
+    if (l < nrow) yz_step_a<T, N1, N2, false>(row, 1, grp, tw, (T)1, n, m2);
+    __syncthreads();
+    cplx<T> y[KB][N2];
+    if (l < nrow) yz_step_b<T, N1, N2>(row, 1, grp, (T)1, y);
+    __syncthreads();
+    if (l < nrow) {
+#pragma unroll
+      for (int b = 0; b < KB; ++b) {
+        const int k1 = grp + 4 * b;
+        if (k1 < N1) {
+#pragma unroll
+          for (int k2 = 0; k2 < N2; ++k2) row[k1 + N1 * k2] = y[b][k2];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // y-lines: every column, results straight to the slab
+  cplx<T>* out = Tb + ((int64_t)c * g.ns + s) * g.ps;
+  constexpr int ypasses = (n + 16 * (kYzThreads / 64) - 1) / (16 * (kYzThreads / 64));
+  for (int ps = 0; ps < ypasses; ++ps) {
+    const int i3 = (ps * (kYzThreads / 64) + wave) * 16 + t;
+    cplx<T>* col = P + i3;
+    if (i3 < n) yz_step_a<T, N1, N2, true>(col, LS, grp, tw, (T)1, n, m2);
+    __syncthreads();
+    if (i3 < n) {
+      cplx<T> y[KB][N2];
+      yz_step_b<T, N1, N2>(col, LS, grp, (T)1, y);
+#pragma unroll
+      for (int b = 0; b < KB; ++b) {
+        const int k1 = grp + 4 * b;
+        if (k1 < N1) {
+#pragma unroll
+          for (int k2 = 0; k2 < N2; ++k2) out[(k1 + N1 * k2) * n + i3] = y[b][k2];
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int N1, int N2>
+__global__ void __launch_bounds__(kYzThreads) k_fwd_yz_reg(ColMap cm, GridGeom g, const cplx<T>* __restrict__ tws,
+                                                           const cplx<T>* __restrict__ Tb,
+                                                           const cplx<T>* __restrict__ X, cplx<T>* __restrict__ HX,
+                                                           T scale) {
+  constexpr int n = N1 * N2, LS = n + 1, KB = (N1 + 3) / 4, JA = (N2 + 3) / 4;
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* P = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* tw = P + n * LS;
+  const int s = blockIdx.x, c = blockIdx.y;
+  int64_t xb;
+  const KDesc& k = col_kd(cm, c, xb);
+  const int g0 = k.plane_start[s], g1 = k.plane_start[s + 1];
+  if (g1 == g0) return;  // block-uniform: this k-point has no plane waves here
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = lane & 15, grp = lane >> 4;
+  const int m2 = g.m2max, nrow = 2 * m2 + 1;
+  for (int i = threadIdx.x; i < n; i += kYzThreads) tw[i] = tws[i];
+  __syncthreads();
+  // y-lines (forward) from the slab: step A loads of rows N2 j1 + j2
+  const cplx<T>* in = Tb + ((int64_t)c * g.ns + s) * g.ps;
+  constexpr int ypasses = (n + 16 * (kYzThreads / 64) - 1) / (16 * (kYzThreads / 64));
+  for (int ps = 0; ps < ypasses; ++ps) {
+    const int i3 = (ps * (kYzThreads / 64) + wave) * 16 + t;
+    const bool ok = i3 < n;
+    cplx<T> u[JA][N1];
+#pragma unroll
+    for (int a = 0; a < JA; ++a) {
+      const int j2 = grp + 4 * a;
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) u[a][j1] = (ok && j2 < N2) ? in[(N2 * j1 + j2) * n + i3] : mk<T>(0, 0);
+    }
+    if (ok) {
+#pragma unroll
+      for (int a = 0; a < JA; ++a) {
+        const int j2 = grp + 4 * a;
+        if (j2 < N2) {
+          RegFft<T, N1>::run(u[a], (T)-1);
+#pragma unroll
+          for (int k1 = 0; k1 < N1; ++k1) P[(k1 * N2 + j2) * LS + i3] = cmul<T>(u[a][k1], tw[j2 * k1]);
+        }
+      }
+    }
+    __syncthreads();
+    cplx<T> y[KB][N2];
+    if (ok) yz_step_b<T, N1, N2>(P + i3, LS, grp, (T)-1, y);
+    __syncthreads();
+    if (ok) {
+#pragma unroll
+      for (int b = 0; b < KB; ++b) {
+        const int k1 = grp + 4 * b;
+        if (k1 < N1) {
+#pragma unroll
+          for (int k2 = 0; k2 < N2; ++k2) {
+            const int r = k1 + N1 * k2;
+            if (row_active(r, n, m2)) P[r * LS + i3] = y[b][k2];
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // z-lines (forward) on the rows the sphere reaches
+  const int zpasses = (nrow + 16 * (kYzThreads / 64) - 1) / (16 * (kYzThreads / 64));
+  for (int ps = 0; ps < zpasses; ++ps) {
+    const int l = (ps * (kYzThreads / 64) + wave) * 16 + t;
+    int r = n - m2 + l;
+    r -= r >= n ? n : 0;
+    cplx<T>* row = P + r * LS;
+    if (l < nrow) yz_step_a<T, N1, N2, false>(row, 1, grp, tw, (T)-1, n, m2);
+    __syncthreads();
+    cplx<T> y[KB][N2];
+    if (l < nrow) yz_step_b<T, N1, N2>(row, 1, grp, (T)-1, y);
+    __syncthreads();
+    if (l < nrow) {
+#pragma unroll
+      for (int b = 0; b < KB; ++b) {
+        const int k1 = grp + 4 * b;
+        if (k1 < N1) {
+#pragma unroll
+          for (int k2 = 0; k2 < N2; ++k2) row[k1 + N1 * k2] = y[b][k2];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // gather of the sphere, scaled, plus the kinetic term
+  const int pbase = g.plane_i1[s] * n * n;
+  const T* kin = kin_of<T>(k);
+  const cplx<T>* x = X + xb;
+  cplx<T>* yv = HX + xb;
+  for (int q = g0 + threadIdx.x; q < g1; q += kYzThreads) {
+    const int e = k.box[q] - pbase;
+    const int i2 = e / n;
+    const cplx<T> v = P[i2 * LS + (e - i2 * n)];
+    const cplx<T> xv = x[q];
+    const T kr = kin[q];
+    yv[q] = mk<T>(v.x * scale + kr * xv.x, v.y * scale + kr * xv.y);
+  }
+}
+
+template <typename T>
+static size_t yz_reg_lds(int n) {
+  return sizeof(cplx<T>) * ((size_t)n * (n + 1) + n);
+}
+
+// (n, N1, N2) of the register plane transforms; false when not applicable
+template <typename T>
+static bool yz_reg_ok(const GridGeom& g) {
+  if (g.n2 != g.n3) return false;
+  if (yz_reg_lds<T>(g.n2) > kLdsMax) return false;
+  switch (g.n2) {
+#define X(nn, a, b) case nn:
+    EAHP_YZREG_SIZES(X)
+#undef X
+    return true;
+    default:
+      return false;
+  }
+}
+
 template <typename T>
 void launch_inv_yz(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const FftPlan& pz,
                    const FftPlan& py, const cplx<T>* twz, const cplx<T>* twy, const cplx<T>* X, cplx<T>* Tb) {
   if (ncols <= 0) return;
+  if (yz_reg_ok<T>(g)) {
+    const size_t l = yz_reg_lds<T>(g.n2);
+    dim3 grid(g.ns, ncols);
+    switch (g.n2) {
+#define X(nn, a, b)                                                                                             \
+  case nn:                                                                                                      \
+    HIPCK(hipFuncSetAttribute((const void*)k_inv_yz_reg<T, a, b>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                              (int)l));                                                                         \
+    hipLaunchKernelGGL((k_inv_yz_reg<T, a, b>), grid, dim3(kYzThreads), l, st, cm, g, twz, X, Tb);                \
+    break;
+      EAHP_YZREG_SIZES(X)
+#undef X
+      default:
+        break;
+    }
+    HIPCK(hipGetLastError());
+    return;
+  }
   const size_t lds = plane_lds<T>(g);
   if (lds > kLdsMax) {
     // split plane: scatter + z-transform per block of z-lines, then the y-lines
@@ -414,8 +698,26 @@ void launch_fwd_yz(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& 
                    const FftPlan& py, const cplx<T>* twz, const cplx<T>* twy, const cplx<T>* Tb, const cplx<T>* X,
                    cplx<T>* HX) {
   if (ncols <= 0) return;
-  const size_t lds = plane_lds<T>(g);
   const T scale = (T)(1.0 / ((double)g.n1 * g.n2 * g.n3));
+  if (yz_reg_ok<T>(g)) {
+    const size_t l = yz_reg_lds<T>(g.n2);
+    dim3 grid(g.ns, ncols);
+    switch (g.n2) {
+#define X(nn, a, b)                                                                                             \
+  case nn:                                                                                                      \
+    HIPCK(hipFuncSetAttribute((const void*)k_fwd_yz_reg<T, a, b>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                              (int)l));                                                                         \
+    hipLaunchKernelGGL((k_fwd_yz_reg<T, a, b>), grid, dim3(kYzThreads), l, st, cm, g, twz, Tb, X, HX, scale);     \
+    break;
+      EAHP_YZREG_SIZES(X)
+#undef X
+      default:
+        break;
+    }
+    HIPCK(hipGetLastError());
+    return;
+  }
+  const size_t lds = plane_lds<T>(g);
   if (lds > kLdsMax) {
     // split plane: the y-lines in place on the slab, then z-transform + gather per block of z-lines
     launch_lines<T>(st, const_cast<cplx<T>*>(Tb), g.ps, ncols * g.ns, g.n2, g.n3, 1, g.n3, py, twy, (T)-1);
@@ -552,12 +854,6 @@ __global__ void __launch_bounds__(64) k_x_local_reg(int ncols, int cb, GridGeom 
     }
   }
 }
-
-// x-lengths with a register x-transform, as (n1, N1, N2)
-#define EAHP_XREG_SIZES(X)                                                                                     \
-  X(18, 3, 6) X(20, 4, 5) X(24, 4, 6) X(27, 3, 9) X(30, 5, 6) X(32, 4, 8) X(36, 6, 6) X(40, 5, 8) X(45, 5, 9)   \
-  X(48, 6, 8) X(50, 5, 10) X(54, 6, 9) X(60, 6, 10) X(64, 8, 8) X(72, 8, 9) X(75, 5, 15) X(80, 8, 10)          \
-  X(81, 9, 9) X(90, 9, 10) X(96, 8, 12) X(100, 10, 10) X(108, 9, 12) X(120, 10, 12) X(128, 8, 16) X(144, 12, 12)
 
 template <typename T>
 static bool launch_x_local_reg(hipStream_t st, int ncols, const GridGeom& g, const cplx<T>* twx, const T* V,
