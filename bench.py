@@ -34,9 +34,11 @@ KERNEL_NAMES = ["inv_yz", "x_local", "fwd_yz", "x_density", "inv_yz_f32", "x_loc
 # with this SHA-1 (hamiltonian.hip + devcommon.h + regfft.h); reported as null
 # once the sources differ.
 MEASURED_TRAFFIC = {
-    "sources_sha1": "b74bac1b2587f214eb65077f1ed1408f57763948",
+    "sources_sha1": "c9a9b270c6ec4f4b50c9420cfb8bf5575f57ab85",
     "config": "si64_gamma_e20",
-    "bytes_per_launch": {"x_local_f32": 724.414e6, "x_local": 1442.439e6},
+    "bytes_per_launch": {"x_local_f32": 764.339e6, "x_local": 1523.705e6, "fwd_yz_f32": 432.656e6,
+                         "fwd_yz": 877.000e6, "inv_yz_f32": 393.331e6, "inv_yz": 782.246e6,
+                         "x_density": 727.351e6},
 }
 
 
