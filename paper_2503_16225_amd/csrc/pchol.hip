@@ -11,8 +11,9 @@
 // (rows and columns are marked done instead of being exchanged); the pivot
 // search is a shuffle reduction in every wave followed by a scan of the 16
 // wave candidates in every thread, so a step takes two barriers.  The
-// triangular inverse runs row by row in pivot order with the 16 columns of
-// each row accumulated in the same registers.
+// factor is written row-major to a scratch matrix; the inverse factor is a
+// second launch, k_chol_uinv, with one wave per column of U (independent
+// backward substitutions, no block barriers).
 #include "devcommon.h"
 #include "kernels.h"
 
@@ -96,7 +97,7 @@ __global__ void __launch_bounds__(1024) k_pchol_reg(int n, const z64* __restrict
     z64 lv = rr == b ? mk<double>(lbb, 0.0) : (isp || rr >= n) ? mk<double>(0.0, 0.0) : cscale<double>(ab, ilbb);
     if (cg == (b & 7) && rr < n) {
       lcol[k & 1][rr] = lv;
-      Lg[rr + (int64_t)k * n] = lv;
+      Lg[(int64_t)rr * n + k] = lv;  // row-major: l(rr, k)
     }
     // this row's l, from the lane of the row that holds column b
     const int src = (lane & ~7) | (b & 7);
@@ -130,54 +131,56 @@ __global__ void __launch_bounds__(1024) k_pchol_reg(int n, const z64* __restrict
   }
   __syncthreads();
   for (int i = t; i < n; i += blockDim.x) piv[i] = pv[i];
-  // X = Lt^-1 with Lt[a][m] = Lg[pv[a] + m n] (lower triangular in pivot order);
-  // thread row rr = pivot position, acc[m] = X[rr][cg + 8 m] once row rr is final
-  z64 acc[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) acc[m] = mk<double>(0.0, 0.0);
-  z64* xrow = &lcol[0][0];  // reused: 2 x kPcMax
-  // Lt[rr][arow] is loaded one row ahead so that its latency overlaps the barrier;
-  // it is zero for rr < arow (rows that were pivots before step arow)
-  z64 lnext = (rr < r) ? Lg[pv[rr]] : mk<double>(0.0, 0.0);
-  for (int arow = 0; arow < r; ++arow) {
-    z64* xr = xrow + (arow & 1) * kPcMax;
-    const z64 l = lnext;
-    if (rr < r && arow + 1 < r) lnext = Lg[pv[rr] + (int64_t)(arow + 1) * n];
-    if (rr == arow) {
-      // row arow of X is final: (e_arow - acc) / Lt[arow][arow]; zero beyond column arow
-      const double inv = 1.0 / l.x;
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int j = cg + 8 * m;
-        const z64 rhs = csub<double>(mk<double>(j == arow ? 1.0 : 0.0, 0.0), acc[m]);
-        acc[m] = j <= arow ? cscale<double>(rhs, inv) : mk<double>(0.0, 0.0);
-        xr[j] = acc[m];
-      }
+}
+
+// Column j < r of U = P L^-H: y = Lt^-H e_j with Lt[a][m] = l(piv[a], m) lower
+// triangular in pivot order, by backward substitution over a = j .. 0 (lane
+// l owns indices l and l + 64); U[piv[m]][j] = y_m for m <= j, 0 otherwise.
+// One wave per column; row piv[a] of the factor is read contiguously and
+// prefetched one step ahead.
+__global__ void __launch_bounds__(64) k_chol_uinv(int n, const int* __restrict__ rank, const int* __restrict__ piv,
+                                                  const z64* __restrict__ Lg, z64* __restrict__ U, int64_t ldu) {
+  const int j = blockIdx.x, l = threadIdx.x;
+  const int r = *rank;
+  if (j >= r) return;
+  __shared__ int pv[kPcMax];
+  for (int i = l; i < n; i += 64) pv[i] = piv[i];
+  __syncthreads();
+  z64 rhs0 = mk<double>(l == j ? 1.0 : 0.0, 0.0), rhs1 = mk<double>(l + 64 == j ? 1.0 : 0.0, 0.0);
+  z64 y0 = mk<double>(0.0, 0.0), y1 = mk<double>(0.0, 0.0);
+  const z64 zero = mk<double>(0.0, 0.0);
+  const z64* row = Lg + (int64_t)pv[j] * n;
+  z64 c0 = l < n ? row[l] : zero, c1 = l + 64 < n ? row[l + 64] : zero;
+  for (int a = j; a >= 0; --a) {
+    const z64 a0 = c0, a1 = c1;
+    if (a > 0) {  // next row, independent of this step's result
+      const z64* nrow = Lg + (int64_t)pv[a - 1] * n;
+      c0 = l < a - 1 + 1 ? nrow[l] : zero;
+      c1 = l + 64 < a ? nrow[l + 64] : zero;
     }
-    __syncthreads();
-    // later rows: acc += Lt[rr][arow] X[arow][:] (rows before arow have l = 0)
-    const z64 lu = rr == arow ? mk<double>(0.0, 0.0) : l;
-#pragma unroll
-    for (int mb = 0; mb < 16; mb += 4) {
-      z64 xw[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) xw[u] = xr[cg + 8 * (mb + u)];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        z64& x = acc[mb + u];
-        x.x = fma(lu.x, xw[u].x, fma(-lu.y, xw[u].y, x.x));
-        x.y = fma(lu.x, xw[u].y, fma(lu.y, xw[u].x, x.y));
-      }
+    // y_a = rhs_a / Lt[a][a] in the lane that owns a, broadcast
+    const bool lo = a < 64;
+    const z64 ra = lo ? rhs0 : rhs1;
+    const z64 da = lo ? a0 : a1;  // Lt[a][a] sits at the lane owning a
+    const int own = a & 63;
+    const double inv = 1.0 / __shfl(da.x, own, 64);
+    const double yx = __shfl(ra.x, own, 64) * inv, yy = __shfl(ra.y, own, 64) * inv;
+    if (l == own) {
+      if (lo) y0 = mk<double>(yx, yy);
+      else y1 = mk<double>(yx, yy);
+    }
+    // rhs_m -= conj(Lt[a][m]) y_a for m < a
+    if (l < a) {
+      rhs0.x -= a0.x * yx + a0.y * yy;
+      rhs0.y -= a0.x * yy - a0.y * yx;
+    }
+    if (l + 64 < a) {
+      rhs1.x -= a1.x * yx + a1.y * yy;
+      rhs1.y -= a1.x * yy - a1.y * yx;
     }
   }
-  // U[pv[k]][j] = conj(X[j][k]) for k <= j < r, zero for every other row of column j
-  if (rr < r) {
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int k = cg + 8 * m;
-      if (k < n) U[pv[k] + (int64_t)rr * ldu] = k <= rr ? mk<double>(acc[m].x, -acc[m].y) : mk<double>(0.0, 0.0);
-    }
-  }
+  if (l < n) U[pv[l] + (int64_t)j * ldu] = l <= j ? y0 : zero;
+  if (l + 64 < n) U[pv[l + 64] + (int64_t)j * ldu] = l + 64 <= j ? y1 : zero;
 }
 
 bool pchol_inv_reg(hipStream_t st, int n, const z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* U,
@@ -186,6 +189,8 @@ bool pchol_inv_reg(hipStream_t st, int n, const z64* G, int64_t ldg, double tol,
   scr.ensure(sizeof(z64) * (size_t)n * n);
   hipLaunchKernelGGL(k_pchol_reg, dim3(1), dim3(1024), 0, st, n, G, ldg, tol, piv, rank, U, ldu, scr.as<z64>(),
                      pivot ? 1 : 0);
+  HIPCK(hipGetLastError());
+  hipLaunchKernelGGL(k_chol_uinv, dim3(n), dim3(64), 0, st, n, rank, piv, scr.as<z64>(), U, ldu);
   HIPCK(hipGetLastError());
   return true;
 }
