@@ -75,21 +75,54 @@ __global__ void __launch_bounds__(256) k_gemm_hn_mfma(int64_t n, int a, int b, c
   const int ia = ta * MT + lc, jb = tb * MT + lc;
   const cplx<T>* Ac = A + (int64_t)min(ia, a - 1) * lda;
   const cplx<T>* Bc = B + (int64_t)min(jb, b - 1) * ldb;
-  for (int64_t r = r0; r < r1; r += MK) {
+  // in single precision the next chunk's rows are loaded into registers while
+  // the current one is multiplied; in double precision the chunk is loaded
+  // and stored directly (the extra registers would cost occupancy)
+  constexpr bool kPre = sizeof(T) == 4;
+  cplx<T> pa[4], pb[4];
+  auto fetch = [&](int64_t r) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t row = r + lr + q;
-      cplx<T> av = mk<T>(0, 0), bv = mk<T>(0, 0);
+      pa[q] = mk<T>(0, 0);
+      pb[q] = mk<T>(0, 0);
       if (row < r1) {
-        if (ia < a) av = Ac[row];
-        if (jb < b) bv = Bc[row];
+        if (ia < a) pa[q] = Ac[row];
+        if (jb < b) pb[q] = Bc[row];
       }
-      Ar[lc * LDK + lr + q] = av.x;
-      Ai[lc * LDK + lr + q] = av.y;
-      Br[lc * LDK + lr + q] = bv.x;
-      Bi[lc * LDK + lr + q] = bv.y;
+    }
+  };
+  if constexpr (kPre) {
+    if (r0 < r1) fetch(r0);
+  }
+  for (int64_t r = r0; r < r1; r += MK) {
+    if constexpr (kPre) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Ar[lc * LDK + lr + q] = pa[q].x;
+        Ai[lc * LDK + lr + q] = pa[q].y;
+        Br[lc * LDK + lr + q] = pb[q].x;
+        Bi[lc * LDK + lr + q] = pb[q].y;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t row = r + lr + q;
+        cplx<T> av = mk<T>(0, 0), bv = mk<T>(0, 0);
+        if (row < r1) {
+          if (ia < a) av = Ac[row];
+          if (jb < b) bv = Bc[row];
+        }
+        Ar[lc * LDK + lr + q] = av.x;
+        Ai[lc * LDK + lr + q] = av.y;
+        Br[lc * LDK + lr + q] = bv.x;
+        Bi[lc * LDK + lr + q] = bv.y;
+      }
     }
     __syncthreads();
+    if constexpr (kPre) {
+      if (r + MK < r1) fetch(r + MK);
+    }
 #pragma unroll
     for (int kk = 0; kk < MK; kk += 4) {
       const int kr = kk + (lane >> 4), cc = lane & 15;
@@ -207,34 +240,44 @@ __global__ void __launch_bounds__(256) k_gemm_nn_mfma(int64_t n, int a, int b, c
     }
   const int ak = t >> 4, arw = (t & 15) * 4;  // A loader: inner index ak, rows arw..arw+3
   const int mc = t >> 2, mq = (t & 3) * 4;    // M loader: column mc, inner indices mq..mq+3
-  for (int k0 = 0; k0 < a; k0 += MK) {
-    {
-      const int k = k0 + ak;
+  // the next chunk of A and M is loaded into registers while the current one
+  // is multiplied (single precision only, as in k_gemm_hn_mfma)
+  constexpr bool kPre = sizeof(T) == 4;
+  cplx<T> pa[4], pm[4];
+  auto fetch = [&](int k0) {
+    const int k = k0 + ak;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t row = row0 + arw + q;
-        cplx<T> v = mk<T>(0, 0);
-        if (row < n && k < a) v = A[row + (int64_t)k * lda];
-        Ar[(arw + q) * LDK + ak] = v.x;
-        Ai[(arw + q) * LDK + ak] = v.y;
-      }
-      const int j = col0 + mc;
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = row0 + arw + q;
+      pa[q] = (row < n && k < a) ? A[row + (int64_t)k * lda] : mk<T>(0, 0);
+    }
+    const int j = col0 + mc;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int kq = k0 + mq + q;
-        cplx<T> mv = mk<T>(0, 0);
-        if (j < b && kq < a) {
-          if (opM == 0) mv = Mm[kq + (int64_t)j * ldm];
-          else {
-            const cplx<T> x = Mm[j + (int64_t)kq * ldm];
-            mv = mk<T>(x.x, -x.y);
-          }
+    for (int q = 0; q < 4; ++q) {
+      const int kq = k0 + mq + q;
+      cplx<T> mv = mk<T>(0, 0);
+      if (j < b && kq < a) {
+        if (opM == 0) mv = Mm[kq + (int64_t)j * ldm];
+        else {
+          const cplx<T> x = Mm[j + (int64_t)kq * ldm];
+          mv = mk<T>(x.x, -x.y);
         }
-        Mr[mc * LDK + mq + q] = mv.x;
-        Mi[mc * LDK + mq + q] = mv.y;
       }
+      pm[q] = mv;
+    }
+  };
+  if (kPre && a > 0) fetch(0);
+  for (int k0 = 0; k0 < a; k0 += MK) {
+    if (!kPre) fetch(k0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Ar[(arw + q) * LDK + ak] = pa[q].x;
+      Ai[(arw + q) * LDK + ak] = pa[q].y;
+      Mr[mc * LDK + mq + q] = pm[q].x;
+      Mi[mc * LDK + mq + q] = pm[q].y;
     }
     __syncthreads();
+    if (kPre && k0 + MK < a) fetch(k0 + MK);
 #pragma unroll
     for (int kk = 0; kk < MK; kk += 4) {
       const int kr = kk + (lane >> 4), cc = lane & 15;
