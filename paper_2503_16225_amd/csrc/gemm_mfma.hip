@@ -134,13 +134,20 @@ __global__ void __launch_bounds__(256) k_gemm_hn_mfma(int64_t n, int a, int b, c
         br[u] = Br[(wj + 16 * u + cc) * LDK + kr];
         bi[u] = Bi[(wj + 16 * u + cc) * LDK + kr];
       }
+      // the eight accumulators take one product each before any takes its
+      // second, so consecutive MFMAs are independent
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
           cre[u][v] = M::mma(ar[u], br[v], cre[u][v]);
-          cre[u][v] = M::mma(ai[u], bi[v], cre[u][v]);
           cim[u][v] = M::mma(ar[u], bi[v], cim[u][v]);
+        }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          cre[u][v] = M::mma(ai[u], bi[v], cre[u][v]);
           cim[u][v] = M::mma(-ai[u], br[v], cim[u][v]);
         }
     }
@@ -289,13 +296,19 @@ __global__ void __launch_bounds__(256) k_gemm_nn_mfma(int64_t n, int a, int b, c
         mr[u] = Mr[(wj + 16 * u + cc) * LDK + kr];
         mi[u] = Mi[(wj + 16 * u + cc) * LDK + kr];
       }
+      // one product per accumulator before the second (independent consecutive MFMAs)
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
           cre[u][v] = Mf::mma(ar[u], mr[v], cre[u][v]);
-          cre[u][v] = Mf::mma(-ai[u], mi[v], cre[u][v]);
           cim[u][v] = Mf::mma(ar[u], mi[v], cim[u][v]);
+        }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          cre[u][v] = Mf::mma(-ai[u], mi[v], cre[u][v]);
           cim[u][v] = Mf::mma(ai[u], mr[v], cim[u][v]);
         }
     }
