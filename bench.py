@@ -190,6 +190,74 @@ def serving(args):
                                                       "tol": prm["tol"], "maxit": prm["maxit"]}}), flush=True)
 
 
+def methods(args):
+    """The paper's comparison of methods (Sec. 5.2-5.3) on one workload: the
+    start is made by SCF until the density residual is below 0.1 (the paper's
+    initial guess); from it EARCG (both precisions), EARGD, L2RCG and SCF run to
+    ||R||_F <= tol.  Reports orbital H-applies, iterations and wall time of each
+    method (one JSON line; not the headline figure)."""
+    import torch
+
+    import workloads as W
+    from paper_2503_16225_amd import binding as B
+
+    sysd = W.config(args.config)
+    tol = args.methods_tol
+    out = {"mode": "methods", "config": args.config, "tol_rnorm": tol, "methods": {}}
+    pb = B.Problem(sysd)
+    Psi = pb.to_device(W.gaussian_block(1, pb.npw, pb.p))
+    st0, _ = pb.scf(Psi, dict(W.DEFAULT_SCF_PARAMS, tol=0.1), allow_noconv=True)
+    start = Psi.clone()
+    R, L, rn0, E0 = pb.residual(start)
+    out["start"] = {"scf_iters": st0["iters"], "napply": st0["napply"], "rnorm": rn0, "energy": E0}
+    print(f"[bench] {args.config} start: SCF {st0['iters']} steps, ||R||={rn0:.3e}", file=sys.stderr, flush=True)
+    pb.close()
+    runs = [("EARCG", B.EAHP_EARCG, B.EAHP_FP64), ("EARCG_mixed", B.EAHP_EARCG, B.EAHP_MIXED),
+            ("EARGD", B.EAHP_EARGD, B.EAHP_FP64), ("L2RCG", B.EAHP_L2RCG, B.EAHP_FP64)]
+    want = set(args.methods_list.split(","))
+    for name, method, prec in runs:
+        if name not in want:
+            continue
+        pb = B.Problem(sysd, precision=prec)
+        Psi = start.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, rc = pb.solve(Psi, dict(W.DEFAULT_PARAMS, tol=tol, maxit=args.methods_maxit, method=method),
+                          allow_noconv=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["methods"][name] = {"iters": st["iters"], "napply": st["napply"], "napply_fp32": st["napply_fp32"],
+                                "rnorm": st["rnorm"], "energy": st["energy"], "seconds": dt, "converged": rc == 0}
+        print(f"[bench] {name}: {st['iters']} it, {st['napply']} H-applies, {st['fom_iters']} FOM iterations, "
+              f"||R||={st['rnorm']:.2e}, {dt:.3f} s", file=sys.stderr, flush=True)
+        out["methods"][name]["fom_iters"] = st["fom_iters"]
+        pb.close()
+    if "SCF" not in want:
+        print(json.dumps(out), flush=True)
+        return
+    # SCF from the same start: density residual tightened until ||R||_F <= tol
+    pb = B.Problem(sysd)
+    Psi = start.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    napply, iters, rtol, rn = 0, 0, 1e-3, float("inf")
+    while rtol >= 1e-12:
+        st, rc = pb.scf(Psi, dict(W.DEFAULT_SCF_PARAMS, tol=rtol), allow_noconv=True)
+        napply += st["napply"]
+        iters += st["iters"]
+        R, L, rn, E = pb.residual(Psi)
+        if rn <= tol:
+            break
+        rtol *= 0.1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["methods"]["SCF"] = {"iters": iters, "napply": napply, "rnorm": rn, "energy": E, "seconds": dt,
+                             "converged": rn <= tol}
+    print(f"[bench] SCF: {iters} steps, {napply} H-applies, ||R||={rn:.2e}, {dt:.3f} s", file=sys.stderr, flush=True)
+    pb.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +275,11 @@ def main():
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--budget-gib", type=int, default=200)
     ap.add_argument("--serving-maxit", type=int, default=200)
+    ap.add_argument("--methods", action="store_true",
+                    help="compare EARCG, EARGD, L2RCG and SCF from the paper's SCF start instead")
+    ap.add_argument("--methods-tol", type=float, default=1e-6)
+    ap.add_argument("--methods-maxit", type=int, default=2000)
+    ap.add_argument("--methods-list", default="EARCG,EARCG_mixed,EARGD,L2RCG,SCF")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not part of this build",
@@ -217,6 +290,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serving > 0:
         serving(args)
+        return
+    if args.methods:
+        methods(args)
         return
     head = measure(args, args.precision)
     other = None

@@ -294,7 +294,8 @@ typedef struct {
   double beta;     /* damping of the mixed update, > 0                                   */
   int depth;       /* Anderson history length 1..16 (1: damped simple mixing)            */
   double eig_tol;  /* eigensolver stop: every ||H x - theta x|| <= eig_tol at every k;   */
-                   /* 0: adaptive, 0.1 x the last density residual within [1e-12, 1e-2] */
+                   /* 0: adaptive, 0.1 x the last density residual within [1e-12, 1e-2]; */
+                   /* then tol counts only after a step solved to max(1e-12, 0.1 tol)   */
   int eig_maxit;   /* eigensolver iterations per k-point and SCF step                   */
 } eahp_scf_params;
 typedef struct {

@@ -20,7 +20,9 @@
 // squares solution of dF g = f (modified Gram-Schmidt QR of dF, columns with
 // r_jj <= 1e-13 max r dropped), rho_next = rho - dX g + beta (f - dF g);
 // without history rho_next = rho + beta f.  Stop when
-// ||rho_out - rho_in||_2 (the L2 norm over the cell) <= tol.
+// ||rho_out - rho_in||_2 (the L2 norm over the cell) <= tol, with the
+// adaptive eigensolver tolerance (0.1 x the last residual, within [1e-12,
+// 1e-2]) only after a step solved to at most max(1e-12, 0.1 tol).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -394,8 +396,13 @@ void scf_run(eahp_problem* pb, z64* Psi, const eahp_scf_params& prm, eahp_scf_st
     dots(pb, Ng, {{fs, fs}}, d);
     res = std::sqrt(std::max(d[0], 0.0)) * l2;
     if (!std::isfinite(res)) fail(EAHP_ENONFINITE, "non-finite density residual");
-    if (res <= prm.tol || it >= prm.maxit) break;
-    if (prm.eig_tol <= 0) eig_tol = std::min(1e-2, std::max(1e-12, 0.1 * res));
+    // with the adaptive eigensolver tolerance a small residual is accepted only
+    // from a step whose eigenpairs were solved to 0.1 tol (a loose solve from a
+    // nearly converged block returns it unchanged, and rho_out = rho_in)
+    const double eig_need = std::max(1e-12, 0.1 * prm.tol);
+    const bool solved_enough = prm.eig_tol > 0 || eig_tol <= eig_need * (1.0 + 1e-12);
+    if ((res <= prm.tol && solved_enough) || it >= prm.maxit) break;
+    if (prm.eig_tol <= 0) eig_tol = std::min(1e-2, std::max(1e-12, 0.1 * std::max(res, prm.tol)));
     nh = std::min(nh + 1, D);
     // entries oldest -> newest
     std::vector<const double*> X_(nh), F_(nh);
