@@ -632,8 +632,9 @@ void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const 
       int dev = 0, ncu = 0;
       HIPCK(hipGetDevice(&dev));
       HIPCK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-      // one work-group per 16 columns: enough waves for the column loops, few work-groups per barrier
-      const int G = std::min({std::max(1, per_cu) * ncu, ncu, std::max(1, (q + 15) / 16)});
+      // one work-group per 32 columns: the grid barrier of every step costs
+      // more with more work-groups than their added bandwidth gains
+      const int G = std::min({std::max(1, per_cu) * ncu, ncu, std::max(1, (q + 31) / 32)});
       int qq = q;
       int64_t la = lda, lv = q;
       void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P};
