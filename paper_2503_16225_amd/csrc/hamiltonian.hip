@@ -26,12 +26,12 @@
 
 // line lengths with register transforms (x lines, square yz planes), as (n1, N1, N2)
 #define EAHP_XREG_SIZES(X)                                                                                     \
-  X(18, 3, 6) X(20, 4, 5) X(24, 4, 6) X(27, 3, 9) X(30, 5, 6) X(32, 4, 8) X(36, 6, 6) X(40, 5, 8) X(45, 5, 9)   \
+  X(12, 3, 4) X(15, 3, 5) X(16, 4, 4) X(18, 3, 6) X(20, 4, 5) X(24, 4, 6) X(27, 3, 9) X(30, 5, 6) X(32, 4, 8) X(36, 6, 6) X(40, 5, 8) X(45, 5, 9)   \
   X(48, 6, 8) X(50, 5, 10) X(54, 6, 9) X(60, 6, 10) X(64, 8, 8) X(72, 8, 9) X(75, 5, 15) X(80, 8, 10)          \
   X(81, 9, 9) X(90, 9, 10) X(96, 8, 12) X(100, 10, 10) X(108, 9, 12) X(120, 10, 12) X(128, 8, 16) X(144, 12, 12)
 // square yz planes whose padded plane fits LDS in single precision (double: up to 100)
 #define EAHP_YZREG_SIZES(X)                                                                                    \
-  X(18, 3, 6) X(20, 4, 5) X(24, 4, 6) X(27, 3, 9) X(30, 5, 6) X(32, 4, 8) X(36, 6, 6) X(40, 5, 8) X(45, 5, 9)   \
+  X(12, 3, 4) X(15, 3, 5) X(16, 4, 4) X(18, 3, 6) X(20, 4, 5) X(24, 4, 6) X(27, 3, 9) X(30, 5, 6) X(32, 4, 8) X(36, 6, 6) X(40, 5, 8) X(45, 5, 9)   \
   X(48, 6, 8) X(50, 5, 10) X(54, 6, 9) X(60, 6, 10) X(64, 8, 8) X(72, 8, 9) X(75, 5, 15) X(80, 8, 10)          \
   X(81, 9, 9) X(90, 9, 10) X(96, 8, 12) X(100, 10, 10) X(108, 9, 12) X(120, 10, 12) X(128, 8, 16)
 

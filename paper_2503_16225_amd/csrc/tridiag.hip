@@ -595,6 +595,16 @@ void tridiag_reg_launch(hipStream_t st, int q, int p, z64* A, int64_t lda, doubl
 }
 }  // namespace
 
+// Q^H Y (forward) or Q Y for q > 512: a wave per column with the column in
+// registers up to q = 1536, a work-group per column beyond
+static void apply_refl_large(hipStream_t st, int q, int p, const z64* Vh, const double* bt, z64* Yt, int forward) {
+  const dim3 g((p + 3) / 4), b(256);
+  if (q <= 1024) hipLaunchKernelGGL(k_apply_refl_reg<16>, g, b, 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, p, forward);
+  else if (q <= 1536)
+    hipLaunchKernelGGL(k_apply_refl_reg<24>, g, b, 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, p, forward);
+  else hipLaunchKernelGGL(k_apply_refl, dim3(p), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, forward);
+}
+
 void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws) {
   if (q <= 0 || p <= 0) return;
   if (q > 3200) fail(EAHP_EINVAL, "projected FOM system larger than 3200");
@@ -640,7 +650,7 @@ void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const 
       void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P};
       HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(G), dim3(1024), args, lds, st));
       HIPCK(hipStreamSynchronize(st));
-      hipLaunchKernelGGL(k_apply_refl, dim3(p), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, 1);
+      apply_refl_large(st, q, p, Vh, bt, Yt, 1);
     }
   } else {
     hipLaunchKernelGGL(k_set_d0, dim3(1), dim3(1), 0, st, A, dd);
@@ -652,7 +662,7 @@ void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const 
     else if (q <= 256) hipLaunchKernelGGL(k_apply_refl_reg<4>, g, b, 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, p, 0);
     else hipLaunchKernelGGL(k_apply_refl_reg<8>, g, b, 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, p, 0);
   } else if (q >= 2) {
-    hipLaunchKernelGGL(k_apply_refl, dim3(p), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, 0);
+    apply_refl_large(st, q, p, Vh, bt, Yt, 0);
   }
   HIPCK(hipGetLastError());
 }
