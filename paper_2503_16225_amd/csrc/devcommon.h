@@ -26,6 +26,33 @@ template <typename T> __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) 
 // s * i * a  (s = +1 or -1)
 template <typename T> __device__ __forceinline__ cplx<T> muli(cplx<T> a, T s) { return mk<T>(-s * a.y, s * a.x); }
 
+// ------------------------------------------------------------------ buffer access
+// Complex loads and stores through a raw buffer resource over [base, base +
+// bytes): a 32-bit byte offset per lane, the base in scalar registers.  An
+// offset at or beyond `bytes` reads zero and drops the store (the hardware's
+// range check), which lets a lane skip an element without a branch.
+constexpr uint32_t kBufOob = 0x7ffffff0u;
+constexpr int kBufDword3 = 0x00020000;
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_buf(const cplx<T>* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<cplx<T>*>(base), (short)0, (int)bytes, kBufDword3);
+}
+template <typename T> __device__ __forceinline__ cplx<T> buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ cplx<float> buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(cplx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <> __device__ __forceinline__ cplx<double> buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(cplx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, cplx<float> v) {
+  using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, cplx<double> v) {
+  using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, (int)off, 0, 0);
+}
+
 // ------------------------------------------------------------------ small DFTs
 // y_k = sum_j u_j exp(sign * 2 pi i j k / R), in place.
 template <typename T, int R> struct Dft;

@@ -389,11 +389,16 @@ static void launch_lines(hipStream_t st, cplx<T>* base, int64_t pstride, int npl
 // 8 waves per (plane, column), the plane in LDS with row stride n + 1.
 // z-lines (rows, only |m2| <= m2max) and y-lines (columns) each take 16
 // lines per wave and 4 lane groups; every step works in place on its
-// line's LDS positions, so each transform needs only the barriers between
-// its two steps (plus one where the natural-order results are written back).
-// The y-transform reads (forward) or writes (inverse) the slab directly:
-// 16 consecutive i3 of one row per lane group.
+// line's LDS positions (step B leaves frequency k1 + N1 k2 of a line at
+// position N2 k1 + k2, and the next transform or the gather reads it there),
+// so each transform needs only the barrier between its two steps and no
+// lane holds more than one sub-DFT.  The y-transform reads (forward) or
+// writes (inverse) the slab directly: 16 consecutive i3 of one row per lane
+// group.
 constexpr int kYzThreads = 512;
+// waves per SIMD the register allocation must allow: two work-groups of 8
+// waves per CU in FP32 (the LDS holds two FP32 planes up to n = 90)
+template <typename T> constexpr int yz_waves_per_simd() { return sizeof(T) == 4 ? 4 : 2; }
 
 __device__ __forceinline__ bool row_active(int r, int n, int m2max) { return r <= m2max || r >= n - m2max; }
 
@@ -423,24 +428,8 @@ __device__ __forceinline__ void yz_step_a(cplx<T>* base, int es, int grp, const 
   }
 }
 
-// Step B, first half: z(k1; j2) for the lane's k1 = grp + 4b into registers
-// and the size-N2 DFTs; y[b][k2] is element k1 + N1 k2 of the line.
 template <typename T, int N1, int N2>
-__device__ __forceinline__ void yz_step_b(const cplx<T>* base, int es, int grp, T sg, cplx<T> (&y)[(N1 + 3) / 4][N2]) {
-  constexpr int KB = (N1 + 3) / 4;
-#pragma unroll
-  for (int b = 0; b < KB; ++b) {
-    const int k1 = grp + 4 * b;
-    if (k1 < N1) {
-#pragma unroll
-      for (int j2 = 0; j2 < N2; ++j2) y[b][j2] = base[(k1 * N2 + j2) * es];
-      RegFft<T, N2>::run(y[b], sg);
-    }
-  }
-}
-
-template <typename T, int N1, int N2>
-__global__ void __launch_bounds__(kYzThreads) k_inv_yz_reg(ColMap cm, GridGeom g, const cplx<T>* __restrict__ tws,
+__global__ void __launch_bounds__(kYzThreads, yz_waves_per_simd<T>()) k_inv_yz_reg(ColMap cm, GridGeom g, const cplx<T>* __restrict__ tws,
                                                            const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Tb) {
   constexpr int n = N1 * N2, LS = n + 1, KB = (N1 + 3) / 4;
   extern __shared__ unsigned char smem_raw[];
@@ -469,7 +458,10 @@ __global__ void __launch_bounds__(kYzThreads) k_inv_yz_reg(ColMap cm, GridGeom g
     P[i2 * LS + (e - i2 * n)] = x[q];
   }
   __syncthreads();
-  // z-lines: rows with |m2| <= m2max
+  // z-lines: rows with |m2| <= m2max.  Step B writes each size-N2 DFT back
+  // over the positions it read (frequency k1 + N1 k2 at position N2 k1 + k2),
+  // so no lane waits for another before writing; the y-lines read the
+  // columns in that order.
   const int zpasses = (nrow + 16 * (kYzThreads / 64) - 1) / (16 * (kYzThreads / 64));
   for (int ps = 0; ps < zpasses; ++ps) {
     const int l = (ps * (kYzThreads / 64) + wave) * 16 + t;
@@ -478,38 +470,42 @@ __global__ void __launch_bounds__(kYzThreads) k_inv_yz_reg(ColMap cm, GridGeom g
     cplx<T>* row = P + r * LS;
     if (l < nrow) yz_step_a<T, N1, N2, false>(row, 1, grp, tw, (T)1, n, m2);
     __syncthreads();
-    cplx<T> y[KB][N2];
-    if (l < nrow) yz_step_b<T, N1, N2>(row, 1, grp, (T)1, y);
-    __syncthreads();
     if (l < nrow) {
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
         const int k1 = grp + 4 * b;
         if (k1 < N1) {
+          cplx<T> y[N2];
 #pragma unroll
-          for (int k2 = 0; k2 < N2; ++k2) row[k1 + N1 * k2] = y[b][k2];
+          for (int j2 = 0; j2 < N2; ++j2) y[j2] = row[k1 * N2 + j2];
+          RegFft<T, N2>::run(y, (T)1);
+#pragma unroll
+          for (int k2 = 0; k2 < N2; ++k2) row[k1 * N2 + k2] = y[k2];
         }
       }
     }
-    __syncthreads();
   }
-  // y-lines: every column, results straight to the slab
+  __syncthreads();
+  // y-lines: every z-frequency i3 (its column at position N2 (i3 mod N1) +
+  // i3 div N1), results straight to the slab, one size-N2 DFT at a time
   cplx<T>* out = Tb + ((int64_t)c * g.ns + s) * g.ps;
   constexpr int ypasses = (n + 16 * (kYzThreads / 64) - 1) / (16 * (kYzThreads / 64));
   for (int ps = 0; ps < ypasses; ++ps) {
     const int i3 = (ps * (kYzThreads / 64) + wave) * 16 + t;
-    cplx<T>* col = P + i3;
+    cplx<T>* col = P + (i3 % N1) * N2 + i3 / N1;
     if (i3 < n) yz_step_a<T, N1, N2, true>(col, LS, grp, tw, (T)1, n, m2);
     __syncthreads();
     if (i3 < n) {
-      cplx<T> y[KB][N2];
-      yz_step_b<T, N1, N2>(col, LS, grp, (T)1, y);
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
         const int k1 = grp + 4 * b;
         if (k1 < N1) {
+          cplx<T> y[N2];
 #pragma unroll
-          for (int k2 = 0; k2 < N2; ++k2) out[(k1 + N1 * k2) * n + i3] = y[b][k2];
+          for (int j2 = 0; j2 < N2; ++j2) y[j2] = col[(k1 * N2 + j2) * LS];
+          RegFft<T, N2>::run(y, (T)1);
+#pragma unroll
+          for (int k2 = 0; k2 < N2; ++k2) out[(k1 + N1 * k2) * n + i3] = y[k2];
         }
       }
     }
@@ -517,7 +513,7 @@ __global__ void __launch_bounds__(kYzThreads) k_inv_yz_reg(ColMap cm, GridGeom g
 }
 
 template <typename T, int N1, int N2>
-__global__ void __launch_bounds__(kYzThreads) k_fwd_yz_reg(ColMap cm, GridGeom g, const cplx<T>* __restrict__ tws,
+__global__ void __launch_bounds__(kYzThreads, yz_waves_per_simd<T>()) k_fwd_yz_reg(ColMap cm, GridGeom g, const cplx<T>* __restrict__ tws,
                                                            const cplx<T>* __restrict__ Tb,
                                                            const cplx<T>* __restrict__ X, cplx<T>* __restrict__ HX,
                                                            T scale) {
@@ -560,57 +556,59 @@ __global__ void __launch_bounds__(kYzThreads) k_fwd_yz_reg(ColMap cm, GridGeom g
       }
     }
     __syncthreads();
-    cplx<T> y[KB][N2];
-    if (ok) yz_step_b<T, N1, N2>(P + i3, LS, grp, (T)-1, y);
-    __syncthreads();
+    // step B in place: frequency k1 + N1 k2 of the column lands in row N2 k1 + k2
     if (ok) {
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
         const int k1 = grp + 4 * b;
         if (k1 < N1) {
+          cplx<T> y[N2];
 #pragma unroll
-          for (int k2 = 0; k2 < N2; ++k2) {
-            const int r = k1 + N1 * k2;
-            if (row_active(r, n, m2)) P[r * LS + i3] = y[b][k2];
-          }
+          for (int j2 = 0; j2 < N2; ++j2) y[j2] = P[(k1 * N2 + j2) * LS + i3];
+          RegFft<T, N2>::run(y, (T)-1);
+#pragma unroll
+          for (int k2 = 0; k2 < N2; ++k2) P[(k1 * N2 + k2) * LS + i3] = y[k2];
         }
       }
     }
   }
   __syncthreads();
-  // z-lines (forward) on the rows the sphere reaches
+  // z-lines (forward) on the rows the sphere reaches (y-frequency r in row
+  // N2 (r mod N1) + r div N1), step B again in place
   const int zpasses = (nrow + 16 * (kYzThreads / 64) - 1) / (16 * (kYzThreads / 64));
   for (int ps = 0; ps < zpasses; ++ps) {
     const int l = (ps * (kYzThreads / 64) + wave) * 16 + t;
     int r = n - m2 + l;
     r -= r >= n ? n : 0;
-    cplx<T>* row = P + r * LS;
+    cplx<T>* row = P + ((r % N1) * N2 + r / N1) * LS;
     if (l < nrow) yz_step_a<T, N1, N2, false>(row, 1, grp, tw, (T)-1, n, m2);
-    __syncthreads();
-    cplx<T> y[KB][N2];
-    if (l < nrow) yz_step_b<T, N1, N2>(row, 1, grp, (T)-1, y);
     __syncthreads();
     if (l < nrow) {
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
         const int k1 = grp + 4 * b;
         if (k1 < N1) {
+          cplx<T> y[N2];
 #pragma unroll
-          for (int k2 = 0; k2 < N2; ++k2) row[k1 + N1 * k2] = y[b][k2];
+          for (int j2 = 0; j2 < N2; ++j2) y[j2] = row[k1 * N2 + j2];
+          RegFft<T, N2>::run(y, (T)-1);
+#pragma unroll
+          for (int k2 = 0; k2 < N2; ++k2) row[k1 * N2 + k2] = y[k2];
         }
       }
     }
-    __syncthreads();
   }
-  // gather of the sphere, scaled, plus the kinetic term
+  __syncthreads();
+  // gather of the sphere (frequency (i2, i3) at row N2 (i2 mod N1) + i2 div N1,
+  // column N2 (i3 mod N1) + i3 div N1), scaled, plus the kinetic term
   const int pbase = g.plane_i1[s] * n * n;
   const T* kin = kin_of<T>(k);
   const cplx<T>* x = X + xb;
   cplx<T>* yv = HX + xb;
   for (int q = g0 + threadIdx.x; q < g1; q += kYzThreads) {
     const int e = k.box[q] - pbase;
-    const int i2 = e / n;
-    const cplx<T> v = P[i2 * LS + (e - i2 * n)];
+    const int i2 = e / n, i3 = e - i2 * n;
+    const cplx<T> v = P[((i2 % N1) * N2 + i2 / N1) * LS + (i3 % N1) * N2 + i3 / N1];
     const cplx<T> xv = x[q];
     const T kr = kin[q];
     yv[q] = mk<T>(v.x * scale + kr * xv.x, v.y * scale + kr * xv.y);
@@ -751,6 +749,50 @@ void launch_fwd_yz(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& 
   HIPCK(hipGetLastError());
 }
 
+// The register x-kernels address a column's active planes through byte
+// offsets: held in registers for the whole work-group where the extra
+// registers cost no occupancy (offsets[a][j1]), else read per column from an
+// LDS table of plane offsets (XOffsets<false>).
+template <typename T, int N1, int N2, bool kDensity>
+constexpr bool x_hoist_offsets() {
+  constexpr int n = N1 * N2;
+  if (kDensity) return !(n == 30 || n == 45 || n == 100 || n == 120 || n == 128 || n == 144);
+  if (sizeof(T) == 4) return !(n == 54 || n == 60 || n == 75 || n == 80 || n == 81 || n == 120 || n == 128);
+  return !(n == 27 || n == 30 || n == 32 || n == 45);
+}
+template <int JA, int N1, int N2, int G, bool kHoist>
+struct XOffsets {
+  uint32_t off[JA][N1];
+  __device__ __forceinline__ void init(const uint32_t* soff, int grp, uint32_t posb) {
+#pragma unroll
+    for (int a = 0; a < JA; ++a) {
+      const int j2 = grp + G * a;
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) off[a][j1] = j2 < N2 ? soff[N2 * j1 + j2] + posb : kBufOob;
+    }
+  }
+  __device__ __forceinline__ uint32_t get(const uint32_t*, int, uint32_t, int a, int j1) const { return off[a][j1]; }
+};
+template <int JA, int N1, int N2, int G>
+struct XOffsets<JA, N1, N2, G, false> {
+  __device__ __forceinline__ void init(const uint32_t*, int, uint32_t) {}
+  __device__ __forceinline__ uint32_t get(const uint32_t* soff, int grp, uint32_t posb, int a, int j1) const {
+    const int j2 = grp + G * a;
+    return j2 < N2 ? soff[N2 * j1 + j2] + posb : kBufOob;
+  }
+};
+// soff[i1] = byte offset of plane i1 in a column's slab, kBufOob if inactive;
+// posb = the lane's byte offset within a plane, kBufOob past the last line.
+// The host keeps the slab below kBufOob bytes, so soff + posb does not wrap
+// and is out of range whenever either term is.
+template <typename T>
+__device__ __forceinline__ void x_plane_offsets(uint32_t* soff, int n1, const GridGeom& g, int lane) {
+  for (int i = lane; i < n1; i += 64) soff[i] = kBufOob;
+  __syncthreads();
+  for (int s = lane; s < g.ns; s += 64) soff[g.plane_i1[s]] = (uint32_t)((int64_t)s * g.ps * (int64_t)sizeof(cplx<T>));
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ x_local, register x-transform
 // The same operation as k_x_local for n1 = N1 N2 (both products of at most two
 // of 2, 3, 4, 5), with the x-transform as a four-step DFT in registers:
@@ -759,7 +801,9 @@ void launch_fwd_yz(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& 
 //   y(k1 + N1 k2) = sum_j2 w_N2^{j2 k2} z(k1; j2).
 // One wave per work-group, 16 (i2, i3) lines per wave, lane = line + 16 grp.
 // Step A (the lane's j2 = grp + 4a): loads of the active planes straight from
-// the slab (16 consecutive positions per plane), size-N1 DFTs, twiddles, to
+// the slab (16 consecutive positions per plane; buffer loads, the inactive
+// planes reading zero through the buffer's range check), size-N1 DFTs,
+// twiddles, to
 // LDS.  Step B (k1 = grp + 4b): size-N2 DFTs, times V_eff (held in registers
 // for the work-group's columns), inverse size-N2 DFTs, twiddles, to LDS.
 // Step A': inverse size-N1 DFTs, stores of the active planes.  An LDS location
@@ -772,18 +816,16 @@ __global__ void __launch_bounds__(64) k_x_local_reg(int ncols, int cb, GridGeom 
   constexpr int JA = (N2 + G - 1) / G, KB = (N1 + G - 1) / G;
   __shared__ cplx<T> buf[n1 * L];
   __shared__ cplx<T> tw[n1];
-  __shared__ int sidx[n1];
+  __shared__ uint32_t soff[n1];
   const int lane = threadIdx.x, t = lane & (L - 1), grp = lane >> 4;
   const int np = g.n2 * g.n3;
   const int pos = blockIdx.x * L + t;
   const bool valid = pos < np;
-  for (int i = lane; i < n1; i += 64) {
-    tw[i] = twx[i];
-    sidx[i] = -1;
-  }
-  __syncthreads();
-  for (int s = lane; s < g.ns; s += 64) sidx[g.plane_i1[s]] = s;
-  __syncthreads();
+  const uint32_t posb = valid ? (uint32_t)pos * (uint32_t)sizeof(cplx<T>) : kBufOob;
+  for (int i = lane; i < n1; i += 64) tw[i] = twx[i];
+  x_plane_offsets<T>(soff, n1, g, lane);
+  XOffsets<JA, N1, N2, G, x_hoist_offsets<T, N1, N2, false>()> xo;
+  xo.init(soff, grp, posb);
   T vr[KB][N2];
 #pragma unroll
   for (int b = 0; b < KB; ++b) {
@@ -792,19 +834,15 @@ __global__ void __launch_bounds__(64) k_x_local_reg(int ncols, int cb, GridGeom 
     for (int k2 = 0; k2 < N2; ++k2)
       vr[b][k2] = (k1 < N1 && valid) ? V[(int64_t)(k1 + N1 * k2) * np + pos] : (T)0;
   }
+  const uint32_t slab_bytes = (uint32_t)((int64_t)g.ns * g.ps * (int64_t)sizeof(cplx<T>));
   const int c0 = blockIdx.y * cb, c1 = min(ncols, c0 + cb);
   for (int c = c0; c < c1; ++c) {
-    cplx<T>* col = Tb + (int64_t)c * g.ns * g.ps + pos;
+    const __amdgpu_buffer_rsrc_t col = make_buf<T>(Tb + (int64_t)c * g.ns * g.ps, slab_bytes);
     cplx<T> u[JA][N1];
 #pragma unroll
-    for (int a = 0; a < JA; ++a) {
-      const int j2 = grp + G * a;
+    for (int a = 0; a < JA; ++a)
 #pragma unroll
-      for (int j1 = 0; j1 < N1; ++j1) {
-        const int s = j2 < N2 ? sidx[N2 * j1 + j2] : -1;
-        u[a][j1] = (s >= 0 && valid) ? col[(int64_t)s * g.ps] : mk<T>(0, 0);
-      }
-    }
+      for (int j1 = 0; j1 < N1; ++j1) u[a][j1] = buf_load<T>(col, xo.get(soff, grp, posb, a, j1));
 #pragma unroll
     for (int a = 0; a < JA; ++a) {
       const int j2 = grp + G * a;
@@ -843,13 +881,8 @@ __global__ void __launch_bounds__(64) k_x_local_reg(int ncols, int cb, GridGeom 
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) x[k1] = buf[(k1 * N2 + j2) * L + t];
         RegFft<T, N1>::run(x, (T)-1);
-        if (valid) {
 #pragma unroll
-          for (int j1 = 0; j1 < N1; ++j1) {
-            const int s = sidx[N2 * j1 + j2];
-            if (s >= 0) col[(int64_t)s * g.ps] = x[j1];
-          }
-        }
+        for (int j1 = 0; j1 < N1; ++j1) buf_store(col, xo.get(soff, grp, posb, a, j1), x[j1]);
       }
     }
   }
@@ -859,6 +892,7 @@ template <typename T>
 static bool launch_x_local_reg(hipStream_t st, int ncols, const GridGeom& g, const cplx<T>* twx, const T* V,
                                cplx<T>* Tb) {
   const int np = g.n2 * g.n3;
+  if ((int64_t)g.ns * g.ps * (int64_t)sizeof(cplx<T>) >= (int64_t)kBufOob) return false;
   const int ntiles = (np + 15) / 16;
   // columns per work-group: V is loaded once per work-group; keep >= 2048 work-groups
   int cb = 8;
@@ -934,40 +968,34 @@ __global__ void __launch_bounds__(64) k_x_density_reg(ColMap cm, int ncols, int 
   constexpr int JA = (N2 + G - 1) / G, KB = (N1 + G - 1) / G;
   __shared__ z64 buf[n1 * L];
   __shared__ z64 tw[n1];
-  __shared__ int sidx[n1];
+  __shared__ uint32_t soff[n1];
   const int lane = threadIdx.x, t = lane & (L - 1), grp = lane >> 4;
   const int np = g.n2 * g.n3;
   const int pos = blockIdx.x * L + t;
   const bool valid = pos < np;
-  for (int i = lane; i < n1; i += 64) {
-    tw[i] = twx[i];
-    sidx[i] = -1;
-  }
-  __syncthreads();
-  for (int s = lane; s < g.ns; s += 64) sidx[g.plane_i1[s]] = s;
-  __syncthreads();
+  const uint32_t posb = valid ? (uint32_t)pos * (uint32_t)sizeof(z64) : kBufOob;
+  for (int i = lane; i < n1; i += 64) tw[i] = twx[i];
+  x_plane_offsets<double>(soff, n1, g, lane);
+  XOffsets<JA, N1, N2, G, x_hoist_offsets<double, N1, N2, true>()> xo;
+  xo.init(soff, grp, posb);
   double acc[KB][N2];
 #pragma unroll
   for (int b = 0; b < KB; ++b)
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) acc[b][k2] = 0.0;
+  const uint32_t slab_bytes = (uint32_t)((int64_t)g.ns * g.ps * (int64_t)sizeof(z64));
   const int cbeg = blockIdx.y * cpg, cend = min(ncols, cbeg + cpg);
   rho += blockIdx.y * sgrp;
   for (int c = cbeg; c < cend; ++c) {
     int64_t base;
     const KDesc& k = col_kd(cm, c, base);
     const double wgt = k.w * occ_over_omega;
-    const z64* col = Tb + (int64_t)c * g.ns * g.ps + pos;
+    const __amdgpu_buffer_rsrc_t col = make_buf<double>(Tb + (int64_t)c * g.ns * g.ps, slab_bytes);
     z64 u[JA][N1];
 #pragma unroll
-    for (int a = 0; a < JA; ++a) {
-      const int j2 = grp + G * a;
+    for (int a = 0; a < JA; ++a)
 #pragma unroll
-      for (int j1 = 0; j1 < N1; ++j1) {
-        const int s = j2 < N2 ? sidx[N2 * j1 + j2] : -1;
-        u[a][j1] = (s >= 0 && valid) ? col[(int64_t)s * g.ps] : mk<double>(0, 0);
-      }
-    }
+      for (int j1 = 0; j1 < N1; ++j1) u[a][j1] = buf_load<double>(col, xo.get(soff, grp, posb, a, j1));
 #pragma unroll
     for (int a = 0; a < JA; ++a) {
       const int j2 = grp + G * a;
@@ -1013,6 +1041,7 @@ __global__ void __launch_bounds__(64) k_x_density_reg(ColMap cm, int ncols, int 
 
 static bool launch_x_density_reg(hipStream_t st, const ColMap& cm, int ncols, const GridGeom& g, const z64* twx,
                                  const z64* Tb, double occ_over_omega, double* rho, int accumulate, DevMem& part) {
+  if ((int64_t)g.ns * g.ps * (int64_t)sizeof(z64) >= (int64_t)kBufOob) return false;
   switch (g.n1) {
 #define X(n, a, b) case n:
     EAHP_XREG_SIZES(X)
