@@ -422,7 +422,7 @@ __device__ __forceinline__ void yz_step_a(cplx<T>* base, int es, int grp, const 
       for (int k1 = 0; k1 < N1; ++k1) {
         cplx<T> w = tw[j2 * k1];
         w.y *= -sg;  // the table holds exp(-2 pi i m / n)
-        base[(k1 * N2 + j2) * es] = cmul<T>(u[k1], w);
+        base[(k1 * N2 + j2) * es] = k1 == 0 ? u[0] : cmul<T>(u[k1], w);
       }
     }
   }
@@ -551,7 +551,8 @@ __global__ void __launch_bounds__(kYzThreads, yz_waves_per_simd<T>()) k_fwd_yz_r
         if (j2 < N2) {
           RegFft<T, N1>::run(u[a], (T)-1);
 #pragma unroll
-          for (int k1 = 0; k1 < N1; ++k1) P[(k1 * N2 + j2) * LS + i3] = cmul<T>(u[a][k1], tw[j2 * k1]);
+          for (int k1 = 0; k1 < N1; ++k1)
+            P[(k1 * N2 + j2) * LS + i3] = k1 == 0 ? u[a][0] : cmul<T>(u[a][k1], tw[j2 * k1]);
         }
       }
     }
@@ -757,8 +758,8 @@ template <typename T, int N1, int N2, bool kDensity>
 constexpr bool x_hoist_offsets() {
   constexpr int n = N1 * N2;
   if (kDensity) return !(n == 30 || n == 45 || n == 100 || n == 120 || n == 128 || n == 144);
-  if (sizeof(T) == 4) return !(n == 54 || n == 60 || n == 75 || n == 80 || n == 81 || n == 120 || n == 128);
-  return !(n == 27 || n == 30 || n == 32 || n == 45);
+  if (sizeof(T) == 4) return !(n == 54 || n == 60 || n == 75 || n == 80 || n == 81 || n == 100 || n == 120 || n == 128);
+  return !(n == 27 || n == 30 || n == 32 || n == 45 || n == 100);
 }
 template <int JA, int N1, int N2, int G, bool kHoist>
 struct XOffsets {
@@ -852,7 +853,7 @@ __global__ void __launch_bounds__(64) k_x_local_reg(int ncols, int cb, GridGeom 
         for (int k1 = 0; k1 < N1; ++k1) {
           cplx<T> w = tw[j2 * k1];
           w.y = -w.y;  // exp(+2 pi i j2 k1 / n1)
-          buf[(k1 * N2 + j2) * L + t] = cmul<T>(u[a][k1], w);
+          buf[(k1 * N2 + j2) * L + t] = k1 == 0 ? u[a][0] : cmul<T>(u[a][k1], w);
         }
       }
     }
@@ -869,7 +870,7 @@ __global__ void __launch_bounds__(64) k_x_local_reg(int ncols, int cb, GridGeom 
         for (int k2 = 0; k2 < N2; ++k2) y[k2] = cscale<T>(y[k2], vr[b][k2]);
         RegFft<T, N2>::run(y, (T)-1);
 #pragma unroll
-        for (int j2 = 0; j2 < N2; ++j2) buf[(k1 * N2 + j2) * L + t] = cmul<T>(y[j2], tw[j2 * k1]);
+        for (int j2 = 0; j2 < N2; ++j2) buf[(k1 * N2 + j2) * L + t] = j2 == 0 ? y[0] : cmul<T>(y[j2], tw[j2 * k1]);
       }
     }
     __syncthreads();
@@ -895,6 +896,8 @@ static bool launch_x_local_reg(hipStream_t st, int ncols, const GridGeom& g, con
   if ((int64_t)g.ns * g.ps * (int64_t)sizeof(cplx<T>) >= (int64_t)kBufOob) return false;
   const int ntiles = (np + 15) / 16;
   // columns per work-group: V is loaded once per work-group; keep >= 2048 work-groups
+  // (8 columns: at 16 the grid of the 90^3 box fills the chip 1.3 times and the
+  // second, partial round of work-groups costs more than the V loads saved)
   int cb = 8;
   while (cb > 1 && (int64_t)ntiles * ((ncols + cb - 1) / cb) < 2048) cb /= 2;
   dim3 grid(ntiles, (ncols + cb - 1) / cb);
@@ -1005,7 +1008,7 @@ __global__ void __launch_bounds__(64) k_x_density_reg(ColMap cm, int ncols, int 
         for (int k1 = 0; k1 < N1; ++k1) {
           z64 w = tw[j2 * k1];
           w.y = -w.y;
-          buf[(k1 * N2 + j2) * L + t] = cmul<double>(u[a][k1], w);
+          buf[(k1 * N2 + j2) * L + t] = k1 == 0 ? u[a][0] : cmul<double>(u[a][k1], w);
         }
       }
     }
