@@ -129,7 +129,11 @@ def measure(args, precision):
     lib.eahp_solver_destroy(sv)
     pb.close()
     elapsed = t1 - t0
-    return {"napply": st.napply - n0, "napply_fp32": st.napply_fp32 - n32, "elapsed": elapsed,
+    nk = len(sysd["kweight"]) if sysd.get("kweight") is not None else 1
+    desc = (f"{args.config}: diamond-structure model, {len(sysd['Z'])} atoms, p={pb.p}, Ecut {sysd['ecut']:g} Ha, "
+            f"{'x'.join(str(n) for n in pb.fft)} box, {'Gamma' if nk == 1 else f'{nk} k-points'}, "
+            f"seeded random start, EARCG outer iterations")
+    return {"napply": st.napply - n0, "napply_fp32": st.napply_fp32 - n32, "elapsed": elapsed, "desc": desc,
             "value": (st.napply - n0) / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
             "energy": st.energy, "rnorm": st.rnorm, "kernels": kern}
 
@@ -320,8 +324,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32 metric solve, f64 outer iteration",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: 2x2x2 diamond supercell, 64 atoms, p=128, Ecut 20 Ha, 90^3 box, "
-                               f"Gamma, seeded random start, EARCG outer iterations",
+        "config": {"workload": head["desc"],
                    "precision": args.precision,
                    "napply": head["napply"], "napply_fp32": head["napply_fp32"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
