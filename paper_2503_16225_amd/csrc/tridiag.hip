@@ -475,8 +475,9 @@ __global__ void __launch_bounds__(256) k_apply_refl_reg(int q, const z64* __rest
 
 // (T - s_l I) y = b for every column l, Gaussian elimination with partial
 // pivoting between adjacent rows, one thread per column.  The running row and
-// right-hand side stay in registers; the finished rows (diagonal, first and
-// second super-diagonal) go to W with the columns interleaved (coalesced).
+// right-hand side stay in registers; the finished rows (inverse of the pivot,
+// first and second super-diagonal) go to W with the columns interleaved
+// (coalesced).
 __global__ void __launch_bounds__(64) k_trisolve_reg(int q, int ncols, const double* __restrict__ d,
                                                      const z64* __restrict__ e, const double* __restrict__ sh,
                                                      z64* B, int64_t ldb, z64* W) {
@@ -484,50 +485,95 @@ __global__ void __launch_bounds__(64) k_trisolve_reg(int q, int ncols, const dou
   if (l >= ncols) return;
   z64* b = B + (int64_t)l * ldb;
   auto row = [&](int i, int c) -> z64& { return W[((int64_t)3 * i + c) * ncols + l]; };
-  auto rdiv = [](z64 a, z64 c) {
+  // 1/c = conj(c) / |c|^2
+  auto rinv = [](z64 c) {
     const double r = 1.0 / (c.x * c.x + c.y * c.y);
-    return mk<double>((a.x * c.x + a.y * c.y) * r, (a.y * c.x - a.x * c.y) * r);
+    return mk<double>(c.x * r, -c.y * r);
   };
   const double s = sh[l];
   z64 Dc = mk<double>(d[0] - s, 0.0);
   z64 Uc = q > 1 ? mk<double>(e[0].x, -e[0].y) : mk<double>(0.0, 0.0);
   z64 bc = b[0];
-  for (int i = 0; i + 1 < q; ++i) {
-    const z64 L = e[i];
-    const z64 Dn = mk<double>(d[i + 1] - s, 0.0);
-    const z64 Un = i + 2 < q ? mk<double>(e[i + 1].x, -e[i + 1].y) : mk<double>(0.0, 0.0);
-    const z64 bn = b[i + 1];
-    if (sqrt(Dc.x * Dc.x + Dc.y * Dc.y) >= sqrt(L.x * L.x + L.y * L.y)) {
-      const z64 f = rdiv(L, Dc);
-      row(i, 0) = Dc;
-      row(i, 1) = Uc;
-      row(i, 2) = mk<double>(0.0, 0.0);
-      b[i] = bc;
-      Dc = csub<double>(Dn, cmul<double>(f, Uc));
-      Uc = Un;
-      bc = csub<double>(bn, cmul<double>(f, bc));
-    } else {
-      const z64 f = rdiv(Dc, L);
-      row(i, 0) = L;
-      row(i, 1) = Dn;
-      row(i, 2) = Un;
-      b[i] = bn;
-      const z64 Dnew = csub<double>(Uc, cmul<double>(f, Dn));
-      Uc = mk<double>(-(f.x * Un.x - f.y * Un.y), -(f.x * Un.y + f.y * Un.x));
-      bc = csub<double>(bc, cmul<double>(f, bn));
-      Dc = Dnew;
+  // forward elimination with row pivoting (the larger of |Dc|, |L| as the
+  // pivot, compared squared); each row keeps the inverse of its pivot, so
+  // the back substitution has no division on its dependency chain.  The
+  // entries of a block of rows are loaded together before the block is
+  // eliminated, one memory latency per block instead of per row.
+  constexpr int PB = 16;
+  for (int i0 = 0; i0 + 1 < q; i0 += PB) {
+    z64 Lb[PB], Ub[PB], Bb[PB];
+    double Db[PB];
+#pragma unroll
+    for (int j = 0; j < PB; ++j) {
+      const int i = i0 + j;
+      if (i + 1 < q) {
+        Lb[j] = e[i];
+        Db[j] = d[i + 1];
+        Ub[j] = i + 2 < q ? mk<double>(e[i + 1].x, -e[i + 1].y) : mk<double>(0.0, 0.0);
+        Bb[j] = b[i + 1];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PB; ++j) {
+      const int i = i0 + j;
+      if (i + 1 < q) {
+        const z64 L = Lb[j];
+        const z64 Dn = mk<double>(Db[j] - s, 0.0);
+        const z64 Un = Ub[j];
+        const z64 bn = Bb[j];
+        if (Dc.x * Dc.x + Dc.y * Dc.y >= L.x * L.x + L.y * L.y) {
+          const z64 iD = rinv(Dc);
+          const z64 f = cmul<double>(L, iD);
+          row(i, 0) = iD;
+          row(i, 1) = Uc;
+          row(i, 2) = mk<double>(0.0, 0.0);
+          b[i] = bc;
+          Dc = csub<double>(Dn, cmul<double>(f, Uc));
+          Uc = Un;
+          bc = csub<double>(bn, cmul<double>(f, bc));
+        } else {
+          const z64 iL = rinv(L);
+          const z64 f = cmul<double>(Dc, iL);
+          row(i, 0) = iL;
+          row(i, 1) = Dn;
+          row(i, 2) = Un;
+          b[i] = bn;
+          const z64 Dnew = csub<double>(Uc, cmul<double>(f, Dn));
+          Uc = mk<double>(-(f.x * Un.x - f.y * Un.y), -(f.x * Un.y + f.y * Un.x));
+          bc = csub<double>(bc, cmul<double>(f, bn));
+          Dc = Dnew;
+        }
+      }
     }
   }
-  // back substitution, x_{i+1} and x_{i+2} carried in registers
-  z64 x1 = rdiv(bc, Dc), x2 = mk<double>(0.0, 0.0);
+  // back substitution, x_{i+1} and x_{i+2} carried in registers, blocks of
+  // rows loaded ahead as above
+  z64 x1 = cmul<double>(bc, rinv(Dc)), x2 = mk<double>(0.0, 0.0);
   b[q - 1] = x1;
-  for (int i = q - 2; i >= 0; --i) {
-    z64 r = csub<double>(b[i], cmul<double>(row(i, 1), x1));
-    r = csub<double>(r, cmul<double>(row(i, 2), x2));
-    const z64 xi = rdiv(r, row(i, 0));
-    b[i] = xi;
-    x2 = x1;
-    x1 = xi;
+  for (int i1 = q - 2; i1 >= 0; i1 -= PB) {
+    z64 R0[PB], R1[PB], R2[PB], Bb[PB];
+#pragma unroll
+    for (int j = 0; j < PB; ++j) {
+      const int i = i1 - j;
+      if (i >= 0) {
+        R0[j] = row(i, 0);
+        R1[j] = row(i, 1);
+        R2[j] = row(i, 2);
+        Bb[j] = b[i];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PB; ++j) {
+      const int i = i1 - j;
+      if (i >= 0) {
+        z64 r = csub<double>(Bb[j], cmul<double>(R1[j], x1));
+        r = csub<double>(r, cmul<double>(R2[j], x2));
+        const z64 xi = cmul<double>(r, R0[j]);
+        b[i] = xi;
+        x2 = x1;
+        x1 = xi;
+      }
+    }
   }
 }
 
