@@ -18,6 +18,7 @@
 //             sphere coefficients, scaled by 1/N_g, plus the kinetic term.
 //   x_density: inverse x-transform of every column of a tile and accumulation
 //             of w_k f |psi|^2 / Omega in registers (fixed order, no atomics).
+#include <algorithm>
 #include <cmath>
 
 #include "devcommon.h"
@@ -889,24 +890,55 @@ __global__ void __launch_bounds__(64) k_x_local_reg(int ncols, int cb, GridGeom 
   }
 }
 
+// work-groups of k_x_local_reg<T, N1, N2> resident on the device at once
+template <typename T, int N1, int N2>
+static int x_local_concurrency() {
+  static const int c = [] {
+    int per = 0, dev = 0, ncu = 0;
+    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_x_local_reg<T, N1, N2>, 64, 0));
+    HIPCK(hipGetDevice(&dev));
+    HIPCK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    return std::max(1, per * ncu);
+  }();
+  return c;
+}
+
+// Columns per work-group.  The work-groups all take about the same time, so
+// they run in rounds of `conc` (the resident ones); among up to 32 column
+// chunks the count whose last round is fullest is taken (the first of equal
+// ones: fewer chunks load V_eff fewer times).  At 90^3 (507 tiles of 16
+// lines) and 128 columns that is 6 chunks of 22 columns, one round of 3042
+// work-groups on 3072 slots.
+static int x_local_columns(int ntiles, int ncols, int conc) {
+  int best = 1;
+  double beff = -1.0;
+  for (int nch = 1; nch <= std::min(ncols, 32); ++nch) {
+    const int64_t items = (int64_t)ntiles * nch;
+    const int64_t rounds = (items + conc - 1) / conc;
+    const double eff = (double)items / (double)(rounds * conc);
+    if (eff > beff + 1e-3) {
+      beff = eff;
+      best = nch;
+    }
+  }
+  return (ncols + best - 1) / best;
+}
+
 template <typename T>
 static bool launch_x_local_reg(hipStream_t st, int ncols, const GridGeom& g, const cplx<T>* twx, const T* V,
                                cplx<T>* Tb) {
   const int np = g.n2 * g.n3;
   if ((int64_t)g.ns * g.ps * (int64_t)sizeof(cplx<T>) >= (int64_t)kBufOob) return false;
   const int ntiles = (np + 15) / 16;
-  // columns per work-group: V is loaded once per work-group; keep >= 2048 work-groups
-  // (8 columns: at 16 the grid of the 90^3 box fills the chip 1.3 times and the
-  // second, partial round of work-groups costs more than the V loads saved)
-  int cb = 8;
-  while (cb > 1 && (int64_t)ntiles * ((ncols + cb - 1) / cb) < 2048) cb /= 2;
-  dim3 grid(ntiles, (ncols + cb - 1) / cb);
   switch (g.n1) {
 #define X(n, a, b)                                                                                           \
-  case n:                                                                                                    \
+  case n: {                                                                                                  \
+    const int cb = x_local_columns(ntiles, ncols, x_local_concurrency<T, a, b>());                           \
+    const dim3 grid(ntiles, (ncols + cb - 1) / cb);                                                          \
     hipLaunchKernelGGL((k_x_local_reg<T, a, b>), grid, dim3(64), 0, st, ncols, cb, g, twx, V, Tb);             \
     HIPCK(hipGetLastError());                                                                                \
-    return true;
+    return true;                                                                                             \
+  }
     EAHP_XREG_SIZES(X)
 #undef X
     default:
