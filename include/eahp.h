@@ -206,6 +206,18 @@ int eahp_transport_qr(eahp_problem* pb, const void* Psi, const void* xi, const v
 int eahp_linesearch(eahp_problem* pb, const void* Psi, const void* eta, double tau0,
                     const eahp_solve_params* prm, double* tau, void* Psi_out, int* trials);
 
+/* The control of Algorithm 2 alone, on the host, for a caller-supplied
+ * f(t) (any smooth function of one variable with f'(0) < 0): fn(t, &f, &df,
+ * user) returns 0 and writes f(t) and f'(t), or returns non-zero to abort
+ * (EAHP_EINVAL).  f0 = f(0), df0 = f'(0).  The same readings as
+ * eahp_linesearch (test, branches, bisection, ls_maxit); only prm->delta,
+ * sigma, gamma, eps and ls_maxit are read.  On success tau is the accepted
+ * step (the last point fn was called at) and trials the number of calls.
+ * No device work. */
+typedef int (*eahp_ls_eval)(double t, double* f, double* df, void* user);
+int eahp_linesearch_host(double f0, double df0, double tau0, const eahp_solve_params* prm, eahp_ls_eval fn,
+                         void* user, double* tau, int* trials);
+
 /* Full EARCG solve (Algorithm 3) from Psi_inout (any full-rank frame: it is
  * orthonormalised by pf first); the minimiser is written back.  Returns
  * EAHP_ENOCONV (with Psi_inout holding the last iterate) at maxit. */
@@ -226,10 +238,16 @@ void eahp_solver_destroy(eahp_solver* sv);
  * every launch of the H-apply kernels: 0 = inverse y/z plane transforms,
  * 1 = x-line transforms with the V_eff product, 2 = forward y/z transforms
  * with the gather and kinetic term, 3 = density x-line transforms; 4, 5, 6 =
- * the single-precision launches of 0, 1, 2 (metric solve of EAHP_MIXED).
- * enable(1) starts recording (and resets), read returns and resets the
- * summed duration, the launch count and the algorithmic bytes (compulsory
- * loads and stores of each launch) since the last read. */
+ * the single-precision launches of 0, 1, 2 (metric solve of EAHP_MIXED);
+ * 7 unused; and around the complex matrix products (MFMA): 8 = A^H B in FP64,
+ * 9 = A M in FP64, 10 = A^H B in FP32, 11 = A M in FP32, each over n >= 1024
+ * rows (Gram matrices, projections, basis updates), 12..15 = the same over
+ * fewer rows (products of the small projected matrices).
+ * enable(1) starts recording (and resets); only one context records the
+ * products at a time (the last one enabled).  read returns and resets the
+ * summed duration, the launch count and, for 0..6, the algorithmic bytes
+ * (compulsory loads and stores of each launch), for 8..15 the flops (8 per
+ * complex multiply-add) since the last read. */
 int eahp_prof_enable(eahp_ctx* ctx, int on);
 int eahp_prof_read(eahp_ctx* ctx, int kernel, double* total_ms, int64_t* launches, double* bytes);
 

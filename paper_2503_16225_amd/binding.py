@@ -78,6 +78,9 @@ class Stats(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+# int (*)(double t, double* f, double* df, void* user) of eahp_linesearch_host
+LS_EVAL = C.CFUNCTYPE(C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
+
 _lib = None
 
 
@@ -115,6 +118,8 @@ def load_library():
         "eahp_retract_qr": ([vp, vp, vp, C.c_double, vp], C.c_int),
         "eahp_transport_qr": ([vp, vp, vp, vp, vp], C.c_int),
         "eahp_linesearch": ([vp, vp, vp, C.c_double, C.POINTER(SolveParams), dp, vp, ip], C.c_int),
+        "eahp_linesearch_host": ([C.c_double, C.c_double, C.c_double, C.POINTER(SolveParams), LS_EVAL, vp, dp, ip],
+                                 C.c_int),
         "eahp_solve": ([vp, vp, C.POINTER(SolveParams), C.POINTER(Stats)], C.c_int),
         "eahp_layout_estimate": ([C.POINTER(SystemDesc), i64p, ip, i64p], C.c_int),
         "eahp_server_create": ([C.c_int, C.c_size_t, C.c_int, C.POINTER(vp)], C.c_int),
@@ -232,6 +237,32 @@ def kpoints_reduce(rot, kfrac, kweight, time_reversal=True):
                                    ko.ctypes.data_as(C.POINTER(C.c_double)), wo.ctypes.data_as(C.POINTER(C.c_double)),
                                    km.ctypes.data_as(C.POINTER(C.c_int)), C.byref(n)))
     return ko.reshape(-1, 3)[:n.value].copy(), wo[:n.value].copy(), km
+
+
+def linesearch_host(evaluate, f0, df0, tau0, params):
+    """The library's Algorithm 2 control on the host for a Python function
+    evaluate(t) -> (f, f'(t)) (host only).  Returns (tau, trials)."""
+    lib = load_library()
+    failed = []
+
+    def cb(t, f, df, user):
+        try:
+            fv, dv = evaluate(t)
+            f[0], df[0] = float(fv), float(dv)
+            return 0
+        except Exception as e:  # reported after the call
+            failed.append(e)
+            return 1
+
+    fn = LS_EVAL(cb)
+    prm = SolveParams.from_dict(params)
+    tau, trials = C.c_double(), C.c_int()
+    rc = lib.eahp_linesearch_host(float(f0), float(df0), float(tau0), C.byref(prm), fn, None, C.byref(tau),
+                                  C.byref(trials))
+    if failed:
+        raise failed[0]
+    _check(rc)
+    return tau.value, trials.value
 
 
 def layout_estimate(sysd):

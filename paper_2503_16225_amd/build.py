@@ -39,6 +39,9 @@ def build(verbose: bool = False) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking failed:\n{r.stderr}")
+    # every symbol must resolve (a reference with the wrong linkage links but fails to load)
+    import ctypes
+    ctypes.CDLL(tmp, mode=os.RTLD_NOW | os.RTLD_LOCAL)
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

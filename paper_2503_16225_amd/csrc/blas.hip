@@ -7,6 +7,7 @@
 //          retraction Psi S^-1, the FOM update V Y, projector expansion P B).
 #include "devcommon.h"
 #include "kernels.h"
+#include "ops.h"
 
 namespace eahp {
 
@@ -25,7 +26,10 @@ void gemm_hn(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t 
              cplx<T>* C, int64_t ldc, double alpha, double beta, DevMem& part, int batch, int64_t sA, int64_t sB,
              int64_t sC) {
   if (a <= 0 || b <= 0 || batch <= 0) return;
+  const int slot = kProfGemm + (sizeof(T) == 4 ? 2 : 0) + (n < 1024 ? 4 : 0);
+  gemm_prof_begin(st, slot);
   gemm_hn_mfma<T>(st, n, a, b, A, lda, B, ldb, C, ldc, alpha, beta, part, batch, sA, sB, sC);
+  gemm_prof_end(st, slot, 8.0 * (double)n * a * b * batch);
 }
 
 template <typename T>
@@ -33,7 +37,10 @@ void gemm_nn(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t 
              int opM, cplx<T>* C, int64_t ldc, double alpha_re, double alpha_im, double beta, int batch, int64_t sA,
              int64_t sM, int64_t sC) {
   if (n <= 0 || b <= 0 || batch <= 0) return;
+  const int slot = kProfGemm + 1 + (sizeof(T) == 4 ? 2 : 0) + (n < 1024 ? 4 : 0);
+  gemm_prof_begin(st, slot);
   gemm_nn_mfma<T>(st, n, a, b, A, lda, M, ldm, opM, C, ldc, alpha_re, alpha_im, beta, batch, sA, sM, sC);
+  gemm_prof_end(st, slot, 8.0 * (double)n * a * b * batch);
 }
 
 template void gemm_hn<double>(hipStream_t, int64_t, int, int, const z64*, int64_t, const z64*, int64_t, z64*, int64_t,

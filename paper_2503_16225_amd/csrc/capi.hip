@@ -2,6 +2,7 @@
 // (Algorithm 3).  Control flow runs on the host; every vector, matrix and
 // reduction operation is a device kernel; only scalars (energies, pairings,
 // norms, ranks) cross to the host.
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -63,87 +64,83 @@ void eval_trial(eahp_problem* pb, const z64* Phi, const z64* eta, double t, Tria
   if (!std::isfinite(tr.df)) fail(EAHP_ENONFINITE, "non-finite slope in the line search");
 }
 
-// Modified secant step (Algorithm 2) with the readings documented with the
-// oracle's line search: approximate Wolfe test f <= f0 + eps|f0| and
-// |f'| <= min(sigma, 1 - 2 delta)|f'(0)|; bisection on equal slopes; a secant
-// point left of a enlarges the bracket without an evaluation; a kept bracket
-// whose right end has energy above f0 is bisected next.  The accepted point is
-// always the last evaluated one, left in tr.
-double secant_step(eahp_problem* pb, const z64* Phi, const z64* eta, double f0, double df0, double tau0,
-                   const eahp_solve_params& prm, Trial& tr, int* trials_out) {
+// Modified secant step (Algorithm 2), in the printed order: the secant point
+// of f' on [a, b] is evaluated, then (1) too high with f' < 0: tau = gamma b,
+// [0, tau]; (2) left of a: tau = b / gamma, [0, tau]; (3) right of b: [b, tau];
+// (4) inside: the half where f' changes sign.  Readings: approximate Wolfe
+// test f <= f0 + eps|f0| and |f'| <= min(sigma, 1 - 2 delta)|f'(0)|; equal
+// slopes take the midpoint; a kept bracket [a, tau] whose new right end has
+// energy above the bound is bisected on the next trial.  ev(t, f, df)
+// evaluates f and f' at t; the accepted point is always the last evaluated
+// one.  Throws EAHP_ELINESEARCH after ls_maxit evaluations.
+template <typename Eval>
+double secant_core(Eval&& evf, double f0, double df0, double tau0, const eahp_solve_params& prm, int* trials_out) {
   const double c = std::min(prm.sigma, 1.0 - 2.0 * prm.delta);
   const double fbound = f0 + prm.eps * std::fabs(f0);
   int trials = 0;
+  double ft = 0, dft = 0;
   auto ev = [&](double t) {
     if (trials >= prm.ls_maxit) fail(EAHP_ELINESEARCH, "line search: no acceptable step");
     ++trials;
-    eval_trial(pb, Phi, eta, t, tr, prm.retraction);
+    evf(t, ft, dft);
+    if (!std::isfinite(ft) || !std::isfinite(dft)) fail(EAHP_ENONFINITE, "non-finite value in the line search");
   };
   auto ok = [&](double f, double df) { return f <= fbound && std::fabs(df) <= c * std::fabs(df0); };
-  if (prm.retraction != EAHP_QR) line_prepare(pb, Phi, eta, pb->arena->line);
   double a = 0.0, dfa = df0;
   double b = tau0;
   ev(b);
-  double dfb = tr.df;
-  double tau = b, ft = tr.sc.E, dft = tr.df;
+  double dfb = dft;
+  double tau = b;
   bool bisect = false;
   while (!ok(ft, dft)) {
     const double den = dfb - dfa;
-    double tn;
-    if (bisect) {
-      tn = 0.5 * (a + b);
-      bisect = false;
-    } else if (den != 0.0 && std::isfinite(den)) {
-      tn = (a * dfb - b * dfa) / den;
-    } else {
-      tn = 0.5 * (a + b);
-    }
-    if (tn < a) {
-      tau = b / prm.gamma;
-      a = 0.0;
-      dfa = df0;
-      b = tau;
-      ev(b);
-      dfb = tr.df;
-      ft = tr.sc.E;
-      dft = tr.df;
-      continue;
-    }
-    ev(tn);
-    const double fn = tr.sc.E, dfn = tr.df;
-    if (fn > fbound && dfn < 0.0) {
+    if (bisect) tau = 0.5 * (a + b);
+    else if (den != 0.0 && std::isfinite(den)) tau = (a * dfb - b * dfa) / den;
+    else tau = 0.5 * (a + b);
+    bisect = false;
+    ev(tau);
+    if (ft > fbound && dft < 0.0) {
       tau = prm.gamma * b;
       a = 0.0;
       dfa = df0;
       b = tau;
       ev(b);
-      dfb = tr.df;
-      ft = tr.sc.E;
-      dft = tr.df;
-    } else if (tn > b) {
+      dfb = dft;
+    } else if (tau < a) {
+      tau = b / prm.gamma;
+      a = 0.0;
+      dfa = df0;
+      b = tau;
+      ev(b);
+      dfb = dft;
+    } else if (tau > b) {
       a = b;
       dfa = dfb;
-      b = tn;
-      dfb = dfn;
-      tau = tn;
-      ft = fn;
-      dft = dfn;
+      b = tau;
+      dfb = dft;
+    } else if (dft >= 0.0) {
+      b = tau;
+      dfb = dft;
+      bisect = ft > fbound;
     } else {
-      tau = tn;
-      ft = fn;
-      dft = dfn;
-      if (dfn >= 0.0) {
-        b = tn;
-        dfb = dfn;
-        bisect = fn > fbound;
-      } else {
-        a = tn;
-        dfa = dfn;
-      }
+      a = tau;
+      dfa = dft;
     }
   }
   if (trials_out) *trials_out = trials;
   return tau;
+}
+
+double secant_step(eahp_problem* pb, const z64* Phi, const z64* eta, double f0, double df0, double tau0,
+                   const eahp_solve_params& prm, Trial& tr, int* trials_out) {
+  if (prm.retraction != EAHP_QR) line_prepare(pb, Phi, eta, pb->arena->line);
+  return secant_core(
+      [&](double t, double& f, double& df) {
+        eval_trial(pb, Phi, eta, t, tr, prm.retraction);
+        f = tr.sc.E;
+        df = tr.df;
+      },
+      f0, df0, tau0, prm, trials_out);
 }
 
 }  // namespace
@@ -754,6 +751,21 @@ int eahp_linesearch(eahp_problem* pb, const void* Psi, const void* eta, double t
   });
 }
 
+int eahp_linesearch_host(double f0, double df0, double tau0, const eahp_solve_params* prm, eahp_ls_eval fn,
+                         void* user, double* tau, int* trials) {
+  return guarded([&] {
+    if (!prm || !fn || !tau) fail(EAHP_EINVAL, "null argument");
+    if (!(df0 < 0)) fail(EAHP_ENODESCENT, "f'(0) is not negative");
+    if (!(tau0 > 0) || !(prm->gamma > 0 && prm->gamma < 1) || prm->ls_maxit <= 0)
+      fail(EAHP_EINVAL, "bad line-search parameters");
+    *tau = secant_core(
+        [&](double t, double& f, double& df) {
+          if (fn(t, &f, &df, user) != 0) fail(EAHP_EINVAL, "evaluation callback failed");
+        },
+        f0, df0, tau0, *prm, trials);
+  });
+}
+
 int eahp_solver_create(eahp_problem* pb, const void* Psi0, const eahp_solve_params* prmp, eahp_solver** out) {
   eahp_solver* sv = nullptr;
   const int rc = guarded([&] {
@@ -830,6 +842,11 @@ int eahp_prof_enable(eahp_ctx* ctx, int on) {
     if (!ctx) fail(EAHP_EINVAL, "null context");
     HIPCK(hipStreamSynchronize(ctx->stream));
     ctx->prof = on != 0;
+    if (on) g_prof_ctx.store(ctx);
+    else {
+      eahp_ctx* expect = ctx;
+      g_prof_ctx.compare_exchange_strong(expect, nullptr);
+    }
     for (auto& s : ctx->slot) {
       s.used = 0;
       s.bytes = 0;

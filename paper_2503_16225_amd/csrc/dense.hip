@@ -10,8 +10,16 @@
 // pchol_inv : diagonally pivoted Cholesky of a Gram matrix with rank cut-off,
 //             returning the inverse factor with the pivot permutation folded in
 //             (the rank-revealing orthonormalisation of Algorithm 4).
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
 #include "devcommon.h"
 #include "kernels.h"
+
+namespace cg = cooperative_groups;
 
 namespace eahp {
 
@@ -155,19 +163,31 @@ __global__ void __launch_bounds__(1024) k_heev(int n, z64* Ab, int64_t lda, int6
 
 bool heev_dc(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
              int64_t sV, int batch, DevMem& scr);
+bool heev_big(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V,
+              int64_t ldv, int64_t sV, int batch, DevMem& scr);
 bool pchol_inv_reg(hipStream_t st, int n, const z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* U,
                    int64_t ldu, DevMem& scr, bool pivot);
+bool pchol_inv_big(hipStream_t st, int n, z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* U, int64_t ldu,
+                   DevMem& scr, bool pivot);
 
 void heev(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
           int64_t sV, int batch, int* info, DevMem& scr) {
   if (n <= 0 || batch <= 0) return;
   if (heev_dc(st, n, A, lda, sA, w, sw, V, ldv, sV, batch, scr)) return;
+  if (heev_big(st, n, A, lda, sA, w, sw, V, ldv, sV, batch, scr)) return;
+  // beyond the divide-and-conquer sizes: cyclic Jacobi, whose sweep limit is
+  // checked here (a synchronisation on this rare path)
   const int np = n + (n & 1), half = np / 2;
   const size_t lds = (size_t)half * (2 * sizeof(int) + 2 * sizeof(double) + sizeof(z64)) + 32 * sizeof(double) + 64;
   const int nt = n <= 32 ? 256 : 1024;
   HIPCK(hipFuncSetAttribute((const void*)k_heev, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_heev, dim3(batch), dim3(nt), lds, st, n, A, lda, sA, w, sw, V, ldv, sV, info);
   HIPCK(hipGetLastError());
+  std::vector<int> h(batch, 0);
+  HIPCK(hipMemcpyAsync(h.data(), info, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  for (int b = 0; b < batch; ++b)
+    if (h[b] != 0) fail(EAHP_ENOCONV, "Jacobi eigensolver did not converge in 40 sweeps");
 }
 
 // ------------------------------------------------------------------ Gauss-Jordan inverse
@@ -350,12 +370,113 @@ __global__ void __launch_bounds__(1024) k_inverse_reg(int n, z64* Ab, int64_t ld
   if (t == 0 && info) info[blockIdx.x] = bad;
 }
 
+// Gauss-Jordan on [A | I] (n x 2n, column-major in W) with partial pivoting
+// for n > 128: the columns are spread over the work-groups of a cooperative
+// grid (column c to group c mod G), one grid barrier per step.  In step k
+// every group reads column k (nobody writes it in step k: once its pivot is
+// chosen, left column k is never read again), chooses the same pivot row
+// (largest modulus among the rows not yet pivots, ties to the smallest index)
+// and eliminates column k from its own columns j > k.  Row p_k of the right
+// half then holds row k of A^-1.
+__global__ void __launch_bounds__(256) k_inverse_coop(int n, z64* A, int64_t lda, z64* W, int* info) {
+  extern __shared__ unsigned char smem_raw[];
+  z64* colk = reinterpret_cast<z64*>(smem_raw);  // n
+  int* used = reinterpret_cast<int*>(colk + n);   // n
+  int* prow = used + n;                           // n
+  z64* prv = reinterpret_cast<z64*>(prow + n + (n & 1));  // own columns
+  __shared__ double cv[4];
+  __shared__ int ci[4];
+  cg::grid_group grid = cg::this_grid();
+  const int G = gridDim.x, g = blockIdx.x, t = threadIdx.x, nt = blockDim.x, lane = t & 63, wv = t >> 6;
+  const int m = 2 * n;
+  for (int j = g; j < m; j += G)
+    for (int i = t; i < n; i += nt)
+      W[i + (int64_t)j * n] = j < n ? A[i + (int64_t)j * lda] : mk<double>(i == j - n ? 1.0 : 0.0, 0.0);
+  for (int i = t; i < n; i += nt) used[i] = 0;
+  int bad = 0;
+  grid.sync();
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int br = 1 << 20;
+    for (int i = t; i < n; i += nt) {
+      const z64 v = W[i + (int64_t)k * n];
+      colk[i] = v;
+      const double a = v.x * v.x + v.y * v.y;
+      if (!used[i] && a > best) {
+        best = a;
+        br = i;
+      }
+    }
+    wave_argmax(best, br);
+    if (lane == 0) {
+      cv[wv] = best;
+      ci[wv] = br;
+    }
+    __syncthreads();
+    best = cv[0];
+    br = ci[0];
+    for (int w = 1; w < (nt >> 6); ++w) argmax_merge(best, br, cv[w], ci[w]);
+    const int p = br;
+    const z64 pz = colk[p];
+    const double den = pz.x * pz.x + pz.y * pz.y;
+    if (!(den > 0)) bad = 1;
+    const z64 pinv = den > 0 ? mk<double>(pz.x / den, -pz.y / den) : mk<double>(0.0, 0.0);
+    // scaled pivot-row entries of the own columns j > k
+    const int j0 = k + 1 + ((g - (k + 1)) % G + G) % G;
+    for (int j = j0 + t * G; j < m; j += nt * G) prv[(j - j0) / G] = cmul<double>(W[p + (int64_t)j * n], pinv);
+    __syncthreads();
+    const int nown = j0 < m ? (m - j0 + G - 1) / G : 0;
+    for (int i = t; i < n; i += nt) {
+      const z64 f = colk[i];
+      for (int c = 0; c < nown; ++c) {
+        z64* wc = W + (int64_t)(j0 + c * G) * n;
+        const z64 pr = prv[c];
+        if (i == p) wc[i] = pr;
+        else wc[i] = csub<double>(wc[i], cmul<double>(f, pr));
+      }
+    }
+    if (t == 0) {
+      used[p] = 1;
+      prow[k] = p;
+    }
+    grid.sync();
+  }
+  // A^-1[k][j] = W[p_k][n + j] for the own right-half columns
+  for (int j = g; j < n; j += G)
+    for (int k = t; k < n; k += nt) A[k + (int64_t)j * lda] = W[prow[k] + (int64_t)(n + j) * n];
+  if (g == 0 && t == 0 && info) info[0] = bad;
+}
+
 void inverse(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, z64* work, int batch, int* info) {
   if (n <= 0 || batch <= 0) return;
   if (n > 1024) fail(EAHP_EINVAL, "inverse: n > 1024");
-  if (n <= 128) hipLaunchKernelGGL(k_inverse_reg, dim3(batch), dim3(1024), 0, st, n, A, lda, sA, info);
-  else hipLaunchKernelGGL(k_inverse, dim3(batch), dim3(1024), 0, st, n, A, lda, sA, work, info);
-  HIPCK(hipGetLastError());
+  if (n <= 128) {
+    hipLaunchKernelGGL(k_inverse_reg, dim3(batch), dim3(1024), 0, st, n, A, lda, sA, info);
+    HIPCK(hipGetLastError());
+    return;
+  }
+  int dev = 0, ncu = 0;
+  HIPCK(hipGetDevice(&dev));
+  HIPCK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  // about 8 columns of [A | I] per work-group, at most one work-group per CU
+  const int G = std::max(1, std::min(ncu, (2 * n + 7) / 8));
+  const int own = (2 * n + G - 1) / G + 1;
+  const size_t lds = sizeof(z64) * n + sizeof(int) * (2 * n + 2) + sizeof(z64) * own + 64;
+  HIPCK(hipFuncSetAttribute((const void*)k_inverse_coop, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int per_cu = 0;
+  HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_inverse_coop, 256, lds));
+  if (per_cu < 1) fail(EAHP_EDEVICE, "the inverse cannot be made resident");
+  std::lock_guard<std::mutex> lk(coop_mutex());
+  for (int b = 0; b < batch; ++b) {
+    int nn = n;
+    z64* Ab = A + b * sA;
+    int64_t la = lda;
+    z64* Wb = work + (int64_t)b * 2 * n * n;
+    int* ib = info ? info + b : nullptr;
+    void* args[] = {&nn, &Ab, &la, &Wb, &ib};
+    HIPCK(hipLaunchCooperativeKernel((const void*)k_inverse_coop, dim3(G), dim3(256), args, lds, st));
+  }
+  HIPCK(hipStreamSynchronize(st));
 }
 
 // ------------------------------------------------------------------ pivoted Cholesky
@@ -479,6 +600,7 @@ void pchol_inv(hipStream_t st, int n, z64* G, int64_t ldg, double tol, int* piv,
                int* info, DevMem& scr, bool pivot) {
   if (n <= 0) return;
   if (pchol_inv_reg(st, n, G, ldg, tol, piv, rank, Uinv, ldu, scr, pivot)) return;
+  if (pchol_inv_big(st, n, G, ldg, tol, piv, rank, Uinv, ldu, scr, pivot)) return;
   const size_t lds = (size_t)n * sizeof(int) + 64;
   HIPCK(hipFuncSetAttribute((const void*)k_pchol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_pchol, dim3(1), dim3(n <= 64 ? 256 : 1024), lds, st, n, G, ldg, tol, piv, rank, Uinv, ldu,

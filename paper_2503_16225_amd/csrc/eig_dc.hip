@@ -666,16 +666,493 @@ __global__ void __launch_bounds__(1024) k_heev_dc(int n, const z64* __restrict__
 
 size_t heev_dc_scratch(int n) { return sizeof(z64) * ((size_t)n * n + n) + 256; }
 
+static void heev_dc_raw(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V,
+                        int64_t ldv, int64_t sV, int batch, double* scr) {
+  const int64_t per = (int64_t)((heev_dc_scratch(n) + 255) / 256 * 256 / sizeof(double));
+  const size_t lds = sizeof(double) * ((size_t)kDcMax * kDcMax + 18 * kDcMax) + sizeof(int) * 10 * kDcMax;
+  HIPCK(hipFuncSetAttribute((const void*)k_heev_dc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_heev_dc, dim3(batch), dim3(1024), lds, st, n, A, lda, sA, w, sw, V, ldv, sV, scr, per);
+  HIPCK(hipGetLastError());
+}
+
 bool heev_dc(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
              int64_t sV, int batch, DevMem& scr) {
   if (n < 1 || n > kDcMax) return false;
   const int64_t per = (int64_t)((heev_dc_scratch(n) + 255) / 256 * 256 / sizeof(double));
   scr.ensure(sizeof(double) * per * batch);
-  const size_t lds = sizeof(double) * ((size_t)kDcMax * kDcMax + 18 * kDcMax) + sizeof(int) * 10 * kDcMax;
-  HIPCK(hipFuncSetAttribute((const void*)k_heev_dc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_heev_dc, dim3(batch), dim3(1024), lds, st, n, A, lda, sA, w, sw, V, ldv, sV,
-                     scr.as<double>(), per);
-  HIPCK(hipGetLastError());
+  heev_dc_raw(st, n, A, lda, sA, w, sw, V, ldv, sV, batch, scr.as<double>());
+  return true;
+}
+
+// ===========================================================================
+// Hermitian eigendecomposition for kDcMax < n <= kDcBig, one matrix at a time:
+//
+//  1. A = Q T Q^H by tridiag_reduce (Householder reflectors, several
+//     work-groups); T Hermitian tridiagonal with T[k+1][k] = e_k.
+//  2. Phases P_0 = 1, P_{k+1} = P_k e_k / |e_k|, so that P^H T P = R is real
+//     symmetric tridiagonal with R[k+1][k] = |e_k| >= 0.
+//  3. R is padded to N' = L mL (L a power of two, mL <= kDcMax) with
+//     decoupled diagonal entries above its spectrum, torn at the L - 1 leaf
+//     boundaries (Cuppen: the coupling |e| is subtracted from the two
+//     diagonal entries beside a boundary and restored as a rank-one term),
+//     and the L leaves are solved by k_heev_dc in one batched launch.
+//  4. log2 L levels of merges, every merge of two blocks on the device in
+//     global memory: the eigenvalues of diag(D1, D2) + rho z z^T with the
+//     deflation rules of k_heev_dc, the roots of the secular equation, the
+//     Gu-Eisenstat eigenvector matrix U (K x K, from the Loewner weights,
+//     columns normalised) and the block's eigenvector columns times U (an FP64
+//     product), into a second buffer (the blocks of a level cover it).
+//  5. V = Q P Z, with Z the leading n x n part of the eigenvector matrix of
+//     the padded R (the pad entries are exactly decoupled, so their
+//     eigenvalues come last and Z vanishes in the pad rows).
+// ===========================================================================
+constexpr int kDcBig = 2048;
+
+namespace {
+
+struct DcBig {
+  int n, N, L, mL;
+  double *Rd, *Rb, *D, *dl, *zz, *tv, *nrm, *zh, *cn, *rc, *rs, *tau;
+  int *srt, *nd, *dfl, *ra, *rb, *org, *outk, *src, *Km, *nrot, *ndf;
+};
+
+__global__ void k_dc_phase(int n, int N, const double* __restrict__ dd, const z64* __restrict__ e, z64* Ph,
+                           double* Rd, double* Rb) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  z64 P = mk<double>(1.0, 0.0);
+  double dmax = 0.0, bmax = 0.0;
+  for (int k = 0; k < n; ++k) {
+    Ph[k] = P;
+    Rd[k] = dd[k];
+    dmax = fmax(dmax, fabs(dd[k]));
+    if (k + 1 < n) {
+      const z64 ek = e[k];
+      const double a = sqrt(ek.x * ek.x + ek.y * ek.y);
+      Rb[k] = a;
+      bmax = fmax(bmax, a);
+      if (a > 0.0) P = cmulz(P, mk<double>(ek.x / a, ek.y / a));
+    }
+  }
+  // pads: decoupled, distinct and above every eigenvalue (Gershgorin)
+  const double big = 2.0 * (dmax + 2.0 * bmax) + 1.0;
+  for (int k = n; k < N; ++k) Rd[k] = big * (1.0 + (double)(k - n + 1) / (double)N);
+  for (int k = n - 1; k < N - 1; ++k) Rb[k] = 0.0;
+}
+
+// leaf matrices (dense complex mL x mL, consecutive) with the tearing corrections
+__global__ void k_dc_leaves(int N, int L, int mL, const double* __restrict__ Rd, const double* __restrict__ Rb,
+                            z64* Al) {
+  const int64_t tot = (int64_t)L * mL * mL;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < tot; x += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(x / ((int64_t)mL * mL));
+    const int rem = (int)(x % ((int64_t)mL * mL));
+    const int r = rem % mL, c = rem / mL;
+    const int s = i * mL;
+    double v = 0.0;
+    if (r == c) {
+      v = Rd[s + r];
+      if (r == 0 && i > 0) v -= Rb[s - 1];
+      if (r == mL - 1 && i < L - 1) v -= Rb[s + mL - 1];
+    } else if (r == c + 1 || c == r + 1) {
+      v = Rb[s + min(r, c)];
+    }
+    Al[x] = mk<double>(v, 0.0);
+  }
+}
+
+// block-diagonal eigenvector matrix of the leaves into Qa (N x N); Qb zeroed
+__global__ void k_dc_init(int N, int mL, const double* __restrict__ wl, const z64* __restrict__ Vl, double* Qa,
+                          double* Qb, double* D) {
+  const int64_t tot = (int64_t)N * N;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < tot; x += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(x % N), c = (int)(x / N);
+    const int i = r / mL;
+    double v = 0.0;
+    if (c / mL == i) v = Vl[(int64_t)i * mL * mL + (r - i * mL) + (int64_t)(c - i * mL) * mL].x;
+    Qa[x] = v;
+    Qb[x] = 0.0;
+    if (r == 0) D[c] = wl[c];
+  }
+}
+
+// merge step A (one work-group per merge of two blocks of size sz): the
+// sorted poles and the rank-one vector z, deflation (one thread), the
+// deflation rotations on the block's columns, the non-deflated poles
+__global__ void __launch_bounds__(1024) k_dc_merge_a(DcBig S, int sz, double* Q) {
+  const int N = S.N, m = 2 * sz, j = blockIdx.x, s = j * m, n1 = sz, n2 = sz, t = threadIdx.x;
+  const double rho = 2.0 * S.Rb[s + n1 - 1];
+  for (int g = t; g < m; g += blockDim.x) {
+    const int jj = g;
+    const double x = S.D[s + g];
+    int lo = 0, cnt;
+    if (jj < n1) {  // entries of the right half strictly below x
+      cnt = n2;
+      while (cnt > 0) {
+        const int h = cnt >> 1;
+        if (S.D[s + n1 + lo + h] < x) {
+          lo += h + 1;
+          cnt -= h + 1;
+        } else {
+          cnt = h;
+        }
+      }
+    } else {  // entries of the left half at or below x
+      cnt = n1;
+      while (cnt > 0) {
+        const int h = cnt >> 1;
+        if (S.D[s + lo + h] <= x) {
+          lo += h + 1;
+          cnt -= h + 1;
+        } else {
+          cnt = h;
+        }
+      }
+    }
+    const int q = (jj < n1 ? jj : jj - n1) + lo;
+    S.srt[s + q] = jj;
+    S.dl[s + q] = x;
+    const int64_t col = (int64_t)(s + jj) * N;
+    S.zz[s + q] = (jj < n1 ? Q[(s + n1 - 1) + col] : Q[(s + n1) + col]) * 0.7071067811865476;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double dmax = 0.0, zmax = 0.0;
+    for (int q = 0; q < m; ++q) {
+      dmax = fmax(dmax, fabs(S.dl[s + q]));
+      zmax = fmax(zmax, fabs(S.zz[s + q]));
+    }
+    const double tol = 8.0 * kEps * fmax(dmax, rho * zmax);
+    int K = 0, nd = 0, nr = 0, pj = -1;
+    for (int jj = 0; jj < m; ++jj) {
+      if (rho * fabs(S.zz[s + jj]) <= tol) {
+        S.dfl[s + nd++] = jj;
+        continue;
+      }
+      if (pj < 0) {
+        pj = jj;
+        continue;
+      }
+      const double zs = S.zz[s + pj], zc = S.zz[s + jj];
+      const double tau = hypot(zc, zs);
+      const double c = zc / tau, sn = -zs / tau;
+      const double tt = S.dl[s + jj] - S.dl[s + pj];
+      if (fabs(tt * c * sn) <= tol) {
+        S.zz[s + jj] = tau;
+        S.zz[s + pj] = 0.0;
+        S.ra[s + nr] = S.srt[s + pj];
+        S.rb[s + nr] = S.srt[s + jj];
+        S.rc[s + nr] = c;
+        S.rs[s + nr] = sn;
+        ++nr;
+        const double dp = S.dl[s + pj], dj = S.dl[s + jj];
+        S.dl[s + pj] = c * c * dp + sn * sn * dj;
+        S.dl[s + jj] = sn * sn * dp + c * c * dj;
+        S.dfl[s + nd++] = pj;
+        pj = jj;
+      } else {
+        S.nd[s + K++] = pj;
+        pj = jj;
+      }
+    }
+    if (pj >= 0) S.nd[s + K++] = pj;
+    S.Km[j] = K;
+    S.nrot[j] = nr;
+    S.ndf[j] = nd;
+  }
+  __syncthreads();
+  const int nr = S.nrot[j], K = S.Km[j];
+  for (int R = t; R < m; R += blockDim.x) {
+    for (int q = 0; q < nr; ++q) {
+      const int64_t ca = (int64_t)(s + S.ra[s + q]) * N, cb = (int64_t)(s + S.rb[s + q]) * N;
+      const double c = S.rc[s + q], sn = S.rs[s + q];
+      const double qa = Q[s + R + ca], qb = Q[s + R + cb];
+      Q[s + R + ca] = c * qa + sn * qb;
+      Q[s + R + cb] = -sn * qa + c * qb;
+    }
+  }
+  for (int i = t; i < K; i += blockDim.x) {
+    S.tv[s + i] = S.dl[s + S.nd[s + i]];
+    S.nrm[s + i] = S.zz[s + S.nd[s + i]];
+  }
+}
+
+// secular roots, 8 lanes per root, 128 roots per work-group
+__global__ void __launch_bounds__(1024) k_dc_secular(DcBig S, int sz, int chunks) {
+  const int m = 2 * sz, j = blockIdx.x / chunks, s = j * m;
+  const int i = (blockIdx.x % chunks) * 128 + (threadIdx.x >> 3), lane8 = threadIdx.x & 7;
+  const int K = S.Km[j];
+  if (i >= K) return;
+  const double rho = 2.0 * S.Rb[s + sz - 1];
+  int o;
+  const double tau = secular_root(S.tv + s, S.nrm + s, K, rho, i, lane8, o);
+  if (lane8 == 0) {
+    S.org[s + i] = o;
+    S.tau[s + i] = tau;
+  }
+}
+
+// merge step B (one work-group per merge): Loewner weights, column norms of U,
+// output order; then U (K x K, scaled columns) and the gathered source columns
+// Qg (m x K) for the product
+__global__ void __launch_bounds__(1024) k_dc_merge_b(DcBig S, int sz, const double* Q, double* Ub, double* Qgb) {
+  const int N = S.N, m = 2 * sz, j = blockIdx.x, s = j * m, t = threadIdx.x;
+  const int K = S.Km[j], nd = S.ndf[j];
+  const double* dK = S.tv + s;
+  for (int i = t; i < K; i += blockDim.x) {
+    const double di = dK[i];
+    double wv = (di - dK[S.org[s + i]]) - S.tau[s + i];
+    for (int k = 0; k < K; ++k)
+      if (k != i) wv *= ((di - dK[S.org[s + k]]) - S.tau[s + k]) / (di - dK[k]);
+    S.zh[s + i] = copysign(sqrt(fmax(-wv, 0.0)), S.nrm[s + i]);
+    S.src[s + i] = s + S.srt[s + S.nd[s + i]];
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += 128) {
+    const int k = k0 + (t >> 3), lane8 = t & 7;
+    double acc = 0.0;
+    if (k < K) {
+      const double lo = dK[S.org[s + k]], tk = S.tau[s + k];
+      for (int i = lane8; i < K; i += 8) {
+        const double u = S.zh[s + i] / ((dK[i] - lo) - tk);
+        acc += u * u;
+      }
+    }
+    acc += dpp_f64<0xB1>(acc);
+    acc += dpp_f64<0x4E>(acc);
+    acc += dpp_f64<0x141>(acc);
+    if (k < K && lane8 == 0) S.cn[s + k] = 1.0 / sqrt(acc);
+  }
+  if (t == 0) {
+    // insertion sort of the deflated values (ascending, stable)
+    for (int a2 = 1; a2 < nd; ++a2) {
+      const int v = S.dfl[s + a2];
+      const double key = S.dl[s + v];
+      int b2 = a2 - 1;
+      while (b2 >= 0 && S.dl[s + S.dfl[s + b2]] > key) {
+        S.dfl[s + b2 + 1] = S.dfl[s + b2];
+        --b2;
+      }
+      S.dfl[s + b2 + 1] = v;
+    }
+    // outk[q] >= 0: root outk[q]; otherwise the column -outk[q] - 1 (deflated)
+    int ia = 0, ib = 0;
+    for (int q = 0; q < m; ++q) {
+      const double lr = ia < K ? dK[S.org[s + ia]] + S.tau[s + ia] : 0.0;
+      const double ld = ib < nd ? S.dl[s + S.dfl[s + ib]] : 0.0;
+      if (ib >= nd || (ia < K && lr <= ld)) {
+        S.outk[s + q] = ia;
+        S.D[s + q] = lr;
+        ++ia;
+      } else {
+        S.outk[s + q] = -(s + S.srt[s + S.dfl[s + ib]] + 1);
+        S.D[s + q] = ld;
+        ++ib;
+      }
+    }
+  }
+  __syncthreads();
+  double* U = Ub + (int64_t)j * m * m;
+  double* Qg = Qgb + (int64_t)j * m * m;
+  for (int64_t x = t; x < (int64_t)K * K; x += blockDim.x) {
+    const int i = (int)(x % K), k = (int)(x / K);
+    U[x] = S.zh[s + i] / ((dK[i] - dK[S.org[s + k]]) - S.tau[s + k]) * S.cn[s + k];
+  }
+  for (int64_t x = t; x < (int64_t)m * K; x += blockDim.x) {
+    const int r = (int)(x % m), i = (int)(x / m);
+    Qg[x] = Q[(s + r) + (int64_t)S.src[s + i] * N];
+  }
+}
+
+// C (m x K, ld m) = A (m x K, ld m) B (K x K, ld K) for every merge (blockIdx.z),
+// K = Km[merge]; 64 x 64 tiles, 256 threads with 4 x 4 results each
+__global__ void __launch_bounds__(256) k_dc_gemm(int m, const int* __restrict__ Km, const double* __restrict__ Ab,
+                                                 const double* __restrict__ Bb, double* Cb) {
+  const int j = blockIdx.z;
+  const int K = Km[j];
+  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  if (c0 >= K || r0 >= m) return;
+  const int64_t stride = (int64_t)m * m;
+  const double* A = Ab + j * stride;
+  const double* B = Bb + j * stride;
+  double* C = Cb + j * stride;
+  __shared__ double As[16][65], Bs[16][65];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      const int rr = e & 63, kk = e >> 6, r = r0 + rr, k = k0 + kk;
+      As[kk][rr] = (r < m && k < K) ? A[r + (int64_t)k * m] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      const int kk = e & 15, cc = e >> 4, k = k0 + kk, c = c0 + cc;
+      Bs[kk][cc] = (k < K && c < K) ? B[k + (int64_t)c * K] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = As[kk][tx + 16 * u];
+        b[u] = Bs[kk][ty + 16 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + tx + 16 * u, c = c0 + ty + 16 * v;
+      if (r < m && c < K) C[r + (int64_t)c * m] = acc[u][v];
+    }
+}
+
+// merged block columns into the other buffer: roots from the product, the
+// deflated columns moved; grid (m columns, merges)
+__global__ void __launch_bounds__(256) k_dc_scatter(DcBig S, int sz, const double* Qold, const double* Qob,
+                                                    double* Qnew) {
+  const int N = S.N, m = 2 * sz, j = blockIdx.y, s = j * m, q = blockIdx.x;
+  const int o = S.outk[s + q];
+  double* dst = Qnew + (int64_t)(s + q) * N + s;
+  if (o >= 0) {
+    const double* src = Qob + (int64_t)j * m * m + (int64_t)o * m;
+    for (int r = threadIdx.x; r < m; r += blockDim.x) dst[r] = src[r];
+  } else {
+    const double* src = Qold + (int64_t)(-o - 1) * N + s;
+    for (int r = threadIdx.x; r < m; r += blockDim.x) dst[r] = src[r];
+  }
+}
+
+// V = P Z (n x n leading part), w = eigenvalues
+__global__ void k_dc_output(int n, int N, const double* __restrict__ Q, const double* __restrict__ D,
+                            const z64* __restrict__ Ph, z64* V, int64_t ldv, double* w) {
+  const int64_t tot = (int64_t)n * n;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < tot; x += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(x % n), c = (int)(x / n);
+    const z64 P = Ph[r];
+    const double z = Q[r + (int64_t)c * N];
+    V[r + (int64_t)c * ldv] = mk<double>(P.x * z, P.y * z);
+    if (r == 0) w[c] = D[c];
+  }
+}
+
+template <typename T> T* carve(char*& p, size_t count) {
+  T* r = reinterpret_cast<T*>(p);
+  p += (sizeof(T) * count + 255) / 256 * 256;
+  return r;
+}
+
+}  // namespace
+
+bool heev_big(hipStream_t st, int n, const z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V,
+              int64_t ldv, int64_t sV, int batch, DevMem& scr) {
+  if (n <= kDcMax || n > kDcBig) return false;
+  int L = 1;
+  while ((n + L - 1) / L > kDcMax) L *= 2;
+  const int mL = (n + L - 1) / L, N = L * mL;
+  // scratch: the Householder stage, the leaves, two N x N eigenvector
+  // buffers, the per-merge U, Qg and the product (N^2 each), the per-index
+  // arrays; laid out once from offset 0 to size it
+  const size_t nn = (size_t)n * n, NN = (size_t)N * N;
+  const int64_t per = (int64_t)((heev_dc_scratch(mL) + 255) / 256 * 256 / sizeof(double));
+  z64 *Ah, *Vh, *e, *Ph, *Al, *Vl;
+  double *dd, *bt, *wl, *lscr, *Qa, *Qb, *Ub, *Qg, *Qo;
+  char* tscr;
+  DcBig S;
+  auto layout = [&](char* p) {
+    Ah = carve<z64>(p, nn);
+    Vh = carve<z64>(p, nn);
+    e = carve<z64>(p, n);
+    Ph = carve<z64>(p, n);
+    dd = carve<double>(p, n);
+    bt = carve<double>(p, n);
+    tscr = carve<char>(p, tridiag_scratch(n));
+    Al = carve<z64>(p, (size_t)L * mL * mL);
+    Vl = carve<z64>(p, (size_t)L * mL * mL);
+    wl = carve<double>(p, (size_t)L * mL);
+    lscr = carve<double>(p, (size_t)per * L);
+    Qa = carve<double>(p, NN);
+    Qb = carve<double>(p, NN);
+    Ub = carve<double>(p, NN);
+    Qg = carve<double>(p, NN);
+    Qo = carve<double>(p, NN);
+    S.n = n;
+    S.N = N;
+    S.L = L;
+    S.mL = mL;
+    S.Rd = carve<double>(p, N);
+    S.Rb = carve<double>(p, N);
+    S.D = carve<double>(p, N);
+    S.dl = carve<double>(p, N);
+    S.zz = carve<double>(p, N);
+    S.tv = carve<double>(p, N);
+    S.nrm = carve<double>(p, N);
+    S.zh = carve<double>(p, N);
+    S.cn = carve<double>(p, N);
+    S.rc = carve<double>(p, N);
+    S.rs = carve<double>(p, N);
+    S.tau = carve<double>(p, N);
+    S.srt = carve<int>(p, N);
+    S.nd = carve<int>(p, N);
+    S.dfl = carve<int>(p, N);
+    S.ra = carve<int>(p, N);
+    S.rb = carve<int>(p, N);
+    S.org = carve<int>(p, N);
+    S.outk = carve<int>(p, N);
+    S.src = carve<int>(p, N);
+    S.Km = carve<int>(p, L);
+    S.nrot = carve<int>(p, L);
+    S.ndf = carve<int>(p, L);
+    return p;
+  };
+  // sized by a layout from the (aligned) address 256, not from null
+  const size_t need = (size_t)(reinterpret_cast<uintptr_t>(layout(reinterpret_cast<char*>((uintptr_t)256))) - 256) + 256;
+  scr.ensure(need);
+  layout(static_cast<char*>(scr.p));
+  for (int b = 0; b < batch; ++b) {
+    // 1. Householder reduction of the Hermitian part of A
+    HIPCK(hipMemcpy2DAsync(Ah, sizeof(z64) * n, A + b * sA, sizeof(z64) * lda, sizeof(z64) * n, n,
+                           hipMemcpyDeviceToDevice, st));
+    hermitize(st, n, Ah, n, 0, 1);
+    tridiag_reduce(st, n, Ah, n, dd, e, Vh, bt, tscr);
+    // 2.-3. real tridiagonal, pads, leaves
+    hipLaunchKernelGGL(k_dc_phase, dim3(1), dim3(64), 0, st, n, N, dd, e, Ph, S.Rd, S.Rb);
+    const int64_t lt = (int64_t)L * mL * mL;
+    hipLaunchKernelGGL(k_dc_leaves, dim3((unsigned)std::min<int64_t>(1024, (lt + 255) / 256)), dim3(256), 0, st, N, L,
+                       mL, S.Rd, S.Rb, Al);
+    heev_dc_raw(st, mL, Al, mL, (int64_t)mL * mL, wl, mL, Vl, mL, (int64_t)mL * mL, L, lscr);
+    hipLaunchKernelGGL(k_dc_init, dim3((unsigned)std::min<int64_t>(4096, ((int64_t)NN + 255) / 256)), dim3(256), 0,
+                       st, N, mL, wl, Vl, Qa, Qb, S.D);
+    HIPCK(hipGetLastError());
+    // 4. merges
+    double* Qcur = Qa;
+    double* Qnxt = Qb;
+    for (int sz = mL; sz < N; sz *= 2) {
+      const int m = 2 * sz, nm = N / m, chunks = (m + 127) / 128;
+      hipLaunchKernelGGL(k_dc_merge_a, dim3(nm), dim3(1024), 0, st, S, sz, Qcur);
+      hipLaunchKernelGGL(k_dc_secular, dim3(nm * chunks), dim3(1024), 0, st, S, sz, chunks);
+      hipLaunchKernelGGL(k_dc_merge_b, dim3(nm), dim3(1024), 0, st, S, sz, Qcur, Ub, Qg);
+      hipLaunchKernelGGL(k_dc_gemm, dim3((m + 63) / 64, (m + 63) / 64, nm), dim3(256), 0, st, m, S.Km, Qg, Ub, Qo);
+      hipLaunchKernelGGL(k_dc_scatter, dim3(m, nm), dim3(256), 0, st, S, sz, Qcur, Qo, Qnxt);
+      HIPCK(hipGetLastError());
+      std::swap(Qcur, Qnxt);
+    }
+    // 5. back to the basis of A
+    z64* Vb = V + b * sV;
+    hipLaunchKernelGGL(k_dc_output, dim3((unsigned)std::min<int64_t>(4096, ((int64_t)nn + 255) / 256)), dim3(256), 0,
+                       st, n, N, Qcur, S.D, Ph, Vb, ldv, w + b * sw);
+    apply_refl(st, n, n, Vh, bt, Vb, ldv, 0);
+    HIPCK(hipGetLastError());
+  }
   return true;
 }
 

@@ -2,6 +2,8 @@
 // on the given stream; sizes are validated by the callers.
 #pragma once
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace eahp {
@@ -100,11 +102,18 @@ template <typename T>
 void scale_rows(hipStream_t st, int m, int ncols, const double* D, cplx<T>* B, int64_t ldb);
 
 // ---- small dense (dense.hip) ---------------------------------------------------
-// Hermitian eigendecomposition A = V diag(w) V^H by parallel cyclic Jacobi, one
-// work-group per matrix (batch over blockIdx.x).  A is overwritten.
+// Hermitian eigendecomposition A = V diag(w) V^H, w ascending (batch of
+// matrices at strides sA, sw, sV): n <= 128 one work-group per matrix
+// (Householder + divide and conquer in LDS); n <= 2048 Householder on
+// several work-groups + divide and conquer in global memory (one matrix at a
+// time, synchronises the stream); larger n cyclic Jacobi (A overwritten,
+// EAHP_ENOCONV after 40 sweeps).  info: device int per matrix (Jacobi only).
 void heev(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, double* w, int64_t sw, z64* V, int64_t ldv,
           int64_t sV, int batch, int* info, DevMem& scr);
-// In-place inverse of a general n x n matrix (Gauss-Jordan, partial pivoting).
+// In-place inverse of a general n x n matrix (Gauss-Jordan, partial pivoting):
+// n <= 128 one work-group per matrix with the matrix in registers; larger n
+// one matrix at a time on a cooperative grid (work: n x 2n per matrix;
+// synchronises the stream).  info: device int per matrix, 1 when a pivot is 0.
 void inverse(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, z64* work, int batch, int* info);
 // Pivoted Cholesky of a Hermitian PSD G (n x n): G[piv, piv] = L L^H with rank r
 // (diagonal pivots below tol * first pivot are dropped); outputs the upper
@@ -138,5 +147,16 @@ void set_identity(hipStream_t st, int p, z64* M, int64_t ldm);
 // (A - s_l I) y_l = c_l for all columns of Yt (q x p, ld q; overwritten by the
 // solutions) through one Householder tridiagonalisation of A (destroyed).
 void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws);
+// Householder reduction of a Hermitian A (q x q, ld lda; destroyed for q > 512)
+// to the Hermitian tridiagonal T = Q^H A Q, Q = H_0 ... H_{q-2}: dd (q reals,
+// the diagonal), e (q complex, e[k] = T[k+1][k]), the reflectors Vh (q x q,
+// ld q, v_k in rows k+1.. of column k) and beta (q); H_k = I - beta_k v_k v_k^H.
+// scr: tridiag_scratch(q) bytes of device memory.  Synchronises the stream.
+size_t tridiag_scratch(int q);
+// held around every launch of a kernel whose work-groups wait on each other
+std::mutex& coop_mutex();
+void tridiag_reduce(hipStream_t st, int q, z64* A, int64_t lda, double* dd, z64* e, z64* Vh, double* beta, void* scr);
+// Y <- Q^H Y (forward = 1) or Q Y (forward = 0) for the reflectors of tridiag_reduce
+void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* beta, z64* Y, int64_t ldy, int forward);
 
 }  // namespace eahp

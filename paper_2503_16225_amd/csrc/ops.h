@@ -2,6 +2,7 @@
 #pragma once
 
 #include <array>
+#include <atomic>
 
 #include "kernels.h"
 
@@ -18,6 +19,13 @@ struct PointScalars {
 };
 
 extern thread_local std::string g_last_error;
+
+// Timing of the complex products on the stream of the context whose timing is
+// enabled (eahp_prof_enable; one context at a time): slot kProfGemm + op
+// (0 A^H B, 1 A M) + 2 (FP32) + 4 (fewer than 1024 rows).
+extern std::atomic<eahp_ctx*> g_prof_ctx;
+void gemm_prof_begin(hipStream_t st, int slot);
+void gemm_prof_end(hipStream_t st, int slot, double flops);
 
 void build_problem(eahp_problem* pb, const eahp_system_desc* d);
 void layout_estimate(const eahp_system_desc* d, std::vector<int64_t>& npw, int n[3], int& ns, size_t& bytes);

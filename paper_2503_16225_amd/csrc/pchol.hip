@@ -195,4 +195,179 @@ bool pchol_inv_reg(hipStream_t st, int n, const z64* G, int64_t ldg, double tol,
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// kPcMax < n <= kPcBig: the same factorisation (logical pivoting, the same
+// pivot and rank rules, the factor written row-major to Lg) blocked by panels
+// of kPb columns in one work-group, with the Schur complement in global
+// memory (G, overwritten after Hermitisation).  Inside a panel a column needs
+// only the panel's earlier columns, kept column-major in P (n x kPb) for
+// coalesced reads; after the panel the live part of the trailing matrix takes
+// the panel's rank-kPb update.
+namespace {
+constexpr int kPcBig = 2048;
+constexpr int kPb = 16;
+}  // namespace
+
+__global__ void __launch_bounds__(1024) k_pchol_big(int n, z64* G, int64_t ldg, double tol, int* __restrict__ piv,
+                                                    int* __restrict__ rank_out, z64* __restrict__ Lg,
+                                                    z64* __restrict__ P, int pivot) {
+  __shared__ double dg[kPcBig];
+  __shared__ int done[kPcBig];
+  __shared__ int pvs[kPcBig];
+  __shared__ z64 lp[kPb];
+  __shared__ double cv[16];
+  __shared__ int ci[16];
+  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wv = t >> 6;
+  for (int64_t e = t; e < (int64_t)n * n; e += nt) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    if (i < j) {
+      const z64 a = G[i + (int64_t)j * ldg], b = G[j + (int64_t)i * ldg];
+      const z64 h = mk<double>(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+      G[i + (int64_t)j * ldg] = h;
+      G[j + (int64_t)i * ldg] = mk<double>(h.x, -h.y);
+    }
+  }
+  for (int i = t; i < n; i += nt) {
+    dg[i] = G[i + (int64_t)i * ldg].x;
+    done[i] = 0;
+  }
+  __syncthreads();
+  double d0 = 0.0;
+  int r = n;
+  for (int k0 = 0; k0 < n && r == n; k0 += kPb) {
+    const int kend = min(n, k0 + kPb);
+    int k = k0;
+    for (; k < kend; ++k) {
+      double best;
+      int b;
+      if (pivot) {
+        double val = -1.0;
+        int row = 1 << 20;
+        for (int i = t; i < n; i += nt)
+          if (!done[i] && dg[i] > val) {
+            val = dg[i];
+            row = i;
+          }
+        wave_argmax(val, row);
+        if (lane == 0) {
+          cv[wv] = val;
+          ci[wv] = row;
+        }
+        __syncthreads();
+        best = lane < (nt >> 6) ? cv[lane] : -2.0;
+        b = lane < (nt >> 6) ? ci[lane] : 1 << 20;
+        row16_argmax(best, b);
+        best = readlane_f64(best, 0);
+        b = __builtin_amdgcn_readlane(b, 0);
+      } else {
+        best = dg[k];
+        b = k;
+      }
+      if (k == 0) d0 = best;
+      if (!(best > tol * d0) || !(best > 0.0)) {
+        r = k;
+        break;
+      }
+      const double lbb = sqrt(best), il = 1.0 / lbb;
+      const int np = k - k0;
+      if (t < np) lp[t] = P[b + (int64_t)t * n];
+      __syncthreads();
+      for (int i = t; i < n; i += nt) {
+        z64 l = mk<double>(0.0, 0.0);
+        if (i == b) {
+          l = mk<double>(lbb, 0.0);
+        } else if (!done[i]) {
+          z64 a = G[i + (int64_t)b * ldg];
+          for (int c = 0; c < np; ++c) {
+            const z64 li = P[i + (int64_t)c * n], lb = lp[c];
+            a.x -= li.x * lb.x + li.y * lb.y;
+            a.y -= li.y * lb.x - li.x * lb.y;
+          }
+          l = cscale<double>(a, il);
+          dg[i] -= l.x * l.x + l.y * l.y;
+        }
+        P[i + (int64_t)np * n] = l;
+        Lg[(int64_t)i * n + k] = l;
+      }
+      __syncthreads();
+      if (t == 0) {
+        done[b] = 1;
+        pvs[k] = b;
+      }
+      __syncthreads();
+    }
+    const int np = k - k0;
+    if (r == n && np > 0 && kend < n) {
+      for (int64_t e = t; e < (int64_t)n * n; e += nt) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        if (done[i] || done[j]) continue;
+        z64 a = G[i + (int64_t)j * ldg];
+        for (int c = 0; c < np; ++c) {
+          const z64 li = P[i + (int64_t)c * n], lj = P[j + (int64_t)c * n];
+          a.x -= li.x * lj.x + li.y * lj.y;
+          a.y -= li.y * lj.x - li.x * lj.y;
+        }
+        G[i + (int64_t)j * ldg] = a;
+      }
+      __syncthreads();
+    }
+  }
+  if (t == 0) {
+    int q = r;
+    for (int i = 0; i < n; ++i)
+      if (!done[i]) pvs[q++] = i;
+    *rank_out = r;
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += nt) piv[i] = pvs[i];
+}
+
+// Column j < r of U = P L^-H for n > kPcMax: the backward substitution of
+// k_chol_uinv with the right-hand side in LDS, one work-group per column.
+__global__ void __launch_bounds__(256) k_chol_uinv_big(int n, const int* __restrict__ rank,
+                                                       const int* __restrict__ piv, const z64* __restrict__ Lg,
+                                                       z64* __restrict__ U, int64_t ldu) {
+  __shared__ z64 rhs[kPcBig];
+  __shared__ int pv[kPcBig];
+  __shared__ z64 ya;
+  const int j = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+  const int r = *rank;
+  if (j >= r) return;
+  for (int i = t; i < n; i += nt) {
+    pv[i] = piv[i];
+    rhs[i] = mk<double>(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int a = j; a >= 0; --a) {
+    const z64* row = Lg + (int64_t)pv[a] * n;  // Lt[a][m] = row[m]
+    if (t == 0) {
+      const double inv = 1.0 / row[a].x;
+      ya = mk<double>(rhs[a].x * inv, rhs[a].y * inv);
+      rhs[a] = ya;
+    }
+    __syncthreads();
+    const z64 y = ya;
+    for (int m = t; m < a; m += nt) {
+      const z64 c = row[m];
+      rhs[m].x -= c.x * y.x + c.y * y.y;
+      rhs[m].y -= c.x * y.y - c.y * y.x;
+    }
+    __syncthreads();
+  }
+  for (int i = t; i < n; i += nt) U[pv[i] + (int64_t)j * ldu] = i <= j ? rhs[i] : mk<double>(0.0, 0.0);
+}
+
+bool pchol_inv_big(hipStream_t st, int n, z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* U, int64_t ldu,
+                   DevMem& scr, bool pivot) {
+  if (n <= kPcMax || n > kPcBig) return false;
+  scr.ensure(sizeof(z64) * ((size_t)n * n + (size_t)n * kPb));
+  z64* Lg = scr.as<z64>();
+  z64* P = Lg + (size_t)n * n;
+  hipLaunchKernelGGL(k_pchol_big, dim3(1), dim3(1024), 0, st, n, G, ldg, tol, piv, rank, Lg, P, pivot ? 1 : 0);
+  HIPCK(hipGetLastError());
+  hipLaunchKernelGGL(k_chol_uinv_big, dim3(n), dim3(256), 0, st, n, rank, piv, Lg, U, ldu);
+  HIPCK(hipGetLastError());
+  return true;
+}
+
 }  // namespace eahp

@@ -1,6 +1,7 @@
 // Problem set-up (plane-wave bases, FFT plans, static fields) and the
 // Kohn-Sham operators on frames: density, potentials, energy, H-apply,
 // Lambda and residual.
+#include <atomic>
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -372,6 +373,33 @@ void fetch_scalars(eahp_problem* pb, int n) {
 double* scal(eahp_problem* pb, int i) { return pb->d_scal.as<double>() + i; }
 
 // -------------------------------------------------------------------- kernel timing
+// the context whose timing is on (for the products, which see only a stream)
+std::atomic<eahp_ctx*> g_prof_ctx{nullptr};
+
+static void slot_begin(eahp_ctx* c, int id) {
+  ProfSlot& s = c->slot[id];
+  if (s.used == (int)s.start.size()) {
+    hipEvent_t a, b;
+    HIPCK(hipEventCreate(&a));
+    HIPCK(hipEventCreate(&b));
+    s.start.push_back(a);
+    s.stop.push_back(b);
+  }
+  HIPCK(hipEventRecord(s.start[s.used], c->stream));
+}
+void gemm_prof_begin(hipStream_t st, int slot) {
+  eahp_ctx* c = g_prof_ctx.load();
+  if (c && c->prof && c->stream == st) slot_begin(c, slot);
+}
+void gemm_prof_end(hipStream_t st, int slot, double flops) {
+  eahp_ctx* c = g_prof_ctx.load();
+  if (!c || !c->prof || c->stream != st) return;
+  ProfSlot& s = c->slot[slot];
+  HIPCK(hipEventRecord(s.stop[s.used], c->stream));
+  ++s.used;
+  s.bytes += flops;
+}
+
 void prof_begin(eahp_problem* pb, int id) {
   eahp_ctx* c = pb->ctx;
   if (!c->prof) return;

@@ -57,6 +57,11 @@ struct eahp_server {
   uint64_t next = 1;
   bool stop = false;
   std::thread sched;
+  // one joinable thread per admitted request; a finished request puts its
+  // ticket into `finished` and the scheduler joins the thread (outside the
+  // lock), so no request thread outlives wait_all or destroy
+  std::map<uint64_t, std::thread> workers;
+  std::vector<uint64_t> finished;
 };
 
 namespace {
@@ -104,6 +109,7 @@ void run_request(eahp_server* sv, Request* rq) {
   if (st) (void)hipStreamDestroy(st);
   std::lock_guard<std::mutex> lk(sv->mu);
   rq->t_done = now_s();
+  sv->finished.push_back(rq->ticket);
   if (rc != EAHP_OK) {
     rq->status = rc;
     rq->err = err;
@@ -119,6 +125,24 @@ void run_request(eahp_server* sv, Request* rq) {
 void scheduler(eahp_server* sv) {
   std::unique_lock<std::mutex> lk(sv->mu);
   for (;;) {
+    // join the threads of finished requests (they may still be releasing the
+    // lock and their per-thread state), without holding the lock
+    if (!sv->finished.empty()) {
+      std::vector<std::thread> done;
+      for (uint64_t id : sv->finished) {
+        auto it = sv->workers.find(id);
+        if (it != sv->workers.end()) {
+          done.push_back(std::move(it->second));
+          sv->workers.erase(it);
+        }
+      }
+      sv->finished.clear();
+      lk.unlock();
+      for (auto& t : done) t.join();
+      lk.lock();
+      sv->cv.notify_all();
+      continue;
+    }
     // admit the first queued request that fits
     Request* pick = nullptr;
     if (sv->active < sv->max_slots) {
@@ -134,10 +158,10 @@ void scheduler(eahp_server* sv) {
       pick->t_start = now_s();
       sv->used += pick->est;
       ++sv->active;
-      std::thread(run_request, sv, pick).detach();
+      sv->workers.emplace(pick->ticket, std::thread(run_request, sv, pick));
       continue;
     }
-    if (sv->stop && sv->queue.empty() && sv->active == 0) return;
+    if (sv->stop && sv->queue.empty() && sv->active == 0 && sv->workers.empty()) return;
     sv->cv.wait(lk);
   }
 }
@@ -258,7 +282,8 @@ int eahp_server_result(eahp_server* sv, uint64_t ticket, void* psi_host) {
 int eahp_server_wait_all(eahp_server* sv) {
   if (!sv) return EAHP_EINVAL;
   std::unique_lock<std::mutex> lk(sv->mu);
-  sv->cv.wait(lk, [&] { return sv->queue.empty() && sv->active == 0; });
+  // also until the scheduler has joined every finished request's thread
+  sv->cv.wait(lk, [&] { return sv->queue.empty() && sv->active == 0 && sv->workers.empty(); });
   return EAHP_OK;
 }
 

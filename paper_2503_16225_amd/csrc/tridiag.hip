@@ -82,10 +82,13 @@ __device__ void tri_matvec(int q, int k, int c_first, int G, const z64* A, int64
   }
 }
 
+// The work-group's vectors v, w and vn (3 q values) live in LDS, or, when
+// vbuf is not null (q too large for LDS), in the work-group's own 3 q slice of
+// vbuf in global memory.
 __global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, double* d, z64* e, z64* Vh,
-                                                  int64_t ldv, double* beta, z64* Pbuf) {
+                                                  int64_t ldv, double* beta, z64* Pbuf, z64* vbuf) {
   extern __shared__ unsigned char smem_raw[];
-  z64* v = reinterpret_cast<z64*>(smem_raw);  // q
+  z64* v = vbuf ? vbuf + (int64_t)3 * q * blockIdx.x : reinterpret_cast<z64*>(smem_raw);  // q
   z64* w = v + q;                             // q
   z64* vn = w + q;                            // q: next reflector
   __shared__ double red[32];
@@ -618,98 +621,124 @@ __device__ __forceinline__ z64 cdiv_(z64 a, z64 b) {
 
 __global__ void k_set_d0(const z64* A, double* d) { d[0] = A[0].x; }
 
-// Y~ (q x p, ld q) := solution of (A - s_l) y~_l = C~[:, l]; A (q x q, ld lda)
-// may be destroyed.  ws grows to what the chosen kernels need.
 namespace {
 template <int NS>
-void tridiag_reg_launch(hipStream_t st, int q, int p, z64* A, int64_t lda, double* dd, z64* e, z64* Vh, double* bt,
-                        z64* Pb, z64* Cb, z64* Yt, int* herr) {
+void tridiag_reg_launch(hipStream_t st, int q, const z64* A, int64_t lda, double* dd, z64* e, z64* Vh, double* bt,
+                        z64* Pb, z64* Cb, int* herr) {
   const int G = (q + kTrWaves * kTrCols - 1) / (kTrWaves * kTrCols);
-  // Pb and Cb are contiguous: 2 q^2 complex slots, 4 q^2 words
+  // Pb and Cb are contiguous: 2 q^2 complex slots, 4 q^2 words; the error
+  // flag (device memory) follows them and starts at zero
   const int64_t nw = (int64_t)4 * q * q;
   hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>(1024, (nw + 255) / 256)), dim3(256), 0, st,
                      reinterpret_cast<unsigned long long*>(Pb), nw, kEmpty);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned long long*>(herr), (int64_t)1,
+                     0ull);
   int qq = q;
   int64_t la = lda, lv = q;
   void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &Pb, &Cb, &herr};
-  *reinterpret_cast<volatile int*>(herr) = 0;
   HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag_reg<NS>, dim3(G), dim3(64 * kTrWaves), args, 0, st));
+  int bad = 0;
+  HIPCK(hipMemcpyAsync(&bad, herr, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
-  if (*reinterpret_cast<volatile int*>(herr) != 0) fail(EAHP_EDEVICE, "exchange wait of the tridiagonal reduction timed out");
-  hipLaunchKernelGGL(k_apply_refl_reg<NS>, dim3((p + 3) / 4), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q,
-                     p, 1);
+  if (bad != 0) fail(EAHP_EDEVICE, "exchange wait of the tridiagonal reduction timed out");
+}
+
+// Work-groups of the L2-resident reduction; its vectors stay in LDS up to
+// q = kTrLdsMax (3 q complex values per work-group).
+constexpr int kTrLdsMax = 3200;
+int tridiag_groups(int q) {
+  int dev = 0, ncu = 0;
+  HIPCK(hipGetDevice(&dev));
+  HIPCK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  // one work-group per 32 columns: the grid barrier of every step costs
+  // more with more work-groups than their added bandwidth gains
+  return std::min(ncu, std::max(1, (q + 31) / 32));
 }
 }  // namespace
 
-// Q^H Y (forward) or Q Y for q > 512: a wave per column with the column in
-// registers up to q = 1536, a work-group per column beyond
-static void apply_refl_large(hipStream_t st, int q, int p, const z64* Vh, const double* bt, z64* Yt, int forward) {
-  const dim3 g((p + 3) / 4), b(256);
-  if (q <= 1024) hipLaunchKernelGGL(k_apply_refl_reg<16>, g, b, 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, p, forward);
-  else if (q <= 1536)
-    hipLaunchKernelGGL(k_apply_refl_reg<24>, g, b, 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, p, forward);
-  else hipLaunchKernelGGL(k_apply_refl, dim3(p), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, forward);
+// Kernels that wait on each other's work-groups must not share the CUs with
+// another such launch from a concurrent stream (the serving loop): one at a
+// time per process, waited for before the next.
+std::mutex& coop_mutex() {
+  static std::mutex m;
+  return m;
 }
 
+size_t tridiag_scratch(int q) {
+  if (q < 2) return 0;
+  if (q <= 512) return sizeof(z64) * 2 * (size_t)q * q + 64;  // exchange slots, error flag
+  size_t b = sizeof(z64) * 2 * (size_t)q;  // double-buffered p
+  if (q > kTrLdsMax) b += sizeof(z64) * 3 * (size_t)q * tridiag_groups(q);
+  return b;
+}
+
+void tridiag_reduce(hipStream_t st, int q, z64* A, int64_t lda, double* dd, z64* e, z64* Vh, double* bt, void* scr) {
+  if (q <= 0) return;
+  if (q == 1) {
+    hipLaunchKernelGGL(k_set_d0, dim3(1), dim3(1), 0, st, A, dd);
+    HIPCK(hipGetLastError());
+    return;
+  }
+  std::lock_guard<std::mutex> lk(coop_mutex());
+  if (q <= 512) {
+    z64* Pb = static_cast<z64*>(scr);
+    z64* Cb = Pb + (size_t)q * q;
+    int* herr = reinterpret_cast<int*>(Cb + (size_t)q * q);
+    if (q <= 128) tridiag_reg_launch<2>(st, q, A, lda, dd, e, Vh, bt, Pb, Cb, herr);
+    else if (q <= 256) tridiag_reg_launch<4>(st, q, A, lda, dd, e, Vh, bt, Pb, Cb, herr);
+    else tridiag_reg_launch<8>(st, q, A, lda, dd, e, Vh, bt, Pb, Cb, herr);
+    return;
+  }
+  const bool gvec = q > kTrLdsMax;
+  const int Gl = tridiag_groups(q);
+  z64* P = static_cast<z64*>(scr);
+  z64* vb = gvec ? P + 2 * (size_t)q : nullptr;
+  const size_t lds = gvec ? 0 : sizeof(z64) * 3 * (size_t)q;
+  HIPCK(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int per_cu = 0;
+  HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tridiag, 1024, lds));
+  if (per_cu < 1) fail(EAHP_EDEVICE, "the tridiagonal reduction cannot be made resident");
+  int qq = q;
+  int64_t la = lda, lv = q;
+  void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P, &vb};
+  HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(Gl), dim3(1024), args, lds, st));
+  HIPCK(hipStreamSynchronize(st));
+}
+
+// Q^H Y (forward) or Q Y: a wave per column with the column in registers up to
+// q = 1536, a work-group per column beyond
+void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* bt, z64* Y, int64_t ldy, int forward) {
+  if (q < 2 || ncols <= 0) return;
+  const dim3 g((ncols + 3) / 4), b(256);
+  if (q <= 128) hipLaunchKernelGGL(k_apply_refl_reg<2>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
+  else if (q <= 256) hipLaunchKernelGGL(k_apply_refl_reg<4>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
+  else if (q <= 512) hipLaunchKernelGGL(k_apply_refl_reg<8>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
+  else if (q <= 1024)
+    hipLaunchKernelGGL(k_apply_refl_reg<16>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
+  else if (q <= 1536)
+    hipLaunchKernelGGL(k_apply_refl_reg<24>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
+  else hipLaunchKernelGGL(k_apply_refl, dim3(ncols), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Y, ldy, forward);
+  HIPCK(hipGetLastError());
+}
+
+// Y~ (q x p, ld q) := solution of (A - s_l) y~_l = C~[:, l]; A (q x q, ld lda)
+// may be destroyed.  ws grows to what the chosen kernels need.
 void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws) {
   if (q <= 0 || p <= 0) return;
-  if (q > 3200) fail(EAHP_EINVAL, "projected FOM system larger than 3200");
-  const bool reg = q >= 2 && q <= 512;
-  // Vh (q x q), W (3 q p), e (q), P (2 q), then d, beta (q each), then for the
-  // register-resident reduction the exchange slots Pb, Cb (q x q each)
-  const size_t base = sizeof(z64) * ((size_t)q * q + (size_t)3 * q * p + 3 * (size_t)q) + sizeof(double) * 2 * q;
-  const size_t need = base + (reg ? sizeof(z64) * 2 * (size_t)q * q : 0) + 512;
-  ws.ensure(need);
+  // Vh (q x q), W (3 q p), e (q), then d, beta (q each), then the scratch of
+  // the reduction
+  const size_t base = sizeof(z64) * ((size_t)q * q + (size_t)3 * q * p + (size_t)q) + sizeof(double) * 2 * q + 64;
+  ws.ensure(base + tridiag_scratch(q) + 256);
   z64* Vh = ws.as<z64>();
   z64* W = Vh + (size_t)q * q;
   z64* e = W + (size_t)3 * q * p;
-  z64* P = e + q;
-  double* dd = reinterpret_cast<double*>(P + 2 * q);
+  double* dd = reinterpret_cast<double*>(e + q);
   double* bt = dd + q;
-  z64* Pb = reinterpret_cast<z64*>(bt + q + 8);
-  z64* Cb = Pb + (size_t)q * q;
-  if (q >= 2) {
-    // kernels that wait on each other's work-groups must not share the CUs
-    // with another such launch from a concurrent stream (the serving loop):
-    // one at a time per process, waited for before the next
-    static std::mutex coop;
-    static int* herr = nullptr;
-    std::lock_guard<std::mutex> lk(coop);
-    if (reg) {
-      if (!herr) HIPCK(hipHostMalloc((void**)&herr, 64, hipHostMallocDefault));
-      if (q <= 128) tridiag_reg_launch<2>(st, q, p, A, lda, dd, e, Vh, bt, Pb, Cb, Yt, herr);
-      else if (q <= 256) tridiag_reg_launch<4>(st, q, p, A, lda, dd, e, Vh, bt, Pb, Cb, Yt, herr);
-      else tridiag_reg_launch<8>(st, q, p, A, lda, dd, e, Vh, bt, Pb, Cb, Yt, herr);
-    } else {
-      const size_t lds = sizeof(z64) * 3 * (size_t)q;
-      HIPCK(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      int per_cu = 0;
-      HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tridiag, 1024, lds));
-      int dev = 0, ncu = 0;
-      HIPCK(hipGetDevice(&dev));
-      HIPCK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-      // one work-group per 32 columns: the grid barrier of every step costs
-      // more with more work-groups than their added bandwidth gains
-      const int G = std::min({std::max(1, per_cu) * ncu, ncu, std::max(1, (q + 31) / 32)});
-      int qq = q;
-      int64_t la = lda, lv = q;
-      void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P};
-      HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(G), dim3(1024), args, lds, st));
-      HIPCK(hipStreamSynchronize(st));
-      apply_refl_large(st, q, p, Vh, bt, Yt, 1);
-    }
-  } else {
-    hipLaunchKernelGGL(k_set_d0, dim3(1), dim3(1), 0, st, A, dd);
-  }
+  void* scr = reinterpret_cast<char*>(ws.p) + (base + 255) / 256 * 256;
+  tridiag_reduce(st, q, A, lda, dd, e, Vh, bt, scr);
+  apply_refl(st, q, p, Vh, bt, Yt, q, 1);
   hipLaunchKernelGGL(k_trisolve_reg, dim3((p + 63) / 64), dim3(64), 0, st, q, p, dd, e, s, Yt, (int64_t)q, W);
-  if (reg) {
-    const dim3 g((p + 3) / 4), b(256);
-    if (q <= 128) hipLaunchKernelGGL(k_apply_refl_reg<2>, g, b, 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, p, 0);
-    else if (q <= 256) hipLaunchKernelGGL(k_apply_refl_reg<4>, g, b, 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, p, 0);
-    else hipLaunchKernelGGL(k_apply_refl_reg<8>, g, b, 0, st, q, Vh, (int64_t)q, bt, Yt, (int64_t)q, p, 0);
-  } else if (q >= 2) {
-    apply_refl_large(st, q, p, Vh, bt, Yt, 0);
-  }
+  apply_refl(st, q, p, Vh, bt, Yt, q, 0);
   HIPCK(hipGetLastError());
 }
 
