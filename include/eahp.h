@@ -181,6 +181,22 @@ int eahp_metric_solve(eahp_problem* pb, const void* Psi, double mu, double rtol,
 /* Energy-adaptive gradient G = Psi - X (Psi^* X)^-1 per k (Sec. 5.2). */
 int eahp_ea_gradient(eahp_problem* pb, const void* Psi, const void* X, void* G);
 
+/* For callers that cannot allocate device memory (graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same G as
+ * eahp_ea_gradient, with every intermediate (the p x p products and their
+ * inverses, the partial tiles of the Gram product, the Gauss-Jordan work and
+ * pivot flags) in a fixed device array of eahp_noalloc_scratch_bytes() bytes
+ * (32 MiB) that the library holds on each device until the process ends; no
+ * hipMalloc, hipFree or other allocation is made.  The array's address on a
+ * device is looked up when the first context is created on that device.
+ * Needs nk p^2 x 16 bytes (x 3 when p > 128) plus the Gram tiles to fit,
+ * else EAHP_EINVAL before any device work.  All calls on one device share
+ * the array: calls that overlap on one device (concurrent streams or host
+ * threads) race and must be serialised by the caller.  Synchronises the
+ * context stream (the singularity check, EAHP_EFOM). */
+int eahp_ea_gradient_noalloc(eahp_problem* pb, const void* Psi, const void* X, void* G);
+size_t eahp_noalloc_scratch_bytes(void);
+
 /* Polar retraction Psi_out = pf(Psi + tau eta) (eqs. (3.1)-(3.2)), per k.
  * Returns EAHP_ENOTPD when (Psi + tau eta)^*(Psi + tau eta) is not positive
  * definite. */

@@ -113,6 +113,8 @@ def load_library():
         "eahp_residual": ([vp, vp, vp, vp, dp, dp], C.c_int),
         "eahp_metric_solve": ([vp, vp, C.c_double, C.c_double, C.c_int, vp, ip, dp], C.c_int),
         "eahp_ea_gradient": ([vp, vp, vp, vp], C.c_int),
+        "eahp_ea_gradient_noalloc": ([vp, vp, vp, vp], C.c_int),
+        "eahp_noalloc_scratch_bytes": ([], C.c_size_t),
         "eahp_retract": ([vp, vp, vp, C.c_double, vp], C.c_int),
         "eahp_transport": ([vp, vp, vp, vp, vp], C.c_int),
         "eahp_retract_qr": ([vp, vp, vp, C.c_double, vp], C.c_int),
@@ -408,6 +410,12 @@ class Problem:
     def ea_gradient(self, Psi, X):
         G = self.empty_frame()
         _check(self.lib.eahp_ea_gradient(self.pb, _ptr(Psi), _ptr(X), _ptr(G)))
+        return G
+
+    def ea_gradient_noalloc(self, Psi, X, G):
+        """eahp_ea_gradient_noalloc into the caller's frame G (no allocation
+        inside the library)."""
+        _check(self.lib.eahp_ea_gradient_noalloc(self.pb, _ptr(Psi), _ptr(X), _ptr(G)))
         return G
 
     def retract(self, Psi, eta, tau, qr=False):

@@ -541,6 +541,7 @@ int eahp_ctx_create(int device, void* hip_stream, eahp_ctx** out) {
     HIPCK(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) fail(EAHP_EINVAL, "no such device");
     HIPCK(hipSetDevice(device));
+    noalloc_init(device);
     auto* c = new eahp_ctx;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;

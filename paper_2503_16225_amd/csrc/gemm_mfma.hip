@@ -355,35 +355,60 @@ __global__ void __launch_bounds__(256) k_gemm_nn_mfma(int64_t n, int a, int b, c
   }
 }
 
-template <typename T>
-void gemm_hn_mfma(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* B,
-                  int64_t ldb, cplx<T>* C, int64_t ldc, double alpha, double beta, DevMem& part, int batch,
-                  int64_t sA, int64_t sB, int64_t sC) {
+// Split of the row dimension: about four work-groups per CU (the loads of one
+// overlap the products of the others), at least 4 chunks of rows each, the
+// partial tiles (written and read once more) under half the input bytes, and
+// at most max_part complex partial values in all.
+static void hn_split(int64_t n, int a, int b, int batch, int64_t max_part, int64_t& nsplit, int64_t& rps,
+                     int64_t& per_split) {
   const int tiles = ((a + MT - 1) / MT) * ((b + MT - 1) / MT);
-  // about four work-groups per CU (the loads of one overlap the products of
-  // the others), at least 4 chunks of rows each, and the partial tiles
-  // (written and read once more) under half the input bytes
   const int64_t in_elems = n * (int64_t)(a + b);
-  int64_t nsplit = (1024 + tiles * batch - 1) / (tiles * batch);
+  per_split = (int64_t)tiles * 4 * 4 * 256;
+  nsplit = (1024 + tiles * batch - 1) / (tiles * batch);
   nsplit = std::min<int64_t>(nsplit, (n + 4 * MK - 1) / (4 * MK));
   nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, in_elems / (2LL * tiles * MT * MT)));
+  nsplit = std::min<int64_t>(nsplit, max_part / std::max<int64_t>(1, per_split * batch));
   nsplit = std::max<int64_t>(1, nsplit);
-  int64_t rps = (n + nsplit - 1) / nsplit;
+  rps = (n + nsplit - 1) / nsplit;
   rps = ((rps + MK - 1) / MK) * MK;
   nsplit = std::max<int64_t>(1, (n + rps - 1) / rps);
   if (n <= 0) {
     nsplit = 1;
     rps = 0;
   }
-  const int64_t per_split = (int64_t)tiles * 4 * 4 * 256;
-  part.ensure(sizeof(cplx<T>) * (size_t)(nsplit * per_split * batch));
+}
+
+size_t gemm_hn_min_part(int a, int b, int batch) {
+  const int tiles = ((a + MT - 1) / MT) * ((b + MT - 1) / MT);
+  return (size_t)tiles * 4 * 4 * 256 * batch;
+}
+
+template <typename T>
+void gemm_hn_mfma_ws(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* B,
+                     int64_t ldb, cplx<T>* C, int64_t ldc, double alpha, double beta, cplx<T>* part, size_t part_elems,
+                     int batch, int64_t sA, int64_t sB, int64_t sC) {
+  const int tiles = ((a + MT - 1) / MT) * ((b + MT - 1) / MT);
+  int64_t nsplit, rps, per_split;
+  hn_split(n, a, b, batch, (int64_t)part_elems, nsplit, rps, per_split);
+  if ((size_t)(nsplit * per_split * batch) > part_elems) fail(EAHP_EINVAL, "Gram product: partial buffer too small");
   hipLaunchKernelGGL((k_gemm_hn_mfma<T>), dim3(tiles, (unsigned)nsplit, batch), dim3(256), 0, st, n, a, b, A, lda, B,
-                     ldb, rps, part.as<cplx<T>>(), sA, sB);
+                     ldb, rps, part, sA, sB);
   HIPCK(hipGetLastError());
   const int nb = (int)std::min<int64_t>(4096, (per_split + 15) / 16);
-  hipLaunchKernelGGL((k_gemm_hn_mfma_reduce<T>), dim3(nb, batch), dim3(256), 0, st, a, b, (int)nsplit,
-                     part.as<cplx<T>>(), C, ldc, alpha, beta, sC);
+  hipLaunchKernelGGL((k_gemm_hn_mfma_reduce<T>), dim3(nb, batch), dim3(256), 0, st, a, b, (int)nsplit, part, C, ldc,
+                     alpha, beta, sC);
   HIPCK(hipGetLastError());
+}
+
+template <typename T>
+void gemm_hn_mfma(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* B,
+                  int64_t ldb, cplx<T>* C, int64_t ldc, double alpha, double beta, DevMem& part, int batch,
+                  int64_t sA, int64_t sB, int64_t sC) {
+  int64_t nsplit, rps, per_split;
+  hn_split(n, a, b, batch, INT64_MAX, nsplit, rps, per_split);
+  const size_t elems = (size_t)(nsplit * per_split * batch);
+  part.ensure(sizeof(cplx<T>) * elems);
+  gemm_hn_mfma_ws<T>(st, n, a, b, A, lda, B, ldb, C, ldc, alpha, beta, part.as<cplx<T>>(), elems, batch, sA, sB, sC);
 }
 
 template <typename T>
@@ -398,6 +423,8 @@ void gemm_nn_mfma(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int
 
 template void gemm_hn_mfma<double>(hipStream_t, int64_t, int, int, const z64*, int64_t, const z64*, int64_t, z64*,
                                    int64_t, double, double, DevMem&, int, int64_t, int64_t, int64_t);
+template void gemm_hn_mfma_ws<double>(hipStream_t, int64_t, int, int, const z64*, int64_t, const z64*, int64_t, z64*,
+                                      int64_t, double, double, z64*, size_t, int, int64_t, int64_t, int64_t);
 template void gemm_hn_mfma<float>(hipStream_t, int64_t, int, int, const c32*, int64_t, const c32*, int64_t, c32*,
                                   int64_t, double, double, DevMem&, int, int64_t, int64_t, int64_t);
 template void gemm_nn_mfma<double>(hipStream_t, int64_t, int, int, const z64*, int64_t, const z64*, int64_t, int,

@@ -72,6 +72,14 @@ template <typename T>
 void gemm_hn(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* B,
              int64_t ldb, cplx<T>* C, int64_t ldc, double alpha, double beta, DevMem& part, int batch = 1,
              int64_t sA = 0, int64_t sB = 0, int64_t sC = 0);
+// The same product with a caller-given partial buffer of part_elems complex
+// values (the row split is capped to fit; EAHP_EINVAL below
+// gemm_hn_min_part(a, b, batch)), no allocation.
+template <typename T>
+void gemm_hn_mfma_ws(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* B,
+                     int64_t ldb, cplx<T>* C, int64_t ldc, double alpha, double beta, cplx<T>* part, size_t part_elems,
+                     int batch, int64_t sA, int64_t sB, int64_t sC);
+size_t gemm_hn_min_part(int a, int b, int batch);
 // C[n x b] = alpha * A[n x a] M[a x b] + beta * C ; opM: 0 = M, 1 = M^H
 template <typename T>
 void gemm_nn(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* M, int64_t ldm,

@@ -24,6 +24,8 @@ extern thread_local std::string g_last_error;
 // enabled (eahp_prof_enable; one context at a time): slot kProfGemm + op
 // (0 A^H B, 1 A M) + 2 (FP32) + 4 (fewer than 1024 rows).
 extern std::atomic<eahp_ctx*> g_prof_ctx;
+// device address of this device's no-allocation scratch array (noalloc.hip)
+void noalloc_init(int device);
 void gemm_prof_begin(hipStream_t st, int slot);
 void gemm_prof_end(hipStream_t st, int slot, double flops);
 
