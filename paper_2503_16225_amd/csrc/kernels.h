@@ -154,7 +154,8 @@ void add_diag(hipStream_t st, int p, z64* M, int64_t ldm, int64_t sM, double v, 
 void set_identity(hipStream_t st, int p, z64* M, int64_t ldm);
 // (A - s_l I) y_l = c_l for all columns of Yt (q x p, ld q; overwritten by the
 // solutions) through one Householder tridiagonalisation of A (destroyed).
-void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws);
+void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws,
+                       DevMem& part);
 // Householder reduction of a Hermitian A (q x q, ld lda; destroyed for q > 512)
 // to the Hermitian tridiagonal T = Q^H A Q, Q = H_0 ... H_{q-2}: dd (q reals,
 // the diagonal), e (q complex, e[k] = T[k+1][k]), the reflectors Vh (q x q,
@@ -164,7 +165,10 @@ size_t tridiag_scratch(int q);
 // held around every launch of a kernel whose work-groups wait on each other
 std::mutex& coop_mutex();
 void tridiag_reduce(hipStream_t st, int q, z64* A, int64_t lda, double* dd, z64* e, z64* Vh, double* beta, void* scr);
-// Y <- Q^H Y (forward = 1) or Q Y (forward = 0) for the reflectors of tridiag_reduce
-void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* beta, z64* Y, int64_t ldy, int forward);
+// Y <- Q^H Y (forward = 1) or Q Y (forward = 0) for the reflectors of tridiag_reduce;
+// for q > 512 with wy_scr and part given: blocked products (MFMA), where
+// wy_scr holds (3 ceil((q-1)/64) 64^2 + 128 ncols) complex values + 512 bytes
+void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* beta, z64* Y, int64_t ldy, int forward,
+                void* wy_scr = nullptr, DevMem* part = nullptr);
 
 }  // namespace eahp

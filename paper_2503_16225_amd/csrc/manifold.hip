@@ -455,7 +455,8 @@ FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64*
     // in the eigenbasis of Sigma: (A_q - s_l) y~_l = (C_q U)[:, l], then Y = Y~ U^H
     copy2d(st, q, q, w.A.template as<z64>(), ldA, w.Ah.template as<z64>(), q);
     gemm_nn<double>(st, q, p, p, w.Cj.template as<z64>(), ldA, w.U.template as<z64>(), p, 0, w.T2.template as<z64>(), q, 1.0, 0.0, 0.0);
-    sylvester_tridiag(st, q, p, w.Ah.template as<z64>(), q, w.s.template as<double>(), w.T2.template as<z64>(), w.tri);
+    sylvester_tridiag(st, q, p, w.Ah.template as<z64>(), q, w.s.template as<double>(), w.T2.template as<z64>(), w.tri,
+                      pb->ws.gemm_part);
     gemm_nn<double>(st, q, p, p, w.T2.template as<z64>(), q, w.U.template as<z64>(), p, 1, w.Y.template as<z64>(), q, 1.0, 0.0, 0.0);
     gemm_nn<double>(st, q, p, p, w.Y.template as<z64>(), q, w.Sig.template as<z64>(), p, 0, w.YS.template as<z64>(), q, 1.0, 0.0, 0.0);
     const cplx<T>* Ys;

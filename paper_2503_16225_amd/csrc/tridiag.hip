@@ -102,6 +102,7 @@ __global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, do
   tri_reflector(q - 1, A + 1, v, red, sc, alpha, b);
   if (g == 0) {
     for (int i = tid; i < q - 1; i += nt) Vh[1 + i] = v[i];
+    if (tid == 0) Vh[0] = mk<double>(0.0, 0.0);
     if (tid == 0) {
       d[0] = A[0].x;
       e[0] = alpha;
@@ -136,24 +137,8 @@ __global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, do
       }
       break;
     }
-    // update owned columns c >= k + 2, one wave per column
-    {
-      const int cf = k + 2;
-      const int c0 = cf + ((g - cf) % G + G) % G;
-      for (int c = c0 + wave * G; c < q; c += nw * G) {
-        const int j = c - (k + 1);
-        const z64 wj = w[j], vj = v[j];
-        z64* col = A + (k + 1) + (int64_t)c * lda;
-        for (int r = lane; r < m; r += 64) {
-          const z64 vr = v[r], wr = w[r];
-          const double ux = vr.x * wj.x + vr.y * wj.y + wr.x * vj.x + wr.y * vj.y;
-          const double uy = vr.y * wj.x - vr.x * wj.y + wr.y * vj.x - wr.x * vj.y;
-          const z64 a = col[r];
-          col[r] = mk<double>(a.x - ux, a.y - uy);
-        }
-      }
-    }
-    // updated column k+1 (rows k+2..), recomputed redundantly: x = A[k+2:, k+1] - v w_0^* - w v_0^*
+    // updated column k+1 (rows k+2..), recomputed redundantly (nobody writes
+    // column k+1 in step k): x = A[k+2:, k+1] - v w_0^* - w v_0^*
     const int m2 = m - 1;
     {
       const z64* colk1 = A + (k + 2) + (int64_t)(k + 1) * lda;
@@ -172,20 +157,52 @@ __global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, do
       dk1 = a.x - 2.0 * (v[0].x * w[0].x + v[0].y * w[0].y);
     }
     __syncthreads();
-    // next reflector from vn (in place), then it becomes v
-    tri_reflector(m2, nullptr, vn, red, sc, alpha, b);
-    for (int i = tid; i < m2; i += nt) v[i] = vn[i];
-    __syncthreads();
+    // next reflector from vn (in place), before the trailing update
+    z64 an;
+    double bn;
+    tri_reflector(m2, nullptr, vn, red, sc, an, bn);
     if (g == 0) {
-      for (int i = tid; i < m2; i += nt) Vh[(k + 2 + i) + (int64_t)(k + 1) * ldv] = v[i];
+      for (int i = tid; i < m2; i += nt) Vh[(k + 2 + i) + (int64_t)(k + 1) * ldv] = vn[i];
+      for (int i = tid; i < k + 2; i += nt) Vh[i + (int64_t)(k + 1) * ldv] = mk<double>(0.0, 0.0);
       if (tid == 0) {
         d[k + 1] = dk1;
-        e[k + 1] = alpha;
-        beta[k + 1] = b;
+        e[k + 1] = an;
+        beta[k + 1] = bn;
       }
     }
-    // p of step k+1 on owned columns c >= k + 2 (already updated by this work-group)
-    tri_matvec(q, k + 1, k + 2, G, A, lda, v, b, Pn);
+    // one pass over every owned column c >= k + 2 (a wave per column): the
+    // rank-2 update A -= v w^H + w v^H, stored back, and in the same pass the
+    // entry of p of step k+1, bn (A[k+2:, c])^H vn
+    {
+      const int cf = k + 2;
+      const int c0 = cf + ((g - cf) % G + G) % G;
+      for (int c = c0 + wave * G; c < q; c += nw * G) {
+        const int j = c - (k + 1);
+        const z64 wj = w[j], vj = v[j];
+        z64* col = A + (k + 1) + (int64_t)c * lda;
+        double sx = 0, sy = 0;
+        for (int r = lane; r < m; r += 64) {
+          const z64 vr = v[r], wr = w[r];
+          const double ux = vr.x * wj.x + vr.y * wj.y + wr.x * vj.x + wr.y * vj.y;
+          const double uy = vr.y * wj.x - vr.x * wj.y + wr.y * vj.x - wr.x * vj.y;
+          const z64 a0 = col[r];
+          const z64 a = mk<double>(a0.x - ux, a0.y - uy);
+          col[r] = a;
+          if (r >= 1) {
+            const z64 x = vn[r - 1];
+            sx += a.x * x.x + a.y * x.y;
+            sy += a.x * x.y - a.y * x.x;
+          }
+        }
+        sx = warp_sum(sx);
+        sy = warp_sum(sy);
+        if (lane == 0) Pn[c - (k + 2)] = mk<double>(bn * sx, bn * sy);
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < m2; i += nt) v[i] = vn[i];
+    b = bn;
+    __syncthreads();
     grid.sync();
   }
 }
@@ -705,14 +722,94 @@ void tridiag_reduce(hipStream_t st, int q, z64* A, int64_t lda, double* dd, z64*
   HIPCK(hipStreamSynchronize(st));
 }
 
+// Compact WY form of a block of nb consecutive reflectors: P = H_k0 ... H_k0+nb-1
+// = I - V T V^H with T upper triangular, T_jj = beta_j and
+// T[0:j, j] = -beta_j T[0:j, 0:j] (V[:, 0:j]^H v_j), from G = V^H V.  One
+// work-group per block (blockIdx.x); writes T^H into TH as well.
+__global__ void __launch_bounds__(256) k_wy_t(int q, int nb, const z64* __restrict__ Gb, const double* __restrict__ beta,
+                                               z64* Tb, z64* THb) {
+  __shared__ z64 Ts[64 * 64];
+  __shared__ z64 gcol[64];
+  const int blk = blockIdx.x, k0 = blk * nb, t = threadIdx.x;
+  const int nbk = min(nb, q - 1 - k0);  // reflectors 0..q-2
+  const z64* G = Gb + (int64_t)blk * nb * nb;
+  for (int e = t; e < nb * nb; e += blockDim.x) Ts[e] = mk<double>(0.0, 0.0);
+  __syncthreads();
+  for (int j = 0; j < nbk; ++j) {
+    const double bj = beta[k0 + j];
+    if (t < j) gcol[t] = G[t + (int64_t)j * nb];
+    __syncthreads();
+    if (t < j) {
+      // row t of T[0:j, 0:j] times gcol (T upper: columns c >= t)
+      z64 acc = mk<double>(0.0, 0.0);
+      for (int c = t; c < j; ++c) acc = cadd<double>(acc, cmul<double>(Ts[t + c * nb], gcol[c]));
+      Ts[t + j * nb] = mk<double>(-bj * acc.x, -bj * acc.y);
+    }
+    if (t == 0) Ts[j + j * nb] = mk<double>(bj, 0.0);
+    __syncthreads();
+  }
+  z64* T = Tb + (int64_t)blk * nb * nb;
+  z64* TH = THb + (int64_t)blk * nb * nb;
+  for (int e = t; e < nb * nb; e += blockDim.x) {
+    const int r = e % nb, c = e / nb;
+    T[e] = Ts[e];
+    const z64 x = Ts[c + r * nb];
+    TH[e] = mk<double>(x.x, -x.y);
+  }
+}
+
+namespace {
+constexpr int kWyNb = 64;
+size_t wy_scratch(int q, int ncols) {
+  const int nblk = (q - 1 + kWyNb - 1) / kWyNb;
+  return sizeof(z64) * ((size_t)3 * nblk * kWyNb * kWyNb + (size_t)2 * kWyNb * ncols) + 512;
+}
+
+// Y <- Q^H Y or Q Y through the compact WY form of blocks of kWyNb reflectors:
+// every block is two products with the reflectors and one with T (MFMA).  Vh
+// must be zero above each reflector (rows <= k of column k).
+void apply_refl_wy(hipStream_t st, int q, int ncols, const z64* Vh, const double* beta, z64* Y, int64_t ldy,
+                   int forward, void* scr, DevMem& part) {
+  const int nb = kWyNb, nblk = (q - 1 + nb - 1) / nb;
+  z64* G = static_cast<z64*>(scr);
+  z64* T = G + (size_t)nblk * nb * nb;
+  z64* TH = T + (size_t)nblk * nb * nb;
+  z64* Z = TH + (size_t)nblk * nb * nb;
+  z64* Z2 = Z + (size_t)nb * ncols;
+  // G_b = V_b^H V_b: the full blocks at once, then the narrower last one
+  const int nfull = (q - 1) / nb, last = (q - 1) - nfull * nb;
+  if (nfull > 0)
+    gemm_hn<double>(st, q, nb, nb, Vh, q, Vh, q, G, nb, 1.0, 0.0, part, nfull, (int64_t)nb * q, (int64_t)nb * q,
+                    (int64_t)nb * nb);
+  if (last > 0)
+    gemm_hn<double>(st, q, last, last, Vh + (int64_t)nfull * nb * q, q, Vh + (int64_t)nfull * nb * q, q,
+                    G + (int64_t)nfull * nb * nb, nb, 1.0, 0.0, part);
+  hipLaunchKernelGGL(k_wy_t, dim3(nblk), dim3(256), 0, st, q, nb, G, beta, T, TH);
+  HIPCK(hipGetLastError());
+  for (int i = 0; i < nblk; ++i) {
+    const int blk = forward ? i : nblk - 1 - i;
+    const int k0 = blk * nb, nbk = std::min(nb, q - 1 - k0);
+    const int r0 = k0 + 1, rows = q - r0;  // the block's reflectors vanish above row k0 + 1
+    const z64* Vb = Vh + (int64_t)k0 * q + r0;
+    // Z = V_b^H Y, Z2 = T^H Z (forward) or T Z, Y -= V_b Z2
+    gemm_hn<double>(st, rows, nbk, ncols, Vb, q, Y + r0, ldy, Z, nbk, 1.0, 0.0, part);
+    gemm_nn<double>(st, nbk, nbk, ncols, (forward ? TH : T) + (int64_t)blk * nb * nb, nb, Z, nbk, 0, Z2, nbk, 1.0,
+                    0.0, 0.0);
+    gemm_nn<double>(st, rows, nbk, ncols, Vb, q, Z2, nbk, 0, Y + r0, ldy, -1.0, 0.0, 1.0);
+  }
+}
+}  // namespace
+
 // Q^H Y (forward) or Q Y: a wave per column with the column in registers up to
-// q = 1536, a work-group per column beyond
-void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* bt, z64* Y, int64_t ldy, int forward) {
+// q = 512, blocked (compact WY) products beyond
+void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* bt, z64* Y, int64_t ldy, int forward,
+                void* wy_scr, DevMem* part) {
   if (q < 2 || ncols <= 0) return;
   const dim3 g((ncols + 3) / 4), b(256);
   if (q <= 128) hipLaunchKernelGGL(k_apply_refl_reg<2>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
   else if (q <= 256) hipLaunchKernelGGL(k_apply_refl_reg<4>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
   else if (q <= 512) hipLaunchKernelGGL(k_apply_refl_reg<8>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
+  else if (wy_scr && part) apply_refl_wy(st, q, ncols, Vh, bt, Y, ldy, forward, wy_scr, *part);
   else if (q <= 1024)
     hipLaunchKernelGGL(k_apply_refl_reg<16>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
   else if (q <= 1536)
@@ -723,22 +820,26 @@ void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* b
 
 // Y~ (q x p, ld q) := solution of (A - s_l) y~_l = C~[:, l]; A (q x q, ld lda)
 // may be destroyed.  ws grows to what the chosen kernels need.
-void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws) {
+void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws,
+                       DevMem& part) {
   if (q <= 0 || p <= 0) return;
   // Vh (q x q), W (3 q p), e (q), then d, beta (q each), then the scratch of
-  // the reduction
+  // the reduction, then that of the blocked reflector products
   const size_t base = sizeof(z64) * ((size_t)q * q + (size_t)3 * q * p + (size_t)q) + sizeof(double) * 2 * q + 64;
-  ws.ensure(base + tridiag_scratch(q) + 256);
+  const size_t tb = (tridiag_scratch(q) + 255) / 256 * 256;
+  const bool wy = q > 512;
+  ws.ensure(base + 256 + tb + (wy ? wy_scratch(q, p) : 0));
   z64* Vh = ws.as<z64>();
   z64* W = Vh + (size_t)q * q;
   z64* e = W + (size_t)3 * q * p;
   double* dd = reinterpret_cast<double*>(e + q);
   double* bt = dd + q;
-  void* scr = reinterpret_cast<char*>(ws.p) + (base + 255) / 256 * 256;
+  char* scr = reinterpret_cast<char*>(ws.p) + (base + 255) / 256 * 256;
+  void* wscr = wy ? scr + tb : nullptr;
   tridiag_reduce(st, q, A, lda, dd, e, Vh, bt, scr);
-  apply_refl(st, q, p, Vh, bt, Yt, q, 1);
+  apply_refl(st, q, p, Vh, bt, Yt, q, 1, wscr, &part);
   hipLaunchKernelGGL(k_trisolve_reg, dim3((p + 63) / 64), dim3(64), 0, st, q, p, dd, e, s, Yt, (int64_t)q, W);
-  apply_refl(st, q, p, Vh, bt, Yt, q, 0);
+  apply_refl(st, q, p, Vh, bt, Yt, q, 0, wscr, &part);
   HIPCK(hipGetLastError());
 }
 

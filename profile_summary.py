@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 results databases (kernel durations, PMC counters).
 
-    python -m paper_2503_16225_amd.profile_summary trace DB [--split-gap-ms G]
-    python -m paper_2503_16225_amd.profile_summary pmc FETCH_DB WRITE_DB --kernel NAME [--copy-bytes B]
+    python profile_summary.py trace DB [--split-gap-ms G]
+    python profile_summary.py pmc FETCH_DB WRITE_DB --kernel NAME [--copy-bytes B]
 
 The pmc mode reports FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the named
 kernel, scaled by the ratio of the known byte count of a plain device copy
