@@ -39,7 +39,7 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}  # dense MFMA peaks of MI355X
-KERNEL_NAMES = ["inv_yz", "x_local", "fwd_yz", "x_density", "inv_yz_f32", "x_local_f32", "fwd_yz_f32", None,
+KERNEL_NAMES = ["inv_yz", "x_local", "fwd_yz", "x_density", "inv_yz_f32", "x_local_f32", "fwd_yz_f32", "tridiag",
                 "gemm_hn_f64", "gemm_nn_f64", "gemm_hn_f32", "gemm_nn_f32",
                 "gemm_hn_f64_small", "gemm_nn_f64_small", "gemm_hn_f32_small", "gemm_nn_f32_small"]
 # HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain

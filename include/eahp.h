@@ -255,15 +255,18 @@ void eahp_solver_destroy(eahp_solver* sv);
  * 1 = x-line transforms with the V_eff product, 2 = forward y/z transforms
  * with the gather and kinetic term, 3 = density x-line transforms; 4, 5, 6 =
  * the single-precision launches of 0, 1, 2 (metric solve of EAHP_MIXED);
- * 7 unused; and around the complex matrix products (MFMA): 8 = A^H B in FP64,
+ * 7 = the Householder reduction of the projected systems of the metric solve
+ * beyond q = 512 (several work-groups, the trailing matrix in memory); and
+ * around the complex matrix products (MFMA): 8 = A^H B in FP64,
  * 9 = A M in FP64, 10 = A^H B in FP32, 11 = A M in FP32, each over n >= 1024
  * rows (Gram matrices, projections, basis updates), 12..15 = the same over
  * fewer rows (products of the small projected matrices).
  * enable(1) starts recording (and resets); only one context records the
  * products at a time (the last one enabled).  read returns and resets the
- * summed duration, the launch count and, for 0..6, the algorithmic bytes
- * (compulsory loads and stores of each launch), for 8..15 the flops (8 per
- * complex multiply-add) since the last read. */
+ * summed duration, the launch count and, for 0..7, the algorithmic bytes
+ * (compulsory loads and stores of each launch; for 7 one read and one write
+ * of the live trailing matrix per step), for 8..15 the flops (8 per complex
+ * multiply-add) since the last read. */
 int eahp_prof_enable(eahp_ctx* ctx, int on);
 int eahp_prof_read(eahp_ctx* ctx, int kernel, double* total_ms, int64_t* launches, double* bytes);
 

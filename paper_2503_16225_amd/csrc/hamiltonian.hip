@@ -44,9 +44,14 @@ template <> __device__ __forceinline__ const double* kin_of<double>(const KDesc&
 template <> __device__ __forceinline__ const float* kin_of<float>(const KDesc& k) { return k.kin32; }
 
 __device__ __forceinline__ const KDesc& col_kd(const ColMap& cm, int c, int64_t& base) {
-  const int kk = cm.k0 + c / cm.cpk;
-  const int j = c - (c / cm.cpk) * cm.cpk;
-  const KDesc& k = cm.kd[kk];
+  const int slot = c / cm.cpk;
+  const int j = c - slot * cm.cpk;
+  if (cm.frame == 2) {
+    const int kk = cm.kmap[slot];
+    base = (int64_t)kk * cm.kstride + (int64_t)j * cm.ld;
+    return cm.kd[kk];
+  }
+  const KDesc& k = cm.kd[cm.k0 + slot];
   base = (cm.frame ? (int64_t)cm.cpk * k.off : 0) + (int64_t)j * k.npw;
   return k;
 }

@@ -97,12 +97,14 @@ struct Workspace {
 }  // namespace eahp
 
 // Optional per-kernel timing with HIP events on the context stream.
-// 0 inv_yz, 1 x_local, 2 fwd_yz, 3 x_density; 4..6 the same in FP32; 7 unused;
+// 0 inv_yz, 1 x_local, 2 fwd_yz, 3 x_density; 4..6 the same in FP32; 7 the
+// L2-resident reduction of the projected FOM systems (q > 512);
 // complex products (the "bytes" field counts flops, 8 per complex multiply-add):
 // 8 A^H B FP64, 9 A M FP64, 10 A^H B FP32, 11 A M FP32 over n >= 1024 rows,
 // 12..15 the same over fewer rows
 constexpr int kProfKernels = 16;
 constexpr int kProfGemm = 8;
+constexpr int kProfTridiag = 7;
 struct ProfSlot {
   std::vector<hipEvent_t> start, stop;
   int used = 0;

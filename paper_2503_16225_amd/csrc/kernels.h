@@ -21,14 +21,19 @@ struct KDesc {
   double w;                 // k-point weight
 };
 
-// Columns of an H-apply: column c belongs to k-point k0 + c / cpk and is
-// column j = c % cpk of that k-point's block; in frame mode the block of k
-// starts at cpk * off_k, otherwise at 0 (single k-point blocks).
+// Columns of an H-apply: column c is column j = c % cpk of the block of
+// k-point k0 + c / cpk.  frame = 1: the block of k starts at cpk * off_k
+// (a frame, ld npw_k); frame = 0: at 0 (one k-point's block, ld npw_k);
+// frame = 2 (padded batch): the k-point is kmap[c / cpk], its block starts at
+// k * kstride and every column has leading dimension ld (rows npw_k.. unused).
 struct ColMap {
   const KDesc* kd;
   int k0;
   int cpk;
   int frame;
+  int64_t ld = 0;
+  int64_t kstride = 0;
+  const int* kmap = nullptr;
 };
 
 struct GridGeom {
@@ -131,6 +136,10 @@ void inverse(hipStream_t st, int n, z64* A, int64_t lda, int64_t sA, z64* work, 
 // the first non-positive one.
 void pchol_inv(hipStream_t st, int n, z64* G, int64_t ldg, double tol, int* piv, int* rank, z64* Uinv,
                int64_t ldu, int* info, DevMem& scr, bool pivot = true);
+// A batch of pivoted factorisations as above (n <= 128): matrix b at G + b sG,
+// piv + b n, rank + b, U + b sU (n x n, columns beyond the rank zeroed).
+void pchol_inv_batched(hipStream_t st, int n, const z64* G, int64_t ldg, int64_t sG, double tol, int* piv, int* rank,
+                       z64* U, int64_t ldu, int64_t sU, int batch, DevMem& scr);
 // qR retraction support: D = Omega(M) - M for a p x p M (batch), where Omega is the
 // skew-Hermitian matrix with the strictly lower triangle of M, minus its
 // conjugate transpose above, and i Im(M_jj) on the diagonal.
@@ -167,7 +176,7 @@ std::mutex& coop_mutex();
 void tridiag_reduce(hipStream_t st, int q, z64* A, int64_t lda, double* dd, z64* e, z64* Vh, double* beta, void* scr);
 // Y <- Q^H Y (forward = 1) or Q Y (forward = 0) for the reflectors of tridiag_reduce;
 // for q > 512 with wy_scr and part given: blocked products (MFMA), where
-// wy_scr holds (3 ceil((q-1)/64) 64^2 + 128 ncols) complex values + 512 bytes
+// wy_scr holds (ceil((q-1)/256) 256^2 + 256 ncols) complex values + 512 bytes
 void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* beta, z64* Y, int64_t ldy, int forward,
                 void* wy_scr = nullptr, DevMem* part = nullptr);
 

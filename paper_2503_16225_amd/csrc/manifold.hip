@@ -525,6 +525,21 @@ void metric_solve(eahp_problem* pb, const z64* Phi, const z64* R, const z64* Lam
   const bool mixed = pb->precision == EAHP_MIXED;
   // single-precision Gram matrices cannot resolve pivots much below 1e-5 of the largest
   const double tol = mixed ? std::max(rank_tol, 1e-5) : rank_tol;
+  if (pb->nk > 1 && p <= 128) {
+    // every k-point at once (fom_batch.hip)
+    LamEig own;
+    if (!leig) {
+      lambda_eig(pb, Lam, own);
+      leig = &own;
+    }
+    std::vector<FomInfo> fi;
+    if (mixed)
+      fom_batch<float>(pb, Phi, R, leig->w.as<double>(), leig->U.as<z64>(), mu, rtol, maxit, tol, X, fi);
+    else
+      fom_batch<double>(pb, Phi, R, leig->w.as<double>(), leig->U.as<z64>(), mu, rtol, maxit, tol, X, fi);
+    if (info) *info = fi;
+    return;
+  }
   for (int ik = 0; ik < pb->nk; ++ik) {
     const int64_t o = (int64_t)p * pb->kp[ik].off;
     const double* lw = leig ? leig->w.as<double>() + (int64_t)ik * p : nullptr;

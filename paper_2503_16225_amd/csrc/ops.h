@@ -53,6 +53,12 @@ void potentials(eahp_problem* pb);
 void density_potentials(eahp_problem* pb, const z64* Psi);
 void apply_H_frame(eahp_problem* pb, const z64* X, z64* HX, bool tb_ready, double* nlvals);
 template <typename T> void apply_H_block(eahp_problem* pb, int ik, int ncols, const cplx<T>* X, cplx<T>* HX);
+// H X on a padded batch of k-point blocks (problem.hip): cpk columns of each
+// of the nact k-points in kmap (device and host copies); block of k at
+// k * kstride, columns with leading dimension ld.
+template <typename T>
+void apply_H_padded(eahp_problem* pb, int nact, const int* kmap_dev, const int* kmap_host, int cpk, const cplx<T>* X,
+                    cplx<T>* HX, int64_t ld, int64_t kstride);
 void evaluate_point(eahp_problem* pb, const z64* Psi, z64* HPsi, z64* R, z64* Lam, PointScalars* out);
 void lambda_residual(eahp_problem* pb, const z64* Psi, const z64* HPsi, z64* R, z64* Lam);
 double frame_dot(eahp_problem* pb, const z64* A, const z64* B);
@@ -101,12 +107,22 @@ struct LobWork {
   DevMem S, HS, T1, T2, T3, T4, R, A, V, w, C, Y, G, PU, piv, th, rn, alpha, idx;
   void ensure(int64_t n, int p);
 };
+// Buffers of the metric solve over all k-points at once (fom_batch.hip), at
+// the precision of the Krylov blocks; k-blocks padded to a common ld.
+struct FomBatchWork {
+  DevMem C, E, Rj, Tmp, V, W, T1, stage;
+  DevMem A, Cj, T2, Ct, Y, YS, YT, YST, wA, QA;
+  DevMem Sig, s, alpha, Gm64, PU64, PU, piv, rank, kinp, kmap, live, norms, Xt, eig, chol;
+  int qcap = 0;
+  int64_t ld = 0;
+};
 struct Arena {
   LobWork lob;
   Scratch s;
   LineFactors line;
   FomWork<double> fw64;
   FomWork<float> fw32;
+  FomBatchWork fb64, fb32;
 };
 
 // Eigendecomposition of Lambda per k (w ascending order not guaranteed).
@@ -133,5 +149,10 @@ int lobpcg_k(eahp_problem* pb, int ik, z64* X, double tol, int maxit, double* th
 void scf_run(eahp_problem* pb, z64* Psi, const eahp_scf_params& prm, eahp_scf_stats* out);
 void metric_solve(eahp_problem* pb, const z64* Phi, const z64* R, const z64* Lam, double mu, double rtol, int maxit,
                   double rank_tol, z64* X, std::vector<FomInfo>* info, const LamEig* leig = nullptr);
+// Algorithm 4 on all k-points at once (fom_batch.hip); lw, lU: eigenvalues and
+// eigenvectors of Lambda per k (nk x p, nk x p x p); info gets one entry per k.
+template <typename T>
+void fom_batch(eahp_problem* pb, const z64* Phi, const z64* R, const double* lw, const z64* lU, double mu, double rtol,
+               int maxit, double rank_tol, z64* X, std::vector<FomInfo>& info);
 
 }  // namespace eahp

@@ -574,6 +574,51 @@ void apply_H_block(eahp_problem* pb, int ik, int ncols, const cplx<T>* X, cplx<T
 template void apply_H_block<double>(eahp_problem*, int, int, const z64*, z64*);
 template void apply_H_block<float>(eahp_problem*, int, int, const c32*, c32*);
 
+// H X for cpk columns of each of the k-points listed in kmap_dev / kmap_host
+// (nact of them) in a padded batch: the block of k-point k starts at
+// k * kstride, every column has leading dimension ld (rows npw_k.. are not
+// read, and not written in HX).  One launch per transform over all columns.
+template <typename T>
+void apply_H_padded(eahp_problem* pb, int nact, const int* kmap_dev, const int* kmap_host, int cpk, const cplx<T>* X,
+                    cplx<T>* HX, int64_t ld, int64_t kstride) {
+  const int ncols = nact * cpk;
+  if (ncols <= 0) return;
+  hipStream_t st = pb->ctx->stream;
+  cplx<T>* Tb = (cplx<T>*)planes_for<T>(pb, ncols);
+  const GridGeom g = geom(pb);
+  ColMap cm{pb->d_kdesc.as<KDesc>(), 0, cpk, 2};
+  cm.ld = ld;
+  cm.kstride = kstride;
+  cm.kmap = kmap_dev;
+  const cplx<T>* twz = sizeof(T) == 8 ? (const cplx<T>*)pb->d_tw[2].p : (const cplx<T>*)pb->d_tw32[2].p;
+  const cplx<T>* twy = sizeof(T) == 8 ? (const cplx<T>*)pb->d_tw[1].p : (const cplx<T>*)pb->d_tw32[1].p;
+  const cplx<T>* twx = sizeof(T) == 8 ? (const cplx<T>*)pb->d_tw[0].p : (const cplx<T>*)pb->d_tw32[0].p;
+  const T* V = sizeof(T) == 8 ? (const T*)pb->d_veff.p : (const T*)pb->d_veff32.p;
+  double nsum = 0;
+  for (int a = 0; a < nact; ++a) nsum += (double)pb->kp[kmap_host[a]].npw * cpk;
+  const int b = 2 * (int)sizeof(T);
+  const int slot0 = sizeof(T) == 8 ? 0 : 4;
+  prof_begin(pb, slot0 + 0);
+  launch_inv_yz<T>(st, cm, ncols, g, pb->plan[2], pb->plan[1], twz, twy, X, Tb);
+  prof_end(pb, slot0 + 0, bytes_inv(pb, ncols, nsum, b));
+  prof_begin(pb, slot0 + 1);
+  launch_x_local<T>(st, ncols, g, pb->plan[0], twx, V, Tb);
+  prof_end(pb, slot0 + 1, bytes_xloc(pb, ncols, b));
+  prof_begin(pb, slot0 + 2);
+  launch_fwd_yz<T>(st, cm, ncols, g, pb->plan[2], pb->plan[1], twz, twy, Tb, X, HX);
+  prof_end(pb, slot0 + 2, bytes_fwd(pb, ncols, nsum, b));
+  for (int a = 0; a < nact; ++a) {
+    const int ik = kmap_host[a];
+    nonlocal_block<T>(pb, ik, cpk, X + (int64_t)ik * kstride, ld, HX + (int64_t)ik * kstride, ld, nullptr);
+  }
+  pb->napply += ncols;
+  if (sizeof(T) == 4) pb->napply32 += ncols;
+}
+template void apply_H_padded<double>(eahp_problem*, int, const int*, const int*, int, const z64*, z64*, int64_t,
+                                     int64_t);
+template void apply_H_padded<float>(eahp_problem*, int, const int*, const int*, int, const c32*, c32*, int64_t,
+                                    int64_t);
+
 // -------------------------------------------------------------------- point evaluation
 // Everything the method needs at a point Psi (orthonormal frame):
 // density, V_eff, energy terms, H Psi, Lambda (Hermitised) and R = H Psi - Psi Lambda.

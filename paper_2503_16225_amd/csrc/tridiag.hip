@@ -18,11 +18,17 @@
 #include <mutex>
 
 #include "devcommon.h"
+#include "exchange.h"
 #include "kernels.h"
+#include "ops.h"
 
 namespace cg = cooperative_groups;
 
 namespace eahp {
+
+using xch::kEmpty;
+using xch::poll_z;
+using xch::put_z;
 
 // Householder tridiagonalisation.  Column k: x = A[k+1:, k] (length m),
 // alpha = -(x0/|x0|) ||x||, v = x - alpha e1, H = I - beta v v^H with
@@ -181,17 +187,31 @@ __global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, do
         const z64 wj = w[j], vj = v[j];
         z64* col = A + (k + 1) + (int64_t)c * lda;
         double sx = 0, sy = 0;
-        for (int r = lane; r < m; r += 64) {
-          const z64 vr = v[r], wr = w[r];
-          const double ux = vr.x * wj.x + vr.y * wj.y + wr.x * vj.x + wr.y * vj.y;
-          const double uy = vr.y * wj.x - vr.x * wj.y + wr.y * vj.x - wr.x * vj.y;
-          const z64 a0 = col[r];
-          const z64 a = mk<double>(a0.x - ux, a0.y - uy);
-          col[r] = a;
-          if (r >= 1) {
-            const z64 x = vn[r - 1];
-            sx += a.x * x.x + a.y * x.y;
-            sy += a.x * x.y - a.y * x.x;
+        // rows in batches of 8 per lane: the loads of a batch are issued
+        // together, so their latency is paid once per batch, not per row
+        constexpr int RB = 8;
+        for (int r0 = lane; r0 < m; r0 += 64 * RB) {
+          z64 a0[RB];
+#pragma unroll
+          for (int u = 0; u < RB; ++u) {
+            const int r = r0 + 64 * u;
+            a0[u] = r < m ? col[r] : mk<double>(0.0, 0.0);
+          }
+#pragma unroll
+          for (int u = 0; u < RB; ++u) {
+            const int r = r0 + 64 * u;
+            if (r < m) {
+              const z64 vr = v[r], wr = w[r];
+              const double ux = vr.x * wj.x + vr.y * wj.y + wr.x * vj.x + wr.y * vj.y;
+              const double uy = vr.y * wj.x - vr.x * wj.y + wr.y * vj.x - wr.x * vj.y;
+              const z64 a = mk<double>(a0[u].x - ux, a0[u].y - uy);
+              col[r] = a;
+              if (r >= 1) {
+                const z64 x = vn[r - 1];
+                sx += a.x * x.x + a.y * x.y;
+                sy += a.x * x.y - a.y * x.x;
+              }
+            }
           }
         }
         sx = warp_sum(sx);
@@ -218,7 +238,6 @@ __global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, do
 namespace {
 constexpr int kTrWaves = 8;  // waves per work-group
 constexpr int kTrCols = 2;   // columns per wave
-constexpr int kTrSpin = 1 << 20;
 
 // Row r (wave-uniform) of a register-distributed vector, in every lane.  The
 // lane read happens inside the branch of the matching slot, so that no slot
@@ -252,37 +271,6 @@ template <int NS> __device__ __forceinline__ void reflector_reg(z64 (&x)[NS], in
     if (lane + 64 * s == r0) x[s] = v0;
 }
 
-// Exchange slots: every value that one wave hands to others has a slot of
-// its own (per step), filled beforehand with a signalling-NaN pattern that no
-// arithmetic produces.  Producers store with device-scope atomic stores, and
-// consumers poll the slot with device-scope atomic loads until the pattern is
-// gone, so no barrier is needed.  Waits are bounded; a timeout is reported.
-constexpr unsigned long long kEmpty = 0x7FF4A5A5A5A5A5A5ull;
-
-__device__ __forceinline__ void put_z(z64* p, z64 v) {
-  unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
-  unsigned long long x = (unsigned long long)__double_as_longlong(v.x);
-  unsigned long long y = (unsigned long long)__double_as_longlong(v.y);
-  if (x == kEmpty) x = 0x7FF8000000000000ull;
-  if (y == kEmpty) y = 0x7FF8000000000000ull;
-  __hip_atomic_store(u, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(u + 1, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ z64 poll_z(const z64* p, bool& ok) {
-  const unsigned long long* u = reinterpret_cast<const unsigned long long*>(p);
-  unsigned long long x = kEmpty, y = kEmpty;
-  for (int spins = 0;; ++spins) {
-    x = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    y = __hip_atomic_load(u + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (x != kEmpty && y != kEmpty) break;
-    if (spins > kTrSpin) {
-      ok = false;
-      break;
-    }
-  }
-  return mk<double>(__longlong_as_double((long long)x), __longlong_as_double((long long)y));
-}
 }  // namespace
 
 template <int NS>
@@ -718,64 +706,77 @@ void tridiag_reduce(hipStream_t st, int q, z64* A, int64_t lda, double* dd, z64*
   int qq = q;
   int64_t la = lda, lv = q;
   void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P, &vb};
+  // algorithmic bytes: every step reads and writes the live trailing columns
+  // (rows k+1.., columns k+2..) once, 32 bytes per complex entry
+  double bytes = 0;
+  for (int64_t k = 0; k + 2 < q; ++k) bytes += 32.0 * (double)(q - k - 1) * (double)(q - k - 2);
+  gemm_prof_begin(st, kProfTridiag);
   HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(Gl), dim3(1024), args, lds, st));
+  gemm_prof_end(st, kProfTridiag, bytes);
   HIPCK(hipStreamSynchronize(st));
 }
 
-// Compact WY form of a block of nb consecutive reflectors: P = H_k0 ... H_k0+nb-1
-// = I - V T V^H with T upper triangular, T_jj = beta_j and
-// T[0:j, j] = -beta_j T[0:j, 0:j] (V[:, 0:j]^H v_j), from G = V^H V.  One
-// work-group per block (blockIdx.x); writes T^H into TH as well.
-__global__ void __launch_bounds__(256) k_wy_t(int q, int nb, const z64* __restrict__ Gb, const double* __restrict__ beta,
-                                               z64* Tb, z64* THb) {
-  __shared__ z64 Ts[64 * 64];
-  __shared__ z64 gcol[64];
-  const int blk = blockIdx.x, k0 = blk * nb, t = threadIdx.x;
-  const int nbk = min(nb, q - 1 - k0);  // reflectors 0..q-2
-  const z64* G = Gb + (int64_t)blk * nb * nb;
-  for (int e = t; e < nb * nb; e += blockDim.x) Ts[e] = mk<double>(0.0, 0.0);
-  __syncthreads();
-  for (int j = 0; j < nbk; ++j) {
-    const double bj = beta[k0 + j];
-    if (t < j) gcol[t] = G[t + (int64_t)j * nb];
-    __syncthreads();
-    if (t < j) {
-      // row t of T[0:j, 0:j] times gcol (T upper: columns c >= t)
-      z64 acc = mk<double>(0.0, 0.0);
-      for (int c = t; c < j; ++c) acc = cadd<double>(acc, cmul<double>(Ts[t + c * nb], gcol[c]));
-      Ts[t + j * nb] = mk<double>(-bj * acc.x, -bj * acc.y);
-    }
-    if (t == 0) Ts[j + j * nb] = mk<double>(bj, 0.0);
-    __syncthreads();
+// Blocks of nb consecutive reflectors P = H_k0 ... H_k0+nb-1 = I - V T V^H
+// (compact WY form).  T is not formed: T^-1 = diag(1/beta) + (the strictly
+// upper part of G = V^H V), so T Z and T^H Z are triangular solves with G.
+// k_wy_trsm solves, for every column z of Z (nbk x ncols, ld ldz) in place,
+// (diag(1/beta) + strictly lower G) z2 = z (forward: the factor T^H of P^H)
+// or (diag(1/beta) + strictly upper G) z2 = z (backward: T of P); one wave
+// per column, entry j in lane j % 64, slot j / 64 (nbk <= 256).
+__global__ void __launch_bounds__(256) k_wy_trsm(int nbk, int nb, const z64* __restrict__ G,
+                                                 const double* __restrict__ beta, z64* Z, int64_t ldz, int ncols,
+                                                 int forward) {
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (col >= ncols) return;
+  z64* zc = Z + (int64_t)col * ldz;
+  z64 z[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = lane + 64 * u;
+    z[u] = j < nbk ? zc[j] : mk<double>(0.0, 0.0);
   }
-  z64* T = Tb + (int64_t)blk * nb * nb;
-  z64* TH = THb + (int64_t)blk * nb * nb;
-  for (int e = t; e < nb * nb; e += blockDim.x) {
-    const int r = e % nb, c = e / nb;
-    T[e] = Ts[e];
-    const z64 x = Ts[c + r * nb];
-    TH[e] = mk<double>(x.x, -x.y);
+  for (int t = 0; t < nbk; ++t) {
+    const int i = forward ? t : nbk - 1 - t;
+    // column i of G (the entries the other unknowns need)
+    z64 gc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = lane + 64 * u;
+      gc[u] = j < nbk ? G[j + (int64_t)i * nb] : mk<double>(0.0, 0.0);
+    }
+    z64 zi = pick_row<4>(z, i);
+    const double bi = beta[i];
+    zi = mk<double>(bi * zi.x, bi * zi.y);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = lane + 64 * u;
+      if (j == i) z[u] = zi;
+      else if (forward ? j > i : j < i) z[u] = csub<double>(z[u], cmul<double>(gc[u], zi));
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = lane + 64 * u;
+    if (j < nbk) zc[j] = z[u];
   }
 }
 
 namespace {
-constexpr int kWyNb = 64;
+constexpr int kWyNb = 256;
 size_t wy_scratch(int q, int ncols) {
   const int nblk = (q - 1 + kWyNb - 1) / kWyNb;
-  return sizeof(z64) * ((size_t)3 * nblk * kWyNb * kWyNb + (size_t)2 * kWyNb * ncols) + 512;
+  return sizeof(z64) * ((size_t)nblk * kWyNb * kWyNb + (size_t)kWyNb * ncols) + 512;
 }
 
-// Y <- Q^H Y or Q Y through the compact WY form of blocks of kWyNb reflectors:
-// every block is two products with the reflectors and one with T (MFMA).  Vh
-// must be zero above each reflector (rows <= k of column k).
+// Y <- Q^H Y or Q Y through blocks of kWyNb reflectors: per block two
+// products with the reflectors (MFMA) and a triangular solve with its Gram
+// matrix.  Vh must be zero above each reflector (rows <= k of column k).
 void apply_refl_wy(hipStream_t st, int q, int ncols, const z64* Vh, const double* beta, z64* Y, int64_t ldy,
                    int forward, void* scr, DevMem& part) {
   const int nb = kWyNb, nblk = (q - 1 + nb - 1) / nb;
   z64* G = static_cast<z64*>(scr);
-  z64* T = G + (size_t)nblk * nb * nb;
-  z64* TH = T + (size_t)nblk * nb * nb;
-  z64* Z = TH + (size_t)nblk * nb * nb;
-  z64* Z2 = Z + (size_t)nb * ncols;
+  z64* Z = G + (size_t)nblk * nb * nb;
   // G_b = V_b^H V_b: the full blocks at once, then the narrower last one
   const int nfull = (q - 1) / nb, last = (q - 1) - nfull * nb;
   if (nfull > 0)
@@ -784,8 +785,6 @@ void apply_refl_wy(hipStream_t st, int q, int ncols, const z64* Vh, const double
   if (last > 0)
     gemm_hn<double>(st, q, last, last, Vh + (int64_t)nfull * nb * q, q, Vh + (int64_t)nfull * nb * q, q,
                     G + (int64_t)nfull * nb * nb, nb, 1.0, 0.0, part);
-  hipLaunchKernelGGL(k_wy_t, dim3(nblk), dim3(256), 0, st, q, nb, G, beta, T, TH);
-  HIPCK(hipGetLastError());
   for (int i = 0; i < nblk; ++i) {
     const int blk = forward ? i : nblk - 1 - i;
     const int k0 = blk * nb, nbk = std::min(nb, q - 1 - k0);
@@ -793,10 +792,11 @@ void apply_refl_wy(hipStream_t st, int q, int ncols, const z64* Vh, const double
     const z64* Vb = Vh + (int64_t)k0 * q + r0;
     // Z = V_b^H Y, Z2 = T^H Z (forward) or T Z, Y -= V_b Z2
     gemm_hn<double>(st, rows, nbk, ncols, Vb, q, Y + r0, ldy, Z, nbk, 1.0, 0.0, part);
-    gemm_nn<double>(st, nbk, nbk, ncols, (forward ? TH : T) + (int64_t)blk * nb * nb, nb, Z, nbk, 0, Z2, nbk, 1.0,
-                    0.0, 0.0);
-    gemm_nn<double>(st, rows, nbk, ncols, Vb, q, Z2, nbk, 0, Y + r0, ldy, -1.0, 0.0, 1.0);
+    hipLaunchKernelGGL(k_wy_trsm, dim3((ncols + 3) / 4), dim3(256), 0, st, nbk, nb, G + (int64_t)blk * nb * nb,
+                       beta + k0, Z, (int64_t)nbk, ncols, forward);
+    gemm_nn<double>(st, rows, nbk, ncols, Vb, q, Z, nbk, 0, Y + r0, ldy, -1.0, 0.0, 1.0);
   }
+  HIPCK(hipGetLastError());
 }
 }  // namespace
 

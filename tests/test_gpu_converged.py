@@ -7,7 +7,10 @@ the tolerance of the convergence experiments).
   to 1e-7 relative and the occupied subspaces to a principal angle of 1e-5
   (Davis-Kahan: sin(angle) <= ||R|| / gap, with a gap of about 0.1 Ha);
 * the 8-atom cell on the unreduced 4x4x4 k-grid (Ecut 15 Ha, 64 k-points),
-  mixed precision, to ||R||_F <= 1e-6.
+  mixed precision, to ||R||_F <= 1e-6;
+* the 216-atom supercell (+2 % strain, Ecut 15 Ha, 86119 plane waves, 120^3,
+  p = 432), mixed precision, to ||R||_F <= 1e-6 (the oracle's density, energy
+  and residual of the returned frame take a minute or two on the host).
 """
 import numpy as np
 import pytest
@@ -34,9 +37,23 @@ def _solve(B, sysd, prec, tol, seed=1, maxit=300):
     return st, out
 
 
-def _oracle_check(om, Phi, st, tol):
-    from oracle import manifold as mf
-    so = mf.state(om, Phi)
+def _oracle_state(om, Phi, chunk=None):
+    """The oracle's energy, Lambda and residual at Phi (H Phi taken `chunk`
+    columns at a time when given, which bounds the host memory)."""
+    from oracle import hamiltonian as ham, manifold as mf
+    if chunk is None:
+        return mf.state(om, Phi)
+    rho = ham.density(om, Phi, chunk=chunk)
+    terms, _, Veff = ham.energy_terms(om, Phi, rho)
+    HPhi = np.concatenate([np.concatenate([ham.apply_H_k(om, ik, Veff, Pk[:, c:c + chunk])
+                                           for c in range(0, Pk.shape[1], chunk)], axis=1)
+                           for ik, Pk in enumerate(om.blocks(Phi))], axis=0)
+    lams, R = mf.lam_residual(om, Phi, HPhi)
+    return dict(E=terms["total"], lams=lams, R=R)
+
+
+def _oracle_check(om, Phi, st, tol, chunk=None):
+    so = _oracle_state(om, Phi, chunk)
     rn = float(np.linalg.norm(so["R"]))
     print("  oracle E", so["E"], "||R||", rn, "| library E", st["energy"], "||R||", st["rnorm"], flush=True)
     assert abs(so["E"] - st["energy"]) <= 1e-10 * abs(so["E"])
@@ -81,3 +98,15 @@ def test_k444_mixed_converges():
     print("k444 mixed", st["iters"], st["energy"], st["rnorm"], "%.2f s" % st["seconds"], "napply", st["napply"],
           flush=True)
     _oracle_check(om, P, st, tol)
+
+
+def test_si216_mixed_converges():
+    B = _lib()
+    from oracle import hamiltonian as ham
+    sysd = W.config("si216_gamma_e15")
+    tol = 1e-6
+    st, P = _solve(B, sysd, B.EAHP_MIXED, tol, maxit=200)
+    print("si216 mixed", st["iters"], st["energy"], st["rnorm"], "%.2f s" % st["seconds"], "napply", st["napply"],
+          "fp32", st["napply_fp32"], flush=True)
+    om = ham.Model(sysd, workers=16)
+    _oracle_check(om, P, st, tol, chunk=16)
