@@ -23,7 +23,12 @@ from the same start ("compare").
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
                        [--precision mixed|fp64] [--no-compare]
-                       [--serving-sample N] [--no-cpu-baseline]
+                       [--serving-sample N] [--no-cpu-baseline] [--no-autotune]
+
+Launch configurations with several valid choices (the work-group count of
+the multi-work-group Householder reduction) are tuned by libeahp's autotuner
+the first time each shape class occurs, which happens in the untimed
+preparation; the choices are reported under "autotune".
 """
 from __future__ import annotations
 
@@ -172,6 +177,7 @@ def measure(args, precision):
         note("warmup", i + 1, args.warmup)
     n0, n32 = st.napply, st.napply_fp32
     rn_start = st.rnorm
+    tuned_before = B.autotune_report()
     _check(lib.eahp_prof_enable(pb.ctx, 1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -182,6 +188,9 @@ def measure(args, precision):
               f"(fp32 {st.napply_fp32}) fom_iters={st.fom_iters} trials={st.ls_trials}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    tuned_in_timed = B.autotune_report() != tuned_before
+    if tuned_in_timed:
+        print(f"{tag}: a launch configuration was tuned inside the timed steps", file=sys.stderr, flush=True)
     kern = {}
     for kid, name in enumerate(KERNEL_NAMES):
         if name is None:
@@ -210,7 +219,7 @@ def measure(args, precision):
     return {"napply": napply, "napply_fp32": napply32, "elapsed": elapsed, "desc": desc,
             "value": napply / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
             "energy": st.energy, "rnorm_timed": [rn_start, rn_end], "prep_steps": prep, "prep_s": t_prep,
-            "ground_state_s": t_gs, "ground_state_iters": prep + it, "kernels": kern}
+            "ground_state_s": t_gs, "ground_state_iters": prep + it, "kernels": kern, "tuned_in_timed": tuned_in_timed}
 
 
 def serving_sample(args):
@@ -393,6 +402,8 @@ def main():
     ap.add_argument("--serving-sample", type=int, default=12,
                     help="requests of the serving stream solved for the p50/p99 latency (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="default launch configurations (no tuning of them in the untimed preparation)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--serving", type=int, default=0, help="run the serving stream with this many requests instead")
@@ -413,6 +424,9 @@ def main():
     import torch
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2503_16225_amd import binding as B
+
+    B.autotune_enable(not args.no_autotune)
     if args.serving > 0:
         serving(args)
         return
@@ -470,7 +484,8 @@ def main():
         "config": {"workload": head["desc"],
                    "precision": args.precision,
                    "napply": head["napply"], "napply_fp32": head["napply_fp32"],
-                   "rnorm_timed": head["rnorm_timed"], "prep_steps": head["prep_steps"]},
+                   "rnorm_timed": head["rnorm_timed"], "prep_steps": head["prep_steps"],
+                   "tuned_in_timed": head["tuned_in_timed"]},
         "ground_states_per_s": (1.0 / head["ground_state_s"]) if head["ground_state_s"] else None,
         "ground_state": {"tol_rnorm": args.gs_tol, "seconds": head["ground_state_s"],
                          "outer_iterations": head["ground_state_iters"], "prep_s": head["prep_s"]},
@@ -484,6 +499,7 @@ def main():
                           "energy_after_headline": head["energy"], "rnorm_timed": other["rnorm_timed"],
                           "ground_states_per_s": (1.0 / other["ground_state_s"]) if other["ground_state_s"] else None,
                           "ground_state_iters": other["ground_state_iters"]}
+    out["autotune"] = B.autotune_report().splitlines() if not args.no_autotune else None
     if args.serving_sample > 0:
         sv = serving_sample(args)
         out["p50_latency_s"] = sv["p50_latency_s"]

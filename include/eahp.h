@@ -270,6 +270,21 @@ void eahp_solver_destroy(eahp_solver* sv);
 int eahp_prof_enable(eahp_ctx* ctx, int on);
 int eahp_prof_read(eahp_ctx* ctx, int kernel, double* total_ms, int64_t* launches, double* bytes);
 
+/* Launch-configuration autotuner (process-wide).  Some kernels have several
+ * valid launch configurations with identical results and a speed that depends
+ * on the shape and the chip (the work-group count of the multi-work-group
+ * Householder reduction of the projected systems of Algorithm 4).  With
+ * enable(1), the first call of such a kernel in a shape class times every
+ * candidate on copies of its inputs (extra device allocations, the caller's
+ * stream synchronised) and keeps the fastest for the rest of the process;
+ * with enable(0) (the default) the default configuration is used and the
+ * kept choices are ignored.  report writes the table as text, one line per
+ * shape class ("dev<N> <kernel> <class>: choice <c> ms <t0> <t1> ..."), into
+ * buf (at most len bytes, NUL-terminated; buf may be NULL) and the size it
+ * needs, NUL included, into *needed (may be NULL).  Host-only calls. */
+int eahp_autotune_enable(int on);
+int eahp_autotune_report(char* buf, size_t len, size_t* needed);
+
 /* Layout of a system without touching the device: plane waves per k-point
  * (npw_per_k[nk], the row counts of the k-blocks of a frame), the FFT box and
  * an estimate of the device bytes one EARCG solve of it needs (frames, the

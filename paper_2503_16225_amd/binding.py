@@ -135,6 +135,10 @@ def load_library():
         "eahp_eigensolve": ([vp, vp, vp, C.c_double, C.c_int, dp, ip, dp], C.c_int),
         "eahp_symmetry_find": ([C.POINTER(SystemDesc), C.c_double, C.c_int, ip, dp, ip], C.c_int),
         "eahp_kpoints_reduce": ([C.c_int, ip, C.c_int, C.c_int, dp, dp, dp, dp, ip, ip], C.c_int),
+        "eahp_prof_enable": ([vp, C.c_int], C.c_int),
+        "eahp_prof_read": ([vp, C.c_int, dp, i64p, dp], C.c_int),
+        "eahp_autotune_enable": ([C.c_int], C.c_int),
+        "eahp_autotune_report": ([C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
         "eahp_strerror": ([C.c_int], C.c_char_p),
         "eahp_last_error": ([], C.c_char_p),
     }
@@ -265,6 +269,22 @@ def linesearch_host(evaluate, f0, df0, tau0, params):
         raise failed[0]
     _check(rc)
     return tau.value, trials.value
+
+
+def autotune_enable(on=True):
+    """Switch the launch-configuration autotuner of libeahp on or off (process-wide)."""
+    _check(load_library().eahp_autotune_enable(1 if on else 0))
+
+
+def autotune_report():
+    """The autotuner's table: one line per tuned shape class, the chosen
+    candidate and the measured milliseconds of every candidate."""
+    lib = load_library()
+    need = C.c_size_t()
+    _check(lib.eahp_autotune_report(None, 0, C.byref(need)))
+    buf = C.create_string_buffer(need.value)
+    _check(lib.eahp_autotune_report(buf, need.value, C.byref(need)))
+    return buf.value.decode()
 
 
 def layout_estimate(sysd):

@@ -163,8 +163,10 @@ void add_diag(hipStream_t st, int p, z64* M, int64_t ldm, int64_t sM, double v, 
 void set_identity(hipStream_t st, int p, z64* M, int64_t ldm);
 // (A - s_l I) y_l = c_l for all columns of Yt (q x p, ld q; overwritten by the
 // solutions) through one Householder tridiagonalisation of A (destroyed).
+// store32: for q > 512, the reduction keeps the trailing matrix in single
+// precision (the single-precision metric solve).
 void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws,
-                       DevMem& part);
+                       DevMem& part, bool store32 = false);
 // Householder reduction of a Hermitian A (q x q, ld lda; destroyed for q > 512)
 // to the Hermitian tridiagonal T = Q^H A Q, Q = H_0 ... H_{q-2}: dd (q reals,
 // the diagonal), e (q complex, e[k] = T[k+1][k]), the reflectors Vh (q x q,
@@ -174,6 +176,9 @@ size_t tridiag_scratch(int q);
 // held around every launch of a kernel whose work-groups wait on each other
 std::mutex& coop_mutex();
 void tridiag_reduce(hipStream_t st, int q, z64* A, int64_t lda, double* dd, z64* e, z64* Vh, double* beta, void* scr);
+// The same for q > 512 with A held in single precision (destroyed); every
+// step computes in FP64 and rounds the updated trailing entries to FP32.
+void tridiag_reduce(hipStream_t st, int q, c32* A, int64_t lda, double* dd, z64* e, z64* Vh, double* beta, void* scr);
 // Y <- Q^H Y (forward = 1) or Q Y (forward = 0) for the reflectors of tridiag_reduce;
 // for q > 512 with wy_scr and part given: blocked products (MFMA), where
 // wy_scr holds (ceil((q-1)/256) 256^2 + 256 ncols) complex values + 512 bytes

@@ -446,7 +446,8 @@ FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64*
   for (;;) {
     ++it;
     ldA = w.qcap;
-    // ---- projected Sylvester A_q Y - Y Sigma = C_q (FP64)
+    // ---- projected Sylvester A_q Y - Y Sigma = C_q (FP64; in single precision
+    // the reduction beyond q = 512 stores its trailing matrix in FP32)
     w.Ah.ensure(sizeof(z64) * q * q);
     w.T1.ensure(sizeof(cplx<T>) * q * p);
     w.T2.ensure(sizeof(z64) * q * p);
@@ -456,7 +457,7 @@ FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64*
     copy2d(st, q, q, w.A.template as<z64>(), ldA, w.Ah.template as<z64>(), q);
     gemm_nn<double>(st, q, p, p, w.Cj.template as<z64>(), ldA, w.U.template as<z64>(), p, 0, w.T2.template as<z64>(), q, 1.0, 0.0, 0.0);
     sylvester_tridiag(st, q, p, w.Ah.template as<z64>(), q, w.s.template as<double>(), w.T2.template as<z64>(), w.tri,
-                      pb->ws.gemm_part);
+                      pb->ws.gemm_part, sizeof(T) == 4);
     gemm_nn<double>(st, q, p, p, w.T2.template as<z64>(), q, w.U.template as<z64>(), p, 1, w.Y.template as<z64>(), q, 1.0, 0.0, 0.0);
     gemm_nn<double>(st, q, p, p, w.Y.template as<z64>(), q, w.Sig.template as<z64>(), p, 0, w.YS.template as<z64>(), q, 1.0, 0.0, 0.0);
     const cplx<T>* Ys;

@@ -3,6 +3,8 @@
 
 #include <array>
 #include <atomic>
+#include <functional>
+#include <string>
 
 #include "kernels.h"
 
@@ -24,6 +26,11 @@ extern thread_local std::string g_last_error;
 // enabled (eahp_prof_enable; one context at a time): slot kProfGemm + op
 // (0 A^H B, 1 A M) + 2 (FP32) + 4 (fewer than 1024 rows).
 extern std::atomic<eahp_ctx*> g_prof_ctx;
+// Autotuner (tune.hip): with tuning on, the first use of `key` runs every
+// candidate 0..ncand-1 through run(c) (warm-up + timed, on scratch data) and
+// keeps the fastest; with tuning off, candidate 0.
+bool autotune_on();
+int autotune(hipStream_t st, const std::string& key, int ncand, const std::function<void(int)>& run);
 // device address of this device's no-allocation scratch array (noalloc.hip)
 void noalloc_init(int device);
 void gemm_prof_begin(hipStream_t st, int slot);

@@ -42,11 +42,21 @@ using xch::put_z;
 // columns c >= k+2, and recomputes the updated column k+1 itself (nobody
 // writes column k+1 in step k), from which it forms the next reflector and
 // the next p entries of its own columns (double-buffered p).
-__device__ void tri_reflector(int m, const z64* x_in, z64* v, double* red, double* sc, z64& alpha, double& b) {
+//
+// The trailing matrix is stored as TA: complex128, or complex64 for the
+// single-precision metric solve (every step still computes in FP64 and rounds
+// the updated entries once, on the store).
+__device__ __forceinline__ z64 tr_ld(const z64& a) { return a; }
+__device__ __forceinline__ z64 tr_ld(const c32& a) { return mk<double>((double)a.x, (double)a.y); }
+__device__ __forceinline__ void tr_st(z64* p, z64 a) { *p = a; }
+__device__ __forceinline__ void tr_st(c32* p, z64 a) { *p = mk<float>((float)a.x, (float)a.y); }
+
+template <typename TA>
+__device__ void tri_reflector(int m, const TA* x_in, z64* v, double* red, double* sc, z64& alpha, double& b) {
   const int tid = threadIdx.x, nt = blockDim.x;
   double s2 = 0;
   for (int i = tid; i < m; i += nt) {
-    const z64 t = x_in ? x_in[i] : v[i];
+    const z64 t = x_in ? tr_ld(x_in[i]) : v[i];
     v[i] = t;
     s2 += t.x * t.x + t.y * t.y;
   }
@@ -66,32 +76,55 @@ __device__ void tri_reflector(int m, const z64* x_in, z64* v, double* red, doubl
   __syncthreads();
 }
 
-// p entries of the owned columns c >= c_first: P[c - (k+1)] = b * conj(A[k+1:, c]) . v
-// one wave per column, wave-level reduction
-__device__ void tri_matvec(int q, int k, int c_first, int G, const z64* A, int64_t lda, const z64* v, double b,
-                           z64* P) {
-  const int m = q - k - 1;
+// Work items of the trailing columns: column c of A belongs to work-group
+// c mod G in every step (so it stays in that work-group's L2), and the
+// work-group's waves split its columns into chunks of kTrChunk rows, one
+// (column, chunk) item per wave at a time.  Each item leaves the partial sum
+// of its rows of an entry of p in slot [chunk][entry]; the readers of p add
+// the chunks in chunk order, so p does not depend on G.
+constexpr int kTrRB = 8;               // rows per lane of one item
+constexpr int kTrChunk = 64 * kTrRB;   // rows of one item
+__host__ __device__ constexpr int tr_nch(int m) { return m > 0 ? (m + kTrChunk - 1) / kTrChunk : 1; }
+
+// p of step 0: slot [ch][c - 1] = b * (rows of chunk ch of A[1:, c])^H v, c >= 1
+template <typename TA>
+__device__ void tri_matvec0(int q, int G, const TA* A, int64_t lda, const z64* v, double b, z64* P) {
+  const int m = q - 1, nch = tr_nch(m);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int g = blockIdx.x;
-  const int c0 = c_first + ((g - c_first) % G + G) % G;
-  for (int c = c0 + wave * G; c < q; c += nw * G) {
-    const z64* col = A + (k + 1) + (int64_t)c * lda;
+  const int c0 = 1 + ((g - 1) % G + G) % G;
+  const int ncolg = c0 < q ? (q - 1 - c0) / G + 1 : 0;
+  for (int t = wave; t < ncolg * nch; t += nw) {
+    const int c = c0 + (t % ncolg) * G, ch = t / ncolg;
+    const TA* col = A + 1 + (int64_t)c * lda;
+    const int r0 = ch * kTrChunk + lane;
+    z64 a[kTrRB];
+#pragma unroll
+    for (int u = 0; u < kTrRB; ++u) {
+      const int r = r0 + 64 * u;
+      a[u] = r < m ? tr_ld(col[r]) : mk<double>(0.0, 0.0);
+    }
     double sx = 0, sy = 0;
-    for (int r = lane; r < m; r += 64) {
-      const z64 a = col[r], vr = v[r];
-      sx += a.x * vr.x + a.y * vr.y;
-      sy += a.x * vr.y - a.y * vr.x;
+#pragma unroll
+    for (int u = 0; u < kTrRB; ++u) {
+      const int r = r0 + 64 * u;
+      if (r < m) {
+        const z64 vr = v[r];
+        sx += a[u].x * vr.x + a[u].y * vr.y;
+        sy += a[u].x * vr.y - a[u].y * vr.x;
+      }
     }
     sx = warp_sum(sx);
     sy = warp_sum(sy);
-    if (lane == 0) P[c - (k + 1)] = mk<double>(b * sx, b * sy);
+    if (lane == 0) P[(int64_t)ch * q + (c - 1)] = mk<double>(b * sx, b * sy);
   }
 }
 
 // The work-group's vectors v, w and vn (3 q values) live in LDS, or, when
 // vbuf is not null (q too large for LDS), in the work-group's own 3 q slice of
 // vbuf in global memory.
-__global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, double* d, z64* e, z64* Vh,
+template <typename TA>
+__global__ void __launch_bounds__(1024) k_tridiag(int q, TA* A, int64_t lda, double* d, z64* e, z64* Vh,
                                                   int64_t ldv, double* beta, z64* Pbuf, z64* vbuf) {
   extern __shared__ unsigned char smem_raw[];
   z64* v = vbuf ? vbuf + (int64_t)3 * q * blockIdx.x : reinterpret_cast<z64*>(smem_raw);  // q
@@ -110,21 +143,40 @@ __global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, do
     for (int i = tid; i < q - 1; i += nt) Vh[1 + i] = v[i];
     if (tid == 0) Vh[0] = mk<double>(0.0, 0.0);
     if (tid == 0) {
-      d[0] = A[0].x;
+      d[0] = tr_ld(A[0]).x;
       e[0] = alpha;
       beta[0] = b;
     }
   }
-  tri_matvec(q, 0, 1, G, A, lda, v, b, Pbuf);
+  const int64_t pst = (int64_t)tr_nch(q - 1) * q;  // slots of one buffer of p partials
+  tri_matvec0(q, G, A, lda, v, b, Pbuf);
   grid.sync();
   for (int k = 0; k + 1 < q; ++k) {
     const int m = q - k - 1;
-    const z64* P = Pbuf + (int64_t)(k & 1) * q;
-    z64* Pn = Pbuf + (int64_t)((k + 1) & 1) * q;
+    const z64* P = Pbuf + (k & 1) * pst;
+    z64* Pn = Pbuf + ((k + 1) & 1) * pst;
+    // chunks of the partials of this step's p (written over m + 1 rows in
+    // step k - 1, over m rows by tri_matvec0)
+    const int nrd = tr_nch(k == 0 ? m : m + 1);
     // w = p - (beta/2)(v^H p) v
     double kx = 0;
     for (int i = tid; i < m; i += nt) {
-      const z64 pi = P[i];
+      // the first 8 chunks loaded together, added in chunk order
+      z64 t[8];
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch) t[ch] = ch < nrd ? P[(int64_t)ch * q + i] : mk<double>(0.0, 0.0);
+      z64 pi = t[0];
+#pragma unroll
+      for (int ch = 1; ch < 8; ++ch)
+        if (ch < nrd) {
+          pi.x += t[ch].x;
+          pi.y += t[ch].y;
+        }
+      for (int ch = 8; ch < nrd; ++ch) {
+        const z64 u = P[(int64_t)ch * q + i];
+        pi.x += u.x;
+        pi.y += u.y;
+      }
       w[i] = pi;
       kx += v[i].x * pi.x + v[i].y * pi.y;
     }
@@ -137,7 +189,7 @@ __global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, do
     if (m == 1) {
       // last step: only the 1 x 1 trailing block remains
       if (g == 0 && tid == 0) {
-        const z64 a = A[(k + 1) + (int64_t)(k + 1) * lda];
+        const z64 a = tr_ld(A[(k + 1) + (int64_t)(k + 1) * lda]);
         const double u = 2.0 * (v[0].x * w[0].x + v[0].y * w[0].y);
         d[k + 1] = a.x - u;
       }
@@ -147,26 +199,26 @@ __global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, do
     // column k+1 in step k): x = A[k+2:, k+1] - v w_0^* - w v_0^*
     const int m2 = m - 1;
     {
-      const z64* colk1 = A + (k + 2) + (int64_t)(k + 1) * lda;
+      const TA* colk1 = A + (k + 2) + (int64_t)(k + 1) * lda;
       const z64 w0 = w[0], v0 = v[0];
       for (int r = tid; r < m2; r += nt) {
         const z64 vr = v[r + 1], wr = w[r + 1];
         const double ux = vr.x * w0.x + vr.y * w0.y + wr.x * v0.x + wr.y * v0.y;
         const double uy = vr.y * w0.x - vr.x * w0.y + wr.y * v0.x - wr.x * v0.y;
-        const z64 a = colk1[r];
+        const z64 a = tr_ld(colk1[r]);
         vn[r] = mk<double>(a.x - ux, a.y - uy);
       }
     }
     double dk1 = 0;
     if (tid == 0) {
-      const z64 a = A[(k + 1) + (int64_t)(k + 1) * lda];
+      const z64 a = tr_ld(A[(k + 1) + (int64_t)(k + 1) * lda]);
       dk1 = a.x - 2.0 * (v[0].x * w[0].x + v[0].y * w[0].y);
     }
     __syncthreads();
     // next reflector from vn (in place), before the trailing update
     z64 an;
     double bn;
-    tri_reflector(m2, nullptr, vn, red, sc, an, bn);
+    tri_reflector<TA>(m2, nullptr, vn, red, sc, an, bn);
     if (g == 0) {
       for (int i = tid; i < m2; i += nt) Vh[(k + 2 + i) + (int64_t)(k + 1) * ldv] = vn[i];
       for (int i = tid; i < k + 2; i += nt) Vh[i + (int64_t)(k + 1) * ldv] = mk<double>(0.0, 0.0);
@@ -176,47 +228,47 @@ __global__ void __launch_bounds__(1024) k_tridiag(int q, z64* A, int64_t lda, do
         beta[k + 1] = bn;
       }
     }
-    // one pass over every owned column c >= k + 2 (a wave per column): the
-    // rank-2 update A -= v w^H + w v^H, stored back, and in the same pass the
-    // entry of p of step k+1, bn (A[k+2:, c])^H vn
+    // one pass over every owned item (column c >= k + 2, chunk of rows): the
+    // rank-2 update A -= v w^H + w v^H, stored back, and in the same pass
+    // the chunk's part of the entry of p of step k+1, bn (A[k+2:, c])^H vn
     {
       const int cf = k + 2;
       const int c0 = cf + ((g - cf) % G + G) % G;
-      for (int c = c0 + wave * G; c < q; c += nw * G) {
+      const int ncolg = c0 < q ? (q - 1 - c0) / G + 1 : 0;
+      const int nch = tr_nch(m);
+      for (int t = wave; t < ncolg * nch; t += nw) {
+        const int c = c0 + (t % ncolg) * G, ch = t / ncolg;
         const int j = c - (k + 1);
         const z64 wj = w[j], vj = v[j];
-        z64* col = A + (k + 1) + (int64_t)c * lda;
+        TA* col = A + (k + 1) + (int64_t)c * lda;
+        const int r0 = ch * kTrChunk + lane;
+        // the item's loads are issued together, so their latency is paid once
+        z64 a0[kTrRB];
+#pragma unroll
+        for (int u = 0; u < kTrRB; ++u) {
+          const int r = r0 + 64 * u;
+          a0[u] = r < m ? tr_ld(col[r]) : mk<double>(0.0, 0.0);
+        }
         double sx = 0, sy = 0;
-        // rows in batches of 8 per lane: the loads of a batch are issued
-        // together, so their latency is paid once per batch, not per row
-        constexpr int RB = 8;
-        for (int r0 = lane; r0 < m; r0 += 64 * RB) {
-          z64 a0[RB];
 #pragma unroll
-          for (int u = 0; u < RB; ++u) {
-            const int r = r0 + 64 * u;
-            a0[u] = r < m ? col[r] : mk<double>(0.0, 0.0);
-          }
-#pragma unroll
-          for (int u = 0; u < RB; ++u) {
-            const int r = r0 + 64 * u;
-            if (r < m) {
-              const z64 vr = v[r], wr = w[r];
-              const double ux = vr.x * wj.x + vr.y * wj.y + wr.x * vj.x + wr.y * vj.y;
-              const double uy = vr.y * wj.x - vr.x * wj.y + wr.y * vj.x - wr.x * vj.y;
-              const z64 a = mk<double>(a0[u].x - ux, a0[u].y - uy);
-              col[r] = a;
-              if (r >= 1) {
-                const z64 x = vn[r - 1];
-                sx += a.x * x.x + a.y * x.y;
-                sy += a.x * x.y - a.y * x.x;
-              }
+        for (int u = 0; u < kTrRB; ++u) {
+          const int r = r0 + 64 * u;
+          if (r < m) {
+            const z64 vr = v[r], wr = w[r];
+            const double ux = vr.x * wj.x + vr.y * wj.y + wr.x * vj.x + wr.y * vj.y;
+            const double uy = vr.y * wj.x - vr.x * wj.y + wr.y * vj.x - wr.x * vj.y;
+            const z64 a = mk<double>(a0[u].x - ux, a0[u].y - uy);
+            tr_st(col + r, a);
+            if (r >= 1) {
+              const z64 x = vn[r - 1];
+              sx += a.x * x.x + a.y * x.y;
+              sy += a.x * x.y - a.y * x.x;
             }
           }
         }
         sx = warp_sum(sx);
         sy = warp_sum(sy);
-        if (lane == 0) Pn[c - (k + 2)] = mk<double>(bn * sx, bn * sy);
+        if (lane == 0) Pn[(int64_t)ch * q + (c - (k + 2))] = mk<double>(bn * sx, bn * sy);
       }
     }
     __syncthreads();
@@ -651,13 +703,15 @@ void tridiag_reg_launch(hipStream_t st, int q, const z64* A, int64_t lda, double
 // Work-groups of the L2-resident reduction; its vectors stay in LDS up to
 // q = kTrLdsMax (3 q complex values per work-group).
 constexpr int kTrLdsMax = 3200;
-int tridiag_groups(int q) {
+// columns per work-group of the candidates of the autotuner (candidate 0:
+// one work-group per 32 columns, the default)
+constexpr int kTrCpw[] = {32, 16, 8, 64};
+constexpr int kTrNcand = 4;
+int tridiag_groups(int q, int cpw = 32) {
   int dev = 0, ncu = 0;
   HIPCK(hipGetDevice(&dev));
   HIPCK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  // one work-group per 32 columns: the grid barrier of every step costs
-  // more with more work-groups than their added bandwidth gains
-  return std::min(ncu, std::max(1, (q + 31) / 32));
+  return std::min(ncu, std::max(1, (q + cpw - 1) / cpw));
 }
 }  // namespace
 
@@ -672,10 +726,69 @@ std::mutex& coop_mutex() {
 size_t tridiag_scratch(int q) {
   if (q < 2) return 0;
   if (q <= 512) return sizeof(z64) * 2 * (size_t)q * q + 64;  // exchange slots, error flag
-  size_t b = sizeof(z64) * 2 * (size_t)q;  // double-buffered p
-  if (q > kTrLdsMax) b += sizeof(z64) * 3 * (size_t)q * tridiag_groups(q);
+  size_t b = sizeof(z64) * 2 * (size_t)tr_nch(q - 1) * q;  // double-buffered partials of p
+  int gmax = 1;
+  for (int c = 0; c < kTrNcand; ++c) gmax = std::max(gmax, tridiag_groups(q, kTrCpw[c]));
+  if (q > kTrLdsMax) b += sizeof(z64) * 3 * (size_t)q * gmax;
   return b;
 }
+
+namespace {
+// the multi-work-group reduction (q > 512); the caller holds coop_mutex()
+template <typename TA>
+void tridiag_l2(hipStream_t st, int q, TA* A, int64_t lda, double* dd, z64* e, z64* Vh, double* bt, void* scr) {
+  const bool gvec = q > kTrLdsMax;
+  z64* P = static_cast<z64*>(scr);
+  z64* vb = gvec ? P + 2 * (size_t)tr_nch(q - 1) * q : nullptr;
+  const size_t lds = gvec ? 0 : sizeof(z64) * 3 * (size_t)q;
+  const void* kern = (const void*)k_tridiag<TA>;
+  HIPCK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int per_cu = 0;
+  HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 1024, lds));
+  if (per_cu < 1) fail(EAHP_EDEVICE, "the tridiagonal reduction cannot be made resident");
+  // work-groups: the autotuner's choice for this size class, timed on a copy
+  // of A (the results do not depend on it: the row chunks of the columns and
+  // the order in which their partial sums are added are the same for every
+  // grid, and every work-group forms the same reflectors)
+  const int qb = (q + 511) / 512 * 512;
+  const std::string key = std::string(sizeof(TA) == 16 ? "k_tridiag<c128>" : "k_tridiag<c64>") + " q<=" +
+                          std::to_string(qb);
+  const int cand = autotune(st, key, kTrNcand, [&](int c) {
+    DevMem Ac, Vc, oc;
+    Ac.alloc(sizeof(TA) * (size_t)q * q);
+    Vc.alloc(sizeof(z64) * (size_t)q * q);
+    oc.alloc(sizeof(z64) * (3 + 2 * (size_t)tr_nch(q - 1)) * q +
+             sizeof(z64) * 3 * (size_t)q * tridiag_groups(q, kTrCpw[c]) + 256);
+    HIPCK(hipMemcpy2DAsync(Ac.p, sizeof(TA) * q, A, sizeof(TA) * lda, sizeof(TA) * q, q, hipMemcpyDeviceToDevice,
+                           st));
+    z64* o = oc.as<z64>();
+    double* d2 = reinterpret_cast<double*>(o);
+    z64* e2 = o + q;
+    double* b2 = reinterpret_cast<double*>(o + 2 * q);
+    z64* P2 = o + 3 * q;
+    z64* vb2 = gvec ? P2 + 2 * (size_t)tr_nch(q - 1) * q : nullptr;
+    int qq = q;
+    int64_t la = q, lv = q;
+    TA* Ap = Ac.as<TA>();
+    z64* Vp = Vc.as<z64>();
+    void* args[] = {&qq, &Ap, &la, &d2, &e2, &Vp, &lv, &b2, &P2, &vb2};
+    HIPCK(hipLaunchCooperativeKernel(kern, dim3(tridiag_groups(q, kTrCpw[c])), dim3(1024), args, lds, st));
+    HIPCK(hipStreamSynchronize(st));  // before the temporaries are freed
+  });
+  const int Gl = tridiag_groups(q, kTrCpw[cand]);
+  int qq = q;
+  int64_t la = lda, lv = q;
+  void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P, &vb};
+  // algorithmic bytes: every step reads and writes the live trailing columns
+  // (rows k+1.., columns k+2..) once
+  double bytes = 0;
+  for (int64_t k = 0; k + 2 < q; ++k) bytes += 2.0 * sizeof(TA) * (double)(q - k - 1) * (double)(q - k - 2);
+  gemm_prof_begin(st, kProfTridiag);
+  HIPCK(hipLaunchCooperativeKernel(kern, dim3(Gl), dim3(1024), args, lds, st));
+  gemm_prof_end(st, kProfTridiag, bytes);
+  HIPCK(hipStreamSynchronize(st));
+}
+}  // namespace
 
 void tridiag_reduce(hipStream_t st, int q, z64* A, int64_t lda, double* dd, z64* e, z64* Vh, double* bt, void* scr) {
   if (q <= 0) return;
@@ -694,26 +807,13 @@ void tridiag_reduce(hipStream_t st, int q, z64* A, int64_t lda, double* dd, z64*
     else tridiag_reg_launch<8>(st, q, A, lda, dd, e, Vh, bt, Pb, Cb, herr);
     return;
   }
-  const bool gvec = q > kTrLdsMax;
-  const int Gl = tridiag_groups(q);
-  z64* P = static_cast<z64*>(scr);
-  z64* vb = gvec ? P + 2 * (size_t)q : nullptr;
-  const size_t lds = gvec ? 0 : sizeof(z64) * 3 * (size_t)q;
-  HIPCK(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  int per_cu = 0;
-  HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tridiag, 1024, lds));
-  if (per_cu < 1) fail(EAHP_EDEVICE, "the tridiagonal reduction cannot be made resident");
-  int qq = q;
-  int64_t la = lda, lv = q;
-  void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &P, &vb};
-  // algorithmic bytes: every step reads and writes the live trailing columns
-  // (rows k+1.., columns k+2..) once, 32 bytes per complex entry
-  double bytes = 0;
-  for (int64_t k = 0; k + 2 < q; ++k) bytes += 32.0 * (double)(q - k - 1) * (double)(q - k - 2);
-  gemm_prof_begin(st, kProfTridiag);
-  HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag, dim3(Gl), dim3(1024), args, lds, st));
-  gemm_prof_end(st, kProfTridiag, bytes);
-  HIPCK(hipStreamSynchronize(st));
+  tridiag_l2<z64>(st, q, A, lda, dd, e, Vh, bt, scr);
+}
+
+void tridiag_reduce(hipStream_t st, int q, c32* A, int64_t lda, double* dd, z64* e, z64* Vh, double* bt, void* scr) {
+  if (q <= 512) fail(EAHP_EINVAL, "single-precision storage is for the reduction beyond q = 512");
+  std::lock_guard<std::mutex> lk(coop_mutex());
+  tridiag_l2<c32>(st, q, A, lda, dd, e, Vh, bt, scr);
 }
 
 // Blocks of nb consecutive reflectors P = H_k0 ... H_k0+nb-1 = I - V T V^H
@@ -821,14 +921,17 @@ void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* b
 // Y~ (q x p, ld q) := solution of (A - s_l) y~_l = C~[:, l]; A (q x q, ld lda)
 // may be destroyed.  ws grows to what the chosen kernels need.
 void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws,
-                       DevMem& part) {
+                       DevMem& part, bool store32) {
   if (q <= 0 || p <= 0) return;
   // Vh (q x q), W (3 q p), e (q), then d, beta (q each), then the scratch of
-  // the reduction, then that of the blocked reflector products
+  // the reduction, then that of the blocked reflector products, then (FP32
+  // storage) the single-precision copy of A
   const size_t base = sizeof(z64) * ((size_t)q * q + (size_t)3 * q * p + (size_t)q) + sizeof(double) * 2 * q + 64;
   const size_t tb = (tridiag_scratch(q) + 255) / 256 * 256;
   const bool wy = q > 512;
-  ws.ensure(base + 256 + tb + (wy ? wy_scratch(q, p) : 0));
+  const bool a32 = store32 && q > 512;
+  const size_t wb = wy ? (wy_scratch(q, p) + 255) / 256 * 256 : 0;
+  ws.ensure(base + 256 + tb + wb + (a32 ? sizeof(c32) * (size_t)q * q : 0));
   z64* Vh = ws.as<z64>();
   z64* W = Vh + (size_t)q * q;
   z64* e = W + (size_t)3 * q * p;
@@ -836,7 +939,13 @@ void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const 
   double* bt = dd + q;
   char* scr = reinterpret_cast<char*>(ws.p) + (base + 255) / 256 * 256;
   void* wscr = wy ? scr + tb : nullptr;
-  tridiag_reduce(st, q, A, lda, dd, e, Vh, bt, scr);
+  if (a32) {
+    c32* A32 = reinterpret_cast<c32*>(scr + tb + wb);
+    convert2d(st, q, q, A, lda, A32, q);
+    tridiag_reduce(st, q, A32, q, dd, e, Vh, bt, scr);
+  } else {
+    tridiag_reduce(st, q, A, lda, dd, e, Vh, bt, scr);
+  }
   apply_refl(st, q, p, Vh, bt, Yt, q, 1, wscr, &part);
   hipLaunchKernelGGL(k_trisolve_reg, dim3((p + 63) / 64), dim3(64), 0, st, q, p, dd, e, s, Yt, (int64_t)q, W);
   apply_refl(st, q, p, Vh, bt, Yt, q, 0, wscr, &part);

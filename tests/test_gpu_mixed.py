@@ -1,7 +1,8 @@
 """Mixed precision (EAHP_MIXED): the metric solve of Algorithm 4 runs in single
 precision (Krylov basis, its H-applies, TPA, orthogonalisation and the Gram
-products; the small projected Sylvester problem stays in FP64), everything
-else in FP64.
+products; the small projected Sylvester problem is solved in FP64, except that
+its Householder reduction beyond q = 512 stores the trailing matrix in FP32),
+everything else in FP64.
 
 Bars: a converged mixed solve matches the dense-SCF ground-state energy to
 1e-7 relative and the FP64 solve's orbital subspace to a 1e-5 principal angle;
