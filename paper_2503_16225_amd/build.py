@@ -15,7 +15,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libeahp.so")
 SOURCES = ["hamiltonian.hip", "blas.hip", "dense.hip", "tridiag.hip", "setup.hip", "problem.hip", "manifold.hip",
            "eig_dc.hip", "pchol.hip", "gemm_mfma.hip", "serve.hip", "symmetry.hip", "scf.hip", "capi.hip",
-           "noalloc.hip", "fom_batch.hip", "tune.hip"]
+           "noalloc.hip", "fom_batch.hip", "tune.hip", "band.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

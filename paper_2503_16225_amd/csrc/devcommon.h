@@ -233,6 +233,7 @@ __device__ __forceinline__ double wave_allsum(double v) {
 // Sixteen doubles held in registers; an element picked by a wave-uniform index
 // compiles to indexed register moves (no scratch, no select chains).
 typedef double d16 __attribute__((ext_vector_type(16)));
+typedef double d8 __attribute__((ext_vector_type(8)));
 
 template <int kCtrl> __device__ __forceinline__ int dpp_i32(int v) {
   return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xF, 0xF, true);

@@ -184,5 +184,16 @@ void tridiag_reduce(hipStream_t st, int q, c32* A, int64_t lda, double* dd, z64*
 // wy_scr holds (ceil((q-1)/256) 256^2 + 256 ncols) complex values + 512 bytes
 void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* beta, z64* Y, int64_t ldy, int forward,
                 void* wy_scr = nullptr, DevMem* part = nullptr);
+// Y <- Q^H Y (forward = 1) or Q Y for Q = H_0 ... H_{q-off-1}, reflector k
+// (column k of Vh, ld q, zero above row k + off) acting on rows k + off ..;
+// scr: refl_blocked_scratch(q - off, ncols) bytes.
+size_t refl_blocked_scratch(int nref, int ncols);
+void apply_refl_blocked(hipStream_t st, int q, int off, int ncols, const z64* Vh, const double* beta, z64* Y,
+                        int64_t ldy, int forward, void* scr, DevMem& part);
+// (A - s_l I) y_l = c_l for all columns of Yt (q x p, ld q; overwritten by the
+// solutions) through a reduction of A (destroyed) to Hermitian band form and
+// banded solves with partial pivoting (band.hip); q > 64.
+void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws,
+                    DevMem& part);
 
 }  // namespace eahp

@@ -862,23 +862,26 @@ __global__ void __launch_bounds__(256) k_wy_trsm(int nbk, int nb, const z64* __r
   }
 }
 
-namespace {
 constexpr int kWyNb = 256;
-size_t wy_scratch(int q, int ncols) {
-  const int nblk = (q - 1 + kWyNb - 1) / kWyNb;
+size_t refl_blocked_scratch(int nref, int ncols) {
+  const int nblk = (nref + kWyNb - 1) / kWyNb;
   return sizeof(z64) * ((size_t)nblk * kWyNb * kWyNb + (size_t)kWyNb * ncols) + 512;
 }
 
-// Y <- Q^H Y or Q Y through blocks of kWyNb reflectors: per block two
+// Y <- Q^H Y or Q Y for Q = H_0 H_1 ... H_{nref-1}, reflector k acting on rows
+// k + off .. q - 1 (off = 1: the tridiagonal reduction; off = the bandwidth:
+// the band reduction), through blocks of kWyNb reflectors: per block two
 // products with the reflectors (MFMA) and a triangular solve with its Gram
-// matrix.  Vh must be zero above each reflector (rows <= k of column k).
-void apply_refl_wy(hipStream_t st, int q, int ncols, const z64* Vh, const double* beta, z64* Y, int64_t ldy,
-                   int forward, void* scr, DevMem& part) {
-  const int nb = kWyNb, nblk = (q - 1 + nb - 1) / nb;
+// matrix.  Column k of Vh must be zero above row k + off.
+void apply_refl_blocked(hipStream_t st, int q, int off, int ncols, const z64* Vh, const double* beta, z64* Y,
+                        int64_t ldy, int forward, void* scr, DevMem& part) {
+  const int nref = q - off;
+  if (nref <= 0 || ncols <= 0) return;
+  const int nb = kWyNb, nblk = (nref + nb - 1) / nb;
   z64* G = static_cast<z64*>(scr);
   z64* Z = G + (size_t)nblk * nb * nb;
   // G_b = V_b^H V_b: the full blocks at once, then the narrower last one
-  const int nfull = (q - 1) / nb, last = (q - 1) - nfull * nb;
+  const int nfull = nref / nb, last = nref - nfull * nb;
   if (nfull > 0)
     gemm_hn<double>(st, q, nb, nb, Vh, q, Vh, q, G, nb, 1.0, 0.0, part, nfull, (int64_t)nb * q, (int64_t)nb * q,
                     (int64_t)nb * nb);
@@ -887,8 +890,8 @@ void apply_refl_wy(hipStream_t st, int q, int ncols, const z64* Vh, const double
                     G + (int64_t)nfull * nb * nb, nb, 1.0, 0.0, part);
   for (int i = 0; i < nblk; ++i) {
     const int blk = forward ? i : nblk - 1 - i;
-    const int k0 = blk * nb, nbk = std::min(nb, q - 1 - k0);
-    const int r0 = k0 + 1, rows = q - r0;  // the block's reflectors vanish above row k0 + 1
+    const int k0 = blk * nb, nbk = std::min(nb, nref - k0);
+    const int r0 = k0 + off, rows = q - r0;  // the block's reflectors vanish above row k0 + off
     const z64* Vb = Vh + (int64_t)k0 * q + r0;
     // Z = V_b^H Y, Z2 = T^H Z (forward) or T Z, Y -= V_b Z2
     gemm_hn<double>(st, rows, nbk, ncols, Vb, q, Y + r0, ldy, Z, nbk, 1.0, 0.0, part);
@@ -898,7 +901,6 @@ void apply_refl_wy(hipStream_t st, int q, int ncols, const z64* Vh, const double
   }
   HIPCK(hipGetLastError());
 }
-}  // namespace
 
 // Q^H Y (forward) or Q Y: a wave per column with the column in registers up to
 // q = 512, blocked (compact WY) products beyond
@@ -909,7 +911,7 @@ void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* b
   if (q <= 128) hipLaunchKernelGGL(k_apply_refl_reg<2>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
   else if (q <= 256) hipLaunchKernelGGL(k_apply_refl_reg<4>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
   else if (q <= 512) hipLaunchKernelGGL(k_apply_refl_reg<8>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
-  else if (wy_scr && part) apply_refl_wy(st, q, ncols, Vh, bt, Y, ldy, forward, wy_scr, *part);
+  else if (wy_scr && part) apply_refl_blocked(st, q, 1, ncols, Vh, bt, Y, ldy, forward, wy_scr, *part);
   else if (q <= 1024)
     hipLaunchKernelGGL(k_apply_refl_reg<16>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
   else if (q <= 1536)
@@ -923,6 +925,10 @@ void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* b
 void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws,
                        DevMem& part, bool store32) {
   if (q <= 0 || p <= 0) return;
+  if (q > 512) {
+    sylvester_band(st, q, p, A, lda, s, Yt, ws, part);
+    return;
+  }
   // Vh (q x q), W (3 q p), e (q), then d, beta (q each), then the scratch of
   // the reduction, then that of the blocked reflector products, then (FP32
   // storage) the single-precision copy of A
@@ -930,7 +936,7 @@ void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const 
   const size_t tb = (tridiag_scratch(q) + 255) / 256 * 256;
   const bool wy = q > 512;
   const bool a32 = store32 && q > 512;
-  const size_t wb = wy ? (wy_scratch(q, p) + 255) / 256 * 256 : 0;
+  const size_t wb = wy ? (refl_blocked_scratch(q - 1, p) + 255) / 256 * 256 : 0;
   ws.ensure(base + 256 + tb + wb + (a32 ? sizeof(c32) * (size_t)q * q : 0));
   z64* Vh = ws.as<z64>();
   z64* W = Vh + (size_t)q * q;

@@ -57,36 +57,36 @@ def test_fom_beyond_512_matches_oracle(p, qmin):
 
 
 def test_autotuned_reduction_identical():
-    """The autotuner's work-group count changes nothing in the result: every
-    column of the multi-work-group reduction is reduced by one wave whatever
-    the grid, so the tuned and the default launches agree bit for bit (the
-    call that tunes, and a later one that takes the kept choice)."""
+    """The autotuner's work-group count changes nothing in the result.  The
+    multi-work-group Householder reduction serves the eigendecompositions of
+    p x p matrices beyond p = 512 (here the Gram matrix of the polar
+    retraction at p = 600): every column of it is reduced by one wave
+    whatever the grid, so the tuned and the default launches agree bit for
+    bit (the call that tunes, and a later one that takes the kept choice)."""
     B = _lib()
-    from oracle import hamiltonian as ham
-    p = 64
-    sysd = W.system(*W.diamond_cell(), 10.0, (0, 0, 0), p=p)
-    om = ham.Model(sysd, workers=8)
-    Z = W.gaussian_block(1, om.npw, om.p)
     from oracle import manifold as mf
-    Phi0 = np.concatenate([mf.polar(b)[0] for b in om.blocks(Z)], axis=0)
-    Veff0, _ = ham.potentials(om, ham.density(om, Phi0))
-    _, V = np.linalg.eigh(ham.dense_H(om, 0, Veff0))
-    Phi = np.ascontiguousarray(V[:, :p]).astype(np.complex128)
+    p = 600
+    sysd = W.system(*W.diamond_cell(), 10.0, (32, 32, 32), p=p)
     gp = B.Problem(sysd)
-    Pd = gp.to_device(Phi)
+    Phi = mf.polar(W.gaussian_block(1, gp.npw, p))[0]
+    eta = W.gaussian_block(2, gp.npw, p)
+    M = Phi.conj().T @ eta
+    eta = eta - Phi @ (0.5 * (M + M.conj().T))
+    Pd, Ed = gp.to_device(Phi), gp.to_device(eta)
     try:
-        X0, its0, _ = gp.metric_solve(Pd, 0.01, 1e-10, 80)
+        X0 = gp.retract(Pd, Ed, 0.3)
         B.autotune_enable(True)
-        X1, its1, _ = gp.metric_solve(Pd, 0.01, 1e-10, 80)
-        X2, its2, _ = gp.metric_solve(Pd, 0.01, 1e-10, 80)
+        X1 = gp.retract(Pd, Ed, 0.3)
+        X2 = gp.retract(Pd, Ed, 0.3)
         rep = B.autotune_report()
+        Xh = gp.to_blocks(X0)
     finally:
         B.autotune_enable(False)
         gp.close()
     print(rep, flush=True)
     assert "k_tridiag" in rep
-    assert its0 == its1 == its2
     assert torch.equal(X0, X1) and torch.equal(X0, X2)
+    assert rel(Xh, mf.polar(Phi + 0.3 * eta)[0]) < 1e-10
 
 
 def test_mixed_fom_beyond_512_solves_to_tolerance():
