@@ -38,7 +38,7 @@ constexpr int kRw = 2 * kBw + 1;    // stored entries per row of B
 constexpr int kWs = kBw + 1;        // active rows of the banded elimination
 constexpr int kPanelRpt = 8;        // panel rows per thread (128 rows per work-group)
 constexpr int kPanelRows = 16 * kPanelRpt;
-constexpr size_t kUbufMax = size_t(3) << 30;  // bytes of eliminated rows held at once
+constexpr size_t kUbufMax = size_t(8) << 30;  // bytes of eliminated rows held at once
 }  // namespace
 
 __global__ void k_band_fill(unsigned long long* p, int64_t n, unsigned long long v) {
@@ -211,7 +211,11 @@ __global__ void k_band_rows(int q, const z64* __restrict__ A, int64_t lda, z64* 
 // k + kBw + 1, whose band spans columns k+1 .. k+2kBw+1) takes the freed
 // slot.  Column k is kept apart in LDS for the pivot search and the
 // multipliers; after the step, column k+1 moves there and its register slot
-// takes column k + 2kBw + 1 (zero in every row but the entering one).
+// takes column k + 2kBw + 1 (zero in every row but the entering one).  A
+// step has two barriers: every wave finds the pivot slot itself (the same
+// arg-max over the same values) and each thread forms the multipliers of its
+// own rows, while the pivot column, the right-hand sides and the row numbers
+// of the next step go to the other of two LDS buffers.
 // Eliminated rows go to Ubuf (row k: U[k][0] the pivot, U[k][1 + d] the entry
 // in column k + 1 + d) and the transformed right-hand side into y; the
 // triangular system U y = z is then solved backwards by one wave, its rows
@@ -221,20 +225,19 @@ __device__ __forceinline__ z64 zz() { return mk<double>(0.0, 0.0); }
 
 __global__ void __launch_bounds__(1024) k_band_gepp(int q, const z64* __restrict__ RB, const double* __restrict__ shift,
                                                     z64* __restrict__ Y, int64_t ldy, z64* __restrict__ Ubuf, int l0) {
-  __shared__ z64 pc[kWs];
-  __shared__ z64 rhs[kWs];
-  __shared__ int rid[kWs];
-  __shared__ z64 lm[kWs];
+  // column k of the active rows, their right-hand sides and row numbers, by
+  // slot; step k reads buffer k & 1 and writes the other
+  __shared__ z64 pcb[2][kWs];
+  __shared__ z64 rhsb[2][kWs];
+  __shared__ int ridb[2][kWs];
   __shared__ z64 urow[2 * kBw];
   __shared__ z64 ent[kRw + 1];  // the entering row (d = 0..2kBw) and its right-hand side
-  __shared__ int sp_s;
-  __shared__ z64 zk_s;
   __shared__ z64 ust[2][kGeppChunk][kRw + 1];  // backward solve: rows of U, then z
   const int l = l0 + blockIdx.x;
   const double sft = shift[l];
   z64* y = Y + (int64_t)l * ldy;
   z64* U = Ubuf + (int64_t)blockIdx.x * q * kRw;
-  const int t = threadIdx.x, cs = t & 127, rg = t >> 7;
+  const int t = threadIdx.x, cs = t & 127, rg = t >> 7, lane = t & 63;
   auto bval = [&](int r, int c) __attribute__((always_inline)) -> z64 {
     if (r >= q || c < 0 || c >= q || c < r - kBw || c > r + kBw) return zz();
     z64 v = RB[(int64_t)r * kRw + (c - r + kBw)];
@@ -266,50 +269,50 @@ __global__ void __launch_bounds__(1024) k_band_gepp(int q, const z64* __restrict
   }
   if (rg == 0) w64 = bval(kBw, c0);
   if (t < kWs) {
-    pc[t] = bval(t, 0);
-    rhs[t] = t < q ? y[t] : zz();
-    rid[t] = t < q ? t : -1;
+    pcb[0][t] = bval(t, 0);
+    rhsb[0][t] = t < q ? y[t] : zz();
+    ridb[0][t] = t < q ? t : -1;
   }
   // one elimination step; e holds the entering row of step k (loaded three
   // steps ahead) and takes that of step k + 3
   auto step = [&](int k, z64& e) __attribute__((always_inline)) {
-    // (A) the entering row into LDS; pivot search and multipliers (wave 0)
+    const z64* pc = pcb[k & 1];
+    const z64* rhs = rhsb[k & 1];
+    const int* rid = ridb[k & 1];
+    z64* pcn = pcb[(k & 1) ^ 1];
+    z64* rhsn = rhsb[(k & 1) ^ 1];
+    int* ridn = ridb[(k & 1) ^ 1];
+    // (A) the entering row into LDS; the pivot slot, found by every wave
+    // alike (the same reduction on the same values); the pivot row
     if (t <= kRw) ent[t] = e;
     e = fetch(k + 3);
-    if (t < 64) {
-      z64 pv = pc[t];
-      double v = rid[t] >= 0 ? pv.x * pv.x + pv.y * pv.y : -1.0;
-      int ix = t;
-      if (t == 0) {
+    int sp;
+    {
+      const z64 pv = pc[lane];
+      double v = rid[lane] >= 0 ? pv.x * pv.x + pv.y * pv.y : -1.0;
+      int ix = lane;
+      if (lane == 0) {
         const z64 p64 = pc[kBw];
         argmax_merge(v, ix, rid[kBw] >= 0 ? p64.x * p64.x + p64.y * p64.y : -1.0, kBw);
       }
       wave_argmax(v, ix);
-      const int sp = ix;
-      const z64 pp = pc[sp];
-      const double den = pp.x * pp.x + pp.y * pp.y;
-      const z64 inv = mk<double>(pp.x / den, -pp.y / den);
-      lm[t] = (t != sp && rid[t] >= 0) ? cmul<double>(pv, inv) : zz();
-      if (t == 0) {
-        lm[kBw] = (kBw != sp && rid[kBw] >= 0) ? cmul<double>(pc[kBw], inv) : zz();
-        sp_s = sp;
-        const z64 zk = rhs[sp];
-        zk_s = zk;
-        U[(int64_t)k * kRw] = pp;
-        y[k] = zk;
-      }
+      sp = ix;
     }
-    __syncthreads();
-    // (B) the pivot row
-    const int sp = sp_s;
-    if (rg == (sp & 7)) {
+    if (sp == kBw ? rg == 0 : rg == (sp & 7)) {
       const z64 v = sp == kBw ? w64 : mk<double>(wre[sp >> 3], wim[sp >> 3]);
       urow[cs] = v;
       U[(int64_t)k * kRw + 1 + ((cs - k - 1) & 127)] = v;
     }
+    const z64 pp = pc[sp];
+    if (t == 0) {
+      U[(int64_t)k * kRw] = pp;
+      y[k] = rhs[sp];
+    }
     __syncthreads();
-    // (C) elimination; column k+1 to LDS; the entering row into slot sp
-    const z64 zk = zk_s;
+    // (B) elimination, each thread forming the multipliers of its rows;
+    // column k+1 into the other buffer; the entering row into slot sp
+    const double den = pp.x * pp.x + pp.y * pp.y;
+    const z64 inv = mk<double>(pp.x / den, -pp.y / den);
     const int csn = (k + 1) & 127;
     const z64 u = urow[cs];
     const int dd = (cs - k - 1) & 127;
@@ -318,11 +321,12 @@ __global__ void __launch_bounds__(1024) k_band_gepp(int q, const z64* __restrict
       z64 val;
       if (rs == sp) {
         val = ev;
-        if (cs == csn) pc[rs] = ent[0];
+        if (cs == csn) pcn[rs] = ent[0];
       } else {
-        val = csub<double>(w, cmul<double>(lm[rs], u));
+        const z64 lr = cmul<double>(pc[rs], inv);
+        val = csub<double>(w, cmul<double>(lr, u));
         if (cs == csn) {
-          pc[rs] = val;
+          pcn[rs] = val;
           val = zz();
         }
       }
@@ -338,10 +342,12 @@ __global__ void __launch_bounds__(1024) k_band_gepp(int q, const z64* __restrict
     if (t < kWs) {
       if (t == sp) {
         const int re = k + kWs;
-        rhs[t] = ent[kRw];
-        rid[t] = re < q ? re : -1;
+        rhsn[t] = ent[kRw];
+        ridn[t] = re < q ? re : -1;
       } else {
-        rhs[t] = csub<double>(rhs[t], cmul<double>(lm[t], zk));
+        const z64 lt = cmul<double>(pc[t], inv);
+        rhsn[t] = csub<double>(rhs[t], cmul<double>(lt, rhs[sp]));
+        ridn[t] = rid[t];
       }
     }
     __syncthreads();
