@@ -54,20 +54,30 @@ __global__ void k_band_fill(unsigned long long* p, int64_t n, unsigned long long
 //   values), r_j = p_{i,j} (row i, held by work-group 0);
 //   alpha = -(x_i/|x_i|) ||x||, v = x - alpha e_i, beta = 2 / v^H v,
 //   w_j = beta v^H p_j = beta (D_j - conj(alpha) r_j), p_j -= v w_j.
+// The lanes m < i of the same sums give v_m^H v_i = conj(D_m) - alpha
+// conj(p_{i,m}) (column m holds v_m below its diagonal), the entries of
+// G = V^H V, from which work-group 0 forms the compact WY factor
+// H_0 ... H_{kBw-1} = I - V T V^H column by column:
+//   T_jj = beta_j,  T[0:j, j] = -beta_j T[0:j, 0:j] G[0:j, j].
 // Outputs: R (upper triangle) over the first rows of P, v_i (zero above row
 // i, v_i[i] = x_i - alpha) into columns 0..kBw-1 and 2kBw..3kBw-1 of V3 and
-// into Vh, beta_i.  A timed-out exchange sets err.
+// into Vh, beta_i, T (kBw x kBw).  A timed-out exchange sets err.
 template <int RPT>
 __global__ void __launch_bounds__(1024) k_band_panel(int m, z64* P, int64_t ldp, z64* V3, int64_t ldv3, z64* Vh,
-                                                     int64_t ldvh, double* beta, z64* part, z64* rowv, int* err) {
+                                                     int64_t ldvh, double* beta, z64* Tout, z64* part, z64* rowv,
+                                                     int* err) {
   __shared__ z64 red[16][64];
   __shared__ z64 red2[16][64];
   __shared__ z64 rsh[64];
   __shared__ z64 v0s[64];
   __shared__ double bsh[64];
+  __shared__ z64 tg[kBw * kBw];  // work-group 0: G (strictly upper part), then T in its place
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = blockIdx.x, G = gridDim.x;
   const int rbase = g * 16 * RPT + w;
+  if (g == 0)
+    for (int e = threadIdx.x; e < kBw * kBw; e += 1024) tg[e] = mk<double>(0.0, 0.0);
+  if (threadIdx.x < kBw) bsh[threadIdx.x] = 0.0;  // columns without a reflector keep beta = 0
   z64 a[RPT];
 #pragma unroll
   for (int s = 0; s < RPT; ++s) {
@@ -117,6 +127,11 @@ __global__ void __launch_bounds__(1024) k_band_panel(int m, z64* P, int64_t ldp,
     const double b = vv > 0 ? 2.0 / vv : 0.0;
     const z64 ca = cjmul<double>(alpha, rj);  // conj(alpha) r_j
     const z64 wj = mk<double>(b * (D.x - ca.x), b * (D.y - ca.y));
+    if (g == 0 && w == 0 && lane < i) {
+      // G[m][i] = v_m^H v_i = conj(D_m) - alpha conj(r_m), m = lane
+      const z64 ar = cmul<double>(alpha, mk<double>(rj.x, -rj.y));
+      tg[lane + kBw * i] = mk<double>(D.x - ar.x, -D.y - ar.y);
+    }
     if (lane > i) {
 #pragma unroll
       for (int s = 0; s < RPT; ++s) {
@@ -137,6 +152,26 @@ __global__ void __launch_bounds__(1024) k_band_panel(int m, z64* P, int64_t ldp,
   }
   __syncthreads();
   if (!ok) err[0] = 1;
+  if (g == 0) {
+    // T column by column, in place of G: lane l of wave pp adds the terms
+    // m = l + pp, l + pp + 16, ... of sum_m T[l][m] G[m][j]; the 16 partial
+    // sums are added in order
+    for (int j = 0; j < kBw; ++j) {
+      z64 acc = mk<double>(0.0, 0.0);
+      for (int mm = lane + w; mm < j; mm += 16) acc = cadd<double>(acc, cmul<double>(tg[lane + kBw * mm], tg[mm + kBw * j]));
+      red[w][lane] = acc;
+      __syncthreads();
+      if (w == 0) {
+        z64 tot = red[0][lane];
+        for (int ww = 1; ww < 16; ++ww) tot = cadd<double>(tot, red[ww][lane]);
+        const double bj = bsh[j];
+        tg[lane + kBw * j] = lane < j ? mk<double>(-bj * tot.x, -bj * tot.y)
+                                      : (lane == j ? mk<double>(bj, 0.0) : mk<double>(0.0, 0.0));
+      }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < kBw * kBw; e += 1024) Tout[e] = tg[e];
+  }
 #pragma unroll
   for (int s = 0; s < RPT; ++s) {
     const int r = rbase + 16 * s, j = lane;
@@ -148,34 +183,6 @@ __global__ void __launch_bounds__(1024) k_band_panel(int m, z64* P, int64_t ldp,
     Vh[r + (int64_t)j * ldvh] = vj;
   }
   if (g == 0 && threadIdx.x < kBw) beta[threadIdx.x] = (int)threadIdx.x < ns ? bsh[threadIdx.x] : 0.0;
-}
-
-// Compact WY factor of H = H_0 ... H_{nb-1} = I - V T V^H from G = V^H V
-// (nb x nb, ld nb) and beta: T^-1 = diag(1/beta) + (strictly upper part of G),
-// so column j of T is T_jj = beta_j, T_ij = -beta_i sum_{k=i+1..j} G_ik T_kj
-// (i < j), by back substitution; one thread per column.
-__global__ void __launch_bounds__(64) k_band_form_t(const z64* __restrict__ G, const double* __restrict__ beta,
-                                                    z64* __restrict__ T) {
-  __shared__ z64 Gs[kBw * kBw];
-  __shared__ z64 Ts[kBw * kBw];
-  const int j = threadIdx.x;
-  for (int e = j; e < kBw * kBw; e += 64) {
-    Gs[e] = G[e];
-    Ts[e] = mk<double>(0.0, 0.0);
-  }
-  __syncthreads();
-  Ts[j + kBw * j] = mk<double>(beta[j], 0.0);
-  for (int i = j - 1; i >= 0; --i) {
-    double sx = 0.0, sy = 0.0;
-    for (int k = i + 1; k <= j; ++k) {
-      const z64 gk = Gs[i + kBw * k], tk = Ts[k + kBw * j];
-      sx += gk.x * tk.x - gk.y * tk.y;
-      sy += gk.x * tk.y + gk.y * tk.x;
-    }
-    Ts[i + kBw * j] = mk<double>(-beta[i] * sx, -beta[i] * sy);
-  }
-  __syncthreads();
-  for (int e = j; e < kBw * kBw; e += 64) T[e] = Ts[e];
 }
 
 // Rows of the band matrix: RB[r * kRw + t] = B[r][r - kBw + t] (t = 0..2kBw),
@@ -200,176 +207,289 @@ __global__ void k_band_rows(int q, const z64* __restrict__ A, int64_t lda, z64* 
 
 // Banded solve with partial pivoting, (B - s I) y = c, one shift per
 // work-group (shift l0 + blockIdx.x, right-hand side and solution in column
-// l0 + blockIdx.x of Y).
+// l0 + blockIdx.x of Y), blocked by panels of kNb columns.
 //
-// Elimination step k picks the pivot among the kBw + 1 rows not yet
-// eliminated (all of column k's non-zeros lie in them); the pivot row has
-// its non-zeros in columns k .. k + 2kBw.  The active rows are held in
-// registers over columns k+1 .. k+2kBw: thread t keeps column slot t % 128
-// (column c in slot c % 128) of the row slots t / 128 + 8 i.  A row keeps its
-// slot until it becomes the pivot; the row that enters the window (row
-// k + kBw + 1, whose band spans columns k+1 .. k+2kBw+1) takes the freed
-// slot.  Column k is kept apart in LDS for the pivot search and the
-// multipliers; after the step, column k+1 moves there and its register slot
-// takes column k + 2kBw + 1 (zero in every row but the entering one).  A
-// step has two barriers: every wave finds the pivot slot itself (the same
-// arg-max over the same values) and each thread forms the multipliers of its
-// own rows, while the pivot column, the right-hand sides and the row numbers
-// of the next step go to the other of two LDS buffers.
+// Gaussian elimination with row pivoting picks the pivot of column k among
+// the rows not yet eliminated; a row r is zero left of column r - kBw, so the
+// pivot lies in rows k .. k + kBw and the pivot row has its non-zeros in
+// columns k .. k + 2kBw.  The rows that can take part in the panel of columns
+// k0 .. k0 + kNb - 1 are the kBw rows left over from earlier panels and the
+// kNb rows k0 + kBw .. k0 + kBw + kNb - 1; they sit in kWin row slots, and a
+// row keeps its slot until it becomes a pivot (its slot then takes a row of
+// the next panel).  Thread t holds column slot t % 128 of the row slots
+// t / 128 + 8 i in registers, over the columns right of the panel (column c
+// in slot c % 128); the panel's own columns are moved to LDS.  Per panel:
+//   * one wave factors the kWin x kNb panel (pivot search, multipliers
+//     L, the panel part of the pivot rows, the right-hand sides) and
+//     inverts the unit lower triangle L11 of the pivot rows' multipliers;
+//   * the pivot rows' parts right of the panel become U12 = L11^-1 A12;
+//   * every other row is updated with the rank-kNb product L21 U12.
 // Eliminated rows go to Ubuf (row k: U[k][0] the pivot, U[k][1 + d] the entry
 // in column k + 1 + d) and the transformed right-hand side into y; the
 // triangular system U y = z is then solved backwards by one wave, its rows
 // staged through LDS by the whole work-group.
-constexpr int kGeppChunk = 32;  // rows of U per LDS stage in the backward solve
+constexpr int kNb = 8;                                 // columns per panel
+constexpr int kWin = kBw + kNb;                        // row slots
+constexpr int kGt = 1024;                              // threads per work-group
+constexpr int kRpt = kWin / 8;                         // row slots per thread
+constexpr int kEnt = kRw + 1;                          // band of an entering row and its right-hand side
+constexpr int kEntN = kNb * kEnt;                      // staged values of a panel's entering rows
+constexpr int kEntPer = (kEntN + kGt - 1) / kGt;
+constexpr int kBsChunk = 8;                            // rows of U per LDS stage in the backward solve
 __device__ __forceinline__ z64 zz() { return mk<double>(0.0, 0.0); }
 
-__global__ void __launch_bounds__(1024) k_band_gepp(int q, const z64* __restrict__ RB, const double* __restrict__ shift,
-                                                    z64* __restrict__ Y, int64_t ldy, z64* __restrict__ Ubuf, int l0) {
-  // column k of the active rows, their right-hand sides and row numbers, by
-  // slot; step k reads buffer k & 1 and writes the other
-  __shared__ z64 pcb[2][kWs];
-  __shared__ z64 rhsb[2][kWs];
-  __shared__ int ridb[2][kWs];
-  __shared__ z64 urow[2 * kBw];
-  __shared__ z64 ent[kRw + 1];  // the entering row (d = 0..2kBw) and its right-hand side
-  __shared__ z64 ust[2][kGeppChunk][kRw + 1];  // backward solve: rows of U, then z
+__global__ void __launch_bounds__(kGt) k_band_gepp(int q, const z64* __restrict__ RB,
+                                                      const double* __restrict__ shift, z64* __restrict__ Y,
+                                                      int64_t ldy, z64* __restrict__ Ubuf, int l0) {
+  __shared__ z64 pnl[kWin][kNb + 1];  // the panel's columns of every slot; multipliers after the panel step
+  __shared__ z64 big[kEntN];          // entering rows, then A12 / U12 (kNb x 128)
+  __shared__ z64 ust[2][kBsChunk][kEnt];  // backward solve: rows of U and z
+  __shared__ z64 linv[kNb][kNb + 1];  // inverse of L11
+  __shared__ z64 rhs[kWin];
+  __shared__ int rid[kWin];  // row held by each slot (-1: none)
+  __shared__ int piv[kWin];  // panel column at which the slot's row became the pivot (-1: not yet)
+  __shared__ int inc[kWin];  // entering row taken by the slot in this panel (-1: none)
+  __shared__ int pj[kNb];    // slot of the pivot of each panel column
+  __shared__ int freel[kNb]; // slots freed by the last panel
+  __shared__ z64 wsave[kRpt][64];  // wave 0's window slots during the panel
   const int l = l0 + blockIdx.x;
   const double sft = shift[l];
   z64* y = Y + (int64_t)l * ldy;
   z64* U = Ubuf + (int64_t)blockIdx.x * q * kRw;
-  const int t = threadIdx.x, cs = t & 127, rg = t >> 7, lane = t & 63;
+  const int t = threadIdx.x, cs = t & 127, rg = t >> 7, lane = t & 63, wv = t >> 6;
   auto bval = [&](int r, int c) __attribute__((always_inline)) -> z64 {
     if (r >= q || c < 0 || c >= q || c < r - kBw || c > r + kBw) return zz();
     z64 v = RB[(int64_t)r * kRw + (c - r + kBw)];
     if (r == c) v.x -= sft;
     return v;
   };
-  // element d = t of the row entering at step kk (d = kRw: its right-hand side)
-  auto fetch = [&](int kk) __attribute__((always_inline)) -> z64 {
-    const int re = kk + kWs;
-    if (re >= q) return zz();
-    if (t == kRw) return y[re];
-    const int c = kk + 1 + t;
-    if (t > kRw || c >= q) return zz();
-    z64 v = RB[(int64_t)re * kRw + t];
-    if (t == kBw) v.x -= sft;
+  // value e of the rows entering the panel at k0: row i = e / kEnt, entry d
+  // (d < kRw: B - s I at column r - kBw + d; d = kRw: the right-hand side)
+  auto ent_val = [&](int k0, int e) __attribute__((always_inline)) -> z64 {
+    if (e >= kEntN) return zz();
+    const int i = e / kEnt, d = e - i * kEnt;
+    const int r = k0 + kBw + i;
+    if (r >= q) return zz();
+    if (d == kRw) return y[r];
+    if (r - kBw + d >= q) return zz();
+    z64 v = RB[(int64_t)r * kRw + d];
+    if (d == kBw) v.x -= sft;
     return v;
   };
-  // the thread's row slots rg + 8 i (i < 8), real and imaginary parts in two
-  // 8-wide vector registers (a slot chosen at run time is read by indexed
-  // register moves), and slot 64 (row group 0) in a register pair of its own
-  d8 wre, wim;
-  z64 w64 = zz();
-  const int c0 = cs == 0 ? 2 * kBw : cs;  // columns 1 .. 2kBw at step 0
+  z64 w[kRpt];  // row slots rg + 8 i, column slot cs
+  z64 pre[kEntPer];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const z64 v = bval(rg + 8 * i, c0);
-    wre[i] = v.x;
-    wim[i] = v.y;
+  for (int i = 0; i < kRpt; ++i) {
+    const int sl = rg + 8 * i;
+    w[i] = sl < kBw ? bval(sl, cs) : zz();  // rows 0..kBw-1, columns 0..127
   }
-  if (rg == 0) w64 = bval(kBw, c0);
-  if (t < kWs) {
-    pcb[0][t] = bval(t, 0);
-    rhsb[0][t] = t < q ? y[t] : zz();
-    ridb[0][t] = t < q ? t : -1;
+  if (t < kWin) {
+    rid[t] = (t < kBw && t < q) ? t : -1;
+    rhs[t] = (t < kBw && t < q) ? y[t] : zz();
   }
-  // one elimination step; e holds the entering row of step k (loaded three
-  // steps ahead) and takes that of step k + 3
-  auto step = [&](int k, z64& e) __attribute__((always_inline)) {
-    const z64* pc = pcb[k & 1];
-    const z64* rhs = rhsb[k & 1];
-    const int* rid = ridb[k & 1];
-    z64* pcn = pcb[(k & 1) ^ 1];
-    z64* rhsn = rhsb[(k & 1) ^ 1];
-    int* ridn = ridb[(k & 1) ^ 1];
-    // (A) the entering row into LDS; the pivot slot, found by every wave
-    // alike (the same reduction on the same values); the pivot row
-    if (t <= kRw) ent[t] = e;
-    e = fetch(k + 3);
-    int sp;
-    {
-      const z64 pv = pc[lane];
-      double v = rid[lane] >= 0 ? pv.x * pv.x + pv.y * pv.y : -1.0;
-      int ix = lane;
-      if (lane == 0) {
-        const z64 p64 = pc[kBw];
-        argmax_merge(v, ix, rid[kBw] >= 0 ? p64.x * p64.x + p64.y * p64.y : -1.0, kBw);
+  if (t < kNb) freel[t] = kBw + t;
+#pragma unroll
+  for (int u = 0; u < kEntPer; ++u) pre[u] = ent_val(0, t + kGt * u);
+  __syncthreads();
+  for (int k0 = 0; k0 < q; k0 += kNb) {
+    const int nsk = min(kNb, q - k0);
+    // (1) the entering rows into LDS (the next panel's are prefetched); the
+    // panel's columns to LDS, their register slots now hold columns
+    // k0 + 128 .. k0 + 143 (zero in every row left over)
+#pragma unroll
+    for (int u = 0; u < kEntPer; ++u) {
+      const int e = t + kGt * u;
+      if (e < kEntN) big[e] = pre[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kEntPer; ++u) pre[u] = ent_val(k0 + kNb, t + kGt * u);
+    const int jc = (cs - k0) & 127;
+    if (jc < kNb) {
+#pragma unroll
+      for (int i = 0; i < kRpt; ++i) {
+        pnl[rg + 8 * i][jc] = w[i];
+        w[i] = zz();
       }
-      wave_argmax(v, ix);
-      sp = ix;
     }
-    if (sp == kBw ? rg == 0 : rg == (sp & 7)) {
-      const z64 v = sp == kBw ? w64 : mk<double>(wre[sp >> 3], wim[sp >> 3]);
-      urow[cs] = v;
-      U[(int64_t)k * kRw + 1 + ((cs - k - 1) & 127)] = v;
-    }
-    const z64 pp = pc[sp];
-    if (t == 0) {
-      U[(int64_t)k * kRw] = pp;
-      y[k] = rhs[sp];
+    if (t < kWin) {
+      int ii = -1;
+      for (int i = 0; i < kNb; ++i)
+        if (freel[i] == t) ii = i;
+      inc[t] = ii;
+      piv[t] = -1;
     }
     __syncthreads();
-    // (B) elimination, each thread forming the multipliers of its rows;
-    // column k+1 into the other buffer; the entering row into slot sp
-    const double den = pp.x * pp.x + pp.y * pp.y;
-    const z64 inv = mk<double>(pp.x / den, -pp.y / den);
-    const int csn = (k + 1) & 127;
-    const z64 u = urow[cs];
-    const int dd = (cs - k - 1) & 127;
-    const z64 ev = ent[dd == 0 ? 2 * kBw : dd];
-    auto update = [&](int rs, z64 w) __attribute__((always_inline)) -> z64 {
-      z64 val;
-      if (rs == sp) {
-        val = ev;
-        if (cs == csn) pcn[rs] = ent[0];
-      } else {
-        const z64 lr = cmul<double>(pc[rs], inv);
-        val = csub<double>(w, cmul<double>(lr, u));
-        if (cs == csn) {
-          pcn[rs] = val;
-          val = zz();
+    // (2) the entering rows into the freed slots
+#pragma unroll
+    for (int i = 0; i < kRpt; ++i) {
+      const int sl = rg + 8 * i, ii = inc[sl];
+      if (ii >= 0) {
+        const int d = kNb + ((cs - k0 - kNb) & 127) - ii;  // column k0 + kNb + ((cs - k0 - kNb) mod 128)
+        w[i] = d <= 2 * kBw ? big[ii * kEnt + d] : zz();
+        if (cs < kNb) pnl[sl][cs] = cs >= ii ? big[ii * kEnt + cs - ii] : zz();
+      }
+    }
+    if (t < kWin && inc[t] >= 0) {
+      const int ii = inc[t], r = k0 + kBw + ii;
+      rhs[t] = big[ii * kEnt + kRw];
+      rid[t] = r < q ? r : -1;
+    }
+    __syncthreads();
+    // (3) the panel, by wave 0, in registers: lane j holds slots j and j + 64
+    // (j < kNb); the pivot row is broadcast from its lane.  Wave 0 parks its
+    // window slots in LDS meanwhile (the branch is uniform, so they take no
+    // registers inside it).
+    if (__builtin_amdgcn_readfirstlane(wv) == 0) {
+#pragma unroll
+      for (int i = 0; i < kRpt; ++i) wsave[i][lane] = w[i];
+      const int s0 = lane, s1 = lane + 64;
+      const bool has1 = lane < kWin - 64;
+      z64 r0[kNb], r1[kNb];
+#pragma unroll
+      for (int cc = 0; cc < kNb; ++cc) {
+        r0[cc] = pnl[s0][cc];
+        r1[cc] = has1 ? pnl[s1][cc] : zz();
+      }
+      bool act0 = rid[s0] >= 0, act1 = has1 && rid[s1] >= 0;
+      z64 h0 = rhs[s0], h1 = has1 ? rhs[s1] : zz();
+#pragma unroll
+      for (int j = 0; j < kNb; ++j) {
+        if (j < nsk) {
+          double v = act0 ? r0[j].x * r0[j].x + r0[j].y * r0[j].y : -1.0;
+          int ix = s0;
+          argmax_merge(v, ix, act1 ? r1[j].x * r1[j].x + r1[j].y * r1[j].y : -1.0, s1);
+          wave_argmax(v, ix);
+          const int p = ix, pl = p & 63;
+          const bool ph = p >= 64;
+          z64 prow[kNb];
+#pragma unroll
+          for (int cc = 0; cc < kNb; ++cc) {
+            if (cc >= j) {
+              const z64 src = ph ? r1[cc] : r0[cc];
+              prow[cc] = mk<double>(readlane_f64(src.x, pl), readlane_f64(src.y, pl));
+            }
+          }
+          const z64 hs = ph ? h1 : h0;
+          const z64 zp = mk<double>(readlane_f64(hs.x, pl), readlane_f64(hs.y, pl));
+          const double rd = 1.0 / (prow[j].x * prow[j].x + prow[j].y * prow[j].y);
+          const z64 inv = mk<double>(prow[j].x * rd, -prow[j].y * rd);
+          if (act0 && s0 != p) {
+            const z64 lr = cmul<double>(r0[j], inv);
+            r0[j] = lr;
+#pragma unroll
+            for (int cc = 0; cc < kNb; ++cc)
+              if (cc > j) r0[cc] = csub<double>(r0[cc], cmul<double>(lr, prow[cc]));
+            h0 = csub<double>(h0, cmul<double>(lr, zp));
+          }
+          if (act1 && s1 != p) {
+            const z64 lr = cmul<double>(r1[j], inv);
+            r1[j] = lr;
+#pragma unroll
+            for (int cc = 0; cc < kNb; ++cc)
+              if (cc > j) r1[cc] = csub<double>(r1[cc], cmul<double>(lr, prow[cc]));
+            h1 = csub<double>(h1, cmul<double>(lr, zp));
+          }
+          if (s0 == p) {
+            act0 = false;
+            piv[s0] = j;
+          }
+          if (s1 == p) {
+            act1 = false;
+            piv[s1] = j;
+          }
+          if (lane == 0) pj[j] = p;
         }
       }
-      return val;
-    };
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const z64 val = update(rg + 8 * i, mk<double>(wre[i], wim[i]));
-      wre[i] = val.x;
-      wim[i] = val.y;
-    }
-    if (rg == 0) w64 = update(kBw, w64);
-    if (t < kWs) {
-      if (t == sp) {
-        const int re = k + kWs;
-        rhsn[t] = ent[kRw];
-        ridn[t] = re < q ? re : -1;
-      } else {
-        const z64 lt = cmul<double>(pc[t], inv);
-        rhsn[t] = csub<double>(rhs[t], cmul<double>(lt, rhs[sp]));
-        ridn[t] = rid[t];
+      for (int cc = 0; cc < kNb; ++cc) {
+        pnl[s0][cc] = r0[cc];
+        if (has1) pnl[s1][cc] = r1[cc];
       }
+      rhs[s0] = h0;
+      if (has1) rhs[s1] = h1;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // L11^-1, column i by lane i: X[i][i] = 1, X[j][i] = -sum_{m=i..j-1} L[j][m] X[m][i]
+      if (lane < kNb) {
+        const int i = lane;
+        for (int j = 0; j < kNb; ++j) {
+          z64 x = zz();
+          if (j == i) x = mk<double>(1.0, 0.0);
+          else if (j > i && j < nsk) {
+            const int pr = pj[j];
+            for (int m = i; m < j; ++m) x = csub<double>(x, cmul<double>(pnl[pr][m], linv[m][i]));
+          }
+          linv[j][i] = x;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kRpt; ++i) w[i] = wsave[i][lane];
     }
     __syncthreads();
-  };
-  z64 e0 = fetch(0), e1 = fetch(1), e2 = fetch(2);
-  __syncthreads();
-  for (int k = 0; k < q; k += 3) {
-    step(k, e0);
-    if (k + 1 < q) step(k + 1, e1);
-    if (k + 2 < q) step(k + 2, e2);
+    // (4) the pivot rows right of the panel (A12) into LDS
+#pragma unroll
+    for (int i = 0; i < kRpt; ++i) {
+      const int jj = piv[rg + 8 * i];
+      if (jj >= 0) big[jj * 128 + cs] = w[i];
+    }
+    __syncthreads();
+    // (5) U12 = L11^-1 A12: thread (rg, cs) forms row rg
+    {
+      const int j = rg;
+      z64 acc = zz();
+#pragma unroll
+      for (int i = 0; i < kNb; ++i)
+        if (i <= j && j < nsk) acc = cadd<double>(acc, cmul<double>(linv[j][i], big[i * 128 + cs]));
+      __syncthreads();
+      big[j * 128 + cs] = acc;
+    }
+    __syncthreads();
+    // (6) rank-kNb update of the other rows; the pivot rows go to U, their
+    // right-hand sides to y, their slots to the next panel
+#pragma unroll
+    for (int i = 0; i < kRpt; ++i) {
+      const int sl = rg + 8 * i;
+      if (rid[sl] >= 0 && piv[sl] < 0) {
+        z64 acc = w[i];
+#pragma unroll
+        for (int jj = 0; jj < kNb; ++jj)
+          if (jj < nsk) acc = csub<double>(acc, cmul<double>(pnl[sl][jj], big[jj * 128 + cs]));
+        w[i] = acc;
+      }
+    }
+    for (int e = t; e < kNb * kRw; e += kGt) {
+      const int j = e / kRw, dd = e - j * kRw;
+      if (j < nsk) {
+        const int pr = pj[j], k = k0 + j;
+        z64 v;
+        if (dd == 0) v = pnl[pr][j];
+        else {
+          const int c = k + dd;
+          v = c < k0 + kNb ? pnl[pr][c - k0] : big[j * 128 + (c & 127)];
+        }
+        U[(int64_t)k * kRw + dd] = v;
+      }
+    }
+    if (t < nsk) {
+      y[k0 + t] = rhs[pj[t]];
+      freel[t] = pj[t];
+    }
+    __syncthreads();
   }
-  // ---- backward solve U y = z.  Chunks of kGeppChunk rows, from the last:
+  // ---- backward solve U y = z.  Chunks of kBsChunk rows, from the last:
   // every thread loads its share of the next chunk while wave 0 solves the
   // current one from LDS.  Lane j of wave 0 holds y[k+1+j] and y[k+65+j].
-  const int nch = (q + kGeppChunk - 1) / kGeppChunk;
-  constexpr int kPer = kGeppChunk * (kRw + 1);
+  const int nch = (q + kBsChunk - 1) / kBsChunk;
+  constexpr int kPer = kBsChunk * kEnt;
+  constexpr int kPerT = (kPer + kGt - 1) / kGt;
   auto stage_ld = [&](int ch, z64* vals) __attribute__((always_inline)) {
-    const int r0 = ch * kGeppChunk;
-    for (int e = t, u = 0; u < (kPer + 1023) / 1024; e += 1024, ++u) {
+    const int r0 = ch * kBsChunk;
+#pragma unroll
+    for (int u = 0; u < kPerT; ++u) {
+      const int e = t + kGt * u;
       z64 v = zz();
       if (e < kPer) {
-        const int rr = e / (kRw + 1), cc = e - rr * (kRw + 1);
+        const int rr = e / kEnt, cc = e - rr * kEnt;
         const int k = r0 + rr;
         if (k < q) v = cc < kRw ? U[(int64_t)k * kRw + cc] : y[k];
       }
@@ -377,10 +497,13 @@ __global__ void __launch_bounds__(1024) k_band_gepp(int q, const z64* __restrict
     }
   };
   auto stage_st = [&](int buf, const z64* vals) __attribute__((always_inline)) {
-    for (int e = t, u = 0; u < (kPer + 1023) / 1024; e += 1024, ++u)
+#pragma unroll
+    for (int u = 0; u < kPerT; ++u) {
+      const int e = t + kGt * u;
       if (e < kPer) (&ust[buf][0][0])[e] = vals[u];
+    }
   };
-  z64 sv[(kPer + 1023) / 1024];
+  z64 sv[kPerT];
   stage_ld(nch - 1, sv);
   stage_st((nch - 1) & 1, sv);
   __syncthreads();
@@ -388,8 +511,8 @@ __global__ void __launch_bounds__(1024) k_band_gepp(int q, const z64* __restrict
   for (int ch = nch - 1; ch >= 0; --ch) {
     if (ch > 0) stage_ld(ch - 1, sv);
     if (t < 64) {
-      const int r0 = ch * kGeppChunk;
-      const int rr_hi = min(kGeppChunk, q - r0) - 1;
+      const int r0 = ch * kBsChunk;
+      const int rr_hi = min(kBsChunk, q - r0) - 1;
       for (int rr = rr_hi; rr >= 0; --rr) {
         const z64* Ur = ust[ch & 1][rr];
         const z64 ua = Ur[1 + t], ub = Ur[1 + kBw + t], u0 = Ur[0], zk = Ur[kRw];
@@ -398,8 +521,8 @@ __global__ void __launch_bounds__(1024) k_band_gepp(int q, const z64* __restrict
         sx = wave_allsum(sx);
         sy = wave_allsum(sy);
         const double nx = zk.x - sx, ny = zk.y - sy;
-        const double den = u0.x * u0.x + u0.y * u0.y;
-        const z64 yk = mk<double>((nx * u0.x + ny * u0.y) / den, (ny * u0.x - nx * u0.y) / den);
+        const double rd = 1.0 / (u0.x * u0.x + u0.y * u0.y);
+        const z64 yk = mk<double>((nx * u0.x + ny * u0.y) * rd, (ny * u0.x - nx * u0.y) * rd);
         if (t == 0) y[r0 + rr] = yk;
         const double a63x = __shfl(ya.x, 63, 64), a63y = __shfl(ya.y, 63, 64);
         const double uax = __shfl_up(ya.x, 1, 64), uay = __shfl_up(ya.y, 1, 64);
@@ -429,7 +552,7 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   // shifts per elimination launch: the eliminated rows of each are kept
   const size_t ubytes_shift = sizeof(z64) * (size_t)q * kRw;
   const int nsh = (int)std::max<size_t>(1, std::min<size_t>((size_t)p, kUbufMax / ubytes_shift));
-  // workspace: Vh (q x q), beta (q), V3 (q x 3b), X (q x b), G, T, N, M (b x b),
+  // workspace: Vh (q x q), beta (q), V3 (q x 3b), X (q x b), T, N, M (b x b),
   // RB (q x kRw), exchange slots, error flag, blocked-product scratch, U rows
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t oVh = 0;
@@ -437,7 +560,7 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   const size_t oV3 = oBt + al(sizeof(double) * q);
   const size_t oX = oV3 + al(sizeof(z64) * (size_t)q * 3 * b);
   const size_t oSm = oX + al(sizeof(z64) * (size_t)q * b);
-  const size_t oRB = oSm + al(sizeof(z64) * 4 * b * b);
+  const size_t oRB = oSm + al(sizeof(z64) * 3 * b * b);
   const size_t oSl = oRB + al(sizeof(z64) * (size_t)q * kRw);
   const size_t nslot = (size_t)b * (gmax + 1) * 64;
   const size_t oErr = oSl + al(sizeof(z64) * nslot);
@@ -449,8 +572,7 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   double* bt = reinterpret_cast<double*>(base + oBt);
   z64* V3 = reinterpret_cast<z64*>(base + oV3);
   z64* X = reinterpret_cast<z64*>(base + oX);
-  z64* Gm = reinterpret_cast<z64*>(base + oSm);
-  z64* Tm = Gm + b * b;
+  z64* Tm = reinterpret_cast<z64*>(base + oSm);
   z64* Nm = Tm + b * b;
   z64* Mm = Nm + b * b;
   z64* RB = reinterpret_cast<z64*>(base + oRB);
@@ -485,13 +607,11 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
       int64_t ldp = lda, ldv = ld3, ldh = q;
       z64* Vp = Vh + (int64_t)k0 * q + (k0 + b);
       double* btp = bt + k0;
-      void* args[] = {&mm, &P, &ldp, &V3, &ldv, &Vp, &ldh, &btp, &part_x, &rowv, &err};
+      void* args[] = {&mm, &P, &ldp, &V3, &ldv, &Vp, &ldh, &btp, &Tm, &part_x, &rowv, &err};
       HIPCK(hipLaunchCooperativeKernel((const void*)k_band_panel<kPanelRpt>, dim3(G), dim3(1024), args, 0, st));
       // trailing update A22 <- H^H A22 H
       z64* A22 = A + (k0 + b) + (int64_t)(k0 + b) * lda;
       z64* Yb = V3 + (int64_t)b * ld3;
-      gemm_hn<double>(st, m, b, b, V3, ld3, V3, ld3, Gm, b, 1.0, 0.0, part);
-      hipLaunchKernelGGL(k_band_form_t, dim3(1), dim3(64), 0, st, Gm, bt + k0, Tm);
       gemm_hn<double>(st, m, m, b, A22, lda, V3, ld3, X, ld3, 1.0, 0.0, part);  // A22^H V = A22 V
       gemm_nn<double>(st, m, b, b, X, ld3, Tm, b, 0, Yb, ld3, 1.0, 0.0, 0.0);
       gemm_hn<double>(st, m, b, b, V3, ld3, Yb, ld3, Nm, b, 1.0, 0.0, part);
@@ -509,7 +629,7 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   apply_refl_blocked(st, q, b, p, Vh, bt, Yt, q, 1, wy, part);
   for (int l0 = 0; l0 < p; l0 += nsh) {
     const int n = std::min(nsh, p - l0);
-    hipLaunchKernelGGL(k_band_gepp, dim3(n), dim3(1024), 0, st, q, RB, s, Yt, (int64_t)q, Ubuf, l0);
+    hipLaunchKernelGGL(k_band_gepp, dim3(n), dim3(kGt), 0, st, q, RB, s, Yt, (int64_t)q, Ubuf, l0);
   }
   apply_refl_blocked(st, q, b, p, Vh, bt, Yt, q, 0, wy, part);
   HIPCK(hipGetLastError());
