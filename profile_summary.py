@@ -1,7 +1,13 @@
 """Summaries of rocprofv3 results databases (kernel durations, PMC counters).
 
     python profile_summary.py trace DB [--split-gap-ms G]
+    python profile_summary.py window DB --kernel NAME --last N
     python profile_summary.py pmc FETCH_DB WRITE_DB --kernel NAME [--copy-bytes B]
+
+The window mode summarises the dispatches from the first of the last N
+dispatches of the named kernel to the end of the trace (bench.py reports how
+many launches of its dominant kernel fall in its timed steps), and that
+kernel's average duration over those N dispatches.
 
 The pmc mode reports FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the named
 kernel, scaled by the ratio of the known byte count of a plain device copy
@@ -45,6 +51,20 @@ def trace(db, top=20, rows=None):
     return out, tot / 1e6
 
 
+def window(db, kernel, last):
+    """Dispatches from the first of the last `last` dispatches whose name
+    starts with `kernel` onwards, and those dispatches' mean duration (ms)."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, duration from kernels order by start").fetchall()
+    hits = [i for i, (name, _, _) in enumerate(rows) if name.split("(")[0] == kernel]
+    if len(hits) < last:
+        raise SystemExit(f"{kernel}: {len(hits)} dispatches in the trace, fewer than {last}")
+    first = hits[-last]
+    sel = [(name, dur) for name, _, dur in rows[first:]]
+    mean = statistics.mean(rows[i][2] for i in hits[-last:]) / 1e6
+    return sel, mean
+
+
 def pmc(db, counter):
     """{kernel: [counter value per dispatch]} (summed over counter instances)."""
     con = sqlite3.connect(db)
@@ -60,7 +80,7 @@ def pmc(db, counter):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "pmc"])
+    ap.add_argument("mode", choices=["trace", "window", "pmc"])
     ap.add_argument("dbs", nargs="+")
     ap.add_argument("--kernel", default=None)
     ap.add_argument("--copy-bytes", type=float, default=536870912.0)
@@ -68,7 +88,20 @@ def main():
     ap.add_argument("--split-gap-ms", type=float, default=0.0,
                     help="report separately the stretches of dispatches separated by idle gaps above this")
     ap.add_argument("--min-dispatches", type=int, default=100)
+    ap.add_argument("--last", type=int, default=0)
+    ap.add_argument("--top", type=int, default=25)
     a = ap.parse_args()
+    if a.mode == "window":
+        sel, mean = window(a.dbs[0], a.kernel, a.last)
+        rows, tot = trace(a.dbs[0], top=a.top, rows=sel)
+        print(f"window: {len(sel)} dispatches from the first of the last {a.last} dispatches of {a.kernel}")
+        print(f"{a.kernel}: mean duration over those {a.last} dispatches {mean:.4f} ms")
+        print(f"total kernel time {tot:.3f} ms")
+        print("| kernel | calls | total ms | avg ms | % |")
+        print("|---|---|---|---|---|")
+        for name, n, t, avg, pct in rows:
+            print(f"| {name} | {n} | {t:.3f} | {avg:.4f} | {pct:.1f} |")
+        return
     if a.mode == "trace":
         segs = segments(a.dbs[0], a.split_gap_ms) if a.split_gap_ms > 0 else [None]
         if a.split_gap_ms > 0:
