@@ -122,7 +122,14 @@ def measure(args, precision):
     from paper_2503_16225_amd.binding import SolveParams, Stats, _check
 
     sysd = W.config(args.config)
-    pb = B.Problem(sysd, precision=B.EAHP_MIXED if precision == "mixed" else B.EAHP_FP64)
+    if args.graphs:
+        # graph capture needs a stream other than the legacy default stream
+        gstream = torch.cuda.Stream()
+        with torch.cuda.stream(gstream):
+            pb = B.Problem(sysd, precision=B.EAHP_MIXED if precision == "mixed" else B.EAHP_FP64)
+        pb.set_graphs(True)
+    else:
+        pb = B.Problem(sysd, precision=B.EAHP_MIXED if precision == "mixed" else B.EAHP_FP64)
     lib = pb.lib
     Z = W.gaussian_block(1, pb.npw, pb.p)
     Psi0 = pb.to_device(Z)
@@ -217,6 +224,7 @@ def measure(args, precision):
         it += 1
         note("to 1e-6", extra, args.gs_maxit)
     lib.eahp_solver_destroy(sv)
+    graphs = pb.graph_stats() if args.graphs else None
     pb.close()
     nk = len(sysd["kweight"]) if sysd.get("kweight") is not None else 1
     desc = (f"{args.config}: diamond-structure model, {len(sysd['Z'])} atoms, p={pb.p}, Ecut {sysd['ecut']:g} Ha, "
@@ -225,7 +233,8 @@ def measure(args, precision):
     return {"napply": napply, "napply_fp32": napply32, "elapsed": elapsed, "desc": desc,
             "value": napply / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
             "energy": st.energy, "rnorm_timed": [rn_start, rn_end], "prep_steps": prep, "prep_s": t_prep,
-            "ground_state_s": t_gs, "ground_state_iters": it_gs, "kernels": kern, "tuned_in_timed": tuned_in_timed}
+            "ground_state_s": t_gs, "ground_state_iters": it_gs, "kernels": kern, "tuned_in_timed": tuned_in_timed,
+            "graphs": graphs}
 
 
 def serving_sample(args):
@@ -410,6 +419,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="default launch configurations (no tuning of them in the untimed preparation)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="frame H-applies captured and replayed as HIP graphs (eahp_problem_set_graphs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--serving", type=int, default=0, help="run the serving stream with this many requests instead")
@@ -491,7 +502,9 @@ def main():
                    "precision": args.precision,
                    "napply": head["napply"], "napply_fp32": head["napply_fp32"],
                    "rnorm_timed": head["rnorm_timed"], "prep_steps": head["prep_steps"],
-                   "tuned_in_timed": head["tuned_in_timed"]},
+                   "tuned_in_timed": head["tuned_in_timed"],
+                   "graphs": None if head["graphs"] is None else {"captured": head["graphs"][0],
+                                                                  "replays": head["graphs"][1]}},
         "ground_states_per_s": (1.0 / head["ground_state_s"]) if head["ground_state_s"] else None,
         "ground_state": {"tol_rnorm": args.gs_tol, "seconds": head["ground_state_s"],
                          "outer_iterations": head["ground_state_iters"], "prep_s": head["prep_s"]},

@@ -270,6 +270,20 @@ void eahp_solver_destroy(eahp_solver* sv);
 int eahp_prof_enable(eahp_ctx* ctx, int on);
 int eahp_prof_read(eahp_ctx* ctx, int kernel, double* total_ms, int64_t* launches, double* bytes);
 
+/* Frame H-applies as replayed HIP graphs (for callers that repeat the same
+ * H-apply many times, such as the solver's line-search trials and the
+ * serving loop, where the launch sequence and not the kernels costs the
+ * time at small sizes).  With on = 1, the frame H-applies of this problem
+ * (eahp_apply_H and those inside the solvers) are captured into a graph the
+ * second time the same frames and workspaces occur and replayed from then
+ * on; results are bit-for-bit those of the plain launches.  Requires a
+ * context stream other than the legacy default stream (EAHP_EINVAL
+ * otherwise).  on = 0 drops the captured graphs.  Kernel timing
+ * (eahp_prof_enable) takes the plain launches.  graph_stats: graphs captured
+ * and replays since the problem was created. */
+int eahp_problem_set_graphs(eahp_problem* pb, int on);
+int eahp_problem_graph_stats(const eahp_problem* pb, int64_t* captured, int64_t* replays);
+
 /* Launch-configuration autotuner (process-wide).  Some kernels have several
  * valid launch configurations with identical results and a speed that depends
  * on the shape and the chip (the work-group count of the multi-work-group

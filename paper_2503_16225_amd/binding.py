@@ -136,6 +136,8 @@ def load_library():
         "eahp_symmetry_find": ([C.POINTER(SystemDesc), C.c_double, C.c_int, ip, dp, ip], C.c_int),
         "eahp_kpoints_reduce": ([C.c_int, ip, C.c_int, C.c_int, dp, dp, dp, dp, ip, ip], C.c_int),
         "eahp_prof_enable": ([vp, C.c_int], C.c_int),
+        "eahp_problem_set_graphs": ([vp, C.c_int], C.c_int),
+        "eahp_problem_graph_stats": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
         "eahp_prof_read": ([vp, C.c_int, dp, i64p, dp], C.c_int),
         "eahp_autotune_enable": ([C.c_int], C.c_int),
         "eahp_autotune_report": ([C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
@@ -408,10 +410,20 @@ class Problem:
         _check(self.lib.eahp_density(self.pb, _ptr(Psi), _ptr(rho), _ptr(veff)))
         return rho, veff
 
-    def apply_H(self, Psi, X):
-        HX = self.empty_frame()
+    def apply_H(self, Psi, X, out=None):
+        HX = self.empty_frame() if out is None else out
         _check(self.lib.eahp_apply_H(self.pb, _ptr(Psi), _ptr(X), _ptr(HX)))
         return HX
+
+    def set_graphs(self, on=True):
+        """eahp_problem_set_graphs: frame H-applies captured and replayed as HIP graphs."""
+        _check(self.lib.eahp_problem_set_graphs(self.pb, 1 if on else 0))
+
+    def graph_stats(self):
+        """(graphs captured, replays) of this problem."""
+        c, r = C.c_int64(), C.c_int64()
+        _check(self.lib.eahp_problem_graph_stats(self.pb, C.byref(c), C.byref(r)))
+        return c.value, r.value
 
     def residual(self, Psi):
         R = self.empty_frame()

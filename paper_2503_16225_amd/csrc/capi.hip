@@ -838,6 +838,25 @@ int eahp_solve(eahp_problem* pb, void* Psi_inout, const eahp_solve_params* prmp,
   return rc != EAHP_OK ? rc : rc2;
 }
 
+int eahp_problem_set_graphs(eahp_problem* pb, int on) {
+  return guarded([&] {
+    check_problem(pb);
+    if (on && pb->ctx->stream == nullptr)
+      fail(EAHP_EINVAL, "graph capture needs a stream other than the legacy default stream");
+    HIPCK(hipStreamSynchronize(pb->ctx->stream));
+    pb->graphs = on != 0;
+    if (!on) pb->drop_graphs();
+  });
+}
+
+int eahp_problem_graph_stats(const eahp_problem* pb, int64_t* captured, int64_t* replays) {
+  return guarded([&] {
+    if (!pb) fail(EAHP_EINVAL, "null problem");
+    if (captured) *captured = pb->graph_captures;
+    if (replays) *replays = pb->graph_replays;
+  });
+}
+
 int eahp_prof_enable(eahp_ctx* ctx, int on) {
   return guarded([&] {
     if (!ctx) fail(EAHP_EINVAL, "null context");

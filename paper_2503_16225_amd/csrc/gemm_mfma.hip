@@ -13,6 +13,8 @@
 // gemm_nn (frame times small matrix): one 64 x 64 output tile per work-group,
 // the inner dimension streamed through LDS 16 at a time, the tile staged
 // through LDS for coalesced stores.
+#include <atomic>
+
 #include "devcommon.h"
 #include "kernels.h"
 
@@ -39,6 +41,19 @@ struct Mfma<float> {
 };
 
 constexpr int MT = 64;       // output tile edge
+constexpr int kXcds = 8;     // MI355X: 8 accelerator dies, each with its own L2
+
+// Work-groups are handed to the dies round-robin in the order of their
+// linear index.  With grouping on, linear index L is mapped to logical
+// index L' so that die d runs the contiguous logical range
+// [start(d), start(d+1)), start(d) = d floor(N/8) + min(d, N mod 8): logical
+// neighbours (the output tiles that read the same block of the large
+// operand) then run on one die and share its L2.
+__device__ __forceinline__ int64_t xcd_order(int64_t L, int64_t N, int group) {
+  if (!group) return L;
+  const int64_t d = L % kXcds, j = L / kXcds, q = N / kXcds, r = N % kXcds;
+  return d * q + (d < r ? d : r) + j;
+}
 constexpr int MK = 16;       // chunk of the inner dimension
 constexpr int LDK = MK + 1;  // padded LDS row
 
@@ -50,14 +65,20 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_gemm_hn_mfma(int64_t n, int a, int b, const cplx<T>* __restrict__ A,
                                                       int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb,
                                                       int64_t rps, cplx<T>* __restrict__ part, int64_t sA,
-                                                      int64_t sB) {
+                                                      int64_t sB, int group) {
   __shared__ T Ar[MT * LDK], Ai[MT * LDK], Br[MT * LDK], Bi[MT * LDK];
   using M = Mfma<T>;
   using acc_t = typename M::acc;
   const int tiles_a = (a + MT - 1) / MT;
   const int tiles = tiles_a * ((b + MT - 1) / MT);
-  const int tile = blockIdx.x, ta = tile % tiles_a, tb = tile / tiles_a;
-  const int split = blockIdx.y, batch = blockIdx.z;
+  // logical order: the tiles of one column block of A (all tb) consecutive
+  const int64_t nwg = (int64_t)gridDim.x * gridDim.y * gridDim.z;
+  const int64_t lin = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+  const int64_t lg = xcd_order(lin, nwg, group);
+  const int tiles_b = tiles / tiles_a;
+  const int tb = (int)(lg % tiles_b), ta = (int)((lg / tiles_b) % tiles_a);
+  const int split = (int)((lg / tiles) % gridDim.y), batch = (int)(lg / ((int64_t)tiles * gridDim.y));
+  const int tile = ta + tiles_a * tb;
   A += batch * sA;
   B += batch * sB;
   const int64_t r0 = split * rps, r1 = min(n, r0 + rps);
@@ -220,7 +241,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_gemm_nn_mfma(int64_t n, int a, int b, const cplx<T>* __restrict__ A,
                                                       int64_t lda, const cplx<T>* __restrict__ Mm, int64_t ldm,
                                                       int opM, cplx<T>* __restrict__ C, int64_t ldc, double are,
-                                                      double aim, double beta, int64_t sA, int64_t sM, int64_t sC) {
+                                                      double aim, double beta, int64_t sA, int64_t sM, int64_t sC,
+                                                      int group) {
   // input planes; reused as the 64 x 32 output staging tile (complex, row fastest)
   __shared__ T lds[4 * MT * LDK];
   T* Ar = lds;
@@ -229,12 +251,18 @@ __global__ void __launch_bounds__(256) k_gemm_nn_mfma(int64_t n, int a, int b, c
   T* Mi = Mr + MT * LDK;
   using Mf = Mfma<T>;
   using acc_t = typename Mf::acc;
-  const int batch = blockIdx.z;
+  // logical order: the column tiles of one row block of A consecutive
+  const int64_t nwg = (int64_t)gridDim.x * gridDim.y * gridDim.z;
+  const int64_t lin = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+  const int64_t lg = xcd_order(lin, nwg, group);
+  const int tcol = (int)(lg % gridDim.y);
+  const int64_t trow = (lg / gridDim.y) % gridDim.x;
+  const int batch = (int)(lg / ((int64_t)gridDim.x * gridDim.y));
   A += batch * sA;
   Mm += batch * sM;
   C += batch * sC;
-  const int64_t row0 = (int64_t)blockIdx.x * MT;
-  const int col0 = blockIdx.y * MT;
+  const int64_t row0 = trow * MT;
+  const int col0 = tcol * MT;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
   acc_t cre[2][2], cim[2][2];
@@ -378,6 +406,10 @@ static void hn_split(int64_t n, int a, int b, int batch, int64_t max_part, int64
   }
 }
 
+// die-grouped tile order of the products (on by default)
+static std::atomic<int> g_xcd_group{1};
+void gemm_set_xcd_group(int on) { g_xcd_group.store(on ? 1 : 0); }
+
 size_t gemm_hn_min_part(int a, int b, int batch) {
   const int tiles = ((a + MT - 1) / MT) * ((b + MT - 1) / MT);
   return (size_t)tiles * 4 * 4 * 256 * batch;
@@ -392,7 +424,7 @@ void gemm_hn_mfma_ws(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, 
   hn_split(n, a, b, batch, (int64_t)part_elems, nsplit, rps, per_split);
   if ((size_t)(nsplit * per_split * batch) > part_elems) fail(EAHP_EINVAL, "Gram product: partial buffer too small");
   hipLaunchKernelGGL((k_gemm_hn_mfma<T>), dim3(tiles, (unsigned)nsplit, batch), dim3(256), 0, st, n, a, b, A, lda, B,
-                     ldb, rps, part, sA, sB);
+                     ldb, rps, part, sA, sB, g_xcd_group.load());
   HIPCK(hipGetLastError());
   const int nb = (int)std::min<int64_t>(4096, (per_split + 15) / 16);
   hipLaunchKernelGGL((k_gemm_hn_mfma_reduce<T>), dim3(nb, batch), dim3(256), 0, st, a, b, (int)nsplit, part, C, ldc,
@@ -417,7 +449,7 @@ void gemm_nn_mfma(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int
                   int batch, int64_t sA, int64_t sM, int64_t sC) {
   dim3 grid((unsigned)((n + MT - 1) / MT), (b + MT - 1) / MT, batch);
   hipLaunchKernelGGL((k_gemm_nn_mfma<T>), grid, dim3(256), 0, st, n, a, b, A, lda, M, ldm, opM, C, ldc, alpha_re,
-                     alpha_im, beta, sA, sM, sC);
+                     alpha_im, beta, sA, sM, sC, g_xcd_group.load());
   HIPCK(hipGetLastError());
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <map>
 #include <cstdint>
 #include <string>
 #include <utility>
@@ -168,5 +169,15 @@ struct eahp_problem {
   int64_t napply = 0, napply32 = 0;
   int fom_iters = 0;
   size_t footprint = 0;
+  // frame H-applies captured as HIP graphs (eahp_problem_set_graphs): keyed by
+  // the frame pointers and every workspace address the captured launches use
+  struct HGraph {
+    int seen = 0;
+    hipGraphExec_t exec = nullptr;
+  };
+  bool graphs = false;
+  std::map<std::array<uintptr_t, 8>, HGraph> hgraphs;
+  int64_t graph_captures = 0, graph_replays = 0;
+  void drop_graphs();
   ~eahp_problem();
 };

@@ -85,6 +85,9 @@ void gemm_hn_mfma_ws(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, 
                      int64_t ldb, cplx<T>* C, int64_t ldc, double alpha, double beta, cplx<T>* part, size_t part_elems,
                      int batch, int64_t sA, int64_t sB, int64_t sC);
 size_t gemm_hn_min_part(int a, int b, int batch);
+// tile order of gemm_hn / gemm_nn: 1 groups the tiles that share a block of
+// the large operand on one die (its L2), 0 the plain order (same results)
+void gemm_set_xcd_group(int on);
 // C[n x b] = alpha * A[n x a] M[a x b] + beta * C ; opM: 0 = M, 1 = M^H
 template <typename T>
 void gemm_nn(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* M, int64_t ldm,

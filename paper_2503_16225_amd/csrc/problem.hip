@@ -514,7 +514,7 @@ void nonlocal_block<float>(eahp_problem* pb, int ik, int ncols, const c32* X, in
 
 // H X for a whole frame with the current V_eff.  tb_ready: the plane buffer
 // already holds the inverse y/z transforms of X (from density_potentials).
-void apply_H_frame(eahp_problem* pb, const z64* X, z64* HX, bool tb_ready, double* nlvals) {
+static void apply_H_frame_launches(eahp_problem* pb, const z64* X, z64* HX, bool tb_ready, double* nlvals) {
   hipStream_t st = pb->ctx->stream;
   const int ncols = pb->nk * pb->p;
   z64* Tb = (z64*)planes_for<double>(pb, ncols);
@@ -538,6 +538,62 @@ void apply_H_frame(eahp_problem* pb, const z64* X, z64* HX, bool tb_ready, doubl
     auto& K = pb->kp[ik];
     const int64_t o = (int64_t)pb->p * K.off;
     nonlocal_block<double>(pb, ik, pb->p, X + o, K.npw, HX + o, K.npw, nlvals ? nlvals + ik * pb->p : nullptr);
+  }
+}
+
+// With graphs on, the launch sequence of a frame H-apply is captured into a
+// HIP graph the second time the same key occurs (the first call runs the
+// launches directly and sizes every workspace they use), and replayed from
+// then on.  The key holds the frame pointers and the addresses of the
+// workspaces the captured kernels read and write, so a workspace that has
+// been reallocated since leads to a new capture rather than a replay.  The
+// graph takes the pointers, not the values: V_eff, the frames and the
+// workspaces are read at replay time.  No memset is captured.  Kernel timing
+// (eahp_prof_enable) runs the launches directly.
+void apply_H_frame(eahp_problem* pb, const z64* X, z64* HX, bool tb_ready, double* nlvals) {
+  hipStream_t st = pb->ctx->stream;
+  const int ncols = pb->nk * pb->p;
+  const bool use = pb->graphs && st != nullptr && !pb->ctx->prof && g_prof_ctx.load() == nullptr;
+  if (!use) {
+    apply_H_frame_launches(pb, X, HX, tb_ready, nlvals);
+    pb->napply += ncols;
+    return;
+  }
+  z64* Tb = (z64*)planes_for<double>(pb, ncols);
+  const std::array<uintptr_t, 8> key = {(uintptr_t)X, (uintptr_t)HX, (uintptr_t)nlvals, (uintptr_t)tb_ready,
+                                        (uintptr_t)Tb, (uintptr_t)pb->ws.small.p, (uintptr_t)pb->ws.gemm_part.p,
+                                        (uintptr_t)pb->d_veff.p};
+  auto& e = pb->hgraphs[key];
+  if (e.exec) {
+    HIPCK(hipGraphLaunch(e.exec, st));
+    ++pb->graph_replays;
+  } else if (e.seen == 0) {
+    e.seen = 1;
+    apply_H_frame_launches(pb, X, HX, tb_ready, nlvals);
+  } else {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCK(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) {  // the caller is capturing: plain launches into its graph
+      apply_H_frame_launches(pb, X, HX, tb_ready, nlvals);
+    } else {
+      HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+      try {
+        apply_H_frame_launches(pb, X, HX, tb_ready, nlvals);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(st, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      hipGraph_t g = nullptr;
+      HIPCK(hipStreamEndCapture(st, &g));
+      const hipError_t ie = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCK(ie);
+      ++pb->graph_captures;
+      HIPCK(hipGraphLaunch(e.exec, st));
+      ++pb->graph_replays;
+    }
   }
   pb->napply += ncols;
 }
@@ -754,7 +810,14 @@ eahp_ctx::~eahp_ctx() {
   }
 }
 
+void eahp_problem::drop_graphs() {
+  for (auto& kv : hgraphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  hgraphs.clear();
+}
+
 eahp_problem::~eahp_problem() {
+  drop_graphs();
   delete arena;
   if (h_scal) (void)hipHostFree(h_scal);
   if (h_info) (void)hipHostFree(h_info);
