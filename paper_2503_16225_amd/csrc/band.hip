@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(kGt) k_band_gepp(int q, const z64* __restrict_
 // ld lda, Hermitian up to rounding; destroyed), s (p shifts), Yt (q x p, ld q:
 // the right-hand sides, overwritten by the solutions).
 void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws,
-                    DevMem& part) {
+                    DevMem& part, const BandAux* aux) {
   if (q <= kBw) fail(EAHP_EINVAL, "band reduction: q must exceed the bandwidth");
   if (p <= 0) return;
   const int b = kBw;
@@ -558,7 +558,7 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   const size_t oVh = 0;
   const size_t oBt = oVh + al(sizeof(z64) * (size_t)q * q);
   const size_t oV3 = oBt + al(sizeof(double) * q);
-  const size_t oX = oV3 + al(sizeof(z64) * (size_t)q * 3 * b);
+  const size_t oX = oV3 + al(sizeof(z64) * (size_t)q * 3 * b * 2);  // two buffers (look-ahead)
   const size_t oSm = oX + al(sizeof(z64) * (size_t)q * b);
   const size_t oRB = oSm + al(sizeof(z64) * 3 * b * b);
   const size_t oSl = oRB + al(sizeof(z64) * (size_t)q * kRw);
@@ -594,10 +594,34 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
     // the cooperative panels wait on each other's work-groups: one such grid
     // at a time per process
     std::lock_guard<std::mutex> lk(coop_mutex());
-    for (int k0 = 0; k0 + b < q; k0 += b) {
+    // With look-ahead, panel i's update of the trailing matrix beyond the
+    // next panel's columns runs on the second stream while panel i + 1 is
+    // factored: the next panel's columns are updated first, and panel i + 1
+    // reads and writes only those columns; X of panel i + 1 waits for the
+    // rest.  That update is submitted after panel i + 1, so that the panel's
+    // work-groups (which wait on each other) are dispatched first.  V3
+    // alternates between two buffers (the second stream still reads panel
+    // i's while panel i + 1 writes its own).
+    const bool look = aux != nullptr && aux->s != nullptr;
+    struct Deferred {
+      bool on = false;
+      int m = 0;
+      z64 *V3 = nullptr, *Yb = nullptr, *A22 = nullptr;
+    } rest;
+    auto submit_rest = [&]() {
+      // A22[:, b:] -= [V Z] [Z V]^H[:, b:] on the second stream, after the event z
+      HIPCK(hipStreamWaitEvent(aux->s, aux->z, 0));
+      gemm_nn<double>(aux->s, rest.m, 2 * b, rest.m - b, rest.V3, ld3, rest.Yb + b, ld3, 1, rest.A22 + (int64_t)b * lda,
+                      lda, -1.0, 0.0, 1.0);
+      HIPCK(hipEventRecord(aux->c, aux->s));
+      rest.on = false;
+      return true;
+    };
+    for (int k0 = 0, idx = 0; k0 + b < q; k0 += b, ++idx) {
       const int m = q - k0 - b, ns = std::min(b, m);
       const int G = (m + kPanelRows - 1) / kPanelRows;
       z64* P = A + (k0 + b) + (int64_t)k0 * lda;
+      z64* V3c = V3 + (int64_t)(idx & 1) * ld3 * 3 * b;
       z64* part_x = slots;
       z64* rowv = slots + (size_t)ns * G * 64;
       const int64_t nw = (int64_t)2 * ns * (G + 1) * 64;
@@ -607,17 +631,32 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
       int64_t ldp = lda, ldv = ld3, ldh = q;
       z64* Vp = Vh + (int64_t)k0 * q + (k0 + b);
       double* btp = bt + k0;
-      void* args[] = {&mm, &P, &ldp, &V3, &ldv, &Vp, &ldh, &btp, &Tm, &part_x, &rowv, &err};
+      void* args[] = {&mm, &P, &ldp, &V3c, &ldv, &Vp, &ldh, &btp, &Tm, &part_x, &rowv, &err};
       HIPCK(hipLaunchCooperativeKernel((const void*)k_band_panel<kPanelRpt>, dim3(G), dim3(1024), args, 0, st));
+      if (rest.on) {
+        submit_rest();
+        HIPCK(hipStreamWaitEvent(st, aux->c, 0));
+      }
       // trailing update A22 <- H^H A22 H
       z64* A22 = A + (k0 + b) + (int64_t)(k0 + b) * lda;
-      z64* Yb = V3 + (int64_t)b * ld3;
-      gemm_hn<double>(st, m, m, b, A22, lda, V3, ld3, X, ld3, 1.0, 0.0, part);  // A22^H V = A22 V
+      z64* Yb = V3c + (int64_t)b * ld3;
+      gemm_hn<double>(st, m, m, b, A22, lda, V3c, ld3, X, ld3, 1.0, 0.0, part);  // A22^H V = A22 V
       gemm_nn<double>(st, m, b, b, X, ld3, Tm, b, 0, Yb, ld3, 1.0, 0.0, 0.0);
-      gemm_hn<double>(st, m, b, b, V3, ld3, Yb, ld3, Nm, b, 1.0, 0.0, part);
+      gemm_hn<double>(st, m, b, b, V3c, ld3, Yb, ld3, Nm, b, 1.0, 0.0, part);
       gemm_hn<double>(st, b, b, b, Tm, b, Nm, b, Mm, b, 1.0, 0.0, part);
-      gemm_nn<double>(st, m, b, b, V3, ld3, Mm, b, 0, Yb, ld3, -0.5, 0.0, 1.0);
-      gemm_nn<double>(st, m, 2 * b, m, V3, ld3, Yb, ld3, 1, A22, lda, -1.0, 0.0, 1.0);
+      gemm_nn<double>(st, m, b, b, V3c, ld3, Mm, b, 0, Yb, ld3, -0.5, 0.0, 1.0);
+      if (look && m > b) {
+        // the next panel's columns now; the rest after the next panel's launch
+        gemm_nn<double>(st, m, 2 * b, b, V3c, ld3, Yb, ld3, 1, A22, lda, -1.0, 0.0, 1.0);
+        HIPCK(hipEventRecord(aux->z, st));
+        rest = Deferred{true, m, V3c, Yb, A22};
+      } else {
+        gemm_nn<double>(st, m, 2 * b, m, V3c, ld3, Yb, ld3, 1, A22, lda, -1.0, 0.0, 1.0);
+      }
+    }
+    if (rest.on) {
+      submit_rest();
+      HIPCK(hipStreamWaitEvent(st, aux->c, 0));
     }
     int bad = 0;
     HIPCK(hipMemcpyAsync(&bad, err, sizeof(int), hipMemcpyDeviceToHost, st));

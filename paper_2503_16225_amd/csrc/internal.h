@@ -117,6 +117,9 @@ struct eahp_ctx {
   hipStream_t stream = nullptr;
   bool prof = false;
   ProfSlot slot[kProfKernels];
+  // second stream and events of overlapped work, created on first use
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t aux_ev[2] = {nullptr, nullptr};
   ~eahp_ctx();
 };
 

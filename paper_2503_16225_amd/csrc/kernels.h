@@ -168,8 +168,14 @@ void set_identity(hipStream_t st, int p, z64* M, int64_t ldm);
 // solutions) through one Householder tridiagonalisation of A (destroyed).
 // store32: for q > 512, the reduction keeps the trailing matrix in single
 // precision (the single-precision metric solve).
+// A second stream (default priority) and two events for work that overlaps the
+// main stream's (the band reduction's look-ahead); owned by a context.
+struct BandAux {
+  hipStream_t s = nullptr;
+  hipEvent_t z = nullptr, c = nullptr;
+};
 void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws,
-                       DevMem& part, bool store32 = false);
+                       DevMem& part, bool store32 = false, const BandAux* aux = nullptr);
 // Householder reduction of a Hermitian A (q x q, ld lda; destroyed for q > 512)
 // to the Hermitian tridiagonal T = Q^H A Q, Q = H_0 ... H_{q-2}: dd (q reals,
 // the diagonal), e (q complex, e[k] = T[k+1][k]), the reflectors Vh (q x q,
@@ -196,7 +202,9 @@ void apply_refl_blocked(hipStream_t st, int q, int off, int ncols, const z64* Vh
 // (A - s_l I) y_l = c_l for all columns of Yt (q x p, ld q; overwritten by the
 // solutions) through a reduction of A (destroyed) to Hermitian band form and
 // banded solves with partial pivoting (band.hip); q > 64.
+// With aux: the trailing update of each panel beyond the next panel's
+// columns runs on aux.s while the next panel is factored (identical results).
 void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws,
-                    DevMem& part);
+                    DevMem& part, const BandAux* aux = nullptr);
 
 }  // namespace eahp

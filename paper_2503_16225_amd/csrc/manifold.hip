@@ -383,6 +383,21 @@ double norm2(eahp_problem* pb, int64_t len, const cplx<T>* x) {
   return pb->h_scal[S_NRM];
 }
 
+// the context's second stream and events (created on first use, on its
+// device; non-blocking, so that it overlaps a caller on the legacy default
+// stream, with the order given by events only)
+static const BandAux& band_aux(eahp_ctx* c) {
+  static thread_local BandAux a;
+  if (!c->aux_stream) {
+    HIPCK(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
+    for (auto& e : c->aux_ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  a.s = c->aux_stream;
+  a.z = c->aux_ev[0];
+  a.c = c->aux_ev[1];
+  return a;
+}
+
 template <typename T>
 FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64* Lam, double mu, double rtol,
               int maxit, double rank_tol, z64* X, const double* lw, const z64* lU) {
@@ -457,7 +472,7 @@ FomInfo fom_k(eahp_problem* pb, int ik, const z64* Phi, const z64* R, const z64*
     copy2d(st, q, q, w.A.template as<z64>(), ldA, w.Ah.template as<z64>(), q);
     gemm_nn<double>(st, q, p, p, w.Cj.template as<z64>(), ldA, w.U.template as<z64>(), p, 0, w.T2.template as<z64>(), q, 1.0, 0.0, 0.0);
     sylvester_tridiag(st, q, p, w.Ah.template as<z64>(), q, w.s.template as<double>(), w.T2.template as<z64>(), w.tri,
-                      pb->ws.gemm_part, sizeof(T) == 4);
+                      pb->ws.gemm_part, sizeof(T) == 4, &band_aux(pb->ctx));
     gemm_nn<double>(st, q, p, p, w.T2.template as<z64>(), q, w.U.template as<z64>(), p, 1, w.Y.template as<z64>(), q, 1.0, 0.0, 0.0);
     gemm_nn<double>(st, q, p, p, w.Y.template as<z64>(), q, w.Sig.template as<z64>(), p, 0, w.YS.template as<z64>(), q, 1.0, 0.0, 0.0);
     const cplx<T>* Ys;

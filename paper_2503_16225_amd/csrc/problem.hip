@@ -808,6 +808,13 @@ eahp_ctx::~eahp_ctx() {
     for (auto e : s.start) (void)hipEventDestroy(e);
     for (auto e : s.stop) (void)hipEventDestroy(e);
   }
+  if (aux_stream) {
+    (void)hipSetDevice(device);
+    (void)hipStreamSynchronize(aux_stream);
+    (void)hipStreamDestroy(aux_stream);
+  }
+  for (auto e : aux_ev)
+    if (e) (void)hipEventDestroy(e);
 }
 
 void eahp_problem::drop_graphs() {

@@ -923,10 +923,10 @@ void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* b
 // Y~ (q x p, ld q) := solution of (A - s_l) y~_l = C~[:, l]; A (q x q, ld lda)
 // may be destroyed.  ws grows to what the chosen kernels need.
 void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws,
-                       DevMem& part, bool store32) {
+                       DevMem& part, bool store32, const BandAux* aux) {
   if (q <= 0 || p <= 0) return;
   if (q > 512) {
-    sylvester_band(st, q, p, A, lda, s, Yt, ws, part);
+    sylvester_band(st, q, p, A, lda, s, Yt, ws, part, aux);
     return;
   }
   // Vh (q x q), W (3 q p), e (q), then d, beta (q each), then the scratch of
