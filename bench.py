@@ -24,11 +24,16 @@ from the same start ("compare").
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
                        [--precision mixed|fp64] [--no-compare]
                        [--serving-sample N] [--no-cpu-baseline] [--no-autotune]
+                       [--tune-save PATH]
 
-Launch configurations with several valid choices (the work-group count of
-the multi-work-group Householder reduction) are tuned by libeahp's autotuner
-the first time each shape class occurs, which happens in the untimed
-preparation; the choices are reported under "autotune".
+Launch configurations with several valid choices and identical results (the
+tile shapes of the complex block products, the work-group count of the
+multi-work-group Householder reduction) come from libeahp's autotuner: the
+table shipped beside the library (tune_table.txt, measured on MI355X) is
+loaded, shape classes it lacks are tuned when they first occur outside the
+timed steps, and inside the timed steps only kept choices are used (nothing
+is timed there).  The table is reported under "autotune"; --tune-save writes
+it to a file.
 """
 from __future__ import annotations
 
@@ -188,6 +193,8 @@ def measure(args, precision):
     n0, n32 = st.napply, st.napply_fp32
     rn_start = st.rnorm
     tuned_before = B.autotune_report()
+    if not args.no_autotune:
+        B.autotune_enable(2)  # kept choices only inside the timed steps
     _check(lib.eahp_prof_enable(pb.ctx, 1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -204,6 +211,8 @@ def measure(args, precision):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     tuned_in_timed = B.autotune_report() != tuned_before
+    if not args.no_autotune:
+        B.autotune_enable(1)
     if tuned_in_timed:
         print(f"{tag}: a launch configuration was tuned inside the timed steps", file=sys.stderr, flush=True)
     kern = {}
@@ -419,6 +428,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="default launch configurations (no tuning of them in the untimed preparation)")
+    ap.add_argument("--tune-save", default=None, help="write the autotune table to this file at the end")
     ap.add_argument("--graphs", action="store_true",
                     help="frame H-applies captured and replayed as HIP graphs (eahp_problem_set_graphs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -519,6 +529,8 @@ def main():
                           "ground_states_per_s": (1.0 / other["ground_state_s"]) if other["ground_state_s"] else None,
                           "ground_state_iters": other["ground_state_iters"]}
     out["autotune"] = B.autotune_report().splitlines() if not args.no_autotune else None
+    if args.tune_save:
+        B.autotune_save(args.tune_save)
     if args.serving_sample > 0:
         sv = serving_sample(args)
         out["p50_latency_s"] = sv["p50_latency_s"]

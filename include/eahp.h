@@ -286,18 +286,48 @@ int eahp_problem_graph_stats(const eahp_problem* pb, int64_t* captured, int64_t*
 
 /* Launch-configuration autotuner (process-wide).  Some kernels have several
  * valid launch configurations with identical results and a speed that depends
- * on the shape and the chip (the work-group count of the multi-work-group
- * Householder reduction of the projected systems of Algorithm 4).  With
- * enable(1), the first call of such a kernel in a shape class times every
- * candidate on copies of its inputs (extra device allocations, the caller's
- * stream synchronised) and keeps the fastest for the rest of the process;
- * with enable(0) (the default) the default configuration is used and the
- * kept choices are ignored.  report writes the table as text, one line per
- * shape class ("dev<N> <kernel> <class>: choice <c> ms <t0> <t1> ..."), into
- * buf (at most len bytes, NUL-terminated; buf may be NULL) and the size it
+ * on the shape and the chip: the tile shape of the complex block products of
+ * Secs. 5.1-5.2 and the work-group count of the multi-work-group Householder
+ * reduction of large Hermitian matrices.  The table maps
+ * "<arch>/<CUs> <kernel> <shape class>" to a choice.
+ * enable(mode): 0 (the default) the default configuration everywhere;
+ * 1 the table's choice, and the first call in a class the table lacks times
+ * every candidate on scratch outputs or copies of its inputs (extra device
+ * allocations, the caller's stream synchronised) and keeps the fastest;
+ * 2 the table's choices, nothing timed (classes it lacks take the default).
+ * The first switch to mode 1 or 2 loads the file tune_table.txt beside the
+ * library, if there is one.  EAHP_EINVAL for another mode.
+ * load(path, added): adds the entries of a saved table (entries already
+ * present are kept); *added (may be NULL) gets their number; EAHP_EINVAL if
+ * the file cannot be read or a line is malformed.  save(path): writes the
+ * table.  report writes the table as text, one line per class
+ * ("<arch>/<CUs> <kernel> <class>: choice <c> ms <t0> <t1> ..."), into buf
+ * (at most len bytes, NUL-terminated; buf may be NULL) and the size it
  * needs, NUL included, into *needed (may be NULL).  Host-only calls. */
-int eahp_autotune_enable(int on);
+int eahp_autotune_enable(int mode);
+int eahp_autotune_load(const char* path, int* added);
+int eahp_autotune_save(const char* path);
 int eahp_autotune_report(char* buf, size_t len, size_t* needed);
+/* Forces candidate `choice` (clamped to the last) of the tile shapes of the
+ * complex block products for every later product, whether tuning is on or
+ * not; -1 returns to the tuned or default choice.  The shapes give identical
+ * results, so this only changes speed; it lets tests compare every shape.
+ * Host-only call. */
+int eahp_autotune_force(int choice);
+
+/* Complex block products on device frames, the building blocks of Secs. 5.1
+ * and 5.2 (Gram matrices V^* W, frame updates V Y), column-major:
+ *   op 0: C (a x b, ldc) = A^H B + beta C, summed over n rows;
+ *         A n x a (lda >= n), B n x b (ldb >= n);
+ *   op 1: C (n x b, ldc) = A M + beta C; A n x a (lda >= n), M = B a x b
+ *         (ldb >= a).
+ * fp32 = 0: complex double, 1: complex float (interleaved re, im).  Products
+ * of op 0 sum the row splits in a fixed order (same bits on every run); op 0
+ * allocates its partial tiles for the call.  Runs on the context's stream
+ * and returns after it has finished.  EAHP_EINVAL for a bad op, negative
+ * size, short leading dimension or null operand. */
+int eahp_block_product(eahp_ctx* ctx, int op, int fp32, int64_t n, int a, int b, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, void* C, int64_t ldc, double beta);
 
 /* Layout of a system without touching the device: plane waves per k-point
  * (npw_per_k[nk], the row counts of the k-blocks of a frame), the FFT box and

@@ -141,6 +141,11 @@ def load_library():
         "eahp_prof_read": ([vp, C.c_int, dp, i64p, dp], C.c_int),
         "eahp_autotune_enable": ([C.c_int], C.c_int),
         "eahp_autotune_report": ([C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
+        "eahp_autotune_force": ([C.c_int], C.c_int),
+        "eahp_autotune_load": ([C.c_char_p, ip], C.c_int),
+        "eahp_autotune_save": ([C.c_char_p], C.c_int),
+        "eahp_block_product": ([vp, C.c_int, C.c_int, C.c_int64, C.c_int, C.c_int, vp, C.c_int64, vp, C.c_int64, vp,
+                                C.c_int64, C.c_double], C.c_int),
         "eahp_strerror": ([C.c_int], C.c_char_p),
         "eahp_last_error": ([], C.c_char_p),
     }
@@ -274,8 +279,27 @@ def linesearch_host(evaluate, f0, df0, tau0, params):
 
 
 def autotune_enable(on=True):
-    """Switch the launch-configuration autotuner of libeahp on or off (process-wide)."""
-    _check(load_library().eahp_autotune_enable(1 if on else 0))
+    """Autotuner mode (process-wide): False/0 off, True/1 tune classes the
+    table lacks, 2 use the table's choices without timing anything."""
+    _check(load_library().eahp_autotune_enable(int(on)))
+
+
+def autotune_load(path):
+    """Add the entries of a saved autotune table; returns how many were new."""
+    n = C.c_int()
+    _check(load_library().eahp_autotune_load(str(path).encode(), C.byref(n)))
+    return n.value
+
+
+def autotune_save(path):
+    """Write the autotune table to a text file."""
+    _check(load_library().eahp_autotune_save(str(path).encode()))
+
+
+def autotune_force(choice):
+    """Force tile shape `choice` of the complex block products (-1: back to
+    the tuned or default shape)."""
+    _check(load_library().eahp_autotune_force(int(choice)))
 
 
 def autotune_report():
@@ -385,6 +409,20 @@ class Problem:
     # ---- buffers --------------------------------------------------------
     def empty_frame(self):
         return self.torch.empty(self.size, dtype=self.torch.complex128, device=self.device)
+
+    def block_product(self, op, A, B, Cout, beta=0.0):
+        """eahp_block_product on device tensors in column-major storage: a
+        tensor of shape (cols, rows), contiguous, complex64 or complex128.
+        op 0: Cout (a x b) = A^H B + beta Cout; op 1: Cout (n x b) = A B + beta Cout."""
+        fp32 = 1 if A.dtype == self.torch.complex64 else 0
+        for t in (A, B, Cout):
+            if not t.is_contiguous() or t.dtype != A.dtype or t.dim() != 2:
+                raise ValueError("block_product: contiguous 2-D tensors of one complex dtype")
+        a, n = A.shape
+        b = B.shape[0]
+        _check(self.lib.eahp_block_product(self.ctx, int(op), fp32, n, a, b, _ptr(A), max(1, n), _ptr(B),
+                                           max(1, B.shape[1]), _ptr(Cout), max(1, Cout.shape[1]), float(beta)))
+        return Cout
 
     def to_device(self, blocks):
         return self.torch.from_numpy(frame_from_blocks(self.npw, self.p, blocks)).to(self.device)

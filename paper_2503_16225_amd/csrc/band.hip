@@ -108,9 +108,18 @@ __global__ void __launch_bounds__(1024) k_band_panel(int m, z64* P, int64_t ldp,
       for (int s = 0; s < 4 && s < RPT; ++s)
         if (s == (i >> 4)) xch::put_z(rowv + (int64_t)i * 64 + lane, a[s]);
     }
-    // wave w adds the partials of work-groups w, w + 16, ... in order
+    // wave w adds the partials of work-groups w, w + 16, ... in order (polled
+    // four at a time)
     z64 pp = mk<double>(0.0, 0.0);
-    for (int gg = w; gg < G; gg += 16) pp = cadd<double>(pp, xch::poll_z(part + ((int64_t)i * G + gg) * 64 + lane, ok));
+    const int cnt = w < G ? (G - 1 - w) / 16 + 1 : 0;
+    for (int j0 = 0; j0 < cnt; j0 += 4) {
+      z64 pv[4];
+      const int nn = min(4, cnt - j0);
+      xch::poll_zn<4>(part + ((int64_t)i * G + w + 16 * j0) * 64 + lane, 16 * 64, nn, pv, ok);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < nn) pp = cadd<double>(pp, pv[j]);
+    }
     red2[w][lane] = pp;
     if (w == 15) rsh[lane] = xch::poll_z(rowv + (int64_t)i * 64 + lane, ok);
     __syncthreads();

@@ -857,6 +857,40 @@ int eahp_problem_graph_stats(const eahp_problem* pb, int64_t* captured, int64_t*
   });
 }
 
+int eahp_block_product(eahp_ctx* ctx, int op, int fp32, int64_t n, int a, int b, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, void* C, int64_t ldc, double beta) {
+  return guarded([&] {
+    if (!ctx) fail(EAHP_EINVAL, "null context");
+    if ((op != 0 && op != 1) || n < 0 || a < 0 || b < 0) fail(EAHP_EINVAL, "bad product operation or sizes");
+    const int64_t rows_c = op == 0 ? a : n;
+    if (lda < std::max<int64_t>(1, n) || ldb < std::max<int64_t>(1, op == 0 ? n : a) ||
+        ldc < std::max<int64_t>(1, rows_c))
+      fail(EAHP_EINVAL, "leading dimension too small");
+    const int64_t rows_b = op == 0 ? n : a;
+    if ((n > 0 && a > 0 && !A) || (rows_b > 0 && b > 0 && !B) || (rows_c > 0 && b > 0 && !C))
+      fail(EAHP_EINVAL, "null operand");
+    HIPCK(hipSetDevice(ctx->device));
+    DevMem part;
+    hipStream_t st = ctx->stream;
+    if (fp32) {
+      if (op == 0)
+        gemm_hn<float>(st, n, a, b, static_cast<const c32*>(A), lda, static_cast<const c32*>(B), ldb,
+                       static_cast<c32*>(C), ldc, 1.0, beta, part);
+      else
+        gemm_nn<float>(st, n, a, b, static_cast<const c32*>(A), lda, static_cast<const c32*>(B), ldb, 0,
+                       static_cast<c32*>(C), ldc, 1.0, 0.0, beta);
+    } else {
+      if (op == 0)
+        gemm_hn<double>(st, n, a, b, static_cast<const z64*>(A), lda, static_cast<const z64*>(B), ldb,
+                        static_cast<z64*>(C), ldc, 1.0, beta, part);
+      else
+        gemm_nn<double>(st, n, a, b, static_cast<const z64*>(A), lda, static_cast<const z64*>(B), ldb, 0,
+                        static_cast<z64*>(C), ldc, 1.0, 0.0, beta);
+    }
+    HIPCK(hipStreamSynchronize(st));
+  });
+}
+
 int eahp_prof_enable(eahp_ctx* ctx, int on) {
   return guarded([&] {
     if (!ctx) fail(EAHP_EINVAL, "null context");

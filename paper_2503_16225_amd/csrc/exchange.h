@@ -40,5 +40,42 @@ __device__ __forceinline__ z64 poll_z(const z64* p, bool& ok) {
   return mk<double>(__longlong_as_double((long long)x), __longlong_as_double((long long)y));
 }
 
+// Polls the n <= N slots p, p + stride, ... together: the loads of every
+// slot not yet filled are in flight at once, so a wave waits about one
+// round trip for all of them instead of one per slot.  v[j] is slot j's value.
+template <int N>
+__device__ __forceinline__ void poll_zn(const z64* p, int64_t stride, int n, z64 (&v)[N], bool& ok) {
+  unsigned long long x[N], y[N];
+  bool done[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    x[j] = y[j] = 0;
+    done[j] = j >= n;
+  }
+  for (int spins = 0;; ++spins) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (!done[j]) {
+        const unsigned long long* u = reinterpret_cast<const unsigned long long*>(p + j * stride);
+        x[j] = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        y[j] = __hip_atomic_load(u + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    bool all = true;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (!done[j]) {
+        if (x[j] != kEmpty && y[j] != kEmpty) done[j] = true;
+        else all = false;
+      }
+    if (all) break;
+    if (spins > kXchSpin) {
+      ok = false;
+      break;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = mk<double>(__longlong_as_double((long long)x[j]), __longlong_as_double((long long)y[j]));
+}
+
 }  // namespace xch
 }  // namespace eahp

@@ -7,16 +7,21 @@
 // element (4 s + l / 16, l % 16) in FP64 and (4 (l / 16) + s, l % 16) in FP32.
 //
 // gemm_hn (Gram matrices, Lambda, projector coefficients): the row dimension
-// n is split over work-groups, each computes 64 x 64 output tiles over its
-// rows and writes the raw fragments; a second kernel sums the splits in a
-// fixed order (deterministic).
-// gemm_nn (frame times small matrix): one 64 x 64 output tile per work-group,
-// the inner dimension streamed through LDS 16 at a time, the tile staged
-// through LDS for coalesced stores.
+// n is split over work-groups, each computes output tiles over its rows and
+// writes the raw fragments; a second kernel sums the splits in a fixed order
+// (deterministic).
+// gemm_nn (frame times small matrix): one output tile per work-group, the
+// inner dimension streamed through LDS 16 at a time, the tile staged through
+// LDS for coalesced stores.
+// Both come in several tile shapes with identical results (see below).
 #include <atomic>
+#include <functional>
+#include <string>
+#include <vector>
 
 #include "devcommon.h"
 #include "kernels.h"
+#include "ops.h"
 
 namespace eahp {
 
@@ -40,8 +45,17 @@ struct Mfma<float> {
   __device__ static int row(int l, int s) { return 4 * (l >> 4) + s; }
 };
 
-constexpr int MT = 64;       // output tile edge
+// Tile shapes.  A work-group of four waves computes a TR x TC output tile,
+// TR = WR BU 16 and TC = WC BV 16: the waves form a WR x WC grid and each
+// holds BU x BV blocks of 16 x 16 (real and imaginary accumulators).  Every
+// shape accumulates each output element over the inner dimension in the same
+// order (chunks of 16 from the start of its row range, four per MFMA), so the
+// shapes give identical results and differ only in speed; the autotuner picks
+// one per shape class.
 constexpr int kXcds = 8;     // MI355X: 8 accelerator dies, each with its own L2
+constexpr int MK = 16;       // chunk of the inner dimension
+constexpr int LDK = MK + 1;  // padded LDS row
+constexpr int MT = 64;       // tile edge of the reference shape (sets the row split of gemm_hn)
 
 // Work-groups are handed to the dies round-robin in the order of their
 // linear index.  With grouping on, linear index L is mapped to logical
@@ -54,91 +68,81 @@ __device__ __forceinline__ int64_t xcd_order(int64_t L, int64_t N, int group) {
   const int64_t d = L % kXcds, j = L / kXcds, q = N / kXcds, r = N % kXcds;
   return d * q + (d < r ? d : r) + j;
 }
-constexpr int MK = 16;       // chunk of the inner dimension
-constexpr int LDK = MK + 1;  // padded LDS row
+
+__device__ __forceinline__ int64_t linear_block() {
+  return blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+}
 
 }  // namespace
 
-// Fragment layout of the partial tiles: for each (batch, split, tile, wave,
-// u, v) a block of 64 lanes x 4 slots (complex).
-template <typename T>
+// Partial tiles of gemm_hn, independent of the tile shape: per (batch, split)
+// the 16 x 16 blocks of the a x b result, block (bi, bj) at (bj nbi + bi) 256,
+// inside a block lane l's slot s at 4 l + s (the MFMA result layout).
+template <typename T, int WR, int WC, int BU, int BV>
 __global__ void __launch_bounds__(256) k_gemm_hn_mfma(int64_t n, int a, int b, const cplx<T>* __restrict__ A,
                                                       int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb,
                                                       int64_t rps, cplx<T>* __restrict__ part, int64_t sA,
                                                       int64_t sB, int group) {
-  __shared__ T Ar[MT * LDK], Ai[MT * LDK], Br[MT * LDK], Bi[MT * LDK];
+  constexpr int TR = WR * BU * 16, TC = WC * BV * 16, NLA = TR / 16, NLB = TC / 16;
+  __shared__ T lds[2 * (TR + TC) * LDK];
+  T* Ar = lds;
+  T* Ai = Ar + TR * LDK;
+  T* Br = Ai + TR * LDK;
+  T* Bi = Br + TC * LDK;
   using M = Mfma<T>;
   using acc_t = typename M::acc;
-  const int tiles_a = (a + MT - 1) / MT;
-  const int tiles = tiles_a * ((b + MT - 1) / MT);
-  // logical order: the tiles of one column block of A (all tb) consecutive
-  const int64_t nwg = (int64_t)gridDim.x * gridDim.y * gridDim.z;
-  const int64_t lin = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
-  const int64_t lg = xcd_order(lin, nwg, group);
-  const int tiles_b = tiles / tiles_a;
+  const int tiles_a = (a + TR - 1) / TR, tiles_b = (b + TC - 1) / TC;
+  const int tiles = tiles_a * tiles_b;
+  // logical order: the tiles of one row block (all tb) consecutive
+  const int64_t lg = xcd_order(linear_block(), (int64_t)gridDim.x * gridDim.y * gridDim.z, group);
   const int tb = (int)(lg % tiles_b), ta = (int)((lg / tiles_b) % tiles_a);
   const int split = (int)((lg / tiles) % gridDim.y), batch = (int)(lg / ((int64_t)tiles * gridDim.y));
-  const int tile = ta + tiles_a * tb;
   A += batch * sA;
   B += batch * sB;
   const int64_t r0 = split * rps, r1 = min(n, r0 + rps);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
-  acc_t cre[2][2], cim[2][2];
+  const int wi = (w % WR) * BU * 16, wj = (w / WR) * BV * 16;
+  acc_t cre[BU][BV], cim[BU][BV];
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int u = 0; u < BU; ++u)
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < BV; ++v) {
       cre[u][v] = acc_t{0, 0, 0, 0};
       cim[u][v] = acc_t{0, 0, 0, 0};
     }
-  const int lc = t >> 2, lr = (t & 3) * 4;
-  const int ia = ta * MT + lc, jb = tb * MT + lc;
-  const cplx<T>* Ac = A + (int64_t)min(ia, a - 1) * lda;
-  const cplx<T>* Bc = B + (int64_t)min(jb, b - 1) * ldb;
-  // in single precision the next chunk's rows are loaded into registers while
-  // the current one is multiplied; in double precision the chunk is loaded
-  // and stored directly (the extra registers would cost occupancy)
+  // loader: thread t takes inner index t % 16 of columns t / 16 + 16 i
+  const int lk = t & 15, lc = t >> 4;
+  const int ia0 = ta * TR + lc, jb0 = tb * TC + lc;
+  const cplx<T>* Ac = A + (int64_t)ia0 * lda + lk;
+  const cplx<T>* Bc = B + (int64_t)jb0 * ldb + lk;
+  // in single precision the next chunk is loaded into registers while the
+  // current one is multiplied; in double precision it is loaded and stored
+  // directly (the extra registers would cost occupancy)
   constexpr bool kPre = sizeof(T) == 4;
-  cplx<T> pa[4], pb[4];
-  auto fetch = [&](int64_t r) {
+  cplx<T> pa[NLA], pb[NLB];
+  auto fetch = [&](int64_t r) __attribute__((always_inline)) {
+    const bool rok = r + lk < r1;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t row = r + lr + q;
-      pa[q] = mk<T>(0, 0);
-      pb[q] = mk<T>(0, 0);
-      if (row < r1) {
-        if (ia < a) pa[q] = Ac[row];
-        if (jb < b) pb[q] = Bc[row];
-      }
-    }
+    for (int i = 0; i < NLA; ++i)
+      pa[i] = (rok && ia0 + 16 * i < a) ? Ac[r + (int64_t)16 * i * lda] : mk<T>(0, 0);
+#pragma unroll
+    for (int i = 0; i < NLB; ++i)
+      pb[i] = (rok && jb0 + 16 * i < b) ? Bc[r + (int64_t)16 * i * ldb] : mk<T>(0, 0);
   };
   if constexpr (kPre) {
     if (r0 < r1) fetch(r0);
   }
   for (int64_t r = r0; r < r1; r += MK) {
-    if constexpr (kPre) {
+    if constexpr (!kPre) fetch(r);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        Ar[lc * LDK + lr + q] = pa[q].x;
-        Ai[lc * LDK + lr + q] = pa[q].y;
-        Br[lc * LDK + lr + q] = pb[q].x;
-        Bi[lc * LDK + lr + q] = pb[q].y;
-      }
-    } else {
+    for (int i = 0; i < NLA; ++i) {
+      Ar[(lc + 16 * i) * LDK + lk] = pa[i].x;
+      Ai[(lc + 16 * i) * LDK + lk] = pa[i].y;
+    }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t row = r + lr + q;
-        cplx<T> av = mk<T>(0, 0), bv = mk<T>(0, 0);
-        if (row < r1) {
-          if (ia < a) av = Ac[row];
-          if (jb < b) bv = Bc[row];
-        }
-        Ar[lc * LDK + lr + q] = av.x;
-        Ai[lc * LDK + lr + q] = av.y;
-        Br[lc * LDK + lr + q] = bv.x;
-        Bi[lc * LDK + lr + q] = bv.y;
-      }
+    for (int i = 0; i < NLB; ++i) {
+      Br[(lc + 16 * i) * LDK + lk] = pb[i].x;
+      Bi[(lc + 16 * i) * LDK + lk] = pb[i].y;
     }
     __syncthreads();
     if constexpr (kPre) {
@@ -147,44 +151,53 @@ __global__ void __launch_bounds__(256) k_gemm_hn_mfma(int64_t n, int a, int b, c
 #pragma unroll
     for (int kk = 0; kk < MK; kk += 4) {
       const int kr = kk + (lane >> 4), cc = lane & 15;
-      T ar[2], ai[2], br[2], bi[2];
+      T ar[BU], ai[BU], br[BV], bi[BV];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < BU; ++u) {
         ar[u] = Ar[(wi + 16 * u + cc) * LDK + kr];
         ai[u] = Ai[(wi + 16 * u + cc) * LDK + kr];
-        br[u] = Br[(wj + 16 * u + cc) * LDK + kr];
-        bi[u] = Bi[(wj + 16 * u + cc) * LDK + kr];
       }
-      // the eight accumulators take one product each before any takes its
-      // second, so consecutive MFMAs are independent
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < BV; ++v) {
+        br[v] = Br[(wj + 16 * v + cc) * LDK + kr];
+        bi[v] = Bi[(wj + 16 * v + cc) * LDK + kr];
+      }
+      // every accumulator takes one product before any takes its second, so
+      // consecutive MFMAs are independent
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
+      for (int u = 0; u < BU; ++u)
+#pragma unroll
+        for (int v = 0; v < BV; ++v) {
           cre[u][v] = M::mma(ar[u], br[v], cre[u][v]);
           cim[u][v] = M::mma(ar[u], bi[v], cim[u][v]);
         }
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < BU; ++u)
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
+        for (int v = 0; v < BV; ++v) {
           cre[u][v] = M::mma(ai[u], bi[v], cre[u][v]);
           cim[u][v] = M::mma(-ai[u], br[v], cim[u][v]);
         }
     }
     __syncthreads();
   }
-  cplx<T>* P = part + ((((int64_t)batch * gridDim.y + split) * tiles + tile) * 4 + w) * 4 * 256;
+  const int nbi = (a + 15) / 16, nbj = (b + 15) / 16;
+  cplx<T>* P = part + ((int64_t)batch * gridDim.y + split) * ((int64_t)nbi * nbj * 256);
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int u = 0; u < BU; ++u)
 #pragma unroll
-    for (int v = 0; v < 2; ++v)
+    for (int v = 0; v < BV; ++v) {
+      const int bi = (ta * TR + wi) / 16 + u, bj = (tb * TC + wj) / 16 + v;
+      if (bi < nbi && bj < nbj) {
+        cplx<T>* Q = P + ((int64_t)bj * nbi + bi) * 256 + lane * 4;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) P[(u * 2 + v) * 256 + lane * 4 + s] = mk<T>(cre[u][v][s], cim[u][v][s]);
+        for (int s = 0; s < 4; ++s) Q[s] = mk<T>(cre[u][v][s], cim[u][v][s]);
+      }
+    }
 }
 
 // C = alpha sum_splits(partials) + beta C.  A work-group takes 16 consecutive
-// fragment positions; its 16 groups of 16 threads sum every 16th split each
+// partial positions; its 16 groups of 16 threads sum every 16th split each
 // (independent loads in flight), and the 16 group sums are added in a fixed
 // order, so the result does not depend on timing.
 template <typename T>
@@ -193,9 +206,8 @@ __global__ void __launch_bounds__(256) k_gemm_hn_mfma_reduce(int a, int b, int n
                                                              int64_t sC) {
   using M = Mfma<T>;
   __shared__ double sx[16][17], sy[16][17];
-  const int tiles_a = (a + MT - 1) / MT;
-  const int tiles = tiles_a * ((b + MT - 1) / MT);
-  const int64_t per_split = (int64_t)tiles * 4 * 4 * 256;
+  const int nbi = (a + 15) / 16, nbj = (b + 15) / 16;
+  const int64_t per_split = (int64_t)nbi * nbj * 256;
   const int batch = blockIdx.y;
   C += batch * sC;
   const cplx<T>* P = part + (int64_t)batch * nsplit * per_split;
@@ -220,11 +232,11 @@ __global__ void __launch_bounds__(256) k_gemm_hn_mfma_reduce(int a, int b, int n
         tx += sx[q][j];
         ty += sy[q][j];
       }
-      const int s = (int)(f & 3), lane = (int)((f >> 2) & 63), uv = (int)((f >> 8) & 3), w = (int)((f >> 10) & 3);
-      const int tile = (int)(f >> 12);
-      const int ta = tile % tiles_a, tb = tile / tiles_a;
-      const int i = ta * MT + (w & 1) * 32 + (uv >> 1) * 16 + M::row(lane, s);
-      const int jj = tb * MT + (w >> 1) * 32 + (uv & 1) * 16 + (lane & 15);
+      const int s = (int)(f & 3), lane = (int)((f >> 2) & 63);
+      const int64_t blk = f >> 8;
+      const int bi = (int)(blk % nbi), bj = (int)(blk / nbi);
+      const int i = bi * 16 + M::row(lane, s);
+      const int jj = bj * 16 + (lane & 15);
       if (i < a && jj < b) {
         cplx<T>* c = C + i + (int64_t)jj * ldc;
         cplx<T> o;
@@ -237,139 +249,146 @@ __global__ void __launch_bounds__(256) k_gemm_hn_mfma_reduce(int a, int b, int n
   }
 }
 
-template <typename T>
+template <typename T, int WR, int WC, int BU, int BV>
 __global__ void __launch_bounds__(256) k_gemm_nn_mfma(int64_t n, int a, int b, const cplx<T>* __restrict__ A,
                                                       int64_t lda, const cplx<T>* __restrict__ Mm, int64_t ldm,
                                                       int opM, cplx<T>* __restrict__ C, int64_t ldc, double are,
                                                       double aim, double beta, int64_t sA, int64_t sM, int64_t sC,
                                                       int group) {
-  // input planes; reused as the 64 x 32 output staging tile (complex, row fastest)
-  __shared__ T lds[4 * MT * LDK];
+  constexpr int TR = WR * BU * 16, TC = WC * BV * 16, NLA = TR / 16, NLB = TC / 16;
+  // input planes; reused as the TR x 16 output staging tile (complex, row fastest)
+  constexpr int kPlanes = 2 * (TR + TC) * LDK, kStage = 2 * 16 * (TR + 1);
+  __shared__ T lds[kPlanes > kStage ? kPlanes : kStage];
   T* Ar = lds;
-  T* Ai = Ar + MT * LDK;
-  T* Mr = Ai + MT * LDK;
-  T* Mi = Mr + MT * LDK;
+  T* Ai = Ar + TR * LDK;
+  T* Mr = Ai + TR * LDK;
+  T* Mi = Mr + TC * LDK;
   using Mf = Mfma<T>;
   using acc_t = typename Mf::acc;
   // logical order: the column tiles of one row block of A consecutive
-  const int64_t nwg = (int64_t)gridDim.x * gridDim.y * gridDim.z;
-  const int64_t lin = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
-  const int64_t lg = xcd_order(lin, nwg, group);
+  const int64_t lg = xcd_order(linear_block(), (int64_t)gridDim.x * gridDim.y * gridDim.z, group);
   const int tcol = (int)(lg % gridDim.y);
   const int64_t trow = (lg / gridDim.y) % gridDim.x;
   const int batch = (int)(lg / ((int64_t)gridDim.x * gridDim.y));
   A += batch * sA;
   Mm += batch * sM;
   C += batch * sC;
-  const int64_t row0 = trow * MT;
-  const int col0 = tcol * MT;
+  const int64_t row0 = trow * TR;
+  const int col0 = tcol * TC;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
-  acc_t cre[2][2], cim[2][2];
+  const int wi = (w % WR) * BU * 16, wj = (w / WR) * BV * 16;
+  acc_t cre[BU][BV], cim[BU][BV];
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int u = 0; u < BU; ++u)
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < BV; ++v) {
       cre[u][v] = acc_t{0, 0, 0, 0};
       cim[u][v] = acc_t{0, 0, 0, 0};
     }
-  const int ak = t >> 4, arw = (t & 15) * 4;  // A loader: inner index ak, rows arw..arw+3
-  const int mc = t >> 2, mq = (t & 3) * 4;    // M loader: column mc, inner indices mq..mq+3
-  // the next chunk of A and M is loaded into registers while the current one
-  // is multiplied (single precision only, as in k_gemm_hn_mfma)
+  // A loader: element e = t + 256 i of the TR x 16 chunk is row e % TR, inner
+  // index e / TR (rows fastest, coalesced); M loader: element e of the
+  // 16 x TC chunk is inner index e % 16, column e / 16 (M) or column e % TC,
+  // inner index e / TC (M^H, whose columns are rows in memory)
   constexpr bool kPre = sizeof(T) == 4;
-  cplx<T> pa[4], pm[4];
-  auto fetch = [&](int k0) {
-    const int k = k0 + ak;
+  cplx<T> pa[NLA], pm[NLB];
+  auto fetch = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t row = row0 + arw + q;
-      pa[q] = (row < n && k < a) ? A[row + (int64_t)k * lda] : mk<T>(0, 0);
+    for (int i = 0; i < NLA; ++i) {
+      const int e = t + 256 * i, k = k0 + e / TR;
+      const int64_t row = row0 + e % TR;
+      pa[i] = (row < n && k < a) ? A[row + (int64_t)k * lda] : mk<T>(0, 0);
     }
-    const int j = col0 + mc;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kq = k0 + mq + q;
+    for (int i = 0; i < NLB; ++i) {
+      const int e = t + 256 * i;
       cplx<T> mv = mk<T>(0, 0);
-      if (j < b && kq < a) {
-        if (opM == 0) mv = Mm[kq + (int64_t)j * ldm];
-        else {
-          const cplx<T> x = Mm[j + (int64_t)kq * ldm];
+      if (opM == 0) {
+        const int k = k0 + (e & 15), j = col0 + (e >> 4);
+        if (j < b && k < a) mv = Mm[k + (int64_t)j * ldm];
+      } else {
+        const int k = k0 + e / TC, j = col0 + e % TC;
+        if (j < b && k < a) {
+          const cplx<T> x = Mm[j + (int64_t)k * ldm];
           mv = mk<T>(x.x, -x.y);
         }
       }
-      pm[q] = mv;
+      pm[i] = mv;
     }
   };
   if (kPre && a > 0) fetch(0);
   for (int k0 = 0; k0 < a; k0 += MK) {
     if (!kPre) fetch(k0);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      Ar[(arw + q) * LDK + ak] = pa[q].x;
-      Ai[(arw + q) * LDK + ak] = pa[q].y;
-      Mr[mc * LDK + mq + q] = pm[q].x;
-      Mi[mc * LDK + mq + q] = pm[q].y;
+    for (int i = 0; i < NLA; ++i) {
+      const int e = t + 256 * i;
+      Ar[(e % TR) * LDK + e / TR] = pa[i].x;
+      Ai[(e % TR) * LDK + e / TR] = pa[i].y;
+    }
+#pragma unroll
+    for (int i = 0; i < NLB; ++i) {
+      const int e = t + 256 * i;
+      const int jj = opM == 0 ? (e >> 4) : e % TC, kk = opM == 0 ? (e & 15) : e / TC;
+      Mr[jj * LDK + kk] = pm[i].x;
+      Mi[jj * LDK + kk] = pm[i].y;
     }
     __syncthreads();
     if (kPre && k0 + MK < a) fetch(k0 + MK);
 #pragma unroll
     for (int kk = 0; kk < MK; kk += 4) {
       const int kr = kk + (lane >> 4), cc = lane & 15;
-      T ar[2], ai[2], mr[2], mi[2];
+      T ar[BU], ai[BU], mr[BV], mi[BV];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < BU; ++u) {
         ar[u] = Ar[(wi + 16 * u + cc) * LDK + kr];
         ai[u] = Ai[(wi + 16 * u + cc) * LDK + kr];
-        mr[u] = Mr[(wj + 16 * u + cc) * LDK + kr];
-        mi[u] = Mi[(wj + 16 * u + cc) * LDK + kr];
+      }
+#pragma unroll
+      for (int v = 0; v < BV; ++v) {
+        mr[v] = Mr[(wj + 16 * v + cc) * LDK + kr];
+        mi[v] = Mi[(wj + 16 * v + cc) * LDK + kr];
       }
       // one product per accumulator before the second (independent consecutive MFMAs)
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < BU; ++u)
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
+        for (int v = 0; v < BV; ++v) {
           cre[u][v] = Mf::mma(ar[u], mr[v], cre[u][v]);
           cim[u][v] = Mf::mma(ar[u], mi[v], cim[u][v]);
         }
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < BU; ++u)
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
+        for (int v = 0; v < BV; ++v) {
           cre[u][v] = Mf::mma(-ai[u], mi[v], cre[u][v]);
           cim[u][v] = Mf::mma(ai[u], mr[v], cim[u][v]);
         }
     }
     __syncthreads();
   }
-  // epilogue in two halves of 32 columns through LDS: St[col][row] (row fastest, stride 65)
+  // epilogue: 16 columns at a time through LDS, St[col][row] (row fastest,
+  // stride TR + 1); the waves of one wave column write, all threads store
   cplx<T>* St = reinterpret_cast<cplx<T>*>(lds);
-  constexpr int SLD = MT + 1;
+  constexpr int SLD = TR + 1;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    if ((w >> 1) == h) {
+  for (int wc = 0; wc < WC; ++wc)
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < BV; ++v) {
+      if (w / WR == wc) {
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
+        for (int u = 0; u < BU; ++u)
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const int rr = wi + 16 * u + Mf::row(lane, s);
-            const int cc = 16 * v + (lane & 15);
-            St[cc * SLD + rr] = mk<T>(cre[u][v][s], cim[u][v][s]);
-          }
-    }
-    __syncthreads();
-    {
-      const int rr = t & 63;
-      const int64_t i = row0 + rr;
+          for (int s = 0; s < 4; ++s)
+            St[(lane & 15) * SLD + wi + 16 * u + Mf::row(lane, s)] = mk<T>(cre[u][v][s], cim[u][v][s]);
+      }
+      __syncthreads();
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int cc = (t >> 6) * 8 + q;
-        const int j = col0 + h * 32 + cc;
-        if (i < n && j < b) {
+      for (int i = 0; i < TR / 16; ++i) {
+        const int e = t + 256 * i, rr = e % TR, cc = e / TR;
+        const int64_t gi = row0 + rr;
+        const int j = col0 + wc * BV * 16 + v * 16 + cc;
+        if (gi < n && j < b) {
           const cplx<T> x = St[cc * SLD + rr];
-          cplx<T>* c = C + i + (int64_t)j * ldc;
+          cplx<T>* c = C + gi + (int64_t)j * ldc;
           double ox = are * (double)x.x - aim * (double)x.y, oy = are * (double)x.y + aim * (double)x.x;
           if (beta != 0.0) {
             ox += beta * (double)c->x;
@@ -378,12 +397,91 @@ __global__ void __launch_bounds__(256) k_gemm_nn_mfma(int64_t n, int a, int b, c
           *c = mk<T>((T)ox, (T)oy);
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
-  }
 }
 
-// Split of the row dimension: about four work-groups per CU (the loads of one
+namespace {
+
+// ---------------------------------------------------------------- shapes
+struct Shape {
+  int wr, wc, bu, bv;
+  int tr() const { return wr * bu * 16; }
+  int tc() const { return wc * bv * 16; }
+};
+
+// candidate 0 is the default (64 x 64)
+template <typename T>
+struct Shapes;
+#define EAHP_GEMM_SHAPES_F32(X) X(2, 2, 2, 2) X(2, 2, 4, 2) X(2, 2, 2, 4) X(2, 2, 4, 4) X(4, 1, 2, 9) X(4, 1, 4, 4)
+#define EAHP_GEMM_SHAPES_F64(X) X(2, 2, 2, 2) X(2, 2, 4, 2) X(2, 2, 2, 4)
+
+using HnFn = void (*)(hipStream_t, dim3, int64_t, int, int, const void*, int64_t, const void*, int64_t, int64_t, void*,
+                      int64_t, int64_t, int);
+using NnFn = void (*)(hipStream_t, dim3, int64_t, int, int, const void*, int64_t, const void*, int64_t, int, void*,
+                      int64_t, double, double, double, int64_t, int64_t, int64_t, int);
+
+template <typename T, int WR, int WC, int BU, int BV>
+void launch_hn(hipStream_t st, dim3 g, int64_t n, int a, int b, const void* A, int64_t lda, const void* B, int64_t ldb,
+               int64_t rps, void* part, int64_t sA, int64_t sB, int group) {
+  hipLaunchKernelGGL((k_gemm_hn_mfma<T, WR, WC, BU, BV>), g, dim3(256), 0, st, n, a, b,
+                     static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(B), ldb, rps,
+                     static_cast<cplx<T>*>(part), sA, sB, group);
+}
+template <typename T, int WR, int WC, int BU, int BV>
+void launch_nn(hipStream_t st, dim3 g, int64_t n, int a, int b, const void* A, int64_t lda, const void* M, int64_t ldm,
+               int opM, void* C, int64_t ldc, double are, double aim, double beta, int64_t sA, int64_t sM, int64_t sC,
+               int group) {
+  hipLaunchKernelGGL((k_gemm_nn_mfma<T, WR, WC, BU, BV>), g, dim3(256), 0, st, n, a, b,
+                     static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(M), ldm, opM,
+                     static_cast<cplx<T>*>(C), ldc, are, aim, beta, sA, sM, sC, group);
+}
+
+template <typename T>
+struct ShapeTable {
+  std::vector<Shape> shape;
+  std::vector<HnFn> hn;
+  std::vector<NnFn> nn;
+};
+
+#define EAHP_GEMM_ADD(WR, WC, BU, BV)                        \
+  t.shape.push_back(Shape{WR, WC, BU, BV});                  \
+  t.hn.push_back(&launch_hn<T, WR, WC, BU, BV>);             \
+  t.nn.push_back(&launch_nn<T, WR, WC, BU, BV>);
+
+template <typename T>
+const ShapeTable<T>& shapes() {
+  static const ShapeTable<T> tab = [] {
+    ShapeTable<T> t;
+    if constexpr (sizeof(T) == 4) {
+      EAHP_GEMM_SHAPES_F32(EAHP_GEMM_ADD)
+    } else {
+      EAHP_GEMM_SHAPES_F64(EAHP_GEMM_ADD)
+    }
+    return t;
+  }();
+  return tab;
+}
+#undef EAHP_GEMM_ADD
+
+// shape class of a product for the autotuner: each size rounded up to the
+// next of 64, 96, 128, 192, 256, 384, ... (half-octave steps)
+int64_t size_class(int64_t x) {
+  int64_t c = 64;
+  while (c < x) c = (c & (c - 1)) == 0 ? c + c / 2 : c / 3 * 4;
+  return c;
+}
+// products below this many flops take the default shape without tuning
+constexpr double kTuneMinFlops = 2e10;
+std::string tune_key(const char* op, int fp32, int64_t n, int a, int b, int batch) {
+  return std::string("gemm_") + op + (fp32 ? " f32" : " f64") + " n" + std::to_string(size_class(n)) + " a" +
+         std::to_string(size_class(a)) + " b" + std::to_string(size_class(b)) + (batch > 1 ? " batched" : "");
+}
+
+}  // namespace
+
+// Split of the row dimension (set with the reference 64 x 64 tiles, the
+// same for every tile shape): about four work-groups per CU (the loads of one
 // overlap the products of the others), at least 4 chunks of rows each, the
 // partial tiles (written and read once more) under half the input bytes, and
 // at most max_part complex partial values in all.
@@ -391,7 +489,7 @@ static void hn_split(int64_t n, int a, int b, int batch, int64_t max_part, int64
                      int64_t& per_split) {
   const int tiles = ((a + MT - 1) / MT) * ((b + MT - 1) / MT);
   const int64_t in_elems = n * (int64_t)(a + b);
-  per_split = (int64_t)tiles * 4 * 4 * 256;
+  per_split = (int64_t)((a + 15) / 16) * ((b + 15) / 16) * 256;
   nsplit = (1024 + tiles * batch - 1) / (tiles * batch);
   nsplit = std::min<int64_t>(nsplit, (n + 4 * MK - 1) / (4 * MK));
   nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, in_elems / (2LL * tiles * MT * MT)));
@@ -411,25 +509,56 @@ static std::atomic<int> g_xcd_group{1};
 void gemm_set_xcd_group(int on) { g_xcd_group.store(on ? 1 : 0); }
 
 size_t gemm_hn_min_part(int a, int b, int batch) {
-  const int tiles = ((a + MT - 1) / MT) * ((b + MT - 1) / MT);
-  return (size_t)tiles * 4 * 4 * 256 * batch;
+  return (size_t)((a + 15) / 16) * ((b + 15) / 16) * 256 * batch;
+}
+
+int gemm_shape_count(int fp32) { return fp32 ? (int)shapes<float>().shape.size() : (int)shapes<double>().shape.size(); }
+
+template <typename T>
+static void hn_launch(hipStream_t st, int c, int64_t n, int a, int b, const cplx<T>* A, int64_t lda,
+                      const cplx<T>* B, int64_t ldb, int64_t rps, int64_t nsplit, cplx<T>* part, int batch,
+                      int64_t sA, int64_t sB) {
+  const auto& tab = shapes<T>();
+  const Shape& sh = tab.shape[c];
+  const int tiles = ((a + sh.tr() - 1) / sh.tr()) * ((b + sh.tc() - 1) / sh.tc());
+  tab.hn[c](st, dim3(tiles, (unsigned)nsplit, batch), n, a, b, A, lda, B, ldb, rps, part, sA, sB, g_xcd_group.load());
+  HIPCK(hipGetLastError());
+}
+
+template <typename T>
+static void hn_reduce(hipStream_t st, int a, int b, int64_t nsplit, int64_t per_split, const cplx<T>* part,
+                      cplx<T>* C, int64_t ldc, double alpha, double beta, int batch, int64_t sC) {
+  const int nb = (int)std::min<int64_t>(4096, (per_split + 15) / 16);
+  hipLaunchKernelGGL((k_gemm_hn_mfma_reduce<T>), dim3(nb, batch), dim3(256), 0, st, a, b, (int)nsplit, part, C, ldc,
+                     alpha, beta, sC);
+  HIPCK(hipGetLastError());
+}
+
+// The tile shape of a product: the forced one, else the autotuner's for the
+// shape class (tuned here on first use when tuning is on and `tune` allows:
+// the candidates run on scratch outputs only), else the default.
+template <typename T>
+static int pick_shape(hipStream_t st, const char* op, int64_t n, int a, int b, int batch, bool tune,
+                      const std::function<void(int)>& run) {
+  const int nc = (int)shapes<T>().shape.size();
+  const int f = autotune_forced();
+  if (f >= 0) return std::min(f, nc - 1);
+  if (8.0 * (double)n * a * b * batch < kTuneMinFlops) return 0;
+  const std::string key = tune_key(op, sizeof(T) == 4, n, a, b, batch);
+  return std::min(tune ? autotune(st, key, nc, run) : autotune_kept(key), nc - 1);
 }
 
 template <typename T>
 void gemm_hn_mfma_ws(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* B,
                      int64_t ldb, cplx<T>* C, int64_t ldc, double alpha, double beta, cplx<T>* part, size_t part_elems,
                      int batch, int64_t sA, int64_t sB, int64_t sC) {
-  const int tiles = ((a + MT - 1) / MT) * ((b + MT - 1) / MT);
   int64_t nsplit, rps, per_split;
   hn_split(n, a, b, batch, (int64_t)part_elems, nsplit, rps, per_split);
   if ((size_t)(nsplit * per_split * batch) > part_elems) fail(EAHP_EINVAL, "Gram product: partial buffer too small");
-  hipLaunchKernelGGL((k_gemm_hn_mfma<T>), dim3(tiles, (unsigned)nsplit, batch), dim3(256), 0, st, n, a, b, A, lda, B,
-                     ldb, rps, part, sA, sB, g_xcd_group.load());
-  HIPCK(hipGetLastError());
-  const int nb = (int)std::min<int64_t>(4096, (per_split + 15) / 16);
-  hipLaunchKernelGGL((k_gemm_hn_mfma_reduce<T>), dim3(nb, batch), dim3(256), 0, st, a, b, (int)nsplit, part, C, ldc,
-                     alpha, beta, sC);
-  HIPCK(hipGetLastError());
+  // no tuning here (no allocation, no synchronisation): the kept choice
+  const int c = pick_shape<T>(st, "hn", n, a, b, batch, false, nullptr);
+  hn_launch<T>(st, c, n, a, b, A, lda, B, ldb, rps, nsplit, part, batch, sA, sB);
+  hn_reduce<T>(st, a, b, nsplit, per_split, part, C, ldc, alpha, beta, batch, sC);
 }
 
 template <typename T>
@@ -440,17 +569,37 @@ void gemm_hn_mfma(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int
   hn_split(n, a, b, batch, INT64_MAX, nsplit, rps, per_split);
   const size_t elems = (size_t)(nsplit * per_split * batch);
   part.ensure(sizeof(cplx<T>) * elems);
-  gemm_hn_mfma_ws<T>(st, n, a, b, A, lda, B, ldb, C, ldc, alpha, beta, part.as<cplx<T>>(), elems, batch, sA, sB, sC);
+  cplx<T>* P = part.as<cplx<T>>();
+  // candidates write only the partial tiles (scratch); the reduction is the same for all
+  const int c = pick_shape<T>(st, "hn", n, a, b, batch, true, [&](int k) {
+    hn_launch<T>(st, k, n, a, b, A, lda, B, ldb, rps, nsplit, P, batch, sA, sB);
+  });
+  hn_launch<T>(st, c, n, a, b, A, lda, B, ldb, rps, nsplit, P, batch, sA, sB);
+  hn_reduce<T>(st, a, b, nsplit, per_split, P, C, ldc, alpha, beta, batch, sC);
 }
 
 template <typename T>
 void gemm_nn_mfma(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* M,
                   int64_t ldm, int opM, cplx<T>* C, int64_t ldc, double alpha_re, double alpha_im, double beta,
                   int batch, int64_t sA, int64_t sM, int64_t sC) {
-  dim3 grid((unsigned)((n + MT - 1) / MT), (b + MT - 1) / MT, batch);
-  hipLaunchKernelGGL((k_gemm_nn_mfma<T>), grid, dim3(256), 0, st, n, a, b, A, lda, M, ldm, opM, C, ldc, alpha_re,
-                     alpha_im, beta, sA, sM, sC, g_xcd_group.load());
-  HIPCK(hipGetLastError());
+  const auto& tab = shapes<T>();
+  auto launch = [&](int k, cplx<T>* Cd, int64_t ldcd, int64_t sCd) {
+    const Shape& sh = tab.shape[k];
+    dim3 grid((unsigned)((n + sh.tr() - 1) / sh.tr()), (b + sh.tc() - 1) / sh.tc(), batch);
+    tab.nn[k](st, grid, n, a, b, A, lda, M, ldm, opM, Cd, ldcd, alpha_re, alpha_im, beta, sA, sM, sC == 0 ? 0 : sCd,
+              g_xcd_group.load());
+    HIPCK(hipGetLastError());
+  };
+  // candidates write a zeroed scratch output of the same size (same loads and stores)
+  DevMem scratch;
+  const int c = pick_shape<T>(st, "nn", n, a, b, batch, true, [&](int k) {
+    if (!scratch.p) {
+      scratch.alloc(sizeof(cplx<T>) * (size_t)n * b * batch);
+      HIPCK(hipMemsetAsync(scratch.p, 0, sizeof(cplx<T>) * (size_t)n * b * batch, st));
+    }
+    launch(k, scratch.as<cplx<T>>(), n, n * (int64_t)b);
+  });
+  launch(c, C, ldc, sC);
 }
 
 template void gemm_hn_mfma<double>(hipStream_t, int64_t, int, int, const z64*, int64_t, const z64*, int64_t, z64*,

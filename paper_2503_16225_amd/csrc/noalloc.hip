@@ -58,6 +58,7 @@ extern "C" int eahp_ea_gradient_noalloc(eahp_problem* pb, const void* Psi, const
     if (!base) fail(EAHP_EDEVICE, "no-allocation scratch not set up on this device (create a context on it first)");
     const int p = pb->p, nk = pb->nk;
     const int64_t pp = (int64_t)p * p;
+    AutotuneHold hold;  // the products take kept launch shapes, never tuned here
     if (p > 1024) fail(EAHP_EINVAL, "p > 1024");
     if (nk > 1024) fail(EAHP_EINVAL, "more than 1024 k-points");
     // layout: M (nk p^2), the Gauss-Jordan work (2 p^2 per k-point, p > 128),

@@ -29,8 +29,22 @@ extern std::atomic<eahp_ctx*> g_prof_ctx;
 // Autotuner (tune.hip): with tuning on, the first use of `key` runs every
 // candidate 0..ncand-1 through run(c) (warm-up + timed, on scratch data) and
 // keeps the fastest; with tuning off, candidate 0.
+// While the stream is being captured into a graph, nothing is timed: the kept
+// choice (or candidate 0) is returned.
 bool autotune_on();
 int autotune(hipStream_t st, const std::string& key, int ncand, const std::function<void(int)>& run);
+// the kept choice of `key` with tuning on (candidate 0 otherwise), never timing
+int autotune_kept(const std::string& key);
+// the candidate forced by eahp_autotune_force (-1: none)
+int autotune_forced();
+// While one exists on a thread, autotune() on that thread times nothing (no
+// allocation, no synchronisation): kept choices or candidate 0.
+struct AutotuneHold {
+  AutotuneHold();
+  ~AutotuneHold();
+  AutotuneHold(const AutotuneHold&) = delete;
+  AutotuneHold& operator=(const AutotuneHold&) = delete;
+};
 // device address of this device's no-allocation scratch array (noalloc.hip)
 void noalloc_init(int device);
 void gemm_prof_begin(hipStream_t st, int slot);
