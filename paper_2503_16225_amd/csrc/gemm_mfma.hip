@@ -480,21 +480,59 @@ std::string tune_key(const char* op, int fp32, int64_t n, int a, int b, int batc
 
 }  // namespace
 
-// Split of the row dimension (set with the reference 64 x 64 tiles, the
-// same for every tile shape): about four work-groups per CU (the loads of one
-// overlap the products of the others), at least 4 chunks of rows each, the
+// Resident work-groups of the reference shape on the whole chip (CUs times
+// work-groups per CU), queried once per precision.
+template <typename T>
+static int64_t hn_slots() {
+  static const int64_t slots = [] {
+    int dev = 0, ncu = 0, per = 0;
+    HIPCK(hipGetDevice(&dev));
+    HIPCK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per, reinterpret_cast<const void*>(&k_gemm_hn_mfma<T, 2, 2, 2, 2>), 256, 0));
+    return (int64_t)std::max(1, ncu) * std::max(1, per);
+  }();
+  return slots;
+}
+
+// Split of the row dimension (set with the reference 64 x 64 tiles, the same
+// for every tile shape, so that all shapes give the same bits).  Tall
+// products (n >= kTallRows): the smallest split count whose work-groups fill
+// their last round of resident work-groups best (a count that leaves the last
+// round mostly empty costs nearly a whole round).  Shorter ones, where a
+// split holds few rows and the fixed cost of a work-group weighs more: about
+// four work-groups per CU.  Always at least 4 chunks of rows per split, the
 // partial tiles (written and read once more) under half the input bytes, and
 // at most max_part complex partial values in all.
-static void hn_split(int64_t n, int a, int b, int batch, int64_t max_part, int64_t& nsplit, int64_t& rps,
-                     int64_t& per_split) {
+constexpr int64_t kTallRows = 16384;
+static void hn_split(int64_t n, int a, int b, int batch, int64_t max_part, int64_t slots, int64_t& nsplit,
+                     int64_t& rps, int64_t& per_split) {
   const int tiles = ((a + MT - 1) / MT) * ((b + MT - 1) / MT);
   const int64_t in_elems = n * (int64_t)(a + b);
   per_split = (int64_t)((a + 15) / 16) * ((b + 15) / 16) * 256;
-  nsplit = (1024 + tiles * batch - 1) / (tiles * batch);
-  nsplit = std::min<int64_t>(nsplit, (n + 4 * MK - 1) / (4 * MK));
-  nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, in_elems / (2LL * tiles * MT * MT)));
-  nsplit = std::min<int64_t>(nsplit, max_part / std::max<int64_t>(1, per_split * batch));
-  nsplit = std::max<int64_t>(1, nsplit);
+  int64_t nmax = (n + 4 * MK - 1) / (4 * MK);
+  nmax = std::min<int64_t>(nmax, std::max<int64_t>(1, in_elems / (2LL * tiles * MT * MT)));
+  nmax = std::min<int64_t>(nmax, max_part / std::max<int64_t>(1, per_split * batch));
+  nmax = std::max<int64_t>(1, nmax);
+  const int64_t w0 = (int64_t)tiles * batch;
+  auto fill = [&](int64_t ns) {
+    const int64_t wg = w0 * ns;
+    return (double)wg / (double)(((wg + slots - 1) / slots) * slots);
+  };
+  if (n >= kTallRows) {
+    nsplit = 1;
+    double best = fill(1);
+    const int64_t upto = std::min<int64_t>(nmax, 4 * slots / std::max<int64_t>(1, w0) + 1);
+    for (int64_t ns = 2; ns <= upto; ++ns) {
+      const double f = fill(ns);
+      if (f > best + 0.02) {
+        best = f;
+        nsplit = ns;
+      }
+    }
+  } else {
+    nsplit = std::min<int64_t>(nmax, (1024 + w0 - 1) / w0);
+  }
   rps = (n + nsplit - 1) / nsplit;
   rps = ((rps + MK - 1) / MK) * MK;
   nsplit = std::max<int64_t>(1, (n + rps - 1) / rps);
@@ -553,7 +591,7 @@ void gemm_hn_mfma_ws(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, 
                      int64_t ldb, cplx<T>* C, int64_t ldc, double alpha, double beta, cplx<T>* part, size_t part_elems,
                      int batch, int64_t sA, int64_t sB, int64_t sC) {
   int64_t nsplit, rps, per_split;
-  hn_split(n, a, b, batch, (int64_t)part_elems, nsplit, rps, per_split);
+  hn_split(n, a, b, batch, (int64_t)part_elems, hn_slots<T>(), nsplit, rps, per_split);
   if ((size_t)(nsplit * per_split * batch) > part_elems) fail(EAHP_EINVAL, "Gram product: partial buffer too small");
   // no tuning here (no allocation, no synchronisation): the kept choice
   const int c = pick_shape<T>(st, "hn", n, a, b, batch, false, nullptr);
@@ -566,7 +604,7 @@ void gemm_hn_mfma(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int
                   int64_t ldb, cplx<T>* C, int64_t ldc, double alpha, double beta, DevMem& part, int batch,
                   int64_t sA, int64_t sB, int64_t sC) {
   int64_t nsplit, rps, per_split;
-  hn_split(n, a, b, batch, INT64_MAX, nsplit, rps, per_split);
+  hn_split(n, a, b, batch, INT64_MAX, hn_slots<T>(), nsplit, rps, per_split);
   const size_t elems = (size_t)(nsplit * per_split * batch);
   part.ensure(sizeof(cplx<T>) * elems);
   cplx<T>* P = part.as<cplx<T>>();
