@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 results databases (kernel durations, PMC counters).
 
     python profile_summary.py trace DB [--split-gap-ms G]
-    python profile_summary.py window DB --kernel NAME --last N
+    python profile_summary.py window DB --kernel NAME --last N [--prefix]
     python profile_summary.py pmc FETCH_DB WRITE_DB --kernel NAME [--copy-bytes B]
 
 The window mode summarises the dispatches from the first of the last N
@@ -51,12 +51,14 @@ def trace(db, top=20, rows=None):
     return out, tot / 1e6
 
 
-def window(db, kernel, last):
-    """Dispatches from the first of the last `last` dispatches whose name
-    starts with `kernel` onwards, and those dispatches' mean duration (ms)."""
+def window(db, kernel, last, prefix=False):
+    """Dispatches from the first of the last `last` dispatches of `kernel`
+    (its name, or with prefix=True every name that starts with it, e.g. all
+    tile shapes of a template) onwards, and those dispatches' mean duration (ms)."""
     con = sqlite3.connect(db)
     rows = con.execute("select name, start, duration from kernels order by start").fetchall()
-    hits = [i for i, (name, _, _) in enumerate(rows) if name.split("(")[0] == kernel]
+    match = (lambda nm: nm.startswith(kernel)) if prefix else (lambda nm: nm == kernel)
+    hits = [i for i, (name, _, _) in enumerate(rows) if match(name.split("(")[0])]
     if len(hits) < last:
         raise SystemExit(f"{kernel}: {len(hits)} dispatches in the trace, fewer than {last}")
     first = hits[-last]
@@ -90,9 +92,10 @@ def main():
     ap.add_argument("--min-dispatches", type=int, default=100)
     ap.add_argument("--last", type=int, default=0)
     ap.add_argument("--top", type=int, default=25)
+    ap.add_argument("--prefix", action="store_true", help="window: match every kernel name starting with --kernel")
     a = ap.parse_args()
     if a.mode == "window":
-        sel, mean = window(a.dbs[0], a.kernel, a.last)
+        sel, mean = window(a.dbs[0], a.kernel, a.last, a.prefix)
         rows, tot = trace(a.dbs[0], top=a.top, rows=sel)
         print(f"window: {len(sel)} dispatches from the first of the last {a.last} dispatches of {a.kernel}")
         print(f"{a.kernel}: mean duration over those {a.last} dispatches {mean:.4f} ms")
