@@ -539,8 +539,11 @@ void metric_solve(eahp_problem* pb, const z64* Phi, const z64* R, const z64* Lam
   if (info) info->clear();
   const int p = pb->p;
   const bool mixed = pb->precision == EAHP_MIXED;
-  // single-precision Gram matrices cannot resolve pivots much below 1e-5 of the largest
-  const double tol = mixed ? std::max(rank_tol, 1e-5) : rank_tol;
+  // the same deflation cut-off in both precisions: a direction whose pivot a
+  // single-precision Gram matrix resolves poorly is still made orthonormal by
+  // the second pass of CholQR2, and dropping fewer directions keeps the
+  // single-precision Krylov spaces closer to the double-precision ones
+  const double tol = rank_tol;
   if (pb->nk > 1 && p <= 128) {
     // every k-point at once (fom_batch.hip)
     LamEig own;
