@@ -497,16 +497,23 @@ static int64_t hn_slots() {
 
 // Split of the row dimension (set with the reference 64 x 64 tiles, the same
 // for every tile shape, so that all shapes give the same bits).  Tall
-// products (n >= kTallRows): the smallest split count whose work-groups fill
-// their last round of resident work-groups best (a count that leaves the last
-// round mostly empty costs nearly a whole round).  Shorter ones, where a
+// products (n >= kTallRows): from the smallest count that keeps a split
+// within max_rows, the count whose work-groups fill their last round of
+// resident work-groups best (a count that leaves the last round mostly empty
+// costs nearly a whole round).  Shorter ones, where a
 // split holds few rows and the fixed cost of a work-group weighs more: about
 // four work-groups per CU.  Always at least 4 chunks of rows per split, the
 // partial tiles (written and read once more) under half the input bytes, and
 // at most max_part complex partial values in all.
 constexpr int64_t kTallRows = 16384;
-static void hn_split(int64_t n, int a, int b, int batch, int64_t max_part, int64_t slots, int64_t& nsplit,
-                     int64_t& rps, int64_t& per_split) {
+// rows summed in the precision of the product per split of a tall product:
+// FP32 sums are kept to 4096 rows (the splits are added in FP64)
+template <typename T>
+constexpr int64_t hn_max_rows() {
+  return sizeof(T) == 4 ? 4096 : INT64_MAX / 2;
+}
+static void hn_split(int64_t n, int a, int b, int batch, int64_t max_part, int64_t slots, int64_t max_rows,
+                     int64_t& nsplit, int64_t& rps, int64_t& per_split) {
   const int tiles = ((a + MT - 1) / MT) * ((b + MT - 1) / MT);
   const int64_t in_elems = n * (int64_t)(a + b);
   per_split = (int64_t)((a + 15) / 16) * ((b + 15) / 16) * 256;
@@ -520,10 +527,12 @@ static void hn_split(int64_t n, int a, int b, int batch, int64_t max_part, int64
     return (double)wg / (double)(((wg + slots - 1) / slots) * slots);
   };
   if (n >= kTallRows) {
-    nsplit = 1;
-    double best = fill(1);
-    const int64_t upto = std::min<int64_t>(nmax, 4 * slots / std::max<int64_t>(1, w0) + 1);
-    for (int64_t ns = 2; ns <= upto; ++ns) {
+    // single precision sums each split's rows in FP32: at most max_rows per split
+    const int64_t nmin = std::min<int64_t>(nmax, (n + max_rows - 1) / max_rows);
+    nsplit = nmin;
+    double best = fill(nmin);
+    const int64_t upto = std::min<int64_t>(nmax, std::max<int64_t>(nmin, 4 * slots / std::max<int64_t>(1, w0) + 1));
+    for (int64_t ns = nmin + 1; ns <= upto; ++ns) {
       const double f = fill(ns);
       if (f > best + 0.02) {
         best = f;
@@ -591,7 +600,7 @@ void gemm_hn_mfma_ws(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, 
                      int64_t ldb, cplx<T>* C, int64_t ldc, double alpha, double beta, cplx<T>* part, size_t part_elems,
                      int batch, int64_t sA, int64_t sB, int64_t sC) {
   int64_t nsplit, rps, per_split;
-  hn_split(n, a, b, batch, (int64_t)part_elems, hn_slots<T>(), nsplit, rps, per_split);
+  hn_split(n, a, b, batch, (int64_t)part_elems, hn_slots<T>(), hn_max_rows<T>(), nsplit, rps, per_split);
   if ((size_t)(nsplit * per_split * batch) > part_elems) fail(EAHP_EINVAL, "Gram product: partial buffer too small");
   // no tuning here (no allocation, no synchronisation): the kept choice
   const int c = pick_shape<T>(st, "hn", n, a, b, batch, false, nullptr);
@@ -604,7 +613,7 @@ void gemm_hn_mfma(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int
                   int64_t ldb, cplx<T>* C, int64_t ldc, double alpha, double beta, DevMem& part, int batch,
                   int64_t sA, int64_t sB, int64_t sC) {
   int64_t nsplit, rps, per_split;
-  hn_split(n, a, b, batch, INT64_MAX, hn_slots<T>(), nsplit, rps, per_split);
+  hn_split(n, a, b, batch, INT64_MAX, hn_slots<T>(), hn_max_rows<T>(), nsplit, rps, per_split);
   const size_t elems = (size_t)(nsplit * per_split * batch);
   part.ensure(sizeof(cplx<T>) * elems);
   cplx<T>* P = part.as<cplx<T>>();
