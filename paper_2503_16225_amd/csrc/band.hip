@@ -194,6 +194,194 @@ __global__ void __launch_bounds__(1024) k_band_panel(int m, z64* P, int64_t ldp,
   if (g == 0 && threadIdx.x < kBw) beta[threadIdx.x] = (int)threadIdx.x < ns ? bsh[threadIdx.x] : 0.0;
 }
 
+// The block update between two panels, W = (I - V T V^H)^H-side terms of
+// A22 <- H^H A22 H with H = I - V T V^H and X = A22 V (Hermitian A22):
+//   Y = X T,  N = V^H Y,  M = T^H N,  Z = Y - V M / 2,
+//   A22 -= V Z^H + Z V^H  (the next panel's columns here, the rest later).
+// Three launches for what are otherwise five products and their split-K
+// reductions; every sum runs in a fixed order.  Blocks of 64 rows; in LDS a
+// 64 x 64 block is row-major with a stride of 65.
+constexpr int kWyLd = kBw + 1;
+// a conj(b)
+__device__ __forceinline__ z64 mulc(z64 a, z64 b) { return mk<double>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+
+// k_wy_y: one work-group per 64 rows b: Y_b = X_b T (written to Y) and the
+// partial N_b = V_b^H Y_b (to Np[b], 64 x 64 column-major).  Thread t takes
+// row (or column) t % 64 and the 4 columns t / 64 + 16 j.
+__global__ void __launch_bounds__(1024) k_wy_y(int m, const z64* __restrict__ X, int64_t ldx, const z64* __restrict__ T,
+                                              const z64* __restrict__ V, int64_t ldv, z64* __restrict__ Y,
+                                              int64_t ldy, z64* __restrict__ Np) {
+  __shared__ z64 sa[kBw * kWyLd];
+  __shared__ z64 sb[kBw * kWyLd];
+  const int t = threadIdx.x, r = t & 63, c0 = t >> 6;
+  const int64_t rb = (int64_t)blockIdx.x * kBw;
+  for (int e = t; e < kBw * kBw; e += 1024) {
+    const int i = e & 63, k = e >> 6;
+    sa[i * kWyLd + k] = rb + i < m ? X[rb + i + (int64_t)k * ldx] : mk<double>(0.0, 0.0);
+    sb[i * kWyLd + k] = T[i + (int64_t)k * kBw];
+  }
+  __syncthreads();
+  z64 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = mk<double>(0.0, 0.0);
+  for (int k = 0; k < kBw; ++k) {
+    const z64 x = sa[r * kWyLd + k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = cadd<double>(acc[j], cmul<double>(x, sb[k * kWyLd + c0 + 16 * j]));
+  }
+  if (rb + r < m) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Y[rb + r + (int64_t)(c0 + 16 * j) * ldy] = acc[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) sa[r * kWyLd + c0 + 16 * j] = rb + r < m ? acc[j] : mk<double>(0.0, 0.0);
+  for (int e = t; e < kBw * kBw; e += 1024) {
+    const int i = e & 63, k = e >> 6;
+    sb[i * kWyLd + k] = rb + i < m ? V[rb + i + (int64_t)k * ldv] : mk<double>(0.0, 0.0);
+  }
+  __syncthreads();
+  // N_b[c1][c2] = sum_i conj(V[i][c1]) Y[i][c2], c1 = t % 64, c2 = t / 64 + 16 j
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = mk<double>(0.0, 0.0);
+  for (int i = 0; i < kBw; ++i) {
+    const z64 v = sb[i * kWyLd + r];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = cadd<double>(acc[j], cjmul<double>(v, sa[i * kWyLd + c0 + 16 * j]));
+  }
+  z64* P = Np + (int64_t)blockIdx.x * kBw * kBw;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) P[r + (c0 + 16 * j) * kBw] = acc[j];
+}
+
+// k_wy_m: one work-group per column c of N: N[:, c] = sum_b Np[b][:, c]
+// (four groups of blocks, added in a fixed order), M[:, c] = T^H N[:, c],
+// and Z_0[:, c] = Y_0[:, c] - V_0 M[:, c] / 2 for the first 64 rows (written
+// over Y), which every work-group of k_wy_z needs.
+__global__ void __launch_bounds__(256) k_wy_m(int m, int nb, const z64* __restrict__ Np, const z64* __restrict__ T,
+                                              z64* __restrict__ M, const z64* __restrict__ V, int64_t ldv, z64* Y,
+                                              int64_t ldy) {
+  __shared__ z64 big[kBw * kWyLd];
+  __shared__ z64 red[4][kBw];
+  __shared__ z64 ncol[kBw], mcol[kBw];
+  const int t = threadIdx.x, i = t & 63, g = t >> 6;
+  const int c = blockIdx.x;
+  z64 s = mk<double>(0.0, 0.0);
+  for (int bb = g; bb < nb; bb += 4) s = cadd<double>(s, Np[(int64_t)bb * kBw * kBw + i + c * kBw]);
+  red[g][i] = s;
+  // T into LDS, row-major: big[k][i] = T[k][i]
+  for (int e = t; e < kBw * kBw; e += 256) {
+    const int k = e & 63, ii = e >> 6;
+    big[k * kWyLd + ii] = T[k + (int64_t)ii * kBw];
+  }
+  __syncthreads();
+  if (t < kBw) ncol[t] = cadd<double>(cadd<double>(red[0][t], red[1][t]), cadd<double>(red[2][t], red[3][t]));
+  __syncthreads();
+  if (t < kBw) {
+    // M[t][c] = sum_k conj(T[k][t]) N[k][c]
+    z64 a = mk<double>(0.0, 0.0);
+    for (int k = 0; k < kBw; ++k) a = cadd<double>(a, cjmul<double>(big[k * kWyLd + t], ncol[k]));
+    mcol[t] = a;
+    M[t + (int64_t)c * kBw] = a;
+  }
+  __syncthreads();
+  for (int e = t; e < kBw * kBw; e += 256) {
+    const int rr = e & 63, k = e >> 6;
+    big[rr * kWyLd + k] = rr < m ? V[rr + (int64_t)k * ldv] : mk<double>(0.0, 0.0);
+  }
+  __syncthreads();
+  if (t < kBw && t < m) {
+    z64 a = mk<double>(0.0, 0.0);
+    for (int k = 0; k < kBw; ++k) a = cadd<double>(a, cmul<double>(big[t * kWyLd + k], mcol[k]));
+    z64* y = Y + t + (int64_t)c * ldy;
+    *y = mk<double>(y->x - 0.5 * a.x, y->y - 0.5 * a.y);
+  }
+}
+
+// k_wy_z: one work-group per 64 rows b: Z_b = Y_b - V_b M / 2 (b >= 1; block
+// 0 comes from k_wy_m) written over Y, and with upd the next panel's columns
+// A22[rows of b, 0:64] -= V_b Z_0^H + Z_b V_0^H.
+__global__ void __launch_bounds__(1024) k_wy_z(int m, const z64* __restrict__ M, const z64* __restrict__ V,
+                                              int64_t ldv, z64* Y, int64_t ldy, z64* A22, int64_t lda, int upd) {
+  __shared__ z64 sa[kBw * kWyLd];
+  __shared__ z64 sb[kBw * kWyLd];
+  const int t = threadIdx.x, r = t & 63, c0 = t >> 6;
+  const int b = blockIdx.x;
+  const int64_t rb = (int64_t)b * kBw;
+  const bool live = rb + r < m;
+  auto load_rows = [&](z64* dst, const z64* src, int64_t ld, int64_t row0) __attribute__((always_inline)) {
+    for (int e = t; e < kBw * kBw; e += 1024) {
+      const int i = e & 63, k = e >> 6;
+      dst[i * kWyLd + k] = row0 + i < m ? src[row0 + i + (int64_t)k * ld] : mk<double>(0.0, 0.0);
+    }
+  };
+  z64 z[4];
+  if (b == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) z[j] = live ? Y[r + (int64_t)(c0 + 16 * j) * ldy] : mk<double>(0.0, 0.0);
+  } else {
+    for (int e = t; e < kBw * kBw; e += 1024) {
+      const int k = e & 63, cc = e >> 6;
+      sa[k * kWyLd + cc] = M[k + (int64_t)cc * kBw];
+    }
+    load_rows(sb, V, ldv, rb);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) z[j] = mk<double>(0.0, 0.0);
+    for (int k = 0; k < kBw; ++k) {
+      const z64 v = sb[r * kWyLd + k];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) z[j] = cadd<double>(z[j], cmul<double>(v, sa[k * kWyLd + c0 + 16 * j]));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const z64 y = live ? Y[rb + r + (int64_t)(c0 + 16 * j) * ldy] : mk<double>(0.0, 0.0);
+      z[j] = mk<double>(y.x - 0.5 * z[j].x, y.y - 0.5 * z[j].y);
+    }
+    if (live) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Y[rb + r + (int64_t)(c0 + 16 * j) * ldy] = z[j];
+    }
+  }
+  if (!upd) return;  // uniform over the work-group
+  // Z_b V_0^H
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) sa[r * kWyLd + c0 + 16 * j] = live ? z[j] : mk<double>(0.0, 0.0);
+  load_rows(sb, V, ldv, 0);
+  __syncthreads();
+  z64 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = mk<double>(0.0, 0.0);
+  for (int k = 0; k < kBw; ++k) {
+    const z64 zr = sa[r * kWyLd + k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = cadd<double>(acc[j], mulc(zr, sb[(c0 + 16 * j) * kWyLd + k]));
+  }
+  // V_b Z_0^H
+  __syncthreads();
+  load_rows(sa, V, ldv, rb);
+  load_rows(sb, Y, ldy, 0);
+  __syncthreads();
+  z64 acc1[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc1[j] = mk<double>(0.0, 0.0);
+  for (int k = 0; k < kBw; ++k) {
+    const z64 vr = sa[r * kWyLd + k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      acc1[j] = cadd<double>(acc1[j], mulc(vr, sb[(c0 + 16 * j) * kWyLd + k]));
+  }
+  if (live) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      z64* a = A22 + rb + r + (int64_t)(c0 + 16 * j) * lda;
+      const z64 d = cadd<double>(acc1[j], acc[j]);
+      *a = mk<double>(a->x - d.x, a->y - d.y);
+    }
+  }
+}
+
 // Rows of the band matrix: RB[r * kRw + t] = B[r][r - kBw + t] (t = 0..2kBw),
 // zero outside the matrix; entries on and below the diagonal come from the
 // lower triangle of A, the others as conjugates of their mirror.
@@ -573,7 +761,8 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   const size_t oSl = oRB + al(sizeof(z64) * (size_t)q * kRw);
   const size_t nslot = (size_t)b * (gmax + 1) * 64;
   const size_t oErr = oSl + al(sizeof(z64) * nslot);
-  const size_t oWy = oErr + 256;
+  const size_t oNp = oErr + 256;  // partial N of the block update: one 64 x 64 block per 64 rows
+  const size_t oWy = oNp + al(sizeof(z64) * (size_t)((q + kBw - 1) / kBw) * kBw * kBw);
   const size_t oU = oWy + al(refl_blocked_scratch(q - b, p));
   ws.ensure(oU + ubytes_shift * nsh);
   char* base = static_cast<char*>(ws.p);
@@ -588,6 +777,7 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   z64* slots = reinterpret_cast<z64*>(base + oSl);
   int* err = reinterpret_cast<int*>(base + oErr);
   void* wy = base + oWy;
+  z64* Npart = reinterpret_cast<z64*>(base + oNp);
   z64* Ubuf = reinterpret_cast<z64*>(base + oU);
   const int64_t ld3 = q;
 
@@ -650,13 +840,16 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
       z64* A22 = A + (k0 + b) + (int64_t)(k0 + b) * lda;
       z64* Yb = V3c + (int64_t)b * ld3;
       gemm_hn<double>(st, m, m, b, A22, lda, V3c, ld3, X, ld3, 1.0, 0.0, part);  // A22^H V = A22 V
-      gemm_nn<double>(st, m, b, b, X, ld3, Tm, b, 0, Yb, ld3, 1.0, 0.0, 0.0);
-      gemm_hn<double>(st, m, b, b, V3c, ld3, Yb, ld3, Nm, b, 1.0, 0.0, part);
-      gemm_hn<double>(st, b, b, b, Tm, b, Nm, b, Mm, b, 1.0, 0.0, part);
-      gemm_nn<double>(st, m, b, b, V3c, ld3, Mm, b, 0, Yb, ld3, -0.5, 0.0, 1.0);
-      if (look && m > b) {
-        // the next panel's columns now; the rest after the next panel's launch
-        gemm_nn<double>(st, m, 2 * b, b, V3c, ld3, Yb, ld3, 1, A22, lda, -1.0, 0.0, 1.0);
+      // Y = X T, N = V^H Y, M = T^H N, Z = Y - V M / 2 (over Y), and with
+      // look-ahead the next panel's columns of A22 -= V Z^H + Z V^H
+      const int nbk = (m + kBw - 1) / kBw;
+      const int upd = (look && m > b) ? 1 : 0;
+      hipLaunchKernelGGL(k_wy_y, dim3(nbk), dim3(1024), 0, st, m, X, ld3, Tm, V3c, ld3, Yb, ld3, Npart);
+      hipLaunchKernelGGL(k_wy_m, dim3(kBw), dim3(256), 0, st, m, nbk, Npart, Tm, Mm, V3c, ld3, Yb, ld3);
+      hipLaunchKernelGGL(k_wy_z, dim3(nbk), dim3(1024), 0, st, m, Mm, V3c, ld3, Yb, ld3, A22, lda, upd);
+      HIPCK(hipGetLastError());
+      if (upd) {
+        // the rest after the next panel's launch
         HIPCK(hipEventRecord(aux->z, st));
         rest = Deferred{true, m, V3c, Yb, A22};
       } else {
