@@ -825,7 +825,11 @@ void tridiag_reduce(hipStream_t st, int q, c32* A, int64_t lda, double* dd, z64*
 // per column, entry j in lane j % 64, slot j / 64 (nbk <= 256).
 __global__ void __launch_bounds__(256) k_wy_trsm(int nbk, int nb, const z64* __restrict__ G,
                                                  const double* __restrict__ beta, z64* Z, int64_t ldz, int ncols,
-                                                 int forward) {
+                                                 int forward, int64_t sG, int64_t sB, int64_t sZ) {
+  // blockIdx.y: the block of reflectors (G, beta and Z at strides sG, sB, sZ)
+  G += blockIdx.y * sG;
+  beta += blockIdx.y * sB;
+  Z += blockIdx.y * sZ;
   const int lane = threadIdx.x & 63;
   const int col = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (col >= ncols) return;
@@ -862,24 +866,38 @@ __global__ void __launch_bounds__(256) k_wy_trsm(int nbk, int nb, const z64* __r
   }
 }
 
+// identity in the leading n x n of each nb x nb block (blockIdx.y), zero elsewhere
+__global__ void k_eye_blocks(int n, int nb, z64* X) {
+  X += (int64_t)blockIdx.y * nb * nb;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nb * nb; e += gridDim.x * blockDim.x) {
+    const int i = e % nb, j = e / nb;
+    X[e] = mk<double>((i == j && i < n) ? 1.0 : 0.0, 0.0);
+  }
+}
+
 constexpr int kWyNb = 256;
 size_t refl_blocked_scratch(int nref, int ncols) {
   const int nblk = (nref + kWyNb - 1) / kWyNb;
-  return sizeof(z64) * ((size_t)nblk * kWyNb * kWyNb + (size_t)kWyNb * ncols) + 512;
+  return sizeof(z64) * (2 * (size_t)nblk * kWyNb * kWyNb + 2 * (size_t)kWyNb * ncols) + 512;
 }
 
 // Y <- Q^H Y or Q Y for Q = H_0 H_1 ... H_{nref-1}, reflector k acting on rows
 // k + off .. q - 1 (off = 1: the tridiagonal reduction; off = the bandwidth:
-// the band reduction), through blocks of kWyNb reflectors: per block two
-// products with the reflectors (MFMA) and a triangular solve with its Gram
-// matrix.  Column k of Vh must be zero above row k + off.
+// the band reduction), through blocks of kWyNb reflectors P = I - V T V^H.
+// T^H = (diag(1/beta) + strictly lower G)^-1 (G = V^H V) of every block is
+// formed first, all blocks in one launch (k_wy_trsm on identity right-hand
+// sides); per block then three products: Z = V^H Y, T^H Z (forward: the
+// factor of P^H) or T Z, Y -= V (T^H Z or T Z).  Column k of Vh must be zero
+// above row k + off.
 void apply_refl_blocked(hipStream_t st, int q, int off, int ncols, const z64* Vh, const double* beta, z64* Y,
                         int64_t ldy, int forward, void* scr, DevMem& part) {
   const int nref = q - off;
   if (nref <= 0 || ncols <= 0) return;
   const int nb = kWyNb, nblk = (nref + nb - 1) / nb;
   z64* G = static_cast<z64*>(scr);
-  z64* Z = G + (size_t)nblk * nb * nb;
+  z64* Xi = G + (size_t)nblk * nb * nb;  // T^H of every block
+  z64* Z = Xi + (size_t)nblk * nb * nb;
+  z64* Z2 = Z + (size_t)nb * ncols;
   // G_b = V_b^H V_b: the full blocks at once, then the narrower last one
   const int nfull = nref / nb, last = nref - nfull * nb;
   if (nfull > 0)
@@ -888,16 +906,30 @@ void apply_refl_blocked(hipStream_t st, int q, int off, int ncols, const z64* Vh
   if (last > 0)
     gemm_hn<double>(st, q, last, last, Vh + (int64_t)nfull * nb * q, q, Vh + (int64_t)nfull * nb * q, q,
                     G + (int64_t)nfull * nb * nb, nb, 1.0, 0.0, part);
+  // T^H of every block: (diag(1/beta) + strictly lower G) X = I
+  const int64_t bb = (int64_t)nb * nb;
+  if (nfull > 0) {
+    hipLaunchKernelGGL(k_eye_blocks, dim3(64, nfull), dim3(256), 0, st, nb, nb, Xi);
+    hipLaunchKernelGGL(k_wy_trsm, dim3((nb + 3) / 4, nfull), dim3(256), 0, st, nb, nb, G, beta, Xi, (int64_t)nb, nb,
+                       1, bb, (int64_t)nb, bb);
+  }
+  if (last > 0) {
+    z64* Xl = Xi + (int64_t)nfull * bb;
+    hipLaunchKernelGGL(k_eye_blocks, dim3(64, 1), dim3(256), 0, st, last, nb, Xl);
+    hipLaunchKernelGGL(k_wy_trsm, dim3((last + 3) / 4, 1), dim3(256), 0, st, last, nb, G + (int64_t)nfull * bb,
+                       beta + (int64_t)nfull * nb, Xl, (int64_t)nb, last, 1, (int64_t)0, (int64_t)0, (int64_t)0);
+  }
   for (int i = 0; i < nblk; ++i) {
     const int blk = forward ? i : nblk - 1 - i;
     const int k0 = blk * nb, nbk = std::min(nb, nref - k0);
     const int r0 = k0 + off, rows = q - r0;  // the block's reflectors vanish above row k0 + off
     const z64* Vb = Vh + (int64_t)k0 * q + r0;
+    const z64* Xb = Xi + (int64_t)blk * bb;
     // Z = V_b^H Y, Z2 = T^H Z (forward) or T Z, Y -= V_b Z2
     gemm_hn<double>(st, rows, nbk, ncols, Vb, q, Y + r0, ldy, Z, nbk, 1.0, 0.0, part);
-    hipLaunchKernelGGL(k_wy_trsm, dim3((ncols + 3) / 4), dim3(256), 0, st, nbk, nb, G + (int64_t)blk * nb * nb,
-                       beta + k0, Z, (int64_t)nbk, ncols, forward);
-    gemm_nn<double>(st, rows, nbk, ncols, Vb, q, Z, nbk, 0, Y + r0, ldy, -1.0, 0.0, 1.0);
+    if (forward) gemm_nn<double>(st, nbk, nbk, ncols, Xb, nb, Z, nbk, 0, Z2, nbk, 1.0, 0.0, 0.0);
+    else gemm_hn<double>(st, nbk, nbk, ncols, Xb, nb, Z, nbk, Z2, nbk, 1.0, 0.0, part);
+    gemm_nn<double>(st, rows, nbk, ncols, Vb, q, Z2, nbk, 0, Y + r0, ldy, -1.0, 0.0, 1.0);
   }
   HIPCK(hipGetLastError());
 }
