@@ -761,7 +761,10 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   const size_t oSl = oRB + al(sizeof(z64) * (size_t)q * kRw);
   const size_t nslot = (size_t)b * (gmax + 1) * 64;
   const size_t oErr = oSl + al(sizeof(z64) * nslot);
-  const size_t oNp = oErr + 256;  // partial N of the block update: one 64 x 64 block per 64 rows
+  const int npan = (q - b + b - 1) / b;  // panels (k0 = 0, b, ... while k0 + b < q)
+  const size_t oTa = oErr + 256;       // the compact WY factor T of every panel
+  const size_t oZf = oTa + al(sizeof(z64) * (size_t)npan * b * b);  // V^H C~ and T^H V^H C~ (b x p each)
+  const size_t oNp = oZf + al(sizeof(z64) * 2 * (size_t)b * p);  // partial N of the block update: one 64 x 64 block per 64 rows
   const size_t oWy = oNp + al(sizeof(z64) * (size_t)((q + kBw - 1) / kBw) * kBw * kBw);
   const size_t oU = oWy + al(refl_blocked_scratch(q - b, p));
   ws.ensure(oU + ubytes_shift * nsh);
@@ -778,6 +781,9 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   int* err = reinterpret_cast<int*>(base + oErr);
   void* wy = base + oWy;
   z64* Npart = reinterpret_cast<z64*>(base + oNp);
+  z64* Tall = reinterpret_cast<z64*>(base + oTa);
+  z64* Zf = reinterpret_cast<z64*>(base + oZf);
+  z64* Zf2 = Zf + (size_t)b * p;
   z64* Ubuf = reinterpret_cast<z64*>(base + oU);
   const int64_t ld3 = q;
 
@@ -802,17 +808,34 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
     // alternates between two buffers (the second stream still reads panel
     // i's while panel i + 1 writes its own).
     const bool look = aux != nullptr && aux->s != nullptr;
+    // With the second stream, panel i's reflectors are also applied to the
+    // right-hand sides there (C~ <- P_i^H C~ with P_i = I - V_i T_i V_i^H,
+    // V_i from Vh, T_i kept per panel), behind panel i's trailing update, so
+    // that this work fills the CUs the latency-bound panels leave idle; the
+    // blocked forward application after the reduction is then skipped.
+    const bool fwd_on_aux = look && aux->part != nullptr && aux->f != nullptr;
     struct Deferred {
-      bool on = false;
-      int m = 0;
+      bool on = false, upd = false;
+      int m = 0, k0 = 0, ns = 0, idx = 0;
       z64 *V3 = nullptr, *Yb = nullptr, *A22 = nullptr;
     } rest;
     auto submit_rest = [&]() {
-      // A22[:, b:] -= [V Z] [Z V]^H[:, b:] on the second stream, after the event z
       HIPCK(hipStreamWaitEvent(aux->s, aux->z, 0));
-      gemm_nn<double>(aux->s, rest.m, 2 * b, rest.m - b, rest.V3, ld3, rest.Yb + b, ld3, 1, rest.A22 + (int64_t)b * lda,
-                      lda, -1.0, 0.0, 1.0);
-      HIPCK(hipEventRecord(aux->c, aux->s));
+      if (rest.upd) {
+        // A22[:, b:] -= [V Z] [Z V]^H[:, b:] on the second stream, after the event z
+        gemm_nn<double>(aux->s, rest.m, 2 * b, rest.m - b, rest.V3, ld3, rest.Yb + b, ld3, 1,
+                        rest.A22 + (int64_t)b * lda, lda, -1.0, 0.0, 1.0);
+        HIPCK(hipEventRecord(aux->c, aux->s));
+      }
+      if (fwd_on_aux) {
+        const int r0 = rest.k0 + b;
+        const z64* Vi = Vh + (int64_t)rest.k0 * q + r0;
+        const z64* Ti = Tall + (int64_t)rest.idx * b * b;
+        gemm_hn<double>(aux->s, rest.m, rest.ns, p, Vi, q, Yt + r0, q, Zf, rest.ns, 1.0, 0.0, *aux->part);
+        gemm_hn<double>(aux->s, rest.ns, rest.ns, p, Ti, b, Zf, rest.ns, Zf2, rest.ns, 1.0, 0.0, *aux->part);
+        gemm_nn<double>(aux->s, rest.m, rest.ns, p, Vi, q, Zf2, rest.ns, 0, Yt + r0, q, -1.0, 0.0, 1.0);
+        HIPCK(hipEventRecord(aux->f, aux->s));
+      }
       rest.on = false;
       return true;
     };
@@ -830,11 +853,13 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
       int64_t ldp = lda, ldv = ld3, ldh = q;
       z64* Vp = Vh + (int64_t)k0 * q + (k0 + b);
       double* btp = bt + k0;
-      void* args[] = {&mm, &P, &ldp, &V3c, &ldv, &Vp, &ldh, &btp, &Tm, &part_x, &rowv, &err};
+      z64* Tp = Tall + (int64_t)idx * b * b;
+      void* args[] = {&mm, &P, &ldp, &V3c, &ldv, &Vp, &ldh, &btp, &Tp, &part_x, &rowv, &err};
       HIPCK(hipLaunchCooperativeKernel((const void*)k_band_panel<kPanelRpt>, dim3(G), dim3(1024), args, 0, st));
       if (rest.on) {
+        const bool had_upd = rest.upd;
         submit_rest();
-        HIPCK(hipStreamWaitEvent(st, aux->c, 0));
+        if (had_upd) HIPCK(hipStreamWaitEvent(st, aux->c, 0));
       }
       // trailing update A22 <- H^H A22 H
       z64* A22 = A + (k0 + b) + (int64_t)(k0 + b) * lda;
@@ -844,22 +869,31 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
       // look-ahead the next panel's columns of A22 -= V Z^H + Z V^H
       const int nbk = (m + kBw - 1) / kBw;
       const int upd = (look && m > b) ? 1 : 0;
-      hipLaunchKernelGGL(k_wy_y, dim3(nbk), dim3(1024), 0, st, m, X, ld3, Tm, V3c, ld3, Yb, ld3, Npart);
-      hipLaunchKernelGGL(k_wy_m, dim3(kBw), dim3(256), 0, st, m, nbk, Npart, Tm, Mm, V3c, ld3, Yb, ld3);
+      hipLaunchKernelGGL(k_wy_y, dim3(nbk), dim3(1024), 0, st, m, X, ld3, Tp, V3c, ld3, Yb, ld3, Npart);
+      hipLaunchKernelGGL(k_wy_m, dim3(kBw), dim3(256), 0, st, m, nbk, Npart, Tp, Mm, V3c, ld3, Yb, ld3);
       hipLaunchKernelGGL(k_wy_z, dim3(nbk), dim3(1024), 0, st, m, Mm, V3c, ld3, Yb, ld3, A22, lda, upd);
       HIPCK(hipGetLastError());
       if (upd) {
         // the rest after the next panel's launch
         HIPCK(hipEventRecord(aux->z, st));
-        rest = Deferred{true, m, V3c, Yb, A22};
+        rest = Deferred{true, true, m, k0, ns, idx, V3c, Yb, A22};
       } else {
         gemm_nn<double>(st, m, 2 * b, m, V3c, ld3, Yb, ld3, 1, A22, lda, -1.0, 0.0, 1.0);
+        if (fwd_on_aux) {
+          // no deferred update: the forward application of this panel right away
+          if (rest.on) submit_rest();
+          HIPCK(hipEventRecord(aux->z, st));
+          rest = Deferred{true, false, m, k0, ns, idx, V3c, Yb, A22};
+          submit_rest();
+        }
       }
     }
     if (rest.on) {
+      const bool had_upd = rest.upd;
       submit_rest();
-      HIPCK(hipStreamWaitEvent(st, aux->c, 0));
+      if (had_upd) HIPCK(hipStreamWaitEvent(st, aux->c, 0));
     }
+    if (fwd_on_aux) HIPCK(hipStreamWaitEvent(st, aux->f, 0));
     int bad = 0;
     HIPCK(hipMemcpyAsync(&bad, err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
@@ -867,7 +901,8 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   }
   hipLaunchKernelGGL(k_band_rows, dim3((unsigned)std::min<int64_t>(8192, ((int64_t)q * kRw + 255) / 256)), dim3(256),
                      0, st, q, A, lda, RB);
-  apply_refl_blocked(st, q, b, p, Vh, bt, Yt, q, 1, wy, part);
+  const bool fwd_done = aux != nullptr && aux->s != nullptr && aux->part != nullptr && aux->f != nullptr;
+  if (!fwd_done) apply_refl_blocked(st, q, b, p, Vh, bt, Yt, q, 1, wy, part);
   for (int l0 = 0; l0 < p; l0 += nsh) {
     const int n = std::min(nsh, p - l0);
     hipLaunchKernelGGL(k_band_gepp, dim3(n), dim3(kGt), 0, st, q, RB, s, Yt, (int64_t)q, Ubuf, l0);

@@ -119,7 +119,8 @@ struct eahp_ctx {
   ProfSlot slot[kProfKernels];
   // second stream and events of overlapped work, created on first use
   hipStream_t aux_stream = nullptr;
-  hipEvent_t aux_ev[2] = {nullptr, nullptr};
+  hipEvent_t aux_ev[3] = {nullptr, nullptr, nullptr};
+  eahp::DevMem aux_part;  // split-K partials of the products on the second stream
   ~eahp_ctx();
 };
 

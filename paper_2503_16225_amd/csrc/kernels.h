@@ -172,7 +172,8 @@ void set_identity(hipStream_t st, int p, z64* M, int64_t ldm);
 // main stream's (the band reduction's look-ahead); owned by a context.
 struct BandAux {
   hipStream_t s = nullptr;
-  hipEvent_t z = nullptr, c = nullptr;
+  hipEvent_t z = nullptr, c = nullptr, f = nullptr;
+  DevMem* part = nullptr;  // split-K partials of the products on s
 };
 void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const double* s, z64* Yt, DevMem& ws,
                        DevMem& part, bool store32 = false, const BandAux* aux = nullptr);

@@ -395,6 +395,8 @@ static const BandAux& band_aux(eahp_ctx* c) {
   a.s = c->aux_stream;
   a.z = c->aux_ev[0];
   a.c = c->aux_ev[1];
+  a.f = c->aux_ev[2];
+  a.part = &c->aux_part;
   return a;
 }
 
