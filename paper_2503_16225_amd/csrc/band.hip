@@ -260,7 +260,11 @@ __global__ void __launch_bounds__(1024) k_wy_y(int m, const z64* __restrict__ X,
 // over Y), which every work-group of k_wy_z needs.
 __global__ void __launch_bounds__(256) k_wy_m(int m, int nb, const z64* __restrict__ Np, const z64* __restrict__ T,
                                               z64* __restrict__ M, const z64* __restrict__ V, int64_t ldv, z64* Y,
-                                              int64_t ldy) {
+                                              int64_t ldy, unsigned long long* fillp, int64_t nfill) {
+  // the exchange slots of the next panel back to the empty pattern (the
+  // current panel, which used them, has finished)
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nfill; e += (int64_t)gridDim.x * blockDim.x)
+    fillp[e] = xch::kEmpty;
   __shared__ z64 big[kBw * kWyLd];
   __shared__ z64 red[4][kBw];
   __shared__ z64 ncol[kBw], mcol[kBw];
@@ -846,9 +850,12 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
       z64* V3c = V3 + (int64_t)(idx & 1) * ld3 * 3 * b;
       z64* part_x = slots;
       z64* rowv = slots + (size_t)ns * G * 64;
-      const int64_t nw = (int64_t)2 * ns * (G + 1) * 64;
-      hipLaunchKernelGGL(k_band_fill, dim3((unsigned)std::min<int64_t>(1024, (nw + 255) / 256)), dim3(256), 0, st,
-                         reinterpret_cast<unsigned long long*>(slots), nw, xch::kEmpty);
+      // the first panel's exchange slots here; the later ones' by k_wy_m of the panel before
+      if (idx == 0) {
+        const int64_t nw = (int64_t)2 * ns * (G + 1) * 64;
+        hipLaunchKernelGGL(k_band_fill, dim3((unsigned)std::min<int64_t>(1024, (nw + 255) / 256)), dim3(256), 0, st,
+                           reinterpret_cast<unsigned long long*>(slots), nw, xch::kEmpty);
+      }
       int mm = m;
       int64_t ldp = lda, ldv = ld3, ldh = q;
       z64* Vp = Vh + (int64_t)k0 * q + (k0 + b);
@@ -870,7 +877,13 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
       const int nbk = (m + kBw - 1) / kBw;
       const int upd = (look && m > b) ? 1 : 0;
       hipLaunchKernelGGL(k_wy_y, dim3(nbk), dim3(1024), 0, st, m, X, ld3, Tp, V3c, ld3, Yb, ld3, Npart);
-      hipLaunchKernelGGL(k_wy_m, dim3(kBw), dim3(256), 0, st, m, nbk, Npart, Tp, Mm, V3c, ld3, Yb, ld3);
+      int64_t nfill = 0;
+      if (k0 + 2 * b < q) {
+        const int m1 = m - b, ns1 = std::min(b, m1), G1 = (m1 + kPanelRows - 1) / kPanelRows;
+        nfill = (int64_t)2 * ns1 * (G1 + 1) * 64;
+      }
+      hipLaunchKernelGGL(k_wy_m, dim3(kBw), dim3(256), 0, st, m, nbk, Npart, Tp, Mm, V3c, ld3, Yb, ld3,
+                         reinterpret_cast<unsigned long long*>(slots), nfill);
       hipLaunchKernelGGL(k_wy_z, dim3(nbk), dim3(1024), 0, st, m, Mm, V3c, ld3, Yb, ld3, A22, lda, upd);
       HIPCK(hipGetLastError());
       if (upd) {
