@@ -198,6 +198,14 @@ void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* b
 // (column k of Vh, ld q, zero above row k + off) acting on rows k + off ..;
 // scr: refl_blocked_scratch(q - off, ncols) bytes.
 size_t refl_blocked_scratch(int nref, int ncols);
+// apply_refl_blocked in two parts: the Gram matrices and triangular factors
+// of the blocks into scr, then the products on ncols columns of Y with zs
+// (2 x 256 x ncols values) for the intermediate blocks; the second part may
+// run on several streams at once on disjoint columns, each with its own zs
+// and part
+void refl_blocked_prepare(hipStream_t st, int q, int off, const z64* Vh, const double* beta, void* scr, DevMem& part);
+void refl_blocked_apply(hipStream_t st, int q, int off, int ncols, const z64* Vh, z64* Y, int64_t ldy, int forward,
+                        const void* scr, z64* zs, DevMem& part);
 void apply_refl_blocked(hipStream_t st, int q, int off, int ncols, const z64* Vh, const double* beta, z64* Y,
                         int64_t ldy, int forward, void* scr, DevMem& part);
 // (A - s_l I) y_l = c_l for all columns of Yt (q x p, ld q; overwritten by the

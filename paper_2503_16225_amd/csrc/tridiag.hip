@@ -889,15 +889,13 @@ size_t refl_blocked_scratch(int nref, int ncols) {
 // sides); per block then three products: Z = V^H Y, T^H Z (forward: the
 // factor of P^H) or T Z, Y -= V (T^H Z or T Z).  Column k of Vh must be zero
 // above row k + off.
-void apply_refl_blocked(hipStream_t st, int q, int off, int ncols, const z64* Vh, const double* beta, z64* Y,
-                        int64_t ldy, int forward, void* scr, DevMem& part) {
+// G and T^H of every block into scr (its first 2 nblk nb^2 values)
+void refl_blocked_prepare(hipStream_t st, int q, int off, const z64* Vh, const double* beta, void* scr, DevMem& part) {
   const int nref = q - off;
-  if (nref <= 0 || ncols <= 0) return;
+  if (nref <= 0) return;
   const int nb = kWyNb, nblk = (nref + nb - 1) / nb;
   z64* G = static_cast<z64*>(scr);
   z64* Xi = G + (size_t)nblk * nb * nb;  // T^H of every block
-  z64* Z = Xi + (size_t)nblk * nb * nb;
-  z64* Z2 = Z + (size_t)nb * ncols;
   // G_b = V_b^H V_b: the full blocks at once, then the narrower last one
   const int nfull = nref / nb, last = nref - nfull * nb;
   if (nfull > 0)
@@ -919,6 +917,20 @@ void apply_refl_blocked(hipStream_t st, int q, int off, int ncols, const z64* Vh
     hipLaunchKernelGGL(k_wy_trsm, dim3((last + 3) / 4, 1), dim3(256), 0, st, last, nb, G + (int64_t)nfull * bb,
                        beta + (int64_t)nfull * nb, Xl, (int64_t)nb, last, 1, (int64_t)0, (int64_t)0, (int64_t)0);
   }
+  HIPCK(hipGetLastError());
+}
+
+// The products with the prepared blocks on ncols columns of Y; zs holds Z
+// and Z2 (nb x ncols each).
+void refl_blocked_apply(hipStream_t st, int q, int off, int ncols, const z64* Vh, z64* Y, int64_t ldy, int forward,
+                        const void* scr, z64* zs, DevMem& part) {
+  const int nref = q - off;
+  if (nref <= 0 || ncols <= 0) return;
+  const int nb = kWyNb, nblk = (nref + nb - 1) / nb;
+  const z64* Xi = static_cast<const z64*>(scr) + (size_t)nblk * nb * nb;
+  const int64_t bb = (int64_t)nb * nb;
+  z64* Z = zs;
+  z64* Z2 = Z + (size_t)nb * ncols;
   for (int i = 0; i < nblk; ++i) {
     const int blk = forward ? i : nblk - 1 - i;
     const int k0 = blk * nb, nbk = std::min(nb, nref - k0);
@@ -932,6 +944,16 @@ void apply_refl_blocked(hipStream_t st, int q, int off, int ncols, const z64* Vh
     gemm_nn<double>(st, rows, nbk, ncols, Vb, q, Z2, nbk, 0, Y + r0, ldy, -1.0, 0.0, 1.0);
   }
   HIPCK(hipGetLastError());
+}
+
+void apply_refl_blocked(hipStream_t st, int q, int off, int ncols, const z64* Vh, const double* beta, z64* Y,
+                        int64_t ldy, int forward, void* scr, DevMem& part) {
+  const int nref = q - off;
+  if (nref <= 0 || ncols <= 0) return;
+  const int nblk = (nref + kWyNb - 1) / kWyNb;
+  refl_blocked_prepare(st, q, off, Vh, beta, scr, part);
+  refl_blocked_apply(st, q, off, ncols, Vh, Y, ldy, forward, scr,
+                     static_cast<z64*>(scr) + 2 * (size_t)nblk * kWyNb * kWyNb, part);
 }
 
 // Q^H Y (forward) or Q Y: a wave per column with the column in registers up to
