@@ -20,6 +20,15 @@ void gemm_nn_mfma(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int
                   int64_t ldm, int opM, cplx<T>* C, int64_t ldc, double alpha_re, double alpha_im, double beta,
                   int batch, int64_t sA, int64_t sM, int64_t sC);
 
+template <typename T>
+void gemm_hn_ragged_mfma(hipStream_t st, const Ragged& rg, int64_t nmax, int a, int b, const cplx<T>* A,
+                         const cplx<T>* B, int64_t ldb, int64_t sB, cplx<T>* C, int64_t ldc, int64_t sC, double alpha,
+                         double beta, DevMem& part, int batch);
+template <typename T>
+void gemm_nn_ragged_mfma(hipStream_t st, const Ragged& rg, int64_t nmax, int a, int b, const cplx<T>* A,
+                         const cplx<T>* M, int64_t ldm, int64_t sM, int opM, cplx<T>* C, int64_t ldc, int64_t sC,
+                         double alpha, double beta, int batch);
+
 // Both products run on the matrix cores (gemm_mfma.hip).
 template <typename T>
 void gemm_hn(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* B, int64_t ldb,
@@ -42,6 +51,37 @@ void gemm_nn(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t 
   gemm_nn_mfma<T>(st, n, a, b, A, lda, M, ldm, opM, C, ldc, alpha_re, alpha_im, beta, batch, sA, sM, sC);
   gemm_prof_end(st, slot, 8.0 * (double)n * a * b * batch);
 }
+
+template <typename T>
+void gemm_hn_ragged(hipStream_t st, const Ragged& rg, int64_t nmax, int64_t ntot, int a, int b, const cplx<T>* A,
+                    const cplx<T>* B, int64_t ldb, int64_t sB, cplx<T>* C, int64_t ldc, int64_t sC, double alpha,
+                    double beta, DevMem& part, int batch) {
+  if (a <= 0 || b <= 0 || batch <= 0) return;
+  const int slot = kProfGemm + (sizeof(T) == 4 ? 2 : 0) + (nmax < 1024 ? 4 : 0);
+  gemm_prof_begin(st, slot);
+  gemm_hn_ragged_mfma<T>(st, rg, nmax, a, b, A, B, ldb, sB, C, ldc, sC, alpha, beta, part, batch);
+  gemm_prof_end(st, slot, 8.0 * (double)ntot * a * b);
+}
+
+template <typename T>
+void gemm_nn_ragged(hipStream_t st, const Ragged& rg, int64_t nmax, int64_t ntot, int a, int b, const cplx<T>* A,
+                    const cplx<T>* M, int64_t ldm, int64_t sM, int opM, cplx<T>* C, int64_t ldc, int64_t sC,
+                    double alpha, double beta, int batch) {
+  if (nmax <= 0 || b <= 0 || batch <= 0) return;
+  const int slot = kProfGemm + 1 + (sizeof(T) == 4 ? 2 : 0) + (nmax < 1024 ? 4 : 0);
+  gemm_prof_begin(st, slot);
+  gemm_nn_ragged_mfma<T>(st, rg, nmax, a, b, A, M, ldm, sM, opM, C, ldc, sC, alpha, beta, batch);
+  gemm_prof_end(st, slot, 8.0 * (double)ntot * a * b);
+}
+
+template void gemm_hn_ragged<double>(hipStream_t, const Ragged&, int64_t, int64_t, int, int, const z64*, const z64*,
+                                     int64_t, int64_t, z64*, int64_t, int64_t, double, double, DevMem&, int);
+template void gemm_hn_ragged<float>(hipStream_t, const Ragged&, int64_t, int64_t, int, int, const c32*, const c32*,
+                                    int64_t, int64_t, c32*, int64_t, int64_t, double, double, DevMem&, int);
+template void gemm_nn_ragged<double>(hipStream_t, const Ragged&, int64_t, int64_t, int, int, const z64*, const z64*,
+                                     int64_t, int64_t, int, z64*, int64_t, int64_t, double, double, int);
+template void gemm_nn_ragged<float>(hipStream_t, const Ragged&, int64_t, int64_t, int, int, const c32*, const c32*,
+                                    int64_t, int64_t, int, c32*, int64_t, int64_t, double, double, int);
 
 template void gemm_hn<double>(hipStream_t, int64_t, int, int, const z64*, int64_t, const z64*, int64_t, z64*, int64_t,
                               double, double, DevMem&, int, int64_t, int64_t, int64_t);
@@ -121,6 +161,29 @@ __global__ void __launch_bounds__(256) k_col_wnorm2(int64_t n, const z64* X, int
 void col_weighted_norm2(hipStream_t st, int64_t n, int ncols, const z64* X, int64_t ldx, const double* w, double* out) {
   if (ncols <= 0) return;
   hipLaunchKernelGGL(k_col_wnorm2, dim3(ncols), dim3(256), 0, st, n, X, ldx, w, out);
+  HIPCK(hipGetLastError());
+}
+
+// The same over the k-blocks of a stacked frame of p columns, one launch:
+// out[k p + j] over the npw_k rows of block k, weights |k+G|^2/2 (kin) or 1
+__global__ void __launch_bounds__(256) k_frame_wnorm2(const KDesc* __restrict__ kd, int p, const z64* X, int kin,
+                                                      double* out) {
+  __shared__ double sh[16];
+  const int j = blockIdx.x, k = blockIdx.y;
+  const int64_t n = kd[k].npw;
+  const z64* x = X + p * kd[k].off + (int64_t)j * n;
+  const double* w = kin ? kd[k].kin : nullptr;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const z64 v = x[i];
+    s += (w ? w[i] : 1.0) * (v.x * v.x + v.y * v.y);
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[(int64_t)k * p + j] = s;
+}
+void frame_col_wnorm2(hipStream_t st, const KDesc* kd, int nk, int p, const z64* X, int kin, double* out) {
+  if (nk <= 0 || p <= 0) return;
+  hipLaunchKernelGGL(k_frame_wnorm2, dim3(p, nk), dim3(256), 0, st, kd, p, X, kin, out);
   HIPCK(hipGetLastError());
 }
 

@@ -389,7 +389,6 @@ void solver_iterate_l2(eahp_solver* sv) {
   Counters cnt(sv);
   hipStream_t st = pb->ctx->stream;
   const int p = pb->p;
-  const int64_t pp = (int64_t)p * p;
   const int64_t N = pb->ntot * p;
   const eahp_solve_params& prm = sv->prm;
   if (!(frame_dot(pb, sv->R, sv->eta) < 0.0)) axpby<double>(st, N, -1.0, sv->R, 0.0, sv->eta);
@@ -397,11 +396,7 @@ void solver_iterate_l2(eahp_solver* sv) {
   // H eta - eta Lambda into G (unused by this method); V_eff is that of Phi
   z64* He = sv->G;
   apply_H_frame(pb, sv->eta, He, false, nullptr);
-  for (int ik = 0; ik < pb->nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    gemm_nn<double>(st, K.npw, p, p, sv->eta + o, K.npw, sv->Lam + ik * pp, p, 0, He + o, K.npw, -1.0, 0.0, 1.0);
-  }
+  frames_nn(pb, sv->eta, sv->Lam, 0, He, -1.0, 1.0);
   const double h = 2.0 * pb->occ * frame_dot_weighted(pb, sv->eta, He);
   double tau = h > 0.0 ? -dE / h : sv->tau_prev;
   tau = std::min(std::max(tau, 1e-10), 1e10);
@@ -600,8 +595,9 @@ int eahp_problem_layout(const eahp_problem* pb, int64_t* npw, int64_t* offsets, 
 size_t eahp_problem_footprint(const eahp_problem* pb) {
   if (!pb) return 0;
   size_t b = pb->d_vion.bytes + pb->d_veff.bytes + pb->d_veff32.bytes + pb->d_rho.bytes + pb->d_box.bytes +
-             pb->ws.planes.bytes + pb->ws.gemm_part.bytes + pb->ws.small.bytes + pb->ws.partial.bytes;
-  for (auto& K : pb->kp) b += K.d_kin.bytes + K.d_kin32.bytes + K.d_box.bytes + K.d_proj.bytes + K.d_proj32.bytes;
+             pb->ws.planes.bytes + pb->ws.gemm_part.bytes + pb->ws.small.bytes + pb->ws.partial.bytes +
+             pb->d_proj.bytes + pb->d_proj32.bytes;
+  for (auto& K : pb->kp) b += K.d_kin.bytes + K.d_kin32.bytes + K.d_box.bytes;
   for (auto& f : pb->ws.f) b += f.bytes;
   return b;
 }

@@ -15,8 +15,9 @@
 // on the retained directions is that of the one-k-point method.  A k-point
 // that has stopped contributes zero blocks from then on, and its solution is
 // formed when it stops.  The projected problems A_j Y - Y Sigma = C_j are
-// solved through the eigendecompositions of A_j (one work-group per k-point up
-// to q = 128) and of Sigma.
+// solved in the eigenbasis of Sigma, through the eigendecompositions of A_j
+// (one work-group per k-point) up to q = 128 and through batched Householder
+// tridiagonal reductions of A_j and shifted tridiagonal solves beyond.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -28,6 +29,10 @@
 namespace eahp {
 
 namespace {
+
+// largest projected order solved through eigendecompositions (one work-group
+// per k-point); larger ones take the batched tridiagonal solve
+constexpr int kEigMax = 128;
 
 template <typename T>
 __global__ void k_frame_to_pad(int p, const KDesc* __restrict__ kd, const z64* __restrict__ src, double scale,
@@ -332,10 +337,7 @@ void fom_batch(eahp_problem* pb, const z64* Phi, const z64* R, const double* lw,
   // Sigma = Lambda - mu I in the eigenbasis of Lambda: s = w - mu, the same U
   affine(st, nk * p, lw, -mu, 1.0, s);
   // TPA: alpha_j = sum_G |k+G|^2/2 |phi_jG|^2
-  for (int k = 0; k < nk; ++k) {
-    const auto& K = pb->kp[k];
-    col_weighted_norm2(st, K.npw, p, Phi + (int64_t)p * K.off, K.npw, K.d_kin.as<double>(), alpha + (int64_t)k * p);
-  }
+  frame_col_wnorm2(st, kd, nk, p, Phi, 1, alpha);
   // V_1 = rrqr(P^-1 C), W_1 = H V_1, A_1 = V_1^H W_1, C_1 = V_1^H C
   hipLaunchKernelGGL(k_tpa_pad<T>, dim3(nblk(sF), nk), dim3(256), 0, st, p, ld, w.kinp.as<double>(), alpha, C, Rj);
   HIPCK(hipGetLastError());
@@ -364,23 +366,32 @@ void fom_batch(eahp_problem* pb, const z64* Phi, const z64* R, const double* lw,
     ++it;
     const int qc = b.qcap();
     const int64_t sA = (int64_t)qc * qc, qp = (int64_t)q * p;
-    // ---- projected A_q Y - Y Sigma = C_q per k (FP64): A_q = Q diag(wA) Q^H,
-    // in the eigenbasis of Sigma every column is a diagonal division
-    w.wA.ensure(sizeof(double) * q * nk);
-    w.QA.ensure(sizeof(z64) * (size_t)q * q * nk);
+    // ---- projected A_q Y - Y Sigma = C_q per k (FP64), in the eigenbasis of
+    // Sigma (the right-hand sides C_q U): up to kEigMax through A_q = Q diag(wA)
+    // Q^H, where every column is a diagonal division; beyond, through one
+    // tridiagonal reduction of A_q per k and a shifted tridiagonal solve per
+    // column, all k-points in the same launches
+    if (q <= kEigMax) {
+      w.wA.ensure(sizeof(double) * q * nk);
+      w.QA.ensure(sizeof(z64) * (size_t)q * q * nk);
+    }
     for (DevMem* m : {&w.T2, &w.Ct, &w.Y, &w.YS}) m->ensure(sizeof(z64) * qp * nk);
     z64* T2 = w.T2.as<z64>();
     z64* Ct = w.Ct.as<z64>();
     z64* Y = w.Y.as<z64>();
     z64* YS = w.YS.as<z64>();
-    heev(st, q, b.A(), qc, sA, w.wA.as<double>(), q, w.QA.as<z64>(), q, (int64_t)q * q, nk, pb->d_info.as<int>(),
-         w.eig);
     gemm_nn<double>(st, q, p, p, b.Cj(), qc, lU, p, 0, T2, q, 1.0, 0.0, 0.0, nk, (int64_t)qc * p, pp, qp);
-    gemm_hn<double>(st, q, q, p, w.QA.as<z64>(), q, T2, q, Ct, q, 1.0, 0.0, pb->ws.gemm_part, nk, (int64_t)q * q, qp,
-                    qp);
-    hipLaunchKernelGGL(k_sylv_divide_b, dim3(nblk(qp), nk), dim3(256), 0, st, q, p, w.wA.as<double>(), (int64_t)q, s,
-                       Ct, qp);
-    gemm_nn<double>(st, q, q, p, w.QA.as<z64>(), q, Ct, q, 0, T2, q, 1.0, 0.0, 0.0, nk, (int64_t)q * q, qp, qp);
+    if (q <= kEigMax) {
+      heev(st, q, b.A(), qc, sA, w.wA.as<double>(), q, w.QA.as<z64>(), q, (int64_t)q * q, nk,
+           pb->d_info.as<int>(), w.eig);
+      gemm_hn<double>(st, q, q, p, w.QA.as<z64>(), q, T2, q, Ct, q, 1.0, 0.0, pb->ws.gemm_part, nk, (int64_t)q * q,
+                      qp, qp);
+      hipLaunchKernelGGL(k_sylv_divide_b, dim3(nblk(qp), nk), dim3(256), 0, st, q, p, w.wA.as<double>(), (int64_t)q,
+                         s, Ct, qp);
+      gemm_nn<double>(st, q, q, p, w.QA.as<z64>(), q, Ct, q, 0, T2, q, 1.0, 0.0, 0.0, nk, (int64_t)q * q, qp, qp);
+    } else {
+      sylvester_tridiag_batched(st, q, p, nk, b.A(), qc, sA, s, T2, w.tri);
+    }
     gemm_nn<double>(st, q, p, p, T2, q, lU, p, 1, Y, q, 1.0, 0.0, 0.0, nk, qp, pp, qp);
     hipLaunchKernelGGL(k_scale_cols_b, dim3(nblk(qp), nk), dim3(256), 0, st, q, p, s, T2);
     gemm_nn<double>(st, q, p, p, T2, q, lU, p, 1, YS, q, 1.0, 0.0, 0.0, nk, qp, pp, qp);

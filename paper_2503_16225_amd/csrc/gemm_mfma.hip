@@ -82,7 +82,7 @@ template <typename T, int WR, int WC, int BU, int BV>
 __global__ void __launch_bounds__(256) k_gemm_hn_mfma(int64_t n, int a, int b, const cplx<T>* __restrict__ A,
                                                       int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb,
                                                       int64_t rps, cplx<T>* __restrict__ part, int64_t sA,
-                                                      int64_t sB, int group) {
+                                                      int64_t sB, int group, Ragged rg) {
   constexpr int TR = WR * BU * 16, TC = WC * BV * 16, NLA = TR / 16, NLB = TC / 16;
   __shared__ T lds[2 * (TR + TC) * LDK];
   T* Ar = lds;
@@ -97,8 +97,26 @@ __global__ void __launch_bounds__(256) k_gemm_hn_mfma(int64_t n, int a, int b, c
   const int64_t lg = xcd_order(linear_block(), (int64_t)gridDim.x * gridDim.y * gridDim.z, group);
   const int tb = (int)(lg % tiles_b), ta = (int)((lg / tiles_b) % tiles_a);
   const int split = (int)((lg / tiles) % gridDim.y), batch = (int)(lg / ((int64_t)tiles * gridDim.y));
-  A += batch * sA;
-  B += batch * sB;
+  if (rg.rows) {
+    // ragged batch: entry `batch` is k-point k (kmap[batch], or batch), whose
+    // n_k rows start at row off_k of the stacked A (A_k at A + a off_k,
+    // leading dimension n_k); B_k is stacked the same way, or padded (at
+    // B + k sB with leading dimension ldb)
+    const int k = rg.kmap ? rg.kmap[batch] : batch;
+    n = rg.rows[2 * k];
+    const int64_t off = rg.rows[2 * k + 1];
+    A += a * off;
+    lda = n;
+    if (rg.stacked) {
+      B += b * off;
+      ldb = n;
+    } else {
+      B += k * sB;
+    }
+  } else {
+    A += batch * sA;
+    B += batch * sB;
+  }
   const int64_t r0 = split * rps, r1 = min(n, r0 + rps);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = (w % WR) * BU * 16, wj = (w / WR) * BV * 16;
@@ -254,7 +272,7 @@ __global__ void __launch_bounds__(256) k_gemm_nn_mfma(int64_t n, int a, int b, c
                                                       int64_t lda, const cplx<T>* __restrict__ Mm, int64_t ldm,
                                                       int opM, cplx<T>* __restrict__ C, int64_t ldc, double are,
                                                       double aim, double beta, int64_t sA, int64_t sM, int64_t sC,
-                                                      int group) {
+                                                      int group, Ragged rg) {
   constexpr int TR = WR * BU * 16, TC = WC * BV * 16, NLA = TR / 16, NLB = TC / 16;
   // input planes; reused as the TR x 16 output staging tile (complex, row fastest)
   constexpr int kPlanes = 2 * (TR + TC) * LDK, kStage = 2 * 16 * (TR + 1);
@@ -270,10 +288,27 @@ __global__ void __launch_bounds__(256) k_gemm_nn_mfma(int64_t n, int a, int b, c
   const int tcol = (int)(lg % gridDim.y);
   const int64_t trow = (lg / gridDim.y) % gridDim.x;
   const int batch = (int)(lg / ((int64_t)gridDim.x * gridDim.y));
-  A += batch * sA;
   Mm += batch * sM;
-  C += batch * sC;
+  if (rg.rows) {
+    // ragged batch (as in k_gemm_hn_mfma): A_k stacked; C_k stacked (at
+    // C + b off_k, leading dimension n_k) or padded (at C + k sC, ldc)
+    const int k = rg.kmap ? rg.kmap[batch] : batch;
+    n = rg.rows[2 * k];
+    const int64_t off = rg.rows[2 * k + 1];
+    A += a * off;
+    lda = n;
+    if (rg.stacked) {
+      C += b * off;
+      ldc = n;
+    } else {
+      C += k * sC;
+    }
+  } else {
+    A += batch * sA;
+    C += batch * sC;
+  }
   const int64_t row0 = trow * TR;
+  if (row0 >= n) return;  // a row tile beyond this entry's rows (uniform over the work-group)
   const int col0 = tcol * TC;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = (w % WR) * BU * 16, wj = (w / WR) * BV * 16;
@@ -417,24 +452,24 @@ struct Shapes;
 #define EAHP_GEMM_SHAPES_F64(X) X(2, 2, 2, 2) X(2, 2, 4, 2) X(2, 2, 2, 4)
 
 using HnFn = void (*)(hipStream_t, dim3, int64_t, int, int, const void*, int64_t, const void*, int64_t, int64_t, void*,
-                      int64_t, int64_t, int);
+                      int64_t, int64_t, int, Ragged);
 using NnFn = void (*)(hipStream_t, dim3, int64_t, int, int, const void*, int64_t, const void*, int64_t, int, void*,
-                      int64_t, double, double, double, int64_t, int64_t, int64_t, int);
+                      int64_t, double, double, double, int64_t, int64_t, int64_t, int, Ragged);
 
 template <typename T, int WR, int WC, int BU, int BV>
 void launch_hn(hipStream_t st, dim3 g, int64_t n, int a, int b, const void* A, int64_t lda, const void* B, int64_t ldb,
-               int64_t rps, void* part, int64_t sA, int64_t sB, int group) {
+               int64_t rps, void* part, int64_t sA, int64_t sB, int group, Ragged rg) {
   hipLaunchKernelGGL((k_gemm_hn_mfma<T, WR, WC, BU, BV>), g, dim3(256), 0, st, n, a, b,
                      static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(B), ldb, rps,
-                     static_cast<cplx<T>*>(part), sA, sB, group);
+                     static_cast<cplx<T>*>(part), sA, sB, group, rg);
 }
 template <typename T, int WR, int WC, int BU, int BV>
 void launch_nn(hipStream_t st, dim3 g, int64_t n, int a, int b, const void* A, int64_t lda, const void* M, int64_t ldm,
                int opM, void* C, int64_t ldc, double are, double aim, double beta, int64_t sA, int64_t sM, int64_t sC,
-               int group) {
+               int group, Ragged rg) {
   hipLaunchKernelGGL((k_gemm_nn_mfma<T, WR, WC, BU, BV>), g, dim3(256), 0, st, n, a, b,
                      static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(M), ldm, opM,
-                     static_cast<cplx<T>*>(C), ldc, are, aim, beta, sA, sM, sC, group);
+                     static_cast<cplx<T>*>(C), ldc, are, aim, beta, sA, sM, sC, group, rg);
 }
 
 template <typename T>
@@ -564,11 +599,12 @@ int gemm_shape_count(int fp32) { return fp32 ? (int)shapes<float>().shape.size()
 template <typename T>
 static void hn_launch(hipStream_t st, int c, int64_t n, int a, int b, const cplx<T>* A, int64_t lda,
                       const cplx<T>* B, int64_t ldb, int64_t rps, int64_t nsplit, cplx<T>* part, int batch,
-                      int64_t sA, int64_t sB) {
+                      int64_t sA, int64_t sB, Ragged rg = Ragged{}) {
   const auto& tab = shapes<T>();
   const Shape& sh = tab.shape[c];
   const int tiles = ((a + sh.tr() - 1) / sh.tr()) * ((b + sh.tc() - 1) / sh.tc());
-  tab.hn[c](st, dim3(tiles, (unsigned)nsplit, batch), n, a, b, A, lda, B, ldb, rps, part, sA, sB, g_xcd_group.load());
+  tab.hn[c](st, dim3(tiles, (unsigned)nsplit, batch), n, a, b, A, lda, B, ldb, rps, part, sA, sB, g_xcd_group.load(),
+            rg);
   HIPCK(hipGetLastError());
 }
 
@@ -634,7 +670,7 @@ void gemm_nn_mfma(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int
     const Shape& sh = tab.shape[k];
     dim3 grid((unsigned)((n + sh.tr() - 1) / sh.tr()), (b + sh.tc() - 1) / sh.tc(), batch);
     tab.nn[k](st, grid, n, a, b, A, lda, M, ldm, opM, Cd, ldcd, alpha_re, alpha_im, beta, sA, sM, sC == 0 ? 0 : sCd,
-              g_xcd_group.load());
+              g_xcd_group.load(), Ragged{});
     HIPCK(hipGetLastError());
   };
   // candidates write a zeroed scratch output of the same size (same loads and stores)
@@ -649,6 +685,41 @@ void gemm_nn_mfma(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int
   launch(c, C, ldc, sC);
 }
 
+// Ragged batches (see Ragged): the row split and the tile shape are those of
+// one nmax-row product (nmax >= every n_k; the kept tile choice, no tuning);
+// splits beyond an entry's rows add zeros.
+template <typename T>
+void gemm_hn_ragged_mfma(hipStream_t st, const Ragged& rg, int64_t nmax, int a, int b, const cplx<T>* A,
+                         const cplx<T>* B, int64_t ldb, int64_t sB, cplx<T>* C, int64_t ldc, int64_t sC, double alpha,
+                         double beta, DevMem& part, int batch) {
+  int64_t nsplit, rps, per_split;
+  hn_split(nmax, a, b, batch, INT64_MAX, hn_slots<T>(), hn_max_rows<T>(), nsplit, rps, per_split);
+  part.ensure(sizeof(cplx<T>) * (size_t)(nsplit * per_split * batch));
+  const int c = pick_shape<T>(st, "hn", nmax, a, b, batch, false, nullptr);
+  hn_launch<T>(st, c, nmax, a, b, A, nmax, B, ldb, rps, nsplit, part.as<cplx<T>>(), batch, 0, sB, rg);
+  hn_reduce<T>(st, a, b, nsplit, per_split, part.as<cplx<T>>(), C, ldc, alpha, beta, batch, sC);
+}
+
+template <typename T>
+void gemm_nn_ragged_mfma(hipStream_t st, const Ragged& rg, int64_t nmax, int a, int b, const cplx<T>* A,
+                         const cplx<T>* M, int64_t ldm, int64_t sM, int opM, cplx<T>* C, int64_t ldc, int64_t sC,
+                         double alpha, double beta, int batch) {
+  const auto& tab = shapes<T>();
+  const int c = pick_shape<T>(st, "nn", nmax, a, b, batch, false, nullptr);
+  const Shape& sh = tab.shape[c];
+  dim3 grid((unsigned)((nmax + sh.tr() - 1) / sh.tr()), (b + sh.tc() - 1) / sh.tc(), batch);
+  tab.nn[c](st, grid, nmax, a, b, A, nmax, M, ldm, opM, C, ldc, alpha, 0.0, beta, 0, sM, sC, g_xcd_group.load(), rg);
+  HIPCK(hipGetLastError());
+}
+
+#define EAHP_RAGGED_INST(T)                                                                                         \
+  template void gemm_hn_ragged_mfma<T>(hipStream_t, const Ragged&, int64_t, int, int, const cplx<T>*, const cplx<T>*, \
+                                       int64_t, int64_t, cplx<T>*, int64_t, int64_t, double, double, DevMem&, int); \
+  template void gemm_nn_ragged_mfma<T>(hipStream_t, const Ragged&, int64_t, int, int, const cplx<T>*, const cplx<T>*, \
+                                       int64_t, int64_t, int, cplx<T>*, int64_t, int64_t, double, double, int);
+EAHP_RAGGED_INST(double)
+EAHP_RAGGED_INST(float)
+#undef EAHP_RAGGED_INST
 template void gemm_hn_mfma<double>(hipStream_t, int64_t, int, int, const z64*, int64_t, const z64*, int64_t, z64*,
                                    int64_t, double, double, DevMem&, int, int64_t, int64_t, int64_t);
 template void gemm_hn_mfma_ws<double>(hipStream_t, int64_t, int, int, const z64*, int64_t, const z64*, int64_t, z64*,

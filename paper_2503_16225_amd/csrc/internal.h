@@ -75,8 +75,6 @@ struct KPoint {
   DevMem d_kin32;        // float[npw]
   DevMem d_box;          // int[npw] linear box index
   DevMem d_plane_start;  // int[ns + 1]
-  DevMem d_proj;         // z64[npw * natoms], column-major
-  DevMem d_proj32;       // c32[npw * natoms]
 };
 
 struct Scalars;        // device scalar workspace (reductions)
@@ -160,6 +158,11 @@ struct eahp_problem {
   eahp::Workspace ws;
   eahp::Arena* arena = nullptr;  // solver-side buffers (retraction, transports, FOM), owned
   eahp::DevMem d_kdesc;     // KDesc[nk]
+  eahp::DevMem d_krows;     // int64 (npw, off) per k: the ragged batch of the per-k products
+  // projectors, stacked like a frame of natoms columns: the block of k-point
+  // k (npw_k x natoms, column-major) starts at natoms * off_k
+  eahp::DevMem d_proj;      // z64
+  eahp::DevMem d_proj32;    // c32
   eahp::DevMem d_kw;        // double[nk]
   eahp::DevMem d_R;         // natoms x 3 positions (device)
   eahp::DevMem d_Zv;        // natoms charges (device)

@@ -93,6 +93,31 @@ template <typename T>
 void gemm_nn(hipStream_t st, int64_t n, int a, int b, const cplx<T>* A, int64_t lda, const cplx<T>* M, int64_t ldm,
              int opM, cplx<T>* C, int64_t ldc, double alpha_re, double alpha_im, double beta, int batch = 1,
              int64_t sA = 0, int64_t sM = 0, int64_t sC = 0);
+// A ragged batch of per-k-point products: entry b is k-point k = kmap[b]
+// (kmap null: k = b), whose n_k rows start at row off_k of stacked
+// column-major operands (rows: (n_k, off_k) pairs in device memory).
+// stacked = 0: the second operand of gemm_hn_ragged (the output of
+// gemm_nn_ragged) is padded instead: block k at k times its stride, with the
+// leading dimension given.
+struct Ragged {
+  const int64_t* rows = nullptr;
+  const int* kmap = nullptr;
+  int stacked = 1;
+};
+// C_b (a x b, ldc, at b sC) = alpha A_k^H B_k + beta C_b, A_k (n_k x a) at
+// A + a off_k with leading dimension n_k, B_k stacked (at B + b off_k, leading
+// dimension n_k) or padded (at B + k sB, ldb); nmax >= every n_k, ntot = the
+// rows of all entries (for the rate).
+template <typename T>
+void gemm_hn_ragged(hipStream_t st, const Ragged& rg, int64_t nmax, int64_t ntot, int a, int b, const cplx<T>* A,
+                    const cplx<T>* B, int64_t ldb, int64_t sB, cplx<T>* C, int64_t ldc, int64_t sC, double alpha,
+                    double beta, DevMem& part, int batch);
+// C_k = alpha A_k op(M_b) + beta C_k (opM 1: M_b^H), M_b at M + b sM, C_k
+// stacked (at C + b off_k, leading dimension n_k) or padded (at C + k sC, ldc)
+template <typename T>
+void gemm_nn_ragged(hipStream_t st, const Ragged& rg, int64_t nmax, int64_t ntot, int a, int b, const cplx<T>* A,
+                    const cplx<T>* M, int64_t ldm, int64_t sM, int opM, cplx<T>* C, int64_t ldc, int64_t sC,
+                    double alpha, double beta, int batch);
 // y = a x + b y (complex, length n, real coefficients)
 template <typename T>
 void axpby(hipStream_t st, int64_t n, double a, const cplx<T>* x, double b, cplx<T>* y);
@@ -104,6 +129,9 @@ void convert2d(hipStream_t st, int rows, int cols, const c32* src, int64_t lds, 
 void convert2d(hipStream_t st, int rows, int cols, const z64* src, int64_t lds, c32* dst, int64_t ldd);
 // y += a x, x single and y double precision
 void axpy_mixed(hipStream_t st, int64_t n, double a, const c32* x, z64* y);
+// out[k p + j] = sum_g w[g] |X_k[g, j]|^2 over the k-blocks of a stacked frame
+// (w: the kinetic energies of k-point k when kin, else 1), one launch
+void frame_col_wnorm2(hipStream_t st, const KDesc* kd, int nk, int p, const z64* X, int kin, double* out);
 // out[j] = sum_g w[g] |x[g, j]|^2 (column reductions), or with w == null plain norms
 void col_weighted_norm2(hipStream_t st, int64_t n, int ncols, const z64* X, int64_t ldx, const double* w,
                         double* out);
@@ -189,6 +217,15 @@ void tridiag_reduce(hipStream_t st, int q, z64* A, int64_t lda, double* dd, z64*
 // The same for q > 512 with A held in single precision (destroyed); every
 // step computes in FP64 and rounds the updated trailing entries to FP32.
 void tridiag_reduce(hipStream_t st, int q, c32* A, int64_t lda, double* dd, z64* e, z64* Vh, double* beta, void* scr);
+// The solve of sylvester_tridiag for nb matrices of order 2 <= q <= 512 at
+// once: A_b (q x q, ld lda, stride sA; kept), Y_b (q x p, ld q, stride q p;
+// overwritten by the solutions of (A_b - s[b p + l] I) y_l = y_l).  The
+// reductions run as few cooperative launches as the resident work-groups
+// allow.  ws grows to sylvester_tridiag_batched_scratch(q, p, nb) bytes.
+// Synchronises the stream.
+size_t sylvester_tridiag_batched_scratch(int q, int p, int nb);
+void sylvester_tridiag_batched(hipStream_t st, int q, int p, int nb, const z64* A, int64_t lda, int64_t sA,
+                               const double* s, z64* Y, DevMem& ws);
 // Y <- Q^H Y (forward = 1) or Q Y (forward = 0) for the reflectors of tridiag_reduce;
 // for q > 512 with wy_scr and part given: blocked products (MFMA), where
 // wy_scr holds (ceil((q-1)/256) 256^2 + 256 ncols) complex values + 512 bytes
@@ -198,6 +235,10 @@ void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* b
 // (column k of Vh, ld q, zero above row k + off) acting on rows k + off ..;
 // scr: refl_blocked_scratch(q - off, ncols) bytes.
 size_t refl_blocked_scratch(int nref, int ncols);
+// apply_refl's register kernel over nb matrices: Vh_b at stride q^2 (ld q),
+// beta_b at q, Y_b at sY; q <= 1536
+void apply_refl_batched(hipStream_t st, int q, int ncols, int nb, const z64* Vh, const double* beta, z64* Y,
+                        int64_t ldy, int64_t sY, int forward);
 // apply_refl_blocked in two parts: the Gram matrices and triangular factors
 // of the blocks into scr, then the products on ncols columns of Y with zs
 // (2 x 256 x ncols values) for the intermediate blocks; the second part may

@@ -28,19 +28,11 @@ void retract(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z64* 
   z64* Gm = s.b.as<z64>();
   axpby<double>(st, N, 1.0, Phi, 0.0, Psi);
   axpby<double>(st, N, tau, eta, 1.0, Psi);
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    gemm_hn<double>(st, K.npw, p, p, Psi + o, K.npw, Psi + o, K.npw, Gm + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
-  }
+  frames_hn(pb, Psi, Psi, Gm);
   heev(st, p, Gm, p, pp, F.d.as<double>(), p, F.V.as<z64>(), p, pp, nk, pb->d_info.as<int>(), pb->ws.eig);
   minval(st, nk * p, F.d.as<double>(), scal(pb, S_MIN));
   spectral_fn(st, p, F.V.as<z64>(), p, pp, F.d.as<double>(), p, -0.5, F.Sinv.as<z64>(), p, pp, nk);
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    gemm_nn<double>(st, K.npw, p, p, Psi + o, K.npw, F.Sinv.as<z64>() + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0, 0.0);
-  }
+  frames_nn(pb, Psi, F.Sinv.as<z64>(), 0, out, 1.0, 0.0);
   fetch_scalars(pb, S_MIN + 1);
   const double dmin = pb->h_scal[S_MIN];
   if (!std::isfinite(dmin)) fail(EAHP_ENONFINITE, "non-finite Gram matrix in the retraction");
@@ -55,16 +47,9 @@ void line_prepare(eahp_problem* pb, const z64* Phi, const z64* eta, LineFactors&
   L.w.ensure(sizeof(double) * nk * p);
   Scratch& s = pb->arena->s;
   s.b.ensure(sizeof(z64) * nk * pp);
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    gemm_hn<double>(st, K.npw, p, p, Phi + o, K.npw, Phi + o, K.npw, L.E0.as<z64>() + ik * pp, p, 1.0, 0.0,
-                    pb->ws.gemm_part);
-    gemm_hn<double>(st, K.npw, p, p, Phi + o, K.npw, eta + o, K.npw, L.A1.as<z64>() + ik * pp, p, 1.0, 0.0,
-                    pb->ws.gemm_part);
-    gemm_hn<double>(st, K.npw, p, p, eta + o, K.npw, eta + o, K.npw, s.b.as<z64>() + ik * pp, p, 1.0, 0.0,
-                    pb->ws.gemm_part);
-  }
+  frames_hn(pb, Phi, Phi, L.E0.as<z64>());
+  frames_hn(pb, Phi, eta, L.A1.as<z64>());
+  frames_hn(pb, eta, eta, s.b.as<z64>());
   hermitize(st, p, L.E0.as<z64>(), p, pp, nk);
   add_diag(st, p, L.E0.as<z64>(), p, pp, -1.0, nk);
   hermitize(st, p, L.A1.as<z64>(), p, pp, nk);  // (X + X^H) / 2 with X = Phi^H eta
@@ -106,11 +91,7 @@ bool retract_line(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, 
   z64* Psi = s.a.as<z64>();
   axpby<double>(st, N, 1.0, Phi, 0.0, Psi);
   axpby<double>(st, N, tau, eta, 1.0, Psi);
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    gemm_nn<double>(st, K.npw, p, p, Psi + o, K.npw, F.Sinv.as<z64>() + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0, 0.0);
-  }
+  frames_nn(pb, Psi, F.Sinv.as<z64>(), 0, out, 1.0, 0.0);
   return true;
 }
 
@@ -135,15 +116,11 @@ void retract_qr(eahp_problem* pb, const z64* Phi, const z64* eta, double tau, z6
   if (nk > 1024) fail(EAHP_EINVAL, "too many k-points for the qR retraction");
   axpby<double>(st, N, 1.0, Phi, 0.0, Psi);
   axpby<double>(st, N, tau, eta, 1.0, Psi);
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    gemm_hn<double>(st, K.npw, p, p, Psi + o, K.npw, Psi + o, K.npw, Gm + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
+  frames_hn(pb, Psi, Psi, Gm);
+  for (int ik = 0; ik < nk; ++ik)
     pchol_inv(st, p, Gm + ik * pp, p, 0.0, piv + (size_t)ik * p, rank + ik, F.Sinv.as<z64>() + ik * pp, p, nullptr,
               pb->ws.chol, false);
-    gemm_nn<double>(st, K.npw, p, p, Psi + o, K.npw, F.Sinv.as<z64>() + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0,
-                    0.0);
-  }
+  frames_nn(pb, Psi, F.Sinv.as<z64>(), 0, out, 1.0, 0.0);
   HIPCK(hipMemcpyAsync(pb->h_info, rank, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
   for (int ik = 0; ik < nk; ++ik)
@@ -164,19 +141,11 @@ void transport_qr(eahp_problem* pb, const z64* Q, const z64* v, const RetractFac
   z64* W = s.d.as<z64>();
   z64* M = s.e.as<z64>();
   const z64* Rinv = F.Sinv.as<z64>();
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    gemm_hn<double>(st, K.npw, p, p, Q + o, K.npw, v + o, K.npw, W + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
-  }
+  frames_hn(pb, Q, v, W);
   gemm_nn<double>(st, p, p, p, W, p, Rinv, p, 0, M, p, 1.0, 0.0, 0.0, nk, pp, pp, pp);
   qr_omega_minus(st, p, M, p, pp, W, p, pp, nk);  // W <- Omega(M) - M
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    gemm_nn<double>(st, K.npw, p, p, v + o, K.npw, Rinv + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0, 0.0);
-    gemm_nn<double>(st, K.npw, p, p, Q + o, K.npw, W + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0, 1.0);
-  }
+  frames_nn(pb, v, Rinv, 0, out, 1.0, 0.0);
+  frames_nn(pb, Q, W, 0, out, 1.0, 1.0);
 }
 
 void lambda_eig(eahp_problem* pb, const z64* Lam, LamEig& E) {
@@ -203,14 +172,10 @@ void transport_self(eahp_problem* pb, const z64* Phi_new, const z64* eta, double
   s.d.ensure(sizeof(z64) * pb->nk * pp);
   z64* ES = s.c.as<z64>();
   z64* M = s.d.as<z64>();
-  for (int ik = 0; ik < pb->nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    gemm_nn<double>(st, K.npw, p, p, eta + o, K.npw, F.Sinv.as<z64>() + ik * pp, p, 0, ES + o, K.npw, 1.0, 0.0, 0.0);
-    gemm_hn<double>(st, K.npw, p, p, ES + o, K.npw, ES + o, K.npw, M + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
-    axpby<double>(st, K.npw * p, 1.0, ES + o, 0.0, out + o);
-    gemm_nn<double>(st, K.npw, p, p, Phi_new + o, K.npw, M + ik * pp, p, 0, out + o, K.npw, -tau, 0.0, 1.0);
-  }
+  frames_nn(pb, eta, F.Sinv.as<z64>(), 0, ES, 1.0, 0.0);
+  frames_hn(pb, ES, ES, M);
+  axpby<double>(st, pb->ntot * p, 1.0, ES, 0.0, out);
+  frames_nn(pb, Phi_new, M, 0, out, -tau, 1.0);
 }
 
 // T_xi(v) = (v - R(xi) X) S^-1 with S X + X S = xi^H v + v^H xi, in the eigenbasis of S
@@ -227,29 +192,19 @@ void transport_general(eahp_problem* pb, const z64* Phi_new, const z64* xi, cons
   z64* Bm = s.d.as<z64>();
   z64* Tm = s.e.as<z64>();
   const z64* V = F.V.as<z64>();
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    gemm_hn<double>(st, K.npw, p, p, xi + o, K.npw, v + o, K.npw, Bm + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
-  }
+  frames_hn(pb, xi, v, Bm);
   hermitize(st, p, Bm, p, pp, nk);  // (B + B^H) / 2
-  for (int ik = 0; ik < nk; ++ik) {
-    // Tm = V^H Bh ; Bm = Tm V  (= V^H Bh V)
-    gemm_hn<double>(st, p, p, p, V + ik * pp, p, Bm + ik * pp, p, Tm + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
-    gemm_nn<double>(st, p, p, p, Tm + ik * pp, p, V + ik * pp, p, 0, Bm + ik * pp, p, 2.0, 0.0, 0.0);
-  }
+  // Tm = V^H Bh ; Bm = 2 Tm V  (= 2 V^H Bh V), all k at once
+  gemm_hn<double>(st, p, p, p, V, p, Bm, p, Tm, p, 1.0, 0.0, pb->ws.gemm_part, nk, pp, pp, pp);
+  gemm_nn<double>(st, p, p, p, Tm, p, V, p, 0, Bm, p, 2.0, 0.0, 0.0, nk, pp, pp, pp);
   lyap_divide(st, p, F.d.as<double>(), Bm, p, nk, p, pp);
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    // X = V Xt V^H
-    gemm_nn<double>(st, p, p, p, V + ik * pp, p, Bm + ik * pp, p, 0, Tm + ik * pp, p, 1.0, 0.0, 0.0);
-    gemm_nn<double>(st, p, p, p, Tm + ik * pp, p, V + ik * pp, p, 1, Bm + ik * pp, p, 1.0, 0.0, 0.0);
-    // W = v - Phi_new X ; out = W S^-1
-    axpby<double>(st, K.npw * p, 1.0, v + o, 0.0, Wf + o);
-    gemm_nn<double>(st, K.npw, p, p, Phi_new + o, K.npw, Bm + ik * pp, p, 0, Wf + o, K.npw, -1.0, 0.0, 1.0);
-    gemm_nn<double>(st, K.npw, p, p, Wf + o, K.npw, F.Sinv.as<z64>() + ik * pp, p, 0, out + o, K.npw, 1.0, 0.0, 0.0);
-  }
+  // X = V Xt V^H
+  gemm_nn<double>(st, p, p, p, V, p, Bm, p, 0, Tm, p, 1.0, 0.0, 0.0, nk, pp, pp, pp);
+  gemm_nn<double>(st, p, p, p, Tm, p, V, p, 1, Bm, p, 1.0, 0.0, 0.0, nk, pp, pp, pp);
+  // W = v - Phi_new X ; out = W S^-1
+  axpby<double>(st, pb->ntot * p, 1.0, v, 0.0, Wf);
+  frames_nn(pb, Phi_new, Bm, 0, Wf, -1.0, 1.0);
+  frames_nn(pb, Wf, F.Sinv.as<z64>(), 0, out, 1.0, 0.0);
 }
 
 // ---------------------------------------------------------------- EA gradient
@@ -261,18 +216,10 @@ void ea_gradient(eahp_problem* pb, const z64* Phi, const z64* X, z64* G) {
   s.d.ensure(sizeof(z64) * nk * pp);
   s.f.ensure(sizeof(z64) * nk * pp * 2);
   z64* M = s.d.as<z64>();
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    gemm_hn<double>(st, K.npw, p, p, Phi + o, K.npw, X + o, K.npw, M + ik * pp, p, 1.0, 0.0, pb->ws.gemm_part);
-  }
+  frames_hn(pb, Phi, X, M);
   inverse(st, p, M, p, pp, s.f.as<z64>(), nk, pb->d_info.as<int>());
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    axpby<double>(st, K.npw * p, 1.0, Phi + o, 0.0, G + o);
-    gemm_nn<double>(st, K.npw, p, p, X + o, K.npw, M + ik * pp, p, 0, G + o, K.npw, -1.0, 0.0, 1.0);
-  }
+  axpby<double>(st, pb->ntot * p, 1.0, Phi, 0.0, G);
+  frames_nn(pb, X, M, 0, G, -1.0, 1.0);
   HIPCK(hipMemcpyAsync(pb->h_info, pb->d_info.p, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
   for (int ik = 0; ik < nk; ++ik)

@@ -82,6 +82,11 @@ void apply_H_padded(eahp_problem* pb, int nact, const int* kmap_dev, const int* 
                     cplx<T>* HX, int64_t ld, int64_t kstride);
 void evaluate_point(eahp_problem* pb, const z64* Psi, z64* HPsi, z64* R, z64* Lam, PointScalars* out);
 void lambda_residual(eahp_problem* pb, const z64* Psi, const z64* HPsi, z64* R, z64* Lam);
+// The per-k products of two frames (p columns, k-blocks stacked), every
+// k-point in one launch: C_k = A_k^H B_k (p x p, C at stride p^2), and
+// C_k = alpha A_k op(M_k) + beta C_k (M_k p x p at stride p^2; opM 1: M_k^H).
+void frames_hn(eahp_problem* pb, const z64* A, const z64* B, z64* C);
+void frames_nn(eahp_problem* pb, const z64* A, const z64* M, int opM, z64* C, double alpha, double beta);
 double frame_dot(eahp_problem* pb, const z64* A, const z64* B);
 double frame_dot_weighted(eahp_problem* pb, const z64* A, const z64* B);  // sum_k w_k Re tr(A_k^H B_k)
 // Energy only (no H-apply); complete_point then adds H Psi, Lambda, R, ||R||_F.
@@ -133,7 +138,7 @@ struct LobWork {
 struct FomBatchWork {
   DevMem C, E, Rj, Tmp, V, W, T1, stage;
   DevMem A, Cj, T2, Ct, Y, YS, YT, YST, wA, QA;
-  DevMem Sig, s, alpha, Gm64, PU64, PU, piv, rank, kinp, kmap, live, norms, Xt, eig, chol;
+  DevMem Sig, s, alpha, Gm64, PU64, PU, piv, rank, kinp, kmap, live, norms, Xt, eig, chol, tri;
   int qcap = 0;
   int64_t ld = 0;
 };

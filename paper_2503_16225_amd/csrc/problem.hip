@@ -323,21 +323,30 @@ void build_problem(eahp_problem* pb, const eahp_system_desc* d) {
   const bool nl = (pb->terms & EAHP_TERM_NONLOCAL) && pb->natoms > 0;
   std::vector<KDesc> kd(pb->nk);
   std::vector<double> kw(pb->nk);
+  if (nl) {
+    pb->d_proj.alloc(sizeof(z64) * pb->ntot * pb->natoms);
+    pb->d_proj32.alloc(sizeof(c32) * pb->ntot * pb->natoms);
+  }
   for (int ik = 0; ik < pb->nk; ++ik) {
     auto& K = pb->kp[ik];
-    if (nl) {
-      K.d_proj.alloc(sizeof(z64) * K.npw * pb->natoms);
-      K.d_proj32.alloc(sizeof(c32) * K.npw * pb->natoms);
+    z64* P = nl ? pb->d_proj.as<z64>() + (int64_t)pb->natoms * K.off : nullptr;
+    c32* P32 = nl ? pb->d_proj32.as<c32>() + (int64_t)pb->natoms * K.off : nullptr;
+    if (nl)
       launch_projectors(st, K.npw, K.d_box.as<int>(), n1, n2, n3, lat, K.k, pb->natoms, pb->d_R.as<double>(),
-                        pb->r_proj, pb->Omega, K.d_proj.as<z64>(), K.d_proj32.as<c32>());
-    }
+                        pb->r_proj, pb->Omega, P, P32);
     kd[ik] = KDesc{K.npw, K.off, K.d_box.as<int>(), K.d_plane_start.as<int>(), K.d_kin.as<double>(),
-                   K.d_kin32.as<float>(), nl ? K.d_proj.as<z64>() : nullptr, nl ? K.d_proj32.as<c32>() : nullptr,
-                   K.w};
+                   K.d_kin32.as<float>(), P, P32, K.w};
     kw[ik] = K.w;
   }
   pb->d_kdesc.alloc(sizeof(KDesc) * pb->nk);
   pb->d_kw.alloc(sizeof(double) * pb->nk);
+  std::vector<int64_t> krows(2 * (size_t)pb->nk);
+  for (int ik = 0; ik < pb->nk; ++ik) {
+    krows[2 * ik] = pb->kp[ik].npw;
+    krows[2 * ik + 1] = pb->kp[ik].off;
+  }
+  pb->d_krows.alloc(sizeof(int64_t) * krows.size());
+  HIPCK(hipMemcpy(pb->d_krows.p, krows.data(), sizeof(int64_t) * krows.size(), hipMemcpyHostToDevice));
   HIPCK(hipMemcpy(pb->d_kdesc.p, kd.data(), sizeof(KDesc) * pb->nk, hipMemcpyHostToDevice));
   HIPCK(hipMemcpy(pb->d_kw.p, kw.data(), sizeof(double) * pb->nk, hipMemcpyHostToDevice));
   pb->d_vals.alloc(sizeof(double) * 2 * pb->nk * std::max(pb->p, 64) * 8);
@@ -477,39 +486,59 @@ void density_potentials(eahp_problem* pb, const z64* Psi) {
 }
 
 // -------------------------------------------------------------------- H-apply
-// Nonlocal part on one k-block: HX += P (D (P^H X)); optional per-column
+// Stacked projectors (the block of k-point k at natoms off_k), and those of
+// k-point ik (npw_k x natoms, leading dimension npw_k).
+template <typename T>
+const cplx<T>* proj_stack(const eahp_problem* pb) {
+  if constexpr (sizeof(T) == 8) return pb->d_proj.as<z64>();
+  else return pb->d_proj32.as<c32>();
+}
+template <typename T>
+const cplx<T>* projectors(const eahp_problem* pb, int ik) {
+  return proj_stack<T>(pb) + (int64_t)pb->natoms * pb->kp[ik].off;
+}
+
+// Nonlocal part on one k-block: HX += P (D (P^H X)); optional (FP64) per-column
 // sum_I D_I |<beta_I, x_j>|^2 into nlvals.
 template <typename T>
 void nonlocal_block(eahp_problem* pb, int ik, int ncols, const cplx<T>* X, int64_t ldx, cplx<T>* HX, int64_t ldh,
-                    double* nlvals);
-
-template <>
-void nonlocal_block<double>(eahp_problem* pb, int ik, int ncols, const z64* X, int64_t ldx, z64* HX, int64_t ldh,
-                            double* nlvals) {
+                    double* nlvals) {
   if (!((pb->terms & EAHP_TERM_NONLOCAL) && pb->natoms > 0) || ncols <= 0) return;
   hipStream_t st = pb->ctx->stream;
-  auto& K = pb->kp[ik];
+  const int64_t n = pb->kp[ik].npw;
   const int na = pb->natoms;
-  pb->ws.small.ensure(sizeof(z64) * (size_t)na * ncols);
-  z64* Bm = pb->ws.small.as<z64>();
-  gemm_hn<double>(st, K.npw, na, ncols, K.d_proj.as<z64>(), K.npw, X, ldx, Bm, na, 1.0, 0.0, pb->ws.gemm_part);
-  if (nlvals) col_weighted_norm2(st, na, ncols, Bm, na, pb->d_D.as<double>(), nlvals);
-  scale_rows<double>(st, na, ncols, pb->d_D.as<double>(), Bm, na);
-  gemm_nn<double>(st, K.npw, na, ncols, K.d_proj.as<z64>(), K.npw, Bm, na, 0, HX, ldh, 1.0, 0.0, 1.0);
+  const cplx<T>* P = projectors<T>(pb, ik);
+  pb->ws.small.ensure(sizeof(cplx<T>) * (size_t)na * ncols);
+  cplx<T>* Bm = pb->ws.small.as<cplx<T>>();
+  gemm_hn<T>(st, n, na, ncols, P, n, X, ldx, Bm, na, 1.0, 0.0, pb->ws.gemm_part);
+  if constexpr (sizeof(T) == 8) {
+    if (nlvals) col_weighted_norm2(st, na, ncols, Bm, na, pb->d_D.as<double>(), nlvals);
+  }
+  scale_rows<T>(st, na, ncols, pb->d_D.as<double>(), Bm, na);
+  gemm_nn<T>(st, n, na, ncols, P, n, Bm, na, 0, HX, ldh, 1.0, 0.0, 1.0);
 }
 
-template <>
-void nonlocal_block<float>(eahp_problem* pb, int ik, int ncols, const c32* X, int64_t ldx, c32* HX, int64_t ldh,
-                           double*) {
-  if (!((pb->terms & EAHP_TERM_NONLOCAL) && pb->natoms > 0) || ncols <= 0) return;
+// The same for the k-points of a ragged batch (nb entries of ncols columns;
+// X and HX stacked like a frame of ncols columns, or padded at kstride with
+// leading dimension ld; rsum: the rows of all entries): three launches for
+// all of them.  nlvals: entry b's columns at b ncols.
+template <typename T>
+void nonlocal_ragged(eahp_problem* pb, const Ragged& rg, int nb, int64_t rsum, int ncols, const cplx<T>* X,
+                     int64_t ld, int64_t kstride, cplx<T>* HX, double* nlvals) {
+  if (!((pb->terms & EAHP_TERM_NONLOCAL) && pb->natoms > 0) || ncols <= 0 || nb <= 0) return;
   hipStream_t st = pb->ctx->stream;
-  auto& K = pb->kp[ik];
   const int na = pb->natoms;
-  pb->ws.small.ensure(sizeof(c32) * (size_t)na * ncols);
-  c32* Bm = pb->ws.small.as<c32>();
-  gemm_hn<float>(st, K.npw, na, ncols, K.d_proj32.as<c32>(), K.npw, X, ldx, Bm, na, 1.0, 0.0, pb->ws.gemm_part);
-  scale_rows<float>(st, na, ncols, pb->d_D.as<double>(), Bm, na);
-  gemm_nn<float>(st, K.npw, na, ncols, K.d_proj32.as<c32>(), K.npw, Bm, na, 0, HX, ldh, 1.0, 0.0, 1.0);
+  const cplx<T>* P = proj_stack<T>(pb);
+  const int64_t sBm = (int64_t)na * ncols;
+  pb->ws.small.ensure(sizeof(cplx<T>) * (size_t)sBm * nb);
+  cplx<T>* Bm = pb->ws.small.as<cplx<T>>();
+  gemm_hn_ragged<T>(st, rg, pb->nmax, rsum, na, ncols, P, X, ld, kstride, Bm, na, sBm, 1.0, 0.0, pb->ws.gemm_part,
+                    nb);
+  if constexpr (sizeof(T) == 8) {
+    if (nlvals) col_weighted_norm2(st, na, ncols * nb, Bm, na, pb->d_D.as<double>(), nlvals);
+  }
+  scale_rows<T>(st, na, ncols * nb, pb->d_D.as<double>(), Bm, na);
+  gemm_nn_ragged<T>(st, rg, pb->nmax, rsum, na, ncols, P, Bm, na, sBm, 0, HX, ld, kstride, 1.0, 1.0, nb);
 }
 
 // H X for a whole frame with the current V_eff.  tb_ready: the plane buffer
@@ -534,10 +563,11 @@ static void apply_H_frame_launches(eahp_problem* pb, const z64* X, z64* HX, bool
   launch_fwd_yz<double>(st, cm, ncols, g, pb->plan[2], pb->plan[1], pb->d_tw[2].as<z64>(), pb->d_tw[1].as<z64>(), Tb,
                         X, HX);
   prof_end(pb, 2, bytes_fwd(pb, ncols, nsum, 16));
-  for (int ik = 0; ik < pb->nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)pb->p * K.off;
-    nonlocal_block<double>(pb, ik, pb->p, X + o, K.npw, HX + o, K.npw, nlvals ? nlvals + ik * pb->p : nullptr);
+  if (pb->nk == 1) {
+    nonlocal_block<double>(pb, 0, pb->p, X, pb->kp[0].npw, HX, pb->kp[0].npw, nlvals);
+  } else {
+    const Ragged rg{pb->d_krows.as<int64_t>(), nullptr, 1};
+    nonlocal_ragged<double>(pb, rg, pb->nk, pb->ntot, pb->p, X, 0, 0, HX, nlvals);
   }
 }
 
@@ -663,9 +693,12 @@ void apply_H_padded(eahp_problem* pb, int nact, const int* kmap_dev, const int* 
   prof_begin(pb, slot0 + 2);
   launch_fwd_yz<T>(st, cm, ncols, g, pb->plan[2], pb->plan[1], twz, twy, Tb, X, HX);
   prof_end(pb, slot0 + 2, bytes_fwd(pb, ncols, nsum, b));
-  for (int a = 0; a < nact; ++a) {
-    const int ik = kmap_host[a];
+  if (nact == 1) {
+    const int ik = kmap_host[0];
     nonlocal_block<T>(pb, ik, cpk, X + (int64_t)ik * kstride, ld, HX + (int64_t)ik * kstride, ld, nullptr);
+  } else {
+    const Ragged rg{pb->d_krows.as<int64_t>(), kmap_dev, 0};
+    nonlocal_ragged<T>(pb, rg, nact, (int64_t)(nsum / cpk), cpk, X, ld, kstride, HX, nullptr);
   }
   pb->napply += ncols;
   if (sizeof(T) == 4) pb->napply32 += ncols;
@@ -724,18 +757,21 @@ void evaluate_energy(eahp_problem* pb, const z64* Psi, PointScalars* out) {
   double* kinv = vals;
   double* nlv = vals + (size_t)nk * p;
   const bool nl = (pb->terms & EAHP_TERM_NONLOCAL) && pb->natoms > 0;
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    col_weighted_norm2(st, K.npw, p, Psi + o, K.npw, K.d_kin.as<double>(), kinv + ik * p);
-    if (nl) {
-      const int na = pb->natoms;
-      pb->ws.small.ensure(sizeof(z64) * (size_t)na * p);
-      z64* Bm = pb->ws.small.as<z64>();
-      gemm_hn<double>(st, K.npw, na, p, K.d_proj.as<z64>(), K.npw, Psi + o, K.npw, Bm, na, 1.0, 0.0,
-                      pb->ws.gemm_part);
-      col_weighted_norm2(st, na, p, Bm, na, pb->d_D.as<double>(), nlv + ik * p);
+  frame_col_wnorm2(st, pb->d_kdesc.as<KDesc>(), nk, p, Psi, 1, kinv);
+  if (nl) {
+    // sum_I D_I |<beta_I, psi_j>|^2 per column, all k-points at once
+    const int na = pb->natoms;
+    pb->ws.small.ensure(sizeof(z64) * (size_t)na * p * nk);
+    z64* Bm = pb->ws.small.as<z64>();
+    if (nk == 1) {
+      const int64_t n = pb->kp[0].npw;
+      gemm_hn<double>(st, n, na, p, projectors<double>(pb, 0), n, Psi, n, Bm, na, 1.0, 0.0, pb->ws.gemm_part);
+    } else {
+      const Ragged rg{pb->d_krows.as<int64_t>(), nullptr, 1};
+      gemm_hn_ragged<double>(st, rg, pb->nmax, pb->ntot, na, p, proj_stack<double>(pb), Psi, 0, 0, Bm, na,
+                             (int64_t)na * p, 1.0, 0.0, pb->ws.gemm_part, nk);
     }
+    col_weighted_norm2(st, na, p * nk, Bm, na, pb->d_D.as<double>(), nlv);
   }
   weighted_sum(st, nk, p, kinv, pb->d_kw.as<double>(), pb->occ, scal(pb, S_KIN));
   if (nl) weighted_sum(st, nk, p, nlv, pb->d_kw.as<double>(), pb->occ, scal(pb, S_NL));
@@ -778,20 +814,44 @@ double frame_dot_weighted(eahp_problem* pb, const z64* A, const z64* B) {
   return pb->h_scal[S_DOT];
 }
 
+// One k-point: the plain product.  Several: one ragged batch over the
+// k-blocks (row counts and offsets in d_krows).
+void frames_hn(eahp_problem* pb, const z64* A, const z64* B, z64* C) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p;
+  if (pb->nk == 1) {
+    const int64_t n = pb->kp[0].npw;
+    gemm_hn<double>(st, n, p, p, A, n, B, n, C, p, 1.0, 0.0, pb->ws.gemm_part);
+    return;
+  }
+  const Ragged rg{pb->d_krows.as<int64_t>(), nullptr, 1};
+  gemm_hn_ragged<double>(st, rg, pb->nmax, pb->ntot, p, p, A, B, 0, 0, C, p, (int64_t)p * p, 1.0, 0.0,
+                         pb->ws.gemm_part, pb->nk);
+}
+
+void frames_nn(eahp_problem* pb, const z64* A, const z64* M, int opM, z64* C, double alpha, double beta) {
+  hipStream_t st = pb->ctx->stream;
+  const int p = pb->p;
+  if (pb->nk == 1) {
+    const int64_t n = pb->kp[0].npw;
+    gemm_nn<double>(st, n, p, p, A, n, M, p, opM, C, n, alpha, 0.0, beta);
+    return;
+  }
+  const Ragged rg{pb->d_krows.as<int64_t>(), nullptr, 1};
+  gemm_nn_ragged<double>(st, rg, pb->nmax, pb->ntot, p, p, A, M, p, (int64_t)p * p, opM, C, 0, 0, alpha, beta,
+                         pb->nk);
+}
+
 // Lambda_k = herm(Psi_k^H (H Psi)_k), R_k = (H Psi)_k - Psi_k Lambda_k
 void lambda_residual(eahp_problem* pb, const z64* Psi, const z64* HPsi, z64* R, z64* Lam) {
   hipStream_t st = pb->ctx->stream;
   const int p = pb->p;
-  for (int ik = 0; ik < pb->nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    z64* L = Lam + (int64_t)ik * p * p;
-    gemm_hn<double>(st, K.npw, p, p, Psi + o, K.npw, HPsi + o, K.npw, L, p, 1.0, 0.0, pb->ws.gemm_part);
-    hermitize(st, p, L, p, 0, 1);
-    if (R) {
-      axpby<double>(st, K.npw * p, 1.0, HPsi + o, 0.0, R + o);
-      gemm_nn<double>(st, K.npw, p, p, Psi + o, K.npw, L, p, 0, R + o, K.npw, -1.0, 0.0, 1.0);
-    }
+  const int64_t pp = (int64_t)p * p;
+  frames_hn(pb, Psi, HPsi, Lam);
+  hermitize(st, p, Lam, p, pp, pb->nk);
+  if (R) {
+    axpby<double>(st, pb->ntot * p, 1.0, HPsi, 0.0, R);
+    frames_nn(pb, Psi, Lam, 0, R, -1.0, 1.0);
   }
 }
 

@@ -327,9 +327,20 @@ template <int NS> __device__ __forceinline__ void reflector_reg(z64 (&x)[NS], in
 
 template <int NS>
 __global__ void __launch_bounds__(64 * kTrWaves) k_tridiag_reg(int q, const z64* __restrict__ A, int64_t lda,
-                                                               double* d, z64* e, z64* Vh, int64_t ldv, double* beta,
-                                                               z64* Pb, z64* Cb, int* err) {
-  // Pb, Cb: q x q exchange slots (row k = step k) holding the kEmpty pattern
+                                                               int64_t sA, double* d, z64* e, z64* Vh, int64_t ldv,
+                                                               int64_t sV, double* beta, z64* Pb, z64* Cb,
+                                                               int64_t sx, int* err) {
+  // Pb, Cb: q x q exchange slots (row k = step k) holding the kEmpty pattern.
+  // blockIdx.y: the matrix of a batch (A, Vh and the slots at strides sA, sV,
+  // sx; d, e and beta at stride q); the work-groups of one matrix exchange
+  // only among themselves
+  A += blockIdx.y * sA;
+  Vh += blockIdx.y * sV;
+  Pb += blockIdx.y * sx;
+  Cb += blockIdx.y * sx;
+  d += (int64_t)blockIdx.y * q;
+  e += (int64_t)blockIdx.y * q;
+  beta += (int64_t)blockIdx.y * q;
   __shared__ z64 sP[2][64 * NS], sC[2][64 * NS];
   __shared__ int sbad;
   const int lane = threadIdx.x & 63;
@@ -489,7 +500,11 @@ __global__ void __launch_bounds__(64 * kTrWaves) k_tridiag_reg(int q, const z64*
 template <int NS>
 __global__ void __launch_bounds__(256) k_apply_refl_reg(int q, const z64* __restrict__ Vh, int64_t ldv,
                                                         const double* __restrict__ beta, z64* B, int64_t ldb,
-                                                        int ncols, int forward) {
+                                                        int ncols, int forward, int64_t sV, int64_t sB) {
+  // blockIdx.y: the matrix of a batch (Vh, B at strides sV, sB; beta at q)
+  Vh += blockIdx.y * sV;
+  B += blockIdx.y * sB;
+  beta += (int64_t)blockIdx.y * q;
   const int lane = threadIdx.x & 63;
   const int l = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (l >= ncols || q < 2) return;
@@ -540,7 +555,14 @@ __global__ void __launch_bounds__(256) k_apply_refl_reg(int q, const z64* __rest
 // (coalesced).
 __global__ void __launch_bounds__(64) k_trisolve_reg(int q, int ncols, const double* __restrict__ d,
                                                      const z64* __restrict__ e, const double* __restrict__ sh,
-                                                     z64* B, int64_t ldb, z64* W) {
+                                                     z64* B, int64_t ldb, z64* W, int64_t sB) {
+  // blockIdx.y: the system of a batch (d, e at stride q, the shifts at
+  // ncols, B at sB, W at 3 q ncols)
+  d += (int64_t)blockIdx.y * q;
+  e += (int64_t)blockIdx.y * q;
+  sh += (int64_t)blockIdx.y * ncols;
+  B += blockIdx.y * sB;
+  W += (int64_t)blockIdx.y * 3 * q * ncols;
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= ncols) return;
   z64* b = B + (int64_t)l * ldb;
@@ -692,7 +714,8 @@ void tridiag_reg_launch(hipStream_t st, int q, const z64* A, int64_t lda, double
                      0ull);
   int qq = q;
   int64_t la = lda, lv = q;
-  void* args[] = {&qq, &A, &la, &dd, &e, &Vh, &lv, &bt, &Pb, &Cb, &herr};
+  int64_t s0 = 0;
+  void* args[] = {&qq, &A, &la, &s0, &dd, &e, &Vh, &lv, &s0, &bt, &Pb, &Cb, &s0, &herr};
   HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag_reg<NS>, dim3(G), dim3(64 * kTrWaves), args, 0, st));
   int bad = 0;
   HIPCK(hipMemcpyAsync(&bad, herr, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -961,16 +984,34 @@ void apply_refl_blocked(hipStream_t st, int q, int off, int ncols, const z64* Vh
 void apply_refl(hipStream_t st, int q, int ncols, const z64* Vh, const double* bt, z64* Y, int64_t ldy, int forward,
                 void* wy_scr, DevMem* part) {
   if (q < 2 || ncols <= 0) return;
-  const dim3 g((ncols + 3) / 4), b(256);
-  if (q <= 128) hipLaunchKernelGGL(k_apply_refl_reg<2>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
-  else if (q <= 256) hipLaunchKernelGGL(k_apply_refl_reg<4>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
-  else if (q <= 512) hipLaunchKernelGGL(k_apply_refl_reg<8>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
-  else if (wy_scr && part) apply_refl_blocked(st, q, 1, ncols, Vh, bt, Y, ldy, forward, wy_scr, *part);
+  if (q > 512 && wy_scr && part) {
+    apply_refl_blocked(st, q, 1, ncols, Vh, bt, Y, ldy, forward, wy_scr, *part);
+    return;
+  }
+  if (q > 1536) {
+    hipLaunchKernelGGL(k_apply_refl, dim3(ncols), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Y, ldy, forward);
+    HIPCK(hipGetLastError());
+    return;
+  }
+  apply_refl_batched(st, q, ncols, 1, Vh, bt, Y, ldy, 0, forward);
+}
+
+// the register kernel over a batch of nb matrices (Vh at stride q^2, beta at
+// q, Y at sY), q <= 1536
+void apply_refl_batched(hipStream_t st, int q, int ncols, int nb, const z64* Vh, const double* bt, z64* Y,
+                        int64_t ldy, int64_t sY, int forward) {
+  if (q < 2 || ncols <= 0 || nb <= 0) return;
+  if (q > 1536) fail(EAHP_EINVAL, "register reflector products: q > 1536");
+  const dim3 g((ncols + 3) / 4, nb), b(256);
+  const int64_t lv = q, sV = (int64_t)q * q;
+  if (q <= 128) hipLaunchKernelGGL(k_apply_refl_reg<2>, g, b, 0, st, q, Vh, lv, bt, Y, ldy, ncols, forward, sV, sY);
+  else if (q <= 256)
+    hipLaunchKernelGGL(k_apply_refl_reg<4>, g, b, 0, st, q, Vh, lv, bt, Y, ldy, ncols, forward, sV, sY);
+  else if (q <= 512)
+    hipLaunchKernelGGL(k_apply_refl_reg<8>, g, b, 0, st, q, Vh, lv, bt, Y, ldy, ncols, forward, sV, sY);
   else if (q <= 1024)
-    hipLaunchKernelGGL(k_apply_refl_reg<16>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
-  else if (q <= 1536)
-    hipLaunchKernelGGL(k_apply_refl_reg<24>, g, b, 0, st, q, Vh, (int64_t)q, bt, Y, ldy, ncols, forward);
-  else hipLaunchKernelGGL(k_apply_refl, dim3(ncols), dim3(256), 0, st, q, Vh, (int64_t)q, bt, Y, ldy, forward);
+    hipLaunchKernelGGL(k_apply_refl_reg<16>, g, b, 0, st, q, Vh, lv, bt, Y, ldy, ncols, forward, sV, sY);
+  else hipLaunchKernelGGL(k_apply_refl_reg<24>, g, b, 0, st, q, Vh, lv, bt, Y, ldy, ncols, forward, sV, sY);
   HIPCK(hipGetLastError());
 }
 
@@ -1007,9 +1048,98 @@ void sylvester_tridiag(hipStream_t st, int q, int p, z64* A, int64_t lda, const 
     tridiag_reduce(st, q, A, lda, dd, e, Vh, bt, scr);
   }
   apply_refl(st, q, p, Vh, bt, Yt, q, 1, wscr, &part);
-  hipLaunchKernelGGL(k_trisolve_reg, dim3((p + 63) / 64), dim3(64), 0, st, q, p, dd, e, s, Yt, (int64_t)q, W);
+  hipLaunchKernelGGL(k_trisolve_reg, dim3((p + 63) / 64), dim3(64), 0, st, q, p, dd, e, s, Yt, (int64_t)q, W,
+                     (int64_t)0);
   apply_refl(st, q, p, Vh, bt, Yt, q, 0, wscr, &part);
   HIPCK(hipGetLastError());
+}
+
+namespace {
+// resident work-groups of k_tridiag_reg<NS> on the device, in matrices of
+// order q: the batch of one cooperative launch
+template <int NS>
+int tridiag_reg_cap(int q) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  HIPCK(hipGetDevice(&dev));
+  HIPCK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tridiag_reg<NS>, 64 * kTrWaves, 0));
+  const int G = (q + kTrWaves * kTrCols - 1) / (kTrWaves * kTrCols);
+  const int cap = per_cu * ncu / G;
+  if (cap < 1) fail(EAHP_EDEVICE, "the tridiagonal reduction cannot be made resident");
+  return cap;
+}
+
+int tridiag_batch_cap(int q) {
+  if (q <= 128) return tridiag_reg_cap<2>(q);
+  if (q <= 256) return tridiag_reg_cap<4>(q);
+  return tridiag_reg_cap<8>(q);
+}
+
+// nb reductions in launches of up to cap matrices each (the work-groups of
+// a launch are all resident); X: 2 q^2 exchange slots per matrix of a launch
+template <int NS>
+void tridiag_reg_batched(hipStream_t st, int q, const z64* A, int64_t lda, int64_t sA, int nb, int cap, double* dd,
+                         z64* e, z64* Vh, double* bt, z64* X, int* herr) {
+  const int G = (q + kTrWaves * kTrCols - 1) / (kTrWaves * kTrCols);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned long long*>(herr), (int64_t)1,
+                     0ull);
+  for (int k0 = 0; k0 < nb; k0 += cap) {
+    const int m = std::min(cap, nb - k0);
+    const int64_t nw = (int64_t)4 * q * q * m;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>(2048, (nw + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<unsigned long long*>(X), nw, kEmpty);
+    int qq = q;
+    int64_t la = lda, sa = sA, lv = q, sv = (int64_t)q * q, sx = 2 * (int64_t)q * q;
+    const z64* Ak = A + k0 * sA;
+    double* dk = dd + (int64_t)k0 * q;
+    z64* ek = e + (int64_t)k0 * q;
+    z64* Vk = Vh + k0 * sv;
+    double* bk = bt + (int64_t)k0 * q;
+    z64* Pb = X;
+    z64* Cb = X + (int64_t)q * q;
+    void* args[] = {&qq, &Ak, &la, &sa, &dk, &ek, &Vk, &lv, &sv, &bk, &Pb, &Cb, &sx, &herr};
+    HIPCK(hipLaunchCooperativeKernel((const void*)k_tridiag_reg<NS>, dim3(G, m), dim3(64 * kTrWaves), args, 0, st));
+  }
+}
+}  // namespace
+
+size_t sylvester_tridiag_batched_scratch(int q, int p, int nb) {
+  if (q < 2 || p <= 0 || nb <= 0) return 0;
+  const int m = std::min(nb, tridiag_batch_cap(q));
+  const size_t per = sizeof(z64) * ((size_t)q * q + (size_t)3 * q * p + q) + sizeof(double) * 2 * q;
+  return per * nb + sizeof(z64) * 2 * (size_t)q * q * m + 256;
+}
+
+void sylvester_tridiag_batched(hipStream_t st, int q, int p, int nb, const z64* A, int64_t lda, int64_t sA,
+                               const double* s, z64* Y, DevMem& ws) {
+  if (q <= 0 || p <= 0 || nb <= 0) return;
+  if (q < 2 || q > 512) fail(EAHP_EINVAL, "batched tridiagonal Sylvester solve: q must be in [2, 512]");
+  ws.ensure(sylvester_tridiag_batched_scratch(q, p, nb));
+  const int cap = tridiag_batch_cap(q);
+  // per matrix: Vh (q^2), W (3 q p), e (q); then d and beta (q each); then the
+  // exchange slots of one launch and the error flag
+  z64* Vh = ws.as<z64>();
+  z64* W = Vh + (size_t)q * q * nb;
+  z64* e = W + (size_t)3 * q * p * nb;
+  double* dd = reinterpret_cast<double*>(e + (size_t)q * nb);
+  double* bt = dd + (size_t)q * nb;
+  z64* X = reinterpret_cast<z64*>(bt + (size_t)q * nb);
+  int* herr = reinterpret_cast<int*>(X + 2 * (size_t)q * q * std::min(nb, cap));
+  {
+    std::lock_guard<std::mutex> lk(coop_mutex());
+    if (q <= 128) tridiag_reg_batched<2>(st, q, A, lda, sA, nb, cap, dd, e, Vh, bt, X, herr);
+    else if (q <= 256) tridiag_reg_batched<4>(st, q, A, lda, sA, nb, cap, dd, e, Vh, bt, X, herr);
+    else tridiag_reg_batched<8>(st, q, A, lda, sA, nb, cap, dd, e, Vh, bt, X, herr);
+    int bad = 0;
+    HIPCK(hipMemcpyAsync(&bad, herr, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (bad != 0) fail(EAHP_EDEVICE, "exchange wait of the tridiagonal reduction timed out");
+  }
+  const int64_t sY = (int64_t)q * p;
+  apply_refl_batched(st, q, p, nb, Vh, bt, Y, q, sY, 1);
+  hipLaunchKernelGGL(k_trisolve_reg, dim3((p + 63) / 64, nb), dim3(64), 0, st, q, p, dd, e, s, Y, (int64_t)q, W, sY);
+  HIPCK(hipGetLastError());
+  apply_refl_batched(st, q, p, nb, Vh, bt, Y, q, sY, 0);
 }
 
 }  // namespace eahp

@@ -102,6 +102,28 @@ def test_k444_metric_solve_every_k(k444):
     assert rel(X, X_o) < 1e-9
 
 
+def test_k444_metric_solve_deep_krylov(k444):
+    """The metric solve to a relative residual of 1e-6: the k-points need 8
+    or 9 FOM iterations, so the projected order q = 16 j crosses 128, where
+    the projected solves change from eigendecompositions to the batched
+    tridiagonal reductions (all 64 k-points in shared cooperative launches)."""
+    om, gp, Phi, st = k444
+    from oracle import earcg
+    rtol, maxit = 1e-6, 40
+    prm = dict(W.DEFAULT_PARAMS, fom_rtol=rtol, fom_maxit=maxit)
+    lam_max = max(np.linalg.eigvalsh(L)[-1] for L in st["lams"])
+    mu = lam_max - float(st["Veff"].min()) + 1.0
+    X_o, info_o = earcg.metric_solve(om, Phi, st["HPhi"], st["lams"], st["Veff"], mu, prm)
+    X, its, rr = gp.metric_solve(gp.to_device(Phi), mu, rtol, maxit)
+    X = gp.to_blocks(X)
+    print("k444 deep fom iterations", sorted(set(its)), "rel", rel(X, X_o), flush=True)
+    assert max(its) * om.p > 128
+    assert its == [i["iters"] for i in info_o]
+    for a, i in zip(rr, info_o):
+        assert abs(a - i["relres"]) <= 1e-7 * i["relres"] + 1e-13
+    assert rel(X, X_o) < 1e-9
+
+
 def test_k444_solver_steps_are_consistent(k444):
     """Two EARCG steps on the GPU (FP64 and mixed): the energy decreases and
     the oracle's energy of the GPU iterate equals the GPU's own."""
