@@ -15,9 +15,9 @@
 // on the retained directions is that of the one-k-point method.  A k-point
 // that has stopped contributes zero blocks from then on, and its solution is
 // formed when it stops.  The projected problems A_j Y - Y Sigma = C_j are
-// solved in the eigenbasis of Sigma, through the eigendecompositions of A_j
-// (one work-group per k-point) up to q = 128 and through batched Householder
-// tridiagonal reductions of A_j and shifted tridiagonal solves beyond.
+// solved in the eigenbasis of Sigma, through batched Householder tridiagonal
+// reductions of A_j and shifted tridiagonal solves (all k-points in the same
+// launches) up to q = 512 and through eigendecompositions of A_j beyond.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -30,9 +30,9 @@ namespace eahp {
 
 namespace {
 
-// largest projected order solved through eigendecompositions (one work-group
-// per k-point); larger ones take the batched tridiagonal solve
-constexpr int kEigMax = 128;
+// largest projected order of the batched tridiagonal solve (larger ones go
+// through eigendecompositions, one k-point at a time)
+constexpr int kTriMax = 512;
 
 template <typename T>
 __global__ void k_frame_to_pad(int p, const KDesc* __restrict__ kd, const z64* __restrict__ src, double scale,
@@ -367,11 +367,11 @@ void fom_batch(eahp_problem* pb, const z64* Phi, const z64* R, const double* lw,
     const int qc = b.qcap();
     const int64_t sA = (int64_t)qc * qc, qp = (int64_t)q * p;
     // ---- projected A_q Y - Y Sigma = C_q per k (FP64), in the eigenbasis of
-    // Sigma (the right-hand sides C_q U): up to kEigMax through A_q = Q diag(wA)
-    // Q^H, where every column is a diagonal division; beyond, through one
-    // tridiagonal reduction of A_q per k and a shifted tridiagonal solve per
-    // column, all k-points in the same launches
-    if (q <= kEigMax) {
+    // Sigma (the right-hand sides C_q U): up to kTriMax through one tridiagonal
+    // reduction of A_q per k and a shifted tridiagonal solve per column, all
+    // k-points in the same launches; beyond, through A_q = Q diag(wA) Q^H,
+    // where every column is a diagonal division
+    if (q > kTriMax) {
       w.wA.ensure(sizeof(double) * q * nk);
       w.QA.ensure(sizeof(z64) * (size_t)q * q * nk);
     }
@@ -381,7 +381,9 @@ void fom_batch(eahp_problem* pb, const z64* Phi, const z64* R, const double* lw,
     z64* Y = w.Y.as<z64>();
     z64* YS = w.YS.as<z64>();
     gemm_nn<double>(st, q, p, p, b.Cj(), qc, lU, p, 0, T2, q, 1.0, 0.0, 0.0, nk, (int64_t)qc * p, pp, qp);
-    if (q <= kEigMax) {
+    if (q <= kTriMax) {
+      sylvester_tridiag_batched(st, q, p, nk, b.A(), qc, sA, s, T2, w.tri);
+    } else {
       heev(st, q, b.A(), qc, sA, w.wA.as<double>(), q, w.QA.as<z64>(), q, (int64_t)q * q, nk,
            pb->d_info.as<int>(), w.eig);
       gemm_hn<double>(st, q, q, p, w.QA.as<z64>(), q, T2, q, Ct, q, 1.0, 0.0, pb->ws.gemm_part, nk, (int64_t)q * q,
@@ -389,8 +391,6 @@ void fom_batch(eahp_problem* pb, const z64* Phi, const z64* R, const double* lw,
       hipLaunchKernelGGL(k_sylv_divide_b, dim3(nblk(qp), nk), dim3(256), 0, st, q, p, w.wA.as<double>(), (int64_t)q,
                          s, Ct, qp);
       gemm_nn<double>(st, q, q, p, w.QA.as<z64>(), q, Ct, q, 0, T2, q, 1.0, 0.0, 0.0, nk, (int64_t)q * q, qp, qp);
-    } else {
-      sylvester_tridiag_batched(st, q, p, nk, b.A(), qc, sA, s, T2, w.tri);
     }
     gemm_nn<double>(st, q, p, p, T2, q, lU, p, 1, Y, q, 1.0, 0.0, 0.0, nk, qp, pp, qp);
     hipLaunchKernelGGL(k_scale_cols_b, dim3(nblk(qp), nk), dim3(256), 0, st, q, p, s, T2);

@@ -719,11 +719,7 @@ void evaluate_point(eahp_problem* pb, const z64* Psi, z64* HPsi, z64* R, z64* La
   double* kinv = vals;
   double* nlv = vals + (size_t)nk * p;
   apply_H_frame(pb, Psi, HPsi, true, nlv);
-  for (int ik = 0; ik < nk; ++ik) {
-    auto& K = pb->kp[ik];
-    const int64_t o = (int64_t)p * K.off;
-    col_weighted_norm2(st, K.npw, p, Psi + o, K.npw, K.d_kin.as<double>(), kinv + ik * p);
-  }
+  frame_col_wnorm2(st, pb->d_kdesc.as<KDesc>(), nk, p, Psi, 1, kinv);
   weighted_sum(st, nk, p, kinv, pb->d_kw.as<double>(), pb->occ, scal(pb, S_KIN));
   if ((pb->terms & EAHP_TERM_NONLOCAL) && pb->natoms > 0)
     weighted_sum(st, nk, p, nlv, pb->d_kw.as<double>(), pb->occ, scal(pb, S_NL));

@@ -1103,8 +1103,15 @@ void tridiag_reg_batched(hipStream_t st, int q, const z64* A, int64_t lda, int64
 }
 }  // namespace
 
+// d_b = Re A_b[0, 0] (order 1: the matrix is its own tridiagonal form)
+__global__ void k_set_d0_b(int nb, const z64* A, int64_t sA, double* d) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) d[b] = A[b * sA].x;
+}
+
 size_t sylvester_tridiag_batched_scratch(int q, int p, int nb) {
-  if (q < 2 || p <= 0 || nb <= 0) return 0;
+  if (q < 1 || p <= 0 || nb <= 0) return 0;
+  if (q == 1) return sizeof(z64) * ((size_t)3 * p + 1) * nb + sizeof(double) * 2 * nb + 256;
   const int m = std::min(nb, tridiag_batch_cap(q));
   const size_t per = sizeof(z64) * ((size_t)q * q + (size_t)3 * q * p + q) + sizeof(double) * 2 * q;
   return per * nb + sizeof(z64) * 2 * (size_t)q * q * m + 256;
@@ -1113,8 +1120,18 @@ size_t sylvester_tridiag_batched_scratch(int q, int p, int nb) {
 void sylvester_tridiag_batched(hipStream_t st, int q, int p, int nb, const z64* A, int64_t lda, int64_t sA,
                                const double* s, z64* Y, DevMem& ws) {
   if (q <= 0 || p <= 0 || nb <= 0) return;
-  if (q < 2 || q > 512) fail(EAHP_EINVAL, "batched tridiagonal Sylvester solve: q must be in [2, 512]");
+  if (q > 512) fail(EAHP_EINVAL, "batched tridiagonal Sylvester solve: q > 512");
   ws.ensure(sylvester_tridiag_batched_scratch(q, p, nb));
+  if (q == 1) {
+    z64* W = ws.as<z64>() + nb;
+    z64* e = W + (size_t)3 * p * nb;
+    double* dd = reinterpret_cast<double*>(e + nb);
+    hipLaunchKernelGGL(k_set_d0_b, dim3((nb + 63) / 64), dim3(64), 0, st, nb, A, sA, dd);
+    hipLaunchKernelGGL(k_trisolve_reg, dim3((p + 63) / 64, nb), dim3(64), 0, st, 1, p, dd, e, s, Y, (int64_t)1, W,
+                       (int64_t)p);
+    HIPCK(hipGetLastError());
+    return;
+  }
   const int cap = tridiag_batch_cap(q);
   // per matrix: Vh (q^2), W (3 q p), e (q); then d and beta (q each); then the
   // exchange slots of one launch and the error flag

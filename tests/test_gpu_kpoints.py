@@ -105,8 +105,9 @@ def test_k444_metric_solve_every_k(k444):
 def test_k444_metric_solve_deep_krylov(k444):
     """The metric solve to a relative residual of 1e-6: the k-points need 8
     or 9 FOM iterations, so the projected order q = 16 j crosses 128, where
-    the projected solves change from eigendecompositions to the batched
-    tridiagonal reductions (all 64 k-points in shared cooperative launches)."""
+    the batched tridiagonal reductions of the projected systems (all 64
+    k-points in shared cooperative launches) change to their next register
+    size."""
     om, gp, Phi, st = k444
     from oracle import earcg
     rtol, maxit = 1e-6, 40
