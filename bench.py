@@ -53,28 +53,38 @@ KERNEL_NAMES = ["inv_yz", "x_local", "fwd_yz", "x_density", "inv_yz_f32", "x_loc
                 "gemm_hn_f64", "gemm_nn_f64", "gemm_hn_f32", "gemm_nn_f32",
                 "gemm_hn_f64_small", "gemm_nn_f64_small", "gemm_hn_f32_small", "gemm_nn_f32_small"]
 # HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain
-# device copy) measured for the kernels built from sources with this SHA-1
-# (hamiltonian.hip + devcommon.h + regfft.h) on the named workload; reported
-# as null once the sources differ.
-MEASURED_TRAFFIC = {
-    "sources_sha1": "b4f4ed1e057254233e66427efba4dc6d778eff00",
-    "config": "si64_gamma_e20",
-    "bytes_per_launch": {"x_local_f32": 704.189e6, "x_local": 1391.384e6, "fwd_yz_f32": 432.328e6,
-                         "fwd_yz": 876.943e6, "inv_yz_f32": 387.903e6, "inv_yz": 775.579e6,
-                         "x_density": 727.324e6},
-}
+# device copy) measured for kernels built from sources with the given SHA-1
+# (of the listed files, in order) on the named workload; a kernel is
+# reported as null once its sources differ.
+MEASURED_TRAFFIC = [
+    {"sources": ("hamiltonian.hip", "devcommon.h", "regfft.h"),
+     "sources_sha1": "b4f4ed1e057254233e66427efba4dc6d778eff00",
+     "config": "si64_gamma_e20",
+     "bytes_per_launch": {"x_local_f32": 704.189e6, "x_local": 1391.384e6, "fwd_yz_f32": 432.328e6,
+                          "fwd_yz": 876.943e6, "inv_yz_f32": 387.903e6, "inv_yz": 775.579e6,
+                          "x_density": 727.324e6}},
+    # every tile shape of the FP32 update product, averaged over the 166
+    # launches of two timed outer iterations
+    {"sources": ("gemm_mfma.hip", "devcommon.h"),
+     "sources_sha1": "6f5cbb6ee9ff15001a6f8b1f3b55297be7c8058c",
+     "config": "si216_gamma_e15",
+     "bytes_per_launch": {"gemm_nn_f32": 2556.171e6}},
+]
 
 
 def measured_traffic(kernel, config):
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
-    h = hashlib.sha1()
-    for f in ("hamiltonian.hip", "devcommon.h", "regfft.h"):
-        with open(os.path.join(here, "paper_2503_16225_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != MEASURED_TRAFFIC["sources_sha1"] or config != MEASURED_TRAFFIC["config"]:
-        return None
-    return MEASURED_TRAFFIC["bytes_per_launch"].get(kernel)
+    for ent in MEASURED_TRAFFIC:
+        if config != ent["config"] or kernel not in ent["bytes_per_launch"]:
+            continue
+        h = hashlib.sha1()
+        for f in ent["sources"]:
+            with open(os.path.join(here, "paper_2503_16225_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() == ent["sources_sha1"]:
+            return ent["bytes_per_launch"][kernel]
+    return None
 
 
 def cpu_baseline(config, seconds=(15.0, 8.0)):
@@ -488,7 +498,7 @@ def main():
         prec = "f32" if "f32" in dom else "f64"
         achieved = by / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                "frac": achieved / PEAK_TFLOPS[prec], "traffic": None}
+                "frac": achieved / PEAK_TFLOPS[prec], "traffic": measured_traffic(dom, args.config)}
     else:
         achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",

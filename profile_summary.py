@@ -2,7 +2,7 @@
 
     python profile_summary.py trace DB [--split-gap-ms G]
     python profile_summary.py window DB --kernel NAME --last N [--prefix]
-    python profile_summary.py pmc FETCH_DB WRITE_DB --kernel NAME [--copy-bytes B]
+    python profile_summary.py pmc FETCH_DB WRITE_DB --kernel NAME [--copy-bytes B] [--prefix --last N]
 
 The window mode summarises the dispatches from the first of the last N
 dispatches of the named kernel to the end of the trace (bench.py reports how
@@ -11,7 +11,9 @@ kernel's average duration over those N dispatches.
 
 The pmc mode reports FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the named
 kernel, scaled by the ratio of the known byte count of a plain device copy
-to what the same counters read for that copy kernel.
+to what the same counters read for that copy kernel; with --prefix every
+kernel whose name starts with NAME counts as one, and --last N averages over
+its last N dispatches only (the timed steps).
 """
 from __future__ import annotations
 
@@ -67,17 +69,44 @@ def window(db, kernel, last, prefix=False):
     return sel, mean
 
 
-def pmc(db, counter):
-    """{kernel: [counter value per dispatch]} (summed over counter instances)."""
+def pmc(db, counter, group=None, last=0):
+    """{kernel: [counter value per dispatch]} (summed over counter instances).
+    group: every kernel name starting with it counts as that one name (e.g.
+    all tile shapes of a template); last > 0 keeps only the last `last`
+    dispatches (in dispatch order) of each name."""
     con = sqlite3.connect(db)
     rows = con.execute(
         "select k.name, p.dispatch_id, p.counter_value from pmc_events p join kernels k on p.dispatch_id = k.dispatch_id "
         "where p.counter_name = ?", (counter,)).fetchall()
     agg = {}
     for name, did, val in rows:
-        agg.setdefault(name.split("(")[0], {}).setdefault(did, 0.0)
-        agg[name.split("(")[0]][did] += float(val)
-    return {k: list(v.values()) for k, v in agg.items()}
+        key = name.split("(")[0]
+        if group and key.startswith(group):
+            key = group
+        agg.setdefault(key, {}).setdefault(did, 0.0)
+        agg[key][did] += float(val)
+    out = {}
+    for k, v in agg.items():
+        vals = [v[d] for d in sorted(v)]
+        out[k] = vals[-last:] if last > 0 and k == group else vals
+    return out
+
+
+def last_dispatch(db, counter, substr):
+    """(name, counter value in bytes) of the last dispatch whose kernel name
+    contains substr (not one of this library's kernels)."""
+    con = sqlite3.connect(db)
+    rows = con.execute(
+        "select k.name, p.dispatch_id, p.counter_value from pmc_events p join kernels k on p.dispatch_id = k.dispatch_id "
+        "where p.counter_name = ? order by p.dispatch_id", (counter,)).fetchall()
+    per = {}
+    for name, did, val in rows:
+        if substr.lower() in name.lower() and "eahp" not in name:
+            per.setdefault(did, [name.split("(")[0], 0.0])[1] += float(val)
+    if not per:
+        return None, float("nan")
+    name, val = per[max(per)]
+    return name, val * 1024.0
 
 
 def main():
@@ -119,12 +148,13 @@ def main():
             for name, n, t, avg, pct in rows:
                 print(f"| {name} | {n} | {t:.3f} | {avg:.4f} | {pct:.1f} |")
         return
-    fetch = pmc(a.dbs[0], "FETCH_SIZE")
-    write = pmc(a.dbs[1], "WRITE_SIZE")
-    # the copy probe is the largest single dispatch of the copy kernel
-    ck = [k for k in fetch if a.copy_kernel.lower() in k.lower() and "eahp" not in k]
-    cf = max(max(fetch[k]) for k in ck) * 1024.0 if ck else float("nan")
-    cw = max(max(write[k]) for k in ck if k in write) * 1024.0 if ck else float("nan")
+    group = a.kernel if a.prefix else None
+    fetch = pmc(a.dbs[0], "FETCH_SIZE", group, a.last)
+    write = pmc(a.dbs[1], "WRITE_SIZE", group, a.last)
+    # the copy probe is the last dispatch of a copy kernel (bench.py --copy-probe
+    # issues it after everything else)
+    ck, cf = last_dispatch(a.dbs[0], "FETCH_SIZE", a.copy_kernel)
+    _, cw = last_dispatch(a.dbs[1], "WRITE_SIZE", a.copy_kernel)
     sf, sw = a.copy_bytes / cf, a.copy_bytes / cw
     print(f"copy probe ({ck}): FETCH {cf:.6g} B, WRITE {cw:.6g} B for a {a.copy_bytes:.6g} B copy "
           f"-> scale FETCH x{sf:.4f}, WRITE x{sw:.4f}")
