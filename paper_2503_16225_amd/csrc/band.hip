@@ -769,9 +769,7 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   const size_t oTa = oErr + 256;       // the compact WY factor T of every panel
   const size_t oZf = oTa + al(sizeof(z64) * (size_t)npan * b * b);  // V^H C~ and T^H V^H C~ (b x p each)
   const size_t oNp = oZf + al(sizeof(z64) * 2 * (size_t)b * p);  // partial N of the block update: one 64 x 64 block per 64 rows
-  const size_t oZa = oNp + al(sizeof(z64) * (size_t)((q + kBw - 1) / kBw) * kBw * kBw);
-  // intermediate blocks of the backward reflector products on the second stream (at most ncu columns)
-  const size_t oWy = oZa + al(sizeof(z64) * 2 * (size_t)256 * std::min(p, ncu));
+  const size_t oWy = oNp + al(sizeof(z64) * (size_t)((q + kBw - 1) / kBw) * kBw * kBw);
   const size_t oU = oWy + al(refl_blocked_scratch(q - b, p));
   ws.ensure(oU + ubytes_shift * nsh);
   char* base = static_cast<char*>(ws.p);
@@ -788,7 +786,6 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   void* wy = base + oWy;
   z64* Npart = reinterpret_cast<z64*>(base + oNp);
   z64* Tall = reinterpret_cast<z64*>(base + oTa);
-  z64* Zaux = reinterpret_cast<z64*>(base + oZa);
   z64* Zf = reinterpret_cast<z64*>(base + oZf);
   z64* Zf2 = Zf + (size_t)b * p;
   z64* Ubuf = reinterpret_cast<z64*>(base + oU);
@@ -917,39 +914,21 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
   }
   hipLaunchKernelGGL(k_band_rows, dim3((unsigned)std::min<int64_t>(8192, ((int64_t)q * kRw + 255) / 256)), dim3(256),
                      0, st, q, A, lda, RB);
-  const bool two = aux != nullptr && aux->s != nullptr && aux->part != nullptr && aux->f != nullptr;
+  const bool fwd_done = aux != nullptr && aux->s != nullptr && aux->part != nullptr && aux->f != nullptr;
   auto gepp = [&](int lb, int le) {
     for (int l0 = lb; l0 < le; l0 += nsh) {
       const int n = std::min(nsh, le - l0);
       hipLaunchKernelGGL(k_band_gepp, dim3(n), dim3(kGt), 0, st, q, RB, s, Yt, (int64_t)q, Ubuf, l0);
     }
   };
-  if (!two) {
-    apply_refl_blocked(st, q, b, p, Vh, bt, Yt, q, 1, wy, part);
-    gepp(0, p);
-    apply_refl_blocked(st, q, b, p, Vh, bt, Yt, q, 0, wy, part);
-  } else {
-    // (the forward products ran during the reduction.)  The shifts whose
-    // work-groups fill one round of the CUs first; their columns then take
-    // the backward products on the second stream while the other shifts'
-    // solves run, which leave CUs idle.
-    const int nblk = (q - b + 255) / 256;
-    z64* zs_main = static_cast<z64*>(wy) + 2 * (size_t)nblk * 256 * 256;
-    refl_blocked_prepare(st, q, b, Vh, bt, wy, part);
-    const int n1 = std::min(p, ncu);
-    gepp(0, n1);
-    if (n1 < p) {
-      HIPCK(hipEventRecord(aux->z, st));
-      HIPCK(hipStreamWaitEvent(aux->s, aux->z, 0));
-      refl_blocked_apply(aux->s, q, b, n1, Vh, Yt, q, 0, wy, Zaux, *aux->part);
-      HIPCK(hipEventRecord(aux->f, aux->s));
-      gepp(n1, p);
-      refl_blocked_apply(st, q, b, p - n1, Vh, Yt + (int64_t)n1 * q, q, 0, wy, zs_main, part);
-      HIPCK(hipStreamWaitEvent(st, aux->f, 0));
-    } else {
-      refl_blocked_apply(st, q, b, p, Vh, Yt, q, 0, wy, zs_main, part);
-    }
-  }
+  // Q^H C~ (unless it ran during the reduction, on the second stream), every
+  // shift's elimination in one launch where the kept rows allow (64 VGPRs and
+  // 73 KB of LDS per work-group leave room for two on a CU, so up to twice
+  // as many shifts as CUs run at once, each filling the other's
+  // latency-bound panel steps), then Q y.
+  if (!fwd_done) apply_refl_blocked(st, q, b, p, Vh, bt, Yt, q, 1, wy, part);
+  gepp(0, p);
+  apply_refl_blocked(st, q, b, p, Vh, bt, Yt, q, 0, wy, part);
   HIPCK(hipGetLastError());
 }
 
