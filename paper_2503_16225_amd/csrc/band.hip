@@ -922,10 +922,9 @@ void sylvester_band(hipStream_t st, int q, int p, z64* A, int64_t lda, const dou
     }
   };
   // Q^H C~ (unless it ran during the reduction, on the second stream), every
-  // shift's elimination in one launch where the kept rows allow (64 VGPRs and
-  // 73 KB of LDS per work-group leave room for two on a CU, so up to twice
-  // as many shifts as CUs run at once, each filling the other's
-  // latency-bound panel steps), then Q y.
+  // shift's elimination in one launch where the kept rows allow (one
+  // work-group per CU at a time: the shifts beyond the first round start as
+  // CUs free up, with no gap between launches), then Q y over all columns.
   if (!fwd_done) apply_refl_blocked(st, q, b, p, Vh, bt, Yt, q, 1, wy, part);
   gepp(0, p);
   apply_refl_blocked(st, q, b, p, Vh, bt, Yt, q, 0, wy, part);
