@@ -448,10 +448,11 @@ struct Shape {
 // candidate 0 is the default (64 x 64)
 template <typename T>
 struct Shapes;
-// (the last, 64 x 16, is the narrow shape for outputs of at most 16 columns)
+// (the last two, 64 x 32 and 64 x 16, are the narrow shapes for outputs of
+// at most 32 and 16 columns)
 #define EAHP_GEMM_SHAPES_F32(X) \
-  X(2, 2, 2, 2) X(2, 2, 4, 2) X(2, 2, 2, 4) X(2, 2, 4, 4) X(4, 1, 2, 9) X(4, 1, 4, 4) X(4, 1, 1, 1)
-#define EAHP_GEMM_SHAPES_F64(X) X(2, 2, 2, 2) X(2, 2, 4, 2) X(2, 2, 2, 4) X(4, 1, 1, 1)
+  X(2, 2, 2, 2) X(2, 2, 4, 2) X(2, 2, 2, 4) X(2, 2, 4, 4) X(4, 1, 2, 9) X(4, 1, 4, 4) X(4, 1, 1, 2) X(4, 1, 1, 1)
+#define EAHP_GEMM_SHAPES_F64(X) X(2, 2, 2, 2) X(2, 2, 4, 2) X(2, 2, 2, 4) X(4, 1, 1, 2) X(4, 1, 1, 1)
 
 using HnFn = void (*)(hipStream_t, dim3, int64_t, int, int, const void*, int64_t, const void*, int64_t, int64_t, void*,
                       int64_t, int64_t, int, Ragged);
@@ -628,10 +629,10 @@ static int pick_shape(hipStream_t st, const char* op, int64_t n, int a, int b, i
   const int nc = (int)shapes<T>().shape.size();
   const int f = autotune_forced();
   if (f >= 0) return std::min(f, nc - 1);
-  // untimed default: the narrow shape for outputs of at most 16 columns (a
-  // 64-column tile would spend three quarters of its products on zeros),
-  // else the 64 x 64 reference
-  if (8.0 * (double)n * a * b * batch < kTuneMinFlops) return b <= 16 ? nc - 1 : 0;
+  // untimed default: a narrow shape for outputs of at most 16 or 32 columns
+  // (a 64-column tile would spend three quarters or half of its products on
+  // zeros), else the 64 x 64 reference
+  if (8.0 * (double)n * a * b * batch < kTuneMinFlops) return b <= 16 ? nc - 1 : (b <= 32 ? nc - 2 : 0);
   const std::string key = tune_key(op, sizeof(T) == 4, n, a, b, batch);
   return std::min(tune ? autotune(st, key, nc, run) : autotune_kept(key), nc - 1);
 }

@@ -21,7 +21,7 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-NSHAPES = 7  # candidates of FP32 (FP64 has 4; forcing beyond clamps to the last)
+NSHAPES = 8  # candidates of FP32 (FP64 has 5; forcing beyond clamps to the last)
 
 CASES = [  # (op, n, a, b)
     (0, 1000, 37, 70),
