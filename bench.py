@@ -66,9 +66,9 @@ MEASURED_TRAFFIC = [
     # every tile shape of the FP32 update product, averaged over the 166
     # launches of two timed outer iterations
     {"sources": ("gemm_mfma.hip", "devcommon.h"),
-     "sources_sha1": "6f5cbb6ee9ff15001a6f8b1f3b55297be7c8058c",
+     "sources_sha1": "a7a6c122dbcbc7c71586b76055adb91f9ff5b272",
      "config": "si216_gamma_e15",
-     "bytes_per_launch": {"gemm_nn_f32": 2556.171e6}},
+     "bytes_per_launch": {"gemm_nn_f32": 2480.913e6}},
 ]
 
 
