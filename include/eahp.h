@@ -290,7 +290,9 @@ int eahp_problem_graph_stats(const eahp_problem* pb, int64_t* captured, int64_t*
  * Secs. 5.1-5.2 and the work-group count of the multi-work-group Householder
  * reduction of large Hermitian matrices.  The table maps
  * "<arch>/<CUs> <kernel> <shape class>" to a choice.
- * enable(mode): 0 (the default) the default configuration everywhere;
+ * enable(mode): 0 (the default) the default configuration everywhere (for
+ * the block products: 64 x 16 or 64 x 32 tiles where the output has at most
+ * 16 or 32 columns, which every mode keeps, else 64 x 64);
  * 1 the table's choice, and the first call in a class the table lacks times
  * every candidate on scratch outputs or copies of its inputs (extra device
  * allocations, the caller's stream synchronised) and keeps the fastest;

@@ -629,10 +629,12 @@ static int pick_shape(hipStream_t st, const char* op, int64_t n, int a, int b, i
   const int nc = (int)shapes<T>().shape.size();
   const int f = autotune_forced();
   if (f >= 0) return std::min(f, nc - 1);
-  // untimed default: a narrow shape for outputs of at most 16 or 32 columns
-  // (a 64-column tile would spend three quarters or half of its products on
-  // zeros), else the 64 x 64 reference
-  if (8.0 * (double)n * a * b * batch < kTuneMinFlops) return b <= 16 ? nc - 1 : (b <= 32 ? nc - 2 : 0);
+  // a narrow shape for outputs of at most 16 or 32 columns (a 64-column tile
+  // would spend three quarters or half of its products on zeros); small
+  // products otherwise take the 64 x 64 reference untimed
+  if (b <= 16) return nc - 1;
+  if (b <= 32) return nc - 2;
+  if (8.0 * (double)n * a * b * batch < kTuneMinFlops) return 0;
   const std::string key = tune_key(op, sizeof(T) == 4, n, a, b, batch);
   return std::min(tune ? autotune(st, key, nc, run) : autotune_kept(key), nc - 1);
 }
