@@ -270,9 +270,13 @@ struct Batch {
     return out;
   }
 
-  void upload(DevMem& d, const std::vector<int>& h) {
-    HIPCK(hipMemcpyAsync(d.p, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, st));
-    HIPCK(hipStreamSynchronize(st));
+  // host -> device without waiting: every target has its own slot of the
+  // pinned stage, rewritten only after a later synchronisation of the stream
+  // (each FOM iteration synchronises on its residual norms and ranks)
+  void upload(DevMem& d, const std::vector<int>& h, int slot) {
+    int* s = w.hstage.as<int>() + (size_t)slot * nk;
+    std::copy(h.begin(), h.end(), s);
+    HIPCK(hipMemcpyAsync(d.p, s, sizeof(int) * h.size(), hipMemcpyHostToDevice, st));
   }
 
   // H V for the columns [q0, q0 + p) of the k-points in `act` (others: zero)
@@ -280,7 +284,7 @@ struct Batch {
     hipLaunchKernelGGL(k_zero_cols<T>, dim3(nblk(ld * p), nk), dim3(256), 0, st, ld, p, W() + (int64_t)q0 * ld, sV());
     HIPCK(hipGetLastError());
     if (act.empty()) return;
-    upload(w.kmap, act);
+    upload(w.kmap, act, 1);
     apply_H_padded<T>(pb, (int)act.size(), w.kmap.as<int>(), act.data(), p, V() + (int64_t)q0 * ld,
                       W() + (int64_t)q0 * ld, ld, sV());
   }
@@ -322,6 +326,7 @@ void fom_batch(eahp_problem* pb, const z64* Phi, const z64* R, const double* lw,
   w.kmap.ensure(sizeof(int) * nk);
   w.live.ensure(sizeof(int) * nk);
   w.norms.ensure(sizeof(double) * p * nk);
+  w.hstage.ensure(sizeof(int) * 2 * nk);
   w.Xt.ensure(sizeof(CT) * (size_t)pb->nmax * p);
   b.grow(4 * p, 0);
   const KDesc* kd = pb->d_kdesc.as<KDesc>();
@@ -443,7 +448,7 @@ void fom_batch(eahp_problem* pb, const z64* Phi, const z64* R, const double* lw,
     if (act.empty()) break;
     // ---- R_j = (I - V V^H) P^-1 E_j, projected twice (stopped k-points: zero)
     hipLaunchKernelGGL(k_tpa_pad<T>, dim3(nblk(sF), nk), dim3(256), 0, st, p, ld, w.kinp.as<double>(), alpha, E, Rj);
-    b.upload(w.live, live);
+    b.upload(w.live, live, 0);
     hipLaunchKernelGGL(k_mask_blocks<T>, dim3(nblk(sF), nk), dim3(256), 0, st, sF, w.live.as<int>(), Rj, sF);
     HIPCK(hipGetLastError());
     w.T1.ensure(sizeof(CT) * qp * nk);

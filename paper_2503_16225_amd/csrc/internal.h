@@ -53,6 +53,19 @@ struct DevMem {
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Pinned host memory (hipHostMalloc): the source of host-to-device copies
+// the host does not wait for.  ensure drops the old contents.
+struct HostPinned {
+  void* p = nullptr;
+  size_t bytes = 0;
+  HostPinned() = default;
+  HostPinned(const HostPinned&) = delete;
+  HostPinned& operator=(const HostPinned&) = delete;
+  ~HostPinned();
+  void ensure(size_t b);  // grows to at least b bytes
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
 // ---------------------------------------------------------------- FFT plans
 constexpr int kMaxStages = 8;
 struct FftPlan {

@@ -44,6 +44,22 @@ void DevMem::ensure(size_t b) {
   if (b > bytes) alloc(b);
 }
 
+HostPinned::~HostPinned() {
+  if (p) (void)hipHostFree(p);
+}
+void HostPinned::ensure(size_t b) {
+  if (b <= bytes) return;
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  bytes = 0;
+  if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    fail(EAHP_ENOMEM, "hipHostMalloc of " + std::to_string(b) + " bytes failed");
+  }
+  bytes = b;
+}
+
 FftPlan make_plan(int n) {
   FftPlan P;
   P.n = n;
