@@ -154,6 +154,27 @@ void conv_b(hipStream_t st, int rows, int cols, const S* src, int64_t lds, int64
 
 unsigned nblk(int64_t n) { return (unsigned)std::min<int64_t>(1024, (n + 255) / 256); }
 
+// X_k = scale Phi_k + (V Y)_k for the k-points k = list[blockIdx.y] (stacked
+// frames; V Y padded, block k at k sF with leading dimension ld).  The product
+// is rounded, then the sum (contraction into a fused multiply-add is off), as
+// in the separate scaling and accumulation of a single k-point.
+template <typename T>
+__global__ void k_pad_to_frame_x(int p, const KDesc* __restrict__ kd, const int* __restrict__ list,
+                                 const cplx<T>* __restrict__ XP, int64_t ld, int64_t sF, const z64* __restrict__ Phi,
+                                 double scale, z64* __restrict__ X) {
+#pragma clang fp contract(off)
+  const int k = list[blockIdx.y];
+  const int64_t n = kd[k].npw, o = (int64_t)p * kd[k].off, tot = n * p;
+  const cplx<T>* xp = XP + (int64_t)k * sF;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / n, r = e - j * n;
+    const cplx<T> v = xp[j * ld + r];
+    const z64 f = Phi[o + e];
+    const double tx = scale * f.x, ty = scale * f.y;
+    X[o + e] = mk<double>(tx + (double)v.x, ty + (double)v.y);
+  }
+}
+
 // Y_k[i, l] *= s_k[l]
 __global__ void k_scale_cols_b(int q, int p, const double* s, z64* Y) {
   const int k = blockIdx.y;
@@ -326,7 +347,8 @@ void fom_batch(eahp_problem* pb, const z64* Phi, const z64* R, const double* lw,
   w.kmap.ensure(sizeof(int) * nk);
   w.live.ensure(sizeof(int) * nk);
   w.norms.ensure(sizeof(double) * p * nk);
-  w.hstage.ensure(sizeof(int) * 2 * nk);
+  w.hstage.ensure(sizeof(int) * 3 * nk);
+  w.done.ensure(sizeof(int) * nk);
   w.Xt.ensure(sizeof(CT) * (size_t)pb->nmax * p);
   b.grow(4 * p, 0);
   const KDesc* kd = pb->d_kdesc.as<KDesc>();
@@ -419,11 +441,34 @@ void fom_batch(eahp_problem* pb, const z64* Phi, const z64* R, const double* lw,
     gemm_nn<T>(st, ld, q, p, b.W(), ld, Yt, q, 0, E, ld, -1.0, 0.0, 1.0, nk, b.sV(), qp, sF);
     gemm_nn<T>(st, ld, q, p, b.V(), ld, Ys, q, 0, E, ld, 1.0, 0.0, 1.0, nk, b.sV(), qp, sF);
     const std::vector<double> nE2 = b.norms(E);
-    std::vector<int> still;
+    std::vector<int> still, done;
     for (int k : act) {
       const double relres = nC2[k] > 0 ? std::sqrt(nE2[k] / nC2[k]) : 0.0;
       if (!std::isfinite(relres)) fail(EAHP_ENONFINITE, "non-finite residual in the metric solve");
+      if (relres <= rtol || it >= maxit) done.push_back(k);
+    }
+    if (done.size() > 1) {
+      // X_k = X0 + V_k Y_k of every k-point that stops here: V Y for all
+      // k-points in one product (the same sums per element as one k-point's
+      // product), then one launch over the stopped ones
+      w.XP.ensure(sizeof(CT) * sF * nk);
+      gemm_nn<T>(st, ld, q, p, b.V(), ld, Yt, q, 0, w.XP.as<CT>(), ld, 1.0, 0.0, 0.0, nk, b.sV(), qp, sF);
+      b.upload(w.done, done, 2);
+      hipLaunchKernelGGL(k_pad_to_frame_x<T>, dim3(nblk((int64_t)pb->nmax * p), (unsigned)done.size()), dim3(256), 0,
+                         st, p, kd, w.done.as<int>(), w.XP.as<CT>(), ld, sF, Phi, 1.0 / mu, X);
+      HIPCK(hipGetLastError());
+    }
+    for (int k : act) {
+      const double relres = nC2[k] > 0 ? std::sqrt(nE2[k] / nC2[k]) : 0.0;
       if (relres <= rtol || it >= maxit) {
+        if (done.size() > 1) {
+          info[k].iters = it;
+          info[k].relres = relres;
+          info[k].q = qeff[k];
+          pb->fom_iters += it;
+          live[k] = 0;
+          continue;
+        }
         // X_k = X0 + V_k Y_k, from this iteration's projected solution
         const auto& K = pb->kp[k];
         z64* Xk = X + (int64_t)p * K.off;

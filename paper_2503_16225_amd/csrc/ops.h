@@ -138,7 +138,7 @@ struct LobWork {
 struct FomBatchWork {
   DevMem C, E, Rj, Tmp, V, W, T1, stage;
   DevMem A, Cj, T2, Ct, Y, YS, YT, YST, wA, QA;
-  DevMem Sig, s, alpha, Gm64, PU64, PU, piv, rank, kinp, kmap, live, norms, Xt, eig, chol, tri;
+  DevMem Sig, s, alpha, Gm64, PU64, PU, piv, rank, kinp, kmap, live, done, norms, Xt, XP, eig, chol, tri;
   HostPinned hstage;  // host sources of the k-point lists uploaded without waiting
   int qcap = 0;
   int64_t ld = 0;
